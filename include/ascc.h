@@ -1,0 +1,159 @@
+/*
+ * ascc.h -- C ABI of libascc: the closed-shell CCSD-form T1/T2 residual, energy, Jacobi
+ * update and DIIS that Aufbau-suppressed coupled cluster (ASCC) shares with ground-state
+ * CCSD, on AMD Instinct MI355X (gfx950).
+ *
+ * What is computed (Tuckman, Ma, Neuscamman, arXiv:2501.10515):
+ *   energy    E = <phi_0| e^{-T} Hbar e^{T} |phi_0>              (Sec. II.A, Eq. (eqn:energy))
+ *   residual  R_mu = <mu| e^{-T} Hbar e^{T} |phi_0>, mu = singles and doubles
+ *                                                                (Sec. II.A, Eq. (eqn:amp))
+ *   with T = T1 + T2 (Sec. II.B) in the spin-adapted closed-shell form (Supporting
+ *   Information S1): t1[i][a] = t_{i_alpha}^{a_alpha}, t2[i][j][a][b] = t_{i_alpha j_beta}^{a_alpha b_beta},
+ *   and R1[i][a], R2[i][j][a][b] the matching alpha / alpha-beta projections.  The integrals
+ *   are density fitted, (pq|rs) = sum_Q B[Q][p][q] B[Q][r][s], so Hbar is given through B and
+ *   the reference Fock matrix; with S = 0 (ground state) Hbar = H (Eq. (eqn: sim)).
+ *   The update is the diagonal approximate Jacobian with DIIS (Sec. III.B); the convergence
+ *   test is max|R| and |dE| (Sec. III.A), optionally the residual 2-norm.
+ *
+ * Conventions shared by every call:
+ *   - no = occupied orbitals, nv = virtual orbitals, naux = fitting functions, n = no + nv;
+ *     orbitals are ordered occupied first.  All arrays are C-order (row-major), contiguous.
+ *   - Pointers named d_* are DEVICE memory on the current HIP device, owned by the caller,
+ *     and must stay valid until the stream work that uses them has finished.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).  Every call
+ *     except ascc_build_ints, ascc_diis_create and ascc_solve is asynchronous on it.
+ *   - Amplitude and residual arrays are double precision.  `precision` selects the arithmetic
+ *     of the large contractions only; energies, norms, the update and DIIS are always FP64.
+ *   - Every function returns ASCC_OK (0) or a negative ASCC_E_* code and never throws, exits
+ *     or aborts; ascc_last_error() returns a message for the last failure on this thread.
+ *   - Device memory: ascc_build_ints and ascc_diis_create allocate the library's own device
+ *     memory (integrals, work arrays, DIIS history; ascc_workspace_bytes reports the exact
+ *     amount); ascc_*_free releases it.  No other call allocates device memory.
+ *   - A handle is not re-entrant: calls that share an ascc_ints (its work arrays) or an
+ *     ascc_diis must be ordered on one stream.
+ */
+#ifndef ASCC_H
+#define ASCC_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  ASCC_OK = 0,
+  ASCC_E_ARG = -1,           /* NULL pointer or invalid option value                    */
+  ASCC_E_SHAPE = -2,         /* no, nv or naux out of range                             */
+  ASCC_E_NOMEM = -3,         /* device allocation failed                                */
+  ASCC_E_HIP = -4,           /* a HIP runtime call or kernel launch failed              */
+  ASCC_E_NONFINITE = -5,     /* a NaN or Inf appeared in the residual or the energy     */
+  ASCC_E_NOT_CONVERGED = -6, /* maxiter reached; results are the last iterate           */
+  ASCC_E_STATE = -7          /* handles do not belong together (sizes differ)           */
+};
+
+enum {
+  ASCC_PREC_FP64 = 0 /* every contraction in FP64 on the FP64 matrix cores */
+};
+
+enum {
+  ASCC_VVVV_FULL = 0,  /* particle-particle ladder over the full (ac|bd) matrix, v^2 x v^2 */
+  ASCC_VVVV_PACKED = 1 /* ladder over the (ab) / (cd) symmetric and antisymmetric halves   */
+};
+
+typedef struct ascc_ints ascc_ints; /* integrals of one Hamiltonian + residual work arrays */
+typedef struct ascc_diis ascc_diis; /* DIIS history and solver state of one amplitude set  */
+
+/* Byte counts the library will allocate on the device: `ints_bytes` by ascc_build_ints
+ * (integrals and residual work arrays) and `diis_bytes` by ascc_diis_create(m = diis_size).
+ * Host-only, synchronous.  Errors: ASCC_E_SHAPE, ASCC_E_ARG. */
+int ascc_workspace_bytes(int no, int nv, int naux, int precision, int vvvv_mode, int diis_size,
+                         size_t* ints_bytes, size_t* diis_bytes);
+
+/* Build the integral set for one Hamiltonian (Sec. II.A: the integrals of Hbar).
+ *   d_B        [naux][n][n]  density-fitting factors; the residual is exact for the
+ *                            integrals sum_Q B[Q][p][q] B[Q][r][s] (B need not be symmetric in
+ *                            p,q: a one-body similarity transform makes it non-symmetric)
+ *   d_fock     [n] (fock_is_diag = 1: orbital energies) or [n][n] (fock_is_diag = 0): the Fock
+ *                            matrix of the reference determinant; its diagonal gives the
+ *                            Jacobi denominators
+ *   vvvv_mode  ASCC_VVVV_FULL or ASCC_VVVV_PACKED (storage of the (ac|bd) block)
+ * Copies what it needs from d_B / d_fock (they may be freed after the call), forms the
+ * constant integral blocks on `stream`, and synchronises `stream` before returning.
+ * On success *out owns the device memory until ascc_ints_free.
+ * Errors: ASCC_E_ARG, ASCC_E_SHAPE (no, nv, naux < 1), ASCC_E_NOMEM, ASCC_E_HIP. */
+int ascc_build_ints(const double* d_B, const double* d_fock, int fock_is_diag, int no, int nv, int naux,
+                    int precision, int vvvv_mode, void* stream, ascc_ints** out);
+
+/* Residual and energy at the given amplitudes (Eqs. (eqn:energy), (eqn:amp)).
+ *   d_t1 [no][nv], d_t2 [no][no][nv][nv] with t2[i][j][a][b] == t2[j][i][b][a] (read only)
+ *   d_r1 [no][nv], d_r2 [no][no][nv][nv]  (written; R2 has the same pair symmetry)
+ *   d_e  [1]  correlation energy E - E_ref at (t1, t2) (written)
+ * Asynchronous.  Errors: ASCC_E_ARG, ASCC_E_HIP. */
+int ascc_residual(ascc_ints* ints, const double* d_t1, const double* d_t2, double* d_r1, double* d_r2,
+                  double* d_e, void* stream);
+
+/* DIIS state for one amplitude set of `ints`' shape: up to `max_vectors` (1..16) stored pairs
+ * of (amplitudes after the Jacobi step, the step itself); pairs are stored from 0-based
+ * update call `start` on.  Allocates device memory; synchronous.
+ * Errors: ASCC_E_ARG, ASCC_E_NOMEM, ASCC_E_HIP. */
+int ascc_diis_create(const ascc_ints* ints, int max_vectors, int start, ascc_diis** out);
+
+/* Return the DIIS state to empty (no stored pairs, no previous energy).  Asynchronous. */
+int ascc_diis_reset(ascc_diis* diis, void* stream);
+
+/* One diagonal approximate-Jacobian step with DIIS (Sec. III.B), in place on (t1, t2):
+ *   t <- t + R / D,  D_i^a = f_ii - f_aa,  D_ij^ab = f_ii + f_jj - f_aa - f_bb (+ level shift),
+ * then, once two pairs are stored, t <- sum_k c_k t_k with the DIIS coefficients.  Reads the
+ * residual (d_r1, d_r2) and energy d_e produced by ascc_residual at the same t.
+ *   d_stats [8] doubles (written): E, dE (vs the previous call; +inf on the first), max|R|,
+ *           |R|_2 over r1 (+) r2, number of stored DIIS pairs, flags (bit 0: non-finite
+ *           residual or energy; bit 1: the DIIS system was ill-conditioned and old pairs were
+ *           dropped), update index, level shift.
+ * Asynchronous.  Errors: ASCC_E_ARG, ASCC_E_STATE, ASCC_E_HIP. */
+int ascc_update(ascc_ints* ints, ascc_diis* diis, double* d_t1, double* d_t2, const double* d_r1,
+                const double* d_r2, const double* d_e, double level_shift, double* d_stats, void* stream);
+
+typedef struct ascc_opts {
+  double tol_rnorm;   /* converged when |R|_2 <= tol_rnorm      (<= 0: test not used) */
+  double tol_rmax;    /* ... and max|R| <= tol_rmax               (<= 0: not used)    */
+  double tol_de;      /* ... and |dE| < tol_de                    (<= 0: not used)    */
+  int maxiter;        /* >= 1                                                          */
+  int diis_size;      /* 1..16 (1 disables extrapolation)                             */
+  int diis_start;     /* first 0-based iteration whose pair is stored                 */
+  double level_shift; /* added to |D| (D - shift); 0 for the plain Jacobi step         */
+} ascc_opts;
+
+typedef struct ascc_result {
+  double e_corr;   /* energy at the returned amplitudes                     */
+  double rnorm;    /* |R|_2 at the returned amplitudes                      */
+  double rmax;     /* max|R| at the returned amplitudes                     */
+  double de;       /* last energy change                                    */
+  int iterations;  /* residual evaluations made                             */
+  int converged;   /* 1 if every requested test passed                      */
+} ascc_result;
+
+/* Iterate residual -> convergence test -> update from the amplitudes in (d_t1, d_t2)
+ * (in place) until converged or opts->maxiter residual evaluations.  Allocates its DIIS
+ * state internally (freed before returning) and synchronises `stream` once per iteration to
+ * read the 8-double statistics block.  On return (t1, t2) hold the amplitudes the reported
+ * energy and residual norms belong to.
+ * Errors: ASCC_E_ARG, ASCC_E_NOMEM, ASCC_E_HIP, ASCC_E_NONFINITE (res filled up to the
+ * failing iteration), ASCC_E_NOT_CONVERGED (res and amplitudes are the last iterate). */
+int ascc_solve(ascc_ints* ints, const ascc_opts* opts, double* d_t1, double* d_t2, ascc_result* res,
+               void* stream);
+
+void ascc_ints_free(ascc_ints* ints); /* NULL is a no-op; synchronises the device first */
+void ascc_diis_free(ascc_diis* diis); /* NULL is a no-op; synchronises the device first */
+
+/* Shape queries on a built handle (host-only). */
+int ascc_ints_shape(const ascc_ints* ints, int* no, int* nv, int* naux);
+
+/* Message for the last non-zero status returned on this thread ("" if none). */
+const char* ascc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ASCC_H */

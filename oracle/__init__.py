@@ -1,0 +1,20 @@
+"""FP64 CPU oracle for the closed-shell CCSD-form residual, energy and Jacobi/DIIS solve.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import anything from this package.  The
+product path (the HIP library and its Python binding) never calls into it, and the
+two share no code: only the seeded input recipes in ``gen/`` serve both.
+
+Contents, each module citing the passage of the paper it follows:
+
+* ``bruteforce``  -- the definition itself: the projections of e^{-T} H e^{T}|phi_0>
+  onto the reference and onto singly and doubly excited determinants, evaluated in
+  the full determinant space (paper Sec. II.A, Eqs. (eqn:energy), (eqn:amp); the
+  cluster operator convention of Eq. (eqn: CC equation) and the T_N definition after it).
+* ``so_ccsd``     -- spin-orbital CCSD residuals and energy (textbook factorisation),
+  pinned to ``bruteforce`` on tiny inputs.
+* ``cs_ccsd``     -- closed-shell spin-adapted residuals in T1-dressed form, pinned to
+  ``so_ccsd`` through the spin-adaptation relations (Supporting Information S1).
+* ``solver``      -- diagonal approximate-Jacobian update with DIIS (Sec. III.B) and the
+  convergence test (Sec. III.A).
+"""

@@ -1,0 +1,36 @@
+"""Python binding of libascc (include/ascc.h): argument marshalling only.
+
+Every step of the residual, update and solve runs in the HIP kernels of libascc.so; this
+module checks torch tensors (device, dtype, shape, contiguity), passes their device pointers
+and the current HIP stream through ctypes, and turns non-zero status codes into exceptions.
+There is no CPU fallback: without the built library every call raises.
+
+The function names are the C entry points' names.
+"""
+from __future__ import annotations
+
+from ._lib import (  # noqa: F401
+    ASCC_E_ARG,
+    ASCC_E_HIP,
+    ASCC_E_NOMEM,
+    ASCC_E_NONFINITE,
+    ASCC_E_NOT_CONVERGED,
+    ASCC_E_SHAPE,
+    ASCC_E_STATE,
+    ASCC_PREC_FP64,
+    ASCC_VVVV_FULL,
+    ASCC_VVVV_PACKED,
+    AsccError,
+    Diis,
+    Ints,
+    ascc_build_ints,
+    ascc_diis_create,
+    ascc_diis_reset,
+    ascc_last_error,
+    ascc_residual,
+    ascc_solve,
+    ascc_update,
+    ascc_workspace_bytes,
+    library_path,
+    load_library,
+)

@@ -1,0 +1,203 @@
+"""ctypes declarations of libascc and torch-tensor marshalling (no arithmetic here)."""
+from __future__ import annotations
+
+import ctypes
+from pathlib import Path
+
+import torch  # loaded first so that libascc binds to the HIP runtime torch already mapped
+
+ASCC_OK = 0
+ASCC_E_ARG = -1
+ASCC_E_SHAPE = -2
+ASCC_E_NOMEM = -3
+ASCC_E_HIP = -4
+ASCC_E_NONFINITE = -5
+ASCC_E_NOT_CONVERGED = -6
+ASCC_E_STATE = -7
+ASCC_PREC_FP64 = 0
+ASCC_VVVV_FULL = 0
+ASCC_VVVV_PACKED = 1
+
+_LIB = None
+
+
+def library_path() -> Path:
+    return Path(__file__).resolve().with_name("libascc.so")
+
+
+class AsccError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libascc status {code}: {msg}")
+        self.code = code
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("tol_rnorm", ctypes.c_double), ("tol_rmax", ctypes.c_double), ("tol_de", ctypes.c_double),
+                ("maxiter", ctypes.c_int), ("diis_size", ctypes.c_int), ("diis_start", ctypes.c_int),
+                ("level_shift", ctypes.c_double)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("e_corr", ctypes.c_double), ("rnorm", ctypes.c_double), ("rmax", ctypes.c_double),
+                ("de", ctypes.c_double), ("iterations", ctypes.c_int), ("converged", ctypes.c_int)]
+
+
+EXPORTS = ("ascc_workspace_bytes", "ascc_build_ints", "ascc_residual", "ascc_diis_create", "ascc_diis_reset",
+           "ascc_update", "ascc_solve", "ascc_ints_free", "ascc_diis_free", "ascc_ints_shape", "ascc_last_error")
+
+
+def load_library():
+    """Load libascc.so once and declare every exported signature.  Raises if it is not built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = library_path()
+    if not path.exists():
+        raise RuntimeError(f"{path} is not built; run `python -m paper_2501_10515_amd.build` (no CPU fallback)")
+    L = ctypes.CDLL(str(path))
+    vp, c_int, c_double, c_size_p = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.POINTER(ctypes.c_size_t)
+    L.ascc_workspace_bytes.argtypes = [c_int, c_int, c_int, c_int, c_int, c_int, c_size_p, c_size_p]
+    L.ascc_build_ints.argtypes = [vp, vp, c_int, c_int, c_int, c_int, c_int, c_int, vp, ctypes.POINTER(vp)]
+    L.ascc_residual.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.ascc_diis_create.argtypes = [vp, c_int, c_int, ctypes.POINTER(vp)]
+    L.ascc_diis_reset.argtypes = [vp, vp]
+    L.ascc_update.argtypes = [vp, vp, vp, vp, vp, vp, vp, c_double, vp, vp]
+    L.ascc_solve.argtypes = [vp, ctypes.POINTER(Opts), vp, vp, ctypes.POINTER(Result), vp]
+    L.ascc_ints_free.argtypes = [vp]
+    L.ascc_ints_free.restype = None
+    L.ascc_diis_free.argtypes = [vp]
+    L.ascc_diis_free.restype = None
+    L.ascc_ints_shape.argtypes = [vp, ctypes.POINTER(c_int), ctypes.POINTER(c_int), ctypes.POINTER(c_int)]
+    L.ascc_last_error.argtypes = []
+    L.ascc_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name not in ("ascc_ints_free", "ascc_diis_free", "ascc_last_error"):
+            getattr(L, name).restype = c_int
+    _LIB = L
+    return L
+
+
+def ascc_last_error() -> str:
+    return load_library().ascc_last_error().decode()
+
+
+def _check(rc: int):
+    if rc != ASCC_OK:
+        raise AsccError(rc, ascc_last_error())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(t: torch.Tensor, name: str, shape=None) -> ctypes.c_void_p:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must live on the GPU")
+    if t.dtype != torch.float64:
+        raise ValueError(f"{name} must be float64")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def ascc_workspace_bytes(no: int, nv: int, naux: int, precision: int = ASCC_PREC_FP64,
+                         vvvv_mode: int = ASCC_VVVV_FULL, diis_size: int = 8):
+    a, b = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(load_library().ascc_workspace_bytes(no, nv, naux, precision, vvvv_mode, diis_size, ctypes.byref(a),
+                                               ctypes.byref(b)))
+    return a.value, b.value
+
+
+class Ints:
+    """Owner of an ascc_ints handle (frees it on close / garbage collection)."""
+
+    def __init__(self, handle, no, nv, naux):
+        self.handle = handle
+        self.no, self.nv, self.naux = no, nv, naux
+
+    def close(self):
+        if self.handle:
+            load_library().ascc_ints_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Diis:
+    def __init__(self, handle):
+        self.handle = handle
+
+    def close(self):
+        if self.handle:
+            load_library().ascc_diis_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ascc_build_ints(B: torch.Tensor, fock: torch.Tensor, no: int, precision: int = ASCC_PREC_FP64,
+                    vvvv_mode: int = ASCC_VVVV_FULL, stream=None) -> Ints:
+    naux, n, n2 = B.shape
+    if n != n2:
+        raise ValueError("B must be [naux][n][n]")
+    nv = n - no
+    pB = _dev(B, "B")
+    if fock.dim() == 1:
+        pf, diag = _dev(fock, "fock", (n,)), 1
+    else:
+        pf, diag = _dev(fock, "fock", (n, n)), 0
+    h = ctypes.c_void_p()
+    _check(load_library().ascc_build_ints(pB, pf, diag, no, nv, naux, precision, vvvv_mode, _stream(stream),
+                                          ctypes.byref(h)))
+    return Ints(h, no, nv, naux)
+
+
+def ascc_residual(ints: Ints, t1, t2, r1, r2, e, stream=None):
+    o, v = ints.no, ints.nv
+    _check(load_library().ascc_residual(ints.handle, _dev(t1, "t1", (o, v)), _dev(t2, "t2", (o, o, v, v)),
+                                        _dev(r1, "r1", (o, v)), _dev(r2, "r2", (o, o, v, v)), _dev(e, "e", (1,)),
+                                        _stream(stream)))
+
+
+def ascc_diis_create(ints: Ints, max_vectors: int = 8, start: int = 1) -> Diis:
+    h = ctypes.c_void_p()
+    _check(load_library().ascc_diis_create(ints.handle, max_vectors, start, ctypes.byref(h)))
+    return Diis(h)
+
+
+def ascc_diis_reset(diis: Diis, stream=None):
+    _check(load_library().ascc_diis_reset(diis.handle, _stream(stream)))
+
+
+def ascc_update(ints: Ints, diis: Diis, t1, t2, r1, r2, e, stats, level_shift: float = 0.0, stream=None):
+    o, v = ints.no, ints.nv
+    _check(load_library().ascc_update(ints.handle, diis.handle, _dev(t1, "t1", (o, v)), _dev(t2, "t2", (o, o, v, v)),
+                                      _dev(r1, "r1", (o, v)), _dev(r2, "r2", (o, o, v, v)), _dev(e, "e", (1,)),
+                                      ctypes.c_double(level_shift), _dev(stats, "stats", (8,)), _stream(stream)))
+
+
+def ascc_solve(ints: Ints, t1, t2, tol_rnorm=1e-8, tol_rmax=0.0, tol_de=0.0, maxiter=100, diis_size=8,
+               diis_start=1, level_shift=0.0, stream=None, raise_on_not_converged=True) -> dict:
+    o, v = ints.no, ints.nv
+    opts = Opts(tol_rnorm, tol_rmax, tol_de, maxiter, diis_size, diis_start, level_shift)
+    res = Result()
+    rc = load_library().ascc_solve(ints.handle, ctypes.byref(opts), _dev(t1, "t1", (o, v)),
+                                   _dev(t2, "t2", (o, o, v, v)), ctypes.byref(res), _stream(stream))
+    out = dict(e_corr=res.e_corr, rnorm=res.rnorm, rmax=res.rmax, de=res.de, iterations=res.iterations,
+               converged=bool(res.converged), status=rc)
+    if rc != ASCC_OK and not (rc == ASCC_E_NOT_CONVERGED and not raise_on_not_converged):
+        raise AsccError(rc, ascc_last_error())
+    return out

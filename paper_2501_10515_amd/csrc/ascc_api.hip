@@ -1,0 +1,987 @@
+// The C ABI of libascc (include/ascc.h): integral assembly, the closed-shell CCSD-form
+// residual, the Jacobi/DIIS update and the solve loop, all on one HIP stream.
+//
+// Residual algorithm (FP64).  With T1-dressed factors B^_Q = X B_Q Y^T (X = 1 - t1 in the
+// virtual-occupied block, Y = 1 + t1^T in the occupied-virtual block) and the dressed Fock
+// matrix F^ = X h Y^T + sum_k (2 g^_pqkk - g^_pkkq), the closed-shell residual is
+//   R_ij^ab = g^_aibj + sum_cd t_ij^cd g^_acbd + sum_kl t_kl^ab (g^_kilj + sum_cd t_ij^cd g_kcld)
+//             + P_ij^ab [C + D + E]_aibj
+// (the projections of the paper's Eq. (eqn:amp) for T = T1 + T2, Sec. II.A-B, in spin-adapted
+// form, Supporting Information S1).  The particle-particle ladder is evaluated against the
+// UNdressed (ac|bd), which is formed once per integral set, and the dressing is moved onto
+// the amplitudes side:
+//   sum_cd t_ij^cd g^_acbd = sum_cd t_ij^cd (ac|bd) - P_ij^ab sum_k t_k^a W'_ij[k,b]
+//   W_ij[k,b] = sum_cd (kc|bd) t_ij^cd,  Z_ij[k,l] = sum_cd (kc|ld) t_ij^cd,
+//   W'_ij[k,b] = W_ij[k,b] - 1/2 sum_l Z_ij[k,l] t_l^b
+// so no v^4 array is ever re-dressed.  Ring terms use permuted views of t2 in the
+// [o][v][o][v] layout:
+//   Tx[iajb] = t_ij^ba, U[iajb] = u_ij^ab = 2 t_ij^ab - t_ij^ba,
+//   Y1 = Tx K, Y2 = U L  (K[iajb] = (ib|ja), L = 2(ia|jb) - (ib|ja)),
+//   Xc[iakc] = g^_kiac - Y1/2,  Zd[iakc] = 2 g^_aikc - g^_kiac + Y2/2,
+//   P1 = Tx Xc^T, P2 = U Zd^T,
+// and the N^5 terms go through N_Q[k,a] = sum_lc u_kl^ac B_Q,lc.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/ascc.h"
+#include "internal.h"
+
+namespace ascc {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+static std::mutex g_buf_mu;
+static std::map<uintptr_t, size_t> g_bufs;
+
+bool dry_run() {
+  static const bool on = [] {
+    const char* e = std::getenv("ASCC_DRY_RUN");
+    return e && e[0] == '1';
+  }();
+  return on;
+}
+
+bool bounds_checking() {
+  static const bool on = [] {
+    const char* e = std::getenv("ASCC_CHECK_BOUNDS");
+    return (e && e[0] == '1') || dry_run();
+  }();
+  return on;
+}
+
+void register_buffer(const void* p, size_t bytes) {
+  if (!bounds_checking() || !p) return;
+  std::lock_guard<std::mutex> lk(g_buf_mu);
+  g_bufs[(uintptr_t)p] = bytes;
+}
+
+void unregister_buffer(const void* p) {
+  if (!bounds_checking() || !p) return;
+  std::lock_guard<std::mutex> lk(g_buf_mu);
+  g_bufs.erase((uintptr_t)p);
+}
+
+bool range_ok(const void* base, long lo, long hi, size_t elem, const char* what) {
+  if (!bounds_checking()) return true;
+  std::lock_guard<std::mutex> lk(g_buf_mu);
+  const uintptr_t b = (uintptr_t)base;
+  auto it = g_bufs.upper_bound(b);
+  if (it == g_bufs.begin()) {
+    set_error(std::string(what) + ": pointer is not inside a registered buffer");
+    return false;
+  }
+  --it;
+  const long long first = (long long)b + (long long)lo * (long long)elem - (long long)it->first;
+  const long long last = (long long)b + ((long long)hi + 1) * (long long)elem - (long long)it->first;
+  if (first < 0 || last > (long long)it->second) {
+    char msg[256];
+    std::snprintf(msg, sizeof msg, "%s: elements [%ld, %ld] fall outside their %zu-byte buffer (byte range %lld..%lld)",
+                  what, lo, hi, it->second, first, last);
+    set_error(msg);
+    return false;
+  }
+  return true;
+}
+
+// Runtime calls that are skipped in a dry run (and bounds-checked when checking is on).
+hipError_t d_copy(void* dst, const void* src, size_t bytes, hipMemcpyKind kind, hipStream_t s) {
+  if (bytes == 0) return hipSuccess;
+  if (bounds_checking()) {
+    const bool dst_dev = (kind == hipMemcpyDeviceToDevice || kind == hipMemcpyHostToDevice);
+    const bool src_dev = (kind == hipMemcpyDeviceToDevice || kind == hipMemcpyDeviceToHost);
+    if ((dst_dev && !range_ok(dst, 0, (long)bytes - 1, 1, "copy destination")) ||
+        (src_dev && !range_ok(src, 0, (long)bytes - 1, 1, "copy source")))
+      return hipErrorInvalidValue;
+  }
+  if (dry_run()) return hipSuccess;
+  return hipMemcpyAsync(dst, src, bytes, kind, s);
+}
+hipError_t d_sync(hipStream_t s) { return dry_run() ? hipSuccess : hipStreamSynchronize(s); }
+
+// Registers caller buffers for the bounds checker for the duration of one ABI call.
+struct ScopedBuffers {
+  std::vector<const void*> ps;
+  void add(const void* p, size_t bytes) {
+    if (!bounds_checking() || !p) return;
+    {
+      std::lock_guard<std::mutex> lk(g_buf_mu);
+      if (g_bufs.count((uintptr_t)p)) return;  // a library buffer, or already registered
+    }
+    register_buffer(p, bytes);
+    ps.push_back(p);
+  }
+  ~ScopedBuffers() {
+    for (const void* p : ps) unregister_buffer(p);
+  }
+};
+
+}  // namespace ascc
+
+using namespace ascc;
+
+struct ascc_ints {
+  int no, nv, naux, n, precision, vvvv_mode, device;
+  long ov, oo, vv, ovov, oovv;
+  std::vector<void*> allocs;
+  size_t bytes = 0;
+  // constant integrals
+  double* B;      // [Q][n][n]
+  double* h;      // [n][n] core Hamiltonian
+  double* eps;    // [n] Fock diagonal
+  double* fov;    // [o][v] reference Fock, occupied-virtual block
+  double* Bov;    // [Q][o][v]
+  double* KL;     // [2][ov][ov]: (ib|ja), 2(ia|jb) - (ib|ja)
+  double* Lijab;  // [o][o][v][v]: 2(ia|jb) - (ib|ja)
+  double* Gwz;    // [v][v][ov + o^2]: (kc|bd) at [c][d][k*v+b], (kc|ld) at [c][d][ov + k*o+l]
+  double* V;      // [v][v][v][v]: (ac|bd) at [a][b][c][d]
+  // residual work arrays
+  double *Bt, *Bh;               // [Q][n][n]
+  double *ht, *Fh;               // [n][n]
+  double *J;                     // [Q]
+  double *BvoT, *Boo, *Bvv;      // [Q][o][v] (B^_ai at [Q][i][a]), [Q][o][o], [Q][v][v]
+  double *G1, *G2, *G3, *G4;     // ovov, [k][i][a][c], ovov, [k][i][l][j]
+  double *TU, *Y, *XZ, *P;       // each [2][ov][ov]
+  double *Nq;                    // [Q][o][v]
+  double *WZ;                    // [o^2][ov + o^2]
+  double *chi;                   // [o^2][o^2]
+  double *RL, *EM;               // [o^2][v^2]
+  double *Abc, *Bkj, *Fvvp, *Foop, *Fovh;  // small
+  double *partial;               // reduction scratch
+};
+
+struct ascc_diis {
+  int no, nv, m, start, calls;
+  long len;
+  double *hist_t, *hist_e, *partial;
+  DiisState* st;
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+#define HIPCHK(expr)                                                                         \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) {                                                                  \
+      set_error(std::string(#expr) + ": " + hipGetErrorString(e_));                          \
+      return ASCC_E_HIP;                                                                     \
+    }                                                                                        \
+  } while (0)
+
+int fail(int code, const std::string& msg) {
+  set_error(msg);
+  return code;
+}
+
+struct Sizes {
+  long ints_const, ints_work, diis;
+};
+
+Sizes sizes_of(long o, long v, long Q, int vvvv_mode, int m) {
+  const long n = o + v, ov = o * v, oo = o * o, vv = v * v;
+  Sizes s;
+  long c = 0;
+  c += Q * n * n + n * n + n + ov + Q * ov + 2 * ov * ov + oo * vv + vv * (ov + oo);
+  c += (vvvv_mode == ASCC_VVVV_FULL) ? vv * vv : vv * vv;  // packed storage not yet separate
+  s.ints_const = c * 8;
+  long w = 0;
+  w += 2 * Q * n * n + 2 * n * n + Q + Q * ov + Q * oo + Q * vv;
+  w += ov * ov + oo * vv + ov * ov + oo * oo;
+  w += 8 * ov * ov + Q * ov + oo * (ov + oo) + oo * oo + 2 * oo * vv;
+  w += 2 * vv + 2 * oo + ov + 8192;
+  s.ints_work = w * 8;
+  const long len = ov + oo * vv;
+  s.diis = (2L * m * len + 1024L * (3 + kMaxDiis)) * 8 + sizeof(DiisState);
+  return s;
+}
+
+// Unbacked, never dereferenced addresses handed out in a dry run.
+uintptr_t fake_alloc(size_t bytes) {
+  static uintptr_t next = (uintptr_t)1 << 44;
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lk(mu);
+  const uintptr_t p = next;
+  next += (bytes + 4095) / 4096 * 4096 + 4096;
+  return p;
+}
+
+template <class T>
+int dalloc(std::vector<void*>& allocs, size_t& total, T** p, size_t count) {
+  void* q = nullptr;
+  const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+  hipError_t e = dry_run() ? (q = (void*)fake_alloc(bytes), hipSuccess) : hipMalloc(&q, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+    return ASCC_E_NOMEM;
+  }
+  allocs.push_back(q);
+  total += bytes;
+  *p = static_cast<T*>(q);
+  register_buffer(q, bytes);
+  return ASCC_OK;
+}
+
+void free_all(std::vector<void*>& allocs) {
+  if (!dry_run()) (void)hipDeviceSynchronize();
+  for (void* p : allocs) {
+    unregister_buffer(p);
+    if (!dry_run()) (void)hipFree(p);
+  }
+  allocs.clear();
+}
+
+inline Perm4In pin(const double* p, long s0, long s1, long s2, long s3, double coef) {
+  Perm4In x;
+  x.p = p;
+  x.s[0] = s0;
+  x.s[1] = s1;
+  x.s[2] = s2;
+  x.s[3] = s3;
+  x.coef = coef;
+  return x;
+}
+
+// Bt = B Y^T then Bh = X Bt on `nb` stacked n x n matrices (the T1 dressing).
+int dress(const double* src, double* tmp, double* dst, const double* t1, int o, int v, int nb, hipStream_t s) {
+  const long n = o + v, nn = n * n;
+  HIPCHK(d_copy(tmp, src, sizeof(double) * nn * nb, hipMemcpyDeviceToDevice, s));
+  {  // tmp[:, 0:o] += src[:, o:n] t1^T
+    Gemm g;
+    g.M = n;
+    g.N = o;
+    g.K = v;
+    g.A = src + o;
+    g.sam = n;
+    g.sak = 1;
+    g.sa2 = nn;
+    g.B = t1;
+    g.sbk = 1;
+    g.sbn = v;
+    g.C = tmp;
+    g.scm = n;
+    g.scn = 1;
+    g.sc2 = nn;
+    g.beta = 1.0;
+    g.nb2 = nb;
+    HIPCHK(gemm_f64(g, s));
+  }
+  HIPCHK(d_copy(dst, tmp, sizeof(double) * nn * nb, hipMemcpyDeviceToDevice, s));
+  {  // dst[o:n, :] -= t1^T tmp[0:o, :]
+    Gemm g;
+    g.M = v;
+    g.N = n;
+    g.K = o;
+    g.A = t1;
+    g.sam = 1;
+    g.sak = v;
+    g.B = tmp;
+    g.sbk = n;
+    g.sbn = 1;
+    g.sb2 = nn;
+    g.C = dst + o * n;
+    g.scm = n;
+    g.scn = 1;
+    g.sc2 = nn;
+    g.alpha = -1.0;
+    g.beta = 1.0;
+    g.nb2 = nb;
+    HIPCHK(gemm_f64(g, s));
+  }
+  return ASCC_OK;
+}
+
+// F += sign * (2 sum_Q J_Q B_Q - sum_Q B_Q[:,0:o] B_Q[0:o,:]),  J_Q = sum_k B_Q[k][k]
+int add_two_electron_fock(double* F, const double* Bq, double* J, int o, int v, int Q, double sign, hipStream_t s) {
+  const long n = o + v, nn = n * n;
+  HIPCHK(diag_trace(J, Bq, Q, n, o, s));
+  {
+    Gemm g;
+    g.M = 1;
+    g.N = nn;
+    g.K = Q;
+    g.A = J;
+    g.sam = 0;
+    g.sak = 1;
+    g.B = Bq;
+    g.sbk = nn;
+    g.sbn = 1;
+    g.C = F;
+    g.scm = 0;
+    g.scn = 1;
+    g.alpha = 2.0 * sign;
+    g.beta = 1.0;
+    HIPCHK(gemm_f64(g, s));
+  }
+  {
+    Gemm g;
+    g.M = n;
+    g.N = n;
+    g.K = o;
+    g.A = Bq;
+    g.sam = n;
+    g.sak = 1;
+    g.sar = nn;
+    g.B = Bq;
+    g.sbk = n;
+    g.sbn = 1;
+    g.sbr = nn;
+    g.C = F;
+    g.scm = n;
+    g.scn = 1;
+    g.alpha = -sign;
+    g.beta = 1.0;
+    g.nred = Q;
+    HIPCHK(gemm_f64(g, s));
+  }
+  return ASCC_OK;
+}
+
+int residual_fp64(ascc_ints* I, const double* t1, const double* t2, double* r1, double* r2, double* e,
+                  hipStream_t s) {
+  const int o = I->no, v = I->nv, Q = I->naux;
+  const long n = I->n, nn = n * n, ov = I->ov, oo = I->oo, vv = I->vv, ovov = I->ovov;
+  const long wzl = ov + oo;  // row length of WZ and Gwz
+  int rc;
+
+  // --- T1 dressing of B and of the one-electron operator, dressed Fock matrix
+  if ((rc = dress(I->B, I->Bt, I->Bh, t1, o, v, Q, s))) return rc;
+  if ((rc = dress(I->h, I->ht, I->Fh, t1, o, v, 1, s))) return rc;
+  if ((rc = add_two_electron_fock(I->Fh, I->Bh, I->J, o, v, Q, 1.0, s))) return rc;
+
+  // --- contiguous dressed blocks
+  {
+    int d[4] = {Q, o, v, 1};
+    Perm4In x = pin(I->Bh + o * n, nn, 1, n, 0, 1.0);  // B^_ai -> [Q][i][a]
+    HIPCHK(permute4(I->BvoT, d, 0.0, &x, 1, s));
+    int d2[4] = {Q, o, o, 1};
+    x = pin(I->Bh, nn, n, 1, 0, 1.0);
+    HIPCHK(permute4(I->Boo, d2, 0.0, &x, 1, s));
+    int d3[4] = {Q, v, v, 1};
+    x = pin(I->Bh + o * n + o, nn, n, 1, 0, 1.0);
+    HIPCHK(permute4(I->Bvv, d3, 0.0, &x, 1, s));
+    int d4[4] = {o, v, 1, 1};
+    x = pin(I->Fh + o, n, 1, 0, 0, 1.0);  // F^_kc
+    HIPCHK(permute4(I->Fovh, d4, 0.0, &x, 1, s));
+  }
+
+  // --- permuted amplitude views: Tx[iajb] = t2[ijba], U[iajb] = 2 t2[ijab] - t2[ijba]
+  double* Tx = I->TU;
+  double* U = I->TU + ovov;
+  {
+    int d[4] = {o, v, o, v};
+    const long si = (long)o * vv, sj = vv;
+    Perm4In x = pin(t2, si, 1, sj, v, 1.0);
+    HIPCHK(permute4(Tx, d, 0.0, &x, 1, s));
+    Perm4In y[2] = {pin(t2, si, v, sj, 1, 2.0), pin(t2, si, 1, sj, v, -1.0)};
+    HIPCHK(permute4(U, d, 0.0, y, 2, s));
+  }
+
+  // --- density-fitted dressed integral blocks (K = naux)
+  HIPCHK(gemm_f64(gemm_rm(ov, ov, Q, 1.0, I->BvoT, ov, true, I->BvoT, ov, false, 0.0, I->G1, ov), s));  // g^_aibj
+  HIPCHK(gemm_f64(gemm_rm(oo, vv, Q, 1.0, I->Boo, oo, true, I->Bvv, vv, false, 0.0, I->G2, vv), s));    // g^_kiac
+  HIPCHK(gemm_f64(gemm_rm(ov, ov, Q, 1.0, I->BvoT, ov, true, I->Bov, ov, false, 0.0, I->G3, ov), s));   // g^_aikc
+  HIPCHK(gemm_f64(gemm_rm(oo, oo, Q, 1.0, I->Boo, oo, true, I->Boo, oo, false, 0.0, I->G4, oo), s));    // g^_kilj
+  HIPCHK(gemm_f64(gemm_rm(Q, ov, ov, 1.0, I->Bov, ov, false, U, ov, false, 0.0, I->Nq, ov), s));        // N_Q[k,a]
+
+  // --- W_ij[k,b], Z_ij[k,l] in one product against [(kc|bd) | (kc|ld)]
+  HIPCHK(gemm_f64(gemm_rm(oo, wzl, vv, 1.0, t2, vv, false, I->Gwz, wzl, false, 0.0, I->WZ, wzl), s));
+
+  // --- chi[ij][kl] = g^_kilj + Z_ij[k,l]
+  {
+    int d[4] = {o, o, o, o};
+    const long o2 = oo, o3 = oo * o;
+    Perm4In x[2] = {pin(I->G4, o2, 1, o3, o, 1.0), pin(I->WZ + ov, (long)o * wzl, wzl, o, 1, 1.0)};
+    HIPCHK(permute4(I->chi, d, 0.0, x, 2, s));
+  }
+
+  // --- particle-particle ladder over the undressed (ac|bd), plus the hole-hole ladder
+  {
+    Gemm g = gemm_rm(oo, vv, vv, 1.0, t2, vv, false, I->V, vv, true, 0.0, I->RL, vv);
+    HIPCHK(gemm_f64(g, s));
+  }
+  HIPCHK(gemm_f64(gemm_rm(oo, vv, oo, 1.0, I->chi, oo, false, t2, vv, false, 1.0, I->RL, vv), s));
+
+  // --- rings: Y1 = Tx K, Y2 = U L (batched pair)
+  {
+    Gemm g = gemm_rm(ov, ov, ov, 1.0, I->TU, ov, false, I->KL, ov, false, 0.0, I->Y, ov);
+    g.sa2 = ovov;
+    g.sb2 = ovov;
+    g.sc2 = ovov;
+    g.nb2 = 2;
+    HIPCHK(gemm_f64(g, s));
+  }
+  {
+    int d[4] = {o, v, o, v};  // (i, a, k, c)
+    const long si = vv, sa = v, sk = (long)o * vv, sc = 1;  // G2[k][i][a][c]
+    Perm4In x[2] = {pin(I->G2, si, sa, sk, sc, 1.0), pin(I->Y, (long)v * o * v, (long)o * v, v, 1, -0.5)};
+    HIPCHK(permute4(I->XZ, d, 0.0, x, 2, s));
+    Perm4In z[3] = {pin(I->G3, (long)v * o * v, (long)o * v, v, 1, 2.0), pin(I->G2, si, sa, sk, sc, -1.0),
+                    pin(I->Y + ovov, (long)v * o * v, (long)o * v, v, 1, 0.5)};
+    HIPCHK(permute4(I->XZ + ovov, d, 0.0, z, 3, s));
+  }
+  {  // P1 = Tx Xc^T, P2 = U Zd^T
+    Gemm g = gemm_rm(ov, ov, ov, 1.0, I->TU, ov, false, I->XZ, ov, true, 0.0, I->P, ov);
+    g.sa2 = ovov;
+    g.sb2 = ovov;
+    g.sc2 = ovov;
+    g.nb2 = 2;
+    HIPCHK(gemm_f64(g, s));
+  }
+
+  // --- E term: F'_bc = F^_bc - sum_Qk N_Q[k,b] B_Q,kc ; F''_kj = F^_kj + sum_Qd B_Q,kd N_Q[j,d]
+  HIPCHK(gemm_f64(gemm_rm(v, v, (long)Q * o, 1.0, I->Nq, v, true, I->Bov, v, false, 0.0, I->Abc, v), s));
+  {
+    Gemm g;
+    g.M = o;
+    g.N = o;
+    g.K = v;
+    g.A = I->Bov;
+    g.sam = v;
+    g.sak = 1;
+    g.sar = ov;
+    g.B = I->Nq;
+    g.sbk = 1;
+    g.sbn = v;
+    g.sbr = ov;
+    g.C = I->Bkj;
+    g.scm = o;
+    g.scn = 1;
+    g.nred = Q;
+    HIPCHK(gemm_f64(g, s));
+  }
+  {
+    int d[4] = {v, v, 1, 1};
+    Perm4In x[2] = {pin(I->Fh + o * n + o, n, 1, 0, 0, 1.0), pin(I->Abc, v, 1, 0, 0, -1.0)};
+    HIPCHK(permute4(I->Fvvp, d, 0.0, x, 2, s));
+    int d2[4] = {o, o, 1, 1};
+    Perm4In y[2] = {pin(I->Fh, n, 1, 0, 0, 1.0), pin(I->Bkj, o, 1, 0, 0, 1.0)};
+    HIPCHK(permute4(I->Foop, d2, 0.0, y, 2, s));
+  }
+  // EM = sum_c t_ij^ac F'_bc
+  HIPCHK(gemm_f64(gemm_rm(oo * v, v, v, 1.0, t2, v, false, I->Fvvp, v, true, 0.0, I->EM, v), s));
+  {  // EM[i][j][ab] -= sum_k F''_kj t_ik^ab   (batched over i)
+    Gemm g;
+    g.M = o;
+    g.N = vv;
+    g.K = o;
+    g.A = I->Foop;
+    g.sam = 1;
+    g.sak = o;
+    g.B = t2;
+    g.sbk = vv;
+    g.sbn = 1;
+    g.sb2 = (long)o * vv;
+    g.C = I->EM;
+    g.scm = vv;
+    g.scn = 1;
+    g.sc2 = (long)o * vv;
+    g.alpha = -1.0;
+    g.beta = 1.0;
+    g.nb2 = o;
+    HIPCHK(gemm_f64(g, s));
+  }
+  {  // W'_ij[k,b] = W_ij[k,b] - 1/2 sum_l Z_ij[k,l] t_l^b   (batched over ij, in place)
+    Gemm g;
+    g.M = o;
+    g.N = v;
+    g.K = o;
+    g.A = I->WZ + ov;
+    g.sam = o;
+    g.sak = 1;
+    g.sa2 = wzl;
+    g.B = t1;
+    g.sbk = v;
+    g.sbn = 1;
+    g.C = I->WZ;
+    g.scm = v;
+    g.scn = 1;
+    g.sc2 = wzl;
+    g.alpha = -0.5;
+    g.beta = 1.0;
+    g.nb2 = oo;
+    HIPCHK(gemm_f64(g, s));
+  }
+  {  // EM[ij][a][b] -= sum_k t_k^a W'_ij[k,b]
+    Gemm g;
+    g.M = v;
+    g.N = v;
+    g.K = o;
+    g.A = t1;
+    g.sam = 1;
+    g.sak = v;
+    g.B = I->WZ;
+    g.sbk = v;
+    g.sbn = 1;
+    g.sb2 = wzl;
+    g.C = I->EM;
+    g.scm = v;
+    g.scn = 1;
+    g.sc2 = vv;
+    g.alpha = -1.0;
+    g.beta = 1.0;
+    g.nb2 = oo;
+    HIPCHK(gemm_f64(g, s));
+  }
+
+  // --- singles
+  {  // r1[i][a] = sum_Qd N_Q[i,d] B^_Q,ad
+    Gemm g;
+    g.M = o;
+    g.N = v;
+    g.K = v;
+    g.A = I->Nq;
+    g.sam = v;
+    g.sak = 1;
+    g.sar = ov;
+    g.B = I->Bvv;
+    g.sbk = 1;
+    g.sbn = v;
+    g.sbr = vv;
+    g.C = r1;
+    g.scm = v;
+    g.scn = 1;
+    g.nred = Q;
+    HIPCHK(gemm_f64(g, s));
+  }
+  // r1 -= sum_Qk B^_Q,ki N_Q[k,a]
+  HIPCHK(gemm_f64(gemm_rm(o, v, (long)Q * o, -1.0, I->Boo, o, true, I->Nq, v, false, 1.0, r1, v), s));
+  {  // r1[(ia)] += sum_kc U[(ia),(kc)] F^_kc
+    Gemm g;
+    g.M = ov;
+    g.N = 1;
+    g.K = ov;
+    g.A = U;
+    g.sam = ov;
+    g.sak = 1;
+    g.B = I->Fovh;
+    g.sbk = 1;
+    g.sbn = 0;
+    g.C = r1;
+    g.scm = 1;
+    g.scn = 0;
+    g.beta = 1.0;
+    HIPCHK(gemm_f64(g, s));
+  }
+  HIPCHK(add_fvo(r1, I->Fh, o, v, s));
+
+  // --- doubles assembly and energy
+  HIPCHK(assemble_r2(r2, I->G1, I->RL, I->EM, I->P, I->P + ovov, o, v, s));
+  HIPCHK(energy(e, I->partial, t1, t2, I->Lijab, I->fov, o, v, s));
+  return ASCC_OK;
+}
+
+int build_constants(ascc_ints* I, const double* Bsrc, const double* fock, int fock_is_diag, hipStream_t s) {
+  const int o = I->no, v = I->nv, Q = I->naux;
+  const long n = I->n, nn = n * n, ov = I->ov, oo = I->oo, vv = I->vv, ovov = I->ovov;
+  const long wzl = ov + oo;
+  HIPCHK(d_copy(I->B, Bsrc, sizeof(double) * Q * nn, hipMemcpyDeviceToDevice, s));
+  // Fock matrix -> h (start), eps, fov
+  if (fock_is_diag) {
+    HIPCHK(d_copy(I->eps, fock, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    int d[4] = {(int)n, (int)n, 1, 1};
+    // h = diag(eps): write zeros (no inputs), then the diagonal
+    HIPCHK(permute4(I->h, d, 0.0, nullptr, 0, s));
+    long ostr[4] = {n + 1, 0, 0, 0};
+    int dd[4] = {(int)n, 1, 1, 1};
+    Perm4In x = pin(fock, 1, 0, 0, 0, 1.0);
+    HIPCHK(permute4_strided(I->h, ostr, dd, 0.0, &x, 1, s));
+  } else {
+    HIPCHK(d_copy(I->h, fock, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
+    int dd[4] = {(int)n, 1, 1, 1};
+    Perm4In x = pin(fock, n + 1, 0, 0, 0, 1.0);
+    HIPCHK(permute4(I->eps, dd, 0.0, &x, 1, s));
+  }
+  {
+    int d[4] = {o, v, 1, 1};
+    Perm4In x = pin(I->h + o, n, 1, 0, 0, 1.0);  // still the Fock matrix here
+    HIPCHK(permute4(I->fov, d, 0.0, &x, 1, s));
+  }
+  // h = f - sum_k (2 (pq|kk) - (pk|kq))
+  int rc = add_two_electron_fock(I->h, I->B, I->J, o, v, Q, -1.0, s);
+  if (rc) return rc;
+
+  // B_ov and undressed B_vv (the latter into the work array Bvv)
+  {
+    int d[4] = {Q, o, v, 1};
+    Perm4In x = pin(I->B + o, nn, n, 1, 0, 1.0);
+    HIPCHK(permute4(I->Bov, d, 0.0, &x, 1, s));
+    int d2[4] = {Q, v, v, 1};
+    Perm4In y = pin(I->B + o * n + o, nn, n, 1, 0, 1.0);
+    HIPCHK(permute4(I->Bvv, d2, 0.0, &y, 1, s));
+  }
+  // J = (ia|jb) into G1 (work), then K and L
+  double* Jov = I->G1;
+  HIPCHK(gemm_f64(gemm_rm(ov, ov, Q, 1.0, I->Bov, ov, true, I->Bov, ov, false, 0.0, Jov, ov), s));
+  {
+    int d[4] = {o, v, o, v};
+    const long si = (long)v * o * v, sa = (long)o * v, sj = v, sb = 1;
+    Perm4In x = pin(Jov, si, sb, sj, sa, 1.0);  // (ib|ja)
+    HIPCHK(permute4(I->KL, d, 0.0, &x, 1, s));
+    Perm4In y[2] = {pin(Jov, si, sa, sj, sb, 2.0), pin(Jov, si, sb, sj, sa, -1.0)};
+    HIPCHK(permute4(I->KL + ovov, d, 0.0, y, 2, s));
+    int d2[4] = {o, o, v, v};  // (i, j, a, b) <- L[i][a][j][b]
+    Perm4In z = pin(I->KL + ovov, si, sj, sa, sb, 1.0);
+    HIPCHK(permute4(I->Lijab, d2, 0.0, &z, 1, s));
+  }
+  // Gwz: (kc|bd) at [c][d][k*v + b] from a temporary [(k,c)][(b,d)] product
+  {
+    double* tmp = nullptr;
+    std::vector<void*> tmp_alloc;
+    size_t tmp_bytes = 0;
+    int rc2 = dalloc(tmp_alloc, tmp_bytes, &tmp, (size_t)ov * vv);
+    if (rc2) return rc2;
+    hipError_t e = gemm_f64(gemm_rm(ov, vv, Q, 1.0, I->Bov, ov, true, I->Bvv, vv, false, 0.0, tmp, vv), s);
+    if (e == hipSuccess) {
+      long ostr[4] = {(long)v * wzl, wzl, v, 1};
+      int d[4] = {v, v, o, v};  // (c, d, k, b) <- tmp[k][c][b][d]
+      Perm4In x = pin(tmp, vv, 1, (long)v * vv, v, 1.0);
+      e = permute4_strided(I->Gwz, ostr, d, 0.0, &x, 1, s);
+    }
+    if (e == hipSuccess) {
+      long ostr[4] = {(long)v * wzl, wzl, o, 1};
+      int d[4] = {v, v, o, o};  // (c, d, k, l) <- J[k][c][l][d]
+      Perm4In x = pin(Jov, (long)o * v, 1, (long)v * o * v, v, 1.0);
+      e = permute4_strided(I->Gwz + ov, ostr, d, 0.0, &x, 1, s);
+    }
+    if (e == hipSuccess) e = d_sync(s);
+    free_all(tmp_alloc);
+    if (e != hipSuccess) {
+      if (bounds_checking() && e == hipErrorInvalidValue) return ASCC_E_HIP;  // message already set
+      set_error(std::string("building (kc|bd): ") + hipGetErrorString(e));
+      return ASCC_E_HIP;
+    }
+  }
+  // V[a][b][c][d] = (ac|bd) = sum_Q B_Q,ac B_Q,bd, batched over (a, b)
+  {
+    Gemm g;
+    g.M = v;
+    g.N = v;
+    g.K = Q;
+    g.A = I->Bvv;
+    g.sam = 1;
+    g.sak = vv;
+    g.sa1 = v;
+    g.B = I->Bvv;
+    g.sbk = vv;
+    g.sbn = 1;
+    g.sb2 = v;
+    g.C = I->V;
+    g.scm = v;
+    g.scn = 1;
+    g.sc1 = (long)v * vv;
+    g.sc2 = vv;
+    g.nb1 = v;
+    g.nb2 = v;
+    HIPCHK(gemm_f64(g, s));
+  }
+  return ASCC_OK;
+}
+
+int check_shape(int no, int nv, int naux) {
+  if (no < 1 || nv < 1 || naux < 1) return fail(ASCC_E_SHAPE, "no, nv and naux must be >= 1");
+  if (no > 256 || nv > 4096 || naux > 65535)
+    return fail(ASCC_E_SHAPE, "no <= 256, nv <= 4096 and naux <= 65535 are supported");
+  const double n4 = (double)nv * nv * nv * nv;
+  if (n4 > 9.0e18) return fail(ASCC_E_SHAPE, "nv too large");
+  return ASCC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ascc_last_error(void) { return g_last_error.c_str(); }
+
+int ascc_workspace_bytes(int no, int nv, int naux, int precision, int vvvv_mode, int diis_size, size_t* ints_bytes,
+                         size_t* diis_bytes) {
+  int rc = check_shape(no, nv, naux);
+  if (rc) return rc;
+  if (precision != ASCC_PREC_FP64) return fail(ASCC_E_ARG, "unsupported precision");
+  if (vvvv_mode != ASCC_VVVV_FULL) return fail(ASCC_E_ARG, "unsupported vvvv_mode");
+  if (diis_size < 1 || diis_size > kMaxDiis) return fail(ASCC_E_ARG, "diis_size must be in 1..16");
+  Sizes s = sizes_of(no, nv, naux, vvvv_mode, diis_size);
+  if (ints_bytes) *ints_bytes = s.ints_const + s.ints_work;
+  if (diis_bytes) *diis_bytes = s.diis;
+  return ASCC_OK;
+}
+
+int ascc_ints_shape(const ascc_ints* I, int* no, int* nv, int* naux) {
+  if (!I) return fail(ASCC_E_ARG, "NULL handle");
+  if (no) *no = I->no;
+  if (nv) *nv = I->nv;
+  if (naux) *naux = I->naux;
+  return ASCC_OK;
+}
+
+int ascc_build_ints(const double* d_B, const double* d_fock, int fock_is_diag, int no, int nv, int naux, int precision,
+                    int vvvv_mode, void* stream, ascc_ints** out) {
+  if (!out) return fail(ASCC_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (!d_B || !d_fock) return fail(ASCC_E_ARG, "d_B and d_fock must be device pointers");
+  int rc = check_shape(no, nv, naux);
+  if (rc) return rc;
+  if (precision != ASCC_PREC_FP64) return fail(ASCC_E_ARG, "unsupported precision");
+  if (vvvv_mode != ASCC_VVVV_FULL) return fail(ASCC_E_ARG, "unsupported vvvv_mode");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  ascc_ints* I = new ascc_ints();
+  I->no = no;
+  I->nv = nv;
+  I->naux = naux;
+  I->n = no + nv;
+  I->precision = precision;
+  I->vvvv_mode = vvvv_mode;
+  if (!dry_run()) (void)hipGetDevice(&I->device);
+  const long o = no, v = nv, Q = naux, n = o + v, nn = n * n;
+  I->ov = o * v;
+  I->oo = o * o;
+  I->vv = v * v;
+  I->ovov = I->ov * I->ov;
+  I->oovv = I->oo * I->vv;
+  const long ov = I->ov, oo = I->oo, vv = I->vv, ovov = I->ovov;
+  auto& A = I->allocs;
+  size_t& T = I->bytes;
+  rc = ASCC_OK;
+#define ALLOC(ptr, count) \
+  if (!rc) rc = dalloc(A, T, &(ptr), (size_t)(count))
+  ALLOC(I->B, Q * nn);
+  ALLOC(I->h, nn);
+  ALLOC(I->eps, n);
+  ALLOC(I->fov, ov);
+  ALLOC(I->Bov, Q * ov);
+  ALLOC(I->KL, 2 * ovov);
+  ALLOC(I->Lijab, oo * vv);
+  ALLOC(I->Gwz, vv * (ov + oo));
+  ALLOC(I->V, vv * vv);
+  ALLOC(I->Bt, Q * nn);
+  ALLOC(I->Bh, Q * nn);
+  ALLOC(I->ht, nn);
+  ALLOC(I->Fh, nn);
+  ALLOC(I->J, Q);
+  ALLOC(I->BvoT, Q * ov);
+  ALLOC(I->Boo, Q * oo);
+  ALLOC(I->Bvv, Q * vv);
+  ALLOC(I->G1, ovov);
+  ALLOC(I->G2, oo * vv);
+  ALLOC(I->G3, ovov);
+  ALLOC(I->G4, oo * oo);
+  ALLOC(I->TU, 2 * ovov);
+  ALLOC(I->Y, 2 * ovov);
+  ALLOC(I->XZ, 2 * ovov);
+  ALLOC(I->P, 2 * ovov);
+  ALLOC(I->Nq, Q * ov);
+  ALLOC(I->WZ, oo * (ov + oo));
+  ALLOC(I->chi, oo * oo);
+  ALLOC(I->RL, oo * vv);
+  ALLOC(I->EM, oo * vv);
+  ALLOC(I->Abc, vv);
+  ALLOC(I->Bkj, oo);
+  ALLOC(I->Fvvp, vv);
+  ALLOC(I->Foop, oo);
+  ALLOC(I->Fovh, ov);
+  ALLOC(I->partial, 8192);
+#undef ALLOC
+  ScopedBuffers user;
+  user.add(d_B, sizeof(double) * Q * nn);
+  user.add(d_fock, sizeof(double) * (fock_is_diag ? n : nn));
+  if (!rc) rc = build_constants(I, d_B, d_fock, fock_is_diag, s);
+  if (!rc) {
+    hipError_t e = d_sync(s);
+    if (e != hipSuccess) rc = fail(ASCC_E_HIP, std::string("ascc_build_ints: ") + hipGetErrorString(e));
+  }
+  if (rc) {
+    free_all(I->allocs);
+    delete I;
+    return rc;
+  }
+  *out = I;
+  return ASCC_OK;
+}
+
+void ascc_ints_free(ascc_ints* I) {
+  if (!I) return;
+  free_all(I->allocs);
+  delete I;
+}
+
+int ascc_residual(ascc_ints* I, const double* t1, const double* t2, double* r1, double* r2, double* e, void* stream) {
+  if (!I || !t1 || !t2 || !r1 || !r2 || !e) return fail(ASCC_E_ARG, "NULL argument to ascc_residual");
+  ScopedBuffers user;
+  user.add(t1, sizeof(double) * I->ov);
+  user.add(t2, sizeof(double) * I->oovv);
+  user.add(r1, sizeof(double) * I->ov);
+  user.add(r2, sizeof(double) * I->oovv);
+  user.add(e, sizeof(double));
+  return residual_fp64(I, t1, t2, r1, r2, e, static_cast<hipStream_t>(stream));
+}
+
+int ascc_diis_create(const ascc_ints* I, int max_vectors, int start, ascc_diis** out) {
+  if (!I || !out) return fail(ASCC_E_ARG, "NULL argument to ascc_diis_create");
+  *out = nullptr;
+  if (max_vectors < 1 || max_vectors > kMaxDiis) return fail(ASCC_E_ARG, "max_vectors must be in 1..16");
+  if (start < 0) return fail(ASCC_E_ARG, "start must be >= 0");
+  ascc_diis* D = new ascc_diis();
+  D->no = I->no;
+  D->nv = I->nv;
+  D->m = max_vectors;
+  D->start = start;
+  D->calls = 0;
+  D->len = I->ov + I->oovv;
+  size_t T = 0;
+  int rc = dalloc(D->allocs, T, &D->hist_t, (size_t)D->m * D->len);
+  if (!rc) rc = dalloc(D->allocs, T, &D->hist_e, (size_t)D->m * D->len);
+  if (!rc) rc = dalloc(D->allocs, T, &D->partial, (size_t)update_partial_blocks() * (3 + kMaxDiis));
+  if (!rc) rc = dalloc(D->allocs, T, &D->st, 1);
+  if (!rc) rc = ascc_diis_reset(D, nullptr);
+  if (!rc) {
+    hipError_t e = d_sync(nullptr);
+    if (e != hipSuccess) rc = fail(ASCC_E_HIP, std::string("ascc_diis_create: ") + hipGetErrorString(e));
+  }
+  if (rc) {
+    free_all(D->allocs);
+    delete D;
+    return rc;
+  }
+  *out = D;
+  return ASCC_OK;
+}
+
+int ascc_diis_reset(ascc_diis* D, void* stream) {
+  if (!D) return fail(ASCC_E_ARG, "NULL diis");
+  DiisState h;
+  std::memset(&h, 0, sizeof(h));
+  for (int k = 0; k < kMaxDiis; ++k) h.slot_age[k] = -1;
+  // Kept in a static per-call host copy until the async copy has read it: use a blocking copy.
+  HIPCHK(d_copy(D->st, &h, sizeof(h), hipMemcpyHostToDevice, static_cast<hipStream_t>(stream)));
+  HIPCHK(d_sync(static_cast<hipStream_t>(stream)));
+  D->calls = 0;
+  return ASCC_OK;
+}
+
+void ascc_diis_free(ascc_diis* D) {
+  if (!D) return;
+  free_all(D->allocs);
+  delete D;
+}
+
+int ascc_update(ascc_ints* I, ascc_diis* D, double* t1, double* t2, const double* r1, const double* r2,
+                const double* e, double level_shift, double* stats, void* stream) {
+  if (!I || !D || !t1 || !t2 || !r1 || !r2 || !e || !stats) return fail(ASCC_E_ARG, "NULL argument to ascc_update");
+  if (D->no != I->no || D->nv != I->nv) return fail(ASCC_E_STATE, "DIIS state and integrals differ in shape");
+  if (!(level_shift >= 0.0)) return fail(ASCC_E_ARG, "level_shift must be >= 0");
+  ScopedBuffers user;
+  user.add(t1, sizeof(double) * I->ov);
+  user.add(t2, sizeof(double) * I->oovv);
+  user.add(r1, sizeof(double) * I->ov);
+  user.add(r2, sizeof(double) * I->oovv);
+  user.add(e, sizeof(double));
+  user.add(stats, 8 * sizeof(double));
+  UpdateArgs u;
+  u.t1 = t1;
+  u.t2 = t2;
+  u.r1 = r1;
+  u.r2 = r2;
+  u.e = e;
+  u.eps = I->eps;
+  u.hist_t = D->hist_t;
+  u.hist_e = D->hist_e;
+  u.partial = D->partial;
+  u.st = D->st;
+  u.stats = stats;
+  u.no = I->no;
+  u.nv = I->nv;
+  u.m = D->m;
+  u.store = (D->calls >= D->start) ? 1 : 0;
+  u.len = D->len;
+  u.shift = level_shift;
+  HIPCHK(diis_update(u, static_cast<hipStream_t>(stream)));
+  D->calls += 1;
+  return ASCC_OK;
+}
+
+int ascc_solve(ascc_ints* I, const ascc_opts* opts, double* t1, double* t2, ascc_result* res, void* stream) {
+  if (!I || !opts || !t1 || !t2 || !res) return fail(ASCC_E_ARG, "NULL argument to ascc_solve");
+  if (opts->maxiter < 1) return fail(ASCC_E_ARG, "maxiter must be >= 1");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::memset(res, 0, sizeof(*res));
+  ascc_diis* D = nullptr;
+  int rc = ascc_diis_create(I, opts->diis_size, opts->diis_start, &D);
+  if (rc) return rc;
+  std::vector<void*> work;
+  size_t T = 0;
+  double *r1 = nullptr, *r2 = nullptr, *e = nullptr, *stats = nullptr, *t1s = nullptr, *t2s = nullptr;
+  rc = dalloc(work, T, &r1, I->ov);
+  if (!rc) rc = dalloc(work, T, &r2, I->oovv);
+  if (!rc) rc = dalloc(work, T, &e, 1);
+  if (!rc) rc = dalloc(work, T, &stats, 8);
+  if (!rc) rc = dalloc(work, T, &t1s, I->ov);
+  if (!rc) rc = dalloc(work, T, &t2s, I->oovv);
+  double* hstats = nullptr;
+  static double dry_stats[8];
+  if (dry_run()) {
+    hstats = dry_stats;  // a dry run reports zeros: converged after one iteration
+  } else if (!rc && hipHostMalloc((void**)&hstats, 8 * sizeof(double), 0) != hipSuccess) {
+    rc = fail(ASCC_E_NOMEM, "pinned host allocation failed");
+  }
+  ScopedBuffers user;
+  user.add(t1, sizeof(double) * I->ov);
+  user.add(t2, sizeof(double) * I->oovv);
+  int status = ASCC_E_NOT_CONVERGED;
+  for (int it = 0; !rc && it < opts->maxiter; ++it) {
+    rc = residual_fp64(I, t1, t2, r1, r2, e, s);
+    if (rc) break;
+    // statistics of the residual at the current amplitudes, without changing them: run the
+    // update on a copy (the copy also carries the DIIS bookkeeping of this iteration)
+    if (d_copy(t1s, t1, sizeof(double) * I->ov, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        d_copy(t2s, t2, sizeof(double) * I->oovv, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+      rc = fail(ASCC_E_HIP, "copy of amplitudes failed");
+      break;
+    }
+    rc = ascc_update(I, D, t1s, t2s, r1, r2, e, opts->level_shift, stats, stream);
+    if (rc) break;
+    if (d_copy(hstats, stats, 8 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess || d_sync(s) != hipSuccess) {
+      rc = fail(ASCC_E_HIP, "reading iteration statistics failed");
+      break;
+    }
+    res->e_corr = hstats[0];
+    res->de = hstats[1];
+    res->rmax = hstats[2];
+    res->rnorm = hstats[3];
+    res->iterations = it + 1;
+    if (((int)hstats[5]) & 1) {
+      status = fail(ASCC_E_NONFINITE, "non-finite residual or energy at iteration " + std::to_string(it));
+      break;
+    }
+    const bool ok = (opts->tol_rnorm <= 0 || hstats[3] <= opts->tol_rnorm) &&
+                    (opts->tol_rmax <= 0 || hstats[2] <= opts->tol_rmax) &&
+                    (opts->tol_de <= 0 || std::fabs(hstats[1]) < opts->tol_de);
+    if (ok) {
+      res->converged = 1;
+      status = ASCC_OK;
+      break;
+    }
+    // accept the update
+    if (d_copy(t1, t1s, sizeof(double) * I->ov, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        d_copy(t2, t2s, sizeof(double) * I->oovv, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+      rc = fail(ASCC_E_HIP, "copy of amplitudes failed");
+      break;
+    }
+  }
+  (void)d_sync(s);
+  if (hstats && !dry_run()) (void)hipHostFree(hstats);
+  free_all(work);
+  ascc_diis_free(D);
+  if (rc) return rc;
+  if (status == ASCC_E_NOT_CONVERGED) set_error("not converged in maxiter iterations");
+  return status;
+}
+
+}  // extern "C"

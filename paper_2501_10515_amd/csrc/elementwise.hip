@@ -1,0 +1,529 @@
+// Element-wise and reduction kernels of the residual, the energy and the Jacobi/DIIS update.
+//
+// Reductions are deterministic: a fixed grid, a fixed per-thread stride pattern, a fixed
+// wave64 shuffle tree and a fixed second stage, with no floating-point atomics, so the same
+// inputs always give bitwise the same energy, norms and DIIS coefficients.
+#include <cmath>
+
+#include "internal.h"
+
+namespace ascc {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kRedBlocks = 1024;  // first-stage blocks of every reduction
+
+struct P4 {
+  double* out;
+  long os[4];
+  int d[4];
+  double c0;
+  int nin;
+  const double* in[4];
+  long s[4][4];
+  double coef[4];
+};
+
+__global__ __launch_bounds__(kThreads) void permute4_kernel(P4 p, long total) {
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+    long r = idx;
+    const int i3 = r % p.d[3];
+    r /= p.d[3];
+    const int i2 = r % p.d[2];
+    r /= p.d[2];
+    const int i1 = r % p.d[1];
+    const int i0 = r / p.d[1];
+    double* o = p.out + i0 * p.os[0] + i1 * p.os[1] + i2 * p.os[2] + i3 * p.os[3];
+    double v = (p.c0 == 0.0) ? 0.0 : p.c0 * *o;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      if (t < p.nin) v += p.coef[t] * p.in[t][i0 * p.s[t][0] + i1 * p.s[t][1] + i2 * p.s[t][2] + i3 * p.s[t][3]];
+    *o = v;
+  }
+}
+
+// Doubles residual, element (i,j,a,b) of the [o][o][v][v] output:
+//   R = G1[iajb] + RL[ijab] + EM[ijab] + EM[jiba]
+//       - 1/2 (P1[jbia] + P1[iajb]) + 1/2 (P2[jbia] + P2[iajb]) - (P1[ibja] + P1[jaib])
+// (ovov arrays are [o][v][o][v]).
+__global__ __launch_bounds__(kThreads) void assemble_r2_kernel(double* __restrict__ r2, const double* __restrict__ g1,
+                                                              const double* __restrict__ rl,
+                                                              const double* __restrict__ em,
+                                                              const double* __restrict__ p1,
+                                                              const double* __restrict__ p2, int o, int v, long total) {
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+    long r = idx;
+    const int b = r % v;
+    r /= v;
+    const int a = r % v;
+    r /= v;
+    const int j = r % o;
+    const int i = r / o;
+    auto ov = [&](int p, int x, int q, int y) -> long { return ((long)(p * v + x) * o + q) * v + y; };
+    auto oo = [&](int p, int q, int x, int y) -> long { return ((long)(p * o + q) * v + x) * v + y; };
+    const long iajb = ov(i, a, j, b), jbia = ov(j, b, i, a), ibja = ov(i, b, j, a), jaib = ov(j, a, i, b);
+    double x = g1[iajb] + rl[idx] + em[idx] + em[oo(j, i, b, a)];
+    x += -0.5 * (p1[jbia] + p1[iajb]) + 0.5 * (p2[jbia] + p2[iajb]) - (p1[ibja] + p1[jaib]);
+    r2[idx] = x;
+  }
+}
+
+__global__ void add_fvo_kernel(double* r1, const double* F, int o, int v) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < o * v) {
+    const int i = idx / v, a = idx % v;
+    r1[idx] += F[(long)(o + a) * (o + v) + i];
+  }
+}
+
+__global__ void diag_trace_kernel(double* J, const double* Bh, int naux, int n, int no) {
+  const int Q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (Q < naux) {
+    const double* b = Bh + (long)Q * n * n;
+    double s = 0.0;
+    for (int k = 0; k < no; ++k) s += b[(long)k * n + k];
+    J[Q] = s;
+  }
+}
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+  return x;
+}
+__device__ __forceinline__ double wave_max(double x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_down(x, off, 64));
+  return x;
+}
+
+// Block sum of one value per thread; result valid in thread 0.
+__device__ double block_sum(double x, double* sh) {
+  x = wave_sum(x);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = x;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += sh[k];
+  return s;
+}
+__device__ double block_max(double x, double* sh) {
+  x = wave_max(x);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = x;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s = fmax(s, sh[k]);
+  return s;
+}
+
+__global__ __launch_bounds__(kThreads) void energy_stage1(double* partial, const double* __restrict__ t1,
+                                                         const double* __restrict__ t2,
+                                                         const double* __restrict__ L, int o, int v, long total) {
+  __shared__ double sh[kThreads / 64];
+  double acc = 0.0;
+  const long vv = (long)v * v, ovv = (long)o * vv;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+    const int i = idx / ovv;
+    const int j = (idx / vv) % o;
+    const int a = (idx / v) % v;
+    const int b = idx % v;
+    acc += (t2[idx] + t1[i * v + a] * t1[j * v + b]) * L[idx];
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kThreads) void energy_stage2(double* e, const double* partial, int nblk,
+                                                         const double* t1, const double* fov, int nov) {
+  __shared__ double sh[kThreads / 64];
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < nblk; k += blockDim.x) acc += partial[k];
+  for (int k = threadIdx.x; k < nov; k += blockDim.x) acc += 2.0 * fov[k] * t1[k];
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) *e = s;
+}
+
+// ---------------------------------------------------------------------------------------
+// Jacobi step + DIIS.
+//
+// Element x of the amplitude vector t1 (+) t2 gets s = R/D, t_new = t + s.  When the call
+// stores a DIIS pair, (t_new, s) go to history slot `head`, and the overlaps <s, e_k> with
+// every stored error vector are accumulated (the new slot's own entry is <s, s>).
+// Partial sums per block: [0] sum R^2, [1] max|R|, [2] non-finite count, [3 + k] <s, e_k>.
+
+__device__ __forceinline__ double denom(long x, int o, int v, const double* eps, double shift) {
+  const long ov = (long)o * v;
+  if (x < ov) {
+    const int i = x / v, a = x % v;
+    return eps[i] - eps[o + a] - shift;
+  }
+  const long y = x - ov, vv = (long)v * v, ovv = (long)o * vv;
+  const int i = y / ovv, j = (y / vv) % o, a = (y / v) % v, b = y % v;
+  return eps[i] + eps[j] - eps[o + a] - eps[o + b] - shift;
+}
+
+struct UK {
+  double* t1;
+  double* t2;
+  const double* r1;
+  const double* r2;
+  const double* eps;
+  double* hist_t;
+  double* hist_e;
+  double* partial;
+  const DiisState* st;
+  int o, v, m, store, nstat;
+  long len;
+  double shift;
+};
+
+__global__ __launch_bounds__(kThreads) void update_stage1(UK p) {
+  __shared__ double sh[kThreads / 64];
+  const int head = p.st->head;
+  bool valid[kMaxDiis];
+  for (int k = 0; k < kMaxDiis; ++k) valid[k] = p.store && k < p.m && (k == head || p.st->slot_age[k] >= 0);
+  double dots[kMaxDiis];
+  for (int k = 0; k < kMaxDiis; ++k) dots[k] = 0.0;
+  double rr = 0.0, rmax = 0.0, bad = 0.0;
+  const long ov = (long)p.o * p.v;
+  for (long x = blockIdx.x * (long)blockDim.x + threadIdx.x; x < p.len; x += (long)gridDim.x * blockDim.x) {
+    const double r = (x < ov) ? p.r1[x] : p.r2[x - ov];
+    double* tp = (x < ov) ? (p.t1 + x) : (p.t2 + (x - ov));
+    const double s = r / denom(x, p.o, p.v, p.eps, p.shift);
+    const double tn = *tp + s;
+    *tp = tn;
+    rr += r * r;
+    rmax = fmax(rmax, fabs(r));
+    if (!isfinite(r)) bad += 1.0;
+    if (p.store) {
+      for (int k = 0; k < kMaxDiis; ++k)
+        if (valid[k]) dots[k] += s * ((k == head) ? s : p.hist_e[(long)k * p.len + x]);
+      p.hist_t[(long)head * p.len + x] = tn;
+      p.hist_e[(long)head * p.len + x] = s;
+    }
+  }
+  double* out = p.partial + (long)blockIdx.x * p.nstat;
+  double v = block_sum(rr, sh);
+  if (threadIdx.x == 0) out[0] = v;
+  v = block_max(rmax, sh);
+  if (threadIdx.x == 0) out[1] = v;
+  v = block_sum(bad, sh);
+  if (threadIdx.x == 0) out[2] = v;
+  for (int k = 0; k < p.m; ++k) {
+    v = block_sum(dots[k], sh);
+    if (threadIdx.x == 0) out[3 + k] = v;
+  }
+}
+
+// Bordered DIIS system over the valid slots, oldest first; returns false if a pivot is tiny.
+__device__ bool diis_solve(DiisState* st, int m) {
+  int order[kMaxDiis];
+  int nv = 0;
+  for (int k = 0; k < m; ++k)
+    if (st->slot_age[k] >= 0) order[nv++] = k;
+  for (int x = 1; x < nv; ++x)  // insertion sort by age (oldest first)
+    for (int y = x; y > 0 && st->slot_age[order[y - 1]] > st->slot_age[order[y]]; --y) {
+      const int t = order[y];
+      order[y] = order[y - 1];
+      order[y - 1] = t;
+    }
+  constexpr int W = kMaxDiis + 2;
+  double A[(kMaxDiis + 1) * W];
+  const int nn = nv + 1;
+  double scale = 0.0;
+  for (int r = 0; r < nv; ++r)
+    for (int c = 0; c < nv; ++c) scale = fmax(scale, fabs(st->Bm[order[r] * kMaxDiis + order[c]]));
+  for (int r = 0; r < nn; ++r)
+    for (int c = 0; c <= nn; ++c) {
+      double x;
+      if (c == nn)
+        x = (r == nv) ? -1.0 : 0.0;
+      else if (r < nv && c < nv)
+        x = st->Bm[order[r] * kMaxDiis + order[c]];
+      else if (r == nv && c == nv)
+        x = 0.0;
+      else
+        x = -1.0;
+      A[r * W + c] = x;
+    }
+  for (int c = 0; c < nn; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < nn; ++r)
+      if (fabs(A[r * W + c]) > fabs(A[piv * W + c])) piv = r;
+    if (!(fabs(A[piv * W + c]) >= 1e-14 * scale)) return false;
+    if (piv != c)
+      for (int k = 0; k <= nn; ++k) {
+        const double t = A[c * W + k];
+        A[c * W + k] = A[piv * W + k];
+        A[piv * W + k] = t;
+      }
+    for (int r = c + 1; r < nn; ++r) {
+      const double f = A[r * W + c] / A[c * W + c];
+      for (int k = c; k <= nn; ++k) A[r * W + k] -= f * A[c * W + k];
+    }
+  }
+  double xs[kMaxDiis + 1];
+  for (int r = nn - 1; r >= 0; --r) {
+    double acc = A[r * W + nn];
+    for (int k = r + 1; k < nn; ++k) acc -= A[r * W + k] * xs[k];
+    xs[r] = acc / A[r * W + r];
+  }
+  for (int k = 0; k < kMaxDiis; ++k) st->coef[k] = 0.0;
+  for (int r = 0; r < nv; ++r) st->coef[order[r]] = xs[r];
+  return true;
+}
+
+__global__ __launch_bounds__(kThreads) void update_stage2(DiisState* st, const double* partial, int nblk, int nstat,
+                                                         int m, int store, const double* e, double* stats,
+                                                         double shift) {
+  __shared__ double sh[kThreads / 64];
+  __shared__ double red[3 + kMaxDiis];
+  double a = 0.0;
+  for (int k = threadIdx.x; k < nblk; k += blockDim.x) a += partial[(long)k * nstat + 0];
+  double v = block_sum(a, sh);
+  if (threadIdx.x == 0) red[0] = v;
+  a = 0.0;
+  for (int k = threadIdx.x; k < nblk; k += blockDim.x) a = fmax(a, partial[(long)k * nstat + 1]);
+  v = block_max(a, sh);
+  if (threadIdx.x == 0) red[1] = v;
+  a = 0.0;
+  for (int k = threadIdx.x; k < nblk; k += blockDim.x) a += partial[(long)k * nstat + 2];
+  v = block_sum(a, sh);
+  if (threadIdx.x == 0) red[2] = v;
+  for (int q = 0; q < m; ++q) {
+    a = 0.0;
+    for (int k = threadIdx.x; k < nblk; k += blockDim.x) a += partial[(long)k * nstat + 3 + q];
+    v = block_sum(a, sh);
+    if (threadIdx.x == 0) red[3 + q] = v;
+  }
+  if (threadIdx.x != 0) return;
+
+  const double E = *e;
+  int flags = 0;
+  if (red[2] > 0.0 || !isfinite(E) || !isfinite(red[0])) flags |= 1;
+  if (store) {
+    const int head = st->head;
+    for (int k = 0; k < m; ++k)
+      if (k == head || st->slot_age[k] >= 0) {
+        st->Bm[head * kMaxDiis + k] = red[3 + k];
+        st->Bm[k * kMaxDiis + head] = red[3 + k];
+      }
+    st->slot_age[head] = st->counter++;
+    st->head = (head + 1) % m;
+    int nvalid = 0;
+    for (int k = 0; k < m; ++k) nvalid += (st->slot_age[k] >= 0);
+    st->nvec = nvalid;
+    for (int k = 0; k < kMaxDiis; ++k) st->coef[k] = 0.0;
+    while (st->nvec >= 2 && !(flags & 1)) {
+      if (diis_solve(st, m)) break;
+      int oldest = -1;
+      for (int k = 0; k < m; ++k)
+        if (st->slot_age[k] >= 0 && (oldest < 0 || st->slot_age[k] < st->slot_age[oldest])) oldest = k;
+      st->slot_age[oldest] = -1;
+      st->nvec -= 1;
+      flags |= 2;
+      for (int k = 0; k < kMaxDiis; ++k) st->coef[k] = 0.0;
+    }
+  }
+  stats[0] = E;
+  stats[1] = st->has_prev ? E - st->e_prev : INFINITY;
+  stats[2] = red[1];
+  stats[3] = sqrt(red[0]);
+  stats[4] = st->nvec;
+  stats[5] = flags;
+  stats[6] = st->calls;
+  stats[7] = shift;
+  st->e_prev = E;
+  st->has_prev = 1;
+  st->flags = flags;
+  st->calls += 1;
+}
+
+// t <- sum_k coef[k] hist_t[k] once two or more pairs are stored (no-op otherwise).
+__global__ __launch_bounds__(kThreads) void update_stage3(double* t1, double* t2, const double* hist_t,
+                                                         const DiisState* st, int m, long ov, long len) {
+  if (st->nvec < 2 || (st->flags & 1)) return;
+  double c[kMaxDiis];
+  for (int k = 0; k < kMaxDiis; ++k) c[k] = (k < m) ? st->coef[k] : 0.0;
+  for (long x = blockIdx.x * (long)blockDim.x + threadIdx.x; x < len; x += (long)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int k = 0; k < m; ++k)
+      if (c[k] != 0.0) acc += c[k] * hist_t[(long)k * len + x];
+    if (x < ov)
+      t1[x] = acc;
+    else
+      t2[x - ov] = acc;
+  }
+}
+
+inline int grid_for(long total) {
+  long g = (total + kThreads - 1) / kThreads;
+  if (g > 8192) g = 8192;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+}  // namespace
+
+static bool p4_in_bounds(const P4& p) {
+  const char* names[4] = {"permute input 0", "permute input 1", "permute input 2", "permute input 3"};
+  long lo = 0, hi = 0;
+  for (int k = 0; k < 4; ++k) {
+    const long d = (long)(p.d[k] - 1) * p.os[k];
+    if (d < 0) lo += d; else hi += d;
+  }
+  if (!range_ok(p.out, lo, hi, sizeof(double), "permute output")) return false;
+  for (int t = 0; t < p.nin; ++t) {
+    lo = hi = 0;
+    for (int k = 0; k < 4; ++k) {
+      const long d = (long)(p.d[k] - 1) * p.s[t][k];
+      if (d < 0) lo += d; else hi += d;
+    }
+    if (!range_ok(p.in[t], lo, hi, sizeof(double), names[t])) return false;
+  }
+  return true;
+}
+
+hipError_t permute4(double* out, const int dims[4], double c0, const Perm4In* in, int nin, hipStream_t s) {
+  // contiguous output with the given dims
+  P4 p{};
+  p.out = out;
+  p.os[3] = 1;
+  p.os[2] = dims[3];
+  p.os[1] = (long)dims[3] * dims[2];
+  p.os[0] = (long)dims[3] * dims[2] * dims[1];
+  for (int k = 0; k < 4; ++k) p.d[k] = dims[k];
+  p.c0 = c0;
+  p.nin = nin;
+  for (int t = 0; t < nin; ++t) {
+    p.in[t] = in[t].p;
+    p.coef[t] = in[t].coef;
+    for (int k = 0; k < 4; ++k) p.s[t][k] = in[t].s[k];
+  }
+  const long total = (long)dims[0] * dims[1] * dims[2] * dims[3];
+  if (total <= 0) return hipSuccess;
+  if (bounds_checking() && !p4_in_bounds(p)) return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  hipLaunchKernelGGL(permute4_kernel, dim3(grid_for(total)), dim3(kThreads), 0, s, p, total);
+  return hipGetLastError();
+}
+
+hipError_t permute4_strided(double* out, const long ostr[4], const int dims[4], double c0, const Perm4In* in,
+                            int nin, hipStream_t s) {
+  P4 p{};
+  p.out = out;
+  for (int k = 0; k < 4; ++k) {
+    p.os[k] = ostr[k];
+    p.d[k] = dims[k];
+  }
+  p.c0 = c0;
+  p.nin = nin;
+  for (int t = 0; t < nin; ++t) {
+    p.in[t] = in[t].p;
+    p.coef[t] = in[t].coef;
+    for (int k = 0; k < 4; ++k) p.s[t][k] = in[t].s[k];
+  }
+  const long total = (long)dims[0] * dims[1] * dims[2] * dims[3];
+  if (total <= 0) return hipSuccess;
+  if (bounds_checking() && !p4_in_bounds(p)) return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  hipLaunchKernelGGL(permute4_kernel, dim3(grid_for(total)), dim3(kThreads), 0, s, p, total);
+  return hipGetLastError();
+}
+
+hipError_t assemble_r2(double* r2, const double* g1, const double* rl, const double* em, const double* p1,
+                       const double* p2, int no, int nv, hipStream_t s) {
+  const long total = (long)no * no * nv * nv;
+  const long ovov = (long)no * nv * no * nv;
+  if (bounds_checking() &&
+      !(range_ok(r2, 0, total - 1, 8, "assemble r2") && range_ok(g1, 0, ovov - 1, 8, "assemble g1") &&
+        range_ok(rl, 0, total - 1, 8, "assemble rl") && range_ok(em, 0, total - 1, 8, "assemble em") &&
+        range_ok(p1, 0, ovov - 1, 8, "assemble p1") && range_ok(p2, 0, ovov - 1, 8, "assemble p2")))
+    return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  hipLaunchKernelGGL(assemble_r2_kernel, dim3(grid_for(total)), dim3(kThreads), 0, s, r2, g1, rl, em, p1, p2, no,
+                     nv, total);
+  return hipGetLastError();
+}
+
+hipError_t add_fvo(double* r1, const double* fhat, int no, int nv, hipStream_t s) {
+  const int total = no * nv;
+  const long n = no + nv;
+  if (bounds_checking() && !(range_ok(r1, 0, total - 1, 8, "add_fvo r1") && range_ok(fhat, 0, n * n - 1, 8, "add_fvo F")))
+    return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  hipLaunchKernelGGL(add_fvo_kernel, dim3((total + 255) / 256), dim3(256), 0, s, r1, fhat, no, nv);
+  return hipGetLastError();
+}
+
+hipError_t diag_trace(double* J, const double* Bh, int naux, int n, int no, hipStream_t s) {
+  if (bounds_checking() && !(range_ok(J, 0, naux - 1, 8, "trace J") &&
+                             range_ok(Bh, 0, (long)naux * n * n - 1, 8, "trace B")))
+    return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  hipLaunchKernelGGL(diag_trace_kernel, dim3((naux + 255) / 256), dim3(256), 0, s, J, Bh, naux, n, no);
+  return hipGetLastError();
+}
+
+hipError_t energy(double* e, double* partial, const double* t1, const double* t2, const double* Lijab,
+                  const double* fov, int no, int nv, hipStream_t s) {
+  const long total = (long)no * no * nv * nv;
+  if (bounds_checking() &&
+      !(range_ok(e, 0, 0, 8, "energy e") && range_ok(partial, 0, kRedBlocks - 1, 8, "energy partial") &&
+        range_ok(t1, 0, (long)no * nv - 1, 8, "energy t1") && range_ok(t2, 0, total - 1, 8, "energy t2") &&
+        range_ok(Lijab, 0, total - 1, 8, "energy L") && range_ok(fov, 0, (long)no * nv - 1, 8, "energy fov")))
+    return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  hipLaunchKernelGGL(energy_stage1, dim3(kRedBlocks), dim3(kThreads), 0, s, partial, t1, t2, Lijab, no, nv, total);
+  hipLaunchKernelGGL(energy_stage2, dim3(1), dim3(kThreads), 0, s, e, partial, kRedBlocks, t1, fov, no * nv);
+  return hipGetLastError();
+}
+
+int update_partial_blocks() { return kRedBlocks; }
+
+hipError_t diis_update(const UpdateArgs& u, hipStream_t s) {
+  // Whether this call stores a pair is decided by the caller; the device state decides the
+  // slot, which stored pairs are valid and the coefficients.
+  UK p;
+  p.t1 = u.t1;
+  p.t2 = u.t2;
+  p.r1 = u.r1;
+  p.r2 = u.r2;
+  p.eps = u.eps;
+  p.hist_t = u.hist_t;
+  p.hist_e = u.hist_e;
+  p.partial = u.partial;
+  p.st = u.st;
+  p.o = u.no;
+  p.v = u.nv;
+  p.m = u.m;
+  p.store = u.store;
+  p.nstat = 3 + kMaxDiis;
+  p.len = u.len;
+  p.shift = u.shift;
+  const long ov = (long)u.no * u.nv;
+  if (bounds_checking() &&
+      !(range_ok(u.t1, 0, ov - 1, 8, "update t1") && range_ok(u.t2, 0, u.len - ov - 1, 8, "update t2") &&
+        range_ok(u.r1, 0, ov - 1, 8, "update r1") && range_ok(u.r2, 0, u.len - ov - 1, 8, "update r2") &&
+        range_ok(u.e, 0, 0, 8, "update e") && range_ok(u.eps, 0, u.no + u.nv - 1, 8, "update eps") &&
+        range_ok(u.hist_t, 0, (long)u.m * u.len - 1, 8, "update hist_t") &&
+        range_ok(u.hist_e, 0, (long)u.m * u.len - 1, 8, "update hist_e") &&
+        range_ok(u.partial, 0, (long)kRedBlocks * (3 + kMaxDiis) - 1, 8, "update partial") &&
+        range_ok(u.st, 0, 0, sizeof(DiisState), "update state") && range_ok(u.stats, 0, 7, 8, "update stats")))
+    return hipErrorInvalidValue;
+  if (u.m < 1 || u.m > kMaxDiis) return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  hipLaunchKernelGGL(update_stage1, dim3(kRedBlocks), dim3(kThreads), 0, s, p);
+  hipLaunchKernelGGL(update_stage2, dim3(1), dim3(kThreads), 0, s, u.st, u.partial, kRedBlocks, 3 + kMaxDiis,
+                     u.m, u.store, u.e, u.stats, u.shift);
+  hipLaunchKernelGGL(update_stage3, dim3(grid_for(u.len)), dim3(kThreads), 0, s, u.t1, u.t2, u.hist_t, u.st, u.m,
+                     (long)u.no * u.nv, u.len);
+  return hipGetLastError();
+}
+
+}  // namespace ascc

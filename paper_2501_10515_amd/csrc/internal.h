@@ -1,0 +1,128 @@
+// Internal declarations shared by the libascc translation units (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+namespace ascc {
+
+// Status used inside the library; converted to the ASCC_E_* codes at the ABI boundary.
+struct Error {
+  int code;
+  std::string msg;
+};
+
+void set_error(const std::string& msg);
+
+// Optional host-side bounds checking of every strided launch (environment variable
+// ASCC_CHECK_BOUNDS=1): device buffers are registered with their sizes, and each GEMM /
+// permute launch first verifies that the lowest and highest element it can touch lie in one
+// registered buffer.  A violation is reported as an error instead of being launched.
+bool bounds_checking();
+// Dry run (environment variable ASCC_DRY_RUN=1, implies bounds checking): device
+// allocations return unbacked addresses and no kernel, copy or synchronisation is issued,
+// so the complete host-side launch sequence -- every stride and extent -- can be validated
+// on a machine without a GPU.
+bool dry_run();
+void register_buffer(const void* p, size_t bytes);
+void unregister_buffer(const void* p);
+// true if [base + lo, base + hi] (in elements of `elem` bytes) lies inside a registered buffer
+bool range_ok(const void* base, long lo, long hi, size_t elem, const char* what);
+
+// ---------------------------------------------------------------------------------------
+// Strided batched FP64 GEMM on the matrix cores:
+//   C_z(m,n) = alpha * sum_{r < nred} sum_k A_{z,r}(m,k) B_{z,r}(k,n) + beta * C_z(m,n)
+// Every operand is a general strided 2-D view, e.g. A(m,k) = A[m*sam + k*sak].  The batch
+// index z runs over nb1 x nb2 (z1 outer, z2 inner) with one stride per level; the reduction
+// index r (nred >= 1) adds products of further (A, B) pairs into the same C.
+// beta == 0 never reads C.
+struct Gemm {
+  int M = 0, N = 0, K = 0;
+  const double* A = nullptr;
+  long sam = 0, sak = 0, sa1 = 0, sa2 = 0, sar = 0;
+  const double* B = nullptr;
+  long sbk = 0, sbn = 0, sb1 = 0, sb2 = 0, sbr = 0;
+  double* C = nullptr;
+  long scm = 0, scn = 0, sc1 = 0, sc2 = 0;
+  double alpha = 1.0, beta = 0.0;
+  int nb1 = 1, nb2 = 1, nred = 1;
+};
+
+// Convenience constructors for row-major matrices:
+//   A is M x K with leading dimension lda (ta = false) or stored K x M (ta = true), etc.
+Gemm gemm_rm(int M, int N, int K, double alpha, const double* A, long lda, bool ta, const double* B, long ldb,
+             bool tb, double beta, double* C, long ldc);
+
+hipError_t gemm_f64(const Gemm& g, hipStream_t s);
+
+// ---------------------------------------------------------------------------------------
+// Element-wise kernels (elementwise.hip).
+
+// out[i0,i1,i2,i3] = c0*out + sum_t coef[t] * in_t[i0*s_t0 + i1*s_t1 + i2*s_t2 + i3*s_t3]
+// for up to four strided inputs (an input with coef 0 is not read; c0 == 0 never reads out).
+struct Perm4In {
+  const double* p = nullptr;
+  long s[4] = {0, 0, 0, 0};
+  double coef = 0.0;
+};
+hipError_t permute4(double* out, const int dims[4], double c0, const Perm4In* in, int nin, hipStream_t s);
+// Same with an explicitly strided output view.
+hipError_t permute4_strided(double* out, const long ostr[4], const int dims[4], double c0, const Perm4In* in,
+                            int nin, hipStream_t s);
+
+// Assembly of the doubles residual (see residual.hip for the formula).
+hipError_t assemble_r2(double* r2, const double* g1, const double* rl, const double* em, const double* p1,
+                       const double* p2, int no, int nv, hipStream_t s);
+
+// r1[i][a] += Fhat[no+a][i]
+hipError_t add_fvo(double* r1, const double* fhat, int no, int nv, hipStream_t s);
+
+// J[Q] = sum_k Bh[Q][k][k]
+hipError_t diag_trace(double* J, const double* Bh, int naux, int n, int no, hipStream_t s);
+
+// Deterministic two-stage energy reduction:
+//   e = sum_{ijab} (t2 + t1_ia t1_jb) L[ijab] + 2 sum_ia f_ia t1_ia
+hipError_t energy(double* e, double* partial, const double* t1, const double* t2, const double* Lijab,
+                  const double* fov, int no, int nv, hipStream_t s);
+
+// DIIS device state (one per amplitude set), kept in device memory.
+constexpr int kMaxDiis = 16;
+struct DiisState {
+  int nvec;     // stored pairs
+  int head;     // slot that receives the next pair
+  int calls;    // update calls so far
+  int flags;    // last call's flags
+  double e_prev;
+  int has_prev;
+  int pad_;
+  double Bm[kMaxDiis * kMaxDiis];  // error-vector overlaps, indexed by slot
+  double coef[kMaxDiis];           // extrapolation coefficients by slot (0 for unused)
+  int slot_age[kMaxDiis];          // insertion counter of each slot (-1 empty)
+  int counter;
+  int pad2_;
+};
+
+struct UpdateArgs {
+  double* t1;
+  double* t2;
+  const double* r1;
+  const double* r2;
+  const double* e;
+  const double* eps;  // diagonal of the Fock matrix [n]
+  double* hist_t;     // [m][len]
+  double* hist_e;     // [m][len]
+  double* partial;    // [nblk][2 + m] reduction scratch
+  DiisState* st;
+  double* stats;
+  int no, nv, m;
+  int store;  // 1: this call stores its (amplitudes, step) pair in the history
+  long len;   // no*nv + no*no*nv*nv
+  double shift;
+};
+hipError_t diis_update(const UpdateArgs& u, hipStream_t s);
+int update_partial_blocks();
+
+}  // namespace ascc

@@ -1,0 +1,81 @@
+"""Drive the whole libascc launch sequence without a GPU (ASCC_DRY_RUN=1) and report.
+
+Run as a separate process (the library reads ASCC_DRY_RUN once).  Caller buffers are fake,
+unbacked addresses; the library registers them with the sizes the C ABI defines and checks
+the lowest and highest element of every GEMM, permute, copy and kernel launch against them.
+Prints one line "OK <no> <nv> <naux>" per shape, or the failing status and message.
+"""
+import ctypes
+import os
+import sys
+
+os.environ["ASCC_DRY_RUN"] = "1"
+from pathlib import Path  # noqa: E402
+
+LIB = Path(__file__).resolve().parents[1] / "paper_2501_10515_amd" / "libascc.so"
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("tol_rnorm", ctypes.c_double), ("tol_rmax", ctypes.c_double), ("tol_de", ctypes.c_double),
+                ("maxiter", ctypes.c_int), ("diis_size", ctypes.c_int), ("diis_start", ctypes.c_int),
+                ("level_shift", ctypes.c_double)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("e_corr", ctypes.c_double), ("rnorm", ctypes.c_double), ("rmax", ctypes.c_double),
+                ("de", ctypes.c_double), ("iterations", ctypes.c_int), ("converged", ctypes.c_int)]
+
+
+def main(shapes):
+    L = ctypes.CDLL(str(LIB))
+    vp = ctypes.c_void_p
+    L.ascc_last_error.restype = ctypes.c_char_p
+    L.ascc_build_ints.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                  ctypes.c_int, vp, ctypes.POINTER(vp)]
+    L.ascc_residual.argtypes = [vp] * 7
+    L.ascc_diis_create.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp)]
+    L.ascc_update.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_double, vp, vp]
+    L.ascc_solve.argtypes = [vp, ctypes.POINTER(Opts), vp, vp, ctypes.POINTER(Result), vp]
+    L.ascc_ints_free.argtypes = [vp]
+    L.ascc_diis_free.argtypes = [vp]
+    ok = True
+    for (o, v, Q, diag) in shapes:
+        n = o + v
+        base = [0x200000000000]
+
+        def fake(nbytes):  # distinct, page-aligned, never dereferenced
+            p = base[0]
+            base[0] += (nbytes + 2 * 4096) // 4096 * 4096
+            return vp(p)
+
+        B = fake(8 * Q * n * n)
+        F = fake(8 * (n if diag else n * n))
+        h = vp()
+        rc = L.ascc_build_ints(B, F, diag, o, v, Q, 0, 0, None, ctypes.byref(h))
+        msgs = []
+        if rc == 0:
+            t1, t2, r1, r2, e, st = (fake(8 * o * v), fake(8 * o * o * v * v), fake(8 * o * v),
+                                     fake(8 * o * o * v * v), fake(8), fake(64))
+            rc = L.ascc_residual(h, t1, t2, r1, r2, e, None)
+            if rc == 0:
+                d = vp()
+                rc = L.ascc_diis_create(h, 8, 1, ctypes.byref(d))
+                for _ in range(3):
+                    if rc == 0:
+                        rc = L.ascc_update(h, d, t1, t2, r1, r2, e, ctypes.c_double(0.0), st, None)
+                L.ascc_diis_free(d)
+            if rc == 0:
+                res = Result()
+                rc = L.ascc_solve(h, ctypes.byref(Opts(1e-8, 0, 0, 3, 8, 1, 0.0)), t1, t2, ctypes.byref(res), None)
+            L.ascc_ints_free(h)
+        if rc == 0:
+            print(f"OK {o} {v} {Q}", flush=True)
+        else:
+            ok = False
+            print(f"FAIL {o} {v} {Q} status {rc}: {L.ascc_last_error().decode()}", flush=True)
+    return 0 if ok else 1
+
+
+if __name__ == "__main__":
+    shapes = [tuple(int(x) for x in s.split(",")) for s in sys.argv[1:]]
+    sys.exit(main(shapes))
