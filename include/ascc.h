@@ -146,6 +146,18 @@ int ascc_solve(ascc_ints* ints, const ascc_opts* opts, double* d_t1, double* d_t
 void ascc_ints_free(ascc_ints* ints); /* NULL is a no-op; synchronises the device first */
 void ascc_diis_free(ascc_diis* diis); /* NULL is a no-op; synchronises the device first */
 
+/* Per-phase timing of ascc_residual / ascc_update on a handle, with HIP events recorded on the
+ * caller's stream around each phase (pp_ladder is the particle-particle ladder contraction,
+ * etc.; names from ascc_phase_name).  ascc_timing_enable(ints, 1) starts recording;
+ * ascc_timing_read waits for the recorded events, returns per phase the summed milliseconds
+ * and the number of recorded intervals (arrays of at least ascc_phase_count() entries), and
+ * clears the record.  Timing adds two event records per phase and no synchronisation.
+ * Errors: ASCC_E_ARG, ASCC_E_HIP. */
+int ascc_phase_count(void);
+const char* ascc_phase_name(int k);
+int ascc_timing_enable(ascc_ints* ints, int enable);
+int ascc_timing_read(ascc_ints* ints, double* ms, int* counts, int n);
+
 /* Shape queries on a built handle (host-only). */
 int ascc_ints_shape(const ascc_ints* ints, int* no, int* nv, int* naux);
 

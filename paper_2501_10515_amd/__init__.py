@@ -27,6 +27,10 @@ from ._lib import (  # noqa: F401
     ascc_diis_create,
     ascc_diis_reset,
     ascc_last_error,
+    ascc_phase_count,
+    ascc_phase_name,
+    ascc_timing_enable,
+    ascc_timing_read,
     ascc_residual,
     ascc_solve,
     ascc_update,

@@ -2,6 +2,7 @@
 from __future__ import annotations
 
 import ctypes
+import os
 from pathlib import Path
 
 import torch  # loaded first so that libascc binds to the HIP runtime torch already mapped
@@ -22,7 +23,9 @@ _LIB = None
 
 
 def library_path() -> Path:
-    return Path(__file__).resolve().with_name("libascc.so")
+    """The in-tree libascc.so (ASCC_LIB may name another build of the same sources)."""
+    override = os.environ.get("ASCC_LIB")
+    return Path(override) if override else Path(__file__).resolve().with_name("libascc.so")
 
 
 class AsccError(RuntimeError):
@@ -43,7 +46,8 @@ class Result(ctypes.Structure):
 
 
 EXPORTS = ("ascc_workspace_bytes", "ascc_build_ints", "ascc_residual", "ascc_diis_create", "ascc_diis_reset",
-           "ascc_update", "ascc_solve", "ascc_ints_free", "ascc_diis_free", "ascc_ints_shape", "ascc_last_error")
+           "ascc_update", "ascc_solve", "ascc_ints_free", "ascc_diis_free", "ascc_ints_shape", "ascc_last_error",
+           "ascc_phase_count", "ascc_phase_name", "ascc_timing_enable", "ascc_timing_read")
 
 
 def load_library():
@@ -70,8 +74,13 @@ def load_library():
     L.ascc_ints_shape.argtypes = [vp, ctypes.POINTER(c_int), ctypes.POINTER(c_int), ctypes.POINTER(c_int)]
     L.ascc_last_error.argtypes = []
     L.ascc_last_error.restype = ctypes.c_char_p
+    L.ascc_phase_count.argtypes = []
+    L.ascc_phase_name.argtypes = [c_int]
+    L.ascc_phase_name.restype = ctypes.c_char_p
+    L.ascc_timing_enable.argtypes = [vp, c_int]
+    L.ascc_timing_read.argtypes = [vp, ctypes.POINTER(c_double), ctypes.POINTER(c_int), c_int]
     for name in EXPORTS:
-        if name not in ("ascc_ints_free", "ascc_diis_free", "ascc_last_error"):
+        if name not in ("ascc_ints_free", "ascc_diis_free", "ascc_last_error", "ascc_phase_name"):
             getattr(L, name).restype = c_int
     _LIB = L
     return L
@@ -201,3 +210,24 @@ def ascc_solve(ints: Ints, t1, t2, tol_rnorm=1e-8, tol_rmax=0.0, tol_de=0.0, max
     if rc != ASCC_OK and not (rc == ASCC_E_NOT_CONVERGED and not raise_on_not_converged):
         raise AsccError(rc, ascc_last_error())
     return out
+
+
+def ascc_phase_count() -> int:
+    return load_library().ascc_phase_count()
+
+
+def ascc_phase_name(k: int) -> str:
+    return load_library().ascc_phase_name(k).decode()
+
+
+def ascc_timing_enable(ints: Ints, enable: bool = True):
+    _check(load_library().ascc_timing_enable(ints.handle, 1 if enable else 0))
+
+
+def ascc_timing_read(ints: Ints) -> dict:
+    """{phase name: (total ms, intervals)} since the last read; waits for the recorded events."""
+    n = ascc_phase_count()
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int * n)()
+    _check(load_library().ascc_timing_read(ints.handle, ms, cnt, n))
+    return {ascc_phase_name(k): (ms[k], cnt[k]) for k in range(n)}

@@ -141,7 +141,9 @@ struct ascc_ints {
   double* KL;     // [2][ov][ov]: (ib|ja), 2(ia|jb) - (ib|ja)
   double* Lijab;  // [o][o][v][v]: 2(ia|jb) - (ib|ja)
   double* Gwz;    // [v][v][ov + o^2]: (kc|bd) at [c][d][k*v+b], (kc|ld) at [c][d][ov + k*o+l]
-  double* V;      // [v][v][v][v]: (ac|bd) at [a][b][c][d]
+  double* V;      // FULL: [v][v][v][v], (ac|bd) at [a][b][c][d]
+                  // PACKED: [2][T(v)][T(v)], (ac|bd) +- (ad|bc) at [p(a,b)][p(c,d)], a <= b, c <= d
+  double *Tp, *Rp;  // ladder operands: FULL [T(o)][v^2]; PACKED [2][T(o)][T(v)]
   // residual work arrays
   double *Bt, *Bh;               // [Q][n][n]
   double *ht, *Fh;               // [n][n]
@@ -155,6 +157,11 @@ struct ascc_ints {
   double *RL, *EM;               // [o^2][v^2]
   double *Abc, *Bkj, *Fvvp, *Foop, *Fovh;  // small
   double *partial;               // reduction scratch
+  double *splitk;                // split-K partial tiles of small-output contractions
+  // optional per-phase timing with HIP events (ascc_timing_enable)
+  bool timing = false;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;  // (phase, (start, end))
+  std::vector<hipEvent_t> event_pool;
 };
 
 struct ascc_diis {
@@ -166,6 +173,36 @@ struct ascc_diis {
 };
 
 namespace {
+
+const char* const kPhaseNames[] = {"dress", "amp_views", "df_ints", "wz", "pp_ladder", "hh_ladder", "ring_y",
+                                   "ring_xz", "ring_p", "n5_terms", "assemble", "energy", "update"};
+constexpr int kNumPhases = sizeof(kPhaseNames) / sizeof(kPhaseNames[0]);
+enum Phase { PH_DRESS, PH_AMP, PH_DF, PH_WZ, PH_LADDER, PH_HH, PH_RING_Y, PH_RING_XZ, PH_RING_P, PH_N5, PH_ASSEMBLE,
+             PH_ENERGY, PH_UPDATE };
+
+hipEvent_t take_event(ascc_ints* I) {
+  if (!I->event_pool.empty()) {
+    hipEvent_t e = I->event_pool.back();
+    I->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Records the start of `phase` on `s` (no-op unless timing is on); close it with phase_end.
+void phase_begin(ascc_ints* I, int phase, hipStream_t s) {
+  if (!I->timing || dry_run()) return;
+  hipEvent_t a = take_event(I), b = take_event(I);
+  if (!a || !b) return;
+  (void)hipEventRecord(a, s);
+  I->marks.push_back({phase, {a, b}});
+}
+void phase_end(ascc_ints* I, hipStream_t s) {
+  if (!I->timing || dry_run() || I->marks.empty()) return;
+  (void)hipEventRecord(I->marks.back().second.second, s);
+}
 
 #define HIPCHK(expr)                                                                         \
   do {                                                                                       \
@@ -181,28 +218,6 @@ int fail(int code, const std::string& msg) {
   return code;
 }
 
-struct Sizes {
-  long ints_const, ints_work, diis;
-};
-
-Sizes sizes_of(long o, long v, long Q, int vvvv_mode, int m) {
-  const long n = o + v, ov = o * v, oo = o * o, vv = v * v;
-  Sizes s;
-  long c = 0;
-  c += Q * n * n + n * n + n + ov + Q * ov + 2 * ov * ov + oo * vv + vv * (ov + oo);
-  c += (vvvv_mode == ASCC_VVVV_FULL) ? vv * vv : vv * vv;  // packed storage not yet separate
-  s.ints_const = c * 8;
-  long w = 0;
-  w += 2 * Q * n * n + 2 * n * n + Q + Q * ov + Q * oo + Q * vv;
-  w += ov * ov + oo * vv + ov * ov + oo * oo;
-  w += 8 * ov * ov + Q * ov + oo * (ov + oo) + oo * oo + 2 * oo * vv;
-  w += 2 * vv + 2 * oo + ov + 8192;
-  s.ints_work = w * 8;
-  const long len = ov + oo * vv;
-  s.diis = (2L * m * len + 1024L * (3 + kMaxDiis)) * 8 + sizeof(DiisState);
-  return s;
-}
-
 // Unbacked, never dereferenced addresses handed out in a dry run.
 uintptr_t fake_alloc(size_t bytes) {
   static uintptr_t next = (uintptr_t)1 << 44;
@@ -211,6 +226,43 @@ uintptr_t fake_alloc(size_t bytes) {
   const uintptr_t p = next;
   next += (bytes + 4095) / 4096 * 4096 + 4096;
   return p;
+}
+
+
+constexpr long kSplitKElems = 1L << 22;  // 32 MiB of split-K partials
+
+// Every device array of an integral set with its element count, in allocation order; the
+// same list gives ascc_workspace_bytes its exact answer.
+std::vector<std::pair<double* ascc_ints::*, long>> ints_plan(long o, long v, long Q, int mode) {
+  const long n = o + v, nn = n * n, ov = o * v, oo = o * o, vv = v * v, ovov = ov * ov;
+  const long To = o * (o + 1) / 2, Tv = v * (v + 1) / 2;
+  const bool full = (mode == ASCC_VVVV_FULL);
+  return {
+      {&ascc_ints::B, Q * nn},        {&ascc_ints::h, nn},           {&ascc_ints::eps, n},
+      {&ascc_ints::fov, ov},          {&ascc_ints::Bov, Q * ov},     {&ascc_ints::KL, 2 * ovov},
+      {&ascc_ints::Lijab, oo * vv},   {&ascc_ints::Gwz, vv * (ov + oo)},
+      {&ascc_ints::V, full ? vv * vv : 2 * Tv * Tv},
+      {&ascc_ints::Tp, full ? To * vv : 2 * To * Tv}, {&ascc_ints::Rp, full ? To * vv : 2 * To * Tv},
+      {&ascc_ints::Bt, Q * nn},       {&ascc_ints::Bh, Q * nn},      {&ascc_ints::ht, nn},
+      {&ascc_ints::Fh, nn},           {&ascc_ints::J, Q},            {&ascc_ints::BvoT, Q * ov},
+      {&ascc_ints::Boo, Q * oo},      {&ascc_ints::Bvv, Q * vv},     {&ascc_ints::G1, ovov},
+      {&ascc_ints::G2, oo * vv},      {&ascc_ints::G3, ovov},        {&ascc_ints::G4, oo * oo},
+      {&ascc_ints::TU, 2 * ovov},     {&ascc_ints::Y, 2 * ovov},     {&ascc_ints::XZ, 2 * ovov},
+      {&ascc_ints::P, 2 * ovov},      {&ascc_ints::Nq, Q * ov},      {&ascc_ints::WZ, oo * (ov + oo)},
+      {&ascc_ints::chi, oo * oo},     {&ascc_ints::RL, oo * vv},     {&ascc_ints::EM, oo * vv},
+      {&ascc_ints::Abc, vv},          {&ascc_ints::Bkj, oo},         {&ascc_ints::Fvvp, vv},
+      {&ascc_ints::Foop, oo},         {&ascc_ints::Fovh, ov},        {&ascc_ints::partial, 8192},
+      {&ascc_ints::splitk, kSplitKElems},
+  };
+}
+
+// Bytes of the (kc|bd) temporary and of one chunk of the packed-vvvv build (freed after the build).
+long build_temp_elems(long o, long v, int mode, long* chunk_a) {
+  const long vvv = v * v * v;
+  long ac = std::max<long>(1, std::min<long>(v, (256L << 20) / std::max<long>(vvv, 1)));  // about 2 GB
+  if (chunk_a) *chunk_a = ac;
+  const long wtmp = o * v * v * v;
+  return (mode == ASCC_VVVV_FULL) ? wtmp : std::max(wtmp, ac * vvv);
 }
 
 template <class T>
@@ -251,7 +303,14 @@ inline Perm4In pin(const double* p, long s0, long s1, long s2, long s3, double c
 }
 
 // Bt = B Y^T then Bh = X Bt on `nb` stacked n x n matrices (the T1 dressing).
-int dress(const double* src, double* tmp, double* dst, const double* t1, int o, int v, int nb, hipStream_t s) {
+inline hipError_t mm(const ascc_ints* I, Gemm g, hipStream_t s) {
+  g.ws = I->splitk;
+  g.ws_elems = kSplitKElems;
+  return gemm_f64(g, s);
+}
+
+int dress(const ascc_ints* I, const double* src, double* tmp, double* dst, const double* t1, int o, int v, int nb,
+          hipStream_t s) {
   const long n = o + v, nn = n * n;
   HIPCHK(d_copy(tmp, src, sizeof(double) * nn * nb, hipMemcpyDeviceToDevice, s));
   {  // tmp[:, 0:o] += src[:, o:n] t1^T
@@ -272,7 +331,7 @@ int dress(const double* src, double* tmp, double* dst, const double* t1, int o, 
     g.sc2 = nn;
     g.beta = 1.0;
     g.nb2 = nb;
-    HIPCHK(gemm_f64(g, s));
+    HIPCHK(mm(I, g, s));
   }
   HIPCHK(d_copy(dst, tmp, sizeof(double) * nn * nb, hipMemcpyDeviceToDevice, s));
   {  // dst[o:n, :] -= t1^T tmp[0:o, :]
@@ -294,13 +353,14 @@ int dress(const double* src, double* tmp, double* dst, const double* t1, int o, 
     g.alpha = -1.0;
     g.beta = 1.0;
     g.nb2 = nb;
-    HIPCHK(gemm_f64(g, s));
+    HIPCHK(mm(I, g, s));
   }
   return ASCC_OK;
 }
 
 // F += sign * (2 sum_Q J_Q B_Q - sum_Q B_Q[:,0:o] B_Q[0:o,:]),  J_Q = sum_k B_Q[k][k]
-int add_two_electron_fock(double* F, const double* Bq, double* J, int o, int v, int Q, double sign, hipStream_t s) {
+int add_two_electron_fock(const ascc_ints* I, double* F, const double* Bq, double* J, int o, int v, int Q, double sign,
+                          hipStream_t s) {
   const long n = o + v, nn = n * n;
   HIPCHK(diag_trace(J, Bq, Q, n, o, s));
   {
@@ -319,7 +379,7 @@ int add_two_electron_fock(double* F, const double* Bq, double* J, int o, int v, 
     g.scn = 1;
     g.alpha = 2.0 * sign;
     g.beta = 1.0;
-    HIPCHK(gemm_f64(g, s));
+    HIPCHK(mm(I, g, s));
   }
   {
     Gemm g;
@@ -340,7 +400,31 @@ int add_two_electron_fock(double* F, const double* Bq, double* J, int o, int v, 
     g.alpha = -sign;
     g.beta = 1.0;
     g.nred = Q;
-    HIPCHK(gemm_f64(g, s));
+    HIPCHK(mm(I, g, s));
+  }
+  return ASCC_OK;
+}
+
+
+// Particle-particle ladder RL[i][j][a][b] = sum_cd t_ij^cd (ac|bd), computed for pairs i <= j
+// only (RL_ji^ba = RL_ij^ab).  FULL: against the full (ac|bd) matrix.  PACKED: against its
+// (ab)-symmetric and antisymmetric halves, R+- = t+- V+-, one batched launch.
+int pp_ladder(ascc_ints* I, const double* t2, hipStream_t s) {
+  const int o = I->no, v = I->nv;
+  const long vv = I->vv, To = (long)o * (o + 1) / 2, Tv = (long)v * (v + 1) / 2;
+  if (I->vvvv_mode == ASCC_VVVV_FULL) {
+    HIPCHK(pack_pairs(I->Tp, t2, o, vv, s));
+    HIPCHK(mm(I, gemm_rm(To, vv, vv, 1.0, I->Tp, vv, false, I->V, vv, true, 0.0, I->Rp, vv), s));
+    HIPCHK(unpack_pairs(I->RL, I->Rp, o, v, s));
+  } else {
+    HIPCHK(pack_tpm(I->Tp, t2, o, v, s));
+    Gemm g = gemm_rm(To, Tv, Tv, 1.0, I->Tp, Tv, false, I->V, Tv, true, 0.0, I->Rp, Tv);
+    g.sa2 = To * Tv;
+    g.sb2 = Tv * Tv;
+    g.sc2 = To * Tv;
+    g.nb2 = 2;
+    HIPCHK(mm(I, g, s));
+    HIPCHK(unpack_rpm(I->RL, I->Rp, o, v, s));
   }
   return ASCC_OK;
 }
@@ -353,9 +437,10 @@ int residual_fp64(ascc_ints* I, const double* t1, const double* t2, double* r1, 
   int rc;
 
   // --- T1 dressing of B and of the one-electron operator, dressed Fock matrix
-  if ((rc = dress(I->B, I->Bt, I->Bh, t1, o, v, Q, s))) return rc;
-  if ((rc = dress(I->h, I->ht, I->Fh, t1, o, v, 1, s))) return rc;
-  if ((rc = add_two_electron_fock(I->Fh, I->Bh, I->J, o, v, Q, 1.0, s))) return rc;
+  phase_begin(I, PH_DRESS, s);
+  if ((rc = dress(I, I->B, I->Bt, I->Bh, t1, o, v, Q, s))) return rc;
+  if ((rc = dress(I, I->h, I->ht, I->Fh, t1, o, v, 1, s))) return rc;
+  if ((rc = add_two_electron_fock(I, I->Fh, I->Bh, I->J, o, v, Q, 1.0, s))) return rc;
 
   // --- contiguous dressed blocks
   {
@@ -373,7 +458,9 @@ int residual_fp64(ascc_ints* I, const double* t1, const double* t2, double* r1, 
     HIPCHK(permute4(I->Fovh, d4, 0.0, &x, 1, s));
   }
 
+  phase_end(I, s);
   // --- permuted amplitude views: Tx[iajb] = t2[ijba], U[iajb] = 2 t2[ijab] - t2[ijba]
+  phase_begin(I, PH_AMP, s);
   double* Tx = I->TU;
   double* U = I->TU + ovov;
   {
@@ -385,17 +472,23 @@ int residual_fp64(ascc_ints* I, const double* t1, const double* t2, double* r1, 
     HIPCHK(permute4(U, d, 0.0, y, 2, s));
   }
 
+  phase_end(I, s);
   // --- density-fitted dressed integral blocks (K = naux)
-  HIPCHK(gemm_f64(gemm_rm(ov, ov, Q, 1.0, I->BvoT, ov, true, I->BvoT, ov, false, 0.0, I->G1, ov), s));  // g^_aibj
-  HIPCHK(gemm_f64(gemm_rm(oo, vv, Q, 1.0, I->Boo, oo, true, I->Bvv, vv, false, 0.0, I->G2, vv), s));    // g^_kiac
-  HIPCHK(gemm_f64(gemm_rm(ov, ov, Q, 1.0, I->BvoT, ov, true, I->Bov, ov, false, 0.0, I->G3, ov), s));   // g^_aikc
-  HIPCHK(gemm_f64(gemm_rm(oo, oo, Q, 1.0, I->Boo, oo, true, I->Boo, oo, false, 0.0, I->G4, oo), s));    // g^_kilj
-  HIPCHK(gemm_f64(gemm_rm(Q, ov, ov, 1.0, I->Bov, ov, false, U, ov, false, 0.0, I->Nq, ov), s));        // N_Q[k,a]
+  phase_begin(I, PH_DF, s);
+  HIPCHK(mm(I, gemm_rm(ov, ov, Q, 1.0, I->BvoT, ov, true, I->BvoT, ov, false, 0.0, I->G1, ov), s));  // g^_aibj
+  HIPCHK(mm(I, gemm_rm(oo, vv, Q, 1.0, I->Boo, oo, true, I->Bvv, vv, false, 0.0, I->G2, vv), s));    // g^_kiac
+  HIPCHK(mm(I, gemm_rm(ov, ov, Q, 1.0, I->BvoT, ov, true, I->Bov, ov, false, 0.0, I->G3, ov), s));   // g^_aikc
+  HIPCHK(mm(I, gemm_rm(oo, oo, Q, 1.0, I->Boo, oo, true, I->Boo, oo, false, 0.0, I->G4, oo), s));    // g^_kilj
+  HIPCHK(mm(I, gemm_rm(Q, ov, ov, 1.0, I->Bov, ov, false, U, ov, false, 0.0, I->Nq, ov), s));        // N_Q[k,a]
 
+  phase_end(I, s);
   // --- W_ij[k,b], Z_ij[k,l] in one product against [(kc|bd) | (kc|ld)]
-  HIPCHK(gemm_f64(gemm_rm(oo, wzl, vv, 1.0, t2, vv, false, I->Gwz, wzl, false, 0.0, I->WZ, wzl), s));
+  phase_begin(I, PH_WZ, s);
+  HIPCHK(mm(I, gemm_rm(oo, wzl, vv, 1.0, t2, vv, false, I->Gwz, wzl, false, 0.0, I->WZ, wzl), s));
 
+  phase_end(I, s);
   // --- chi[ij][kl] = g^_kilj + Z_ij[k,l]
+  phase_begin(I, PH_HH, s);
   {
     int d[4] = {o, o, o, o};
     const long o2 = oo, o3 = oo * o;
@@ -403,22 +496,27 @@ int residual_fp64(ascc_ints* I, const double* t1, const double* t2, double* r1, 
     HIPCHK(permute4(I->chi, d, 0.0, x, 2, s));
   }
 
+  phase_end(I, s);
   // --- particle-particle ladder over the undressed (ac|bd), plus the hole-hole ladder
-  {
-    Gemm g = gemm_rm(oo, vv, vv, 1.0, t2, vv, false, I->V, vv, true, 0.0, I->RL, vv);
-    HIPCHK(gemm_f64(g, s));
-  }
-  HIPCHK(gemm_f64(gemm_rm(oo, vv, oo, 1.0, I->chi, oo, false, t2, vv, false, 1.0, I->RL, vv), s));
+  phase_begin(I, PH_LADDER, s);
+  if ((rc = pp_ladder(I, t2, s))) return rc;
+  phase_end(I, s);
+  phase_begin(I, PH_HH, s);
+  HIPCHK(mm(I, gemm_rm(oo, vv, oo, 1.0, I->chi, oo, false, t2, vv, false, 1.0, I->RL, vv), s));
+  phase_end(I, s);
 
   // --- rings: Y1 = Tx K, Y2 = U L (batched pair)
+  phase_begin(I, PH_RING_Y, s);
   {
     Gemm g = gemm_rm(ov, ov, ov, 1.0, I->TU, ov, false, I->KL, ov, false, 0.0, I->Y, ov);
     g.sa2 = ovov;
     g.sb2 = ovov;
     g.sc2 = ovov;
     g.nb2 = 2;
-    HIPCHK(gemm_f64(g, s));
+    HIPCHK(mm(I, g, s));
   }
+  phase_end(I, s);
+  phase_begin(I, PH_RING_XZ, s);
   {
     int d[4] = {o, v, o, v};  // (i, a, k, c)
     const long si = vv, sa = v, sk = (long)o * vv, sc = 1;  // G2[k][i][a][c]
@@ -428,17 +526,21 @@ int residual_fp64(ascc_ints* I, const double* t1, const double* t2, double* r1, 
                     pin(I->Y + ovov, (long)v * o * v, (long)o * v, v, 1, 0.5)};
     HIPCHK(permute4(I->XZ + ovov, d, 0.0, z, 3, s));
   }
+  phase_end(I, s);
+  phase_begin(I, PH_RING_P, s);
   {  // P1 = Tx Xc^T, P2 = U Zd^T
     Gemm g = gemm_rm(ov, ov, ov, 1.0, I->TU, ov, false, I->XZ, ov, true, 0.0, I->P, ov);
     g.sa2 = ovov;
     g.sb2 = ovov;
     g.sc2 = ovov;
     g.nb2 = 2;
-    HIPCHK(gemm_f64(g, s));
+    HIPCHK(mm(I, g, s));
   }
 
+  phase_end(I, s);
+  phase_begin(I, PH_N5, s);
   // --- E term: F'_bc = F^_bc - sum_Qk N_Q[k,b] B_Q,kc ; F''_kj = F^_kj + sum_Qd B_Q,kd N_Q[j,d]
-  HIPCHK(gemm_f64(gemm_rm(v, v, (long)Q * o, 1.0, I->Nq, v, true, I->Bov, v, false, 0.0, I->Abc, v), s));
+  HIPCHK(mm(I, gemm_rm(v, v, (long)Q * o, 1.0, I->Nq, v, true, I->Bov, v, false, 0.0, I->Abc, v), s));
   {
     Gemm g;
     g.M = o;
@@ -456,7 +558,7 @@ int residual_fp64(ascc_ints* I, const double* t1, const double* t2, double* r1, 
     g.scm = o;
     g.scn = 1;
     g.nred = Q;
-    HIPCHK(gemm_f64(g, s));
+    HIPCHK(mm(I, g, s));
   }
   {
     int d[4] = {v, v, 1, 1};
@@ -467,7 +569,7 @@ int residual_fp64(ascc_ints* I, const double* t1, const double* t2, double* r1, 
     HIPCHK(permute4(I->Foop, d2, 0.0, y, 2, s));
   }
   // EM = sum_c t_ij^ac F'_bc
-  HIPCHK(gemm_f64(gemm_rm(oo * v, v, v, 1.0, t2, v, false, I->Fvvp, v, true, 0.0, I->EM, v), s));
+  HIPCHK(mm(I, gemm_rm(oo * v, v, v, 1.0, t2, v, false, I->Fvvp, v, true, 0.0, I->EM, v), s));
   {  // EM[i][j][ab] -= sum_k F''_kj t_ik^ab   (batched over i)
     Gemm g;
     g.M = o;
@@ -487,7 +589,7 @@ int residual_fp64(ascc_ints* I, const double* t1, const double* t2, double* r1, 
     g.alpha = -1.0;
     g.beta = 1.0;
     g.nb2 = o;
-    HIPCHK(gemm_f64(g, s));
+    HIPCHK(mm(I, g, s));
   }
   {  // W'_ij[k,b] = W_ij[k,b] - 1/2 sum_l Z_ij[k,l] t_l^b   (batched over ij, in place)
     Gemm g;
@@ -508,7 +610,7 @@ int residual_fp64(ascc_ints* I, const double* t1, const double* t2, double* r1, 
     g.alpha = -0.5;
     g.beta = 1.0;
     g.nb2 = oo;
-    HIPCHK(gemm_f64(g, s));
+    HIPCHK(mm(I, g, s));
   }
   {  // EM[ij][a][b] -= sum_k t_k^a W'_ij[k,b]
     Gemm g;
@@ -529,7 +631,7 @@ int residual_fp64(ascc_ints* I, const double* t1, const double* t2, double* r1, 
     g.alpha = -1.0;
     g.beta = 1.0;
     g.nb2 = oo;
-    HIPCHK(gemm_f64(g, s));
+    HIPCHK(mm(I, g, s));
   }
 
   // --- singles
@@ -550,10 +652,10 @@ int residual_fp64(ascc_ints* I, const double* t1, const double* t2, double* r1, 
     g.scm = v;
     g.scn = 1;
     g.nred = Q;
-    HIPCHK(gemm_f64(g, s));
+    HIPCHK(mm(I, g, s));
   }
   // r1 -= sum_Qk B^_Q,ki N_Q[k,a]
-  HIPCHK(gemm_f64(gemm_rm(o, v, (long)Q * o, -1.0, I->Boo, o, true, I->Nq, v, false, 1.0, r1, v), s));
+  HIPCHK(mm(I, gemm_rm(o, v, (long)Q * o, -1.0, I->Boo, o, true, I->Nq, v, false, 1.0, r1, v), s));
   {  // r1[(ia)] += sum_kc U[(ia),(kc)] F^_kc
     Gemm g;
     g.M = ov;
@@ -569,13 +671,18 @@ int residual_fp64(ascc_ints* I, const double* t1, const double* t2, double* r1, 
     g.scm = 1;
     g.scn = 0;
     g.beta = 1.0;
-    HIPCHK(gemm_f64(g, s));
+    HIPCHK(mm(I, g, s));
   }
   HIPCHK(add_fvo(r1, I->Fh, o, v, s));
 
+  phase_end(I, s);
   // --- doubles assembly and energy
+  phase_begin(I, PH_ASSEMBLE, s);
   HIPCHK(assemble_r2(r2, I->G1, I->RL, I->EM, I->P, I->P + ovov, o, v, s));
+  phase_end(I, s);
+  phase_begin(I, PH_ENERGY, s);
   HIPCHK(energy(e, I->partial, t1, t2, I->Lijab, I->fov, o, v, s));
+  phase_end(I, s);
   return ASCC_OK;
 }
 
@@ -606,7 +713,7 @@ int build_constants(ascc_ints* I, const double* Bsrc, const double* fock, int fo
     HIPCHK(permute4(I->fov, d, 0.0, &x, 1, s));
   }
   // h = f - sum_k (2 (pq|kk) - (pk|kq))
-  int rc = add_two_electron_fock(I->h, I->B, I->J, o, v, Q, -1.0, s);
+  int rc = add_two_electron_fock(I, I->h, I->B, I->J, o, v, Q, -1.0, s);
   if (rc) return rc;
 
   // B_ov and undressed B_vv (the latter into the work array Bvv)
@@ -620,7 +727,7 @@ int build_constants(ascc_ints* I, const double* Bsrc, const double* fock, int fo
   }
   // J = (ia|jb) into G1 (work), then K and L
   double* Jov = I->G1;
-  HIPCHK(gemm_f64(gemm_rm(ov, ov, Q, 1.0, I->Bov, ov, true, I->Bov, ov, false, 0.0, Jov, ov), s));
+  HIPCHK(mm(I, gemm_rm(ov, ov, Q, 1.0, I->Bov, ov, true, I->Bov, ov, false, 0.0, Jov, ov), s));
   {
     int d[4] = {o, v, o, v};
     const long si = (long)v * o * v, sa = (long)o * v, sj = v, sb = 1;
@@ -639,7 +746,7 @@ int build_constants(ascc_ints* I, const double* Bsrc, const double* fock, int fo
     size_t tmp_bytes = 0;
     int rc2 = dalloc(tmp_alloc, tmp_bytes, &tmp, (size_t)ov * vv);
     if (rc2) return rc2;
-    hipError_t e = gemm_f64(gemm_rm(ov, vv, Q, 1.0, I->Bov, ov, true, I->Bvv, vv, false, 0.0, tmp, vv), s);
+    hipError_t e = mm(I, gemm_rm(ov, vv, Q, 1.0, I->Bov, ov, true, I->Bvv, vv, false, 0.0, tmp, vv), s);
     if (e == hipSuccess) {
       long ostr[4] = {(long)v * wzl, wzl, v, 1};
       int d[4] = {v, v, o, v};  // (c, d, k, b) <- tmp[k][c][b][d]
@@ -660,13 +767,13 @@ int build_constants(ascc_ints* I, const double* Bsrc, const double* fock, int fo
       return ASCC_E_HIP;
     }
   }
-  // V[a][b][c][d] = (ac|bd) = sum_Q B_Q,ac B_Q,bd, batched over (a, b)
-  {
+  // V[a][b][c][d] = (ac|bd) = sum_Q B_Q,ac B_Q,bd, batched over (a, b); packed: in chunks of a
+  auto vslab = [&](int a0, int na, double* dst) -> hipError_t {
     Gemm g;
     g.M = v;
     g.N = v;
     g.K = Q;
-    g.A = I->Bvv;
+    g.A = I->Bvv + (long)a0 * v;
     g.sam = 1;
     g.sak = vv;
     g.sa1 = v;
@@ -674,14 +781,37 @@ int build_constants(ascc_ints* I, const double* Bsrc, const double* fock, int fo
     g.sbk = vv;
     g.sbn = 1;
     g.sb2 = v;
-    g.C = I->V;
+    g.C = dst;
     g.scm = v;
     g.scn = 1;
     g.sc1 = (long)v * vv;
     g.sc2 = vv;
-    g.nb1 = v;
+    g.nb1 = na;
     g.nb2 = v;
-    HIPCHK(gemm_f64(g, s));
+    return mm(I, g, s);
+  };
+  if (I->vvvv_mode == ASCC_VVVV_FULL) {
+    HIPCHK(vslab(0, v, I->V));
+  } else {
+    long ac = 1;
+    const long elems = build_temp_elems(o, v, I->vvvv_mode, &ac);
+    double* tmp = nullptr;
+    std::vector<void*> tmp_alloc;
+    size_t tmp_bytes = 0;
+    int rc3 = dalloc(tmp_alloc, tmp_bytes, &tmp, (size_t)elems);
+    if (rc3) return rc3;
+    hipError_t e = hipSuccess;
+    for (int a0 = 0; a0 < v && e == hipSuccess; a0 += (int)ac) {
+      const int na = (int)std::min<long>(ac, v - a0);
+      e = vslab(a0, na, tmp);
+      if (e == hipSuccess) e = pack_vvvv(I->V, tmp, a0, a0 + na, v, s);
+    }
+    if (e == hipSuccess) e = d_sync(s);
+    free_all(tmp_alloc);
+    if (e != hipSuccess) {
+      if (!(bounds_checking() && e == hipErrorInvalidValue)) set_error(std::string("building vvvv: ") + hipGetErrorString(e));
+      return ASCC_E_HIP;
+    }
   }
   return ASCC_OK;
 }
@@ -706,12 +836,48 @@ int ascc_workspace_bytes(int no, int nv, int naux, int precision, int vvvv_mode,
   int rc = check_shape(no, nv, naux);
   if (rc) return rc;
   if (precision != ASCC_PREC_FP64) return fail(ASCC_E_ARG, "unsupported precision");
-  if (vvvv_mode != ASCC_VVVV_FULL) return fail(ASCC_E_ARG, "unsupported vvvv_mode");
+  if (vvvv_mode != ASCC_VVVV_FULL && vvvv_mode != ASCC_VVVV_PACKED) return fail(ASCC_E_ARG, "unsupported vvvv_mode");
   if (diis_size < 1 || diis_size > kMaxDiis) return fail(ASCC_E_ARG, "diis_size must be in 1..16");
-  Sizes s = sizes_of(no, nv, naux, vvvv_mode, diis_size);
-  if (ints_bytes) *ints_bytes = s.ints_const + s.ints_work;
-  if (diis_bytes) *diis_bytes = s.diis;
+  size_t total = 0;
+  for (const auto& item : ints_plan(no, nv, naux, vvvv_mode))
+    total += std::max<size_t>((size_t)item.second, 1) * sizeof(double);
+  const long len = (long)no * nv + (long)no * no * nv * nv;
+  if (ints_bytes) *ints_bytes = total;
+  if (diis_bytes)
+    *diis_bytes = 2 * (size_t)diis_size * len * sizeof(double) +
+                  (size_t)update_partial_blocks() * (3 + kMaxDiis) * sizeof(double) + sizeof(DiisState);
   return ASCC_OK;
+}
+
+int ascc_phase_count(void) { return kNumPhases; }
+
+const char* ascc_phase_name(int k) { return (k >= 0 && k < kNumPhases) ? kPhaseNames[k] : ""; }
+
+int ascc_timing_enable(ascc_ints* I, int on) {
+  if (!I) return fail(ASCC_E_ARG, "NULL handle");
+  I->timing = (on != 0);
+  return ASCC_OK;
+}
+
+int ascc_timing_read(ascc_ints* I, double* ms, int* counts, int n) {
+  if (!I || !ms || !counts || n < kNumPhases) return fail(ASCC_E_ARG, "ascc_timing_read needs arrays of ascc_phase_count() entries");
+  for (int k = 0; k < n; ++k) {
+    ms[k] = 0.0;
+    counts[k] = 0;
+  }
+  int rc = ASCC_OK;
+  for (auto& m : I->marks) {
+    float t = 0.f;
+    hipError_t e = hipEventSynchronize(m.second.second);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, m.second.first, m.second.second);
+    if (e != hipSuccess && rc == ASCC_OK) rc = fail(ASCC_E_HIP, std::string("event timing: ") + hipGetErrorString(e));
+    ms[m.first] += t;
+    counts[m.first] += 1;
+    I->event_pool.push_back(m.second.first);
+    I->event_pool.push_back(m.second.second);
+  }
+  I->marks.clear();
+  return rc;
 }
 
 int ascc_ints_shape(const ascc_ints* I, int* no, int* nv, int* naux) {
@@ -730,7 +896,7 @@ int ascc_build_ints(const double* d_B, const double* d_fock, int fock_is_diag, i
   int rc = check_shape(no, nv, naux);
   if (rc) return rc;
   if (precision != ASCC_PREC_FP64) return fail(ASCC_E_ARG, "unsupported precision");
-  if (vvvv_mode != ASCC_VVVV_FULL) return fail(ASCC_E_ARG, "unsupported vvvv_mode");
+  if (vvvv_mode != ASCC_VVVV_FULL && vvvv_mode != ASCC_VVVV_PACKED) return fail(ASCC_E_ARG, "unsupported vvvv_mode");
   hipStream_t s = static_cast<hipStream_t>(stream);
   ascc_ints* I = new ascc_ints();
   I->no = no;
@@ -746,49 +912,10 @@ int ascc_build_ints(const double* d_B, const double* d_fock, int fock_is_diag, i
   I->vv = v * v;
   I->ovov = I->ov * I->ov;
   I->oovv = I->oo * I->vv;
-  const long ov = I->ov, oo = I->oo, vv = I->vv, ovov = I->ovov;
-  auto& A = I->allocs;
-  size_t& T = I->bytes;
   rc = ASCC_OK;
-#define ALLOC(ptr, count) \
-  if (!rc) rc = dalloc(A, T, &(ptr), (size_t)(count))
-  ALLOC(I->B, Q * nn);
-  ALLOC(I->h, nn);
-  ALLOC(I->eps, n);
-  ALLOC(I->fov, ov);
-  ALLOC(I->Bov, Q * ov);
-  ALLOC(I->KL, 2 * ovov);
-  ALLOC(I->Lijab, oo * vv);
-  ALLOC(I->Gwz, vv * (ov + oo));
-  ALLOC(I->V, vv * vv);
-  ALLOC(I->Bt, Q * nn);
-  ALLOC(I->Bh, Q * nn);
-  ALLOC(I->ht, nn);
-  ALLOC(I->Fh, nn);
-  ALLOC(I->J, Q);
-  ALLOC(I->BvoT, Q * ov);
-  ALLOC(I->Boo, Q * oo);
-  ALLOC(I->Bvv, Q * vv);
-  ALLOC(I->G1, ovov);
-  ALLOC(I->G2, oo * vv);
-  ALLOC(I->G3, ovov);
-  ALLOC(I->G4, oo * oo);
-  ALLOC(I->TU, 2 * ovov);
-  ALLOC(I->Y, 2 * ovov);
-  ALLOC(I->XZ, 2 * ovov);
-  ALLOC(I->P, 2 * ovov);
-  ALLOC(I->Nq, Q * ov);
-  ALLOC(I->WZ, oo * (ov + oo));
-  ALLOC(I->chi, oo * oo);
-  ALLOC(I->RL, oo * vv);
-  ALLOC(I->EM, oo * vv);
-  ALLOC(I->Abc, vv);
-  ALLOC(I->Bkj, oo);
-  ALLOC(I->Fvvp, vv);
-  ALLOC(I->Foop, oo);
-  ALLOC(I->Fovh, ov);
-  ALLOC(I->partial, 8192);
-#undef ALLOC
+  for (const auto& item : ints_plan(no, nv, naux, vvvv_mode)) {
+    if (!rc) rc = dalloc(I->allocs, I->bytes, &(I->*(item.first)), (size_t)item.second);
+  }
   ScopedBuffers user;
   user.add(d_B, sizeof(double) * Q * nn);
   user.add(d_fock, sizeof(double) * (fock_is_diag ? n : nn));
@@ -809,6 +936,11 @@ int ascc_build_ints(const double* d_B, const double* d_fock, int fock_is_diag, i
 void ascc_ints_free(ascc_ints* I) {
   if (!I) return;
   free_all(I->allocs);
+  for (auto& m : I->marks) {
+    (void)hipEventDestroy(m.second.first);
+    (void)hipEventDestroy(m.second.second);
+  }
+  for (hipEvent_t e : I->event_pool) (void)hipEventDestroy(e);
   delete I;
 }
 
@@ -902,7 +1034,9 @@ int ascc_update(ascc_ints* I, ascc_diis* D, double* t1, double* t2, const double
   u.store = (D->calls >= D->start) ? 1 : 0;
   u.len = D->len;
   u.shift = level_shift;
+  phase_begin(I, PH_UPDATE, static_cast<hipStream_t>(stream));
   HIPCHK(diis_update(u, static_cast<hipStream_t>(stream)));
+  phase_end(I, static_cast<hipStream_t>(stream));
   D->calls += 1;
   return ASCC_OK;
 }

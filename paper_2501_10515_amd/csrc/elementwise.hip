@@ -3,6 +3,7 @@
 // Reductions are deterministic: a fixed grid, a fixed per-thread stride pattern, a fixed
 // wave64 shuffle tree and a fixed second stage, with no floating-point atomics, so the same
 // inputs always give bitwise the same energy, norms and DIIS coefficients.
+#include <algorithm>
 #include <cmath>
 
 #include "internal.h"
@@ -361,6 +362,99 @@ __global__ __launch_bounds__(kThreads) void update_stage3(double* t1, double* t2
   }
 }
 
+
+// ---------------------------------------------------------------------------------------
+// Pair packing for the particle-particle ladder.
+//
+// Pair index of i <= j among n: pidx(i, j) = i*n - i*(i-1)/2 + (j - i)  (row-major upper triangle).
+__device__ __forceinline__ long pidx(long i, long j, long n) { return i * n - i * (i - 1) / 2 + (j - i); }
+
+// out[p(i,j)][x] = in[i][j][x] for i <= j (rows of a pair-symmetric array).
+__global__ __launch_bounds__(kThreads) void pack_pairs_kernel(double* __restrict__ out, const double* __restrict__ in,
+                                                             int o, long L) {
+  const int i = blockIdx.y / o, j = blockIdx.y % o;
+  if (i > j) return;
+  const double* src = in + ((long)i * o + j) * L;
+  double* dst = out + pidx(i, j, o) * L;
+  for (long x = blockIdx.x * (long)blockDim.x + threadIdx.x; x < L; x += (long)gridDim.x * blockDim.x) dst[x] = src[x];
+}
+
+// RL[i][j][a][b] = Rp[p(i,j)][a][b] (i <= j), Rp[p(j,i)][b][a] (i > j).
+__global__ __launch_bounds__(kThreads) void unpack_pairs_kernel(double* __restrict__ RL, const double* __restrict__ Rp,
+                                                               int o, int v) {
+  const int i = blockIdx.y / o, j = blockIdx.y % o;
+  const long vv = (long)v * v;
+  double* dst = RL + ((long)i * o + j) * vv;
+  const double* src = Rp + (i <= j ? pidx(i, j, o) : pidx(j, i, o)) * vv;
+  for (long x = blockIdx.x * (long)blockDim.x + threadIdx.x; x < vv; x += (long)gridDim.x * blockDim.x) {
+    const int a = x / v, b = x % v;
+    dst[x] = (i <= j) ? src[x] : src[(long)b * v + a];
+  }
+}
+
+// t+-[p(i,j)][p(c,d)] for i <= j, c <= d:
+//   t+ = (t_ij^cd + t_ij^dc)/2 (c < d), t_ij^cc (c = d);  t- = (t_ij^cd - t_ij^dc)/2 (c < d), 0 (c = d).
+__global__ __launch_bounds__(kThreads) void pack_tpm_kernel(double* __restrict__ tp, const double* __restrict__ t2,
+                                                           int o, int v) {
+  const int i = blockIdx.y / o, j = blockIdx.y % o;
+  if (i > j) return;
+  const long To = (long)o * (o + 1) / 2, Tv = (long)v * (v + 1) / 2, vv = (long)v * v;
+  const double* src = t2 + ((long)i * o + j) * vv;
+  const long p = pidx(i, j, o);
+  double* plus = tp + p * Tv;
+  double* minus = tp + (To + p) * Tv;
+  for (long x = blockIdx.x * (long)blockDim.x + threadIdx.x; x < vv; x += (long)gridDim.x * blockDim.x) {
+    const int c = x / v, d = x % v;
+    if (c > d) continue;
+    const double a = src[x], b = src[(long)d * v + c];
+    const long k = pidx(c, d, v);
+    plus[k] = (c == d) ? a : 0.5 * (a + b);
+    minus[k] = (c == d) ? 0.0 : 0.5 * (a - b);
+  }
+}
+
+// RL[i][j][a][b] from R+-[p][p(a,b)]: R^ab = R+ + R- (a <= b), R+ - R- (a > b), with R_ij = R_ji^T.
+__global__ __launch_bounds__(kThreads) void unpack_rpm_kernel(double* __restrict__ RL, const double* __restrict__ Rp,
+                                                             int o, int v) {
+  const int i = blockIdx.y / o, j = blockIdx.y % o;
+  const long To = (long)o * (o + 1) / 2, Tv = (long)v * (v + 1) / 2, vv = (long)v * v;
+  const long p = (i <= j) ? pidx(i, j, o) : pidx(j, i, o);
+  const double* plus = Rp + p * Tv;
+  const double* minus = Rp + (To + p) * Tv;
+  double* dst = RL + ((long)i * o + j) * vv;
+  for (long x = blockIdx.x * (long)blockDim.x + threadIdx.x; x < vv; x += (long)gridDim.x * blockDim.x) {
+    int a = x / v, b = x % v;
+    if (i > j) {
+      const int t = a;
+      a = b;
+      b = t;
+    }
+    const long k = (a <= b) ? pidx(a, b, v) : pidx(b, a, v);
+    dst[x] = (a <= b) ? plus[k] + minus[k] : plus[k] - minus[k];
+  }
+}
+
+// V+-[p(a,b)][p(c,d)] for a in [a0, a1), b >= a, from W[a - a0][b][c][d] = (ac|bd):
+//   V+ = W[.][c][d] + W[.][d][c] (c < d), W[.][c][c] (c = d);  V- = W[.][c][d] - W[.][d][c] (c < d), 0 (c = d).
+__global__ __launch_bounds__(kThreads) void pack_vvvv_kernel(double* __restrict__ Vp, const double* __restrict__ W,
+                                                            int a0, int v) {
+  const int a = a0 + blockIdx.y / v, b = blockIdx.y % v;
+  if (b < a) return;
+  const long Tv = (long)v * (v + 1) / 2, vv = (long)v * v;
+  const double* src = W + ((long)(a - a0) * v + b) * vv;
+  const long r = pidx(a, b, v);
+  double* plus = Vp + r * Tv;
+  double* minus = Vp + (Tv + r) * Tv;
+  for (long x = blockIdx.x * (long)blockDim.x + threadIdx.x; x < vv; x += (long)gridDim.x * blockDim.x) {
+    const int c = x / v, d = x % v;
+    if (c > d) continue;
+    const double w1 = src[x], w2 = src[(long)d * v + c];
+    const long k = pidx(c, d, v);
+    plus[k] = (c == d) ? w1 : w1 + w2;
+    minus[k] = (c == d) ? 0.0 : w1 - w2;
+  }
+}
+
 inline int grid_for(long total) {
   long g = (total + kThreads - 1) / kThreads;
   if (g > 8192) g = 8192;
@@ -481,6 +575,60 @@ hipError_t energy(double* e, double* partial, const double* t1, const double* t2
   if (dry_run()) return hipSuccess;
   hipLaunchKernelGGL(energy_stage1, dim3(kRedBlocks), dim3(kThreads), 0, s, partial, t1, t2, Lijab, no, nv, total);
   hipLaunchKernelGGL(energy_stage2, dim3(1), dim3(kThreads), 0, s, e, partial, kRedBlocks, t1, fov, no * nv);
+  return hipGetLastError();
+}
+
+
+static bool chk(const void* p, long n, const char* what) { return range_ok(p, 0, n - 1, 8, what); }
+
+hipError_t pack_pairs(double* out, const double* in, int o, long L, hipStream_t s) {
+  const long To = (long)o * (o + 1) / 2;
+  if (bounds_checking() && !(chk(out, To * L, "pack_pairs out") && chk(in, (long)o * o * L, "pack_pairs in")))
+    return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  dim3 grid((unsigned)std::min<long>((L + kThreads - 1) / kThreads, 64), o * o);
+  hipLaunchKernelGGL(pack_pairs_kernel, grid, dim3(kThreads), 0, s, out, in, o, L);
+  return hipGetLastError();
+}
+
+hipError_t unpack_pairs(double* RL, const double* Rp, int o, int v, hipStream_t s) {
+  const long To = (long)o * (o + 1) / 2, vv = (long)v * v;
+  if (bounds_checking() && !(chk(RL, (long)o * o * vv, "unpack_pairs RL") && chk(Rp, To * vv, "unpack_pairs Rp")))
+    return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  dim3 grid((unsigned)std::min<long>((vv + kThreads - 1) / kThreads, 64), o * o);
+  hipLaunchKernelGGL(unpack_pairs_kernel, grid, dim3(kThreads), 0, s, RL, Rp, o, v);
+  return hipGetLastError();
+}
+
+hipError_t pack_tpm(double* tp, const double* t2, int o, int v, hipStream_t s) {
+  const long To = (long)o * (o + 1) / 2, Tv = (long)v * (v + 1) / 2, vv = (long)v * v;
+  if (bounds_checking() && !(chk(tp, 2 * To * Tv, "pack_tpm out") && chk(t2, (long)o * o * vv, "pack_tpm t2")))
+    return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  dim3 grid((unsigned)std::min<long>((vv + kThreads - 1) / kThreads, 64), o * o);
+  hipLaunchKernelGGL(pack_tpm_kernel, grid, dim3(kThreads), 0, s, tp, t2, o, v);
+  return hipGetLastError();
+}
+
+hipError_t unpack_rpm(double* RL, const double* Rp, int o, int v, hipStream_t s) {
+  const long To = (long)o * (o + 1) / 2, Tv = (long)v * (v + 1) / 2, vv = (long)v * v;
+  if (bounds_checking() && !(chk(RL, (long)o * o * vv, "unpack_rpm RL") && chk(Rp, 2 * To * Tv, "unpack_rpm Rp")))
+    return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  dim3 grid((unsigned)std::min<long>((vv + kThreads - 1) / kThreads, 64), o * o);
+  hipLaunchKernelGGL(unpack_rpm_kernel, grid, dim3(kThreads), 0, s, RL, Rp, o, v);
+  return hipGetLastError();
+}
+
+hipError_t pack_vvvv(double* Vp, const double* W, int a0, int a1, int v, hipStream_t s) {
+  const long Tv = (long)v * (v + 1) / 2, vv = (long)v * v;
+  if (a1 <= a0) return hipSuccess;
+  if (bounds_checking() && !(chk(Vp, 2 * Tv * Tv, "pack_vvvv out") && chk(W, (long)(a1 - a0) * v * vv, "pack_vvvv in")))
+    return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  dim3 grid((unsigned)std::min<long>((vv + kThreads - 1) / kThreads, 64), (a1 - a0) * v);
+  hipLaunchKernelGGL(pack_vvvv_kernel, grid, dim3(kThreads), 0, s, Vp, W, a0, v);
   return hipGetLastError();
 }
 

@@ -49,6 +49,11 @@ struct Gemm {
   long scm = 0, scn = 0, sc1 = 0, sc2 = 0;
   double alpha = 1.0, beta = 0.0;
   int nb1 = 1, nb2 = 1, nred = 1;
+  // Optional scratch for split-K: when the output has too few tiles to fill the chip, the
+  // (reduction x K) iteration space is cut into slices whose partial tiles land here and
+  // are then summed in a fixed order (deterministic).  nullptr disables splitting.
+  double* ws = nullptr;
+  long ws_elems = 0;
 };
 
 // Convenience constructors for row-major matrices:
@@ -76,6 +81,13 @@ hipError_t permute4_strided(double* out, const long ostr[4], const int dims[4], 
 // Assembly of the doubles residual (see residual.hip for the formula).
 hipError_t assemble_r2(double* r2, const double* g1, const double* rl, const double* em, const double* p1,
                        const double* p2, int no, int nv, hipStream_t s);
+
+// Pair packing of the particle-particle ladder (p(i,j) = row-major index of i <= j).
+hipError_t pack_pairs(double* out, const double* in, int o, long L, hipStream_t s);     // out[p][x] = in[i][j][x]
+hipError_t unpack_pairs(double* RL, const double* Rp, int o, int v, hipStream_t s);    // mirror i > j rows
+hipError_t pack_tpm(double* tp, const double* t2, int o, int v, hipStream_t s);         // [2][T(o)][T(v)]
+hipError_t unpack_rpm(double* RL, const double* Rp, int o, int v, hipStream_t s);       // from [2][T(o)][T(v)]
+hipError_t pack_vvvv(double* Vp, const double* W, int a0, int a1, int v, hipStream_t s);  // rows a0 <= a < a1
 
 // r1[i][a] += Fhat[no+a][i]
 hipError_t add_fvo(double* r1, const double* fhat, int no, int nv, hipStream_t s);

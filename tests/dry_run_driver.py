@@ -39,7 +39,9 @@ def main(shapes):
     L.ascc_ints_free.argtypes = [vp]
     L.ascc_diis_free.argtypes = [vp]
     ok = True
-    for (o, v, Q, diag) in shapes:
+    for shape in shapes:
+        o, v, Q, diag = shape[:4]
+        mode = shape[4] if len(shape) > 4 else 0
         n = o + v
         base = [0x200000000000]
 
@@ -51,7 +53,7 @@ def main(shapes):
         B = fake(8 * Q * n * n)
         F = fake(8 * (n if diag else n * n))
         h = vp()
-        rc = L.ascc_build_ints(B, F, diag, o, v, Q, 0, 0, None, ctypes.byref(h))
+        rc = L.ascc_build_ints(B, F, diag, o, v, Q, 0, mode, None, ctypes.byref(h))
         msgs = []
         if rc == 0:
             t1, t2, r1, r2, e, st = (fake(8 * o * v), fake(8 * o * o * v * v), fake(8 * o * v),
@@ -69,10 +71,10 @@ def main(shapes):
                 rc = L.ascc_solve(h, ctypes.byref(Opts(1e-8, 0, 0, 3, 8, 1, 0.0)), t1, t2, ctypes.byref(res), None)
             L.ascc_ints_free(h)
         if rc == 0:
-            print(f"OK {o} {v} {Q}", flush=True)
+            print(f"OK {o} {v} {Q} mode {mode}", flush=True)
         else:
             ok = False
-            print(f"FAIL {o} {v} {Q} status {rc}: {L.ascc_last_error().decode()}", flush=True)
+            print(f"FAIL {o} {v} {Q} mode {mode} status {rc}: {L.ascc_last_error().decode()}", flush=True)
     return 0 if ok else 1
 
 

@@ -39,17 +39,19 @@ SHAPES = [
 ]
 
 
+@pytest.mark.parametrize("mode", ["full", "packed"])
 @pytest.mark.parametrize("o,v,Q,seed,full", SHAPES)
-def test_residual_and_energy_match_oracle(P, o, v, Q, seed, full):
+def test_residual_and_energy_match_oracle(P, o, v, Q, seed, full, mode):
     from oracle import cs_ccsd
 
     from .gpu_util import dev, gpu_residual
 
-    print(f"case o={o} v={v} Q={Q} seed={seed} full_fock={full}", flush=True)
+    print(f"case o={o} v={v} Q={Q} seed={seed} full_fock={full} vvvv={mode}", flush=True)
     B, eps, fock, t1, t2 = _case(o, v, Q, seed, full)
     r1_ref, r2_ref = cs_ccsd.residual(B, fock, t1, t2)
     e_ref = cs_ccsd.energy(B, fock, t1, t2)
-    ints = P.ascc_build_ints(dev(B), dev(fock if full else eps), o)
+    vm = P.ASCC_VVVV_FULL if mode == "full" else P.ASCC_VVVV_PACKED
+    ints = P.ascc_build_ints(dev(B), dev(fock if full else eps), o, vvvv_mode=vm)
     r1, r2, e = gpu_residual(P, ints, t1, t2)
     ints.close()
     assert np.abs(r1 - r1_ref).max() <= TOL
@@ -126,8 +128,13 @@ def test_solve_matches_oracle_o5v20q60(P):
 
 
 @pytest.mark.slow
-def test_residual_parity_o20v180q600_full(P):
-    """Full-size residual (the o20 v180 Q600 workload, literal generator) against the oracle."""
+def test_residual_parity_o20v180q600_full_size():
+    """Full-size residual (the o20 v180 Q600 workload, literal generator) against the oracle, both vvvv modes."""
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2501_10515_amd as P
     from oracle import cs_ccsd
 
     from .gpu_util import dev, gpu_residual
@@ -135,13 +142,16 @@ def test_residual_parity_o20v180q600_full(P):
     o, v, Q = 20, 180, 600
     B, eps = make_system(o, v, Q, 1)
     t1, t2 = random_amplitudes(o, v, 77, 0.01, 0.01)
-    ints = P.ascc_build_ints(dev(B), dev(eps), o)
-    r1, r2, e = gpu_residual(P, ints, t1, t2)
-    ints.close()
     fock = np.diag(eps)
     r1_ref, r2_ref = cs_ccsd.residual(B, fock, t1, t2)
     e_ref = cs_ccsd.energy(B, fock, t1, t2)
     scale = max(1.0, np.abs(r2_ref).max())
-    assert np.abs(r1 - r1_ref).max() <= TOL * scale
-    assert np.abs(r2 - r2_ref).max() <= TOL * scale
-    assert abs(e - e_ref) <= TOL * max(1.0, abs(e_ref))
+    for vm in (P.ASCC_VVVV_FULL, P.ASCC_VVVV_PACKED):
+        print(f"o20v180q600 vvvv_mode={vm}", flush=True)
+        ints = P.ascc_build_ints(dev(B), dev(eps), o, vvvv_mode=vm)
+        r1, r2, e = gpu_residual(P, ints, t1, t2)
+        ints.close()
+        torch.cuda.empty_cache()
+        assert np.abs(r1 - r1_ref).max() <= TOL * scale
+        assert np.abs(r2 - r2_ref).max() <= TOL * scale
+        assert abs(e - e_ref) <= TOL * max(1.0, abs(e_ref))
