@@ -53,7 +53,11 @@ enum {
 };
 
 enum {
-  ASCC_PREC_FP64 = 0 /* every contraction in FP64 on the FP64 matrix cores */
+  ASCC_PREC_FP64 = 0,  /* every contraction in FP64 on the FP64 matrix cores                    */
+  ASCC_PREC_FP32 = 1,  /* the N^6 contractions (pp ladder, W/Z, rings) on FP32 matrix cores     */
+  ASCC_PREC_BF16X3 = 2 /* the same on bf16 matrix cores with x = hi + lo splits: hi*hi + hi*lo  */
+                       /* + lo*hi.  Both low modes accumulate in FP32 within K chunks of 2048   */
+                       /* and in FP64 across chunks; everything else stays FP64               */
 };
 
 enum {
@@ -77,6 +81,9 @@ int ascc_workspace_bytes(int no, int nv, int naux, int precision, int vvvv_mode,
  *   d_fock     [n] (fock_is_diag = 1: orbital energies) or [n][n] (fock_is_diag = 0): the Fock
  *                            matrix of the reference determinant; its diagonal gives the
  *                            Jacobi denominators
+ *   precision  ASCC_PREC_FP64, or a low precision (ASCC_PREC_FP32 / ASCC_PREC_BF16X3): the
+ *              handle then also holds FP32 copies of the constant operands and can switch
+ *              between FP64 and low precision (ascc_set_precision)
  *   vvvv_mode  ASCC_VVVV_FULL or ASCC_VVVV_PACKED (storage of the (ac|bd) block)
  * Copies what it needs from d_B / d_fock (they may be freed after the call), forms the
  * constant integral blocks on `stream`, and synchronises `stream` before returning.
@@ -84,6 +91,14 @@ int ascc_workspace_bytes(int no, int nv, int naux, int precision, int vvvv_mode,
  * Errors: ASCC_E_ARG, ASCC_E_SHAPE (no, nv, naux < 1), ASCC_E_NOMEM, ASCC_E_HIP. */
 int ascc_build_ints(const double* d_B, const double* d_fock, int fock_is_diag, int no, int nv, int naux,
                     int precision, int vvvv_mode, void* stream, ascc_ints** out);
+
+/* Arithmetic of the N^6 contractions in the following ascc_residual calls on this handle:
+ * ASCC_PREC_FP64 always; ASCC_PREC_FP32 / ASCC_PREC_BF16X3 only if the handle was built with a
+ * low precision (it then holds FP32 copies of the constant operands).  ascc_build_ints starts
+ * the handle in the precision it was built with.  Host-only.
+ * Errors: ASCC_E_ARG, ASCC_E_STATE (low precision requested on an FP64-only handle). */
+int ascc_set_precision(ascc_ints* ints, int precision);
+int ascc_get_precision(const ascc_ints* ints);
 
 /* Residual and energy at the given amplitudes (Eqs. (eqn:energy), (eqn:amp)).
  *   d_t1 [no][nv], d_t2 [no][no][nv][nv] with t2[i][j][a][b] == t2[j][i][b][a] (read only)
@@ -122,6 +137,12 @@ typedef struct ascc_opts {
   int diis_size;      /* 1..16 (1 disables extrapolation)                             */
   int diis_start;     /* first 0-based iteration whose pair is stored                 */
   double level_shift; /* added to |D| (D - shift); 0 for the plain Jacobi step         */
+  /* FP64 refinement of a low-precision solve: when the handle's precision is FP32 or BF16X3,
+   * the iteration first runs in that precision without a convergence test until |R|_2 <=
+   * lowp_rnorm or lowp_maxiter iterations (<= 0: that bound unused), then restarts DIIS and
+   * continues in FP64 until the tests above pass.  The handle's precision is restored. */
+  double lowp_rnorm;
+  int lowp_maxiter;
 } ascc_opts;
 
 typedef struct ascc_result {
@@ -131,6 +152,7 @@ typedef struct ascc_result {
   double de;       /* last energy change                                    */
   int iterations;  /* residual evaluations made                             */
   int converged;   /* 1 if every requested test passed                      */
+  int lowp_iterations; /* of which in low precision                         */
 } ascc_result;
 
 /* Iterate residual -> convergence test -> update from the amplitudes in (d_t1, d_t2)

@@ -17,6 +17,8 @@ from ._lib import (  # noqa: F401
     ASCC_E_NOT_CONVERGED,
     ASCC_E_SHAPE,
     ASCC_E_STATE,
+    ASCC_PREC_BF16X3,
+    ASCC_PREC_FP32,
     ASCC_PREC_FP64,
     ASCC_VVVV_FULL,
     ASCC_VVVV_PACKED,
@@ -31,7 +33,9 @@ from ._lib import (  # noqa: F401
     ascc_phase_name,
     ascc_timing_enable,
     ascc_timing_read,
+    ascc_get_precision,
     ascc_residual,
+    ascc_set_precision,
     ascc_solve,
     ascc_update,
     ascc_workspace_bytes,

@@ -16,6 +16,8 @@ ASCC_E_NONFINITE = -5
 ASCC_E_NOT_CONVERGED = -6
 ASCC_E_STATE = -7
 ASCC_PREC_FP64 = 0
+ASCC_PREC_FP32 = 1
+ASCC_PREC_BF16X3 = 2
 ASCC_VVVV_FULL = 0
 ASCC_VVVV_PACKED = 1
 
@@ -37,17 +39,19 @@ class AsccError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("tol_rnorm", ctypes.c_double), ("tol_rmax", ctypes.c_double), ("tol_de", ctypes.c_double),
                 ("maxiter", ctypes.c_int), ("diis_size", ctypes.c_int), ("diis_start", ctypes.c_int),
-                ("level_shift", ctypes.c_double)]
+                ("level_shift", ctypes.c_double), ("lowp_rnorm", ctypes.c_double), ("lowp_maxiter", ctypes.c_int)]
 
 
 class Result(ctypes.Structure):
     _fields_ = [("e_corr", ctypes.c_double), ("rnorm", ctypes.c_double), ("rmax", ctypes.c_double),
-                ("de", ctypes.c_double), ("iterations", ctypes.c_int), ("converged", ctypes.c_int)]
+                ("de", ctypes.c_double), ("iterations", ctypes.c_int), ("converged", ctypes.c_int),
+                ("lowp_iterations", ctypes.c_int)]
 
 
 EXPORTS = ("ascc_workspace_bytes", "ascc_build_ints", "ascc_residual", "ascc_diis_create", "ascc_diis_reset",
            "ascc_update", "ascc_solve", "ascc_ints_free", "ascc_diis_free", "ascc_ints_shape", "ascc_last_error",
-           "ascc_phase_count", "ascc_phase_name", "ascc_timing_enable", "ascc_timing_read")
+           "ascc_phase_count", "ascc_phase_name", "ascc_timing_enable", "ascc_timing_read", "ascc_set_precision",
+           "ascc_get_precision")
 
 
 def load_library():
@@ -78,6 +82,8 @@ def load_library():
     L.ascc_phase_name.argtypes = [c_int]
     L.ascc_phase_name.restype = ctypes.c_char_p
     L.ascc_timing_enable.argtypes = [vp, c_int]
+    L.ascc_set_precision.argtypes = [vp, c_int]
+    L.ascc_get_precision.argtypes = [vp]
     L.ascc_timing_read.argtypes = [vp, ctypes.POINTER(c_double), ctypes.POINTER(c_int), c_int]
     for name in EXPORTS:
         if name not in ("ascc_ints_free", "ascc_diis_free", "ascc_last_error", "ascc_phase_name"):
@@ -199,14 +205,15 @@ def ascc_update(ints: Ints, diis: Diis, t1, t2, r1, r2, e, stats, level_shift: f
 
 
 def ascc_solve(ints: Ints, t1, t2, tol_rnorm=1e-8, tol_rmax=0.0, tol_de=0.0, maxiter=100, diis_size=8,
-               diis_start=1, level_shift=0.0, stream=None, raise_on_not_converged=True) -> dict:
+               diis_start=1, level_shift=0.0, lowp_rnorm=0.0, lowp_maxiter=0, stream=None,
+               raise_on_not_converged=True) -> dict:
     o, v = ints.no, ints.nv
-    opts = Opts(tol_rnorm, tol_rmax, tol_de, maxiter, diis_size, diis_start, level_shift)
+    opts = Opts(tol_rnorm, tol_rmax, tol_de, maxiter, diis_size, diis_start, level_shift, lowp_rnorm, lowp_maxiter)
     res = Result()
     rc = load_library().ascc_solve(ints.handle, ctypes.byref(opts), _dev(t1, "t1", (o, v)),
                                    _dev(t2, "t2", (o, o, v, v)), ctypes.byref(res), _stream(stream))
     out = dict(e_corr=res.e_corr, rnorm=res.rnorm, rmax=res.rmax, de=res.de, iterations=res.iterations,
-               converged=bool(res.converged), status=rc)
+               converged=bool(res.converged), lowp_iterations=res.lowp_iterations, status=rc)
     if rc != ASCC_OK and not (rc == ASCC_E_NOT_CONVERGED and not raise_on_not_converged):
         raise AsccError(rc, ascc_last_error())
     return out
@@ -231,3 +238,11 @@ def ascc_timing_read(ints: Ints) -> dict:
     cnt = (ctypes.c_int * n)()
     _check(load_library().ascc_timing_read(ints.handle, ms, cnt, n))
     return {ascc_phase_name(k): (ms[k], cnt[k]) for k in range(n)}
+
+
+def ascc_set_precision(ints: Ints, precision: int):
+    _check(load_library().ascc_set_precision(ints.handle, precision))
+
+
+def ascc_get_precision(ints: Ints) -> int:
+    return load_library().ascc_get_precision(ints.handle)

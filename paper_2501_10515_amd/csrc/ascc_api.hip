@@ -158,6 +158,10 @@ struct ascc_ints {
   double *Abc, *Bkj, *Fvvp, *Foop, *Fovh;  // small
   double *partial;               // reduction scratch
   double *splitk;                // split-K partial tiles of small-output contractions
+  // FP32 shadows of the large-contraction operands (only for a low-precision integral set)
+  float *Vf, *GwzTf, *KLf;       // constant: vvvv, [ov+o^2][v^2] transposed (kc|bd)|(kc|ld), K|L
+  float *Tpf, *t2f, *TUf, *XZf;  // per residual: ladder rows, t2 rows, Tx|U, Xc|Zd
+  int cur_prec = 0;              // arithmetic of the large contractions in the next residual
   // optional per-phase timing with HIP events (ascc_timing_enable)
   bool timing = false;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;  // (phase, (start, end))
@@ -253,6 +257,19 @@ std::vector<std::pair<double* ascc_ints::*, long>> ints_plan(long o, long v, lon
       {&ascc_ints::Abc, vv},          {&ascc_ints::Bkj, oo},         {&ascc_ints::Fvvp, vv},
       {&ascc_ints::Foop, oo},         {&ascc_ints::Fovh, ov},        {&ascc_ints::partial, 8192},
       {&ascc_ints::splitk, kSplitKElems},
+  };
+}
+
+// FP32 shadows allocated for a low-precision integral set.
+std::vector<std::pair<float* ascc_ints::*, long>> lowp_plan(long o, long v, int mode) {
+  const long ov = o * v, oo = o * o, vv = v * v, ovov = ov * ov;
+  const long To = o * (o + 1) / 2, Tv = v * (v + 1) / 2;
+  const bool full = (mode == ASCC_VVVV_FULL);
+  return {
+      {&ascc_ints::Vf, full ? vv * vv : 2 * Tv * Tv}, {&ascc_ints::GwzTf, (ov + oo) * vv},
+      {&ascc_ints::KLf, 2 * ovov},                    {&ascc_ints::Tpf, full ? To * vv : 2 * To * Tv},
+      {&ascc_ints::t2f, oo * vv},                     {&ascc_ints::TUf, 2 * ovov},
+      {&ascc_ints::XZf, 2 * ovov},
   };
 }
 
@@ -406,24 +423,57 @@ int add_two_electron_fock(const ascc_ints* I, double* F, const double* Bq, doubl
 }
 
 
+// C_z[m][n] = sum_k A_z[m][k] B_z[n][k] in the handle's current low precision (FP64 result).
+GemmLP lp_nt(const ascc_ints* I, long M, long N, long K, int nb, const float* A, long lda, long sa2, const float* B,
+             long ldb, long sb2, double* C, long ldc, long sc2) {
+  GemmLP g;
+  g.M = (int)M;
+  g.N = (int)N;
+  g.K = (int)K;
+  g.nb = nb;
+  g.A = A;
+  g.lda = lda;
+  g.sa2 = sa2;
+  g.B = B;
+  g.ldb = ldb;
+  g.sb2 = sb2;
+  g.C = C;
+  g.scm = ldc;
+  g.scn = 1;
+  g.sc2 = sc2;
+  g.prec = (I->cur_prec == ASCC_PREC_BF16X3) ? kPrecBF16x3 : kPrecFP32;
+  return g;
+}
+
 // Particle-particle ladder RL[i][j][a][b] = sum_cd t_ij^cd (ac|bd), computed for pairs i <= j
 // only (RL_ji^ba = RL_ij^ab).  FULL: against the full (ac|bd) matrix.  PACKED: against its
 // (ab)-symmetric and antisymmetric halves, R+- = t+- V+-, one batched launch.
 int pp_ladder(ascc_ints* I, const double* t2, hipStream_t s) {
   const int o = I->no, v = I->nv;
   const long vv = I->vv, To = (long)o * (o + 1) / 2, Tv = (long)v * (v + 1) / 2;
+  const bool lowp = I->cur_prec != ASCC_PREC_FP64;
   if (I->vvvv_mode == ASCC_VVVV_FULL) {
     HIPCHK(pack_pairs(I->Tp, t2, o, vv, s));
-    HIPCHK(mm(I, gemm_rm(To, vv, vv, 1.0, I->Tp, vv, false, I->V, vv, true, 0.0, I->Rp, vv), s));
+    if (lowp) {
+      HIPCHK(cvt_f32(I->Tpf, I->Tp, To * vv, s));
+      HIPCHK(gemm_lowp(lp_nt(I, To, vv, vv, 1, I->Tpf, vv, 0, I->Vf, vv, 0, I->Rp, vv, 0), s));
+    } else {
+      HIPCHK(mm(I, gemm_rm(To, vv, vv, 1.0, I->Tp, vv, false, I->V, vv, true, 0.0, I->Rp, vv), s));
+    }
     HIPCHK(unpack_pairs(I->RL, I->Rp, o, v, s));
   } else {
     HIPCHK(pack_tpm(I->Tp, t2, o, v, s));
-    Gemm g = gemm_rm(To, Tv, Tv, 1.0, I->Tp, Tv, false, I->V, Tv, true, 0.0, I->Rp, Tv);
-    g.sa2 = To * Tv;
-    g.sb2 = Tv * Tv;
-    g.sc2 = To * Tv;
-    g.nb2 = 2;
-    HIPCHK(mm(I, g, s));
+    if (lowp) {
+      HIPCHK(cvt_f32(I->Tpf, I->Tp, 2 * To * Tv, s));
+      HIPCHK(gemm_lowp(lp_nt(I, To, Tv, Tv, 2, I->Tpf, Tv, To * Tv, I->Vf, Tv, Tv * Tv, I->Rp, Tv, To * Tv), s));
+    } else {
+      Gemm g = gemm_rm(To, Tv, Tv, 1.0, I->Tp, Tv, false, I->V, Tv, true, 0.0, I->Rp, Tv);
+      g.sa2 = To * Tv;
+      g.sb2 = Tv * Tv;
+      g.sc2 = To * Tv;
+      g.nb2 = 2;
+      HIPCHK(mm(I, g, s));
+    }
     HIPCHK(unpack_rpm(I->RL, I->Rp, o, v, s));
   }
   return ASCC_OK;
@@ -484,7 +534,13 @@ int residual_fp64(ascc_ints* I, const double* t1, const double* t2, double* r1, 
   phase_end(I, s);
   // --- W_ij[k,b], Z_ij[k,l] in one product against [(kc|bd) | (kc|ld)]
   phase_begin(I, PH_WZ, s);
-  HIPCHK(mm(I, gemm_rm(oo, wzl, vv, 1.0, t2, vv, false, I->Gwz, wzl, false, 0.0, I->WZ, wzl), s));
+  const bool lowp = I->cur_prec != ASCC_PREC_FP64;
+  if (lowp) {
+    HIPCHK(cvt_f32(I->t2f, t2, oo * vv, s));
+    HIPCHK(gemm_lowp(lp_nt(I, oo, wzl, vv, 1, I->t2f, vv, 0, I->GwzTf, vv, 0, I->WZ, wzl, 0), s));
+  } else {
+    HIPCHK(mm(I, gemm_rm(oo, wzl, vv, 1.0, t2, vv, false, I->Gwz, wzl, false, 0.0, I->WZ, wzl), s));
+  }
 
   phase_end(I, s);
   // --- chi[ij][kl] = g^_kilj + Z_ij[k,l]
@@ -507,7 +563,10 @@ int residual_fp64(ascc_ints* I, const double* t1, const double* t2, double* r1, 
 
   // --- rings: Y1 = Tx K, Y2 = U L (batched pair)
   phase_begin(I, PH_RING_Y, s);
-  {
+  if (lowp) {  // K and L are symmetric matrices, so B[n][k] = B[k][n]
+    HIPCHK(cvt_f32(I->TUf, I->TU, 2 * ovov, s));
+    HIPCHK(gemm_lowp(lp_nt(I, ov, ov, ov, 2, I->TUf, ov, ovov, I->KLf, ov, ovov, I->Y, ov, ovov), s));
+  } else {
     Gemm g = gemm_rm(ov, ov, ov, 1.0, I->TU, ov, false, I->KL, ov, false, 0.0, I->Y, ov);
     g.sa2 = ovov;
     g.sb2 = ovov;
@@ -528,7 +587,10 @@ int residual_fp64(ascc_ints* I, const double* t1, const double* t2, double* r1, 
   }
   phase_end(I, s);
   phase_begin(I, PH_RING_P, s);
-  {  // P1 = Tx Xc^T, P2 = U Zd^T
+  if (lowp) {  // P1 = Tx Xc^T, P2 = U Zd^T
+    HIPCHK(cvt_f32(I->XZf, I->XZ, 2 * ovov, s));
+    HIPCHK(gemm_lowp(lp_nt(I, ov, ov, ov, 2, I->TUf, ov, ovov, I->XZf, ov, ovov, I->P, ov, ovov), s));
+  } else {
     Gemm g = gemm_rm(ov, ov, ov, 1.0, I->TU, ov, false, I->XZ, ov, true, 0.0, I->P, ov);
     g.sa2 = ovov;
     g.sb2 = ovov;
@@ -816,6 +878,31 @@ int build_constants(ascc_ints* I, const double* Bsrc, const double* fock, int fo
   return ASCC_OK;
 }
 
+// FP32 shadows of the constant operands: (ac|bd), [(kc|bd)|(kc|ld)] transposed to [n][(cd)], K|L.
+int build_lowp_shadows(ascc_ints* I, hipStream_t s) {
+  const long vv = I->vv, ov = I->ov, oo = I->oo, wzl = ov + oo;
+  const long Tv = (long)I->nv * (I->nv + 1) / 2;
+  const long nV = (I->vvvv_mode == ASCC_VVVV_FULL) ? vv * vv : 2 * Tv * Tv;
+  HIPCHK(cvt_f32(I->Vf, I->V, nV, s));
+  HIPCHK(cvt_f32(I->KLf, I->KL, 2 * I->ovov, s));
+  double* tmp = nullptr;
+  std::vector<void*> tmp_alloc;
+  size_t tmp_bytes = 0;
+  int rc = dalloc(tmp_alloc, tmp_bytes, &tmp, (size_t)(wzl * vv));
+  if (rc) return rc;
+  int d[4] = {(int)wzl, (int)vv, 1, 1};  // tmp[n][cd] = Gwz[cd][n]
+  Perm4In x = pin(I->Gwz, 1, wzl, 0, 0, 1.0);
+  hipError_t e = permute4(tmp, d, 0.0, &x, 1, s);
+  if (e == hipSuccess) e = cvt_f32(I->GwzTf, tmp, wzl * vv, s);
+  if (e == hipSuccess) e = d_sync(s);
+  free_all(tmp_alloc);
+  if (e != hipSuccess) {
+    if (!(bounds_checking() && e == hipErrorInvalidValue)) set_error(std::string("FP32 shadows: ") + hipGetErrorString(e));
+    return ASCC_E_HIP;
+  }
+  return ASCC_OK;
+}
+
 int check_shape(int no, int nv, int naux) {
   if (no < 1 || nv < 1 || naux < 1) return fail(ASCC_E_SHAPE, "no, nv and naux must be >= 1");
   if (no > 256 || nv > 4096 || naux > 65535)
@@ -835,12 +922,15 @@ int ascc_workspace_bytes(int no, int nv, int naux, int precision, int vvvv_mode,
                          size_t* diis_bytes) {
   int rc = check_shape(no, nv, naux);
   if (rc) return rc;
-  if (precision != ASCC_PREC_FP64) return fail(ASCC_E_ARG, "unsupported precision");
+  if (precision < ASCC_PREC_FP64 || precision > ASCC_PREC_BF16X3) return fail(ASCC_E_ARG, "unsupported precision");
   if (vvvv_mode != ASCC_VVVV_FULL && vvvv_mode != ASCC_VVVV_PACKED) return fail(ASCC_E_ARG, "unsupported vvvv_mode");
   if (diis_size < 1 || diis_size > kMaxDiis) return fail(ASCC_E_ARG, "diis_size must be in 1..16");
   size_t total = 0;
   for (const auto& item : ints_plan(no, nv, naux, vvvv_mode))
     total += std::max<size_t>((size_t)item.second, 1) * sizeof(double);
+  if (precision != ASCC_PREC_FP64)
+    for (const auto& item : lowp_plan(no, nv, vvvv_mode))
+      total += std::max<size_t>((size_t)item.second, 1) * sizeof(float);
   const long len = (long)no * nv + (long)no * no * nv * nv;
   if (ints_bytes) *ints_bytes = total;
   if (diis_bytes)
@@ -848,6 +938,17 @@ int ascc_workspace_bytes(int no, int nv, int naux, int precision, int vvvv_mode,
                   (size_t)update_partial_blocks() * (3 + kMaxDiis) * sizeof(double) + sizeof(DiisState);
   return ASCC_OK;
 }
+
+int ascc_set_precision(ascc_ints* I, int precision) {
+  if (!I) return fail(ASCC_E_ARG, "NULL handle");
+  if (precision < ASCC_PREC_FP64 || precision > ASCC_PREC_BF16X3) return fail(ASCC_E_ARG, "unsupported precision");
+  if (precision != ASCC_PREC_FP64 && I->precision == ASCC_PREC_FP64)
+    return fail(ASCC_E_STATE, "integral set was built for FP64 only (no FP32 shadows)");
+  I->cur_prec = precision;
+  return ASCC_OK;
+}
+
+int ascc_get_precision(const ascc_ints* I) { return I ? I->cur_prec : -1; }
 
 int ascc_phase_count(void) { return kNumPhases; }
 
@@ -895,7 +996,7 @@ int ascc_build_ints(const double* d_B, const double* d_fock, int fock_is_diag, i
   if (!d_B || !d_fock) return fail(ASCC_E_ARG, "d_B and d_fock must be device pointers");
   int rc = check_shape(no, nv, naux);
   if (rc) return rc;
-  if (precision != ASCC_PREC_FP64) return fail(ASCC_E_ARG, "unsupported precision");
+  if (precision < ASCC_PREC_FP64 || precision > ASCC_PREC_BF16X3) return fail(ASCC_E_ARG, "unsupported precision");
   if (vvvv_mode != ASCC_VVVV_FULL && vvvv_mode != ASCC_VVVV_PACKED) return fail(ASCC_E_ARG, "unsupported vvvv_mode");
   hipStream_t s = static_cast<hipStream_t>(stream);
   ascc_ints* I = new ascc_ints();
@@ -916,10 +1017,17 @@ int ascc_build_ints(const double* d_B, const double* d_fock, int fock_is_diag, i
   for (const auto& item : ints_plan(no, nv, naux, vvvv_mode)) {
     if (!rc) rc = dalloc(I->allocs, I->bytes, &(I->*(item.first)), (size_t)item.second);
   }
+  if (precision != ASCC_PREC_FP64) {
+    for (const auto& item : lowp_plan(no, nv, vvvv_mode)) {
+      if (!rc) rc = dalloc(I->allocs, I->bytes, &(I->*(item.first)), (size_t)item.second);
+    }
+  }
+  I->cur_prec = precision;
   ScopedBuffers user;
   user.add(d_B, sizeof(double) * Q * nn);
   user.add(d_fock, sizeof(double) * (fock_is_diag ? n : nn));
   if (!rc) rc = build_constants(I, d_B, d_fock, fock_is_diag, s);
+  if (!rc && precision != ASCC_PREC_FP64) rc = build_lowp_shadows(I, s);
   if (!rc) {
     hipError_t e = d_sync(s);
     if (e != hipSuccess) rc = fail(ASCC_E_HIP, std::string("ascc_build_ints: ") + hipGetErrorString(e));
@@ -1046,6 +1154,8 @@ int ascc_solve(ascc_ints* I, const ascc_opts* opts, double* t1, double* t2, ascc
   if (opts->maxiter < 1) return fail(ASCC_E_ARG, "maxiter must be >= 1");
   hipStream_t s = static_cast<hipStream_t>(stream);
   std::memset(res, 0, sizeof(*res));
+  const int prec0 = I->cur_prec;
+  bool lowp_phase = (prec0 != ASCC_PREC_FP64);
   ascc_diis* D = nullptr;
   int rc = ascc_diis_create(I, opts->diis_size, opts->diis_start, &D);
   if (rc) return rc;
@@ -1069,6 +1179,7 @@ int ascc_solve(ascc_ints* I, const ascc_opts* opts, double* t1, double* t2, ascc
   user.add(t1, sizeof(double) * I->ov);
   user.add(t2, sizeof(double) * I->oovv);
   int status = ASCC_E_NOT_CONVERGED;
+  int lowp_iters = 0;
   for (int it = 0; !rc && it < opts->maxiter; ++it) {
     rc = residual_fp64(I, t1, t2, r1, r2, e, s);
     if (rc) break;
@@ -1094,13 +1205,29 @@ int ascc_solve(ascc_ints* I, const ascc_opts* opts, double* t1, double* t2, ascc
       status = fail(ASCC_E_NONFINITE, "non-finite residual or energy at iteration " + std::to_string(it));
       break;
     }
-    const bool ok = (opts->tol_rnorm <= 0 || hstats[3] <= opts->tol_rnorm) &&
-                    (opts->tol_rmax <= 0 || hstats[2] <= opts->tol_rmax) &&
-                    (opts->tol_de <= 0 || std::fabs(hstats[1]) < opts->tol_de);
-    if (ok) {
-      res->converged = 1;
-      status = ASCC_OK;
-      break;
+    if (lowp_phase) {
+      // low-precision bulk: no convergence test; hand over to FP64 once the residual is small
+      // enough or the low-precision budget is spent (the DIIS history restarts in FP64)
+      ++lowp_iters;
+      res->lowp_iterations = lowp_iters;
+      const bool done = (opts->lowp_rnorm > 0 && hstats[3] <= opts->lowp_rnorm) ||
+                        (opts->lowp_maxiter > 0 && lowp_iters >= opts->lowp_maxiter);
+      if (done) {
+        lowp_phase = false;
+        I->cur_prec = ASCC_PREC_FP64;
+        rc = ascc_diis_reset(D, stream);
+        if (rc) break;
+        continue;  // re-evaluate the same amplitudes in FP64
+      }
+    } else {
+      const bool ok = (opts->tol_rnorm <= 0 || hstats[3] <= opts->tol_rnorm) &&
+                      (opts->tol_rmax <= 0 || hstats[2] <= opts->tol_rmax) &&
+                      (opts->tol_de <= 0 || std::fabs(hstats[1]) < opts->tol_de);
+      if (ok) {
+        res->converged = 1;
+        status = ASCC_OK;
+        break;
+      }
     }
     // accept the update
     if (d_copy(t1, t1s, sizeof(double) * I->ov, hipMemcpyDeviceToDevice, s) != hipSuccess ||
@@ -1109,6 +1236,7 @@ int ascc_solve(ascc_ints* I, const ascc_opts* opts, double* t1, double* t2, ascc
       break;
     }
   }
+  I->cur_prec = prec0;
   (void)d_sync(s);
   if (hstats && !dry_run()) (void)hipHostFree(hstats);
   free_all(work);

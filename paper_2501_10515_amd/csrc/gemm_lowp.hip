@@ -1,0 +1,295 @@
+// Low-precision contractions on the matrix cores, FP64 result:
+//
+//   C_z(m,n) = alpha * sum_k A_z[m][k] B_z[n][k] + beta * C_z(m,n)
+//
+// A and B are FP32 shadows of FP64 operands (row-major, K contiguous, rounded to nearest even
+// by the conversion kernels); C is FP64 with general strides.  Two arithmetic policies:
+//
+//   FP32   : v_mfma_f32_16x16x4_f32 on the FP32 values.
+//   BF16X3 : each FP32 value is split x = hi + lo with hi = RNE_bf16(x), lo = RNE_bf16(x - hi)
+//            while it is staged into LDS; v_mfma_f32_16x16x32_bf16 forms
+//            lo*hi + hi*lo + hi*hi (the lo*lo term, relative size 2^-16, is dropped).
+//
+// Both accumulate in FP32 inside a K chunk and add each chunk's partial sum into the FP64 C tile
+// (which the workgroup owns for the whole K range), so accumulation across chunks is FP64.
+//
+// MFMA lane layouts (gfx950, measured): f32 16x16x4 -- lane l supplies A(l%16, l/16) and
+// B(l/16, l%16); bf16 16x16x32 -- lane l supplies A(l%16, 8(l/16)+j) and B(8(l/16)+j, l%16),
+// j = 0..7; both return register r of lane l as C(4(l/16)+r, l%16).
+#include <cstdint>
+
+#include "internal.h"
+
+namespace ascc {
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned short us4 __attribute__((ext_vector_type(4)));
+
+struct LP {
+  int M, N, K;
+  const float* A;
+  long lda, sa2;
+  const float* B;
+  long ldb, sb2;
+  double* C;
+  long scm, scn, sc2;
+  double alpha, beta;
+  int tiles_m, tiles_n;
+  int chunk;  // K-tiles per FP32 accumulation chunk
+};
+
+// Round-to-nearest-even FP32 -> bf16 bits (finite inputs; NaN stays NaN).
+__device__ __forceinline__ unsigned short bf16_rne(float f) {
+  const uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  const uint32_t r = u + 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(r >> 16);
+}
+__device__ __forceinline__ float bf16_to_f(unsigned short h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+__device__ __forceinline__ void tile_of_lp(int bid, int tiles_m, int total, int& tm, int& tn) {
+  const int q = total >> 3, rem = total & 7;
+  const int x = bid & 7, local = bid >> 3;
+  const int tile = x * q + min(x, rem) + local;
+  tm = tile % tiles_m;
+  tn = tile / tiles_m;
+}
+
+constexpr int BM = 128, BN = 128, NT = 256;
+
+template <bool BF16>
+__global__ __launch_bounds__(NT, 1) void gemm_lowp_kernel(LP p) {
+  // K depth per LDS stage and row pitch of the staged tiles (elements)
+  constexpr int BK = 32;
+  constexpr int PITCH = BF16 ? (BK + 8) : (BK + 4);
+  // per stage each thread moves 4 float4 of A and 4 of B (128 x 32 floats each)
+  constexpr int LQ = BM * BK / 4 / NT;
+  static_assert(LQ == 4, "tile config");
+  using ST = typename std::conditional<BF16, unsigned short, float>::type;
+  constexpr int PLANES = BF16 ? 2 : 1;
+  __shared__ __attribute__((aligned(16))) ST As[2][PLANES][BM * PITCH];
+  __shared__ __attribute__((aligned(16))) ST Bs[2][PLANES][BN * PITCH];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;  // 2 x 2 waves of 64 x 64
+  int tm, tn;
+  tile_of_lp(blockIdx.x, p.tiles_m, p.tiles_m * p.tiles_n, tm, tn);
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int z = blockIdx.y;
+  const float* Ab = p.A + z * p.sa2;
+  const float* Bb = p.B + z * p.sb2;
+  double* Cb = p.C + z * p.sc2;
+
+  f4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+  const int nkt = (p.K + BK - 1) / BK;
+  f4 ra[LQ], rb[LQ];
+  // chunk c = tid + NT*l of the tile: row c/8, k offset 4*(c%8)
+  auto load = [&](int kt) {
+    const int k0 = kt * BK;
+#pragma unroll
+    for (int l = 0; l < LQ; ++l) {
+      const int c = tid + l * NT;
+      const int r = c >> 3, kq = (c & 7) * 4;
+      const int gk = k0 + kq;
+      const int gm = m0 + r, gn = n0 + r;
+      f4 va = f4{0.f, 0.f, 0.f, 0.f}, vb = va;
+      if (gm < p.M) {
+        const float* src = Ab + gm * p.lda + gk;
+        if (gk + 3 < p.K && ((reinterpret_cast<uintptr_t>(src) & 15) == 0)) {
+          va = *reinterpret_cast<const f4*>(src);
+        } else {
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+            if (gk + t < p.K) va[t] = src[t];
+        }
+      }
+      if (gn < p.N) {
+        const float* src = Bb + gn * p.ldb + gk;
+        if (gk + 3 < p.K && ((reinterpret_cast<uintptr_t>(src) & 15) == 0)) {
+          vb = *reinterpret_cast<const f4*>(src);
+        } else {
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+            if (gk + t < p.K) vb[t] = src[t];
+        }
+      }
+      ra[l] = va;
+      rb[l] = vb;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int l = 0; l < LQ; ++l) {
+      const int c = tid + l * NT;
+      const int r = c >> 3, kq = (c & 7) * 4;
+      if constexpr (BF16) {
+        us4 ah, al, bh, bl;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          ah[t] = bf16_rne(ra[l][t]);
+          al[t] = bf16_rne(ra[l][t] - bf16_to_f(ah[t]));
+          bh[t] = bf16_rne(rb[l][t]);
+          bl[t] = bf16_rne(rb[l][t] - bf16_to_f(bh[t]));
+        }
+        *reinterpret_cast<us4*>(&As[buf][0][r * PITCH + kq]) = ah;
+        *reinterpret_cast<us4*>(&As[buf][1][r * PITCH + kq]) = al;
+        *reinterpret_cast<us4*>(&Bs[buf][0][r * PITCH + kq]) = bh;
+        *reinterpret_cast<us4*>(&Bs[buf][1][r * PITCH + kq]) = bl;
+      } else {
+        *reinterpret_cast<f4*>(&As[buf][0][r * PITCH + kq]) = ra[l];
+        *reinterpret_cast<f4*>(&Bs[buf][0][r * PITCH + kq]) = rb[l];
+      }
+    }
+  };
+
+  auto flush = [&](bool first) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gm = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
+          const int gn = n0 + wn * 64 + j * 16 + (lane & 15);
+          if (gm < p.M && gn < p.N) {
+            double* c = Cb + gm * p.scm + gn * p.scn;
+            const double v = p.alpha * (double)acc[i][j][r];
+            if (first)
+              *c = (p.beta == 0.0) ? v : v + p.beta * *c;
+            else
+              *c += v;
+          }
+          acc[i][j][r] = 0.f;
+        }
+  };
+
+  const int lr = lane & 15, lg = lane >> 4;
+  if (nkt > 0) {
+    load(0);
+    store(0);
+  }
+  __syncthreads();
+  for (int kc = 0; kc < nkt; kc += p.chunk) {
+  const int kend = min(nkt, kc + p.chunk);
+  for (int kt = kc; kt < kend; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nkt) load(kt + 1);
+    if constexpr (BF16) {
+      const ST* ah = As[cur][0];
+      const ST* al = As[cur][1];
+      const ST* bh = Bs[cur][0];
+      const ST* bl = Bs[cur][1];
+      bf8 xa[4][2], xb[4][2];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int off = (wm * 64 + i * 16 + lr) * PITCH + 8 * lg;
+        xa[i][0] = *reinterpret_cast<const bf8*>(ah + off);
+        xa[i][1] = *reinterpret_cast<const bf8*>(al + off);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int off = (wn * 64 + j * 16 + lr) * PITCH + 8 * lg;
+        xb[j][0] = *reinterpret_cast<const bf8*>(bh + off);
+        xb[j][1] = *reinterpret_cast<const bf8*>(bl + off);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[i][1], xb[j][0], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[i][0], xb[j][1], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[i][0], xb[j][0], acc[i][j], 0, 0, 0);
+        }
+    } else {
+      const float* as = As[cur][0];
+      const float* bs = Bs[cur][0];
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 4) {
+        float xa[4], xb[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) xa[i] = as[(wm * 64 + i * 16 + lr) * PITCH + kk + lg];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) xb[j] = bs[(wn * 64 + j * 16 + lr) * PITCH + kk + lg];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[i], xb[j], acc[i][j], 0, 0, 0);
+      }
+    }
+    if (kt + 1 < nkt) store(cur ^ 1);
+    __syncthreads();
+  }
+  flush(kc == 0);
+  }
+  if (nkt == 0) flush(true);
+}
+
+// FP64 -> FP32 (round to nearest even), contiguous.
+__global__ __launch_bounds__(256) void cvt_f32_kernel(float* __restrict__ out, const double* __restrict__ in, long n) {
+  for (long x = blockIdx.x * 256L + threadIdx.x; x < n; x += (long)gridDim.x * 256) out[x] = (float)in[x];
+}
+
+}  // namespace
+
+hipError_t cvt_f32(float* out, const double* in, long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (bounds_checking() && !(range_ok(out, 0, n - 1, 4, "cvt_f32 out") && range_ok(in, 0, n - 1, 8, "cvt_f32 in")))
+    return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  long g = (n + 255) / 256;
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL(cvt_f32_kernel, dim3((unsigned)g), dim3(256), 0, s, out, in, n);
+  return hipGetLastError();
+}
+
+hipError_t gemm_lowp(const GemmLP& g, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0 || g.nb <= 0) return hipSuccess;
+  if (g.K <= 0 || g.nb > 65535 || (g.prec != kPrecFP32 && g.prec != kPrecBF16x3)) return hipErrorInvalidValue;
+  if (bounds_checking()) {
+    const long la = (long)(g.M - 1) * g.lda + (g.K - 1) + (long)(g.nb - 1) * g.sa2;
+    const long lb = (long)(g.N - 1) * g.ldb + (g.K - 1) + (long)(g.nb - 1) * g.sb2;
+    long lo = 0, hi = 0;
+    const long dc[3] = {(long)(g.M - 1) * g.scm, (long)(g.N - 1) * g.scn, (long)(g.nb - 1) * g.sc2};
+    for (long d : dc) {
+      if (d < 0) lo += d; else hi += d;
+    }
+    if (!(range_ok(g.A, 0, la, 4, "lowp A") && range_ok(g.B, 0, lb, 4, "lowp B") &&
+          range_ok(g.C, lo, hi, 8, "lowp C")))
+      return hipErrorInvalidValue;
+  }
+  if (dry_run()) return hipSuccess;
+  LP p;
+  p.M = g.M;
+  p.N = g.N;
+  p.K = g.K;
+  p.A = g.A;
+  p.lda = g.lda;
+  p.sa2 = g.sa2;
+  p.B = g.B;
+  p.ldb = g.ldb;
+  p.sb2 = g.sb2;
+  p.C = g.C;
+  p.scm = g.scm;
+  p.scn = g.scn;
+  p.sc2 = g.sc2;
+  p.alpha = g.alpha;
+  p.beta = g.beta;
+  p.tiles_m = (g.M + BM - 1) / BM;
+  p.tiles_n = (g.N + BN - 1) / BN;
+  p.chunk = g.chunk_ktiles > 0 ? g.chunk_ktiles : 64;
+  dim3 grid(p.tiles_m * p.tiles_n, g.nb, 1);
+  if (g.prec == kPrecBF16x3)
+    hipLaunchKernelGGL((gemm_lowp_kernel<true>), grid, dim3(NT), 0, s, p);
+  else
+    hipLaunchKernelGGL((gemm_lowp_kernel<false>), grid, dim3(NT), 0, s, p);
+  return hipGetLastError();
+}
+
+}  // namespace ascc

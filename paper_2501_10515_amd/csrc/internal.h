@@ -63,6 +63,26 @@ Gemm gemm_rm(int M, int N, int K, double alpha, const double* A, long lda, bool 
 
 hipError_t gemm_f64(const Gemm& g, hipStream_t s);
 
+// Low-precision contraction with FP64 result (gemm_lowp.hip):
+//   C_z(m,n) = alpha * sum_k A_z[m*lda + k] * B_z[n*ldb + k] + beta * C_z(m,n)
+// A, B are FP32 (K contiguous); prec selects FP32 MFMA or split-BF16x3 MFMA; FP32 accumulation
+// inside chunks of chunk_ktiles K-tiles (32 wide), FP64 accumulation across chunks.
+constexpr int kPrecFP64 = 0, kPrecFP32 = 1, kPrecBF16x3 = 2;
+struct GemmLP {
+  int M = 0, N = 0, K = 0, nb = 1;
+  const float* A = nullptr;
+  long lda = 0, sa2 = 0;
+  const float* B = nullptr;
+  long ldb = 0, sb2 = 0;
+  double* C = nullptr;
+  long scm = 0, scn = 1, sc2 = 0;
+  double alpha = 1.0, beta = 0.0;
+  int prec = kPrecFP32;
+  int chunk_ktiles = 64;
+};
+hipError_t gemm_lowp(const GemmLP& g, hipStream_t s);
+hipError_t cvt_f32(float* out, const double* in, long n, hipStream_t s);
+
 // ---------------------------------------------------------------------------------------
 // Element-wise kernels (elementwise.hip).
 

@@ -18,12 +18,13 @@ LIB = Path(__file__).resolve().parents[1] / "paper_2501_10515_amd" / "libascc.so
 class Opts(ctypes.Structure):
     _fields_ = [("tol_rnorm", ctypes.c_double), ("tol_rmax", ctypes.c_double), ("tol_de", ctypes.c_double),
                 ("maxiter", ctypes.c_int), ("diis_size", ctypes.c_int), ("diis_start", ctypes.c_int),
-                ("level_shift", ctypes.c_double)]
+                ("level_shift", ctypes.c_double), ("lowp_rnorm", ctypes.c_double), ("lowp_maxiter", ctypes.c_int)]
 
 
 class Result(ctypes.Structure):
     _fields_ = [("e_corr", ctypes.c_double), ("rnorm", ctypes.c_double), ("rmax", ctypes.c_double),
-                ("de", ctypes.c_double), ("iterations", ctypes.c_int), ("converged", ctypes.c_int)]
+                ("de", ctypes.c_double), ("iterations", ctypes.c_int), ("converged", ctypes.c_int),
+                ("lowp_iterations", ctypes.c_int)]
 
 
 def main(shapes):
@@ -42,6 +43,7 @@ def main(shapes):
     for shape in shapes:
         o, v, Q, diag = shape[:4]
         mode = shape[4] if len(shape) > 4 else 0
+        prec = shape[5] if len(shape) > 5 else 0
         n = o + v
         base = [0x200000000000]
 
@@ -53,7 +55,7 @@ def main(shapes):
         B = fake(8 * Q * n * n)
         F = fake(8 * (n if diag else n * n))
         h = vp()
-        rc = L.ascc_build_ints(B, F, diag, o, v, Q, 0, mode, None, ctypes.byref(h))
+        rc = L.ascc_build_ints(B, F, diag, o, v, Q, prec, mode, None, ctypes.byref(h))
         msgs = []
         if rc == 0:
             t1, t2, r1, r2, e, st = (fake(8 * o * v), fake(8 * o * o * v * v), fake(8 * o * v),
@@ -68,10 +70,11 @@ def main(shapes):
                 L.ascc_diis_free(d)
             if rc == 0:
                 res = Result()
-                rc = L.ascc_solve(h, ctypes.byref(Opts(1e-8, 0, 0, 3, 8, 1, 0.0)), t1, t2, ctypes.byref(res), None)
+                rc = L.ascc_solve(h, ctypes.byref(Opts(1e-8, 0, 0, 3, 8, 1, 0.0, 1e-3, 1)), t1, t2, ctypes.byref(res),
+                                  None)
             L.ascc_ints_free(h)
         if rc == 0:
-            print(f"OK {o} {v} {Q} mode {mode}", flush=True)
+            print(f"OK {o} {v} {Q} mode {mode} prec {prec}", flush=True)
         else:
             ok = False
             print(f"FAIL {o} {v} {Q} mode {mode} status {rc}: {L.ascc_last_error().decode()}", flush=True)

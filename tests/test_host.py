@@ -64,7 +64,9 @@ def test_workspace_bytes_scale_with_the_shape():
 
 @pytest.mark.parametrize("shapes", [["1,1,1,1", "2,3,8,1", "3,5,12,0", "5,20,60,1", "7,45,37,0"],
                                     ["1,1,1,1,1", "2,3,8,1,1", "3,5,12,0,1", "5,20,60,1,1", "7,45,37,0,1"],
-                                    ["20,180,600,1", "40,360,1200,1,1", "30,270,900,0,1", "20,180,600,1,1"]])
+                                    ["20,180,600,1", "40,360,1200,1,1", "30,270,900,0,1", "20,180,600,1,1"],
+                                    ["2,3,8,1,0,1", "5,20,60,1,1,2", "7,45,37,0,0,2", "20,180,600,1,1,2",
+                                     "40,360,1200,1,1,1"]])
 def test_every_launch_stays_in_bounds_dry_run(shapes):
     """The full build / residual / update / solve launch sequence, bounds-checked without a GPU."""
     r = subprocess.run([sys.executable, str(ROOT / "tests" / "dry_run_driver.py"), *shapes], capture_output=True,
