@@ -1,7 +1,8 @@
 """Throughput of one CCSD-form iteration (residual + energy + norms + Jacobi/DIIS update) on one MI355X.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--vvvv full|packed]
-                [--generator literal|converging] [--no-cpu-baseline]
+                [--precision fp64|fp32|bf16x3] [--generator literal|converging] [--no-compare]
+                [--no-cpu-baseline]
 
 A step is one pass of the whole iteration on the device: T1 dressing, every residual term,
 the energy and residual-norm reductions, the Jacobi update and DIIS (ascc_residual followed
@@ -12,9 +13,14 @@ timed region; the integral set (including the vvvv block) is built before it as 
 value = F_N6 / seconds-per-step in TFLOP/s, with the fixed algorithmic count
 F_N6(o,v) = 2[T(o)T(v)^2 + S(o)S(v)^2] + 4 o^4 v^2 + 10 o^3 v^3 (T(n) = n(n+1)/2, S(n) = n(n-1)/2).
 
-roofline: the particle-particle ladder contraction (phase pp_ladder), timed with HIP events on
-the stream it runs on during the timed region; achieved = its algorithmic flops per residual
-(2[T(o)T(v)^2 + S(o)S(v)^2]) / its mean duration, against the FP64 matrix peak.
+roofline: the particle-particle ladder contraction (phase pp_ladder, one batched launch), timed
+with HIP events on the stream it runs on during the timed region; achieved = its algorithmic
+flops per residual (2[T(o)T(v)^2 + S(o)S(v)^2]) / its mean duration, against the matrix peak of
+the arithmetic that carries it (FP64 78.6, FP32 157.3, split-BF16x3 2516.6/3 TFLOP/s).
+
+variants (FP64 runs): the same workload and step with the other vvvv storage and with the N^6
+contractions in FP32 and in split-BF16x3 (fewer steps each), as TFLOP/s on the same F_N6 count
+and speedup over the main run.
 
 cpu_baseline: the FP64 oracle (oracle/cs_ccsd.py, numpy) timed on the host for one residual
 evaluation of the same workload (rank 0 only), as F_N6 / seconds.
@@ -77,39 +83,18 @@ def cpu_baseline(B, eps, o, v):
             "sample": f"one residual + energy evaluation of the same workload ({dt:.1f} s, numpy FP64)"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="o20v180q600", choices=sorted(WORKLOADS))
-    ap.add_argument("--vvvv", default="full", choices=["full", "packed"])
-    ap.add_argument("--generator", default="literal", choices=["literal", "converging"])
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
-              file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-
-    import paper_2501_10515_amd as P
-
-    wl = WORKLOADS[args.workload]
-    o, v, Q, seed = wl["no"], wl["nv"], wl["naux"], wl["seed"]
-    sigma = converging_sigma(v, Q) if args.generator == "converging" else 0.05
-    B, eps = make_system(o, v, Q, seed, sigma=sigma)
+def run_throughput(P, torch, B, eps, o, v, Q, vvvv, precision, steps, warmup):
+    """Time `steps` iterations (residual + update) from T = 0 after `warmup` untimed ones."""
     dev = torch.device("cuda:0")
+    mode = P.ASCC_VVVV_FULL if vvvv == "full" else P.ASCC_VVVV_PACKED
+    prec = {"fp64": P.ASCC_PREC_FP64, "fp32": P.ASCC_PREC_FP32, "bf16x3": P.ASCC_PREC_BF16X3}[precision]
     dB = torch.from_numpy(B).to(dev)
     deps = torch.from_numpy(eps).to(dev)
-    mode = P.ASCC_VVVV_FULL if args.vvvv == "full" else P.ASCC_VVVV_PACKED
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ints = P.ascc_build_ints(dB, deps, o, vvvv_mode=mode)
+    ints = P.ascc_build_ints(dB, deps, o, precision=prec, vvvv_mode=mode)
     build_s = time.perf_counter() - t0
     del dB
-
     t1 = torch.zeros((o, v), dtype=torch.float64, device=dev)
     t2 = torch.zeros((o, o, v, v), dtype=torch.float64, device=dev)
     r1, r2 = torch.empty_like(t1), torch.empty_like(t2)
@@ -122,7 +107,7 @@ def main():
         P.ascc_residual(ints, t1, t2, r1, r2, e)
         P.ascc_update(ints, diis, t1, t2, r1, r2, e, stats)
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
     P.ascc_timing_read(ints)  # discard
@@ -131,21 +116,163 @@ def main():
     torch.cuda.synchronize()
     w0 = time.perf_counter()
     ev0.record(stream)
-    for _ in range(args.steps):
+    for _ in range(steps):
         step()
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
     P.ascc_timing_enable(ints, False)
     phases = P.ascc_timing_read(ints)
-    ms_step = ev0.elapsed_time(ev1) / args.steps
-    flops = f_n6(o, v)
-    value = flops / (ms_step * 1e-3) / 1e12
+    ms_step = ev0.elapsed_time(ev1) / steps
+    st = stats.cpu().numpy()
+    diis.close()
+    ints.close()
+    del t1, t2, r1, r2
+    torch.cuda.empty_cache()
+    return dict(ms_step=ms_step, wall=wall, build_s=build_s, phases=phases, steps=steps,
+                last={"E": float(st[0]), "rnorm": float(st[3]), "finite": bool(np.isfinite(st[3]))})
 
+
+def serve_requests(nreq: int):
+    """The request stream: Poisson arrivals (mean 20/s), no ~ U{4..24}, nv = 9 no, naux = 3(no+nv).
+
+    Arrival gaps come from default_rng(99).exponential(0.05); request k draws no and then its
+    inputs (convergence-variant width) from default_rng(100 + k).
+    """
+    import concurrent.futures as cf
+
+    gaps = np.random.default_rng(99).exponential(0.05, nreq)
+    arrivals = np.cumsum(gaps)
+
+    def one(k):
+        rng = np.random.default_rng(100 + k)
+        o = int(rng.integers(4, 25))
+        v, Q = 9 * o, 3 * (10 * o)
+        B, eps = make_system(o, v, Q, None, sigma=converging_sigma(v, Q), rng=rng)
+        return o, B, eps
+
+    with cf.ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        reqs = list(ex.map(one, range(nreq)))
+    return arrivals, reqs
+
+
+def run_serving(P, arrivals, reqs, precision: int, budget: int, max_active: int, tol_rnorm: float):
+    srv = P.Server(budget, max_active=max_active, precision=precision, vvvv_mode=P.ASCC_VVVV_PACKED,
+                   use_graphs=True, tol_rnorm=tol_rnorm, maxiter=150, lowp_rnorm=1e-5)
+    n = len(reqs)
+    ids = []
+    t0 = time.perf_counter()
+    nxt = 0
+    last_print = 0.0
+    while True:
+        now = time.perf_counter() - t0
+        while nxt < n and arrivals[nxt] <= now:
+            o, B, eps = reqs[nxt]
+            ids.append(srv.submit(B, eps, o, float(arrivals[nxt])))
+            nxt += 1
+        q, r, d = srv.step(now)
+        if now - last_print > 15.0:
+            print(f"serve: t={now:.1f}s submitted={nxt} queued={q} running={r} done={d}", file=sys.stderr, flush=True)
+            last_print = now
+        if nxt == n and d == n:
+            break
+        if now > 1800:
+            raise TimeoutError("serving did not finish in 30 min")
+        if r == 0 and nxt < n:
+            time.sleep(max(0.0, min(0.002, arrivals[nxt] - now)))
+    infos = [srv.info(i) for i in ids]
+    srv.close()
+    lat = np.array([x["t_done"] - x["t_submit"] for x in infos])
+    done = max(x["t_done"] for x in infos)
+    ok = sum(1 for x in infos if x["status"] == 0)
+    return dict(solves_per_s=n / (done - float(arrivals[0])), p50_s=float(np.percentile(lat, 50)),
+                p99_s=float(np.percentile(lat, 99)), converged=ok, n=n,
+                mean_iterations=float(np.mean([x["iterations"] for x in infos])),
+                mean_lowp_iterations=float(np.mean([x["lowp_iterations"] for x in infos])),
+                energies=[x["e_corr"] for x in infos])
+
+
+def serve_main(args):
+    import torch  # noqa: F401
+
+    import paper_2501_10515_amd as P
+
+    arrivals, reqs = serve_requests(args.requests)
+    budget = int(args.budget_gb * (1 << 30))
+    out = {"metric": "served solves/s (continuous batching, Poisson arrivals 20 req/s)", "unit": "solves/s",
+           "n_gpus": 1, "data": "synthetic", "dtype": "f64",
+           "config": {"workload": f"serve{args.requests}", "arrival_rate_per_s": 20, "no": "U{4..24}",
+                      "nv": "9 no", "naux": "3 (no + nv)", "seeds": f"100..{99 + args.requests}",
+                      "generator": "converging", "hbm_budget_gb": args.budget_gb, "max_active": args.max_active,
+                      "tol_rnorm": args.serve_tol, "vvvv": "packed"}}
+    res = {}
+    for name, pc in (("bf16x3_refined", P.ASCC_PREC_BF16X3), ("fp32_refined", P.ASCC_PREC_FP32),
+                     ("fp64", P.ASCC_PREC_FP64)):
+        if args.serve_precisions and name.split("_")[0] not in args.serve_precisions.split(","):
+            continue
+        r = run_serving(P, arrivals, reqs, pc, budget, args.max_active, args.serve_tol)
+        res[name] = r
+    base = res.get("fp64")
+    for name, r in res.items():
+        if base is not None and name != "fp64":
+            r["max_abs_dE_vs_fp64"] = float(max(abs(a - b) for a, b in zip(r["energies"], base["energies"])))
+    for r in res.values():
+        r.pop("energies")
+    main = res.get("bf16x3_refined") or next(iter(res.values()))
+    out["value"] = round(main["solves_per_s"], 4)
+    out["higher_is_better"] = True
+    out["vs_baseline"] = None
+    out["p50_s"] = round(main["p50_s"], 4)
+    out["p99_s"] = round(main["p99_s"], 4)
+    out["modes"] = res
+    print(json.dumps(out), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="o20v180q600", choices=sorted(WORKLOADS))
+    ap.add_argument("--vvvv", default="full", choices=["full", "packed"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--generator", default="literal", choices=["literal", "converging"])
+    ap.add_argument("--no-compare", action="store_true", help="skip the low-precision comparison runs")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve", action="store_true", help="run the request-serving workload instead")
+    ap.add_argument("--requests", type=int, default=256)
+    ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--max-active", type=int, default=32)
+    ap.add_argument("--serve-tol", type=float, default=1e-7)
+    ap.add_argument("--serve-precisions", default="", help="comma list of fp64,fp32,bf16x3 (default all)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    if args.serve:
+        serve_main(args)
+        return
+
+    import torch
+
+    import paper_2501_10515_amd as P
+
+    wl = WORKLOADS[args.workload]
+    o, v, Q, seed = wl["no"], wl["nv"], wl["naux"], wl["seed"]
+    sigma = converging_sigma(v, Q) if args.generator == "converging" else 0.05
+    B, eps = make_system(o, v, Q, seed, sigma=sigma)
+    flops = f_n6(o, v)
+
+    main_run = run_throughput(P, torch, B, eps, o, v, Q, args.vvvv, args.precision, args.steps, args.warmup)
+    ms_step = main_run["ms_step"]
+    value = flops / (ms_step * 1e-3) / 1e12
+    phases = main_run["phases"]
     lad_ms, lad_n = phases["pp_ladder"]
     lad_avg = lad_ms / max(lad_n, 1)
     achieved = ladder_flops(o, v) / (lad_avg * 1e-3) / 1e12
-    st = stats.cpu().numpy()
+    peak = {"fp64": FP64_MFMA_PEAK_TFLOPS, "fp32": 157.3, "bf16x3": 2516.6 / 3}[args.precision]
 
     out = {
         "metric": METRIC,
@@ -162,19 +289,37 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": args.workload, "no": o, "nv": v, "naux": Q, "seed": seed, "generator": args.generator,
-            "sigma": sigma, "vvvv": args.vvvv, "precision": "fp64",
+            "sigma": sigma, "vvvv": args.vvvv, "precision": args.precision,
             "step": "ascc_residual + ascc_update (one Jacobi/DIIS iteration)", "flops_per_step_F_N6": flops,
         },
         "roofline": {
-            "bound": "mfma", "kernel": "pp_ladder (gemm_f64_kernel)", "achieved": round(achieved, 3),
-            "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP64_MFMA_PEAK_TFLOPS, 4),
+            "bound": "mfma", "kernel": "pp_ladder (gemm_f64_kernel, one batched launch)" if args.precision == "fp64"
+            else "pp_ladder (gemm_lowp_kernel, one batched launch)",
+            "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
             "traffic": None, "launch_ms": round(lad_avg, 4), "algorithmic_flops_per_launch": ladder_flops(o, v),
         },
-        "phases_ms_per_step": {k: round(ms / max(args.steps, 1), 4) for k, (ms, n) in phases.items() if n},
-        "build_ints_s": round(build_s, 3),
-        "wall_s": round(wall, 3),
-        "last_stats": {"E": float(st[0]), "rnorm": float(st[3]), "finite": bool(np.isfinite(st[3]))},
+        "phases_ms_per_step": {k: round(ms / main_run["steps"], 4) for k, (ms, n) in phases.items() if n},
+        "build_ints_s": round(main_run["build_s"], 3),
+        "wall_s": round(main_run["wall"], 3),
+        "last_stats": main_run["last"],
     }
+    if not args.no_compare and args.precision == "fp64":
+        comp = {}
+        other = "packed" if args.vvvv == "full" else "full"
+        for vm, pr in ((other, "fp64"), (args.vvvv, "fp32"), (args.vvvv, "bf16x3"), ("packed", "bf16x3")):
+            key = f"{pr}_{vm}"
+            if key in comp:
+                continue
+            try:
+                r = run_throughput(P, torch, B, eps, o, v, Q, vm, pr, max(3, args.steps // 3), 2)
+                rl, rn = r["phases"]["pp_ladder"]
+                comp[key] = {"tflops": round(flops / (r["ms_step"] * 1e-3) / 1e12, 3),
+                             "ms_per_step": round(r["ms_step"], 4),
+                             "speedup_vs_main": round(ms_step / r["ms_step"], 3),
+                             "pp_ladder_ms": round(rl / max(rn, 1), 4)}
+            except Exception as exc:  # keep the primary measurement if a comparison fails
+                comp[key] = {"error": str(exc)[:200]}
+        out["variants"] = comp
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(B, eps, o, v)
     print(json.dumps(out), flush=True)

@@ -26,9 +26,11 @@
  *     of the large contractions only; energies, norms, the update and DIIS are always FP64.
  *   - Every function returns ASCC_OK (0) or a negative ASCC_E_* code and never throws, exits
  *     or aborts; ascc_last_error() returns a message for the last failure on this thread.
- *   - Device memory: ascc_build_ints and ascc_diis_create allocate the library's own device
- *     memory (integrals, work arrays, DIIS history; ascc_workspace_bytes reports the exact
- *     amount); ascc_*_free releases it.  No other call allocates device memory.
+ *   - Device memory: ascc_build_ints, ascc_batch_reserve and ascc_diis_create allocate the
+ *     library's own device memory (integrals, work arrays, DIIS history; ascc_workspace_bytes
+ *     reports the amount for the first and the last); ascc_*_free releases it.  ascc_solve
+ *     allocates its DIIS state and iteration arrays and frees them before returning.  No other
+ *     call allocates device memory.
  *   - A handle is not re-entrant: calls that share an ascc_ints (its work arrays) or an
  *     ascc_diis must be ordered on one stream.
  */
@@ -68,9 +70,10 @@ enum {
 typedef struct ascc_ints ascc_ints; /* integrals of one Hamiltonian + residual work arrays */
 typedef struct ascc_diis ascc_diis; /* DIIS history and solver state of one amplitude set  */
 
-/* Byte counts the library will allocate on the device: `ints_bytes` by ascc_build_ints
- * (integrals and residual work arrays) and `diis_bytes` by ascc_diis_create(m = diis_size).
- * Host-only, synchronous.  Errors: ASCC_E_SHAPE, ASCC_E_ARG. */
+/* Device bytes of an integral set (`ints_bytes`: integrals, residual work arrays and the largest
+ * build-time temporary, as carved by ascc_build_ints_ws) and of a DIIS state with m = diis_size
+ * (`diis_bytes`, as carved by ascc_diis_create_ws).  Host-only, synchronous.
+ * Errors: ASCC_E_SHAPE, ASCC_E_ARG. */
 int ascc_workspace_bytes(int no, int nv, int naux, int precision, int vvvv_mode, int diis_size,
                          size_t* ints_bytes, size_t* diis_bytes);
 
@@ -100,6 +103,15 @@ int ascc_build_ints(const double* d_B, const double* d_fock, int fock_is_diag, i
 int ascc_set_precision(ascc_ints* ints, int precision);
 int ascc_get_precision(const ascc_ints* ints);
 
+/* ascc_build_ints carving every device array, build-time temporaries included, from the
+ * caller's workspace d_workspace (256-byte aligned, ws_bytes >= the ints_bytes that
+ * ascc_workspace_bytes reports) instead of allocating: for callers that admit work by memory
+ * footprint or must not call the allocator.  The workspace must outlive the handle.
+ * Errors: as ascc_build_ints, ASCC_E_NOMEM if ws_bytes is too small. */
+int ascc_build_ints_ws(const double* d_B, const double* d_fock, int fock_is_diag, int no, int nv, int naux,
+                       int precision, int vvvv_mode, void* d_workspace, size_t ws_bytes, void* stream,
+                       ascc_ints** out);
+
 /* Residual and energy at the given amplitudes (Eqs. (eqn:energy), (eqn:amp)).
  *   d_t1 [no][nv], d_t2 [no][no][nv][nv] with t2[i][j][a][b] == t2[j][i][b][a] (read only)
  *   d_r1 [no][nv], d_r2 [no][no][nv][nv]  (written; R2 has the same pair symmetry)
@@ -108,11 +120,32 @@ int ascc_get_precision(const ascc_ints* ints);
 int ascc_residual(ascc_ints* ints, const double* d_t1, const double* d_t2, double* d_r1, double* d_r2,
                   double* d_e, void* stream);
 
+/* Capacity for batched residuals of up to max_states amplitude sets on this integral set:
+ * allocates the stacked ladder operands and one ladder result per state (device memory;
+ * freed by ascc_ints_free; a larger later request reallocates).  Synchronous.
+ * Errors: ASCC_E_ARG, ASCC_E_NOMEM. */
+int ascc_batch_reserve(ascc_ints* ints, int max_states);
+
+/* Residuals and energies of nstates amplitude sets that share this integral set (several
+ * states of one Hamiltonian).  d_t1[k], d_t2[k], d_r1[k], d_r2[k] are host arrays of device
+ * pointers with the shapes of ascc_residual; d_e is a device array [nstates].  The particle-
+ * particle ladders of all states are one launch over the shared vvvv block (its tiles are
+ * streamed once for the batch); every other term runs per state.  Each state's result is the
+ * one ascc_residual gives for it alone (the same arithmetic in the same order).  Asynchronous.
+ * Errors: ASCC_E_ARG, ASCC_E_STATE (nstates above the reserved capacity), ASCC_E_HIP. */
+int ascc_residual_batch(ascc_ints* ints, int nstates, const double* const* d_t1, const double* const* d_t2,
+                        double* const* d_r1, double* const* d_r2, double* d_e, void* stream);
+
 /* DIIS state for one amplitude set of `ints`' shape: up to `max_vectors` (1..16) stored pairs
  * of (amplitudes after the Jacobi step, the step itself); pairs are stored from 0-based
  * update call `start` on.  Allocates device memory; synchronous.
  * Errors: ASCC_E_ARG, ASCC_E_NOMEM, ASCC_E_HIP. */
 int ascc_diis_create(const ascc_ints* ints, int max_vectors, int start, ascc_diis** out);
+
+/* ascc_diis_create carving from a caller workspace (256-byte aligned, >= the diis_bytes of
+ * ascc_workspace_bytes for the same max_vectors); no allocation.  Errors: as ascc_diis_create. */
+int ascc_diis_create_ws(const ascc_ints* ints, int max_vectors, int start, void* d_workspace, size_t ws_bytes,
+                        ascc_diis** out);
 
 /* Return the DIIS state to empty (no stored pairs, no previous energy).  Asynchronous. */
 int ascc_diis_reset(ascc_diis* diis, void* stream);
@@ -165,7 +198,52 @@ typedef struct ascc_result {
 int ascc_solve(ascc_ints* ints, const ascc_opts* opts, double* d_t1, double* d_t2, ascc_result* res,
                void* stream);
 
-void ascc_ints_free(ascc_ints* ints); /* NULL is a no-op; synchronises the device first */
+/* ---- Request server: many independent solves on one GPU --------------------------------
+ * A request is one Hamiltonian (DF tensor + orbital energies, diagonal Fock) solved from T = 0
+ * with opts.solve.  The server owns one device slab of hbm_budget bytes (allocated at creation)
+ * and carves each admitted request's complete working set from it, admitting queued requests in
+ * arrival order whenever the head of the queue fits and fewer than max_active are running.
+ * Every running request has its own stream; one iteration (ascc_residual + ascc_update) is
+ * captured per precision into a hipGraph (use_graphs = 1) and replayed, and each
+ * ascc_server_step launches one iteration for every running request whose previous iteration
+ * has finished, so requests overlap on the device and join or leave between iterations.  With a
+ * low `precision` the bulk iterations run in it and the last ones in FP64 (opts.solve.lowp_*).
+ * All calls are host-side and never wait for the device except ascc_server_free (and the
+ * synchronous integral build of a request during the step that admits it). */
+typedef struct ascc_server ascc_server;
+
+typedef struct ascc_server_opts {
+  size_t hbm_budget; /* bytes of device memory for all requests together           */
+  int max_active;    /* requests running at once (one stream each)                  */
+  int precision;     /* ASCC_PREC_*: arithmetic of the bulk iterations             */
+  int vvvv_mode;     /* ASCC_VVVV_FULL or ASCC_VVVV_PACKED                         */
+  int use_graphs;    /* 1: replay a captured hipGraph per iteration                */
+  ascc_opts solve;   /* tolerances, maxiter, DIIS, FP64-refinement switch          */
+} ascc_server_opts;
+
+typedef struct ascc_request_info {
+  int id, no, nv, naux;
+  int status; /* 1 queued, 2 running, ASCC_OK converged, or a negative ASCC_E_* code */
+  int iterations, lowp_iterations;
+  double e_corr, rnorm, rmax; /* of the last completed iteration                     */
+  double t_submit, t_admit, t_done; /* caller clock values (ascc_server_submit/step) */
+  size_t bytes;                     /* HBM footprint                                  */
+} ascc_request_info;
+
+/* Errors: ASCC_E_ARG, ASCC_E_NOMEM (slab allocation). */
+int ascc_server_create(const ascc_server_opts* opts, ascc_server** out);
+/* Queue a request; h_B [naux][n][n] and h_eps [n] are host arrays, copied before returning.
+ * Errors: ASCC_E_ARG, ASCC_E_SHAPE, ASCC_E_NOMEM (larger than the whole budget). */
+int ascc_server_submit(ascc_server* srv, const double* h_B, const double* h_eps, int no, int nv, int naux,
+                       double t_submit, int* id);
+/* Retire finished requests, admit queued ones, launch the next iterations; `now` is the caller's
+ * clock, recorded as admission / completion times.  Errors: ASCC_E_ARG, ASCC_E_HIP. */
+int ascc_server_step(ascc_server* srv, double now, int* n_queued, int* n_running, int* n_done);
+int ascc_server_info(const ascc_server* srv, int id, ascc_request_info* info);
+void ascc_server_free(ascc_server* srv); /* waits for the device, then releases everything */
+
+void ascc_ints_free(ascc_ints* ints); /* NULL is a no-op; waits for the device first unless the
+                                         handle was carved from a caller workspace */
 void ascc_diis_free(ascc_diis* diis); /* NULL is a no-op; synchronises the device first */
 
 /* Per-phase timing of ascc_residual / ascc_update on a handle, with HIP events recorded on the

@@ -25,8 +25,12 @@ from ._lib import (  # noqa: F401
     AsccError,
     Diis,
     Ints,
+    Server,
+    ascc_batch_reserve,
     ascc_build_ints,
+    ascc_build_ints_ws,
     ascc_diis_create,
+    ascc_diis_create_ws,
     ascc_diis_reset,
     ascc_last_error,
     ascc_phase_count,
@@ -35,6 +39,7 @@ from ._lib import (  # noqa: F401
     ascc_timing_read,
     ascc_get_precision,
     ascc_residual,
+    ascc_residual_batch,
     ascc_set_precision,
     ascc_solve,
     ascc_update,

@@ -42,6 +42,19 @@ class Opts(ctypes.Structure):
                 ("level_shift", ctypes.c_double), ("lowp_rnorm", ctypes.c_double), ("lowp_maxiter", ctypes.c_int)]
 
 
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_active", ctypes.c_int), ("precision", ctypes.c_int),
+                ("vvvv_mode", ctypes.c_int), ("use_graphs", ctypes.c_int), ("solve", Opts)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int), ("no", ctypes.c_int), ("nv", ctypes.c_int), ("naux", ctypes.c_int),
+                ("status", ctypes.c_int), ("iterations", ctypes.c_int), ("lowp_iterations", ctypes.c_int),
+                ("e_corr", ctypes.c_double), ("rnorm", ctypes.c_double), ("rmax", ctypes.c_double),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("bytes", ctypes.c_size_t)]
+
+
 class Result(ctypes.Structure):
     _fields_ = [("e_corr", ctypes.c_double), ("rnorm", ctypes.c_double), ("rmax", ctypes.c_double),
                 ("de", ctypes.c_double), ("iterations", ctypes.c_int), ("converged", ctypes.c_int),
@@ -51,7 +64,9 @@ class Result(ctypes.Structure):
 EXPORTS = ("ascc_workspace_bytes", "ascc_build_ints", "ascc_residual", "ascc_diis_create", "ascc_diis_reset",
            "ascc_update", "ascc_solve", "ascc_ints_free", "ascc_diis_free", "ascc_ints_shape", "ascc_last_error",
            "ascc_phase_count", "ascc_phase_name", "ascc_timing_enable", "ascc_timing_read", "ascc_set_precision",
-           "ascc_get_precision")
+           "ascc_get_precision", "ascc_batch_reserve", "ascc_residual_batch", "ascc_build_ints_ws",
+           "ascc_diis_create_ws", "ascc_server_create", "ascc_server_submit", "ascc_server_step",
+           "ascc_server_info", "ascc_server_free")
 
 
 def load_library():
@@ -71,6 +86,12 @@ def load_library():
     L.ascc_diis_reset.argtypes = [vp, vp]
     L.ascc_update.argtypes = [vp, vp, vp, vp, vp, vp, vp, c_double, vp, vp]
     L.ascc_solve.argtypes = [vp, ctypes.POINTER(Opts), vp, vp, ctypes.POINTER(Result), vp]
+    L.ascc_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]
+    L.ascc_server_submit.argtypes = [vp, vp, vp, c_int, c_int, c_int, c_double, ctypes.POINTER(c_int)]
+    L.ascc_server_step.argtypes = [vp, c_double, ctypes.POINTER(c_int), ctypes.POINTER(c_int), ctypes.POINTER(c_int)]
+    L.ascc_server_info.argtypes = [vp, c_int, ctypes.POINTER(RequestInfo)]
+    L.ascc_server_free.argtypes = [vp]
+    L.ascc_server_free.restype = None
     L.ascc_ints_free.argtypes = [vp]
     L.ascc_ints_free.restype = None
     L.ascc_diis_free.argtypes = [vp]
@@ -83,10 +104,16 @@ def load_library():
     L.ascc_phase_name.restype = ctypes.c_char_p
     L.ascc_timing_enable.argtypes = [vp, c_int]
     L.ascc_set_precision.argtypes = [vp, c_int]
+    L.ascc_build_ints_ws.argtypes = [vp, vp, c_int, c_int, c_int, c_int, c_int, c_int, vp, ctypes.c_size_t, vp,
+                                     ctypes.POINTER(vp)]
+    L.ascc_diis_create_ws.argtypes = [vp, c_int, c_int, vp, ctypes.c_size_t, ctypes.POINTER(vp)]
+    L.ascc_batch_reserve.argtypes = [vp, c_int]
+    L.ascc_residual_batch.argtypes = [vp, c_int, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                      ctypes.POINTER(vp), vp, vp]
     L.ascc_get_precision.argtypes = [vp]
     L.ascc_timing_read.argtypes = [vp, ctypes.POINTER(c_double), ctypes.POINTER(c_int), c_int]
     for name in EXPORTS:
-        if name not in ("ascc_ints_free", "ascc_diis_free", "ascc_last_error", "ascc_phase_name"):
+        if name not in ("ascc_ints_free", "ascc_diis_free", "ascc_last_error", "ascc_phase_name", "ascc_server_free"):
             getattr(L, name).restype = c_int
     _LIB = L
     return L
@@ -131,9 +158,10 @@ def ascc_workspace_bytes(no: int, nv: int, naux: int, precision: int = ASCC_PREC
 class Ints:
     """Owner of an ascc_ints handle (frees it on close / garbage collection)."""
 
-    def __init__(self, handle, no, nv, naux):
+    def __init__(self, handle, no, nv, naux, workspace=None):
         self.handle = handle
         self.no, self.nv, self.naux = no, nv, naux
+        self.workspace = workspace  # keeps a caller workspace alive as long as the handle
 
     def close(self):
         if self.handle:
@@ -148,8 +176,9 @@ class Ints:
 
 
 class Diis:
-    def __init__(self, handle):
+    def __init__(self, handle, workspace=None):
         self.handle = handle
+        self.workspace = workspace  # keeps a caller workspace alive as long as the handle
 
     def close(self):
         if self.handle:
@@ -246,3 +275,102 @@ def ascc_set_precision(ints: Ints, precision: int):
 
 def ascc_get_precision(ints: Ints) -> int:
     return load_library().ascc_get_precision(ints.handle)
+
+
+def ascc_batch_reserve(ints: Ints, max_states: int):
+    _check(load_library().ascc_batch_reserve(ints.handle, max_states))
+
+
+def ascc_residual_batch(ints: Ints, t1s, t2s, r1s, r2s, e, stream=None):
+    """Residuals of len(t1s) amplitude sets on one integral set; e is a device array [nstates]."""
+    o, v = ints.no, ints.nv
+    n = len(t1s)
+    if not (len(t2s) == len(r1s) == len(r2s) == n):
+        raise ValueError("t1s, t2s, r1s, r2s must have the same length")
+    arr = ctypes.c_void_p * n
+    p1 = arr(*[_dev(t, "t1", (o, v)) for t in t1s])
+    p2 = arr(*[_dev(t, "t2", (o, o, v, v)) for t in t2s])
+    q1 = arr(*[_dev(t, "r1", (o, v)) for t in r1s])
+    q2 = arr(*[_dev(t, "r2", (o, o, v, v)) for t in r2s])
+    _check(load_library().ascc_residual_batch(ints.handle, n, p1, p2, q1, q2, _dev(e, "e", (n,)), _stream(stream)))
+
+
+def _workspace_ptr(ws: torch.Tensor, nbytes: int) -> ctypes.c_void_p:
+    if ws.device.type != "cuda" or not ws.is_contiguous():
+        raise ValueError("workspace must be a contiguous GPU tensor")
+    if ws.numel() * ws.element_size() < nbytes:
+        raise ValueError("workspace is smaller than required")
+    if ws.data_ptr() % 256:
+        raise ValueError("workspace must be 256-byte aligned")
+    return ctypes.c_void_p(ws.data_ptr())
+
+
+def ascc_build_ints_ws(B: torch.Tensor, fock: torch.Tensor, no: int, workspace: torch.Tensor,
+                       precision: int = ASCC_PREC_FP64, vvvv_mode: int = ASCC_VVVV_FULL, stream=None) -> Ints:
+    naux, n, _ = B.shape
+    nv = n - no
+    if fock.dim() == 1:
+        pf, diag = _dev(fock, "fock", (n,)), 1
+    else:
+        pf, diag = _dev(fock, "fock", (n, n)), 0
+    nbytes = workspace.numel() * workspace.element_size()
+    h = ctypes.c_void_p()
+    _check(load_library().ascc_build_ints_ws(_dev(B, "B"), pf, diag, no, nv, naux, precision, vvvv_mode,
+                                             _workspace_ptr(workspace, 0), nbytes, _stream(stream), ctypes.byref(h)))
+    return Ints(h, no, nv, naux, workspace)
+
+
+def ascc_diis_create_ws(ints: Ints, workspace: torch.Tensor, max_vectors: int = 8, start: int = 1) -> Diis:
+    nbytes = workspace.numel() * workspace.element_size()
+    h = ctypes.c_void_p()
+    _check(load_library().ascc_diis_create_ws(ints.handle, max_vectors, start, _workspace_ptr(workspace, 0), nbytes,
+                                              ctypes.byref(h)))
+    return Diis(h, workspace)
+
+
+class Server:
+    """Request server (ascc_server_*): submit host-side DF tensors, step the loop, read results."""
+
+    def __init__(self, hbm_budget: int, max_active: int = 16, precision: int = ASCC_PREC_FP64,
+                 vvvv_mode: int = ASCC_VVVV_PACKED, use_graphs: bool = True, tol_rnorm=1e-8, tol_rmax=0.0,
+                 tol_de=0.0, maxiter=100, diis_size=8, diis_start=1, lowp_rnorm=0.0, lowp_maxiter=0):
+        opts = ServerOpts(hbm_budget, max_active, precision, vvvv_mode, 1 if use_graphs else 0,
+                          Opts(tol_rnorm, tol_rmax, tol_de, maxiter, diis_size, diis_start, 0.0, lowp_rnorm,
+                               lowp_maxiter))
+        h = ctypes.c_void_p()
+        _check(load_library().ascc_server_create(ctypes.byref(opts), ctypes.byref(h)))
+        self.handle = h
+
+    def submit(self, B, eps, no: int, t_submit: float) -> int:
+        import numpy as np
+
+        B = np.ascontiguousarray(B, dtype=np.float64)
+        eps = np.ascontiguousarray(eps, dtype=np.float64)
+        naux, n, _ = B.shape
+        rid = ctypes.c_int()
+        _check(load_library().ascc_server_submit(self.handle, B.ctypes.data_as(ctypes.c_void_p),
+                                                 eps.ctypes.data_as(ctypes.c_void_p), no, n - no, naux,
+                                                 ctypes.c_double(t_submit), ctypes.byref(rid)))
+        return rid.value
+
+    def step(self, now: float):
+        q, r, d = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(load_library().ascc_server_step(self.handle, ctypes.c_double(now), ctypes.byref(q), ctypes.byref(r),
+                                               ctypes.byref(d)))
+        return q.value, r.value, d.value
+
+    def info(self, rid: int) -> dict:
+        x = RequestInfo()
+        _check(load_library().ascc_server_info(self.handle, rid, ctypes.byref(x)))
+        return {k: getattr(x, k) for k, _ in RequestInfo._fields_}
+
+    def close(self):
+        if self.handle:
+            load_library().ascc_server_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

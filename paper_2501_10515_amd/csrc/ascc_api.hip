@@ -123,6 +123,30 @@ struct ScopedBuffers {
   }
 };
 
+constexpr size_t kAlign = 256;
+
+// Where a handle's device arrays come from: carved from a caller workspace (base != nullptr,
+// no runtime allocation at all) or allocated with hipMalloc.
+struct Pool {
+  char* base = nullptr;
+  size_t size = 0, off = 0;
+  std::vector<void*> owned;   // hipMalloc'd blocks
+  std::vector<void*> carved;  // carved arrays (for the bounds checker)
+  size_t total = 0;
+};
+
+// A scratch pool for build-time temporaries: the untouched rest of a carved workspace, or
+// separate hipMalloc blocks.  Released with free_all once the temporaries are no longer used.
+Pool sub_pool(const Pool& P) {
+  Pool t;
+  if (P.base) {
+    const size_t o = (P.off + kAlign - 1) / kAlign * kAlign;
+    t.base = P.base + std::min(o, P.size);
+    t.size = P.size - std::min(o, P.size);
+  }
+  return t;
+}
+
 }  // namespace ascc
 
 using namespace ascc;
@@ -130,8 +154,7 @@ using namespace ascc;
 struct ascc_ints {
   int no, nv, naux, n, precision, vvvv_mode, device;
   long ov, oo, vv, ovov, oovv;
-  std::vector<void*> allocs;
-  size_t bytes = 0;
+  Pool pool;
   // constant integrals
   double* B;      // [Q][n][n]
   double* h;      // [n][n] core Hamiltonian
@@ -162,6 +185,11 @@ struct ascc_ints {
   float *Vf, *GwzTf, *KLf;       // constant: vvvv, [ov+o^2][v^2] transposed (kc|bd)|(kc|ld), K|L
   float *Tpf, *t2f, *TUf, *XZf;  // per residual: ladder rows, t2 rows, Tx|U, Xc|Zd
   int cur_prec = 0;              // arithmetic of the large contractions in the next residual
+  // multi-state batches (ascc_batch_reserve): stacked ladder operands and per-state RL
+  int max_states = 0;
+  double *Tp_all = nullptr, *Rp_all = nullptr, *RL_all = nullptr;
+  float* Tpf_all = nullptr;
+  Pool batch;
   // optional per-phase timing with HIP events (ascc_timing_enable)
   bool timing = false;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;  // (phase, (start, end))
@@ -173,7 +201,7 @@ struct ascc_diis {
   long len;
   double *hist_t, *hist_e, *partial;
   DiisState* st;
-  std::vector<void*> allocs;
+  Pool pool;
 };
 
 namespace {
@@ -232,7 +260,6 @@ uintptr_t fake_alloc(size_t bytes) {
   return p;
 }
 
-
 constexpr long kSplitKElems = 1L << 22;  // 32 MiB of split-K partials
 
 // Every device array of an integral set with its element count, in allocation order; the
@@ -282,30 +309,61 @@ long build_temp_elems(long o, long v, int mode, long* chunk_a) {
   return (mode == ASCC_VVVV_FULL) ? wtmp : std::max(wtmp, ac * vvv);
 }
 
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Bytes a DIIS state carves from a workspace.
+size_t diis_footprint(long o, long v, int m) {
+  const long len = o * v + o * o * v * v;
+  size_t off = 0;
+  off = align_up(off) + sizeof(double) * m * len;
+  off = align_up(off) + sizeof(double) * m * len;
+  off = align_up(off) + sizeof(double) * update_partial_blocks() * (3 + kMaxDiis);
+  off = align_up(off) + sizeof(DiisState);
+  return align_up(off);
+}
+
 template <class T>
-int dalloc(std::vector<void*>& allocs, size_t& total, T** p, size_t count) {
-  void* q = nullptr;
+int dalloc(Pool& P, T** out, size_t count) {
   const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+  if (P.base) {
+    const size_t o = (P.off + kAlign - 1) / kAlign * kAlign;
+    if (o + bytes > P.size) {
+      set_error("workspace too small: needs at least " + std::to_string(o + bytes) + " bytes");
+      return ASCC_E_NOMEM;
+    }
+    *out = reinterpret_cast<T*>(P.base + o);
+    P.off = o + bytes;
+    P.total += bytes;
+    P.carved.push_back(*out);
+    register_buffer(*out, bytes);
+    return ASCC_OK;
+  }
+  void* q = nullptr;
   hipError_t e = dry_run() ? (q = (void*)fake_alloc(bytes), hipSuccess) : hipMalloc(&q, bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     set_error("hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
     return ASCC_E_NOMEM;
   }
-  allocs.push_back(q);
-  total += bytes;
-  *p = static_cast<T*>(q);
+  P.owned.push_back(q);
+  P.total += bytes;
+  *out = static_cast<T*>(q);
   register_buffer(q, bytes);
   return ASCC_OK;
 }
 
-void free_all(std::vector<void*>& allocs) {
-  if (!dry_run()) (void)hipDeviceSynchronize();
-  for (void* p : allocs) {
+void free_all(Pool& P) {
+  if (!P.owned.empty() && !dry_run()) (void)hipDeviceSynchronize();
+  for (void* p : P.owned) {
     unregister_buffer(p);
     if (!dry_run()) (void)hipFree(p);
   }
-  allocs.clear();
+  for (void* p : P.carved) unregister_buffer(p);
+  P.owned.clear();
+  P.carved.clear();
+  P.off = 0;
+  P.total = 0;
 }
 
 inline Perm4In pin(const double* p, long s0, long s1, long s2, long s3, double coef) {
@@ -445,42 +503,67 @@ GemmLP lp_nt(const ascc_ints* I, long M, long N, long K, int nb, const float* A,
   return g;
 }
 
-// Particle-particle ladder RL[i][j][a][b] = sum_cd t_ij^cd (ac|bd), computed for pairs i <= j
-// only (RL_ji^ba = RL_ij^ab).  FULL: against the full (ac|bd) matrix.  PACKED: against its
-// (ab)-symmetric and antisymmetric halves, R+- = t+- V+-, one batched launch.
-int pp_ladder(ascc_ints* I, const double* t2, hipStream_t s) {
+// Particle-particle ladder RL_s[i][j][a][b] = sum_cd (t_s)_ij^cd (ac|bd) for S states in one
+// launch, computed for pairs i <= j only (RL_ji^ba = RL_ij^ab).  The S states' ladder rows are
+// stacked, so the vvvv operand is streamed once for all of them.  FULL: against the full (ac|bd)
+// matrix.  PACKED: against its (ab)-symmetric and antisymmetric halves, R+- = t+- V+-, both
+// halves in the same batched launch.  Tp/Rp hold [2][S*T(o)][T(v)] (PACKED) or [S*T(o)][v^2].
+int pp_ladder_states(ascc_ints* I, int S, const double* const* t2s, double* const* RLs, double* Tp, double* Rp,
+                     float* Tpf, hipStream_t s) {
   const int o = I->no, v = I->nv;
   const long vv = I->vv, To = (long)o * (o + 1) / 2, Tv = (long)v * (v + 1) / 2;
+  const long M = S * To;
   const bool lowp = I->cur_prec != ASCC_PREC_FP64;
   if (I->vvvv_mode == ASCC_VVVV_FULL) {
-    HIPCHK(pack_pairs(I->Tp, t2, o, vv, s));
+    for (int k = 0; k < S; ++k) HIPCHK(pack_pairs(Tp + k * To * vv, t2s[k], o, vv, s));
     if (lowp) {
-      HIPCHK(cvt_f32(I->Tpf, I->Tp, To * vv, s));
-      HIPCHK(gemm_lowp(lp_nt(I, To, vv, vv, 1, I->Tpf, vv, 0, I->Vf, vv, 0, I->Rp, vv, 0), s));
+      HIPCHK(cvt_f32(Tpf, Tp, M * vv, s));
+      HIPCHK(gemm_lowp(lp_nt(I, M, vv, vv, 1, Tpf, vv, 0, I->Vf, vv, 0, Rp, vv, 0), s));
     } else {
-      HIPCHK(mm(I, gemm_rm(To, vv, vv, 1.0, I->Tp, vv, false, I->V, vv, true, 0.0, I->Rp, vv), s));
+      HIPCHK(gemm_f64(gemm_rm(M, vv, vv, 1.0, Tp, vv, false, I->V, vv, true, 0.0, Rp, vv), s));
     }
-    HIPCHK(unpack_pairs(I->RL, I->Rp, o, v, s));
+    for (int k = 0; k < S; ++k) HIPCHK(unpack_pairs(RLs[k], Rp + k * To * vv, o, v, s));
   } else {
-    HIPCHK(pack_tpm(I->Tp, t2, o, v, s));
+    for (int k = 0; k < S; ++k) HIPCHK(pack_tpm(Tp + k * To * Tv, Tp + (M + k * To) * Tv, t2s[k], o, v, s));
     if (lowp) {
-      HIPCHK(cvt_f32(I->Tpf, I->Tp, 2 * To * Tv, s));
-      HIPCHK(gemm_lowp(lp_nt(I, To, Tv, Tv, 2, I->Tpf, Tv, To * Tv, I->Vf, Tv, Tv * Tv, I->Rp, Tv, To * Tv), s));
+      HIPCHK(cvt_f32(Tpf, Tp, 2 * M * Tv, s));
+      HIPCHK(gemm_lowp(lp_nt(I, M, Tv, Tv, 2, Tpf, Tv, M * Tv, I->Vf, Tv, Tv * Tv, Rp, Tv, M * Tv), s));
     } else {
-      Gemm g = gemm_rm(To, Tv, Tv, 1.0, I->Tp, Tv, false, I->V, Tv, true, 0.0, I->Rp, Tv);
-      g.sa2 = To * Tv;
+      Gemm g = gemm_rm(M, Tv, Tv, 1.0, Tp, Tv, false, I->V, Tv, true, 0.0, Rp, Tv);
+      g.sa2 = M * Tv;
       g.sb2 = Tv * Tv;
-      g.sc2 = To * Tv;
+      g.sc2 = M * Tv;
       g.nb2 = 2;
-      HIPCHK(mm(I, g, s));
+      HIPCHK(gemm_f64(g, s));  // no split-K: each row is summed the same way for any batch size
     }
-    HIPCHK(unpack_rpm(I->RL, I->Rp, o, v, s));
+    for (int k = 0; k < S; ++k) HIPCHK(unpack_rpm(RLs[k], Rp + k * To * Tv, Rp + (M + k * To) * Tv, o, v, s));
   }
   return ASCC_OK;
 }
 
-int residual_fp64(ascc_ints* I, const double* t1, const double* t2, double* r1, double* r2, double* e,
-                  hipStream_t s) {
+int pp_ladder(ascc_ints* I, const double* t2, hipStream_t s) {
+  double* RL = I->RL;
+  return pp_ladder_states(I, 1, &t2, &RL, I->Tp, I->Rp, I->Tpf, s);
+}
+
+// One state's residual.  RLx == nullptr: the ladder is computed here into I->RL; otherwise RLx
+// already holds this state's particle-particle ladder (from a batched launch).
+size_t ints_footprint(long o, long v, long Q, int precision, int mode) {
+  size_t off = 0;
+  for (const auto& item : ints_plan(o, v, Q, mode))
+    off = align_up(off) + std::max<size_t>((size_t)item.second, 1) * sizeof(double);
+  if (precision != ASCC_PREC_FP64)
+    for (const auto& item : lowp_plan(o, v, mode))
+      off = align_up(off) + std::max<size_t>((size_t)item.second, 1) * sizeof(float);
+  const long vv = v * v, wzl = o * v + o * o;
+  long temp = build_temp_elems(o, v, mode, nullptr);
+  if (precision != ASCC_PREC_FP64) temp = std::max(temp, wzl * vv);
+  return align_up(off) + sizeof(double) * (size_t)std::max<long>(temp, 1);
+}
+
+int residual_core(ascc_ints* I, const double* t1, const double* t2, double* r1, double* r2, double* e,
+                  double* RLx, hipStream_t s) {
+  double* RL = RLx ? RLx : I->RL;
   const int o = I->no, v = I->nv, Q = I->naux;
   const long n = I->n, nn = n * n, ov = I->ov, oo = I->oo, vv = I->vv, ovov = I->ovov;
   const long wzl = ov + oo;  // row length of WZ and Gwz
@@ -555,10 +638,10 @@ int residual_fp64(ascc_ints* I, const double* t1, const double* t2, double* r1, 
   phase_end(I, s);
   // --- particle-particle ladder over the undressed (ac|bd), plus the hole-hole ladder
   phase_begin(I, PH_LADDER, s);
-  if ((rc = pp_ladder(I, t2, s))) return rc;
+  if (!RLx && (rc = pp_ladder(I, t2, s))) return rc;
   phase_end(I, s);
   phase_begin(I, PH_HH, s);
-  HIPCHK(mm(I, gemm_rm(oo, vv, oo, 1.0, I->chi, oo, false, t2, vv, false, 1.0, I->RL, vv), s));
+  HIPCHK(mm(I, gemm_rm(oo, vv, oo, 1.0, I->chi, oo, false, t2, vv, false, 1.0, RL, vv), s));
   phase_end(I, s);
 
   // --- rings: Y1 = Tx K, Y2 = U L (batched pair)
@@ -740,12 +823,17 @@ int residual_fp64(ascc_ints* I, const double* t1, const double* t2, double* r1, 
   phase_end(I, s);
   // --- doubles assembly and energy
   phase_begin(I, PH_ASSEMBLE, s);
-  HIPCHK(assemble_r2(r2, I->G1, I->RL, I->EM, I->P, I->P + ovov, o, v, s));
+  HIPCHK(assemble_r2(r2, I->G1, RL, I->EM, I->P, I->P + ovov, o, v, s));
   phase_end(I, s);
   phase_begin(I, PH_ENERGY, s);
   HIPCHK(energy(e, I->partial, t1, t2, I->Lijab, I->fov, o, v, s));
   phase_end(I, s);
   return ASCC_OK;
+}
+
+int residual_fp64(ascc_ints* I, const double* t1, const double* t2, double* r1, double* r2, double* e,
+                  hipStream_t s) {
+  return residual_core(I, t1, t2, r1, r2, e, nullptr, s);
 }
 
 int build_constants(ascc_ints* I, const double* Bsrc, const double* fock, int fock_is_diag, hipStream_t s) {
@@ -804,9 +892,8 @@ int build_constants(ascc_ints* I, const double* Bsrc, const double* fock, int fo
   // Gwz: (kc|bd) at [c][d][k*v + b] from a temporary [(k,c)][(b,d)] product
   {
     double* tmp = nullptr;
-    std::vector<void*> tmp_alloc;
-    size_t tmp_bytes = 0;
-    int rc2 = dalloc(tmp_alloc, tmp_bytes, &tmp, (size_t)ov * vv);
+    Pool tmp_alloc = sub_pool(I->pool);
+    int rc2 = dalloc(tmp_alloc, &tmp, (size_t)ov * vv);
     if (rc2) return rc2;
     hipError_t e = mm(I, gemm_rm(ov, vv, Q, 1.0, I->Bov, ov, true, I->Bvv, vv, false, 0.0, tmp, vv), s);
     if (e == hipSuccess) {
@@ -858,9 +945,8 @@ int build_constants(ascc_ints* I, const double* Bsrc, const double* fock, int fo
     long ac = 1;
     const long elems = build_temp_elems(o, v, I->vvvv_mode, &ac);
     double* tmp = nullptr;
-    std::vector<void*> tmp_alloc;
-    size_t tmp_bytes = 0;
-    int rc3 = dalloc(tmp_alloc, tmp_bytes, &tmp, (size_t)elems);
+    Pool tmp_alloc = sub_pool(I->pool);
+    int rc3 = dalloc(tmp_alloc, &tmp, (size_t)elems);
     if (rc3) return rc3;
     hipError_t e = hipSuccess;
     for (int a0 = 0; a0 < v && e == hipSuccess; a0 += (int)ac) {
@@ -886,9 +972,8 @@ int build_lowp_shadows(ascc_ints* I, hipStream_t s) {
   HIPCHK(cvt_f32(I->Vf, I->V, nV, s));
   HIPCHK(cvt_f32(I->KLf, I->KL, 2 * I->ovov, s));
   double* tmp = nullptr;
-  std::vector<void*> tmp_alloc;
-  size_t tmp_bytes = 0;
-  int rc = dalloc(tmp_alloc, tmp_bytes, &tmp, (size_t)(wzl * vv));
+  Pool tmp_alloc = sub_pool(I->pool);
+  int rc = dalloc(tmp_alloc, &tmp, (size_t)(wzl * vv));
   if (rc) return rc;
   int d[4] = {(int)wzl, (int)vv, 1, 1};  // tmp[n][cd] = Gwz[cd][n]
   Perm4In x = pin(I->Gwz, 1, wzl, 0, 0, 1.0);
@@ -925,17 +1010,8 @@ int ascc_workspace_bytes(int no, int nv, int naux, int precision, int vvvv_mode,
   if (precision < ASCC_PREC_FP64 || precision > ASCC_PREC_BF16X3) return fail(ASCC_E_ARG, "unsupported precision");
   if (vvvv_mode != ASCC_VVVV_FULL && vvvv_mode != ASCC_VVVV_PACKED) return fail(ASCC_E_ARG, "unsupported vvvv_mode");
   if (diis_size < 1 || diis_size > kMaxDiis) return fail(ASCC_E_ARG, "diis_size must be in 1..16");
-  size_t total = 0;
-  for (const auto& item : ints_plan(no, nv, naux, vvvv_mode))
-    total += std::max<size_t>((size_t)item.second, 1) * sizeof(double);
-  if (precision != ASCC_PREC_FP64)
-    for (const auto& item : lowp_plan(no, nv, vvvv_mode))
-      total += std::max<size_t>((size_t)item.second, 1) * sizeof(float);
-  const long len = (long)no * nv + (long)no * no * nv * nv;
-  if (ints_bytes) *ints_bytes = total;
-  if (diis_bytes)
-    *diis_bytes = 2 * (size_t)diis_size * len * sizeof(double) +
-                  (size_t)update_partial_blocks() * (3 + kMaxDiis) * sizeof(double) + sizeof(DiisState);
+  if (ints_bytes) *ints_bytes = ints_footprint(no, nv, naux, precision, vvvv_mode);
+  if (diis_bytes) *diis_bytes = diis_footprint(no, nv, diis_size);
   return ASCC_OK;
 }
 
@@ -989,8 +1065,24 @@ int ascc_ints_shape(const ascc_ints* I, int* no, int* nv, int* naux) {
   return ASCC_OK;
 }
 
+static int build_ints_impl(const double* d_B, const double* d_fock, int fock_is_diag, int no, int nv, int naux,
+                           int precision, int vvvv_mode, void* ws, size_t ws_bytes, void* stream, ascc_ints** out);
+
 int ascc_build_ints(const double* d_B, const double* d_fock, int fock_is_diag, int no, int nv, int naux, int precision,
                     int vvvv_mode, void* stream, ascc_ints** out) {
+  return build_ints_impl(d_B, d_fock, fock_is_diag, no, nv, naux, precision, vvvv_mode, nullptr, 0, stream, out);
+}
+
+int ascc_build_ints_ws(const double* d_B, const double* d_fock, int fock_is_diag, int no, int nv, int naux,
+                       int precision, int vvvv_mode, void* d_workspace, size_t ws_bytes, void* stream,
+                       ascc_ints** out) {
+  if (!d_workspace) return fail(ASCC_E_ARG, "d_workspace is NULL");
+  return build_ints_impl(d_B, d_fock, fock_is_diag, no, nv, naux, precision, vvvv_mode, d_workspace, ws_bytes, stream,
+                         out);
+}
+
+static int build_ints_impl(const double* d_B, const double* d_fock, int fock_is_diag, int no, int nv, int naux,
+                           int precision, int vvvv_mode, void* ws, size_t ws_bytes, void* stream, ascc_ints** out) {
   if (!out) return fail(ASCC_E_ARG, "out is NULL");
   *out = nullptr;
   if (!d_B || !d_fock) return fail(ASCC_E_ARG, "d_B and d_fock must be device pointers");
@@ -1013,13 +1105,22 @@ int ascc_build_ints(const double* d_B, const double* d_fock, int fock_is_diag, i
   I->vv = v * v;
   I->ovov = I->ov * I->ov;
   I->oovv = I->oo * I->vv;
+  if (ws) {
+    if ((reinterpret_cast<uintptr_t>(ws) & (kAlign - 1)) != 0) {
+      delete I;
+      return fail(ASCC_E_ARG, "d_workspace must be 256-byte aligned");
+    }
+    I->pool.base = static_cast<char*>(ws);
+    I->pool.size = ws_bytes;
+    register_buffer(ws, ws_bytes);
+  }
   rc = ASCC_OK;
   for (const auto& item : ints_plan(no, nv, naux, vvvv_mode)) {
-    if (!rc) rc = dalloc(I->allocs, I->bytes, &(I->*(item.first)), (size_t)item.second);
+    if (!rc) rc = dalloc(I->pool, &(I->*(item.first)), (size_t)item.second);
   }
   if (precision != ASCC_PREC_FP64) {
     for (const auto& item : lowp_plan(no, nv, vvvv_mode)) {
-      if (!rc) rc = dalloc(I->allocs, I->bytes, &(I->*(item.first)), (size_t)item.second);
+      if (!rc) rc = dalloc(I->pool, &(I->*(item.first)), (size_t)item.second);
     }
   }
   I->cur_prec = precision;
@@ -1033,7 +1134,8 @@ int ascc_build_ints(const double* d_B, const double* d_fock, int fock_is_diag, i
     if (e != hipSuccess) rc = fail(ASCC_E_HIP, std::string("ascc_build_ints: ") + hipGetErrorString(e));
   }
   if (rc) {
-    free_all(I->allocs);
+    free_all(I->pool);
+    if (ws) unregister_buffer(ws);
     delete I;
     return rc;
   }
@@ -1043,7 +1145,9 @@ int ascc_build_ints(const double* d_B, const double* d_fock, int fock_is_diag, i
 
 void ascc_ints_free(ascc_ints* I) {
   if (!I) return;
-  free_all(I->allocs);
+  free_all(I->batch);
+  free_all(I->pool);
+  if (I->pool.base) unregister_buffer(I->pool.base);
   for (auto& m : I->marks) {
     (void)hipEventDestroy(m.second.first);
     (void)hipEventDestroy(m.second.second);
@@ -1063,7 +1167,67 @@ int ascc_residual(ascc_ints* I, const double* t1, const double* t2, double* r1, 
   return residual_fp64(I, t1, t2, r1, r2, e, static_cast<hipStream_t>(stream));
 }
 
+int ascc_batch_reserve(ascc_ints* I, int max_states) {
+  if (!I) return fail(ASCC_E_ARG, "NULL handle");
+  if (max_states < 1 || max_states > 4096) return fail(ASCC_E_ARG, "max_states must be in 1..4096");
+  if (max_states <= I->max_states) return ASCC_OK;
+  free_all(I->batch);
+  I->max_states = 0;
+  I->Tp_all = I->Rp_all = I->RL_all = nullptr;
+  I->Tpf_all = nullptr;
+  const long o = I->no, v = I->nv, To = o * (o + 1) / 2, Tv = v * (v + 1) / 2, vv = I->vv;
+  const long rows = (I->vvvv_mode == ASCC_VVVV_FULL) ? To * vv : 2 * To * Tv;
+  int rc = dalloc(I->batch, &I->Tp_all, (size_t)(max_states * rows));
+  if (!rc) rc = dalloc(I->batch, &I->Rp_all, (size_t)(max_states * rows));
+  if (!rc) rc = dalloc(I->batch, &I->RL_all, (size_t)(max_states * I->oovv));
+  if (!rc && I->precision != ASCC_PREC_FP64) rc = dalloc(I->batch, &I->Tpf_all, (size_t)(max_states * rows));
+  if (rc) {
+    free_all(I->batch);
+    return rc;
+  }
+  I->max_states = max_states;
+  return ASCC_OK;
+}
+
+int ascc_residual_batch(ascc_ints* I, int nstates, const double* const* t1, const double* const* t2,
+                        double* const* r1, double* const* r2, double* e, void* stream) {
+  if (!I || !t1 || !t2 || !r1 || !r2 || !e) return fail(ASCC_E_ARG, "NULL argument to ascc_residual_batch");
+  if (nstates < 1 || nstates > I->max_states)
+    return fail(ASCC_E_STATE, "nstates exceeds the capacity reserved with ascc_batch_reserve");
+  for (int k = 0; k < nstates; ++k)
+    if (!t1[k] || !t2[k] || !r1[k] || !r2[k]) return fail(ASCC_E_ARG, "NULL state pointer");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  ScopedBuffers user;
+  for (int k = 0; k < nstates; ++k) {
+    user.add(t1[k], sizeof(double) * I->ov);
+    user.add(t2[k], sizeof(double) * I->oovv);
+    user.add(r1[k], sizeof(double) * I->ov);
+    user.add(r2[k], sizeof(double) * I->oovv);
+  }
+  user.add(e, sizeof(double) * nstates);
+  std::vector<double*> RLs(nstates);
+  for (int k = 0; k < nstates; ++k) RLs[k] = I->RL_all + (long)k * I->oovv;
+  phase_begin(I, PH_LADDER, s);
+  int rc = pp_ladder_states(I, nstates, t2, RLs.data(), I->Tp_all, I->Rp_all, I->Tpf_all, s);
+  phase_end(I, s);
+  if (rc) return rc;
+  for (int k = 0; k < nstates && !rc; ++k) rc = residual_core(I, t1[k], t2[k], r1[k], r2[k], e + k, RLs[k], s);
+  return rc;
+}
+
+static int diis_create_impl(const ascc_ints* I, int max_vectors, int start, void* ws, size_t ws_bytes, ascc_diis** out);
+
 int ascc_diis_create(const ascc_ints* I, int max_vectors, int start, ascc_diis** out) {
+  return diis_create_impl(I, max_vectors, start, nullptr, 0, out);
+}
+
+int ascc_diis_create_ws(const ascc_ints* I, int max_vectors, int start, void* d_workspace, size_t ws_bytes,
+                        ascc_diis** out) {
+  if (!d_workspace) return fail(ASCC_E_ARG, "d_workspace is NULL");
+  return diis_create_impl(I, max_vectors, start, d_workspace, ws_bytes, out);
+}
+
+static int diis_create_impl(const ascc_ints* I, int max_vectors, int start, void* ws, size_t ws_bytes, ascc_diis** out) {
   if (!I || !out) return fail(ASCC_E_ARG, "NULL argument to ascc_diis_create");
   *out = nullptr;
   if (max_vectors < 1 || max_vectors > kMaxDiis) return fail(ASCC_E_ARG, "max_vectors must be in 1..16");
@@ -1075,18 +1239,25 @@ int ascc_diis_create(const ascc_ints* I, int max_vectors, int start, ascc_diis**
   D->start = start;
   D->calls = 0;
   D->len = I->ov + I->oovv;
-  size_t T = 0;
-  int rc = dalloc(D->allocs, T, &D->hist_t, (size_t)D->m * D->len);
-  if (!rc) rc = dalloc(D->allocs, T, &D->hist_e, (size_t)D->m * D->len);
-  if (!rc) rc = dalloc(D->allocs, T, &D->partial, (size_t)update_partial_blocks() * (3 + kMaxDiis));
-  if (!rc) rc = dalloc(D->allocs, T, &D->st, 1);
+  if (ws) {
+    if ((reinterpret_cast<uintptr_t>(ws) & (kAlign - 1)) != 0) {
+      delete D;
+      return fail(ASCC_E_ARG, "d_workspace must be 256-byte aligned");
+    }
+    D->pool.base = static_cast<char*>(ws);
+    D->pool.size = ws_bytes;
+  }
+  int rc = dalloc(D->pool, &D->hist_t, (size_t)D->m * D->len);
+  if (!rc) rc = dalloc(D->pool, &D->hist_e, (size_t)D->m * D->len);
+  if (!rc) rc = dalloc(D->pool, &D->partial, (size_t)update_partial_blocks() * (3 + kMaxDiis));
+  if (!rc) rc = dalloc(D->pool, &D->st, 1);
   if (!rc) rc = ascc_diis_reset(D, nullptr);
   if (!rc) {
     hipError_t e = d_sync(nullptr);
     if (e != hipSuccess) rc = fail(ASCC_E_HIP, std::string("ascc_diis_create: ") + hipGetErrorString(e));
   }
   if (rc) {
-    free_all(D->allocs);
+    free_all(D->pool);
     delete D;
     return rc;
   }
@@ -1108,7 +1279,7 @@ int ascc_diis_reset(ascc_diis* D, void* stream) {
 
 void ascc_diis_free(ascc_diis* D) {
   if (!D) return;
-  free_all(D->allocs);
+  free_all(D->pool);
   delete D;
 }
 
@@ -1139,7 +1310,7 @@ int ascc_update(ascc_ints* I, ascc_diis* D, double* t1, double* t2, const double
   u.no = I->no;
   u.nv = I->nv;
   u.m = D->m;
-  u.store = (D->calls >= D->start) ? 1 : 0;
+  u.start = D->start;
   u.len = D->len;
   u.shift = level_shift;
   phase_begin(I, PH_UPDATE, static_cast<hipStream_t>(stream));
@@ -1159,15 +1330,14 @@ int ascc_solve(ascc_ints* I, const ascc_opts* opts, double* t1, double* t2, ascc
   ascc_diis* D = nullptr;
   int rc = ascc_diis_create(I, opts->diis_size, opts->diis_start, &D);
   if (rc) return rc;
-  std::vector<void*> work;
-  size_t T = 0;
+  Pool work;
   double *r1 = nullptr, *r2 = nullptr, *e = nullptr, *stats = nullptr, *t1s = nullptr, *t2s = nullptr;
-  rc = dalloc(work, T, &r1, I->ov);
-  if (!rc) rc = dalloc(work, T, &r2, I->oovv);
-  if (!rc) rc = dalloc(work, T, &e, 1);
-  if (!rc) rc = dalloc(work, T, &stats, 8);
-  if (!rc) rc = dalloc(work, T, &t1s, I->ov);
-  if (!rc) rc = dalloc(work, T, &t2s, I->oovv);
+  rc = dalloc(work, &r1, I->ov);
+  if (!rc) rc = dalloc(work, &r2, I->oovv);
+  if (!rc) rc = dalloc(work, &e, 1);
+  if (!rc) rc = dalloc(work, &stats, 8);
+  if (!rc) rc = dalloc(work, &t1s, I->ov);
+  if (!rc) rc = dalloc(work, &t2s, I->oovv);
   double* hstats = nullptr;
   static double dry_stats[8];
   if (dry_run()) {

@@ -178,7 +178,7 @@ struct UK {
   double* hist_e;
   double* partial;
   const DiisState* st;
-  int o, v, m, store, nstat;
+  int o, v, m, start, nstat;
   long len;
   double shift;
 };
@@ -186,8 +186,9 @@ struct UK {
 __global__ __launch_bounds__(kThreads) void update_stage1(UK p) {
   __shared__ double sh[kThreads / 64];
   const int head = p.st->head;
+  const bool store = p.st->calls >= p.start;  // decided on the device, so a captured graph replays it
   bool valid[kMaxDiis];
-  for (int k = 0; k < kMaxDiis; ++k) valid[k] = p.store && k < p.m && (k == head || p.st->slot_age[k] >= 0);
+  for (int k = 0; k < kMaxDiis; ++k) valid[k] = store && k < p.m && (k == head || p.st->slot_age[k] >= 0);
   double dots[kMaxDiis];
   for (int k = 0; k < kMaxDiis; ++k) dots[k] = 0.0;
   double rr = 0.0, rmax = 0.0, bad = 0.0;
@@ -201,7 +202,7 @@ __global__ __launch_bounds__(kThreads) void update_stage1(UK p) {
     rr += r * r;
     rmax = fmax(rmax, fabs(r));
     if (!isfinite(r)) bad += 1.0;
-    if (p.store) {
+    if (store) {
       for (int k = 0; k < kMaxDiis; ++k)
         if (valid[k]) dots[k] += s * ((k == head) ? s : p.hist_e[(long)k * p.len + x]);
       p.hist_t[(long)head * p.len + x] = tn;
@@ -280,8 +281,9 @@ __device__ bool diis_solve(DiisState* st, int m) {
 }
 
 __global__ __launch_bounds__(kThreads) void update_stage2(DiisState* st, const double* partial, int nblk, int nstat,
-                                                         int m, int store, const double* e, double* stats,
+                                                         int m, int start, const double* e, double* stats,
                                                          double shift) {
+  const bool store = st->calls >= start;
   __shared__ double sh[kThreads / 64];
   __shared__ double red[3 + kMaxDiis];
   double a = 0.0;
@@ -394,15 +396,15 @@ __global__ __launch_bounds__(kThreads) void unpack_pairs_kernel(double* __restri
 
 // t+-[p(i,j)][p(c,d)] for i <= j, c <= d:
 //   t+ = (t_ij^cd + t_ij^dc)/2 (c < d), t_ij^cc (c = d);  t- = (t_ij^cd - t_ij^dc)/2 (c < d), 0 (c = d).
-__global__ __launch_bounds__(kThreads) void pack_tpm_kernel(double* __restrict__ tp, const double* __restrict__ t2,
-                                                           int o, int v) {
+__global__ __launch_bounds__(kThreads) void pack_tpm_kernel(double* __restrict__ tplus, double* __restrict__ tminus,
+                                                           const double* __restrict__ t2, int o, int v) {
   const int i = blockIdx.y / o, j = blockIdx.y % o;
   if (i > j) return;
-  const long To = (long)o * (o + 1) / 2, Tv = (long)v * (v + 1) / 2, vv = (long)v * v;
+  const long Tv = (long)v * (v + 1) / 2, vv = (long)v * v;
   const double* src = t2 + ((long)i * o + j) * vv;
   const long p = pidx(i, j, o);
-  double* plus = tp + p * Tv;
-  double* minus = tp + (To + p) * Tv;
+  double* plus = tplus + p * Tv;
+  double* minus = tminus + p * Tv;
   for (long x = blockIdx.x * (long)blockDim.x + threadIdx.x; x < vv; x += (long)gridDim.x * blockDim.x) {
     const int c = x / v, d = x % v;
     if (c > d) continue;
@@ -414,13 +416,13 @@ __global__ __launch_bounds__(kThreads) void pack_tpm_kernel(double* __restrict__
 }
 
 // RL[i][j][a][b] from R+-[p][p(a,b)]: R^ab = R+ + R- (a <= b), R+ - R- (a > b), with R_ij = R_ji^T.
-__global__ __launch_bounds__(kThreads) void unpack_rpm_kernel(double* __restrict__ RL, const double* __restrict__ Rp,
-                                                             int o, int v) {
+__global__ __launch_bounds__(kThreads) void unpack_rpm_kernel(double* __restrict__ RL, const double* __restrict__ Rplus,
+                                                             const double* __restrict__ Rminus, int o, int v) {
   const int i = blockIdx.y / o, j = blockIdx.y % o;
-  const long To = (long)o * (o + 1) / 2, Tv = (long)v * (v + 1) / 2, vv = (long)v * v;
+  const long Tv = (long)v * (v + 1) / 2, vv = (long)v * v;
   const long p = (i <= j) ? pidx(i, j, o) : pidx(j, i, o);
-  const double* plus = Rp + p * Tv;
-  const double* minus = Rp + (To + p) * Tv;
+  const double* plus = Rplus + p * Tv;
+  const double* minus = Rminus + p * Tv;
   double* dst = RL + ((long)i * o + j) * vv;
   for (long x = blockIdx.x * (long)blockDim.x + threadIdx.x; x < vv; x += (long)gridDim.x * blockDim.x) {
     int a = x / v, b = x % v;
@@ -601,23 +603,25 @@ hipError_t unpack_pairs(double* RL, const double* Rp, int o, int v, hipStream_t 
   return hipGetLastError();
 }
 
-hipError_t pack_tpm(double* tp, const double* t2, int o, int v, hipStream_t s) {
+hipError_t pack_tpm(double* tplus, double* tminus, const double* t2, int o, int v, hipStream_t s) {
   const long To = (long)o * (o + 1) / 2, Tv = (long)v * (v + 1) / 2, vv = (long)v * v;
-  if (bounds_checking() && !(chk(tp, 2 * To * Tv, "pack_tpm out") && chk(t2, (long)o * o * vv, "pack_tpm t2")))
+  if (bounds_checking() && !(chk(tplus, To * Tv, "pack_tpm plus") && chk(tminus, To * Tv, "pack_tpm minus") &&
+                             chk(t2, (long)o * o * vv, "pack_tpm t2")))
     return hipErrorInvalidValue;
   if (dry_run()) return hipSuccess;
   dim3 grid((unsigned)std::min<long>((vv + kThreads - 1) / kThreads, 64), o * o);
-  hipLaunchKernelGGL(pack_tpm_kernel, grid, dim3(kThreads), 0, s, tp, t2, o, v);
+  hipLaunchKernelGGL(pack_tpm_kernel, grid, dim3(kThreads), 0, s, tplus, tminus, t2, o, v);
   return hipGetLastError();
 }
 
-hipError_t unpack_rpm(double* RL, const double* Rp, int o, int v, hipStream_t s) {
+hipError_t unpack_rpm(double* RL, const double* Rplus, const double* Rminus, int o, int v, hipStream_t s) {
   const long To = (long)o * (o + 1) / 2, Tv = (long)v * (v + 1) / 2, vv = (long)v * v;
-  if (bounds_checking() && !(chk(RL, (long)o * o * vv, "unpack_rpm RL") && chk(Rp, 2 * To * Tv, "unpack_rpm Rp")))
+  if (bounds_checking() && !(chk(RL, (long)o * o * vv, "unpack_rpm RL") && chk(Rplus, To * Tv, "unpack_rpm plus") &&
+                             chk(Rminus, To * Tv, "unpack_rpm minus")))
     return hipErrorInvalidValue;
   if (dry_run()) return hipSuccess;
   dim3 grid((unsigned)std::min<long>((vv + kThreads - 1) / kThreads, 64), o * o);
-  hipLaunchKernelGGL(unpack_rpm_kernel, grid, dim3(kThreads), 0, s, RL, Rp, o, v);
+  hipLaunchKernelGGL(unpack_rpm_kernel, grid, dim3(kThreads), 0, s, RL, Rplus, Rminus, o, v);
   return hipGetLastError();
 }
 
@@ -650,7 +654,7 @@ hipError_t diis_update(const UpdateArgs& u, hipStream_t s) {
   p.o = u.no;
   p.v = u.nv;
   p.m = u.m;
-  p.store = u.store;
+  p.start = u.start;
   p.nstat = 3 + kMaxDiis;
   p.len = u.len;
   p.shift = u.shift;
@@ -668,7 +672,7 @@ hipError_t diis_update(const UpdateArgs& u, hipStream_t s) {
   if (dry_run()) return hipSuccess;
   hipLaunchKernelGGL(update_stage1, dim3(kRedBlocks), dim3(kThreads), 0, s, p);
   hipLaunchKernelGGL(update_stage2, dim3(1), dim3(kThreads), 0, s, u.st, u.partial, kRedBlocks, 3 + kMaxDiis,
-                     u.m, u.store, u.e, u.stats, u.shift);
+                     u.m, u.start, u.e, u.stats, u.shift);
   hipLaunchKernelGGL(update_stage3, dim3(grid_for(u.len)), dim3(kThreads), 0, s, u.t1, u.t2, u.hist_t, u.st, u.m,
                      (long)u.no * u.nv, u.len);
   return hipGetLastError();

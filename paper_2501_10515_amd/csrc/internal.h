@@ -105,8 +105,9 @@ hipError_t assemble_r2(double* r2, const double* g1, const double* rl, const dou
 // Pair packing of the particle-particle ladder (p(i,j) = row-major index of i <= j).
 hipError_t pack_pairs(double* out, const double* in, int o, long L, hipStream_t s);     // out[p][x] = in[i][j][x]
 hipError_t unpack_pairs(double* RL, const double* Rp, int o, int v, hipStream_t s);    // mirror i > j rows
-hipError_t pack_tpm(double* tp, const double* t2, int o, int v, hipStream_t s);         // [2][T(o)][T(v)]
-hipError_t unpack_rpm(double* RL, const double* Rp, int o, int v, hipStream_t s);       // from [2][T(o)][T(v)]
+// t+ rows -> tplus[T(o)][T(v)], t- rows -> tminus[T(o)][T(v)] (and back for R+-)
+hipError_t pack_tpm(double* tplus, double* tminus, const double* t2, int o, int v, hipStream_t s);
+hipError_t unpack_rpm(double* RL, const double* Rplus, const double* Rminus, int o, int v, hipStream_t s);
 hipError_t pack_vvvv(double* Vp, const double* W, int a0, int a1, int v, hipStream_t s);  // rows a0 <= a < a1
 
 // r1[i][a] += Fhat[no+a][i]
@@ -150,7 +151,7 @@ struct UpdateArgs {
   DiisState* st;
   double* stats;
   int no, nv, m;
-  int store;  // 1: this call stores its (amplitudes, step) pair in the history
+  int start;  // calls before this (device-side count) store no pair in the history
   long len;   // no*nv + no*no*nv*nv
   double shift;
 };

@@ -37,6 +37,13 @@ def main(shapes):
     L.ascc_diis_create.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp)]
     L.ascc_update.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_double, vp, vp]
     L.ascc_solve.argtypes = [vp, ctypes.POINTER(Opts), vp, vp, ctypes.POINTER(Result), vp]
+    L.ascc_batch_reserve.argtypes = [vp, ctypes.c_int]
+    L.ascc_residual_batch.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                      ctypes.POINTER(vp), vp, vp]
+    L.ascc_workspace_bytes.argtypes = [ctypes.c_int] * 6 + [ctypes.POINTER(ctypes.c_size_t)] * 2
+    L.ascc_build_ints_ws.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_int, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    L.ascc_diis_create_ws.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, ctypes.c_size_t, ctypes.POINTER(vp)]
     L.ascc_ints_free.argtypes = [vp]
     L.ascc_diis_free.argtypes = [vp]
     ok = True
@@ -68,11 +75,46 @@ def main(shapes):
                     if rc == 0:
                         rc = L.ascc_update(h, d, t1, t2, r1, r2, e, ctypes.c_double(0.0), st, None)
                 L.ascc_diis_free(d)
+            if rc == 0:  # a batch of three states
+                S = 3
+                rc = L.ascc_batch_reserve(h, S)
+                arr = vp * S
+                bt1 = arr(*[fake(8 * o * v) for _ in range(S)])
+                bt2 = arr(*[fake(8 * o * o * v * v) for _ in range(S)])
+                br1 = arr(*[fake(8 * o * v) for _ in range(S)])
+                br2 = arr(*[fake(8 * o * o * v * v) for _ in range(S)])
+                if rc == 0:
+                    rc = L.ascc_residual_batch(h, S, bt1, bt2, br1, br2, fake(8 * S), None)
             if rc == 0:
                 res = Result()
                 rc = L.ascc_solve(h, ctypes.byref(Opts(1e-8, 0, 0, 3, 8, 1, 0.0, 1e-3, 1)), t1, t2, ctypes.byref(res),
                                   None)
             L.ascc_ints_free(h)
+        if rc == 0:  # the same build and an update carved from exact-size workspaces
+            ib, dbytes = ctypes.c_size_t(), ctypes.c_size_t()
+            rc = L.ascc_workspace_bytes(o, v, Q, prec, mode, 8, ctypes.byref(ib), ctypes.byref(dbytes))
+            h2 = vp()
+            if rc == 0:
+                rc = L.ascc_build_ints_ws(B, F, diag, o, v, Q, prec, mode, fake(ib.value), ib.value, None,
+                                          ctypes.byref(h2))
+            if rc == 0:
+                d2 = vp()
+                rc = L.ascc_diis_create_ws(h2, 8, 1, fake(dbytes.value), dbytes.value, ctypes.byref(d2))
+                t1, t2, r1, r2, e, st = (fake(8 * o * v), fake(8 * o * o * v * v), fake(8 * o * v),
+                                         fake(8 * o * o * v * v), fake(8), fake(64))
+                if rc == 0:
+                    rc = L.ascc_residual(h2, t1, t2, r1, r2, e, None)
+                if rc == 0:
+                    rc = L.ascc_update(h2, d2, t1, t2, r1, r2, e, ctypes.c_double(0.0), st, None)
+                L.ascc_diis_free(d2)
+            if rc == 0:  # one byte short of the reported size must be refused
+                h3 = vp()
+                rc3 = L.ascc_build_ints_ws(B, F, diag, o, v, Q, prec, mode, fake(ib.value), ib.value - 1, None,
+                                           ctypes.byref(h3))
+                if rc3 != -3:
+                    rc = -100
+                    print("undersized workspace accepted", flush=True)
+            L.ascc_ints_free(h2)
         if rc == 0:
             print(f"OK {o} {v} {Q} mode {mode} prec {prec}", flush=True)
         else:

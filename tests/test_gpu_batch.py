@@ -1,0 +1,72 @@
+"""Several amplitude sets on one integral set: one batched ladder launch, per-state results
+identical to the single-state residual (bitwise) and to the oracle."""
+import numpy as np
+import pytest
+
+from gen.synth_df import make_system, random_amplitudes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2501_10515_amd as P
+
+    P.load_library()
+    return P
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+@pytest.mark.parametrize("mode", ["full", "packed"])
+@pytest.mark.parametrize("o,v,Q,S", [(3, 7, 15, 3), (6, 40, 90, 5)])
+def test_batch_equals_alone_bitwise(P, o, v, Q, S, mode, prec):
+    import torch
+
+    from oracle import cs_ccsd
+
+    from .gpu_util import dev, gpu_residual, host
+
+    print(f"case o={o} v={v} Q={Q} S={S} vvvv={mode} prec={prec}", flush=True)
+    B, eps = make_system(o, v, Q, 42, sigma=0.1)
+    amps = [random_amplitudes(o, v, 300 + k, 0.05, 0.05) for k in range(S)]
+    pc = P.ASCC_PREC_FP64 if prec == "fp64" else P.ASCC_PREC_BF16X3
+    vm = P.ASCC_VVVV_FULL if mode == "full" else P.ASCC_VVVV_PACKED
+    ints = P.ascc_build_ints(dev(B), dev(eps), o, precision=pc, vvvv_mode=vm)
+    P.ascc_batch_reserve(ints, S)
+    t1s = [dev(a[0]) for a in amps]
+    t2s = [dev(a[1]) for a in amps]
+    r1s = [torch.empty_like(t) for t in t1s]
+    r2s = [torch.empty_like(t) for t in t2s]
+    e = torch.empty(S, dtype=torch.float64, device="cuda")
+    P.ascc_residual_batch(ints, t1s, t2s, r1s, r2s, e)
+    torch.cuda.synchronize()
+    eb = host(e)
+    for k in range(S):
+        r1, r2, ek = gpu_residual(P, ints, *amps[k])
+        assert np.array_equal(host(r1s[k]), r1) and np.array_equal(host(r2s[k]), r2), f"state {k}"
+        assert eb[k] == ek
+        if prec == "fp64":
+            ref1, ref2 = cs_ccsd.residual(B, np.diag(eps), *amps[k])
+            assert max(np.abs(r1 - ref1).max(), np.abs(r2 - ref2).max()) <= 1e-10
+    ints.close()
+
+
+def test_batch_capacity_is_enforced(P):
+    import torch
+
+    from .gpu_util import dev
+
+    B, eps = make_system(2, 3, 8, 1)
+    ints = P.ascc_build_ints(dev(B), dev(eps), 2)
+    P.ascc_batch_reserve(ints, 1)
+    t1 = torch.zeros((2, 3), dtype=torch.float64, device="cuda")
+    t2 = torch.zeros((2, 2, 3, 3), dtype=torch.float64, device="cuda")
+    e = torch.empty(2, dtype=torch.float64, device="cuda")
+    with pytest.raises(P.AsccError) as exc:
+        P.ascc_residual_batch(ints, [t1, t1], [t2, t2], [t1.clone(), t1.clone()], [t2.clone(), t2.clone()], e)
+    assert exc.value.code == P.ASCC_E_STATE
+    ints.close()
