@@ -106,7 +106,9 @@ int ascc_get_precision(const ascc_ints* ints);
 /* ascc_build_ints carving every device array, build-time temporaries included, from the
  * caller's workspace d_workspace (256-byte aligned, ws_bytes >= the ints_bytes that
  * ascc_workspace_bytes reports) instead of allocating: for callers that admit work by memory
- * footprint or must not call the allocator.  The workspace must outlive the handle.
+ * footprint or must not call the allocator.  Unlike ascc_build_ints it does not synchronise:
+ * the build is queued on `stream` (d_B and d_fock must stay valid until it has run; later work
+ * on the same stream is ordered after it).  The workspace must outlive the handle.
  * Errors: as ascc_build_ints, ASCC_E_NOMEM if ws_bytes is too small. */
 int ascc_build_ints_ws(const double* d_B, const double* d_fock, int fock_is_diag, int no, int nv, int naux,
                        int precision, int vvvv_mode, void* d_workspace, size_t ws_bytes, void* stream,

@@ -292,11 +292,14 @@ std::vector<std::pair<float* ascc_ints::*, long>> lowp_plan(long o, long v, int 
   const long ov = o * v, oo = o * o, vv = v * v, ovov = ov * ov;
   const long To = o * (o + 1) / 2, Tv = v * (v + 1) / 2;
   const bool full = (mode == ASCC_VVVV_FULL);
+  // rows x padded leading dimension (lowp_ld); one float = one bf16 hi + one bf16 lo for BF16X3
+  const long lvv = lowp_ld(vv), lTv = lowp_ld(Tv), lov = lowp_ld(ov);
+  (void)ovov;
   return {
-      {&ascc_ints::Vf, full ? vv * vv : 2 * Tv * Tv}, {&ascc_ints::GwzTf, (ov + oo) * vv},
-      {&ascc_ints::KLf, 2 * ovov},                    {&ascc_ints::Tpf, full ? To * vv : 2 * To * Tv},
-      {&ascc_ints::t2f, oo * vv},                     {&ascc_ints::TUf, 2 * ovov},
-      {&ascc_ints::XZf, 2 * ovov},
+      {&ascc_ints::Vf, full ? vv * lvv : 2 * Tv * lTv}, {&ascc_ints::GwzTf, (ov + oo) * lvv},
+      {&ascc_ints::KLf, 2 * ov * lov},                  {&ascc_ints::Tpf, full ? To * lvv : 2 * To * lTv},
+      {&ascc_ints::t2f, oo * lvv},                      {&ascc_ints::TUf, 2 * ov * lov},
+      {&ascc_ints::XZf, 2 * ov * lov},
   };
 }
 
@@ -482,8 +485,8 @@ int add_two_electron_fock(const ascc_ints* I, double* F, const double* Bq, doubl
 
 
 // C_z[m][n] = sum_k A_z[m][k] B_z[n][k] in the handle's current low precision (FP64 result).
-GemmLP lp_nt(const ascc_ints* I, long M, long N, long K, int nb, const float* A, long lda, long sa2, const float* B,
-             long ldb, long sb2, double* C, long ldc, long sc2) {
+GemmLP lp_nt(const ascc_ints* I, long M, long N, long K, int nb, const float* A, long lda, long sa2, long a_plane,
+             const float* B, long ldb, long sb2, long b_plane, double* C, long ldc, long sc2) {
   GemmLP g;
   g.M = (int)M;
   g.N = (int)N;
@@ -492,15 +495,23 @@ GemmLP lp_nt(const ascc_ints* I, long M, long N, long K, int nb, const float* A,
   g.A = A;
   g.lda = lda;
   g.sa2 = sa2;
+  g.a_plane = a_plane;
   g.B = B;
   g.ldb = ldb;
   g.sb2 = sb2;
+  g.b_plane = b_plane;
   g.C = C;
   g.scm = ldc;
   g.scn = 1;
   g.sc2 = sc2;
   g.prec = (I->cur_prec == ASCC_PREC_BF16X3) ? kPrecBF16x3 : kPrecFP32;
   return g;
+}
+
+// Low-precision shadow of rows x cols FP64 (contiguous rows) with leading dimension lowp_ld(cols).
+hipError_t shadow(const ascc_ints* I, float* out, const double* in, long rows, long cols, hipStream_t s) {
+  const int prec = (I->cur_prec == ASCC_PREC_BF16X3) ? kPrecBF16x3 : kPrecFP32;
+  return to_lowp_2d(prec, out, lowp_ld(cols), in, cols, rows, cols, s);
 }
 
 // Particle-particle ladder RL_s[i][j][a][b] = sum_cd (t_s)_ij^cd (ac|bd) for S states in one
@@ -517,8 +528,9 @@ int pp_ladder_states(ascc_ints* I, int S, const double* const* t2s, double* cons
   if (I->vvvv_mode == ASCC_VVVV_FULL) {
     for (int k = 0; k < S; ++k) HIPCHK(pack_pairs(Tp + k * To * vv, t2s[k], o, vv, s));
     if (lowp) {
-      HIPCHK(cvt_f32(Tpf, Tp, M * vv, s));
-      HIPCHK(gemm_lowp(lp_nt(I, M, vv, vv, 1, Tpf, vv, 0, I->Vf, vv, 0, Rp, vv, 0), s));
+      const long ld = lowp_ld(vv);
+      HIPCHK(shadow(I, Tpf, Tp, M, vv, s));
+      HIPCHK(gemm_lowp(lp_nt(I, M, vv, vv, 1, Tpf, ld, 0, M * ld, I->Vf, ld, 0, vv * ld, Rp, vv, 0), s));
     } else {
       HIPCHK(gemm_f64(gemm_rm(M, vv, vv, 1.0, Tp, vv, false, I->V, vv, true, 0.0, Rp, vv), s));
     }
@@ -526,8 +538,10 @@ int pp_ladder_states(ascc_ints* I, int S, const double* const* t2s, double* cons
   } else {
     for (int k = 0; k < S; ++k) HIPCHK(pack_tpm(Tp + k * To * Tv, Tp + (M + k * To) * Tv, t2s[k], o, v, s));
     if (lowp) {
-      HIPCHK(cvt_f32(Tpf, Tp, 2 * M * Tv, s));
-      HIPCHK(gemm_lowp(lp_nt(I, M, Tv, Tv, 2, Tpf, Tv, M * Tv, I->Vf, Tv, Tv * Tv, Rp, Tv, M * Tv), s));
+      const long ld = lowp_ld(Tv);
+      HIPCHK(shadow(I, Tpf, Tp, 2 * M, Tv, s));
+      HIPCHK(gemm_lowp(lp_nt(I, M, Tv, Tv, 2, Tpf, ld, M * ld, 2 * M * ld, I->Vf, ld, Tv * ld, 2 * Tv * ld, Rp, Tv,
+                             M * Tv), s));
     } else {
       Gemm g = gemm_rm(M, Tv, Tv, 1.0, Tp, Tv, false, I->V, Tv, true, 0.0, Rp, Tv);
       g.sa2 = M * Tv;
@@ -619,8 +633,9 @@ int residual_core(ascc_ints* I, const double* t1, const double* t2, double* r1, 
   phase_begin(I, PH_WZ, s);
   const bool lowp = I->cur_prec != ASCC_PREC_FP64;
   if (lowp) {
-    HIPCHK(cvt_f32(I->t2f, t2, oo * vv, s));
-    HIPCHK(gemm_lowp(lp_nt(I, oo, wzl, vv, 1, I->t2f, vv, 0, I->GwzTf, vv, 0, I->WZ, wzl, 0), s));
+    const long ld = lowp_ld(vv);
+    HIPCHK(shadow(I, I->t2f, t2, oo, vv, s));
+    HIPCHK(gemm_lowp(lp_nt(I, oo, wzl, vv, 1, I->t2f, ld, 0, oo * ld, I->GwzTf, ld, 0, wzl * ld, I->WZ, wzl, 0), s));
   } else {
     HIPCHK(mm(I, gemm_rm(oo, wzl, vv, 1.0, t2, vv, false, I->Gwz, wzl, false, 0.0, I->WZ, wzl), s));
   }
@@ -647,8 +662,10 @@ int residual_core(ascc_ints* I, const double* t1, const double* t2, double* r1, 
   // --- rings: Y1 = Tx K, Y2 = U L (batched pair)
   phase_begin(I, PH_RING_Y, s);
   if (lowp) {  // K and L are symmetric matrices, so B[n][k] = B[k][n]
-    HIPCHK(cvt_f32(I->TUf, I->TU, 2 * ovov, s));
-    HIPCHK(gemm_lowp(lp_nt(I, ov, ov, ov, 2, I->TUf, ov, ovov, I->KLf, ov, ovov, I->Y, ov, ovov), s));
+    const long ld = lowp_ld(ov);
+    HIPCHK(shadow(I, I->TUf, I->TU, 2 * ov, ov, s));
+    HIPCHK(gemm_lowp(lp_nt(I, ov, ov, ov, 2, I->TUf, ld, ov * ld, 2 * ov * ld, I->KLf, ld, ov * ld, 2 * ov * ld, I->Y,
+                           ov, ovov), s));
   } else {
     Gemm g = gemm_rm(ov, ov, ov, 1.0, I->TU, ov, false, I->KL, ov, false, 0.0, I->Y, ov);
     g.sa2 = ovov;
@@ -671,8 +688,10 @@ int residual_core(ascc_ints* I, const double* t1, const double* t2, double* r1, 
   phase_end(I, s);
   phase_begin(I, PH_RING_P, s);
   if (lowp) {  // P1 = Tx Xc^T, P2 = U Zd^T
-    HIPCHK(cvt_f32(I->XZf, I->XZ, 2 * ovov, s));
-    HIPCHK(gemm_lowp(lp_nt(I, ov, ov, ov, 2, I->TUf, ov, ovov, I->XZf, ov, ovov, I->P, ov, ovov), s));
+    const long ld = lowp_ld(ov);
+    HIPCHK(shadow(I, I->XZf, I->XZ, 2 * ov, ov, s));
+    HIPCHK(gemm_lowp(lp_nt(I, ov, ov, ov, 2, I->TUf, ld, ov * ld, 2 * ov * ld, I->XZf, ld, ov * ld, 2 * ov * ld, I->P,
+                           ov, ovov), s));
   } else {
     Gemm g = gemm_rm(ov, ov, ov, 1.0, I->TU, ov, false, I->XZ, ov, true, 0.0, I->P, ov);
     g.sa2 = ovov;
@@ -908,7 +927,7 @@ int build_constants(ascc_ints* I, const double* Bsrc, const double* fock, int fo
       Perm4In x = pin(Jov, (long)o * v, 1, (long)v * o * v, v, 1.0);
       e = permute4_strided(I->Gwz + ov, ostr, d, 0.0, &x, 1, s);
     }
-    if (e == hipSuccess) e = d_sync(s);
+    if (e == hipSuccess && !tmp_alloc.base) e = d_sync(s);  // carved temporaries need no wait
     free_all(tmp_alloc);
     if (e != hipSuccess) {
       if (bounds_checking() && e == hipErrorInvalidValue) return ASCC_E_HIP;  // message already set
@@ -954,7 +973,7 @@ int build_constants(ascc_ints* I, const double* Bsrc, const double* fock, int fo
       e = vslab(a0, na, tmp);
       if (e == hipSuccess) e = pack_vvvv(I->V, tmp, a0, a0 + na, v, s);
     }
-    if (e == hipSuccess) e = d_sync(s);
+    if (e == hipSuccess && !tmp_alloc.base) e = d_sync(s);  // carved temporaries need no wait
     free_all(tmp_alloc);
     if (e != hipSuccess) {
       if (!(bounds_checking() && e == hipErrorInvalidValue)) set_error(std::string("building vvvv: ") + hipGetErrorString(e));
@@ -968,9 +987,13 @@ int build_constants(ascc_ints* I, const double* Bsrc, const double* fock, int fo
 int build_lowp_shadows(ascc_ints* I, hipStream_t s) {
   const long vv = I->vv, ov = I->ov, oo = I->oo, wzl = ov + oo;
   const long Tv = (long)I->nv * (I->nv + 1) / 2;
-  const long nV = (I->vvvv_mode == ASCC_VVVV_FULL) ? vv * vv : 2 * Tv * Tv;
-  HIPCHK(cvt_f32(I->Vf, I->V, nV, s));
-  HIPCHK(cvt_f32(I->KLf, I->KL, 2 * I->ovov, s));
+
+  if (I->vvvv_mode == ASCC_VVVV_FULL) {
+    HIPCHK(shadow(I, I->Vf, I->V, vv, vv, s));
+  } else {
+    HIPCHK(shadow(I, I->Vf, I->V, 2 * Tv, Tv, s));
+  }
+  HIPCHK(shadow(I, I->KLf, I->KL, 2 * ov, ov, s));
   double* tmp = nullptr;
   Pool tmp_alloc = sub_pool(I->pool);
   int rc = dalloc(tmp_alloc, &tmp, (size_t)(wzl * vv));
@@ -978,8 +1001,8 @@ int build_lowp_shadows(ascc_ints* I, hipStream_t s) {
   int d[4] = {(int)wzl, (int)vv, 1, 1};  // tmp[n][cd] = Gwz[cd][n]
   Perm4In x = pin(I->Gwz, 1, wzl, 0, 0, 1.0);
   hipError_t e = permute4(tmp, d, 0.0, &x, 1, s);
-  if (e == hipSuccess) e = cvt_f32(I->GwzTf, tmp, wzl * vv, s);
-  if (e == hipSuccess) e = d_sync(s);
+  if (e == hipSuccess) e = shadow(I, I->GwzTf, tmp, wzl, vv, s);
+  if (e == hipSuccess && !tmp_alloc.base) e = d_sync(s);  // carved temporaries need no wait
   free_all(tmp_alloc);
   if (e != hipSuccess) {
     if (!(bounds_checking() && e == hipErrorInvalidValue)) set_error(std::string("FP32 shadows: ") + hipGetErrorString(e));
@@ -1019,7 +1042,9 @@ int ascc_set_precision(ascc_ints* I, int precision) {
   if (!I) return fail(ASCC_E_ARG, "NULL handle");
   if (precision < ASCC_PREC_FP64 || precision > ASCC_PREC_BF16X3) return fail(ASCC_E_ARG, "unsupported precision");
   if (precision != ASCC_PREC_FP64 && I->precision == ASCC_PREC_FP64)
-    return fail(ASCC_E_STATE, "integral set was built for FP64 only (no FP32 shadows)");
+    return fail(ASCC_E_STATE, "integral set was built for FP64 only (no low-precision shadows)");
+  if (precision != ASCC_PREC_FP64 && precision != I->precision)
+    return fail(ASCC_E_STATE, "integral set holds shadows for its build precision only");
   I->cur_prec = precision;
   return ASCC_OK;
 }
@@ -1129,7 +1154,7 @@ static int build_ints_impl(const double* d_B, const double* d_fock, int fock_is_
   user.add(d_fock, sizeof(double) * (fock_is_diag ? n : nn));
   if (!rc) rc = build_constants(I, d_B, d_fock, fock_is_diag, s);
   if (!rc && precision != ASCC_PREC_FP64) rc = build_lowp_shadows(I, s);
-  if (!rc) {
+  if (!rc && !ws) {  // a workspace build stays asynchronous on `stream`
     hipError_t e = d_sync(s);
     if (e != hipSuccess) rc = fail(ASCC_E_HIP, std::string("ascc_build_ints: ") + hipGetErrorString(e));
   }
@@ -1177,10 +1202,11 @@ int ascc_batch_reserve(ascc_ints* I, int max_states) {
   I->Tpf_all = nullptr;
   const long o = I->no, v = I->nv, To = o * (o + 1) / 2, Tv = v * (v + 1) / 2, vv = I->vv;
   const long rows = (I->vvvv_mode == ASCC_VVVV_FULL) ? To * vv : 2 * To * Tv;
+  const long lrows = (I->vvvv_mode == ASCC_VVVV_FULL) ? To * lowp_ld(vv) : 2 * To * lowp_ld(Tv);
   int rc = dalloc(I->batch, &I->Tp_all, (size_t)(max_states * rows));
   if (!rc) rc = dalloc(I->batch, &I->Rp_all, (size_t)(max_states * rows));
   if (!rc) rc = dalloc(I->batch, &I->RL_all, (size_t)(max_states * I->oovv));
-  if (!rc && I->precision != ASCC_PREC_FP64) rc = dalloc(I->batch, &I->Tpf_all, (size_t)(max_states * rows));
+  if (!rc && I->precision != ASCC_PREC_FP64) rc = dalloc(I->batch, &I->Tpf_all, (size_t)(max_states * lrows));
   if (rc) {
     free_all(I->batch);
     return rc;

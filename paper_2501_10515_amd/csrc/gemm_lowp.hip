@@ -231,6 +231,191 @@ __global__ __launch_bounds__(NT, 1) void gemm_lowp_kernel(LP p) {
   if (nkt == 0) flush(true);
 }
 
+// Row-padded conversions: out row r holds in row r (cols values) then zeros up to ldo.
+__global__ __launch_bounds__(256) void cvt_f32_2d_kernel(float* __restrict__ out, long ldo, const double* __restrict__ in,
+                                                         long ldi, long rows, long cols) {
+  const long total = rows * ldo;
+  for (long x = blockIdx.x * 256L + threadIdx.x; x < total; x += (long)gridDim.x * 256) {
+    const long r = x / ldo, c = x - r * ldo;
+    out[x] = (c < cols) ? (float)in[r * ldi + c] : 0.f;
+  }
+}
+
+__global__ __launch_bounds__(256) void split_bf16_2d_kernel(unsigned short* __restrict__ hi, unsigned short* __restrict__ lo,
+                                                            long ldo, const double* __restrict__ in, long ldi, long rows,
+                                                            long cols) {
+  const long total = rows * ldo;
+  for (long x = blockIdx.x * 256L + threadIdx.x; x < total; x += (long)gridDim.x * 256) {
+    const long r = x / ldo, c = x - r * ldo;
+    unsigned short h = 0, l = 0;
+    if (c < cols) {
+      const double d = in[r * ldi + c];
+      h = bf16_rne((float)d);
+      l = bf16_rne((float)(d - (double)bf16_to_f(h)));
+    }
+    hi[x] = h;
+    lo[x] = l;
+  }
+}
+
+// FP64 -> (hi, lo) bf16 planes: hi = RNE_bf16(RNE_fp32(x)), lo = RNE_bf16(RNE_fp32(x - hi)).
+__global__ __launch_bounds__(256) void split_bf16_kernel(unsigned short* __restrict__ hi, unsigned short* __restrict__ lo,
+                                                         const double* __restrict__ in, long n) {
+  for (long x = blockIdx.x * 256L + threadIdx.x; x < n; x += (long)gridDim.x * 256) {
+    const double d = in[x];
+    const unsigned short h = bf16_rne((float)d);
+    hi[x] = h;
+    lo[x] = bf16_rne((float)(d - (double)bf16_to_f(h)));
+  }
+}
+
+
+// ---------------------------------------------------------------------------------------
+// Split-BF16x3 on pre-split operands: A and B are (hi, lo) bf16 planes with padded leading
+// dimensions (multiples of 8 elements, zero padding), so every staging load is one 16-byte
+// chunk and no conversion happens in the kernel.  Workgroup tile 256 x 128, eight waves of
+// 64 x 64 (4 x 4 tiles of the 16x16x32 instruction), two LDS stages of K = 32.
+struct LPB {
+  int M, N, K;
+  const unsigned short* A;
+  long lda, sa2, a_plane;
+  const unsigned short* B;
+  long ldb, sb2, b_plane;
+  double* C;
+  long scm, scn, sc2;
+  double alpha, beta;
+  int tiles_m, tiles_n;
+  int chunk;
+};
+
+constexpr int BM2 = 256, BN2 = 128, BK2 = 32, NT2 = 512, PITCH2 = BK2 + 8;
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(NT2, 1) void gemm_bf16x3_kernel(LPB p) {
+  __shared__ __attribute__((aligned(16))) unsigned short As[2][2][BM2 * PITCH2];
+  __shared__ __attribute__((aligned(16))) unsigned short Bs[2][2][BN2 * PITCH2];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;  // 4 x 2 waves of 64 x 64
+  int tm, tn;
+  tile_of_lp(blockIdx.x, p.tiles_m, p.tiles_m * p.tiles_n, tm, tn);
+  const int m0 = tm * BM2, n0 = tn * BN2;
+  const int z = blockIdx.y;
+  const unsigned short* Ab = p.A + z * p.sa2;
+  const unsigned short* Bb = p.B + z * p.sb2;
+  double* Cb = p.C + z * p.sc2;
+
+  f4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+  const int nkt = (p.K + BK2 - 1) / BK2;
+  u4 ra[4], rb[2];
+  // Workgroup-uniform bases (scalar registers) plus 32-bit per-lane element offsets keep the
+  // address arithmetic out of the vector register budget.
+  const unsigned short* Arow = Ab + (long)m0 * p.lda;
+  const unsigned short* Brow = Bb + (long)n0 * p.ldb;
+  const int lda = (int)p.lda, ldb = (int)p.ldb;
+  // A: 256 rows x 4 chunks x 2 planes = 2048 chunks (4 per thread); B: 1024 chunks (2 per thread)
+  auto load = [&](int kt) {
+    const int k0 = kt * BK2;
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      const int c = tid + l * NT2;
+      const int plane = c >> 10, rem = c & 1023, row = rem >> 2, kc = (rem & 3) * 8;
+      const int gk = k0 + kc;
+      u4 v = u4{0u, 0u, 0u, 0u};
+      if (m0 + row < p.M && gk < lda)
+        v = *reinterpret_cast<const u4*>((plane ? Arow + p.a_plane : Arow) + (unsigned)(row * lda + gk));
+      ra[l] = v;
+    }
+#pragma unroll
+    for (int l = 0; l < 2; ++l) {
+      const int c = tid + l * NT2;
+      const int plane = c >> 9, rem = c & 511, row = rem >> 2, kc = (rem & 3) * 8;
+      const int gk = k0 + kc;
+      u4 v = u4{0u, 0u, 0u, 0u};
+      if (n0 + row < p.N && gk < ldb)
+        v = *reinterpret_cast<const u4*>((plane ? Brow + p.b_plane : Brow) + (unsigned)(row * ldb + gk));
+      rb[l] = v;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      const int c = tid + l * NT2;
+      const int plane = c >> 10, rem = c & 1023, row = rem >> 2, kc = (rem & 3) * 8;
+      *reinterpret_cast<u4*>(&As[buf][plane][row * PITCH2 + kc]) = ra[l];
+    }
+#pragma unroll
+    for (int l = 0; l < 2; ++l) {
+      const int c = tid + l * NT2;
+      const int plane = c >> 9, rem = c & 511, row = rem >> 2, kc = (rem & 3) * 8;
+      *reinterpret_cast<u4*>(&Bs[buf][plane][row * PITCH2 + kc]) = rb[l];
+    }
+  };
+  double* Cw = Cb + (long)(m0 + wm * 64) * p.scm + (long)(n0 + wn * 64) * p.scn;  // wave-uniform
+  const int scm = (int)p.scm, scn = (int)p.scn;
+  auto flush = [&](bool first) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int lm = i * 16 + 4 * (lane >> 4) + r, ln = j * 16 + (lane & 15);
+          if (m0 + wm * 64 + lm < p.M && n0 + wn * 64 + ln < p.N) {
+            double* c = Cw + (lm * scm + ln * scn);
+            const double v = p.alpha * (double)acc[i][j][r];
+            if (first)
+              *c = (p.beta == 0.0) ? v : v + p.beta * *c;
+            else
+              *c += v;
+          }
+          acc[i][j][r] = 0.f;
+        }
+  };
+
+  const int lr = lane & 15, lg = lane >> 4;
+  if (nkt > 0) {
+    load(0);
+    store(0);
+  }
+  __syncthreads();
+  for (int kc = 0; kc < nkt; kc += p.chunk) {
+    const int kend = min(nkt, kc + p.chunk);
+    for (int kt = kc; kt < kend; ++kt) {
+      const int cur = kt & 1;
+      if (kt + 1 < nkt) load(kt + 1);
+      // all A fragments stay in registers; B fragments are loaded one 16-column panel at a time
+      bf8 xa[4][2];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int off = (wm * 64 + i * 16 + lr) * PITCH2 + 8 * lg;
+        xa[i][0] = *reinterpret_cast<const bf8*>(&As[cur][0][off]);
+        xa[i][1] = *reinterpret_cast<const bf8*>(&As[cur][1][off]);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int off = (wn * 64 + j * 16 + lr) * PITCH2 + 8 * lg;
+        const bf8 bh = *reinterpret_cast<const bf8*>(&Bs[cur][0][off]);
+        const bf8 bl = *reinterpret_cast<const bf8*>(&Bs[cur][1][off]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[i][1], bh, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[i][0], bl, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[i][0], bh, acc[i][j], 0, 0, 0);
+        }
+      }
+      if (kt + 1 < nkt) store(cur ^ 1);
+      __syncthreads();
+    }
+    flush(kc == 0);
+  }
+  if (nkt == 0) flush(true);
+}
+
 // FP64 -> FP32 (round to nearest even), contiguous.
 __global__ __launch_bounds__(256) void cvt_f32_kernel(float* __restrict__ out, const double* __restrict__ in, long n) {
   for (long x = blockIdx.x * 256L + threadIdx.x; x < n; x += (long)gridDim.x * 256) out[x] = (float)in[x];
@@ -249,22 +434,84 @@ hipError_t cvt_f32(float* out, const double* in, long n, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t split_bf16(unsigned short* planes, const double* in, long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (bounds_checking() && !(range_ok(planes, 0, 2 * n - 1, 2, "split_bf16 out") && range_ok(in, 0, n - 1, 8, "split_bf16 in")))
+    return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  long g = (n + 255) / 256;
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL(split_bf16_kernel, dim3((unsigned)g), dim3(256), 0, s, planes, planes + n, in, n);
+  return hipGetLastError();
+}
+
+hipError_t to_lowp_2d(int prec, float* out, long ldo, const double* in, long ldi, long rows, long cols,
+                      hipStream_t s) {
+  const long total = rows * ldo;
+  if (total <= 0) return hipSuccess;
+  if (bounds_checking() && !(range_ok(out, 0, total - 1, 4, "lowp shadow") &&
+                             range_ok(in, 0, (rows - 1) * ldi + cols - 1, 8, "lowp source")))
+    return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  long g = (total + 255) / 256;
+  if (g > 8192) g = 8192;
+  if (prec == kPrecBF16x3) {
+    unsigned short* hi = reinterpret_cast<unsigned short*>(out);
+    hipLaunchKernelGGL(split_bf16_2d_kernel, dim3((unsigned)g), dim3(256), 0, s, hi, hi + total, ldo, in, ldi, rows, cols);
+  } else {
+    hipLaunchKernelGGL(cvt_f32_2d_kernel, dim3((unsigned)g), dim3(256), 0, s, out, ldo, in, ldi, rows, cols);
+  }
+  return hipGetLastError();
+}
+
 hipError_t gemm_lowp(const GemmLP& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.nb <= 0) return hipSuccess;
   if (g.K <= 0 || g.nb > 65535 || (g.prec != kPrecFP32 && g.prec != kPrecBF16x3)) return hipErrorInvalidValue;
+  const bool bf = (g.prec == kPrecBF16x3);
+  if (bf && ((g.lda | g.ldb | g.sa2 | g.sb2 | g.a_plane | g.b_plane) & 7)) return hipErrorInvalidValue;
+  if (bf && (g.lda < g.K || g.ldb < g.K)) return hipErrorInvalidValue;
   if (bounds_checking()) {
-    const long la = (long)(g.M - 1) * g.lda + (g.K - 1) + (long)(g.nb - 1) * g.sa2;
-    const long lb = (long)(g.N - 1) * g.ldb + (g.K - 1) + (long)(g.nb - 1) * g.sb2;
+    // bf16: every staged chunk stays inside its padded row, hi and lo planes
+    const long la = (long)(g.M - 1) * g.lda + (bf ? g.lda - 1 : g.K - 1) + (long)(g.nb - 1) * g.sa2;
+    const long lb = (long)(g.N - 1) * g.ldb + (bf ? g.ldb - 1 : g.K - 1) + (long)(g.nb - 1) * g.sb2;
     long lo = 0, hi = 0;
     const long dc[3] = {(long)(g.M - 1) * g.scm, (long)(g.N - 1) * g.scn, (long)(g.nb - 1) * g.sc2};
     for (long d : dc) {
       if (d < 0) lo += d; else hi += d;
     }
-    if (!(range_ok(g.A, 0, la, 4, "lowp A") && range_ok(g.B, 0, lb, 4, "lowp B") &&
-          range_ok(g.C, lo, hi, 8, "lowp C")))
+    const size_t el = bf ? 2 : 4;
+    if (!(range_ok(g.A, 0, la + (bf ? g.a_plane : 0), el, "lowp A") &&
+          range_ok(g.B, 0, lb + (bf ? g.b_plane : 0), el, "lowp B") && range_ok(g.C, lo, hi, 8, "lowp C")))
       return hipErrorInvalidValue;
   }
   if (dry_run()) return hipSuccess;
+  const int chunk = g.chunk_ktiles > 0 ? g.chunk_ktiles : 64;
+  if (bf) {
+    LPB p;
+    p.M = g.M;
+    p.N = g.N;
+    p.K = g.K;
+    p.A = reinterpret_cast<const unsigned short*>(g.A);
+    p.lda = g.lda;
+    p.sa2 = g.sa2;
+    p.a_plane = g.a_plane;
+    p.B = reinterpret_cast<const unsigned short*>(g.B);
+    p.ldb = g.ldb;
+    p.sb2 = g.sb2;
+    p.b_plane = g.b_plane;
+    p.C = g.C;
+    p.scm = g.scm;
+    p.scn = g.scn;
+    p.sc2 = g.sc2;
+    p.alpha = g.alpha;
+    p.beta = g.beta;
+    p.tiles_m = (g.M + BM2 - 1) / BM2;
+    p.tiles_n = (g.N + BN2 - 1) / BN2;
+    p.chunk = chunk;
+    dim3 grid(p.tiles_m * p.tiles_n, g.nb, 1);
+    hipLaunchKernelGGL(gemm_bf16x3_kernel, grid, dim3(NT2), 0, s, p);
+    return hipGetLastError();
+  }
   LP p;
   p.M = g.M;
   p.N = g.N;
@@ -283,12 +530,9 @@ hipError_t gemm_lowp(const GemmLP& g, hipStream_t s) {
   p.beta = g.beta;
   p.tiles_m = (g.M + BM - 1) / BM;
   p.tiles_n = (g.N + BN - 1) / BN;
-  p.chunk = g.chunk_ktiles > 0 ? g.chunk_ktiles : 64;
+  p.chunk = chunk;
   dim3 grid(p.tiles_m * p.tiles_n, g.nb, 1);
-  if (g.prec == kPrecBF16x3)
-    hipLaunchKernelGGL((gemm_lowp_kernel<true>), grid, dim3(NT), 0, s, p);
-  else
-    hipLaunchKernelGGL((gemm_lowp_kernel<false>), grid, dim3(NT), 0, s, p);
+  hipLaunchKernelGGL((gemm_lowp_kernel<false>), grid, dim3(NT), 0, s, p);
   return hipGetLastError();
 }
 

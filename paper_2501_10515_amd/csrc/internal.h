@@ -79,9 +79,17 @@ struct GemmLP {
   double alpha = 1.0, beta = 0.0;
   int prec = kPrecFP32;
   int chunk_ktiles = 64;
+  // BF16X3: A and B point at the hi planes; the lo planes start a_plane / b_plane bf16
+  // elements later (lda, ldb, sa2, sb2 in bf16 elements, multiples of 8)
+  long a_plane = 0, b_plane = 0;
 };
 hipError_t gemm_lowp(const GemmLP& g, hipStream_t s);
 hipError_t cvt_f32(float* out, const double* in, long n, hipStream_t s);
+// Low-precision shadow of a row-major FP64 matrix with the leading dimension padded to ldo
+// (a multiple of 8; padding zeroed).  FP32: one float array.  BF16X3: the same bytes hold two
+// bf16 planes, hi[rows*ldo] then lo[rows*ldo].
+hipError_t to_lowp_2d(int prec, float* out, long ldo, const double* in, long ldi, long rows, long cols, hipStream_t s);
+inline long lowp_ld(long k) { return (k + 7) / 8 * 8; }
 
 // ---------------------------------------------------------------------------------------
 // Element-wise kernels (elementwise.hip).

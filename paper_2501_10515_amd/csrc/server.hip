@@ -224,7 +224,6 @@ int admit(ascc_server* S, Request* R, double now) {
     if ((rc = capture(R, ASCC_PREC_FP64, &R->g_fp64))) return rc;
   }
   (void)ascc_set_precision(R->ints, R->lowp_phase ? S->opts.precision : ASCC_PREC_FP64);
-  std::vector<double>().swap(R->hB);  // host copy no longer needed
   R->t_admit = now;
   R->status = 2;
   return ASCC_OK;
@@ -250,6 +249,10 @@ int launch(Request* R) {
 bool consume(ascc_server* S, Request* R, double now) {
   const ascc_opts& o = S->opts.solve;
   const double* st = R->hstats;
+  if (R->iterations == 0) {  // the uploads ran before this iteration on the same stream
+    std::vector<double>().swap(R->hB);
+    std::vector<double>().swap(R->heps);
+  }
   R->iterations += 1;
   R->e_corr = st[0];
   R->de = st[1];
