@@ -13,10 +13,11 @@ timed region; the integral set (including the vvvv block) is built before it as 
 value = F_N6 / seconds-per-step in TFLOP/s, with the fixed algorithmic count
 F_N6(o,v) = 2[T(o)T(v)^2 + S(o)S(v)^2] + 4 o^4 v^2 + 10 o^3 v^3 (T(n) = n(n+1)/2, S(n) = n(n-1)/2).
 
-roofline: the particle-particle ladder contraction (phase pp_ladder, one batched launch), timed
-with HIP events on the stream it runs on during the timed region; achieved = its algorithmic
-flops per residual (2[T(o)T(v)^2 + S(o)S(v)^2]) / its mean duration, against the matrix peak of
-the arithmetic that carries it (FP64 78.6, FP32 157.3, split-BF16x3 2516.6/3 TFLOP/s).
+roofline: the particle-particle ladder contraction (phase pp_ladder: exactly one kernel launch),
+timed with HIP events on the stream it runs on during the timed region; achieved = its algorithmic
+flops per launch (2[T(o)T(v)^2 + S(o)S(v)^2] per state) / its mean duration, against the matrix
+peak of the arithmetic that carries it (FP64 78.6, FP32 157.3, split-BF16x3 2516.6/3 TFLOP/s);
+traffic = HBM bytes per launch from rocprofv3 counters (table below), null where not measured.
 
 variants (FP64 runs): the same workload and step with the other vvvv storage and with the N^6
 contractions in FP32 and in split-BF16x3 (fewer steps each), as TFLOP/s on the same F_N6 count
@@ -38,10 +39,35 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-from gen.synth_df import WORKLOADS, converging_sigma, make_system  # noqa: E402
+from gen.synth_df import WORKLOADS, converging_sigma, make_system, single_excitation_guesses  # noqa: E402
 
 METRIC = "N^6 residual TFLOP/s, mixed vs FP64 @|dE|<1e-6 Eh; solves/s + p99 latency"
 FP64_MFMA_PEAK_TFLOPS = 78.6
+LADDER_KERNEL = {"fp64": "gemm_f64_kernel", "fp32": "gemm_lowp_kernel", "bf16x3": "gemm_bf16x3_kernel"}
+LADDER_SOURCE = {"fp64": "gemm_f64.hip", "fp32": "gemm_lowp.hip", "bf16x3": "gemm_lowp.hip"}
+
+# HBM bytes per ladder launch from rocprofv3 FETCH_SIZE and WRITE_SIZE runs of this bench command,
+# each scaled by what the counter reads for a plain 2 GiB copy (fetch x2.000, write x1.000), keyed by
+# (workload, vvvv, precision) with the sha256 of the kernel source they were taken on: a kernel
+# changed since then reports null.
+TRAFFIC = {
+    ("o20v180q600", "full", "fp64"): (14.82e9, "132983eb39f6f5ef534c583f7444d2b5a90556416368972815aa9bac2d833264"),
+}
+
+
+def traffic_bytes(workload, vvvv, precision):
+    import hashlib
+
+    hit = TRAFFIC.get((workload, vvvv, precision))
+    if hit is None:
+        return None
+    src = os.path.join(ROOT, "paper_2501_10515_amd", "csrc", LADDER_SOURCE[precision])
+    try:
+        with open(src, "rb") as f:
+            digest = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    return hit[0] if digest == hit[1] else None
 
 
 def tri(n):
@@ -60,8 +86,12 @@ def ladder_flops(o, v):
     return 2 * (tri(o) * tri(v) ** 2 + stri(o) * stri(v) ** 2)
 
 
-def cpu_baseline(B, eps, o, v):
-    """One oracle residual evaluation on the host cores (bounded: a single residual)."""
+def cpu_baseline(B, eps, o, v, nstates=1):
+    """One oracle residual evaluation on the host cores (bounded: a single residual).
+
+    For several states sharing the integrals the rate is that of one state's residual (the
+    oracle has no batched form), which is what nstates independent evaluations would reach.
+    """
     from oracle import cs_ccsd
 
     try:
@@ -80,11 +110,17 @@ def cpu_baseline(B, eps, o, v):
     cs_ccsd.energy(B, fock, t1, t2)
     dt = time.perf_counter() - t0
     return {"value": f_n6(o, v) / dt / 1e12, "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"one residual + energy evaluation of the same workload ({dt:.1f} s, numpy FP64)"}
+            "sample": (f"one residual + energy evaluation of the same workload ({dt:.1f} s, numpy FP64)"
+                       + (f"; one of its {nstates} states" if nstates > 1 else ""))}
 
 
-def run_throughput(P, torch, B, eps, o, v, Q, vvvv, precision, steps, warmup):
-    """Time `steps` iterations (residual + update) from T = 0 after `warmup` untimed ones."""
+def run_throughput(P, torch, B, eps, o, v, Q, vvvv, precision, steps, warmup, guesses=None):
+    """Time `steps` iterations (residual + update) after `warmup` untimed ones.
+
+    guesses None: one state from T = 0.  Otherwise one state per (i, a) pair, T2 = 0 and
+    t1[i, a] = 0.5, all sharing the integral set: one ascc_residual_batch call (one ladder
+    launch over every state) and one ascc_update per state, each with its own DIIS history.
+    """
     dev = torch.device("cuda:0")
     mode = P.ASCC_VVVV_FULL if vvvv == "full" else P.ASCC_VVVV_PACKED
     prec = {"fp64": P.ASCC_PREC_FP64, "fp32": P.ASCC_PREC_FP32, "bf16x3": P.ASCC_PREC_BF16X3}[precision]
@@ -93,19 +129,29 @@ def run_throughput(P, torch, B, eps, o, v, Q, vvvv, precision, steps, warmup):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ints = P.ascc_build_ints(dB, deps, o, precision=prec, vvvv_mode=mode)
+    torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
     del dB
-    t1 = torch.zeros((o, v), dtype=torch.float64, device=dev)
-    t2 = torch.zeros((o, o, v, v), dtype=torch.float64, device=dev)
-    r1, r2 = torch.empty_like(t1), torch.empty_like(t2)
-    e = torch.empty(1, dtype=torch.float64, device=dev)
-    stats = torch.empty(8, dtype=torch.float64, device=dev)
-    diis = P.ascc_diis_create(ints, 8, 1)
+    nst = 1 if guesses is None else len(guesses)
+    t1s = [torch.zeros((o, v), dtype=torch.float64, device=dev) for _ in range(nst)]
+    t2s = [torch.zeros((o, o, v, v), dtype=torch.float64, device=dev) for _ in range(nst)]
+    for k, (i, a) in enumerate(guesses or []):
+        t1s[k][i, a] = 0.5
+    r1s, r2s = [torch.empty_like(t) for t in t1s], [torch.empty_like(t) for t in t2s]
+    e = torch.empty(nst, dtype=torch.float64, device=dev)
+    stats = torch.empty((nst, 8), dtype=torch.float64, device=dev)
+    diis = [P.ascc_diis_create(ints, 8, 1) for _ in range(nst)]
     stream = torch.cuda.current_stream()
+    if guesses is not None:
+        P.ascc_batch_reserve(ints, nst)
 
     def step():
-        P.ascc_residual(ints, t1, t2, r1, r2, e)
-        P.ascc_update(ints, diis, t1, t2, r1, r2, e, stats)
+        if guesses is None:
+            P.ascc_residual(ints, t1s[0], t2s[0], r1s[0], r2s[0], e)
+        else:
+            P.ascc_residual_batch(ints, t1s, t2s, r1s, r2s, e)
+        for k in range(nst):
+            P.ascc_update(ints, diis[k], t1s[k], t2s[k], r1s[k], r2s[k], e[k:k + 1], stats[k])
 
     for _ in range(warmup):
         step()
@@ -125,12 +171,15 @@ def run_throughput(P, torch, B, eps, o, v, Q, vvvv, precision, steps, warmup):
     phases = P.ascc_timing_read(ints)
     ms_step = ev0.elapsed_time(ev1) / steps
     st = stats.cpu().numpy()
-    diis.close()
+    for d in diis:
+        d.close()
     ints.close()
-    del t1, t2, r1, r2
+    del t1s, t2s, r1s, r2s
     torch.cuda.empty_cache()
-    return dict(ms_step=ms_step, wall=wall, build_s=build_s, phases=phases, steps=steps,
-                last={"E": float(st[0]), "rnorm": float(st[3]), "finite": bool(np.isfinite(st[3]))})
+    return dict(ms_step=ms_step, wall=wall, build_s=build_s, phases=phases, steps=steps, nstates=nst,
+                last={"E": [float(x) for x in st[:, 0]] if nst > 1 else float(st[0, 0]),
+                      "rnorm": [float(x) for x in st[:, 3]] if nst > 1 else float(st[0, 3]),
+                      "finite": bool(np.isfinite(st[:, 3]).all())})
 
 
 def serve_requests(nreq: int):
@@ -247,7 +296,7 @@ def main():
     ap.add_argument("--serve-precisions", default="", help="comma list of fp64,fp32,bf16x3 (default all)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+        print("bench.py measures one GPU only: there is no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
 
@@ -262,16 +311,20 @@ def main():
     wl = WORKLOADS[args.workload]
     o, v, Q, seed = wl["no"], wl["nv"], wl["naux"], wl["seed"]
     sigma = converging_sigma(v, Q) if args.generator == "converging" else 0.05
-    B, eps = make_system(o, v, Q, seed, sigma=sigma)
-    flops = f_n6(o, v)
+    rng = np.random.default_rng(seed)
+    B, eps = make_system(o, v, Q, seed, sigma=sigma, rng=rng)
+    nstates = wl.get("nstates", 1)
+    guesses = single_excitation_guesses(o, v, nstates, rng) if nstates > 1 else None
+    flops = nstates * f_n6(o, v)
 
-    main_run = run_throughput(P, torch, B, eps, o, v, Q, args.vvvv, args.precision, args.steps, args.warmup)
+    main_run = run_throughput(P, torch, B, eps, o, v, Q, args.vvvv, args.precision, args.steps, args.warmup,
+                              guesses)
     ms_step = main_run["ms_step"]
     value = flops / (ms_step * 1e-3) / 1e12
     phases = main_run["phases"]
     lad_ms, lad_n = phases["pp_ladder"]
     lad_avg = lad_ms / max(lad_n, 1)
-    achieved = ladder_flops(o, v) / (lad_avg * 1e-3) / 1e12
+    achieved = nstates * ladder_flops(o, v) / (lad_avg * 1e-3) / 1e12
     peak = {"fp64": FP64_MFMA_PEAK_TFLOPS, "fp32": 157.3, "bf16x3": 2516.6 / 3}[args.precision]
 
     out = {
@@ -288,15 +341,18 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": args.workload, "no": o, "nv": v, "naux": Q, "seed": seed, "generator": args.generator,
+            "workload": args.workload, "no": o, "nv": v, "naux": Q, "seed": seed, "nstates": nstates,
+            "generator": args.generator,
             "sigma": sigma, "vvvv": args.vvvv, "precision": args.precision,
-            "step": "ascc_residual + ascc_update (one Jacobi/DIIS iteration)", "flops_per_step_F_N6": flops,
+            "step": ("ascc_residual + ascc_update (one Jacobi/DIIS iteration)" if nstates == 1 else
+                     f"ascc_residual_batch over {nstates} states + {nstates} x ascc_update"),
+            "flops_per_step_F_N6": flops,
         },
         "roofline": {
-            "bound": "mfma", "kernel": "pp_ladder (gemm_f64_kernel, one batched launch)" if args.precision == "fp64"
-            else "pp_ladder (gemm_lowp_kernel, one batched launch)",
+            "bound": "mfma", "kernel": f"pp_ladder ({LADDER_KERNEL[args.precision]}, one launch)",
             "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-            "traffic": None, "launch_ms": round(lad_avg, 4), "algorithmic_flops_per_launch": ladder_flops(o, v),
+            "traffic": traffic_bytes(args.workload, args.vvvv, args.precision), "launch_ms": round(lad_avg, 4),
+            "algorithmic_flops_per_launch": nstates * ladder_flops(o, v),
         },
         "phases_ms_per_step": {k: round(ms / main_run["steps"], 4) for k, (ms, n) in phases.items() if n},
         "build_ints_s": round(main_run["build_s"], 3),
@@ -311,7 +367,8 @@ def main():
             if key in comp:
                 continue
             try:
-                r = run_throughput(P, torch, B, eps, o, v, Q, vm, pr, max(3, args.steps // 3), 2)
+                r = run_throughput(P, torch, B, eps, o, v, Q, vm, pr, max(3, args.steps // 3), min(2, args.warmup),
+                                   guesses)
                 rl, rn = r["phases"]["pp_ladder"]
                 comp[key] = {"tflops": round(flops / (r["ms_step"] * 1e-3) / 1e12, 3),
                              "ms_per_step": round(r["ms_step"], 4),
@@ -321,7 +378,7 @@ def main():
                 comp[key] = {"error": str(exc)[:200]}
         out["variants"] = comp
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(B, eps, o, v)
+        out["cpu_baseline"] = cpu_baseline(B, eps, o, v, nstates)
     print(json.dumps(out), flush=True)
 
 

@@ -206,11 +206,12 @@ struct ascc_diis {
 
 namespace {
 
-const char* const kPhaseNames[] = {"dress", "amp_views", "df_ints", "wz", "pp_ladder", "hh_ladder", "ring_y",
-                                   "ring_xz", "ring_p", "n5_terms", "assemble", "energy", "update"};
+const char* const kPhaseNames[] = {"dress",  "amp_views", "df_ints", "wz",      "pp_pack",  "pp_ladder",
+                                   "pp_unpack", "hh_ladder", "ring_y", "ring_xz", "ring_p", "n5_terms",
+                                   "assemble", "energy",    "update"};
 constexpr int kNumPhases = sizeof(kPhaseNames) / sizeof(kPhaseNames[0]);
-enum Phase { PH_DRESS, PH_AMP, PH_DF, PH_WZ, PH_LADDER, PH_HH, PH_RING_Y, PH_RING_XZ, PH_RING_P, PH_N5, PH_ASSEMBLE,
-             PH_ENERGY, PH_UPDATE };
+enum Phase { PH_DRESS, PH_AMP, PH_DF, PH_WZ, PH_PACK, PH_LADDER, PH_UNPACK, PH_HH, PH_RING_Y, PH_RING_XZ, PH_RING_P,
+             PH_N5, PH_ASSEMBLE, PH_ENERGY, PH_UPDATE };
 
 hipEvent_t take_event(ascc_ints* I) {
   if (!I->event_pool.empty()) {
@@ -525,21 +526,31 @@ int pp_ladder_states(ascc_ints* I, int S, const double* const* t2s, double* cons
   const long vv = I->vv, To = (long)o * (o + 1) / 2, Tv = (long)v * (v + 1) / 2;
   const long M = S * To;
   const bool lowp = I->cur_prec != ASCC_PREC_FP64;
+  // Phases: pp_pack (pair packing and low-precision operands), pp_ladder (the one contraction
+  // launch, nothing else), pp_unpack (scatter back to [i][j][a][b]).
   if (I->vvvv_mode == ASCC_VVVV_FULL) {
+    const long ld = lowp_ld(vv);
+    phase_begin(I, PH_PACK, s);
     for (int k = 0; k < S; ++k) HIPCHK(pack_pairs(Tp + k * To * vv, t2s[k], o, vv, s));
-    if (lowp) {
-      const long ld = lowp_ld(vv);
-      HIPCHK(shadow(I, Tpf, Tp, M, vv, s));
+    if (lowp) HIPCHK(shadow(I, Tpf, Tp, M, vv, s));
+    phase_end(I, s);
+    phase_begin(I, PH_LADDER, s);
+    if (lowp)
       HIPCHK(gemm_lowp(lp_nt(I, M, vv, vv, 1, Tpf, ld, 0, M * ld, I->Vf, ld, 0, vv * ld, Rp, vv, 0), s));
-    } else {
+    else
       HIPCHK(gemm_f64(gemm_rm(M, vv, vv, 1.0, Tp, vv, false, I->V, vv, true, 0.0, Rp, vv), s));
-    }
+    phase_end(I, s);
+    phase_begin(I, PH_UNPACK, s);
     for (int k = 0; k < S; ++k) HIPCHK(unpack_pairs(RLs[k], Rp + k * To * vv, o, v, s));
+    phase_end(I, s);
   } else {
+    const long ld = lowp_ld(Tv);
+    phase_begin(I, PH_PACK, s);
     for (int k = 0; k < S; ++k) HIPCHK(pack_tpm(Tp + k * To * Tv, Tp + (M + k * To) * Tv, t2s[k], o, v, s));
+    if (lowp) HIPCHK(shadow(I, Tpf, Tp, 2 * M, Tv, s));
+    phase_end(I, s);
+    phase_begin(I, PH_LADDER, s);
     if (lowp) {
-      const long ld = lowp_ld(Tv);
-      HIPCHK(shadow(I, Tpf, Tp, 2 * M, Tv, s));
       HIPCHK(gemm_lowp(lp_nt(I, M, Tv, Tv, 2, Tpf, ld, M * ld, 2 * M * ld, I->Vf, ld, Tv * ld, 2 * Tv * ld, Rp, Tv,
                              M * Tv), s));
     } else {
@@ -550,7 +561,10 @@ int pp_ladder_states(ascc_ints* I, int S, const double* const* t2s, double* cons
       g.nb2 = 2;
       HIPCHK(gemm_f64(g, s));  // no split-K: each row is summed the same way for any batch size
     }
+    phase_end(I, s);
+    phase_begin(I, PH_UNPACK, s);
     for (int k = 0; k < S; ++k) HIPCHK(unpack_rpm(RLs[k], Rp + k * To * Tv, Rp + (M + k * To) * Tv, o, v, s));
+    phase_end(I, s);
   }
   return ASCC_OK;
 }
@@ -560,8 +574,6 @@ int pp_ladder(ascc_ints* I, const double* t2, hipStream_t s) {
   return pp_ladder_states(I, 1, &t2, &RL, I->Tp, I->Rp, I->Tpf, s);
 }
 
-// One state's residual.  RLx == nullptr: the ladder is computed here into I->RL; otherwise RLx
-// already holds this state's particle-particle ladder (from a batched launch).
 size_t ints_footprint(long o, long v, long Q, int precision, int mode) {
   size_t off = 0;
   for (const auto& item : ints_plan(o, v, Q, mode))
@@ -575,6 +587,8 @@ size_t ints_footprint(long o, long v, long Q, int precision, int mode) {
   return align_up(off) + sizeof(double) * (size_t)std::max<long>(temp, 1);
 }
 
+// One state's residual.  RLx == nullptr: the ladder is computed here into I->RL; otherwise RLx
+// already holds this state's particle-particle ladder (from a batched launch).
 int residual_core(ascc_ints* I, const double* t1, const double* t2, double* r1, double* r2, double* e,
                   double* RLx, hipStream_t s) {
   double* RL = RLx ? RLx : I->RL;
@@ -652,9 +666,7 @@ int residual_core(ascc_ints* I, const double* t1, const double* t2, double* r1, 
 
   phase_end(I, s);
   // --- particle-particle ladder over the undressed (ac|bd), plus the hole-hole ladder
-  phase_begin(I, PH_LADDER, s);
   if (!RLx && (rc = pp_ladder(I, t2, s))) return rc;
-  phase_end(I, s);
   phase_begin(I, PH_HH, s);
   HIPCHK(mm(I, gemm_rm(oo, vv, oo, 1.0, I->chi, oo, false, t2, vv, false, 1.0, RL, vv), s));
   phase_end(I, s);
@@ -1233,9 +1245,7 @@ int ascc_residual_batch(ascc_ints* I, int nstates, const double* const* t1, cons
   user.add(e, sizeof(double) * nstates);
   std::vector<double*> RLs(nstates);
   for (int k = 0; k < nstates; ++k) RLs[k] = I->RL_all + (long)k * I->oovv;
-  phase_begin(I, PH_LADDER, s);
   int rc = pp_ladder_states(I, nstates, t2, RLs.data(), I->Tp_all, I->Rp_all, I->Tpf_all, s);
-  phase_end(I, s);
   if (rc) return rc;
   for (int k = 0; k < nstates && !rc; ++k) rc = residual_core(I, t1[k], t2[k], r1[k], r2[k], e + k, RLs[k], s);
   return rc;
