@@ -51,7 +51,7 @@ LADDER_SOURCE = {"fp64": "gemm_f64.hip", "fp32": "gemm_lowp.hip", "bf16x3": "gem
 # (workload, vvvv, precision) with the sha256 of the kernel source they were taken on: a kernel
 # changed since then reports null.
 TRAFFIC = {
-    ("o20v180q600", "full", "fp64"): (14.82e9, "132983eb39f6f5ef534c583f7444d2b5a90556416368972815aa9bac2d833264"),
+    ("o20v180q600", "full", "fp64"): (4.72e9, "6f8b9630d77823b544c9f3b95e7eb93892c6b64b3dd4a39a5014a9738b326860"),
 }
 
 

@@ -164,9 +164,10 @@ struct ascc_ints {
   double* KL;     // [2][ov][ov]: (ib|ja), 2(ia|jb) - (ib|ja)
   double* Lijab;  // [o][o][v][v]: 2(ia|jb) - (ib|ja)
   double* Gwz;    // [v][v][ov + o^2]: (kc|bd) at [c][d][k*v+b], (kc|ld) at [c][d][ov + k*o+l]
-  double* V;      // FULL: [v][v][v][v], (ac|bd) at [a][b][c][d]
+  double* V;      // FULL: [v^2][v^2], (ac|bd) at [R(a,b)][R(c,d)] (pair order: a <= b first, see pack_full)
                   // PACKED: [2][T(v)][T(v)], (ac|bd) +- (ad|bc) at [p(a,b)][p(c,d)], a <= b, c <= d
-  double *Tp, *Rp;  // ladder operands: FULL [T(o)][v^2]; PACKED [2][T(o)][T(v)]
+  double* pairtab;  // FULL: int32 [T(v)]: row R(b,a) of V for pair p(a,b), a <= b
+  double *Tp, *Rp;  // ladder operands [2][T(o)][T(v)]: t+- (pack_tpm) and R+- (unpack_rpm)
   // residual work arrays
   double *Bt, *Bh;               // [Q][n][n]
   double *ht, *Fh;               // [n][n]
@@ -261,6 +262,9 @@ uintptr_t fake_alloc(size_t bytes) {
   return p;
 }
 
+// Pair-row tables of a FULL integral set (see gemm_f64_ladder).
+inline int* pair_minus(const ascc_ints* I) { return reinterpret_cast<int*>(I->pairtab); }
+
 constexpr long kSplitKElems = 1L << 22;  // 32 MiB of split-K partials
 
 // Every device array of an integral set with its element count, in allocation order; the
@@ -274,7 +278,8 @@ std::vector<std::pair<double* ascc_ints::*, long>> ints_plan(long o, long v, lon
       {&ascc_ints::fov, ov},          {&ascc_ints::Bov, Q * ov},     {&ascc_ints::KL, 2 * ovov},
       {&ascc_ints::Lijab, oo * vv},   {&ascc_ints::Gwz, vv * (ov + oo)},
       {&ascc_ints::V, full ? vv * vv : 2 * Tv * Tv},
-      {&ascc_ints::Tp, full ? To * vv : 2 * To * Tv}, {&ascc_ints::Rp, full ? To * vv : 2 * To * Tv},
+      {&ascc_ints::pairtab, full ? Tv : 0},
+      {&ascc_ints::Tp, 2 * To * Tv},  {&ascc_ints::Rp, 2 * To * Tv},
       {&ascc_ints::Bt, Q * nn},       {&ascc_ints::Bh, Q * nn},      {&ascc_ints::ht, nn},
       {&ascc_ints::Fh, nn},           {&ascc_ints::J, Q},            {&ascc_ints::BvoT, Q * ov},
       {&ascc_ints::Boo, Q * oo},      {&ascc_ints::Bvv, Q * vv},     {&ascc_ints::G1, ovov},
@@ -292,13 +297,13 @@ std::vector<std::pair<double* ascc_ints::*, long>> ints_plan(long o, long v, lon
 std::vector<std::pair<float* ascc_ints::*, long>> lowp_plan(long o, long v, int mode) {
   const long ov = o * v, oo = o * o, vv = v * v, ovov = ov * ov;
   const long To = o * (o + 1) / 2, Tv = v * (v + 1) / 2;
-  const bool full = (mode == ASCC_VVVV_FULL);
+  (void)mode;  // both storage modes keep the packed halves in low precision
   // rows x padded leading dimension (lowp_ld); one float = one bf16 hi + one bf16 lo for BF16X3
   const long lvv = lowp_ld(vv), lTv = lowp_ld(Tv), lov = lowp_ld(ov);
   (void)ovov;
   return {
-      {&ascc_ints::Vf, full ? vv * lvv : 2 * Tv * lTv}, {&ascc_ints::GwzTf, (ov + oo) * lvv},
-      {&ascc_ints::KLf, 2 * ov * lov},                  {&ascc_ints::Tpf, full ? To * lvv : 2 * To * lTv},
+      {&ascc_ints::Vf, 2 * Tv * lTv}, {&ascc_ints::GwzTf, (ov + oo) * lvv},
+      {&ascc_ints::KLf, 2 * ov * lov}, {&ascc_ints::Tpf, 2 * To * lTv},
       {&ascc_ints::t2f, oo * lvv},                      {&ascc_ints::TUf, 2 * ov * lov},
       {&ascc_ints::XZf, 2 * ov * lov},
   };
@@ -310,7 +315,8 @@ long build_temp_elems(long o, long v, int mode, long* chunk_a) {
   long ac = std::max<long>(1, std::min<long>(v, (256L << 20) / std::max<long>(vvv, 1)));  // about 2 GB
   if (chunk_a) *chunk_a = ac;
   const long wtmp = o * v * v * v;
-  return (mode == ASCC_VVVV_FULL) ? wtmp : std::max(wtmp, ac * vvv);
+  (void)mode;
+  return std::max(wtmp, ac * vvv);
 }
 
 
@@ -516,56 +522,41 @@ hipError_t shadow(const ascc_ints* I, float* out, const double* in, long rows, l
 }
 
 // Particle-particle ladder RL_s[i][j][a][b] = sum_cd (t_s)_ij^cd (ac|bd) for S states in one
-// launch, computed for pairs i <= j only (RL_ji^ba = RL_ij^ab).  The S states' ladder rows are
-// stacked, so the vvvv operand is streamed once for all of them.  FULL: against the full (ac|bd)
-// matrix.  PACKED: against its (ab)-symmetric and antisymmetric halves, R+- = t+- V+-, both
-// halves in the same batched launch.  Tp/Rp hold [2][S*T(o)][T(v)] (PACKED) or [S*T(o)][v^2].
+// launch, computed for pairs i <= j only (RL_ji^ba = RL_ij^ab) and through the (ab)-symmetric and
+// antisymmetric halves: R+- = t+- V+- with t+-_ij^cd = (t_ij^cd +- t_ij^dc)/2 over c <= d and
+// V+-[(ab)][(cd)] = (ac|bd) +- (ad|bc) over a <= b (diagonal cd: (ac|bc) and 0), both halves in
+// one launch.  PACKED stores V+-; FULL stores the full (ac|bd) matrix in pair order, and its
+// halves are V[n][k] +- V[pm[n]][k], formed while the FP64 contraction stages them (and rounded
+// into the low-precision shadow); there the diagonal V+ is 2(ac|bc), so t+ carries t_ij^cc / 2.
+// The S states' rows are stacked, so the vvvv operand is streamed once for all of them.  Tp/Rp
+// hold [2][S*T(o)][T(v)].
 int pp_ladder_states(ascc_ints* I, int S, const double* const* t2s, double* const* RLs, double* Tp, double* Rp,
                      float* Tpf, hipStream_t s) {
   const int o = I->no, v = I->nv;
-  const long vv = I->vv, To = (long)o * (o + 1) / 2, Tv = (long)v * (v + 1) / 2;
+  const long To = (long)o * (o + 1) / 2, Tv = (long)v * (v + 1) / 2;
   const long M = S * To;
   const bool lowp = I->cur_prec != ASCC_PREC_FP64;
+  const bool full = I->vvvv_mode == ASCC_VVVV_FULL;
+  const long ld = lowp_ld(Tv);
   // Phases: pp_pack (pair packing and low-precision operands), pp_ladder (the one contraction
   // launch, nothing else), pp_unpack (scatter back to [i][j][a][b]).
-  if (I->vvvv_mode == ASCC_VVVV_FULL) {
-    const long ld = lowp_ld(vv);
-    phase_begin(I, PH_PACK, s);
-    for (int k = 0; k < S; ++k) HIPCHK(pack_pairs(Tp + k * To * vv, t2s[k], o, vv, s));
-    if (lowp) HIPCHK(shadow(I, Tpf, Tp, M, vv, s));
-    phase_end(I, s);
-    phase_begin(I, PH_LADDER, s);
-    if (lowp)
-      HIPCHK(gemm_lowp(lp_nt(I, M, vv, vv, 1, Tpf, ld, 0, M * ld, I->Vf, ld, 0, vv * ld, Rp, vv, 0), s));
-    else
-      HIPCHK(gemm_f64(gemm_rm(M, vv, vv, 1.0, Tp, vv, false, I->V, vv, true, 0.0, Rp, vv), s));
-    phase_end(I, s);
-    phase_begin(I, PH_UNPACK, s);
-    for (int k = 0; k < S; ++k) HIPCHK(unpack_pairs(RLs[k], Rp + k * To * vv, o, v, s));
-    phase_end(I, s);
-  } else {
-    const long ld = lowp_ld(Tv);
-    phase_begin(I, PH_PACK, s);
-    for (int k = 0; k < S; ++k) HIPCHK(pack_tpm(Tp + k * To * Tv, Tp + (M + k * To) * Tv, t2s[k], o, v, s));
-    if (lowp) HIPCHK(shadow(I, Tpf, Tp, 2 * M, Tv, s));
-    phase_end(I, s);
-    phase_begin(I, PH_LADDER, s);
-    if (lowp) {
-      HIPCHK(gemm_lowp(lp_nt(I, M, Tv, Tv, 2, Tpf, ld, M * ld, 2 * M * ld, I->Vf, ld, Tv * ld, 2 * Tv * ld, Rp, Tv,
-                             M * Tv), s));
-    } else {
-      Gemm g = gemm_rm(M, Tv, Tv, 1.0, Tp, Tv, false, I->V, Tv, true, 0.0, Rp, Tv);
-      g.sa2 = M * Tv;
-      g.sb2 = Tv * Tv;
-      g.sc2 = M * Tv;
-      g.nb2 = 2;
-      HIPCHK(gemm_f64(g, s));  // no split-K: each row is summed the same way for any batch size
-    }
-    phase_end(I, s);
-    phase_begin(I, PH_UNPACK, s);
-    for (int k = 0; k < S; ++k) HIPCHK(unpack_rpm(RLs[k], Rp + k * To * Tv, Rp + (M + k * To) * Tv, o, v, s));
-    phase_end(I, s);
-  }
+  phase_begin(I, PH_PACK, s);
+  const double dscale = full ? 0.5 : 1.0;  // full: the combined diagonal V+ is doubled
+  for (int k = 0; k < S; ++k) HIPCHK(pack_tpm(Tp + k * To * Tv, Tp + (M + k * To) * Tv, t2s[k], o, v, dscale, s));
+  if (lowp) HIPCHK(shadow(I, Tpf, Tp, 2 * M, Tv, s));
+  phase_end(I, s);
+  phase_begin(I, PH_LADDER, s);
+  if (lowp)
+    HIPCHK(gemm_lowp(lp_nt(I, M, Tv, Tv, 2, Tpf, ld, M * ld, 2 * M * ld, I->Vf, ld, Tv * ld, 2 * Tv * ld, Rp, Tv,
+                           M * Tv), s));
+  else if (full)
+    HIPCHK(gemm_f64_ladder((int)M, (int)Tv, Tp, I->V, I->vv, I->vv, pair_minus(I), Rp, s));
+  else
+    HIPCHK(gemm_f64_ladder((int)M, (int)Tv, Tp, I->V, Tv, 0, nullptr, Rp, s));
+  phase_end(I, s);
+  phase_begin(I, PH_UNPACK, s);
+  for (int k = 0; k < S; ++k) HIPCHK(unpack_rpm(RLs[k], Rp + k * To * Tv, Rp + (M + k * To) * Tv, o, v, s));
+  phase_end(I, s);
   return ASCC_OK;
 }
 
@@ -970,27 +961,26 @@ int build_constants(ascc_ints* I, const double* Bsrc, const double* fock, int fo
     g.nb2 = v;
     return mm(I, g, s);
   };
-  if (I->vvvv_mode == ASCC_VVVV_FULL) {
-    HIPCHK(vslab(0, v, I->V));
-  } else {
-    long ac = 1;
-    const long elems = build_temp_elems(o, v, I->vvvv_mode, &ac);
-    double* tmp = nullptr;
-    Pool tmp_alloc = sub_pool(I->pool);
-    int rc3 = dalloc(tmp_alloc, &tmp, (size_t)elems);
-    if (rc3) return rc3;
-    hipError_t e = hipSuccess;
-    for (int a0 = 0; a0 < v && e == hipSuccess; a0 += (int)ac) {
-      const int na = (int)std::min<long>(ac, v - a0);
-      e = vslab(a0, na, tmp);
-      if (e == hipSuccess) e = pack_vvvv(I->V, tmp, a0, a0 + na, v, s);
-    }
-    if (e == hipSuccess && !tmp_alloc.base) e = d_sync(s);  // carved temporaries need no wait
-    free_all(tmp_alloc);
-    if (e != hipSuccess) {
-      if (!(bounds_checking() && e == hipErrorInvalidValue)) set_error(std::string("building vvvv: ") + hipGetErrorString(e));
-      return ASCC_E_HIP;
-    }
+  // in chunks of a through a temporary: scattered to the full matrix in pair order, or packed
+  const bool full = I->vvvv_mode == ASCC_VVVV_FULL;
+  if (full) HIPCHK(pair_minus_rows(pair_minus(I), v, s));
+  long ac = 1;
+  const long elems = build_temp_elems(o, v, I->vvvv_mode, &ac);
+  double* tmp = nullptr;
+  Pool tmp_alloc = sub_pool(I->pool);
+  int rc3 = dalloc(tmp_alloc, &tmp, (size_t)elems);
+  if (rc3) return rc3;
+  hipError_t e = hipSuccess;
+  for (int a0 = 0; a0 < v && e == hipSuccess; a0 += (int)ac) {
+    const int na = (int)std::min<long>(ac, v - a0);
+    e = vslab(a0, na, tmp);
+    if (e == hipSuccess) e = full ? pack_full(I->V, tmp, a0, a0 + na, v, s) : pack_vvvv(I->V, tmp, a0, a0 + na, v, s);
+  }
+  if (e == hipSuccess && !tmp_alloc.base) e = d_sync(s);  // carved temporaries need no wait
+  free_all(tmp_alloc);
+  if (e != hipSuccess) {
+    if (!(bounds_checking() && e == hipErrorInvalidValue)) set_error(std::string("building vvvv: ") + hipGetErrorString(e));
+    return ASCC_E_HIP;
   }
   return ASCC_OK;
 }
@@ -1000,8 +990,9 @@ int build_lowp_shadows(ascc_ints* I, hipStream_t s) {
   const long vv = I->vv, ov = I->ov, oo = I->oo, wzl = ov + oo;
   const long Tv = (long)I->nv * (I->nv + 1) / 2;
 
-  if (I->vvvv_mode == ASCC_VVVV_FULL) {
-    HIPCHK(shadow(I, I->Vf, I->V, vv, vv, s));
+  if (I->vvvv_mode == ASCC_VVVV_FULL) {  // the packed halves, formed from the full matrix
+    const int prec = (I->cur_prec == ASCC_PREC_BF16X3) ? kPrecBF16x3 : kPrecFP32;
+    HIPCHK(to_lowp_pm(prec, I->Vf, lowp_ld(Tv), I->V, vv, vv, pair_minus(I), Tv, s));
   } else {
     HIPCHK(shadow(I, I->Vf, I->V, 2 * Tv, Tv, s));
   }
@@ -1213,8 +1204,7 @@ int ascc_batch_reserve(ascc_ints* I, int max_states) {
   I->Tp_all = I->Rp_all = I->RL_all = nullptr;
   I->Tpf_all = nullptr;
   const long o = I->no, v = I->nv, To = o * (o + 1) / 2, Tv = v * (v + 1) / 2, vv = I->vv;
-  const long rows = (I->vvvv_mode == ASCC_VVVV_FULL) ? To * vv : 2 * To * Tv;
-  const long lrows = (I->vvvv_mode == ASCC_VVVV_FULL) ? To * lowp_ld(vv) : 2 * To * lowp_ld(Tv);
+  const long rows = 2 * To * Tv, lrows = 2 * To * lowp_ld(Tv);
   int rc = dalloc(I->batch, &I->Tp_all, (size_t)(max_states * rows));
   if (!rc) rc = dalloc(I->batch, &I->Rp_all, (size_t)(max_states * rows));
   if (!rc) rc = dalloc(I->batch, &I->RL_all, (size_t)(max_states * I->oovv));

@@ -371,33 +371,10 @@ __global__ __launch_bounds__(kThreads) void update_stage3(double* t1, double* t2
 // Pair index of i <= j among n: pidx(i, j) = i*n - i*(i-1)/2 + (j - i)  (row-major upper triangle).
 __device__ __forceinline__ long pidx(long i, long j, long n) { return i * n - i * (i - 1) / 2 + (j - i); }
 
-// out[p(i,j)][x] = in[i][j][x] for i <= j (rows of a pair-symmetric array).
-__global__ __launch_bounds__(kThreads) void pack_pairs_kernel(double* __restrict__ out, const double* __restrict__ in,
-                                                             int o, long L) {
-  const int i = blockIdx.y / o, j = blockIdx.y % o;
-  if (i > j) return;
-  const double* src = in + ((long)i * o + j) * L;
-  double* dst = out + pidx(i, j, o) * L;
-  for (long x = blockIdx.x * (long)blockDim.x + threadIdx.x; x < L; x += (long)gridDim.x * blockDim.x) dst[x] = src[x];
-}
-
-// RL[i][j][a][b] = Rp[p(i,j)][a][b] (i <= j), Rp[p(j,i)][b][a] (i > j).
-__global__ __launch_bounds__(kThreads) void unpack_pairs_kernel(double* __restrict__ RL, const double* __restrict__ Rp,
-                                                               int o, int v) {
-  const int i = blockIdx.y / o, j = blockIdx.y % o;
-  const long vv = (long)v * v;
-  double* dst = RL + ((long)i * o + j) * vv;
-  const double* src = Rp + (i <= j ? pidx(i, j, o) : pidx(j, i, o)) * vv;
-  for (long x = blockIdx.x * (long)blockDim.x + threadIdx.x; x < vv; x += (long)gridDim.x * blockDim.x) {
-    const int a = x / v, b = x % v;
-    dst[x] = (i <= j) ? src[x] : src[(long)b * v + a];
-  }
-}
-
 // t+-[p(i,j)][p(c,d)] for i <= j, c <= d:
-//   t+ = (t_ij^cd + t_ij^dc)/2 (c < d), t_ij^cc (c = d);  t- = (t_ij^cd - t_ij^dc)/2 (c < d), 0 (c = d).
+//   t+ = (t_ij^cd + t_ij^dc)/2 (c < d), dscale * t_ij^cc (c = d);  t- = (t_ij^cd - t_ij^dc)/2 (c < d), 0 (c = d).
 __global__ __launch_bounds__(kThreads) void pack_tpm_kernel(double* __restrict__ tplus, double* __restrict__ tminus,
-                                                           const double* __restrict__ t2, int o, int v) {
+                                                           const double* __restrict__ t2, int o, int v, double dscale) {
   const int i = blockIdx.y / o, j = blockIdx.y % o;
   if (i > j) return;
   const long Tv = (long)v * (v + 1) / 2, vv = (long)v * v;
@@ -410,7 +387,7 @@ __global__ __launch_bounds__(kThreads) void pack_tpm_kernel(double* __restrict__
     if (c > d) continue;
     const double a = src[x], b = src[(long)d * v + c];
     const long k = pidx(c, d, v);
-    plus[k] = (c == d) ? a : 0.5 * (a + b);
+    plus[k] = (c == d) ? dscale * a : 0.5 * (a + b);
     minus[k] = (c == d) ? 0.0 : 0.5 * (a - b);
   }
 }
@@ -454,6 +431,32 @@ __global__ __launch_bounds__(kThreads) void pack_vvvv_kernel(double* __restrict_
     const long k = pidx(c, d, v);
     plus[k] = (c == d) ? w1 : w1 + w2;
     minus[k] = (c == d) ? 0.0 : w1 - w2;
+  }
+}
+
+// Pair order of the full (ac|bd) storage: R(a,b) = p(a,b) for a <= b, T(v) + strict pair index of
+// (b,a) for a > b; pm[n] = R(b,a) for pair n = (a <= b) (n itself when a = b).
+__device__ __forceinline__ long pair_order(long a, long b, long v) {
+  const long Tv = v * (v + 1) / 2;
+  return a <= b ? pidx(a, b, v) : Tv + pidx(b, a, v) - (b + 1);
+}
+
+__global__ __launch_bounds__(kThreads) void pair_minus_rows_kernel(int* __restrict__ pm, int v) {
+  const int a = blockIdx.x * kThreads + threadIdx.x;
+  if (a >= v) return;
+  for (int b = a; b < v; ++b) pm[pidx(a, b, v)] = (int)pair_order(b, a, v);
+}
+
+// Full (ac|bd) in pair order: V[R(a,b)][R(c,d)] = W[a - a0][b][c][d] for a in [a0, a1).
+__global__ __launch_bounds__(kThreads) void pack_full_kernel(double* __restrict__ V, const double* __restrict__ W,
+                                                            int a0, int v) {
+  const int a = a0 + blockIdx.y / v, b = blockIdx.y % v;
+  const long vv = (long)v * v;
+  const double* src = W + ((long)(a - a0) * v + b) * vv;
+  double* dst = V + pair_order(a, b, v) * vv;
+  for (long x = blockIdx.x * (long)blockDim.x + threadIdx.x; x < vv; x += (long)gridDim.x * blockDim.x) {
+    const int c = x / v, d = x % v;
+    dst[pair_order(c, d, v)] = src[x];
   }
 }
 
@@ -583,34 +586,14 @@ hipError_t energy(double* e, double* partial, const double* t1, const double* t2
 
 static bool chk(const void* p, long n, const char* what) { return range_ok(p, 0, n - 1, 8, what); }
 
-hipError_t pack_pairs(double* out, const double* in, int o, long L, hipStream_t s) {
-  const long To = (long)o * (o + 1) / 2;
-  if (bounds_checking() && !(chk(out, To * L, "pack_pairs out") && chk(in, (long)o * o * L, "pack_pairs in")))
-    return hipErrorInvalidValue;
-  if (dry_run()) return hipSuccess;
-  dim3 grid((unsigned)std::min<long>((L + kThreads - 1) / kThreads, 64), o * o);
-  hipLaunchKernelGGL(pack_pairs_kernel, grid, dim3(kThreads), 0, s, out, in, o, L);
-  return hipGetLastError();
-}
-
-hipError_t unpack_pairs(double* RL, const double* Rp, int o, int v, hipStream_t s) {
-  const long To = (long)o * (o + 1) / 2, vv = (long)v * v;
-  if (bounds_checking() && !(chk(RL, (long)o * o * vv, "unpack_pairs RL") && chk(Rp, To * vv, "unpack_pairs Rp")))
-    return hipErrorInvalidValue;
-  if (dry_run()) return hipSuccess;
-  dim3 grid((unsigned)std::min<long>((vv + kThreads - 1) / kThreads, 64), o * o);
-  hipLaunchKernelGGL(unpack_pairs_kernel, grid, dim3(kThreads), 0, s, RL, Rp, o, v);
-  return hipGetLastError();
-}
-
-hipError_t pack_tpm(double* tplus, double* tminus, const double* t2, int o, int v, hipStream_t s) {
+hipError_t pack_tpm(double* tplus, double* tminus, const double* t2, int o, int v, double dscale, hipStream_t s) {
   const long To = (long)o * (o + 1) / 2, Tv = (long)v * (v + 1) / 2, vv = (long)v * v;
   if (bounds_checking() && !(chk(tplus, To * Tv, "pack_tpm plus") && chk(tminus, To * Tv, "pack_tpm minus") &&
                              chk(t2, (long)o * o * vv, "pack_tpm t2")))
     return hipErrorInvalidValue;
   if (dry_run()) return hipSuccess;
   dim3 grid((unsigned)std::min<long>((vv + kThreads - 1) / kThreads, 64), o * o);
-  hipLaunchKernelGGL(pack_tpm_kernel, grid, dim3(kThreads), 0, s, tplus, tminus, t2, o, v);
+  hipLaunchKernelGGL(pack_tpm_kernel, grid, dim3(kThreads), 0, s, tplus, tminus, t2, o, v, dscale);
   return hipGetLastError();
 }
 
@@ -633,6 +616,26 @@ hipError_t pack_vvvv(double* Vp, const double* W, int a0, int a1, int v, hipStre
   if (dry_run()) return hipSuccess;
   dim3 grid((unsigned)std::min<long>((vv + kThreads - 1) / kThreads, 64), (a1 - a0) * v);
   hipLaunchKernelGGL(pack_vvvv_kernel, grid, dim3(kThreads), 0, s, Vp, W, a0, v);
+  return hipGetLastError();
+}
+
+hipError_t pair_minus_rows(int* pm, int v, hipStream_t s) {
+  const long Tv = (long)v * (v + 1) / 2;
+  if (v <= 0) return hipSuccess;
+  if (bounds_checking() && !range_ok(pm, 0, Tv - 1, sizeof(int), "pair rows")) return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  hipLaunchKernelGGL(pair_minus_rows_kernel, dim3((v + kThreads - 1) / kThreads), dim3(kThreads), 0, s, pm, v);
+  return hipGetLastError();
+}
+
+hipError_t pack_full(double* V, const double* W, int a0, int a1, int v, hipStream_t s) {
+  const long vv = (long)v * v;
+  if (a1 <= a0) return hipSuccess;
+  if (bounds_checking() && !(chk(V, vv * vv, "pack_full out") && chk(W, (long)(a1 - a0) * v * vv, "pack_full in")))
+    return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  dim3 grid((unsigned)std::min<long>((vv + kThreads - 1) / kThreads, 64), (a1 - a0) * v);
+  hipLaunchKernelGGL(pack_full_kernel, grid, dim3(kThreads), 0, s, V, W, a0, v);
   return hipGetLastError();
 }
 

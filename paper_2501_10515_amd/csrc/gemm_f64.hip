@@ -1,11 +1,11 @@
-// Strided, batched FP64 GEMM on the CDNA4 matrix cores (v_mfma_f64_16x16x4_f64).
+// Strided, batched FP64 GEMM on the CDNA4 matrix cores.
 //
 // C_z(m,n) = alpha * sum_r sum_k A_{z,r}(m,k) B_{z,r}(k,n) + beta * C_z(m,n)
 //
 // Every contraction of the residual is expressed through this one kernel family: the
 // operands are arbitrary strided 2-D views (a permuted slice of T2 or of an integral block
 // is just another pair of strides), tiles are staged through LDS, and each wave64 owns a
-// (BM/WM) x (BN/WN) block of 16x16 MFMA accumulators.
+// (BM/WM) x (BN/WN) block of the output.
 //
 // The inner product uses v_mfma_f64_4x4x4_f64 (four independent 4x4x4 products per wave64),
 // which sustains about 1.6x the FP64 rate of the 16x16x4 form on gfx950 (measured with register
@@ -13,6 +13,10 @@
 // q = (l%16)/4, supplies A_q(l%4, l/16) and B_q(l/16, l%4), and receives D_q(l/16, l%4); the
 // CBSZ/ABID broadcast fields have no effect on this instruction, so operands are arranged in
 // registers instead (see the main loop).
+//
+// The particle-particle ladder has its own entry point (gemm_f64_ladder): 256 x 128 tiles when
+// the pair dimension fits them, and optionally the symmetric/antisymmetric vvvv combinations
+// formed while staging from the stored full (ac|bd) matrix.
 #include <algorithm>
 
 #include "internal.h"
@@ -34,17 +38,25 @@ struct GP {
   int tiles_m, tiles_n;
   int split, it_per_split;  // split-K: slices of the (nred x K-tile) iteration space
   double* part;             // partial tiles [split][nb1*nb2][M][N] when split > 1
+  const int* pm;            // pair-combined B (ladder): second row of pair n
 };
 
-// Workgroup-to-tile map that gives each of the 8 XCDs (workgroups are dispatched to them
-// round-robin) one contiguous range of tiles, M-tile fastest, so the workgroups that share a
-// B panel run on the same XCD and hit the same L2.
-__device__ __forceinline__ void tile_of(int bid, int tiles_m, int total, int& tm, int& tn) {
+// Workgroup-to-tile map.  Workgroups are dispatched to the 8 XCDs round-robin; each XCD gets
+// one contiguous range of tiles, walked in groups of kGroupM M-tiles (M fastest inside a group)
+// so that the workgroups resident on one XCD at a time cover a compact block of C and share
+// both A and B panels in that XCD's L2.
+constexpr int kGroupM = 8;
+__device__ __forceinline__ void tile_of(int bid, int tiles_m, int tiles_n, int& tm, int& tn) {
+  const int total = tiles_m * tiles_n;
   const int q = total >> 3, rem = total & 7;
   const int x = bid & 7, local = bid >> 3;
-  const int tile = x * q + min(x, rem) + local;
-  tm = tile % tiles_m;
-  tn = tile / tiles_m;
+  const int t = x * q + min(x, rem) + local;
+  const int per = kGroupM * tiles_n;
+  const int g = t / per, first = g * kGroupM;
+  const int gs = min(tiles_m - first, kGroupM);
+  const int r = t - g * per;
+  tm = first + r % gs;
+  tn = r / gs;
 }
 
 #ifndef ASCC_GEMM_BK
@@ -54,14 +66,17 @@ __device__ __forceinline__ void tile_of(int bid, int tiles_m, int total, int& tm
 #define ASCC_GEMM_MINBLOCKS 2  // workgroups per CU the 128x128 tile is register-budgeted for
 #endif
 
-template <int BM, int BN, int BK, int WM, int WN, bool AMF, bool BNF>
-__global__ __launch_bounds__(WM* WN * 64, (WM * WN >= 4) ? ASCC_GEMM_MINBLOCKS : 4) void gemm_f64_kernel(GP p) {
+// PM: B is pair-combined (ladder against the full (ac|bd) in pair order): for batch z2 = 0 (+)
+// or 1 (-), B(k, n) = V[n][k] +- V[pm[n]][k] (rows of V at stride sbn).
+template <int BM, int BN, int BK, int WM, int WN, bool AMF, bool BNF, bool PM = false>
+__global__ __launch_bounds__(WM* WN * 64, (WM * WN >= 8) ? 1 : (WM * WN >= 4) ? ASCC_GEMM_MINBLOCKS : 4) void gemm_f64_kernel(GP p) {
   constexpr int NT = WM * WN * 64;
   constexpr int TM = BM / WM, TN = BN / WN;
   constexpr int RB = TM / 4, CP = TN / 16;
   constexpr int LA = BM * BK / NT, LB = BK * BN / NT;
   constexpr int PA = BM + 1, PB = BN + 1;  // +1 double: conflict-free transposing stores
   static_assert(RB >= 1 && CP >= 1 && LA >= 1 && LB >= 1 && TM % 4 == 0 && TN % 16 == 0, "tile config");
+  static_assert(!PM || (!BNF && NT % BK == 0), "pair-combined B is staged k-fast");
   __shared__ double As[2][BK * PA];
   __shared__ double Bs[2][BK * PB];
 
@@ -71,10 +86,19 @@ __global__ __launch_bounds__(WM* WN * 64, (WM * WN >= 4) ? ASCC_GEMM_MINBLOCKS :
 
   int tm, tn;
   const int ntiles = p.tiles_m * p.tiles_n;
-  const int slice = blockIdx.x / ntiles;
-  tile_of(blockIdx.x - slice * ntiles, p.tiles_m, ntiles, tm, tn);
+  int bid = blockIdx.x, z2 = blockIdx.y;
+  if constexpr (PM) {
+    // Both halves of a tile read the same V rows: they are dispatched back to back to the same
+    // XCD (workgroups b and b + 8 share an XCD), so the second one finds them in L2.
+    const int x = bid & 7, local = bid >> 3;
+    z2 = local & 1;
+    bid = ((local >> 1) << 3) | x;
+    if (bid >= ntiles) return;  // padding of the grid to whole groups of 8
+  }
+  const int slice = bid / ntiles;
+  tile_of(bid - slice * ntiles, p.tiles_m, p.tiles_n, tm, tn);
   const int m0 = tm * BM, n0 = tn * BN;
-  const int z1 = blockIdx.z, z2 = blockIdx.y;
+  const int z1 = blockIdx.z;
   const double* Ab = p.A + z1 * p.sa1 + z2 * p.sa2;
   const double* Bb = p.B + z1 * p.sb1 + z2 * p.sb2;
   double* Cb = p.C + z1 * p.sc1 + z2 * p.sc2;
@@ -92,6 +116,18 @@ __global__ __launch_bounds__(WM* WN * 64, (WM * WN >= 4) ? ASCC_GEMM_MINBLOCKS :
   const int it_end = min(nkt * p.nred, it_begin + p.it_per_split);
 
   double ra[LA], rb[LB];
+  // pair-combined B: the two V rows of each staged pair n are fixed for the whole K loop
+  const double* pva[PM ? LB : 1];
+  const double* pvb[PM ? LB : 1];
+  if constexpr (PM) {
+#pragma unroll
+    for (int l = 0; l < LB; ++l) {
+      const int gn = n0 + (tid + l * NT) / BK;
+      pva[l] = gn < p.N ? Bb + (long)gn * p.sbn : nullptr;
+      pvb[l] = gn < p.N ? Bb + (long)p.pm[gn] * p.sbn : nullptr;
+    }
+  }
+  const bool minus = PM && z2 == 1;
   auto load = [&](int it) {
     const int r = it / nkt, k0 = (it % nkt) * BK;
     const double* Ar = Ab + r * p.sar;
@@ -104,13 +140,27 @@ __global__ __launch_bounds__(WM* WN * 64, (WM * WN >= 4) ? ASCC_GEMM_MINBLOCKS :
       const int gm = m0 + m, gk = k0 + k;
       ra[l] = (gm < p.M && gk < p.K) ? Ar[gm * p.sam + gk * p.sak] : 0.0;
     }
+    if constexpr (PM) {
+      const int gk = k0 + tid % BK;  // the same k for every element this thread stages
 #pragma unroll
-    for (int l = 0; l < LB; ++l) {
-      const int e = tid + l * NT;
-      const int n = BNF ? (e % BN) : (e / BK);
-      const int k = BNF ? (e / BN) : (e % BK);
-      const int gn = n0 + n, gk = k0 + k;
-      rb[l] = (gn < p.N && gk < p.K) ? Br[gk * p.sbk + gn * p.sbn] : 0.0;
+      for (int l = 0; l < LB; ++l) {
+        double x = 0.0;
+        if (pva[l] && gk < p.K) {
+          const double u = pva[l][gk], w = pvb[l][gk];
+          x = minus ? u - w : u + w;
+        }
+        rb[l] = x;
+      }
+      (void)Br;
+    } else {
+#pragma unroll
+      for (int l = 0; l < LB; ++l) {
+        const int e = tid + l * NT;
+        const int n = BNF ? (e % BN) : (e / BK);
+        const int k = BNF ? (e / BN) : (e % BK);
+        const int gn = n0 + n, gk = k0 + k;
+        rb[l] = (gn < p.N && gk < p.K) ? Br[gk * p.sbk + gn * p.sbn] : 0.0;
+      }
     }
   };
   auto store = [&](int buf) {
@@ -232,6 +282,24 @@ hipError_t launch_cfg(const GP& p0, bool amf, bool bnf, int nb1, double* ws, lon
   return hipGetLastError();
 }
 
+// Ladder: both halves (grid.y = 2), no split-K, A/B staged k-fast.
+template <int BM, int WM>
+hipError_t launch_ladder(GP p, bool pm, hipStream_t s) {
+  p.tiles_m = (p.M + BM - 1) / BM;
+  p.tiles_n = (p.N + 127) / 128;
+  p.split = 1;
+  p.it_per_split = (p.K + ASCC_GEMM_BK - 1) / ASCC_GEMM_BK;
+  p.part = nullptr;
+  const int tiles = p.tiles_m * p.tiles_n;
+  // pair-combined: the two halves interleave in grid.x (see the kernel), padded to groups of 8
+  dim3 grid(pm ? 2 * ((tiles + 7) / 8 * 8) : tiles, pm ? 1 : 2, 1), block(WM * 2 * 64);
+  if (pm)
+    hipLaunchKernelGGL((gemm_f64_kernel<BM, 128, ASCC_GEMM_BK, WM, 2, false, false, true>), grid, block, 0, s, p);
+  else
+    hipLaunchKernelGGL((gemm_f64_kernel<BM, 128, ASCC_GEMM_BK, WM, 2, false, false, false>), grid, block, 0, s, p);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 Gemm gemm_rm(int M, int N, int K, double alpha, const double* A, long lda, bool ta, const double* B, long ldb,
@@ -319,6 +387,7 @@ hipError_t gemm_f64(const Gemm& g, hipStream_t s) {
   p.beta = g.beta;
   p.nb2 = g.nb2;
   p.nred = g.nred;
+  p.pm = nullptr;
   // Global-load order: an operand whose m (n) stride is 1 is read m-fast (n-fast).
   const bool amf = (g.sam == 1 && g.sak != 1);
   const bool bnf = (g.sbn == 1) || (g.sbk != 1);
@@ -327,6 +396,48 @@ hipError_t gemm_f64(const Gemm& g, hipStream_t s) {
   const long tiles64 = (long)((g.M + 63) / 64) * ((g.N + 63) / 64) * nbatch;
   if (g.M >= 48 && g.N >= 48 && tiles64 >= 128) return launch_cfg<64, 64, 16, 2, 2>(p, amf, bnf, g.nb1, g.ws, g.ws_elems, s);
   return launch_cfg<32, 32, 16, 1, 1>(p, amf, bnf, g.nb1, g.ws, g.ws_elems, s);
+}
+
+hipError_t gemm_f64_ladder(int M, int Tv, const double* A, const double* V, long ldv, long vrows, const int* pm,
+                           double* C, hipStream_t s) {
+  if (M <= 0 || Tv <= 0) return hipSuccess;
+  const bool pmode = pm != nullptr;
+  if (pmode && (ldv < Tv || vrows < Tv)) return hipErrorInvalidValue;
+  const long half = (long)M * Tv;
+  if (bounds_checking()) {
+    const long vlast = pmode ? (vrows - 1) * ldv + Tv - 1 : 2L * Tv * Tv - 1;
+    if (!(range_ok(A, 0, 2 * half - 1, sizeof(double), "ladder A") && range_ok(C, 0, 2 * half - 1, sizeof(double), "ladder C") &&
+          range_ok(V, 0, vlast, sizeof(double), "ladder V") &&
+          (!pmode || range_ok(pm, 0, Tv - 1, sizeof(int), "ladder pair rows"))))
+      return hipErrorInvalidValue;
+  }
+  if (dry_run()) return hipSuccess;
+  GP p{};
+  p.M = M;
+  p.N = Tv;
+  p.K = Tv;
+  p.A = A;
+  p.sam = Tv;
+  p.sak = 1;
+  p.sa2 = half;
+  p.B = V;
+  p.sbk = 1;
+  p.sbn = pmode ? ldv : Tv;
+  p.sb2 = pmode ? 0 : (long)Tv * Tv;
+  p.C = C;
+  p.scm = Tv;
+  p.scn = 1;
+  p.sc2 = half;
+  p.alpha = 1.0;
+  p.beta = 0.0;
+  p.nb2 = 2;
+  p.nred = 1;
+  p.pm = pm;
+  // 256-row tiles read the vvvv operand once per 256 pair rows; take them unless their row
+  // padding costs more than the 128-row tiles' second pass
+  const long pad256 = (M + 255L) / 256 * 256, pad128 = (M + 127L) / 128 * 128;
+  if (pad256 * 19 <= pad128 * 20) return launch_ladder<256, 4>(p, pmode, s);
+  return launch_ladder<128, 2>(p, pmode, s);
 }
 
 }  // namespace ascc

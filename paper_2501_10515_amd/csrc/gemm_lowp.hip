@@ -258,6 +258,33 @@ __global__ __launch_bounds__(256) void split_bf16_2d_kernel(unsigned short* __re
   }
 }
 
+// Low-precision shadow of the vvvv halves formed from the full (ac|bd) matrix in pair order (rows
+// at stride ldv): row r = h*Tv + n (h = 0: +, 1: -), column k < Tv, zero padding up to ldo; in FP64
+// x = V[n][k] +- V[pm[n]][k], then rounded as to_lowp_2d rounds (FP32, or bf16 hi/lo planes).
+template <bool BF>
+__global__ __launch_bounds__(256) void lowp_pm_kernel(unsigned short* __restrict__ hi, unsigned short* __restrict__ lo,
+                                                      float* __restrict__ out, long ldo, const double* __restrict__ V,
+                                                      long ldv, const int* __restrict__ pm, long Tv) {
+  const long total = 2 * Tv * ldo;
+  for (long x = blockIdx.x * 256L + threadIdx.x; x < total; x += (long)gridDim.x * 256) {
+    const long r = x / ldo, c = x - r * ldo;
+    double d = 0.0;
+    if (c < Tv) {
+      const bool minus = r >= Tv;
+      const long n = minus ? r - Tv : r;
+      const double u = V[n * ldv + c], w = V[(long)pm[n] * ldv + c];
+      d = minus ? u - w : u + w;
+    }
+    if (BF) {
+      const unsigned short h = bf16_rne((float)d);
+      hi[x] = h;
+      lo[x] = bf16_rne((float)(d - (double)bf16_to_f(h)));
+    } else {
+      out[x] = (float)d;
+    }
+  }
+}
+
 // FP64 -> (hi, lo) bf16 planes: hi = RNE_bf16(RNE_fp32(x)), lo = RNE_bf16(RNE_fp32(x - hi)).
 __global__ __launch_bounds__(256) void split_bf16_kernel(unsigned short* __restrict__ hi, unsigned short* __restrict__ lo,
                                                          const double* __restrict__ in, long n) {
@@ -533,6 +560,29 @@ hipError_t gemm_lowp(const GemmLP& g, hipStream_t s) {
   p.chunk = chunk;
   dim3 grid(p.tiles_m * p.tiles_n, g.nb, 1);
   hipLaunchKernelGGL((gemm_lowp_kernel<false>), grid, dim3(NT), 0, s, p);
+  return hipGetLastError();
+}
+
+hipError_t to_lowp_pm(int prec, float* out, long ldo, const double* V, long ldv, long vrows, const int* pm, long Tv,
+                      hipStream_t s) {
+  const long total = 2 * Tv * ldo;
+  if (total <= 0) return hipSuccess;
+  if (ldo < Tv || ldv < Tv || vrows < Tv) return hipErrorInvalidValue;
+  if (bounds_checking() && !(range_ok(out, 0, total - 1, 4, "vvvv shadow") &&
+                             range_ok(V, 0, (vrows - 1) * ldv + Tv - 1, 8, "full vvvv") &&
+                             range_ok(pm, 0, Tv - 1, 4, "pair rows")))
+    return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  long g = (total + 255) / 256;
+  if (g > 8192) g = 8192;
+  if (prec == kPrecBF16x3) {
+    unsigned short* hi = reinterpret_cast<unsigned short*>(out);
+    hipLaunchKernelGGL(lowp_pm_kernel<true>, dim3((unsigned)g), dim3(256), 0, s, hi, hi + total, nullptr, ldo, V, ldv,
+                       pm, Tv);
+  } else {
+    hipLaunchKernelGGL(lowp_pm_kernel<false>, dim3((unsigned)g), dim3(256), 0, s, nullptr, nullptr, out, ldo, V, ldv,
+                       pm, Tv);
+  }
   return hipGetLastError();
 }
 

@@ -63,6 +63,16 @@ Gemm gemm_rm(int M, int N, int K, double alpha, const double* A, long lda, bool 
 
 hipError_t gemm_f64(const Gemm& g, hipStream_t s);
 
+// Particle-particle ladder over pair indices, both halves h = 0 (+), 1 (-) in one launch:
+//   C[h][m][n] = sum_k A[h][m][k] * Vh(n, k),   m < M;  n, k < Tv
+// A and C are row-major [2][M][Tv].  pm == nullptr: Vh is stored, row-major [2][Tv][Tv] (V).
+// Otherwise V is the full (ac|bd) matrix in pair order (see pack_full), [vrows = v^2][ldv], and
+// Vh(n, k) = V[n][k] +- V[pm[n]][k] = (ac|bd) +- (ad|bc) for n = (a <= b), k = (c <= d) (on the
+// diagonal k = (c,c) this is twice the packed V+, so A carries half the diagonal t+).
+// No split-K, so every output is summed in the same order whatever M is.
+hipError_t gemm_f64_ladder(int M, int Tv, const double* A, const double* V, long ldv, long vrows, const int* pm,
+                           double* C, hipStream_t s);
+
 // Low-precision contraction with FP64 result (gemm_lowp.hip):
 //   C_z(m,n) = alpha * sum_k A_z[m*lda + k] * B_z[n*ldb + k] + beta * C_z(m,n)
 // A, B are FP32 (K contiguous); prec selects FP32 MFMA or split-BF16x3 MFMA; FP32 accumulation
@@ -89,6 +99,10 @@ hipError_t cvt_f32(float* out, const double* in, long n, hipStream_t s);
 // (a multiple of 8; padding zeroed).  FP32: one float array.  BF16X3: the same bytes hold two
 // bf16 planes, hi[rows*ldo] then lo[rows*ldo].
 hipError_t to_lowp_2d(int prec, float* out, long ldo, const double* in, long ldi, long rows, long cols, hipStream_t s);
+// Packed vvvv halves [2][Tv][ldo] (zero padded) in low precision, formed from the full (ac|bd)
+// matrix in pair order [vrows][ldv] as gemm_f64_ladder forms them (V[n][k] +- V[pm[n]][k]).
+hipError_t to_lowp_pm(int prec, float* out, long ldo, const double* V, long ldv, long vrows, const int* pm, long Tv,
+                      hipStream_t s);
 inline long lowp_ld(long k) { return (k + 7) / 8 * 8; }
 
 // ---------------------------------------------------------------------------------------
@@ -106,15 +120,18 @@ hipError_t permute4(double* out, const int dims[4], double c0, const Perm4In* in
 hipError_t permute4_strided(double* out, const long ostr[4], const int dims[4], double c0, const Perm4In* in,
                             int nin, hipStream_t s);
 
-// Assembly of the doubles residual (see residual.hip for the formula).
+// Assembly of the doubles residual from the ring, ladder and E-term pieces (formula at the kernel).
 hipError_t assemble_r2(double* r2, const double* g1, const double* rl, const double* em, const double* p1,
                        const double* p2, int no, int nv, hipStream_t s);
 
 // Pair packing of the particle-particle ladder (p(i,j) = row-major index of i <= j).
-hipError_t pack_pairs(double* out, const double* in, int o, long L, hipStream_t s);     // out[p][x] = in[i][j][x]
-hipError_t unpack_pairs(double* RL, const double* Rp, int o, int v, hipStream_t s);    // mirror i > j rows
+// Full (ac|bd) storage in pair order R(a,b) (a <= b: p(a,b); a > b: T(v) + strict index of (b,a)):
+// pm[n] = R(b,a) for pair n = (a <= b); pack_full scatters W[a - a0][b][c][d] = (ac|bd), a0 <= a < a1,
+// to V[R(a,b)][R(c,d)].
+hipError_t pair_minus_rows(int* pm, int v, hipStream_t s);
+hipError_t pack_full(double* V, const double* W, int a0, int a1, int v, hipStream_t s);
 // t+ rows -> tplus[T(o)][T(v)], t- rows -> tminus[T(o)][T(v)] (and back for R+-)
-hipError_t pack_tpm(double* tplus, double* tminus, const double* t2, int o, int v, hipStream_t s);
+hipError_t pack_tpm(double* tplus, double* tminus, const double* t2, int o, int v, double dscale, hipStream_t s);
 hipError_t unpack_rpm(double* RL, const double* Rplus, const double* Rminus, int o, int v, hipStream_t s);
 hipError_t pack_vvvv(double* Vp, const double* W, int a0, int a1, int v, hipStream_t s);  // rows a0 <= a < a1
 
