@@ -43,7 +43,8 @@ from gen.synth_df import WORKLOADS, converging_sigma, make_system, single_excita
 
 METRIC = "N^6 residual TFLOP/s, mixed vs FP64 @|dE|<1e-6 Eh; solves/s + p99 latency"
 FP64_MFMA_PEAK_TFLOPS = 78.6
-LADDER_KERNEL = {"fp64": "gemm_f64_kernel", "fp32": "gemm_lowp_kernel", "bf16x3": "gemm_bf16x3_kernel"}
+LADDER_KERNEL = {"fp64": "gemm_f64_kernel", "fp32": "gemm_lowp_kernel",
+                 "bf16x3": "gemm_bf16x3_dma_kernel or gemm_bf16x3_kernel by size"}
 LADDER_SOURCE = {"fp64": "gemm_f64.hip", "fp32": "gemm_lowp.hip", "bf16x3": "gemm_lowp.hip"}
 
 # HBM bytes per ladder launch from rocprofv3 FETCH_SIZE and WRITE_SIZE runs of this bench command,

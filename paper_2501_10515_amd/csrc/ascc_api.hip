@@ -492,8 +492,8 @@ int add_two_electron_fock(const ascc_ints* I, double* F, const double* Bq, doubl
 
 
 // C_z[m][n] = sum_k A_z[m][k] B_z[n][k] in the handle's current low precision (FP64 result).
-GemmLP lp_nt(const ascc_ints* I, long M, long N, long K, int nb, const float* A, long lda, long sa2, long a_plane,
-             const float* B, long ldb, long sb2, long b_plane, double* C, long ldc, long sc2) {
+GemmLP lp_nt(const ascc_ints* I, long M, long N, long K, int nb, const float* A, long lda, long sa2, const float* B,
+             long ldb, long sb2, double* C, long ldc, long sc2) {
   GemmLP g;
   g.M = (int)M;
   g.N = (int)N;
@@ -502,16 +502,20 @@ GemmLP lp_nt(const ascc_ints* I, long M, long N, long K, int nb, const float* A,
   g.A = A;
   g.lda = lda;
   g.sa2 = sa2;
-  g.a_plane = a_plane;
   g.B = B;
   g.ldb = ldb;
   g.sb2 = sb2;
-  g.b_plane = b_plane;
   g.C = C;
   g.scm = ldc;
   g.scn = 1;
   g.sc2 = sc2;
   g.prec = (I->cur_prec == ASCC_PREC_BF16X3) ? kPrecBF16x3 : kPrecFP32;
+  if (g.prec == kPrecBF16x3) {  // one float of a shadow = one bf16 pair: strides in bf16 elements
+    g.lda *= 2;
+    g.sa2 *= 2;
+    g.ldb *= 2;
+    g.sb2 *= 2;
+  }
   return g;
 }
 
@@ -547,8 +551,7 @@ int pp_ladder_states(ascc_ints* I, int S, const double* const* t2s, double* cons
   phase_end(I, s);
   phase_begin(I, PH_LADDER, s);
   if (lowp)
-    HIPCHK(gemm_lowp(lp_nt(I, M, Tv, Tv, 2, Tpf, ld, M * ld, 2 * M * ld, I->Vf, ld, Tv * ld, 2 * Tv * ld, Rp, Tv,
-                           M * Tv), s));
+    HIPCHK(gemm_lowp(lp_nt(I, M, Tv, Tv, 2, Tpf, ld, M * ld, I->Vf, ld, Tv * ld, Rp, Tv, M * Tv), s));
   else if (full)
     HIPCHK(gemm_f64_ladder((int)M, (int)Tv, Tp, I->V, I->vv, I->vv, pair_minus(I), Rp, s));
   else
@@ -640,7 +643,7 @@ int residual_core(ascc_ints* I, const double* t1, const double* t2, double* r1, 
   if (lowp) {
     const long ld = lowp_ld(vv);
     HIPCHK(shadow(I, I->t2f, t2, oo, vv, s));
-    HIPCHK(gemm_lowp(lp_nt(I, oo, wzl, vv, 1, I->t2f, ld, 0, oo * ld, I->GwzTf, ld, 0, wzl * ld, I->WZ, wzl, 0), s));
+    HIPCHK(gemm_lowp(lp_nt(I, oo, wzl, vv, 1, I->t2f, ld, 0, I->GwzTf, ld, 0, I->WZ, wzl, 0), s));
   } else {
     HIPCHK(mm(I, gemm_rm(oo, wzl, vv, 1.0, t2, vv, false, I->Gwz, wzl, false, 0.0, I->WZ, wzl), s));
   }
@@ -667,8 +670,7 @@ int residual_core(ascc_ints* I, const double* t1, const double* t2, double* r1, 
   if (lowp) {  // K and L are symmetric matrices, so B[n][k] = B[k][n]
     const long ld = lowp_ld(ov);
     HIPCHK(shadow(I, I->TUf, I->TU, 2 * ov, ov, s));
-    HIPCHK(gemm_lowp(lp_nt(I, ov, ov, ov, 2, I->TUf, ld, ov * ld, 2 * ov * ld, I->KLf, ld, ov * ld, 2 * ov * ld, I->Y,
-                           ov, ovov), s));
+    HIPCHK(gemm_lowp(lp_nt(I, ov, ov, ov, 2, I->TUf, ld, ov * ld, I->KLf, ld, ov * ld, I->Y, ov, ovov), s));
   } else {
     Gemm g = gemm_rm(ov, ov, ov, 1.0, I->TU, ov, false, I->KL, ov, false, 0.0, I->Y, ov);
     g.sa2 = ovov;
@@ -693,8 +695,7 @@ int residual_core(ascc_ints* I, const double* t1, const double* t2, double* r1, 
   if (lowp) {  // P1 = Tx Xc^T, P2 = U Zd^T
     const long ld = lowp_ld(ov);
     HIPCHK(shadow(I, I->XZf, I->XZ, 2 * ov, ov, s));
-    HIPCHK(gemm_lowp(lp_nt(I, ov, ov, ov, 2, I->TUf, ld, ov * ld, 2 * ov * ld, I->XZf, ld, ov * ld, 2 * ov * ld, I->P,
-                           ov, ovov), s));
+    HIPCHK(gemm_lowp(lp_nt(I, ov, ov, ov, 2, I->TUf, ld, ov * ld, I->XZf, ld, ov * ld, I->P, ov, ovov), s));
   } else {
     Gemm g = gemm_rm(ov, ov, ov, 1.0, I->TU, ov, false, I->XZ, ov, true, 0.0, I->P, ov);
     g.sa2 = ovov;

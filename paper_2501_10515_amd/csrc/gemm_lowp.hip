@@ -2,13 +2,14 @@
 //
 //   C_z(m,n) = alpha * sum_k A_z[m][k] B_z[n][k] + beta * C_z(m,n)
 //
-// A and B are FP32 shadows of FP64 operands (row-major, K contiguous, rounded to nearest even
-// by the conversion kernels); C is FP64 with general strides.  Two arithmetic policies:
+// A and B are low-precision shadows of FP64 operands (row-major, K contiguous, zero-padded rows,
+// rounded to nearest even by the conversion kernels); C is FP64 with general strides.  Two
+// arithmetic policies:
 //
-//   FP32   : v_mfma_f32_16x16x4_f32 on the FP32 values.
-//   BF16X3 : each FP32 value is split x = hi + lo with hi = RNE_bf16(x), lo = RNE_bf16(x - hi)
-//            while it is staged into LDS; v_mfma_f32_16x16x32_bf16 forms
-//            lo*hi + hi*lo + hi*hi (the lo*lo term, relative size 2^-16, is dropped).
+//   FP32   : v_mfma_f32_16x16x4_f32 on FP32 shadows.
+//   BF16X3 : the shadows are two bf16 planes, x = hi + lo with hi = RNE_bf16(x),
+//            lo = RNE_bf16(x - hi); v_mfma_f32_16x16x32_bf16 forms lo*hi + hi*lo + hi*hi (the
+//            lo*lo term, relative size 2^-16, is dropped).
 //
 // Both accumulate in FP32 inside a K chunk and add each chunk's partial sum into the FP64 C tile
 // (which the workgroup owns for the whole K range), so accumulation across chunks is FP64.
@@ -16,6 +17,7 @@
 // MFMA lane layouts (gfx950, measured): f32 16x16x4 -- lane l supplies A(l%16, l/16) and
 // B(l/16, l%16); bf16 16x16x32 -- lane l supplies A(l%16, 8(l/16)+j) and B(8(l/16)+j, l%16),
 // j = 0..7; both return register r of lane l as C(4(l/16)+r, l%16).
+#include <algorithm>
 #include <cstdint>
 
 #include "internal.h"
@@ -25,7 +27,6 @@ namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
-typedef unsigned short us4 __attribute__((ext_vector_type(4)));
 
 struct LP {
   int M, N, K;
@@ -49,6 +50,22 @@ __device__ __forceinline__ unsigned short bf16_rne(float f) {
 }
 __device__ __forceinline__ float bf16_to_f(unsigned short h) { return __uint_as_float(((uint32_t)h) << 16); }
 
+// Same, walked in groups of 8 M-tiles (M fastest inside a group): the workgroups resident on one
+// XCD at a time cover a compact block of C and share A and B slices in its L2.
+__device__ __forceinline__ void tile_of_grouped(int bid, int tiles_m, int tiles_n, int& tm, int& tn) {
+  constexpr int GM = 8;
+  const int total = tiles_m * tiles_n;
+  const int q = total >> 3, rem = total & 7;
+  const int x = bid & 7, local = bid >> 3;
+  const int t = x * q + min(x, rem) + local;
+  const int per = GM * tiles_n;
+  const int g = t / per, first = g * GM;
+  const int gs = min(tiles_m - first, GM);
+  const int r = t - g * per;
+  tm = first + r % gs;
+  tn = r / gs;
+}
+
 __device__ __forceinline__ void tile_of_lp(int bid, int tiles_m, int total, int& tm, int& tn) {
   const int q = total >> 3, rem = total & 7;
   const int x = bid & 7, local = bid >> 3;
@@ -59,18 +76,16 @@ __device__ __forceinline__ void tile_of_lp(int bid, int tiles_m, int total, int&
 
 constexpr int BM = 128, BN = 128, NT = 256;
 
-template <bool BF16>
+// FP32 policy: 128 x 128 tiles, four 64 x 64 waves, v_mfma_f32_16x16x4_f32.
 __global__ __launch_bounds__(NT, 1) void gemm_lowp_kernel(LP p) {
   // K depth per LDS stage and row pitch of the staged tiles (elements)
   constexpr int BK = 32;
-  constexpr int PITCH = BF16 ? (BK + 8) : (BK + 4);
+  constexpr int PITCH = BK + 4;
   // per stage each thread moves 4 float4 of A and 4 of B (128 x 32 floats each)
   constexpr int LQ = BM * BK / 4 / NT;
   static_assert(LQ == 4, "tile config");
-  using ST = typename std::conditional<BF16, unsigned short, float>::type;
-  constexpr int PLANES = BF16 ? 2 : 1;
-  __shared__ __attribute__((aligned(16))) ST As[2][PLANES][BM * PITCH];
-  __shared__ __attribute__((aligned(16))) ST Bs[2][PLANES][BN * PITCH];
+  __shared__ __attribute__((aligned(16))) float As[2][BM * PITCH];
+  __shared__ __attribute__((aligned(16))) float Bs[2][BN * PITCH];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;  // 2 x 2 waves of 64 x 64
@@ -129,23 +144,8 @@ __global__ __launch_bounds__(NT, 1) void gemm_lowp_kernel(LP p) {
     for (int l = 0; l < LQ; ++l) {
       const int c = tid + l * NT;
       const int r = c >> 3, kq = (c & 7) * 4;
-      if constexpr (BF16) {
-        us4 ah, al, bh, bl;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          ah[t] = bf16_rne(ra[l][t]);
-          al[t] = bf16_rne(ra[l][t] - bf16_to_f(ah[t]));
-          bh[t] = bf16_rne(rb[l][t]);
-          bl[t] = bf16_rne(rb[l][t] - bf16_to_f(bh[t]));
-        }
-        *reinterpret_cast<us4*>(&As[buf][0][r * PITCH + kq]) = ah;
-        *reinterpret_cast<us4*>(&As[buf][1][r * PITCH + kq]) = al;
-        *reinterpret_cast<us4*>(&Bs[buf][0][r * PITCH + kq]) = bh;
-        *reinterpret_cast<us4*>(&Bs[buf][1][r * PITCH + kq]) = bl;
-      } else {
-        *reinterpret_cast<f4*>(&As[buf][0][r * PITCH + kq]) = ra[l];
-        *reinterpret_cast<f4*>(&Bs[buf][0][r * PITCH + kq]) = rb[l];
-      }
+      *reinterpret_cast<f4*>(&As[buf][r * PITCH + kq]) = ra[l];
+      *reinterpret_cast<f4*>(&Bs[buf][r * PITCH + kq]) = rb[l];
     }
   };
 
@@ -181,47 +181,19 @@ __global__ __launch_bounds__(NT, 1) void gemm_lowp_kernel(LP p) {
   for (int kt = kc; kt < kend; ++kt) {
     const int cur = kt & 1;
     if (kt + 1 < nkt) load(kt + 1);
-    if constexpr (BF16) {
-      const ST* ah = As[cur][0];
-      const ST* al = As[cur][1];
-      const ST* bh = Bs[cur][0];
-      const ST* bl = Bs[cur][1];
-      bf8 xa[4][2], xb[4][2];
+    const float* as = As[cur];
+    const float* bs = Bs[cur];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int off = (wm * 64 + i * 16 + lr) * PITCH + 8 * lg;
-        xa[i][0] = *reinterpret_cast<const bf8*>(ah + off);
-        xa[i][1] = *reinterpret_cast<const bf8*>(al + off);
-      }
+    for (int kk = 0; kk < BK; kk += 4) {
+      float xa[4], xb[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int off = (wn * 64 + j * 16 + lr) * PITCH + 8 * lg;
-        xb[j][0] = *reinterpret_cast<const bf8*>(bh + off);
-        xb[j][1] = *reinterpret_cast<const bf8*>(bl + off);
-      }
+      for (int i = 0; i < 4; ++i) xa[i] = as[(wm * 64 + i * 16 + lr) * PITCH + kk + lg];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) xb[j] = bs[(wn * 64 + j * 16 + lr) * PITCH + kk + lg];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[i][1], xb[j][0], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[i][0], xb[j][1], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[i][0], xb[j][0], acc[i][j], 0, 0, 0);
-        }
-    } else {
-      const float* as = As[cur][0];
-      const float* bs = Bs[cur][0];
-#pragma unroll
-      for (int kk = 0; kk < BK; kk += 4) {
-        float xa[4], xb[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) xa[i] = as[(wm * 64 + i * 16 + lr) * PITCH + kk + lg];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) xb[j] = bs[(wn * 64 + j * 16 + lr) * PITCH + kk + lg];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[i], xb[j], acc[i][j], 0, 0, 0);
-      }
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[i], xb[j], acc[i][j], 0, 0, 0);
     }
     if (kt + 1 < nkt) store(cur ^ 1);
     __syncthreads();
@@ -241,8 +213,10 @@ __global__ __launch_bounds__(256) void cvt_f32_2d_kernel(float* __restrict__ out
   }
 }
 
-__global__ __launch_bounds__(256) void split_bf16_2d_kernel(unsigned short* __restrict__ hi, unsigned short* __restrict__ lo,
-                                                            long ldo, const double* __restrict__ in, long ldi, long rows,
+// Interleaved split of a row-padded matrix: row r of the output holds, for each K-block kb of 32,
+// hi[32] at r * 2ldo + 64kb and lo[32] right after it (ldo a multiple of 32; padding zeroed).
+__global__ __launch_bounds__(256) void split_bf16_2d_kernel(unsigned short* __restrict__ out, long ldo,
+                                                            const double* __restrict__ in, long ldi, long rows,
                                                             long cols) {
   const long total = rows * ldo;
   for (long x = blockIdx.x * 256L + threadIdx.x; x < total; x += (long)gridDim.x * 256) {
@@ -253,18 +227,19 @@ __global__ __launch_bounds__(256) void split_bf16_2d_kernel(unsigned short* __re
       h = bf16_rne((float)d);
       l = bf16_rne((float)(d - (double)bf16_to_f(h)));
     }
-    hi[x] = h;
-    lo[x] = l;
+    const long o = r * 2 * ldo + (c >> 5) * 64 + (c & 31);
+    out[o] = h;
+    out[o + 32] = l;
   }
 }
 
 // Low-precision shadow of the vvvv halves formed from the full (ac|bd) matrix in pair order (rows
 // at stride ldv): row r = h*Tv + n (h = 0: +, 1: -), column k < Tv, zero padding up to ldo; in FP64
-// x = V[n][k] +- V[pm[n]][k], then rounded as to_lowp_2d rounds (FP32, or bf16 hi/lo planes).
+// x = V[n][k] +- V[pm[n]][k], then rounded and laid out as to_lowp_2d does (FP32, or interleaved bf16).
 template <bool BF>
-__global__ __launch_bounds__(256) void lowp_pm_kernel(unsigned short* __restrict__ hi, unsigned short* __restrict__ lo,
-                                                      float* __restrict__ out, long ldo, const double* __restrict__ V,
-                                                      long ldv, const int* __restrict__ pm, long Tv) {
+__global__ __launch_bounds__(256) void lowp_pm_kernel(unsigned short* __restrict__ bo, float* __restrict__ out,
+                                                      long ldo, const double* __restrict__ V, long ldv,
+                                                      const int* __restrict__ pm, long Tv) {
   const long total = 2 * Tv * ldo;
   for (long x = blockIdx.x * 256L + threadIdx.x; x < total; x += (long)gridDim.x * 256) {
     const long r = x / ldo, c = x - r * ldo;
@@ -277,37 +252,40 @@ __global__ __launch_bounds__(256) void lowp_pm_kernel(unsigned short* __restrict
     }
     if (BF) {
       const unsigned short h = bf16_rne((float)d);
-      hi[x] = h;
-      lo[x] = bf16_rne((float)(d - (double)bf16_to_f(h)));
+      const long o = r * 2 * ldo + (c >> 5) * 64 + (c & 31);
+      bo[o] = h;
+      bo[o + 32] = bf16_rne((float)(d - (double)bf16_to_f(h)));
     } else {
       out[x] = (float)d;
     }
   }
 }
 
-// FP64 -> (hi, lo) bf16 planes: hi = RNE_bf16(RNE_fp32(x)), lo = RNE_bf16(RNE_fp32(x - hi)).
-__global__ __launch_bounds__(256) void split_bf16_kernel(unsigned short* __restrict__ hi, unsigned short* __restrict__ lo,
-                                                         const double* __restrict__ in, long n) {
-  for (long x = blockIdx.x * 256L + threadIdx.x; x < n; x += (long)gridDim.x * 256) {
-    const double d = in[x];
-    const unsigned short h = bf16_rne((float)d);
-    hi[x] = h;
-    lo[x] = bf16_rne((float)(d - (double)bf16_to_f(h)));
-  }
-}
 
 
 // ---------------------------------------------------------------------------------------
-// Split-BF16x3 on pre-split operands: A and B are (hi, lo) bf16 planes with padded leading
-// dimensions (multiples of 8 elements, zero padding), so every staging load is one 16-byte
-// chunk and no conversion happens in the kernel.  Workgroup tile 256 x 128, eight waves of
-// 64 x 64 (4 x 4 tiles of the 16x16x32 instruction), two LDS stages of K = 32.
+// Split-BF16x3 on pre-split operands: each row of A and B holds, per K-block of 32, the 32 hi
+// values then the 32 lo values (bf16; row stride lda/ldb a multiple of 64, zero padding), so one
+// K-step of a row is one 128-byte line, every staging load is one 16-byte chunk and no
+// conversion happens in the kernel.
+//
+// LDS tiles hold 32 K-values per row (64 bytes) with no padding; the 16-byte chunk c of row r is
+// stored at slot c ^ ((r >> 1) & 3).  Measured on gfx950 (bank-conflict counters), this makes both
+// the fragment reads of v_mfma_f32_16x16x32_bf16 (row = lane % 16, chunk = lane / 16) and the
+// four-lanes-per-row staging stores conflict-free; padded 80-byte rows conflict 2-way on both.
+//
+// Two kernels: 256 x 128 tiles of eight 64 x 64 waves with register-staged loads (small and
+// medium contractions), and 256 x 256 tiles of four 128 x 128 waves whose operands are loaded
+// straight into LDS by buffer_load ... lds, double-buffered, with the accumulators in AGPRs
+// (large contractions: half the LDS traffic per MFMA and no staging registers).
+__device__ __forceinline__ int lds_slot(int r, int c) { return r * 32 + ((c ^ ((r >> 1) & 3)) << 3); }
+
 struct LPB {
   int M, N, K;
   const unsigned short* A;
-  long lda, sa2, a_plane;
+  long lda, sa2;
   const unsigned short* B;
-  long ldb, sb2, b_plane;
+  long ldb, sb2;
   double* C;
   long scm, scn, sc2;
   double alpha, beta;
@@ -315,12 +293,12 @@ struct LPB {
   int chunk;
 };
 
-constexpr int BM2 = 256, BN2 = 128, BK2 = 32, NT2 = 512, PITCH2 = BK2 + 8;
+constexpr int BM2 = 256, BN2 = 128, BK2 = 32, NT2 = 512;
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(NT2, 1) void gemm_bf16x3_kernel(LPB p) {
-  __shared__ __attribute__((aligned(16))) unsigned short As[2][2][BM2 * PITCH2];
-  __shared__ __attribute__((aligned(16))) unsigned short Bs[2][2][BN2 * PITCH2];
+  __shared__ __attribute__((aligned(16))) unsigned short As[2][2][BM2 * BK2];
+  __shared__ __attribute__((aligned(16))) unsigned short Bs[2][2][BN2 * BK2];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;  // 4 x 2 waves of 64 x 64
   int tm, tn;
@@ -343,7 +321,7 @@ __global__ __launch_bounds__(NT2, 1) void gemm_bf16x3_kernel(LPB p) {
   // address arithmetic out of the vector register budget.
   const unsigned short* Arow = Ab + (long)m0 * p.lda;
   const unsigned short* Brow = Bb + (long)n0 * p.ldb;
-  const int lda = (int)p.lda, ldb = (int)p.ldb;
+  const int lda = (int)p.lda, ldb = (int)p.ldb, kpad = lda / 2;  // lda == ldb for these operands
   // A: 256 rows x 4 chunks x 2 planes = 2048 chunks (4 per thread); B: 1024 chunks (2 per thread)
   auto load = [&](int kt) {
     const int k0 = kt * BK2;
@@ -353,8 +331,8 @@ __global__ __launch_bounds__(NT2, 1) void gemm_bf16x3_kernel(LPB p) {
       const int plane = c >> 10, rem = c & 1023, row = rem >> 2, kc = (rem & 3) * 8;
       const int gk = k0 + kc;
       u4 v = u4{0u, 0u, 0u, 0u};
-      if (m0 + row < p.M && gk < lda)
-        v = *reinterpret_cast<const u4*>((plane ? Arow + p.a_plane : Arow) + (unsigned)(row * lda + gk));
+      if (m0 + row < p.M && gk < kpad)
+        v = *reinterpret_cast<const u4*>(Arow + (unsigned)(row * lda + 2 * k0 + plane * 32 + kc));
       ra[l] = v;
     }
 #pragma unroll
@@ -363,8 +341,8 @@ __global__ __launch_bounds__(NT2, 1) void gemm_bf16x3_kernel(LPB p) {
       const int plane = c >> 9, rem = c & 511, row = rem >> 2, kc = (rem & 3) * 8;
       const int gk = k0 + kc;
       u4 v = u4{0u, 0u, 0u, 0u};
-      if (n0 + row < p.N && gk < ldb)
-        v = *reinterpret_cast<const u4*>((plane ? Brow + p.b_plane : Brow) + (unsigned)(row * ldb + gk));
+      if (n0 + row < p.N && gk < kpad)
+        v = *reinterpret_cast<const u4*>(Brow + (unsigned)(row * ldb + 2 * k0 + plane * 32 + kc));
       rb[l] = v;
     }
   };
@@ -373,13 +351,13 @@ __global__ __launch_bounds__(NT2, 1) void gemm_bf16x3_kernel(LPB p) {
     for (int l = 0; l < 4; ++l) {
       const int c = tid + l * NT2;
       const int plane = c >> 10, rem = c & 1023, row = rem >> 2, kc = (rem & 3) * 8;
-      *reinterpret_cast<u4*>(&As[buf][plane][row * PITCH2 + kc]) = ra[l];
+      *reinterpret_cast<u4*>(&As[buf][plane][lds_slot(row, kc >> 3)]) = ra[l];
     }
 #pragma unroll
     for (int l = 0; l < 2; ++l) {
       const int c = tid + l * NT2;
       const int plane = c >> 9, rem = c & 511, row = rem >> 2, kc = (rem & 3) * 8;
-      *reinterpret_cast<u4*>(&Bs[buf][plane][row * PITCH2 + kc]) = rb[l];
+      *reinterpret_cast<u4*>(&Bs[buf][plane][lds_slot(row, kc >> 3)]) = rb[l];
     }
   };
   double* Cw = Cb + (long)(m0 + wm * 64) * p.scm + (long)(n0 + wn * 64) * p.scn;  // wave-uniform
@@ -419,13 +397,13 @@ __global__ __launch_bounds__(NT2, 1) void gemm_bf16x3_kernel(LPB p) {
       bf8 xa[4][2];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int off = (wm * 64 + i * 16 + lr) * PITCH2 + 8 * lg;
+        const int off = lds_slot(wm * 64 + i * 16 + lr, lg);
         xa[i][0] = *reinterpret_cast<const bf8*>(&As[cur][0][off]);
         xa[i][1] = *reinterpret_cast<const bf8*>(&As[cur][1][off]);
       }
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int off = (wn * 64 + j * 16 + lr) * PITCH2 + 8 * lg;
+        const int off = lds_slot(wn * 64 + j * 16 + lr, lg);
         const bf8 bh = *reinterpret_cast<const bf8*>(&Bs[cur][0][off]);
         const bf8 bl = *reinterpret_cast<const bf8*>(&Bs[cur][1][off]);
 #pragma unroll
@@ -443,34 +421,108 @@ __global__ __launch_bounds__(NT2, 1) void gemm_bf16x3_kernel(LPB p) {
   if (nkt == 0) flush(true);
 }
 
-// FP64 -> FP32 (round to nearest even), contiguous.
-__global__ __launch_bounds__(256) void cvt_f32_kernel(float* __restrict__ out, const double* __restrict__ in, long n) {
-  for (long x = blockIdx.x * 256L + threadIdx.x; x < n; x += (long)gridDim.x * 256) out[x] = (float)in[x];
+// 256 x 256 tiles, four waves of 128 x 128 (8 x 8 fragments, accumulators in AGPRs).  Each wave
+// stages one operand half per K-step (A hi, A lo, B hi, B lo: 256 rows x 64 bytes) with sixteen
+// buffer_load_dwordx4 ... lds (lane l of an instruction writes LDS bytes 16l .. 16l + 15, so lanes
+// pick the global chunk that belongs at their swizzled slot); rows past M or N and K-blocks past
+// the padded row read as zero through the buffer range check.  Per K-step: wait for the stage,
+// barrier, read all fragments, issue the next stage into the other buffer, run 192 MFMAs.
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(3))) char lds_char_t;
+constexpr int BM3 = 256, BN3 = 256, NT3 = 256;
+
+__global__ __launch_bounds__(NT3, 1) void gemm_bf16x3_dma_kernel(LPB p) {
+  __shared__ __attribute__((aligned(1024))) unsigned short T[2][4][256 * 32];  // [stage][plane][row slots]
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave >> 1, wn = wave & 1;
+  int tm, tn;
+  tile_of_grouped(blockIdx.x, p.tiles_m, p.tiles_n, tm, tn);
+  const int m0 = tm * BM3, n0 = tn * BN3;
+  const int z = blockIdx.y;
+  const bool isA = wave < 2;
+  const unsigned short* base = isA ? p.A + z * p.sa2 + (long)m0 * p.lda : p.B + z * p.sb2 + (long)n0 * p.ldb;
+  const int ld = isA ? (int)p.lda : (int)p.ldb;  // row stride (bf16): K-blocks of [hi 32 | lo 32]
+  const int plane = wave & 1;
+  const int rows = min(256, isA ? p.M - m0 : p.N - n0);
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, rows * ld * 2, 0x00020000);
+  const int r = lane >> 2, c = (lane & 3) ^ ((r >> 1) & 3);  // row in a 16-row block, chunk loaded
+  auto issue = [&](int kt, int stage) {
+    const int gk = kt * 32 + c * 8, col = kt * 64 + plane * 32 + c * 8;
+    lds_char_t* dst = (lds_char_t*)(lds_void_t*)&T[stage][wave][0];
+#pragma unroll
+    for (int g = 0; g < 16; ++g) {
+      const unsigned off = 2 * gk < ld ? (unsigned)(((g * 16 + r) * ld + col) * 2) : 0x80000000u;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_t*)(dst + g * 1024), 16, off, 0, 0, 0);
+    }
+  };
+  double* Cb = p.C + z * p.sc2;
+  f4 acc[8][8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  auto flush = [&](bool first) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int gm = m0 + wm * 128 + i * 16 + 4 * (lane >> 4) + q, gn = n0 + wn * 128 + j * 16 + (lane & 15);
+          if (gm < p.M && gn < p.N) {
+            double* cp = Cb + (long)gm * p.scm + (long)gn * p.scn;
+            const double v = p.alpha * (double)acc[i][j][q];
+            if (first)
+              *cp = (p.beta == 0.0) ? v : v + p.beta * *cp;
+            else
+              *cp += v;
+          }
+          acc[i][j][q] = 0.f;
+        }
+  };
+  const int nkt = (p.K + 31) / 32;
+  const int lr = lane & 15, lg = lane >> 4;
+  if (nkt > 0) issue(0, 0);
+  for (int kc = 0; kc < nkt; kc += p.chunk) {
+    const int kend = min(nkt, kc + p.chunk);
+    for (int kt = kc; kt < kend; ++kt) {
+      const int cur = kt & 1;
+      __builtin_amdgcn_s_waitcnt(0xF70);  // vmcnt(0): this wave's part of stage kt has landed
+      __syncthreads();                     // every wave's has; stage cur ^ 1 is no longer read
+      bf8 xa[8][2], xb[8][2];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int off = lds_slot(wm * 128 + i * 16 + lr, lg);
+        xa[i][0] = *reinterpret_cast<const bf8*>(&T[cur][0][off]);
+        xa[i][1] = *reinterpret_cast<const bf8*>(&T[cur][1][off]);
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int off = lds_slot(wn * 128 + j * 16 + lr, lg);
+        xb[j][0] = *reinterpret_cast<const bf8*>(&T[cur][2][off]);
+        xb[j][1] = *reinterpret_cast<const bf8*>(&T[cur][3][off]);
+      }
+      if (kt + 1 < nkt) issue(kt + 1, cur ^ 1);
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[i][1], xb[j][0], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[i][0], xb[j][1], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[i][0], xb[j][0], acc[i][j], 0, 0, 0);
+        }
+    }
+    flush(kc == 0);
+  }
+  if (nkt == 0) flush(true);
 }
+
 
 }  // namespace
 
-hipError_t cvt_f32(float* out, const double* in, long n, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  if (bounds_checking() && !(range_ok(out, 0, n - 1, 4, "cvt_f32 out") && range_ok(in, 0, n - 1, 8, "cvt_f32 in")))
-    return hipErrorInvalidValue;
-  if (dry_run()) return hipSuccess;
-  long g = (n + 255) / 256;
-  if (g > 8192) g = 8192;
-  hipLaunchKernelGGL(cvt_f32_kernel, dim3((unsigned)g), dim3(256), 0, s, out, in, n);
-  return hipGetLastError();
-}
 
-hipError_t split_bf16(unsigned short* planes, const double* in, long n, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  if (bounds_checking() && !(range_ok(planes, 0, 2 * n - 1, 2, "split_bf16 out") && range_ok(in, 0, n - 1, 8, "split_bf16 in")))
-    return hipErrorInvalidValue;
-  if (dry_run()) return hipSuccess;
-  long g = (n + 255) / 256;
-  if (g > 8192) g = 8192;
-  hipLaunchKernelGGL(split_bf16_kernel, dim3((unsigned)g), dim3(256), 0, s, planes, planes + n, in, n);
-  return hipGetLastError();
-}
 
 hipError_t to_lowp_2d(int prec, float* out, long ldo, const double* in, long ldi, long rows, long cols,
                       hipStream_t s) {
@@ -483,8 +535,8 @@ hipError_t to_lowp_2d(int prec, float* out, long ldo, const double* in, long ldi
   long g = (total + 255) / 256;
   if (g > 8192) g = 8192;
   if (prec == kPrecBF16x3) {
-    unsigned short* hi = reinterpret_cast<unsigned short*>(out);
-    hipLaunchKernelGGL(split_bf16_2d_kernel, dim3((unsigned)g), dim3(256), 0, s, hi, hi + total, ldo, in, ldi, rows, cols);
+    hipLaunchKernelGGL(split_bf16_2d_kernel, dim3((unsigned)g), dim3(256), 0, s, reinterpret_cast<unsigned short*>(out),
+                       ldo, in, ldi, rows, cols);
   } else {
     hipLaunchKernelGGL(cvt_f32_2d_kernel, dim3((unsigned)g), dim3(256), 0, s, out, ldo, in, ldi, rows, cols);
   }
@@ -495,10 +547,10 @@ hipError_t gemm_lowp(const GemmLP& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.nb <= 0) return hipSuccess;
   if (g.K <= 0 || g.nb > 65535 || (g.prec != kPrecFP32 && g.prec != kPrecBF16x3)) return hipErrorInvalidValue;
   const bool bf = (g.prec == kPrecBF16x3);
-  if (bf && ((g.lda | g.ldb | g.sa2 | g.sb2 | g.a_plane | g.b_plane) & 7)) return hipErrorInvalidValue;
-  if (bf && (g.lda < g.K || g.ldb < g.K)) return hipErrorInvalidValue;
+  // bf16: interleaved rows; the row strides are equal multiples of 64 and cover K
+  if (bf && (((g.lda | g.ldb | g.sa2 | g.sb2) & 63) || g.lda != g.ldb || g.lda / 2 < g.K)) return hipErrorInvalidValue;
   if (bounds_checking()) {
-    // bf16: every staged chunk stays inside its padded row, hi and lo planes
+    // bf16: every staged chunk stays inside its padded row
     const long la = (long)(g.M - 1) * g.lda + (bf ? g.lda - 1 : g.K - 1) + (long)(g.nb - 1) * g.sa2;
     const long lb = (long)(g.N - 1) * g.ldb + (bf ? g.ldb - 1 : g.K - 1) + (long)(g.nb - 1) * g.sb2;
     long lo = 0, hi = 0;
@@ -507,12 +559,11 @@ hipError_t gemm_lowp(const GemmLP& g, hipStream_t s) {
       if (d < 0) lo += d; else hi += d;
     }
     const size_t el = bf ? 2 : 4;
-    if (!(range_ok(g.A, 0, la + (bf ? g.a_plane : 0), el, "lowp A") &&
-          range_ok(g.B, 0, lb + (bf ? g.b_plane : 0), el, "lowp B") && range_ok(g.C, lo, hi, 8, "lowp C")))
+    if (!(range_ok(g.A, 0, la, el, "lowp A") && range_ok(g.B, 0, lb, el, "lowp B") && range_ok(g.C, lo, hi, 8, "lowp C")))
       return hipErrorInvalidValue;
   }
   if (dry_run()) return hipSuccess;
-  const int chunk = g.chunk_ktiles > 0 ? g.chunk_ktiles : 64;
+  const int chunk = g.chunk_ktiles > 0 ? g.chunk_ktiles : (bf ? 256 : 64);
   if (bf) {
     LPB p;
     p.M = g.M;
@@ -521,22 +572,27 @@ hipError_t gemm_lowp(const GemmLP& g, hipStream_t s) {
     p.A = reinterpret_cast<const unsigned short*>(g.A);
     p.lda = g.lda;
     p.sa2 = g.sa2;
-    p.a_plane = g.a_plane;
     p.B = reinterpret_cast<const unsigned short*>(g.B);
     p.ldb = g.ldb;
     p.sb2 = g.sb2;
-    p.b_plane = g.b_plane;
     p.C = g.C;
     p.scm = g.scm;
     p.scn = g.scn;
     p.sc2 = g.sc2;
     p.alpha = g.alpha;
     p.beta = g.beta;
-    p.tiles_m = (g.M + BM2 - 1) / BM2;
-    p.tiles_n = (g.N + BN2 - 1) / BN2;
     p.chunk = chunk;
-    dim3 grid(p.tiles_m * p.tiles_n, g.nb, 1);
-    hipLaunchKernelGGL(gemm_bf16x3_kernel, grid, dim3(NT2), 0, s, p);
+    // buffer descriptors cover one tile's rows: 256 * ld bf16 must stay below 2^31 bytes
+    const long t3 = (long)((g.M + BM3 - 1) / BM3) * ((g.N + BN3 - 1) / BN3) * g.nb;
+    if (t3 >= 256 && 512L * g.lda < (1L << 31)) {
+      p.tiles_m = (g.M + BM3 - 1) / BM3;
+      p.tiles_n = (g.N + BN3 - 1) / BN3;
+      hipLaunchKernelGGL(gemm_bf16x3_dma_kernel, dim3(p.tiles_m * p.tiles_n, g.nb, 1), dim3(NT3), 0, s, p);
+    } else {
+      p.tiles_m = (g.M + BM2 - 1) / BM2;
+      p.tiles_n = (g.N + BN2 - 1) / BN2;
+      hipLaunchKernelGGL(gemm_bf16x3_kernel, dim3(p.tiles_m * p.tiles_n, g.nb, 1), dim3(NT2), 0, s, p);
+    }
     return hipGetLastError();
   }
   LP p;
@@ -559,7 +615,7 @@ hipError_t gemm_lowp(const GemmLP& g, hipStream_t s) {
   p.tiles_n = (g.N + BN - 1) / BN;
   p.chunk = chunk;
   dim3 grid(p.tiles_m * p.tiles_n, g.nb, 1);
-  hipLaunchKernelGGL((gemm_lowp_kernel<false>), grid, dim3(NT), 0, s, p);
+  hipLaunchKernelGGL(gemm_lowp_kernel, grid, dim3(NT), 0, s, p);
   return hipGetLastError();
 }
 
@@ -575,14 +631,11 @@ hipError_t to_lowp_pm(int prec, float* out, long ldo, const double* V, long ldv,
   if (dry_run()) return hipSuccess;
   long g = (total + 255) / 256;
   if (g > 8192) g = 8192;
-  if (prec == kPrecBF16x3) {
-    unsigned short* hi = reinterpret_cast<unsigned short*>(out);
-    hipLaunchKernelGGL(lowp_pm_kernel<true>, dim3((unsigned)g), dim3(256), 0, s, hi, hi + total, nullptr, ldo, V, ldv,
-                       pm, Tv);
-  } else {
-    hipLaunchKernelGGL(lowp_pm_kernel<false>, dim3((unsigned)g), dim3(256), 0, s, nullptr, nullptr, out, ldo, V, ldv,
-                       pm, Tv);
-  }
+  if (prec == kPrecBF16x3)
+    hipLaunchKernelGGL(lowp_pm_kernel<true>, dim3((unsigned)g), dim3(256), 0, s,
+                       reinterpret_cast<unsigned short*>(out), nullptr, ldo, V, ldv, pm, Tv);
+  else
+    hipLaunchKernelGGL(lowp_pm_kernel<false>, dim3((unsigned)g), dim3(256), 0, s, nullptr, out, ldo, V, ldv, pm, Tv);
   return hipGetLastError();
 }
 

@@ -76,7 +76,8 @@ hipError_t gemm_f64_ladder(int M, int Tv, const double* A, const double* V, long
 // Low-precision contraction with FP64 result (gemm_lowp.hip):
 //   C_z(m,n) = alpha * sum_k A_z[m*lda + k] * B_z[n*ldb + k] + beta * C_z(m,n)
 // A, B are FP32 (K contiguous); prec selects FP32 MFMA or split-BF16x3 MFMA; FP32 accumulation
-// inside chunks of chunk_ktiles K-tiles (32 wide), FP64 accumulation across chunks.
+// inside chunks of chunk_ktiles K-tiles (32 wide; 0 = the default of the precision: 64 for FP32,
+// 256 for split-BF16x3), FP64 accumulation across chunks.
 constexpr int kPrecFP64 = 0, kPrecFP32 = 1, kPrecBF16x3 = 2;
 struct GemmLP {
   int M = 0, N = 0, K = 0, nb = 1;
@@ -88,22 +89,21 @@ struct GemmLP {
   long scm = 0, scn = 1, sc2 = 0;
   double alpha = 1.0, beta = 0.0;
   int prec = kPrecFP32;
-  int chunk_ktiles = 64;
-  // BF16X3: A and B point at the hi planes; the lo planes start a_plane / b_plane bf16
-  // elements later (lda, ldb, sa2, sb2 in bf16 elements, multiples of 8)
-  long a_plane = 0, b_plane = 0;
+  int chunk_ktiles = 0;
+  // BF16X3: A and B are interleaved splits (see to_lowp_2d); lda, ldb, sa2, sb2 count bf16
+  // elements (lda == ldb, multiples of 64, lda / 2 >= K)
 };
 hipError_t gemm_lowp(const GemmLP& g, hipStream_t s);
-hipError_t cvt_f32(float* out, const double* in, long n, hipStream_t s);
 // Low-precision shadow of a row-major FP64 matrix with the leading dimension padded to ldo
-// (a multiple of 8; padding zeroed).  FP32: one float array.  BF16X3: the same bytes hold two
-// bf16 planes, hi[rows*ldo] then lo[rows*ldo].
+// (a multiple of 32; padding zeroed).  FP32: one float per element, row stride ldo.  BF16X3: the
+// same bytes as bf16, row stride 2 ldo, each K-block of 32 stored as hi[32] then lo[32] with
+// hi = RNE_bf16(x), lo = RNE_bf16(x - hi).
 hipError_t to_lowp_2d(int prec, float* out, long ldo, const double* in, long ldi, long rows, long cols, hipStream_t s);
 // Packed vvvv halves [2][Tv][ldo] (zero padded) in low precision, formed from the full (ac|bd)
 // matrix in pair order [vrows][ldv] as gemm_f64_ladder forms them (V[n][k] +- V[pm[n]][k]).
 hipError_t to_lowp_pm(int prec, float* out, long ldo, const double* V, long ldv, long vrows, const int* pm, long Tv,
                       hipStream_t s);
-inline long lowp_ld(long k) { return (k + 7) / 8 * 8; }
+inline long lowp_ld(long k) { return (k + 31) / 32 * 32; }
 
 // ---------------------------------------------------------------------------------------
 // Element-wise kernels (elementwise.hip).
