@@ -2,7 +2,7 @@
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--vvvv full|packed]
                 [--precision fp64|fp32|bf16x3] [--generator literal|converging] [--no-compare]
-                [--no-cpu-baseline]
+                [--no-cpu-baseline] [--serve ...] [--solve [--solve-tol T] [--lowp-rnorm R]]
 
 A step is one pass of the whole iteration on the device: T1 dressing, every residual term,
 the energy and residual-norm reductions, the Jacobi update and DIIS (ascc_residual followed
@@ -278,6 +278,60 @@ def serve_main(args):
     print(json.dumps(out), flush=True)
 
 
+def solve_main(args):
+    """Precision study: one workload (convergence-variant generator) solved to the same tolerance with
+    FP64 contractions and with low-precision bulk iterations finished in FP64; |dE| against FP64."""
+    import torch
+
+    import paper_2501_10515_amd as P
+
+    wl = WORKLOADS[args.workload]
+    o, v, Q, seed = wl["no"], wl["nv"], wl["naux"], wl["seed"]
+    sigma = converging_sigma(v, Q)
+    B, eps = make_system(o, v, Q, seed, sigma=sigma)
+    dev = torch.device("cuda:0")
+    mode = P.ASCC_VVVV_FULL if args.vvvv == "full" else P.ASCC_VVVV_PACKED
+    tol = args.solve_tol
+    res = {}
+    for name, pc, lowp_rnorm in (("fp64", P.ASCC_PREC_FP64, 0.0), ("bf16x3_refined", P.ASCC_PREC_BF16X3, args.lowp_rnorm),
+                                 ("fp32_refined", P.ASCC_PREC_FP32, args.lowp_rnorm)):
+        if args.serve_precisions and name.split("_")[0] not in args.serve_precisions.split(","):
+            continue
+        dB, deps = torch.from_numpy(B).to(dev), torch.from_numpy(eps).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ints = P.ascc_build_ints(dB, deps, o, precision=pc, vvvv_mode=mode)
+        torch.cuda.synchronize()
+        t_build = time.perf_counter() - t0
+        del dB
+        t1 = torch.zeros((o, v), dtype=torch.float64, device=dev)
+        t2 = torch.zeros((o, o, v, v), dtype=torch.float64, device=dev)
+        t0 = time.perf_counter()
+        r = P.ascc_solve(ints, t1, t2, tol_rnorm=tol, maxiter=args.solve_maxiter, lowp_rnorm=lowp_rnorm,
+                         raise_on_not_converged=False)
+        torch.cuda.synchronize()
+        t_solve = time.perf_counter() - t0
+        res[name] = {"e_corr": r["e_corr"], "rnorm": r["rnorm"], "rmax": r["rmax"], "iterations": r["iterations"],
+                     "lowp_iterations": r["lowp_iterations"], "converged": r["converged"],
+                     "solve_s": round(t_solve, 3), "build_s": round(t_build, 3)}
+        ints.close()
+        del t1, t2
+        torch.cuda.empty_cache()
+    base = res.get("fp64")
+    for name, r in res.items():
+        if base is not None and name != "fp64":
+            r["abs_dE_vs_fp64"] = abs(r["e_corr"] - base["e_corr"])
+            r["speedup_vs_fp64"] = round(base["solve_s"] / r["solve_s"], 3)
+    main = res.get("bf16x3_refined") or next(iter(res.values()))
+    out = {"metric": "time to converged energy, mixed vs FP64 (|dE| < 1e-6 Eh)", "unit": "s",
+           "value": main["solve_s"], "higher_is_better": False, "n_gpus": 1, "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": args.workload, "no": o, "nv": v, "naux": Q, "seed": seed, "generator": "converging",
+                      "sigma": sigma, "vvvv": args.vvvv, "tol_rnorm": tol, "lowp_rnorm": args.lowp_rnorm},
+           "modes": res}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -295,6 +349,10 @@ def main():
     ap.add_argument("--max-active", type=int, default=32)
     ap.add_argument("--serve-tol", type=float, default=1e-7)
     ap.add_argument("--serve-precisions", default="", help="comma list of fp64,fp32,bf16x3 (default all)")
+    ap.add_argument("--solve", action="store_true", help="precision study: full solves of --workload per mode")
+    ap.add_argument("--solve-tol", type=float, default=1e-7)
+    ap.add_argument("--solve-maxiter", type=int, default=60)
+    ap.add_argument("--lowp-rnorm", type=float, default=1e-5)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: there is no multi-GPU path (run with --gpus 1)",
@@ -303,6 +361,9 @@ def main():
 
     if args.serve:
         serve_main(args)
+        return
+    if args.solve:
+        solve_main(args)
         return
 
     import torch

@@ -185,6 +185,9 @@ struct ascc_ints {
   // FP32 shadows of the large-contraction operands (only for a low-precision integral set)
   float *Vf, *GwzTf, *KLf;       // constant: vvvv, [ov+o^2][v^2] transposed (kc|bd)|(kc|ld), K|L
   float *Tpf, *t2f, *TUf, *XZf;  // per residual: ladder rows, t2 rows, Tx|U, Xc|Zd
+  // per residual, K = naux or o^2 contiguous: B^_ai as [ia][Q], B^_ki [ki][Q], B^_ac [ac][Q],
+  // B^_kc [kc][Q], B^_kc as [Q][kc], t2 as [ab][ij], chi [ij][kl]
+  float *BvoTtf, *BooTf, *BvvTf, *BovTf, *Bovf, *t2Tf, *chif;
   int cur_prec = 0;              // arithmetic of the large contractions in the next residual
   // multi-state batches (ascc_batch_reserve): stacked ladder operands and per-state RL
   int max_states = 0;
@@ -294,18 +297,20 @@ std::vector<std::pair<double* ascc_ints::*, long>> ints_plan(long o, long v, lon
 }
 
 // FP32 shadows allocated for a low-precision integral set.
-std::vector<std::pair<float* ascc_ints::*, long>> lowp_plan(long o, long v, int mode) {
-  const long ov = o * v, oo = o * o, vv = v * v, ovov = ov * ov;
+std::vector<std::pair<float* ascc_ints::*, long>> lowp_plan(long o, long v, long Q, int mode) {
+  const long ov = o * v, oo = o * o, vv = v * v;
   const long To = o * (o + 1) / 2, Tv = v * (v + 1) / 2;
   (void)mode;  // both storage modes keep the packed halves in low precision
   // rows x padded leading dimension (lowp_ld); one float = one bf16 hi + one bf16 lo for BF16X3
-  const long lvv = lowp_ld(vv), lTv = lowp_ld(Tv), lov = lowp_ld(ov);
-  (void)ovov;
+  const long lvv = lowp_ld(vv), lTv = lowp_ld(Tv), lov = lowp_ld(ov), lQ = lowp_ld(Q), loo = lowp_ld(oo);
   return {
-      {&ascc_ints::Vf, 2 * Tv * lTv}, {&ascc_ints::GwzTf, (ov + oo) * lvv},
+      {&ascc_ints::Vf, 2 * Tv * lTv},  {&ascc_ints::GwzTf, (ov + oo) * lvv},
       {&ascc_ints::KLf, 2 * ov * lov}, {&ascc_ints::Tpf, 2 * To * lTv},
-      {&ascc_ints::t2f, oo * lvv},                      {&ascc_ints::TUf, 2 * ov * lov},
-      {&ascc_ints::XZf, 2 * ov * lov},
+      {&ascc_ints::t2f, oo * lvv},     {&ascc_ints::TUf, 2 * ov * lov},
+      {&ascc_ints::XZf, 2 * ov * lov}, {&ascc_ints::BvoTtf, ov * lQ},
+      {&ascc_ints::BooTf, oo * lQ},    {&ascc_ints::BvvTf, vv * lQ},
+      {&ascc_ints::BovTf, ov * lQ},    {&ascc_ints::Bovf, Q * lov},
+      {&ascc_ints::t2Tf, vv * loo},    {&ascc_ints::chif, oo * loo},
   };
 }
 
@@ -519,6 +524,14 @@ GemmLP lp_nt(const ascc_ints* I, long M, long N, long K, int nb, const float* A,
   return g;
 }
 
+int lowp_kind(const ascc_ints* I) { return (I->cur_prec == ASCC_PREC_BF16X3) ? kPrecBF16x3 : kPrecFP32; }
+
+// Low-precision shadow of a transpose: out row r = column r of in ([cols][ldi]), leading dimension
+// lowp_ld(cols).
+hipError_t shadow_t(const ascc_ints* I, float* out, const double* in, long ldi, long rows, long cols, hipStream_t s) {
+  return to_lowp_t(lowp_kind(I), out, lowp_ld(cols), in, ldi, rows, cols, s);
+}
+
 // Low-precision shadow of rows x cols FP64 (contiguous rows) with leading dimension lowp_ld(cols).
 hipError_t shadow(const ascc_ints* I, float* out, const double* in, long rows, long cols, hipStream_t s) {
   const int prec = (I->cur_prec == ASCC_PREC_BF16X3) ? kPrecBF16x3 : kPrecFP32;
@@ -573,7 +586,7 @@ size_t ints_footprint(long o, long v, long Q, int precision, int mode) {
   for (const auto& item : ints_plan(o, v, Q, mode))
     off = align_up(off) + std::max<size_t>((size_t)item.second, 1) * sizeof(double);
   if (precision != ASCC_PREC_FP64)
-    for (const auto& item : lowp_plan(o, v, mode))
+    for (const auto& item : lowp_plan(o, v, Q, mode))
       off = align_up(off) + std::max<size_t>((size_t)item.second, 1) * sizeof(float);
   const long vv = v * v, wzl = o * v + o * o;
   long temp = build_temp_elems(o, v, mode, nullptr);
@@ -626,20 +639,34 @@ int residual_core(ascc_ints* I, const double* t1, const double* t2, double* r1, 
     Perm4In y[2] = {pin(t2, si, v, sj, 1, 2.0), pin(t2, si, 1, sj, v, -1.0)};
     HIPCHK(permute4(U, d, 0.0, y, 2, s));
   }
+  const bool lowp = I->cur_prec != ASCC_PREC_FP64;
+  const long lov = lowp_ld(ov), lQ = lowp_ld(Q), loo = lowp_ld(oo);
+  if (lowp) HIPCHK(shadow(I, I->TUf, I->TU, 2 * ov, ov, s));  // Tx|U rows, K = ov
 
   phase_end(I, s);
   // --- density-fitted dressed integral blocks (K = naux)
   phase_begin(I, PH_DF, s);
-  HIPCHK(mm(I, gemm_rm(ov, ov, Q, 1.0, I->BvoT, ov, true, I->BvoT, ov, false, 0.0, I->G1, ov), s));  // g^_aibj
-  HIPCHK(mm(I, gemm_rm(oo, vv, Q, 1.0, I->Boo, oo, true, I->Bvv, vv, false, 0.0, I->G2, vv), s));    // g^_kiac
-  HIPCHK(mm(I, gemm_rm(ov, ov, Q, 1.0, I->BvoT, ov, true, I->Bov, ov, false, 0.0, I->G3, ov), s));   // g^_aikc
-  HIPCHK(mm(I, gemm_rm(oo, oo, Q, 1.0, I->Boo, oo, true, I->Boo, oo, false, 0.0, I->G4, oo), s));    // g^_kilj
-  HIPCHK(mm(I, gemm_rm(Q, ov, ov, 1.0, I->Bov, ov, false, U, ov, false, 0.0, I->Nq, ov), s));        // N_Q[k,a]
+  // g^_aibj enters R2 unmultiplied by amplitudes: always FP64, so the low-precision residual's
+  // rounding floor stays proportional to the amplitudes
+  HIPCHK(mm(I, gemm_rm(ov, ov, Q, 1.0, I->BvoT, ov, true, I->BvoT, ov, false, 0.0, I->G1, ov), s));    // g^_aibj
+  if (lowp) {  // the same products on K-contiguous low-precision shadows (B^_kc ones are constant)
+    HIPCHK(shadow_t(I, I->BvoTtf, I->BvoT, ov, ov, Q, s));
+    HIPCHK(shadow_t(I, I->BooTf, I->Boo, oo, oo, Q, s));
+    HIPCHK(shadow_t(I, I->BvvTf, I->Bvv, vv, vv, Q, s));
+    HIPCHK(gemm_lowp(lp_nt(I, oo, vv, Q, 1, I->BooTf, lQ, 0, I->BvvTf, lQ, 0, I->G2, vv, 0), s));    // g^_kiac
+    HIPCHK(gemm_lowp(lp_nt(I, ov, ov, Q, 1, I->BvoTtf, lQ, 0, I->BovTf, lQ, 0, I->G3, ov, 0), s));   // g^_aikc
+    // N_Q[k,a] = sum_lc B_Q,lc u_kl^ac: U is a symmetric ov x ov matrix, so its rows are its columns
+    HIPCHK(gemm_lowp(lp_nt(I, Q, ov, ov, 1, I->Bovf, lov, 0, I->TUf + ov * lov, lov, 0, I->Nq, ov, 0), s));
+  } else {
+    HIPCHK(mm(I, gemm_rm(oo, vv, Q, 1.0, I->Boo, oo, true, I->Bvv, vv, false, 0.0, I->G2, vv), s));    // g^_kiac
+    HIPCHK(mm(I, gemm_rm(ov, ov, Q, 1.0, I->BvoT, ov, true, I->Bov, ov, false, 0.0, I->G3, ov), s));   // g^_aikc
+    HIPCHK(mm(I, gemm_rm(Q, ov, ov, 1.0, I->Bov, ov, false, U, ov, false, 0.0, I->Nq, ov), s));        // N_Q[k,a]
+  }
+  HIPCHK(mm(I, gemm_rm(oo, oo, Q, 1.0, I->Boo, oo, true, I->Boo, oo, false, 0.0, I->G4, oo), s));      // g^_kilj
 
   phase_end(I, s);
   // --- W_ij[k,b], Z_ij[k,l] in one product against [(kc|bd) | (kc|ld)]
   phase_begin(I, PH_WZ, s);
-  const bool lowp = I->cur_prec != ASCC_PREC_FP64;
   if (lowp) {
     const long ld = lowp_ld(vv);
     HIPCHK(shadow(I, I->t2f, t2, oo, vv, s));
@@ -662,14 +689,21 @@ int residual_core(ascc_ints* I, const double* t1, const double* t2, double* r1, 
   // --- particle-particle ladder over the undressed (ac|bd), plus the hole-hole ladder
   if (!RLx && (rc = pp_ladder(I, t2, s))) return rc;
   phase_begin(I, PH_HH, s);
-  HIPCHK(mm(I, gemm_rm(oo, vv, oo, 1.0, I->chi, oo, false, t2, vv, false, 1.0, RL, vv), s));
+  if (lowp) {  // RL[ij][ab] += sum_kl chi[ij][kl] t2[kl][ab], with t2 transposed to K = kl contiguous
+    HIPCHK(shadow(I, I->chif, I->chi, oo, oo, s));
+    HIPCHK(shadow_t(I, I->t2Tf, t2, vv, vv, oo, s));
+    GemmLP g = lp_nt(I, oo, vv, oo, 1, I->chif, loo, 0, I->t2Tf, loo, 0, RL, vv, 0);
+    g.beta = 1.0;
+    HIPCHK(gemm_lowp(g, s));
+  } else {
+    HIPCHK(mm(I, gemm_rm(oo, vv, oo, 1.0, I->chi, oo, false, t2, vv, false, 1.0, RL, vv), s));
+  }
   phase_end(I, s);
 
   // --- rings: Y1 = Tx K, Y2 = U L (batched pair)
   phase_begin(I, PH_RING_Y, s);
   if (lowp) {  // K and L are symmetric matrices, so B[n][k] = B[k][n]
-    const long ld = lowp_ld(ov);
-    HIPCHK(shadow(I, I->TUf, I->TU, 2 * ov, ov, s));
+    const long ld = lov;
     HIPCHK(gemm_lowp(lp_nt(I, ov, ov, ov, 2, I->TUf, ld, ov * ld, I->KLf, ld, ov * ld, I->Y, ov, ovov), s));
   } else {
     Gemm g = gemm_rm(ov, ov, ov, 1.0, I->TU, ov, false, I->KL, ov, false, 0.0, I->Y, ov);
@@ -998,6 +1032,9 @@ int build_lowp_shadows(ascc_ints* I, hipStream_t s) {
     HIPCHK(shadow(I, I->Vf, I->V, 2 * Tv, Tv, s));
   }
   HIPCHK(shadow(I, I->KLf, I->KL, 2 * ov, ov, s));
+  const long Q = I->naux;
+  HIPCHK(shadow_t(I, I->BovTf, I->Bov, ov, ov, Q, s));  // B_kc (undressed by T1) as [kc][Q]
+  HIPCHK(shadow(I, I->Bovf, I->Bov, Q, ov, s));         // and as [Q][kc]
   double* tmp = nullptr;
   Pool tmp_alloc = sub_pool(I->pool);
   int rc = dalloc(tmp_alloc, &tmp, (size_t)(wzl * vv));
@@ -1148,7 +1185,7 @@ static int build_ints_impl(const double* d_B, const double* d_fock, int fock_is_
     if (!rc) rc = dalloc(I->pool, &(I->*(item.first)), (size_t)item.second);
   }
   if (precision != ASCC_PREC_FP64) {
-    for (const auto& item : lowp_plan(no, nv, vvvv_mode)) {
+    for (const auto& item : lowp_plan(no, nv, naux, vvvv_mode)) {
       if (!rc) rc = dalloc(I->pool, &(I->*(item.first)), (size_t)item.second);
     }
   }
@@ -1377,6 +1414,7 @@ int ascc_solve(ascc_ints* I, const ascc_opts* opts, double* t1, double* t2, ascc
   user.add(t2, sizeof(double) * I->oovv);
   int status = ASCC_E_NOT_CONVERGED;
   int lowp_iters = 0;
+  LowpStall stall;
   for (int it = 0; !rc && it < opts->maxiter; ++it) {
     rc = residual_fp64(I, t1, t2, r1, r2, e, s);
     if (rc) break;
@@ -1404,11 +1442,12 @@ int ascc_solve(ascc_ints* I, const ascc_opts* opts, double* t1, double* t2, ascc
     }
     if (lowp_phase) {
       // low-precision bulk: no convergence test; hand over to FP64 once the residual is small
-      // enough or the low-precision budget is spent (the DIIS history restarts in FP64)
+      // enough, stops improving (its rounding floor), or the low-precision budget is spent (the
+      // DIIS history restarts in FP64)
       ++lowp_iters;
       res->lowp_iterations = lowp_iters;
       const bool done = (opts->lowp_rnorm > 0 && hstats[3] <= opts->lowp_rnorm) ||
-                        (opts->lowp_maxiter > 0 && lowp_iters >= opts->lowp_maxiter);
+                        (opts->lowp_maxiter > 0 && lowp_iters >= opts->lowp_maxiter) || stall.stalled(hstats[3]);
       if (done) {
         lowp_phase = false;
         I->cur_prec = ASCC_PREC_FP64;

@@ -233,6 +233,40 @@ __global__ __launch_bounds__(256) void split_bf16_2d_kernel(unsigned short* __re
   }
 }
 
+// Transposing low-precision shadow: out row r (< rows) holds in[c][r] for c < cols, zero padding
+// up to ldo (a multiple of 32), laid out as to_lowp_2d lays out its rows.  32 x 32 tiles through
+// LDS, so both the reads (along r) and the writes (along c) are coalesced.
+template <bool BF>
+__global__ __launch_bounds__(256) void lowp_t_kernel(void* __restrict__ outp, long ldo, const double* __restrict__ in,
+                                                     long ldi, long rows, long cols) {
+  __shared__ double tile[32][33];
+  const long r0 = (long)blockIdx.x * 32, c0 = (long)blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int cy = ty + 8 * k;
+    const long r = r0 + tx, c = c0 + cy;
+    tile[cy][tx] = (r < rows && c < cols) ? in[c * ldi + r] : 0.0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int ry = ty + 8 * k;
+    const long r = r0 + ry, c = c0 + tx;
+    if (r >= rows) continue;
+    const double d = tile[tx][ry];
+    if (BF) {
+      unsigned short* out = reinterpret_cast<unsigned short*>(outp);
+      const unsigned short h = bf16_rne((float)d);
+      const long o = r * 2 * ldo + (c >> 5) * 64 + (c & 31);
+      out[o] = h;
+      out[o + 32] = bf16_rne((float)(d - (double)bf16_to_f(h)));
+    } else {
+      reinterpret_cast<float*>(outp)[r * ldo + c] = (float)d;
+    }
+  }
+}
+
 // Low-precision shadow of the vvvv halves formed from the full (ac|bd) matrix in pair order (rows
 // at stride ldv): row r = h*Tv + n (h = 0: +, 1: -), column k < Tv, zero padding up to ldo; in FP64
 // x = V[n][k] +- V[pm[n]][k], then rounded and laid out as to_lowp_2d does (FP32, or interleaved bf16).
@@ -636,6 +670,22 @@ hipError_t to_lowp_pm(int prec, float* out, long ldo, const double* V, long ldv,
                        reinterpret_cast<unsigned short*>(out), nullptr, ldo, V, ldv, pm, Tv);
   else
     hipLaunchKernelGGL(lowp_pm_kernel<false>, dim3((unsigned)g), dim3(256), 0, s, nullptr, out, ldo, V, ldv, pm, Tv);
+  return hipGetLastError();
+}
+
+hipError_t to_lowp_t(int prec, float* out, long ldo, const double* in, long ldi, long rows, long cols, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  if ((ldo & 31) || ldo < cols || ldi < rows || (rows + 31) / 32 > 0x7fffffffL || ldo / 32 > 65535)
+    return hipErrorInvalidValue;
+  if (bounds_checking() && !(range_ok(out, 0, rows * ldo - 1, 4, "transposed shadow") &&
+                             range_ok(in, 0, (cols - 1) * ldi + rows - 1, 8, "transposed shadow source")))
+    return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  const dim3 grid((unsigned)((rows + 31) / 32), (unsigned)(ldo / 32));
+  if (prec == kPrecBF16x3)
+    hipLaunchKernelGGL(lowp_t_kernel<true>, grid, dim3(256), 0, s, (void*)out, ldo, in, ldi, rows, cols);
+  else
+    hipLaunchKernelGGL(lowp_t_kernel<false>, grid, dim3(256), 0, s, (void*)out, ldo, in, ldi, rows, cols);
   return hipGetLastError();
 }
 

@@ -99,11 +99,31 @@ hipError_t gemm_lowp(const GemmLP& g, hipStream_t s);
 // same bytes as bf16, row stride 2 ldo, each K-block of 32 stored as hi[32] then lo[32] with
 // hi = RNE_bf16(x), lo = RNE_bf16(x - hi).
 hipError_t to_lowp_2d(int prec, float* out, long ldo, const double* in, long ldi, long rows, long cols, hipStream_t s);
+// Transposed shadow: out row r (r < rows) = column r of in ([cols][ldi] FP64), padded to ldo.
+hipError_t to_lowp_t(int prec, float* out, long ldo, const double* in, long ldi, long rows, long cols, hipStream_t s);
 // Packed vvvv halves [2][Tv][ldo] (zero padded) in low precision, formed from the full (ac|bd)
 // matrix in pair order [vrows][ldv] as gemm_f64_ladder forms them (V[n][k] +- V[pm[n]][k]).
 hipError_t to_lowp_pm(int prec, float* out, long ldo, const double* V, long ldv, long vrows, const int* pm, long Tv,
                       hipStream_t s);
 inline long lowp_ld(long k) { return (k + 31) / 32 * 32; }
+
+// Hand-over test of a low-precision bulk phase: the residual norm has reached the rounding floor
+// of the contractions when it has not set a new minimum (by 1%) for kPatience iterations.
+struct LowpStall {
+  static constexpr int kPatience = 4;
+  double best = 0.0;
+  int since = 0;
+  bool stalled(double rnorm) {
+    if (since == 0 && best == 0.0) best = rnorm;
+    if (rnorm < 0.99 * best) {
+      best = rnorm;
+      since = 0;
+    } else {
+      ++since;
+    }
+    return since >= kPatience;
+  }
+};
 
 // ---------------------------------------------------------------------------------------
 // Element-wise kernels (elementwise.hip).

@@ -47,6 +47,7 @@ struct Request {
   hipEvent_t ev = nullptr;
   hipGraphExec_t g_low = nullptr, g_fp64 = nullptr;
   bool inflight = false, lowp_phase = false;
+  LowpStall stall;
   int iterations = 0, lowp_iterations = 0;
   double e_corr = 0, rnorm = 0, rmax = 0, de = 0;
 };
@@ -266,7 +267,7 @@ bool consume(ascc_server* S, Request* R, double now) {
   if (R->lowp_phase) {
     R->lowp_iterations += 1;
     const bool done = (o.lowp_rnorm > 0 && st[3] <= o.lowp_rnorm) ||
-                      (o.lowp_maxiter > 0 && R->lowp_iterations >= o.lowp_maxiter);
+                      (o.lowp_maxiter > 0 && R->lowp_iterations >= o.lowp_maxiter) || R->stall.stalled(st[3]);
     if (done) {
       R->lowp_phase = false;
       (void)ascc_set_precision(R->ints, ASCC_PREC_FP64);
