@@ -262,6 +262,7 @@ def serve_main(args):
             continue
         r = run_serving(P, arrivals, reqs, pc, budget, args.max_active, args.serve_tol)
         res[name] = r
+        print(f"serving mode {name}: {r['solves_per_s']:.3f} solves/s", file=sys.stderr, flush=True)
     base = res.get("fp64")
     for name, r in res.items():
         if base is not None and name != "fp64":
@@ -311,6 +312,7 @@ def solve_main(args):
                          raise_on_not_converged=False)
         torch.cuda.synchronize()
         t_solve = time.perf_counter() - t0
+        print(f"solve mode {name}: {t_solve:.2f} s, {r['iterations']} iterations", file=sys.stderr, flush=True)
         res[name] = {"e_corr": r["e_corr"], "rnorm": r["rnorm"], "rmax": r["rmax"], "iterations": r["iterations"],
                      "lowp_iterations": r["lowp_iterations"], "converged": r["converged"],
                      "solve_s": round(t_solve, 3), "build_s": round(t_build, 3)}

@@ -43,29 +43,76 @@ __global__ __launch_bounds__(kThreads) void permute4_kernel(P4 p, long total) {
   }
 }
 
+// Same operation when the output is contiguous along i3 and some inputs are contiguous along
+// another index t instead (a transposition): 32 x 32 tiles over (i_t, i3) for fixed (i_u, i_w);
+// the transposed inputs (bit q of tmask) are summed into an LDS tile with reads along i_t, the
+// others are read along i3 with the output row, so reads and writes are coalesced.
+__global__ __launch_bounds__(kThreads) void permute4_tiled_kernel(P4 p, int t, int u, int w, int tiles3, int tmask) {
+  __shared__ double tile[32][33];
+  const int it0 = (blockIdx.x / tiles3) * 32, i30 = (blockIdx.x % tiles3) * 32;
+  const long iu = blockIdx.y, iw = blockIdx.z;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  const int dt = p.d[t], d3 = p.d[3];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {  // tile[i3 - i30][it - it0], reads along it
+    const long i3 = i30 + ty + 8 * k, it = it0 + tx;
+    double acc = 0.0;
+    if (i3 < d3 && it < dt)
+      for (int q = 0; q < p.nin; ++q)
+        if ((tmask >> q) & 1)
+          acc += p.coef[q] * p.in[q][iu * p.s[q][u] + iw * p.s[q][w] + it * p.s[q][t] + i3 * p.s[q][3]];
+    tile[ty + 8 * k][tx] = acc;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {  // output along i3
+    const long it = it0 + ty + 8 * k, i3 = i30 + tx;
+    if (it < dt && i3 < d3) {
+      double* o = p.out + iu * p.os[u] + iw * p.os[w] + it * p.os[t] + i3 * p.os[3];
+      double v = (p.c0 == 0.0) ? 0.0 : p.c0 * *o;
+      for (int q = 0; q < p.nin; ++q)
+        if (!((tmask >> q) & 1)) v += p.coef[q] * p.in[q][iu * p.s[q][u] + iw * p.s[q][w] + it * p.s[q][t] + i3 * p.s[q][3]];
+      *o = v + tile[tx][ty + 8 * k];
+    }
+  }
+}
+
 // Doubles residual, element (i,j,a,b) of the [o][o][v][v] output:
 //   R = G1[iajb] + RL[ijab] + EM[ijab] + EM[jiba]
 //       - 1/2 (P1[jbia] + P1[iajb]) + 1/2 (P2[jbia] + P2[iajb]) - (P1[ibja] + P1[jaib])
-// (ovov arrays are [o][v][o][v]).
+// (ovov arrays are [o][v][o][v]).  One workgroup per (i, j) and 32 x 32 block of (a, b): the four
+// terms that run along a (EM[jiba], P1[jbia], P2[jbia], P1[ibja]) are summed into an LDS tile
+// with reads along a, then the output row is written along b, where every other term is
+// contiguous, so all reads and writes are coalesced.
 __global__ __launch_bounds__(kThreads) void assemble_r2_kernel(double* __restrict__ r2, const double* __restrict__ g1,
                                                               const double* __restrict__ rl,
                                                               const double* __restrict__ em,
                                                               const double* __restrict__ p1,
-                                                              const double* __restrict__ p2, int o, int v, long total) {
-  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
-    long r = idx;
-    const int b = r % v;
-    r /= v;
-    const int a = r % v;
-    r /= v;
-    const int j = r % o;
-    const int i = r / o;
-    auto ov = [&](int p, int x, int q, int y) -> long { return ((long)(p * v + x) * o + q) * v + y; };
-    auto oo = [&](int p, int q, int x, int y) -> long { return ((long)(p * o + q) * v + x) * v + y; };
-    const long iajb = ov(i, a, j, b), jbia = ov(j, b, i, a), ibja = ov(i, b, j, a), jaib = ov(j, a, i, b);
-    double x = g1[iajb] + rl[idx] + em[idx] + em[oo(j, i, b, a)];
-    x += -0.5 * (p1[jbia] + p1[iajb]) + 0.5 * (p2[jbia] + p2[iajb]) - (p1[ibja] + p1[jaib]);
-    r2[idx] = x;
+                                                              const double* __restrict__ p2, int o, int v) {
+  __shared__ double tile[32][33];
+  const int tv = (v + 31) / 32;
+  const int a0 = (blockIdx.x / tv) * 32, b0 = (blockIdx.x % tv) * 32;
+  const int i = blockIdx.y, j = blockIdx.z;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  auto ov = [&](int p, int x, int q, int y) -> long { return ((long)(p * v + x) * o + q) * v + y; };
+  const long ij = ((long)i * o + j) * v * v, ji = ((long)j * o + i) * v * v;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {  // tile[b - b0][a - a0], reads along a
+    const int b = b0 + ty + 8 * k, a = a0 + tx;
+    double t = 0.0;
+    if (a < v && b < v)
+      t = em[ji + (long)b * v + a] - 0.5 * p1[ov(j, b, i, a)] + 0.5 * p2[ov(j, b, i, a)] - p1[ov(i, b, j, a)];
+    tile[ty + 8 * k][tx] = t;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {  // output along b
+    const int a = a0 + ty + 8 * k, b = b0 + tx;
+    if (a < v && b < v) {
+      const long x = ij + (long)a * v + b;
+      const long iajb = ov(i, a, j, b);
+      r2[x] = g1[iajb] + rl[x] + em[x] - 0.5 * p1[iajb] + 0.5 * p2[iajb] - p1[ov(j, a, i, b)] + tile[tx][ty + 8 * k];
+    }
   }
 }
 
@@ -488,6 +535,52 @@ static bool p4_in_bounds(const P4& p) {
   return true;
 }
 
+// Drops size-1 dimensions (the remaining ones keep their order, right-aligned), then takes the
+// tiled kernel when the output is contiguous along its last index and some input is contiguous
+// along another index of at least 16.
+static hipError_t launch_permute(P4 p, long total, hipStream_t s) {
+  P4 c = p;
+  int k2 = 3;
+  for (int k = 3; k >= 0; --k) {
+    if (p.d[k] == 1) continue;
+    c.d[k2] = p.d[k];
+    c.os[k2] = p.os[k];
+    for (int q = 0; q < p.nin; ++q) c.s[q][k2] = p.s[q][k];
+    --k2;
+  }
+  for (; k2 >= 0; --k2) {
+    c.d[k2] = 1;
+    c.os[k2] = 0;
+    for (int q = 0; q < p.nin; ++q) c.s[q][k2] = 0;
+  }
+  int t = -1, tmask = 0;
+  if (c.os[3] == 1 && c.d[3] >= 16) {
+    for (int k = 2; k >= 0 && t < 0; --k) {
+      if (c.d[k] < 16) continue;
+      int m = 0;
+      for (int q = 0; q < c.nin; ++q)
+        if (c.s[q][k] == 1 && c.s[q][3] != 1) m |= 1 << q;
+      if (m) {
+        t = k;
+        tmask = m;
+      }
+    }
+  }
+  if (t >= 0) {
+    int u = -1, w = -1;
+    for (int k = 0; k < 3; ++k)
+      if (k != t) (u < 0 ? u : w) = k;
+    const long tiles_t = (c.d[t] + 31) / 32, tiles3 = (c.d[3] + 31) / 32;
+    if (tiles_t * tiles3 <= 0x7fffffffL && c.d[u] <= 65535 && c.d[w] <= 65535) {
+      hipLaunchKernelGGL(permute4_tiled_kernel, dim3((unsigned)(tiles_t * tiles3), (unsigned)c.d[u], (unsigned)c.d[w]),
+                         dim3(kThreads), 0, s, c, t, u, w, (int)tiles3, tmask);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL(permute4_kernel, dim3(grid_for(total)), dim3(kThreads), 0, s, p, total);
+  return hipGetLastError();
+}
+
 hipError_t permute4(double* out, const int dims[4], double c0, const Perm4In* in, int nin, hipStream_t s) {
   // contiguous output with the given dims
   P4 p{};
@@ -508,8 +601,7 @@ hipError_t permute4(double* out, const int dims[4], double c0, const Perm4In* in
   if (total <= 0) return hipSuccess;
   if (bounds_checking() && !p4_in_bounds(p)) return hipErrorInvalidValue;
   if (dry_run()) return hipSuccess;
-  hipLaunchKernelGGL(permute4_kernel, dim3(grid_for(total)), dim3(kThreads), 0, s, p, total);
-  return hipGetLastError();
+  return launch_permute(p, total, s);
 }
 
 hipError_t permute4_strided(double* out, const long ostr[4], const int dims[4], double c0, const Perm4In* in,
@@ -531,8 +623,7 @@ hipError_t permute4_strided(double* out, const long ostr[4], const int dims[4], 
   if (total <= 0) return hipSuccess;
   if (bounds_checking() && !p4_in_bounds(p)) return hipErrorInvalidValue;
   if (dry_run()) return hipSuccess;
-  hipLaunchKernelGGL(permute4_kernel, dim3(grid_for(total)), dim3(kThreads), 0, s, p, total);
-  return hipGetLastError();
+  return launch_permute(p, total, s);
 }
 
 hipError_t assemble_r2(double* r2, const double* g1, const double* rl, const double* em, const double* p1,
@@ -545,8 +636,9 @@ hipError_t assemble_r2(double* r2, const double* g1, const double* rl, const dou
         range_ok(p1, 0, ovov - 1, 8, "assemble p1") && range_ok(p2, 0, ovov - 1, 8, "assemble p2")))
     return hipErrorInvalidValue;
   if (dry_run()) return hipSuccess;
-  hipLaunchKernelGGL(assemble_r2_kernel, dim3(grid_for(total)), dim3(kThreads), 0, s, r2, g1, rl, em, p1, p2, no,
-                     nv, total);
+  const int tv = (nv + 31) / 32;
+  hipLaunchKernelGGL(assemble_r2_kernel, dim3((unsigned)(tv * tv), (unsigned)no, (unsigned)no), dim3(kThreads), 0, s, r2,
+                     g1, rl, em, p1, p2, no, nv);
   return hipGetLastError();
 }
 
