@@ -53,6 +53,7 @@ LADDER_SOURCE = {"fp64": "gemm_f64.hip", "fp32": "gemm_lowp.hip", "bf16x3": "gem
 # changed since then reports null.
 TRAFFIC = {
     ("o20v180q600", "full", "fp64"): (4.72e9, "6f8b9630d77823b544c9f3b95e7eb93892c6b64b3dd4a39a5014a9738b326860"),
+    ("o40v360q1200", "packed", "bf16x3"): (148.5e9, "8ad008633cc3e480492421d76a3250465080aeffeda05d027978bf5093ec2ec6"),
 }
 
 
