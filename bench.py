@@ -207,9 +207,10 @@ def serve_requests(nreq: int):
     return arrivals, reqs
 
 
-def run_serving(P, arrivals, reqs, precision: int, budget: int, max_active: int, tol_rnorm: float):
+def run_serving(P, arrivals, reqs, precision: int, budget: int, max_active: int, tol_rnorm: float,
+                lowp_rnorm: float = 1e-5):
     srv = P.Server(budget, max_active=max_active, precision=precision, vvvv_mode=P.ASCC_VVVV_PACKED,
-                   use_graphs=True, tol_rnorm=tol_rnorm, maxiter=150, lowp_rnorm=1e-5)
+                   use_graphs=True, tol_rnorm=tol_rnorm, maxiter=150, lowp_rnorm=lowp_rnorm)
     n = len(reqs)
     ids = []
     t0 = time.perf_counter()
@@ -255,13 +256,13 @@ def serve_main(args):
            "config": {"workload": f"serve{args.requests}", "arrival_rate_per_s": 20, "no": "U{4..24}",
                       "nv": "9 no", "naux": "3 (no + nv)", "seeds": f"100..{99 + args.requests}",
                       "generator": "converging", "hbm_budget_gb": args.budget_gb, "max_active": args.max_active,
-                      "tol_rnorm": args.serve_tol, "vvvv": "packed"}}
+                      "tol_rnorm": args.serve_tol, "lowp_rnorm": args.lowp_rnorm, "vvvv": "packed"}}
     res = {}
     for name, pc in (("bf16x3_refined", P.ASCC_PREC_BF16X3), ("fp32_refined", P.ASCC_PREC_FP32),
                      ("fp64", P.ASCC_PREC_FP64)):
         if args.serve_precisions and name.split("_")[0] not in args.serve_precisions.split(","):
             continue
-        r = run_serving(P, arrivals, reqs, pc, budget, args.max_active, args.serve_tol)
+        r = run_serving(P, arrivals, reqs, pc, budget, args.max_active, args.serve_tol, args.lowp_rnorm)
         res[name] = r
         print(f"serving mode {name}: {r['solves_per_s']:.3f} solves/s", file=sys.stderr, flush=True)
     base = res.get("fp64")
@@ -355,7 +356,8 @@ def main():
     ap.add_argument("--solve", action="store_true", help="precision study: full solves of --workload per mode")
     ap.add_argument("--solve-tol", type=float, default=1e-7)
     ap.add_argument("--solve-maxiter", type=int, default=60)
-    ap.add_argument("--lowp-rnorm", type=float, default=1e-5)
+    ap.add_argument("--lowp-rnorm", type=float, default=1e-7,
+                    help="hand-over residual norm of the low-precision bulk (the rounding-floor test also applies)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: there is no multi-GPU path (run with --gpus 1)",

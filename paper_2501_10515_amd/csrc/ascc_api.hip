@@ -268,7 +268,7 @@ uintptr_t fake_alloc(size_t bytes) {
 // Pair-row tables of a FULL integral set (see gemm_f64_ladder).
 inline int* pair_minus(const ascc_ints* I) { return reinterpret_cast<int*>(I->pairtab); }
 
-constexpr long kSplitKElems = 1L << 22;  // 32 MiB of split-K partials
+constexpr long kSplitKElems = 1L << 23;  // 64 MiB of split-K partials
 
 // Every device array of an integral set with its element count, in allocation order; the
 // same list gives ascc_workspace_bytes its exact answer.

@@ -392,7 +392,10 @@ hipError_t gemm_f64(const Gemm& g, hipStream_t s) {
   const bool amf = (g.sam == 1 && g.sak != 1);
   const bool bnf = (g.sbn == 1) || (g.sbk != 1);
   const long tiles128 = (long)((g.M + 127) / 128) * ((g.N + 127) / 128) * nbatch;
-  if (g.M >= 96 && g.N >= 96 && tiles128 >= 256) return launch_cfg<128, 128, ASCC_GEMM_BK, 2, 2>(p, amf, bnf, g.nb1, g.ws, g.ws_elems, s);
+  // 128 x 128 tiles when they fill the chip, or when a long K lets split-K make up the count
+  const bool long_k = g.ws && (long)g.K * g.nred >= 8192 && tiles128 >= 64;
+  if (g.M >= 96 && g.N >= 96 && (tiles128 >= 256 || long_k))
+    return launch_cfg<128, 128, ASCC_GEMM_BK, 2, 2>(p, amf, bnf, g.nb1, g.ws, g.ws_elems, s);
   const long tiles64 = (long)((g.M + 63) / 64) * ((g.N + 63) / 64) * nbatch;
   if (g.M >= 48 && g.N >= 48 && tiles64 >= 128) return launch_cfg<64, 64, 16, 2, 2>(p, amf, bnf, g.nb1, g.ws, g.ws_elems, s);
   return launch_cfg<32, 32, 16, 1, 1>(p, amf, bnf, g.nb1, g.ws, g.ws_elems, s);
