@@ -7,8 +7,9 @@ python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--vvvv fu
 A step is one pass of the whole iteration on the device: T1 dressing, every residual term,
 the energy and residual-norm reductions, the Jacobi update and DIIS (ascc_residual followed
 by ascc_update), starting from T = 0 and continuing the real iteration sequence.  Inputs are
-generated on the host from the seeded recipe in gen/synth_df.py and copied to HBM before the
-timed region; the integral set (including the vvvv block) is built before it as well.
+generated on the host from the seeded recipe in gen/synth_df.py (by default at the
+convergence-variant width, so the timed steps are a converging iteration with finite values; the
+work per step does not depend on the values) and copied to HBM before the timed region; the integral set (including the vvvv block) is built before it as well.
 
 value = F_N6 / seconds-per-step in TFLOP/s, with the fixed algorithmic count
 F_N6(o,v) = 2[T(o)T(v)^2 + S(o)S(v)^2] + 4 o^4 v^2 + 10 o^3 v^3 (T(n) = n(n+1)/2, S(n) = n(n-1)/2).
@@ -52,7 +53,7 @@ LADDER_SOURCE = {"fp64": "gemm_f64.hip", "fp32": "gemm_lowp.hip", "bf16x3": "gem
 # (workload, vvvv, precision) with the sha256 of the kernel source they were taken on: a kernel
 # changed since then reports null.
 TRAFFIC = {
-    ("o20v180q600", "full", "fp64"): (4.72e9, "6f8b9630d77823b544c9f3b95e7eb93892c6b64b3dd4a39a5014a9738b326860"),
+    ("o20v180q600", "full", "fp64"): (4.854e9, "3b15a4311da48af103d0df122e7bfc85d253be8e0d090854514c533d9633113f"),
     ("o40v360q1200", "packed", "bf16x3"): (148.5e9, "8ad008633cc3e480492421d76a3250465080aeffeda05d027978bf5093ec2ec6"),
 }
 
@@ -344,7 +345,8 @@ def main():
     ap.add_argument("--workload", default="o20v180q600", choices=sorted(WORKLOADS))
     ap.add_argument("--vvvv", default="full", choices=["full", "packed"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"])
-    ap.add_argument("--generator", default="literal", choices=["literal", "converging"])
+    ap.add_argument("--generator", default="converging", choices=["literal", "converging"],
+                    help="integral width: the convergence variant (default) or the literal sigma = 0.05")
     ap.add_argument("--no-compare", action="store_true", help="skip the low-precision comparison runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve", action="store_true", help="run the request-serving workload instead")

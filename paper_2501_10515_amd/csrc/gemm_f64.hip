@@ -7,16 +7,18 @@
 // is just another pair of strides), tiles are staged through LDS, and each wave64 owns a
 // (BM/WM) x (BN/WN) block of the output.
 //
-// The inner product uses v_mfma_f64_4x4x4_f64 (four independent 4x4x4 products per wave64),
-// which sustains about 1.6x the FP64 rate of the 16x16x4 form on gfx950 (measured with register
-// operands: ~72-75 vs ~45-49 TFLOP/s).  Lane layout (gfx950, measured): lane l belongs to block
-// q = (l%16)/4, supplies A_q(l%4, l/16) and B_q(l/16, l%4), and receives D_q(l/16, l%4); the
-// CBSZ/ABID broadcast fields have no effect on this instruction, so operands are arranged in
-// registers instead (see the main loop).
+// The inner product uses v_mfma_f64_16x16x4_f64.  With register operands the 4x4x4 form issues
+// more FP64 work per cycle on gfx950, but fed from LDS the 16x16x4 form wins (3-8% on the
+// residual's shapes, measured): a 64 x 64 wave tile needs 16 instructions and 8 LDS reads per
+// K-step of 4 instead of 64 and 20.  Lane layout (measured): lane l supplies A(l%16, l/16) and
+// B(l/16, l%16); register r of the result holds D(l/16 + 4r, l%16).
 //
-// The particle-particle ladder has its own entry point (gemm_f64_ladder): 256 x 128 tiles when
-// the pair dimension fits them, and optionally the symmetric/antisymmetric vvvv combinations
-// formed while staging from the stored full (ac|bd) matrix.
+// Tile configurations: 128 x 128 (4 waves, two workgroups per CU), 256 x 128 and 192 x 192
+// (8 waves, one per CU), all with K staged 16 deep, chosen per call by how well whole rounds of 256 workgroups cover
+// the output; 64 x 64 and 32 x 32 for small outputs; 128 x 128 with split-K when a long K meets
+// too few tiles.  The particle-particle ladder has its own entry point (gemm_f64_ladder): 256-,
+// 224- or 128-row tiles, whichever pads the pair dimension least, and optionally the
+// symmetric/antisymmetric vvvv combinations formed while staging from the stored full (ac|bd).
 #include <algorithm>
 
 #include "internal.h"
@@ -59,23 +61,17 @@ __device__ __forceinline__ void tile_of(int bid, int tiles_m, int tiles_n, int& 
   tn = r / gs;
 }
 
-#ifndef ASCC_GEMM_BK
-#define ASCC_GEMM_BK 8  // K depth of one LDS stage of the 128x128 tile
-#endif
-#ifndef ASCC_GEMM_MINBLOCKS
-#define ASCC_GEMM_MINBLOCKS 2  // workgroups per CU the 128x128 tile is register-budgeted for
-#endif
-
 // PM: B is pair-combined (ladder against the full (ac|bd) in pair order): for batch z2 = 0 (+)
 // or 1 (-), B(k, n) = V[n][k] +- V[pm[n]][k] (rows of V at stride sbn).
-template <int BM, int BN, int BK, int WM, int WN, bool AMF, bool BNF, bool PM = false>
-__global__ __launch_bounds__(WM* WN * 64, (WM * WN >= 8) ? 1 : (WM * WN >= 4) ? ASCC_GEMM_MINBLOCKS : 4) void gemm_f64_kernel(GP p) {
+// MINB: workgroups per CU the register budget is sized for.
+template <int BM, int BN, int BK, int WM, int WN, int MINB, bool AMF, bool BNF, bool PM = false>
+__global__ __launch_bounds__(WM* WN * 64, MINB) void gemm_f64_kernel(GP p) {
   constexpr int NT = WM * WN * 64;
   constexpr int TM = BM / WM, TN = BN / WN;
-  constexpr int RB = TM / 4, CP = TN / 16;
+  constexpr int RI = TM / 16, RJ = TN / 16;
   constexpr int LA = BM * BK / NT, LB = BK * BN / NT;
   constexpr int PA = BM + 1, PB = BN + 1;  // +1 double: conflict-free transposing stores
-  static_assert(RB >= 1 && CP >= 1 && LA >= 1 && LB >= 1 && TM % 4 == 0 && TN % 16 == 0, "tile config");
+  static_assert(RI >= 1 && RJ >= 1 && LA >= 1 && LB >= 1 && TM % 16 == 0 && TN % 16 == 0, "tile config");
   static_assert(!PM || (!BNF && NT % BK == 0), "pair-combined B is staged k-fast");
   __shared__ double As[2][BK * PA];
   __shared__ double Bs[2][BK * PB];
@@ -103,19 +99,20 @@ __global__ __launch_bounds__(WM* WN * 64, (WM * WN >= 8) ? 1 : (WM * WN >= 4) ? 
   const double* Bb = p.B + z1 * p.sb1 + z2 * p.sb2;
   double* Cb = p.C + z1 * p.sc1 + z2 * p.sc2;
 
-  // acc[x][y]: lane l holds C(4x + l/16, 16y + l%16) of the wave's tile (x: 4-row block,
-  // y: 16-column panel)
-  double acc[RB][CP];
+  // acc[i][j]: register r of lane l holds C(16i + l/16 + 4r, 16j + l%16) of the wave's tile
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  d4 acc[RI][RJ];
 #pragma unroll
-  for (int x = 0; x < RB; ++x)
+  for (int i = 0; i < RI; ++i)
 #pragma unroll
-    for (int y = 0; y < CP; ++y) acc[x][y] = 0.0;
+    for (int j = 0; j < RJ; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
   const int nkt = (p.K + BK - 1) / BK;
   const int it_begin = slice * p.it_per_split;
   const int it_end = min(nkt * p.nred, it_begin + p.it_per_split);
 
   double ra[LA], rb[LB];
+  double rw[PM ? LB : 1];  // pair-combined B: second row, combined with rb only when staged to LDS
   // pair-combined B: the two V rows of each staged pair n are fixed for the whole K loop
   const double* pva[PM ? LB : 1];
   const double* pvb[PM ? LB : 1];
@@ -128,6 +125,7 @@ __global__ __launch_bounds__(WM* WN * 64, (WM * WN >= 8) ? 1 : (WM * WN >= 4) ? 
     }
   }
   const bool minus = PM && z2 == 1;
+  (void)rw;
   auto load = [&](int it) {
     const int r = it / nkt, k0 = (it % nkt) * BK;
     const double* Ar = Ab + r * p.sar;
@@ -144,12 +142,9 @@ __global__ __launch_bounds__(WM* WN * 64, (WM * WN >= 8) ? 1 : (WM * WN >= 4) ? 
       const int gk = k0 + tid % BK;  // the same k for every element this thread stages
 #pragma unroll
       for (int l = 0; l < LB; ++l) {
-        double x = 0.0;
-        if (pva[l] && gk < p.K) {
-          const double u = pva[l][gk], w = pvb[l][gk];
-          x = minus ? u - w : u + w;
-        }
-        rb[l] = x;
+        const bool ok = pva[l] && gk < p.K;
+        rb[l] = ok ? pva[l][gk] : 0.0;
+        rw[l] = ok ? pvb[l][gk] : 0.0;
       }
       (void)Br;
     } else {
@@ -176,15 +171,15 @@ __global__ __launch_bounds__(WM* WN * 64, (WM * WN >= 8) ? 1 : (WM * WN >= 4) ? 
       const int e = tid + l * NT;
       const int n = BNF ? (e % BN) : (e / BK);
       const int k = BNF ? (e / BN) : (e % BK);
-      Bs[buf][k * PB + n] = rb[l];
+      // the combination waits for the loads here, after the MFMAs, not where they are issued
+      if constexpr (PM)
+        Bs[buf][k * PB + n] = minus ? rb[l] - rw[l] : rb[l] + rw[l];
+      else
+        Bs[buf][k * PB + n] = rb[l];
     }
   };
 
-  // Operands of v_mfma_f64_4x4x4 (block q = (l%16)/4 of lane l; A_q(l%4, l/16), B_q(l/16, l%4)):
-  // the A register of 4-row block x carries the same four rows in all four blocks (each group of
-  // 16 lanes reads 4 distinct LDS words), the B register of panel y gives block q the columns
-  // 16y + 4q .. 16y + 4q + 3, so one instruction yields C(4x .. 4x+3, 16y .. 16y+15).
-  const int fk = lane >> 4, fa = lane & 3, fb = lane & 15;
+  const int lk = lane >> 4, l16 = lane & 15;
   if (it_begin < it_end) {
     load(it_begin);
     store(0);
@@ -193,19 +188,19 @@ __global__ __launch_bounds__(WM* WN * 64, (WM * WN >= 8) ? 1 : (WM * WN >= 4) ? 
   for (int it = it_begin; it < it_end; ++it) {
     const int cur = (it - it_begin) & 1;
     if (it + 1 < it_end) load(it + 1);
-    const double* as = As[cur] + fk * PA + wm * TM + fa;
-    const double* bs = Bs[cur] + fk * PB + wn * TN + fb;
+    const double* as = As[cur] + lk * PA + wm * TM + l16;
+    const double* bs = Bs[cur] + lk * PB + wn * TN + l16;
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
-      double b[CP];
+      double a[RI], b[RJ];
 #pragma unroll
-      for (int y = 0; y < CP; ++y) b[y] = bs[kk * PB + 16 * y];
+      for (int i = 0; i < RI; ++i) a[i] = as[kk * PA + 16 * i];
 #pragma unroll
-      for (int x = 0; x < RB; ++x) {
-        const double a = as[kk * PA + 4 * x];
+      for (int j = 0; j < RJ; ++j) b[j] = bs[kk * PB + 16 * j];
 #pragma unroll
-        for (int y = 0; y < CP; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, b[y], acc[x][y], 0, 0, 0);
-      }
+      for (int i = 0; i < RI; ++i)
+#pragma unroll
+        for (int j = 0; j < RJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     if (it + 1 < it_end) store(cur ^ 1);
     __syncthreads();
@@ -213,22 +208,24 @@ __global__ __launch_bounds__(WM* WN * 64, (WM * WN >= 8) ? 1 : (WM * WN >= 4) ? 
 
   // epilogue
 #pragma unroll
-  for (int x = 0; x < RB; ++x)
+  for (int i = 0; i < RI; ++i)
 #pragma unroll
-    for (int y = 0; y < CP; ++y) {
-      const int gm = m0 + wm * TM + 4 * x + fk;
-      const int gn = n0 + wn * TN + 16 * y + fb;
-      if (gm < p.M && gn < p.N) {
-        const double v = p.alpha * acc[x][y];
-        if (p.split > 1) {
-          const long zl = (long)z1 * gridDim.y + z2;
-          p.part[(((long)slice * gridDim.z * gridDim.y + zl) * p.M + gm) * p.N + gn] = v;
-        } else {
-          double* c = Cb + gm * p.scm + gn * p.scn;
-          *c = (p.beta == 0.0) ? v : v + p.beta * *c;
+    for (int j = 0; j < RJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + wm * TM + 16 * i + lk + 4 * r;
+        const int gn = n0 + wn * TN + 16 * j + l16;
+        if (gm < p.M && gn < p.N) {
+          const double v = p.alpha * acc[i][j][r];
+          if (p.split > 1) {
+            const long zl = (long)z1 * gridDim.y + z2;
+            p.part[(((long)slice * gridDim.z * gridDim.y + zl) * p.M + gm) * p.N + gn] = v;
+          } else {
+            double* c = Cb + gm * p.scm + gn * p.scn;
+            *c = (p.beta == 0.0) ? v : v + p.beta * *c;
+          }
         }
       }
-    }
 }
 
 // C_z(m,n) = beta * C_z(m,n) + sum_s part[s][z][m][n], summed in slice order.
@@ -245,7 +242,7 @@ __global__ __launch_bounds__(256) void splitk_reduce(GP p, int nb1, long total) 
   }
 }
 
-template <int BM, int BN, int BK, int WM, int WN>
+template <int BM, int BN, int BK, int WM, int WN, int MINB>
 hipError_t launch_cfg(const GP& p0, bool amf, bool bnf, int nb1, double* ws, long ws_elems, hipStream_t s) {
   GP p = p0;
   p.tiles_m = (p.M + BM - 1) / BM;
@@ -257,7 +254,8 @@ hipError_t launch_cfg(const GP& p0, bool amf, bool bnf, int nb1, double* ws, lon
   p.part = nullptr;
   const long outs = (long)p.M * p.N * p.nb2 * nb1;
   if (ws && tiles < 192 && nit >= 16) {
-    int sp = (int)std::min<long>({(512 + tiles - 1) / tiles, (long)nit / 8, 256L});
+    // slices enough for one full round of resident workgroups (MINB per CU)
+    int sp = (int)std::min<long>({(256L * MINB + tiles - 1) / tiles, (long)nit / 8, 256L});
     if (ws_elems > 0) sp = (int)std::min<long>(sp, ws_elems / std::max<long>(outs, 1));
     if (sp > 1) {
       p.it_per_split = (nit + sp - 1) / sp;
@@ -268,13 +266,13 @@ hipError_t launch_cfg(const GP& p0, bool amf, bool bnf, int nb1, double* ws, lon
   dim3 grid(p.tiles_m * p.tiles_n * p.split, p.nb2, nb1);
   dim3 block(WM * WN * 64);
   if (amf && bnf)
-    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, WM, WN, true, true>), grid, block, 0, s, p);
+    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, WM, WN, MINB, true, true>), grid, block, 0, s, p);
   else if (amf)
-    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, WM, WN, true, false>), grid, block, 0, s, p);
+    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, WM, WN, MINB, true, false>), grid, block, 0, s, p);
   else if (bnf)
-    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, WM, WN, false, true>), grid, block, 0, s, p);
+    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, WM, WN, MINB, false, true>), grid, block, 0, s, p);
   else
-    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, WM, WN, false, false>), grid, block, 0, s, p);
+    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, WM, WN, MINB, false, false>), grid, block, 0, s, p);
   if (p.split > 1) {
     const long blocks = std::min<long>((outs + 255) / 256, 4096);
     hipLaunchKernelGGL(splitk_reduce, dim3((unsigned)blocks), dim3(256), 0, s, p, nb1, outs);
@@ -282,21 +280,22 @@ hipError_t launch_cfg(const GP& p0, bool amf, bool bnf, int nb1, double* ws, lon
   return hipGetLastError();
 }
 
-// Ladder: both halves (grid.y = 2), no split-K, A/B staged k-fast.
+// Ladder: BM x 128 tiles of 8 waves, both halves (grid.y = 2), no split-K, A/B staged k-fast.
 template <int BM, int WM>
 hipError_t launch_ladder(GP p, bool pm, hipStream_t s) {
+  constexpr int BK = 16, WN = 8 / WM;
   p.tiles_m = (p.M + BM - 1) / BM;
   p.tiles_n = (p.N + 127) / 128;
   p.split = 1;
-  p.it_per_split = (p.K + ASCC_GEMM_BK - 1) / ASCC_GEMM_BK;
+  p.it_per_split = (p.K + BK - 1) / BK;
   p.part = nullptr;
   const int tiles = p.tiles_m * p.tiles_n;
   // pair-combined: the two halves interleave in grid.x (see the kernel), padded to groups of 8
-  dim3 grid(pm ? 2 * ((tiles + 7) / 8 * 8) : tiles, pm ? 1 : 2, 1), block(WM * 2 * 64);
+  dim3 grid(pm ? 2 * ((tiles + 7) / 8 * 8) : tiles, pm ? 1 : 2, 1), block(512);
   if (pm)
-    hipLaunchKernelGGL((gemm_f64_kernel<BM, 128, ASCC_GEMM_BK, WM, 2, false, false, true>), grid, block, 0, s, p);
+    hipLaunchKernelGGL((gemm_f64_kernel<BM, 128, BK, WM, WN, 1, false, false, true>), grid, block, 0, s, p);
   else
-    hipLaunchKernelGGL((gemm_f64_kernel<BM, 128, ASCC_GEMM_BK, WM, 2, false, false, false>), grid, block, 0, s, p);
+    hipLaunchKernelGGL((gemm_f64_kernel<BM, 128, BK, WM, WN, 1, false, false, false>), grid, block, 0, s, p);
   return hipGetLastError();
 }
 
@@ -392,13 +391,26 @@ hipError_t gemm_f64(const Gemm& g, hipStream_t s) {
   const bool amf = (g.sam == 1 && g.sak != 1);
   const bool bnf = (g.sbn == 1) || (g.sbk != 1);
   const long tiles128 = (long)((g.M + 127) / 128) * ((g.N + 127) / 128) * nbatch;
-  // 128 x 128 tiles when they fill the chip, or when a long K lets split-K make up the count
+  if (g.M >= 96 && g.N >= 96 && tiles128 >= 256) {
+    // Large outputs: among 128x128 (4 waves), 256x128 and 192x192 (8 waves) take the least
+    // estimated time = whole rounds of 256 tiles x tile area / sustained rate (measured on full
+    // rounds: 59.5, 60, 61.5 TFLOP/s), which prices both the padding of M and N and the partly
+    // filled last round.
+    auto est = [&](int bm, int bn, double rate) {
+      const long t = (long)((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn) * nbatch;
+      return (double)((t + 255) / 256) * bm * bn / rate;
+    };
+    const double e128 = est(128, 128, 59.5), e256 = est(256, 128, 60.0), e192 = est(192, 192, 61.5);
+    if (e192 < e128 && e192 <= e256) return launch_cfg<192, 192, 16, 2, 4, 1>(p, amf, bnf, g.nb1, nullptr, 0, s);
+    if (e256 < e128) return launch_cfg<256, 128, 16, 4, 2, 1>(p, amf, bnf, g.nb1, nullptr, 0, s);
+    return launch_cfg<128, 128, 16, 2, 2, 2>(p, amf, bnf, g.nb1, g.ws, g.ws_elems, s);
+  }
+  // a long K lets split-K make up for too few 128 x 128 tiles
   const bool long_k = g.ws && (long)g.K * g.nred >= 8192 && tiles128 >= 64;
-  if (g.M >= 96 && g.N >= 96 && (tiles128 >= 256 || long_k))
-    return launch_cfg<128, 128, ASCC_GEMM_BK, 2, 2>(p, amf, bnf, g.nb1, g.ws, g.ws_elems, s);
+  if (g.M >= 96 && g.N >= 96 && long_k) return launch_cfg<128, 128, 16, 2, 2, 2>(p, amf, bnf, g.nb1, g.ws, g.ws_elems, s);
   const long tiles64 = (long)((g.M + 63) / 64) * ((g.N + 63) / 64) * nbatch;
-  if (g.M >= 48 && g.N >= 48 && tiles64 >= 128) return launch_cfg<64, 64, 16, 2, 2>(p, amf, bnf, g.nb1, g.ws, g.ws_elems, s);
-  return launch_cfg<32, 32, 16, 1, 1>(p, amf, bnf, g.nb1, g.ws, g.ws_elems, s);
+  if (g.M >= 48 && g.N >= 48 && tiles64 >= 128) return launch_cfg<64, 64, 16, 2, 2, 2>(p, amf, bnf, g.nb1, g.ws, g.ws_elems, s);
+  return launch_cfg<32, 32, 16, 1, 1, 3>(p, amf, bnf, g.nb1, g.ws, g.ws_elems, s);
 }
 
 hipError_t gemm_f64_ladder(int M, int Tv, const double* A, const double* V, long ldv, long vrows, const int* pm,
@@ -436,10 +448,11 @@ hipError_t gemm_f64_ladder(int M, int Tv, const double* A, const double* V, long
   p.nb2 = 2;
   p.nred = 1;
   p.pm = pm;
-  // 256-row tiles read the vvvv operand once per 256 pair rows; take them unless their row
-  // padding costs more than the 128-row tiles' second pass
-  const long pad256 = (M + 255L) / 256 * 256, pad128 = (M + 127L) / 128 * 128;
-  if (pad256 * 19 <= pad128 * 20) return launch_ladder<256, 4>(p, pmode, s);
+  // Row tiles of 256, 224 or 128 pair rows: the least padded M wins (each extra row is a full
+  // row of wasted products); on a tie the taller tile, which reads the vvvv operand fewer times.
+  const long pad256 = (M + 255L) / 256 * 256, pad224 = (M + 223L) / 224 * 224, pad128 = (M + 127L) / 128 * 128;
+  if (pad256 <= pad224 && pad256 <= pad128) return launch_ladder<256, 4>(p, pmode, s);
+  if (pad224 <= pad128) return launch_ladder<224, 2>(p, pmode, s);
   return launch_ladder<128, 2>(p, pmode, s);
 }
 
