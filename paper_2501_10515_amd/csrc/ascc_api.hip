@@ -515,6 +515,8 @@ GemmLP lp_nt(const ascc_ints* I, long M, long N, long K, int nb, const float* A,
   g.scn = 1;
   g.sc2 = sc2;
   g.prec = (I->cur_prec == ASCC_PREC_BF16X3) ? kPrecBF16x3 : kPrecFP32;
+  g.ws = I->splitk;
+  g.ws_elems = kSplitKElems;
   if (g.prec == kPrecBF16x3) {  // one float of a shadow = one bf16 pair: strides in bf16 elements
     g.lda *= 2;
     g.sa2 *= 2;
@@ -563,8 +565,11 @@ int pp_ladder_states(ascc_ints* I, int S, const double* const* t2s, double* cons
   if (lowp) HIPCHK(shadow(I, Tpf, Tp, 2 * M, Tv, s));
   phase_end(I, s);
   phase_begin(I, PH_LADDER, s);
-  if (lowp)
-    HIPCHK(gemm_lowp(lp_nt(I, M, Tv, Tv, 2, Tpf, ld, M * ld, I->Vf, ld, Tv * ld, Rp, Tv, M * Tv), s));
+  if (lowp) {  // no split-K: a state's rows are summed in the same order whatever S is
+    GemmLP g = lp_nt(I, M, Tv, Tv, 2, Tpf, ld, M * ld, I->Vf, ld, Tv * ld, Rp, Tv, M * Tv);
+    g.ws = nullptr;
+    HIPCHK(gemm_lowp(g, s));
+  }
   else if (full)
     HIPCHK(gemm_f64_ladder((int)M, (int)Tv, Tp, I->V, I->vv, I->vv, pair_minus(I), Rp, s));
   else

@@ -38,7 +38,9 @@ struct LP {
   long scm, scn, sc2;
   double alpha, beta;
   int tiles_m, tiles_n;
-  int chunk;  // K-tiles per FP32 accumulation chunk
+  int chunk;    // K-tiles per FP32 accumulation chunk
+  int ktps;     // K-tiles per split-K slice (blockIdx.z); the whole K when not split
+  long cslice;  // C offset between slices (partial tiles of a split launch), 0 otherwise
 };
 
 // Round-to-nearest-even FP32 -> bf16 bits (finite inputs; NaN stays NaN).
@@ -95,7 +97,7 @@ __global__ __launch_bounds__(NT, 1) void gemm_lowp_kernel(LP p) {
   const int z = blockIdx.y;
   const float* Ab = p.A + z * p.sa2;
   const float* Bb = p.B + z * p.sb2;
-  double* Cb = p.C + z * p.sc2;
+  double* Cb = p.C + z * p.sc2 + blockIdx.z * p.cslice;
 
   f4 acc[4][4];
 #pragma unroll
@@ -103,7 +105,8 @@ __global__ __launch_bounds__(NT, 1) void gemm_lowp_kernel(LP p) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
-  const int nkt = (p.K + BK - 1) / BK;
+  // K-tiles [kt0, nkt) of this split-K slice
+  const int kt0 = blockIdx.z * p.ktps, nkt = min((p.K + BK - 1) / BK, kt0 + p.ktps);
   f4 ra[LQ], rb[LQ];
   // chunk c = tid + NT*l of the tile: row c/8, k offset 4*(c%8)
   auto load = [&](int kt) {
@@ -171,15 +174,15 @@ __global__ __launch_bounds__(NT, 1) void gemm_lowp_kernel(LP p) {
   };
 
   const int lr = lane & 15, lg = lane >> 4;
-  if (nkt > 0) {
-    load(0);
+  if (kt0 < nkt) {
+    load(kt0);
     store(0);
   }
   __syncthreads();
-  for (int kc = 0; kc < nkt; kc += p.chunk) {
+  for (int kc = kt0; kc < nkt; kc += p.chunk) {
   const int kend = min(nkt, kc + p.chunk);
   for (int kt = kc; kt < kend; ++kt) {
-    const int cur = kt & 1;
+    const int cur = (kt - kt0) & 1;
     if (kt + 1 < nkt) load(kt + 1);
     const float* as = As[cur];
     const float* bs = Bs[cur];
@@ -198,9 +201,9 @@ __global__ __launch_bounds__(NT, 1) void gemm_lowp_kernel(LP p) {
     if (kt + 1 < nkt) store(cur ^ 1);
     __syncthreads();
   }
-  flush(kc == 0);
+  flush(kc == kt0);
   }
-  if (nkt == 0) flush(true);
+  if (kt0 >= nkt) flush(true);
 }
 
 // Row-padded conversions: out row r holds in row r (cols values) then zeros up to ldo.
@@ -325,6 +328,8 @@ struct LPB {
   double alpha, beta;
   int tiles_m, tiles_n;
   int chunk;
+  int ktps;
+  long cslice;
 };
 
 constexpr int BM2 = 256, BN2 = 128, BK2 = 32, NT2 = 512;
@@ -341,7 +346,7 @@ __global__ __launch_bounds__(NT2, 1) void gemm_bf16x3_kernel(LPB p) {
   const int z = blockIdx.y;
   const unsigned short* Ab = p.A + z * p.sa2;
   const unsigned short* Bb = p.B + z * p.sb2;
-  double* Cb = p.C + z * p.sc2;
+  double* Cb = p.C + z * p.sc2 + blockIdx.z * p.cslice;
 
   f4 acc[4][4];
 #pragma unroll
@@ -349,7 +354,7 @@ __global__ __launch_bounds__(NT2, 1) void gemm_bf16x3_kernel(LPB p) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
-  const int nkt = (p.K + BK2 - 1) / BK2;
+  const int kt0 = blockIdx.z * p.ktps, nkt = min((p.K + BK2 - 1) / BK2, kt0 + p.ktps);
   u4 ra[4], rb[2];
   // Workgroup-uniform bases (scalar registers) plus 32-bit per-lane element offsets keep the
   // address arithmetic out of the vector register budget.
@@ -417,15 +422,15 @@ __global__ __launch_bounds__(NT2, 1) void gemm_bf16x3_kernel(LPB p) {
   };
 
   const int lr = lane & 15, lg = lane >> 4;
-  if (nkt > 0) {
-    load(0);
+  if (kt0 < nkt) {
+    load(kt0);
     store(0);
   }
   __syncthreads();
-  for (int kc = 0; kc < nkt; kc += p.chunk) {
+  for (int kc = kt0; kc < nkt; kc += p.chunk) {
     const int kend = min(nkt, kc + p.chunk);
     for (int kt = kc; kt < kend; ++kt) {
-      const int cur = kt & 1;
+      const int cur = (kt - kt0) & 1;
       if (kt + 1 < nkt) load(kt + 1);
       // all A fragments stay in registers; B fragments are loaded one 16-column panel at a time
       bf8 xa[4][2];
@@ -450,9 +455,9 @@ __global__ __launch_bounds__(NT2, 1) void gemm_bf16x3_kernel(LPB p) {
       if (kt + 1 < nkt) store(cur ^ 1);
       __syncthreads();
     }
-    flush(kc == 0);
+    flush(kc == kt0);
   }
-  if (nkt == 0) flush(true);
+  if (kt0 >= nkt) flush(true);
 }
 
 // 256 x 256 tiles, four waves of 128 x 128 (8 x 8 fragments, accumulators in AGPRs).  Each wave
@@ -491,7 +496,7 @@ __global__ __launch_bounds__(NT3, 1) void gemm_bf16x3_dma_kernel(LPB p) {
       __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_t*)(dst + g * 1024), 16, off, 0, 0, 0);
     }
   };
-  double* Cb = p.C + z * p.sc2;
+  double* Cb = p.C + z * p.sc2 + blockIdx.z * p.cslice;
   f4 acc[8][8];
 #pragma unroll
   for (int i = 0; i < 8; ++i)
@@ -516,13 +521,13 @@ __global__ __launch_bounds__(NT3, 1) void gemm_bf16x3_dma_kernel(LPB p) {
           acc[i][j][q] = 0.f;
         }
   };
-  const int nkt = (p.K + 31) / 32;
+  const int kt0 = blockIdx.z * p.ktps, nkt = min((p.K + 31) / 32, kt0 + p.ktps);
   const int lr = lane & 15, lg = lane >> 4;
-  if (nkt > 0) issue(0, 0);
-  for (int kc = 0; kc < nkt; kc += p.chunk) {
+  if (kt0 < nkt) issue(kt0, 0);
+  for (int kc = kt0; kc < nkt; kc += p.chunk) {
     const int kend = min(nkt, kc + p.chunk);
     for (int kt = kc; kt < kend; ++kt) {
-      const int cur = kt & 1;
+      const int cur = (kt - kt0) & 1;
       __builtin_amdgcn_s_waitcnt(0xF70);  // vmcnt(0): this wave's part of stage kt has landed
       __syncthreads();                     // every wave's has; stage cur ^ 1 is no longer read
       bf8 xa[8][2], xb[8][2];
@@ -548,11 +553,42 @@ __global__ __launch_bounds__(NT3, 1) void gemm_bf16x3_dma_kernel(LPB p) {
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[i][0], xb[j][0], acc[i][j], 0, 0, 0);
         }
     }
-    flush(kc == 0);
+    flush(kc == kt0);
   }
-  if (nkt == 0) flush(true);
+  if (kt0 >= nkt) flush(true);
 }
 
+
+// C_z(m,n) = beta * C_z(m,n) + sum_s part[s][z][m][n], summed in slice order.
+__global__ __launch_bounds__(256) void lowp_splitk_reduce(double* C, long scm, long scn, long sc2, double beta,
+                                                          const double* part, int M, int N, long total, int split) {
+  for (long x = blockIdx.x * 256L + threadIdx.x; x < total; x += (long)gridDim.x * 256) {
+    const long mn = (long)M * N;
+    const long z = x / mn, r = x % mn;
+    const int m = (int)(r / N), n = (int)(r % N);
+    double acc = 0.0;
+    for (int sl = 0; sl < split; ++sl) acc += part[(long)sl * total + x];
+    double* c = C + z * sc2 + m * scm + n * scn;
+    *c = (beta == 0.0) ? acc : acc + beta * *c;
+  }
+}
+
+// Split-K plan for a launch of `tiles` workgroups (one per CU) over nkt K-tiles of 32: slices of
+// at least 16 K-tiles, enough of them for one round of 256 workgroups, as the scratch allows.
+struct SplitPlan {
+  int split = 1, ktps = 0;
+};
+SplitPlan plan_split(const GemmLP& g, long tiles, int nkt) {
+  SplitPlan sp;
+  sp.ktps = nkt;
+  const long outs = (long)g.M * g.N * g.nb;
+  if (!g.ws || tiles >= 192 || nkt < 32) return sp;
+  long n = std::min<long>({(256 + tiles - 1) / tiles, (long)nkt / 16, g.ws_elems / std::max<long>(outs, 1)});
+  if (n < 2) return sp;
+  sp.ktps = (int)((nkt + n - 1) / n);
+  sp.split = (nkt + sp.ktps - 1) / sp.ktps;
+  return sp;
+}
 
 }  // namespace
 
@@ -593,7 +629,8 @@ hipError_t gemm_lowp(const GemmLP& g, hipStream_t s) {
       if (d < 0) lo += d; else hi += d;
     }
     const size_t el = bf ? 2 : 4;
-    if (!(range_ok(g.A, 0, la, el, "lowp A") && range_ok(g.B, 0, lb, el, "lowp B") && range_ok(g.C, lo, hi, 8, "lowp C")))
+    if (!(range_ok(g.A, 0, la, el, "lowp A") && range_ok(g.B, 0, lb, el, "lowp B") && range_ok(g.C, lo, hi, 8, "lowp C") &&
+          (!g.ws || range_ok(g.ws, 0, g.ws_elems - 1, 8, "lowp split-K scratch"))))
       return hipErrorInvalidValue;
   }
   if (dry_run()) return hipSuccess;
@@ -616,16 +653,34 @@ hipError_t gemm_lowp(const GemmLP& g, hipStream_t s) {
     p.alpha = g.alpha;
     p.beta = g.beta;
     p.chunk = chunk;
+    p.cslice = 0;
+    const int nkt = (g.K + 31) / 32;
     // buffer descriptors cover one tile's rows: 256 * ld bf16 must stay below 2^31 bytes
     const long t3 = (long)((g.M + BM3 - 1) / BM3) * ((g.N + BN3 - 1) / BN3) * g.nb;
     if (t3 >= 256 && 512L * g.lda < (1L << 31)) {
       p.tiles_m = (g.M + BM3 - 1) / BM3;
       p.tiles_n = (g.N + BN3 - 1) / BN3;
+      p.ktps = nkt;
       hipLaunchKernelGGL(gemm_bf16x3_dma_kernel, dim3(p.tiles_m * p.tiles_n, g.nb, 1), dim3(NT3), 0, s, p);
-    } else {
-      p.tiles_m = (g.M + BM2 - 1) / BM2;
-      p.tiles_n = (g.N + BN2 - 1) / BN2;
-      hipLaunchKernelGGL(gemm_bf16x3_kernel, dim3(p.tiles_m * p.tiles_n, g.nb, 1), dim3(NT2), 0, s, p);
+      return hipGetLastError();
+    }
+    p.tiles_m = (g.M + BM2 - 1) / BM2;
+    p.tiles_n = (g.N + BN2 - 1) / BN2;
+    const SplitPlan sp = plan_split(g, (long)p.tiles_m * p.tiles_n * g.nb, nkt);
+    p.ktps = sp.ktps;
+    if (sp.split > 1) {  // partial tiles [split][nb][M][N] in the scratch, then the ordered sum
+      p.C = g.ws;
+      p.scm = g.N;
+      p.scn = 1;
+      p.sc2 = (long)g.M * g.N;
+      p.cslice = (long)g.M * g.N * g.nb;
+      p.beta = 0.0;
+    }
+    hipLaunchKernelGGL(gemm_bf16x3_kernel, dim3(p.tiles_m * p.tiles_n, g.nb, sp.split), dim3(NT2), 0, s, p);
+    if (sp.split > 1) {
+      const long total = (long)g.M * g.N * g.nb;
+      hipLaunchKernelGGL(lowp_splitk_reduce, dim3((unsigned)std::min<long>((total + 255) / 256, 4096)), dim3(256), 0, s,
+                         g.C, g.scm, g.scn, g.sc2, g.beta, g.ws, g.M, g.N, total, sp.split);
     }
     return hipGetLastError();
   }
@@ -648,8 +703,23 @@ hipError_t gemm_lowp(const GemmLP& g, hipStream_t s) {
   p.tiles_m = (g.M + BM - 1) / BM;
   p.tiles_n = (g.N + BN - 1) / BN;
   p.chunk = chunk;
-  dim3 grid(p.tiles_m * p.tiles_n, g.nb, 1);
-  hipLaunchKernelGGL(gemm_lowp_kernel, grid, dim3(NT), 0, s, p);
+  p.cslice = 0;
+  const SplitPlan sp = plan_split(g, (long)p.tiles_m * p.tiles_n * g.nb, (g.K + 31) / 32);
+  p.ktps = sp.ktps;
+  if (sp.split > 1) {
+    p.C = g.ws;
+    p.scm = g.N;
+    p.scn = 1;
+    p.sc2 = (long)g.M * g.N;
+    p.cslice = (long)g.M * g.N * g.nb;
+    p.beta = 0.0;
+  }
+  hipLaunchKernelGGL(gemm_lowp_kernel, dim3(p.tiles_m * p.tiles_n, g.nb, sp.split), dim3(NT), 0, s, p);
+  if (sp.split > 1) {
+    const long total = (long)g.M * g.N * g.nb;
+    hipLaunchKernelGGL(lowp_splitk_reduce, dim3((unsigned)std::min<long>((total + 255) / 256, 4096)), dim3(256), 0, s,
+                       g.C, g.scm, g.scn, g.sc2, g.beta, g.ws, g.M, g.N, total, sp.split);
+  }
   return hipGetLastError();
 }
 

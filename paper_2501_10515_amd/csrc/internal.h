@@ -92,6 +92,11 @@ struct GemmLP {
   int chunk_ktiles = 0;
   // BF16X3: A and B are interleaved splits (see to_lowp_2d); lda, ldb, sa2, sb2 count bf16
   // elements (lda == ldb, multiples of 64, lda / 2 >= K)
+  // Optional split-K scratch: an output with too few tiles to fill the chip has its K range cut
+  // into slices (each at least 512 of K, each FP32 chunk starting at its slice's start) whose
+  // FP64 partial tiles land here and are then summed in slice order (deterministic).
+  double* ws = nullptr;
+  long ws_elems = 0;
 };
 hipError_t gemm_lowp(const GemmLP& g, hipStream_t s);
 // Low-precision shadow of a row-major FP64 matrix with the leading dimension padded to ldo
