@@ -169,8 +169,10 @@ struct ascc_ints {
   double* pairtab;  // FULL: int32 [T(v)]: row R(b,a) of V for pair p(a,b), a <= b
   double *Tp, *Rp;  // ladder operands [2][T(o)][T(v)]: t+- (pack_tpm) and R+- (unpack_rpm)
   // residual work arrays
-  double *Bt, *Bh;               // [Q][n][n]
-  double *ht, *Fh;               // [n][n]
+  double* Bc;                    // [Q][n][o] T1 correction of the first o columns of B
+  double* Bh;                    // [Q][n][n]
+  double* hc;                    // [n][o]
+  double* Fh;                    // [n][n]
   double *J;                     // [Q]
   double *BvoT, *Boo, *Bvv;      // [Q][o][v] (B^_ai at [Q][i][a]), [Q][o][o], [Q][v][v]
   double *G1, *G2, *G3, *G4;     // ovov, [k][i][a][c], ovov, [k][i][l][j]
@@ -283,7 +285,7 @@ std::vector<std::pair<double* ascc_ints::*, long>> ints_plan(long o, long v, lon
       {&ascc_ints::V, full ? vv * vv : 2 * Tv * Tv},
       {&ascc_ints::pairtab, full ? Tv : 0},
       {&ascc_ints::Tp, 2 * To * Tv},  {&ascc_ints::Rp, 2 * To * Tv},
-      {&ascc_ints::Bt, Q * nn},       {&ascc_ints::Bh, Q * nn},      {&ascc_ints::ht, nn},
+      {&ascc_ints::Bc, Q * n * o},    {&ascc_ints::Bh, Q * nn},      {&ascc_ints::hc, n * o},
       {&ascc_ints::Fh, nn},           {&ascc_ints::J, Q},            {&ascc_ints::BvoT, Q * ov},
       {&ascc_ints::Boo, Q * oo},      {&ascc_ints::Bvv, Q * vv},     {&ascc_ints::G1, ovov},
       {&ascc_ints::G2, oo * vv},      {&ascc_ints::G3, ovov},        {&ascc_ints::G4, oo * oo},
@@ -392,59 +394,37 @@ inline Perm4In pin(const double* p, long s0, long s1, long s2, long s3, double c
   return x;
 }
 
-// Bt = B Y^T then Bh = X Bt on `nb` stacked n x n matrices (the T1 dressing).
+// FP64 contraction with the integral set's split-K scratch.
 inline hipError_t mm(const ascc_ints* I, Gemm g, hipStream_t s) {
   g.ws = I->splitk;
   g.ws_elems = kSplitKElems;
   return gemm_f64(g, s);
 }
 
-int dress(const ascc_ints* I, const double* src, double* tmp, double* dst, const double* t1, int o, int v, int nb,
+// T1 dressing of `nb` stacked n x n matrices, dst = X src Y^T with X = 1 - F, Y^T = 1 + F and
+// F[o + a][i] = t1[i][a]: one GEMM for the correction of the first o columns, tc = src[:, o:n] t1^T,
+// then one streaming pass (dress_apply) that forms dst from src and tc.
+int dress(const ascc_ints* I, const double* src, double* tc, double* dst, const double* t1, int o, int v, int nb,
           hipStream_t s) {
   const long n = o + v, nn = n * n;
-  HIPCHK(d_copy(tmp, src, sizeof(double) * nn * nb, hipMemcpyDeviceToDevice, s));
-  {  // tmp[:, 0:o] += src[:, o:n] t1^T
-    Gemm g;
-    g.M = n;
-    g.N = o;
-    g.K = v;
-    g.A = src + o;
-    g.sam = n;
-    g.sak = 1;
-    g.sa2 = nn;
-    g.B = t1;
-    g.sbk = 1;
-    g.sbn = v;
-    g.C = tmp;
-    g.scm = n;
-    g.scn = 1;
-    g.sc2 = nn;
-    g.beta = 1.0;
-    g.nb2 = nb;
-    HIPCHK(mm(I, g, s));
-  }
-  HIPCHK(d_copy(dst, tmp, sizeof(double) * nn * nb, hipMemcpyDeviceToDevice, s));
-  {  // dst[o:n, :] -= t1^T tmp[0:o, :]
-    Gemm g;
-    g.M = v;
-    g.N = n;
-    g.K = o;
-    g.A = t1;
-    g.sam = 1;
-    g.sak = v;
-    g.B = tmp;
-    g.sbk = n;
-    g.sbn = 1;
-    g.sb2 = nn;
-    g.C = dst + o * n;
-    g.scm = n;
-    g.scn = 1;
-    g.sc2 = nn;
-    g.alpha = -1.0;
-    g.beta = 1.0;
-    g.nb2 = nb;
-    HIPCHK(mm(I, g, s));
-  }
+  Gemm g;
+  g.M = (int)n;
+  g.N = o;
+  g.K = v;
+  g.A = src + o;
+  g.sam = n;
+  g.sak = 1;
+  g.sa2 = nn;
+  g.B = t1;
+  g.sbk = 1;
+  g.sbn = v;
+  g.C = tc;
+  g.scm = o;
+  g.scn = 1;
+  g.sc2 = n * o;
+  g.nb2 = nb;
+  HIPCHK(mm(I, g, s));
+  HIPCHK(dress_apply(dst, src, tc, t1, o, v, nb, s));
   return ASCC_OK;
 }
 
@@ -611,8 +591,8 @@ int residual_core(ascc_ints* I, const double* t1, const double* t2, double* r1, 
 
   // --- T1 dressing of B and of the one-electron operator, dressed Fock matrix
   phase_begin(I, PH_DRESS, s);
-  if ((rc = dress(I, I->B, I->Bt, I->Bh, t1, o, v, Q, s))) return rc;
-  if ((rc = dress(I, I->h, I->ht, I->Fh, t1, o, v, 1, s))) return rc;
+  if ((rc = dress(I, I->B, I->Bc, I->Bh, t1, o, v, Q, s))) return rc;
+  if ((rc = dress(I, I->h, I->hc, I->Fh, t1, o, v, 1, s))) return rc;
   if ((rc = add_two_electron_fock(I, I->Fh, I->Bh, I->J, o, v, Q, 1.0, s))) return rc;
 
   // --- contiguous dressed blocks

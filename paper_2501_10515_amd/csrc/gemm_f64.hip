@@ -406,7 +406,7 @@ hipError_t gemm_f64(const Gemm& g, hipStream_t s) {
     return launch_cfg<128, 128, 16, 2, 2, 2>(p, amf, bnf, g.nb1, g.ws, g.ws_elems, s);
   }
   // a long K lets split-K make up for too few 128 x 128 tiles
-  const bool long_k = g.ws && (long)g.K * g.nred >= 8192 && tiles128 >= 64;
+  const bool long_k = g.ws && (long)g.K * g.nred >= 2048 && tiles128 >= 64;
   if (g.M >= 96 && g.N >= 96 && long_k) return launch_cfg<128, 128, 16, 2, 2, 2>(p, amf, bnf, g.nb1, g.ws, g.ws_elems, s);
   const long tiles64 = (long)((g.M + 63) / 64) * ((g.N + 63) / 64) * nbatch;
   if (g.M >= 48 && g.N >= 48 && tiles64 >= 128) return launch_cfg<64, 64, 16, 2, 2, 2>(p, amf, bnf, g.nb1, g.ws, g.ws_elems, s);

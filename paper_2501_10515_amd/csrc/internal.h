@@ -163,6 +163,11 @@ hipError_t pack_vvvv(double* Vp, const double* W, int a0, int a1, int v, hipStre
 // r1[i][a] += Fhat[no+a][i]
 hipError_t add_fvo(double* r1, const double* fhat, int no, int nv, hipStream_t s);
 
+// T1 dressing of nb stacked n x n matrices S (n = o + v) given Tc[z][x][i] = sum_a S[z][x][o+a] t1[i][a]:
+//   D[p][q] = b(p, q) - [p >= o] sum_{i<o} t1[i][p-o] b(i, q),  b(x, q) = S[x][q] + [q < o] Tc[x][q].
+hipError_t dress_apply(double* D, const double* S, const double* Tc, const double* t1, int o, int v, int nb,
+                       hipStream_t s);
+
 // J[Q] = sum_k Bh[Q][k][k]
 hipError_t diag_trace(double* J, const double* Bh, int naux, int n, int no, hipStream_t s);
 
