@@ -691,7 +691,8 @@ int residual_core(ascc_ints* I, const double* t1, const double* t2, double* r1, 
     const long ld = lov;
     HIPCHK(gemm_lowp(lp_nt(I, ov, ov, ov, 2, I->TUf, ld, ov * ld, I->KLf, ld, ov * ld, I->Y, ov, ovov), s));
   } else {
-    Gemm g = gemm_rm(ov, ov, ov, 1.0, I->TU, ov, false, I->KL, ov, false, 0.0, I->Y, ov);
+    // K and L are symmetric, so B(k, n) = KL[n][k]: both operands K-contiguous
+    Gemm g = gemm_rm(ov, ov, ov, 1.0, I->TU, ov, false, I->KL, ov, true, 0.0, I->Y, ov);
     g.sa2 = ovov;
     g.sb2 = ovov;
     g.sc2 = ovov;

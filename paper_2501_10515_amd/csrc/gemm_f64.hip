@@ -20,6 +20,7 @@
 // 224- or 128-row tiles, whichever pads the pair dimension least, and optionally the
 // symmetric/antisymmetric vvvv combinations formed while staging from the stored full (ac|bd).
 #include <algorithm>
+#include <cstdint>
 
 #include "internal.h"
 
@@ -280,6 +281,185 @@ hipError_t launch_cfg(const GP& p0, bool amf, bool bnf, int nb1, double* ws, lon
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------------------
+// Direct-to-LDS path for K-contiguous operands, A(m,k) = A[m*sam + k] and B(k,n) = B[n*sbn + k]:
+// rows go from global memory straight into LDS with global_load_lds_dwordx4 (lane l of an
+// instruction writes LDS bytes 16l .. 16l + 15), S stages in flight, one barrier per stage and no
+// staging registers.  A stage holds 8 K-values of every tile row (64 bytes) with the 16-byte chunk
+// c of row r at slot c ^ ((r >> 1) & 3), which makes the fragment reads conflict-free.  Each
+// fragment read returns two K-values and feeds two MFMAs: lane group g = l / 16 supplies K = 2g to
+// the first and 2g + 1 to the second, identically for A and B.  Rows past M or N and K-values past
+// K are read from a 16-byte zero block instead, so every load instruction runs on all lanes and the
+// per-wave vmcnt bookkeeping is exact.  PM: B is pair-combined as in gemm_f64_kernel, both rows of
+// each pair staged and combined at the fragment read.
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) const void gbl_void_t;
+__device__ __attribute__((aligned(16))) double kZero16[2];
+
+// s_waitcnt vmcnt(N) (bits 3:0 and 15:14), no wait on the other counters
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt(0xF70 | (N & 15) | ((N >> 4) << 14));
+}
+
+template <int BM, int BN, int WM, int WN, int S, bool PM>
+__global__ __launch_bounds__(WM* WN * 64, 1) void gemm_f64_dma_kernel(GP p) {
+  typedef double dd2 __attribute__((ext_vector_type(2)));
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  constexpr int NW = WM * WN;
+  constexpr int TM = BM / WM, TN = BN / WN, RI = TM / 16, RJ = TN / 16;
+  constexpr int NB = PM ? 2 : 1;
+  constexpr int IA = BM / 16, IB = BN / 16, NI = IA + NB * IB;  // 1 KB load instructions per stage
+  constexpr int NPW = (NI + NW - 1) / NW, NPWMIN = NI / NW;      // per wave
+  constexpr int ROWS = BM + NB * BN;
+  static_assert(TM % 16 == 0 && TN % 16 == 0 && S >= 3 && NPWMIN >= 1, "tile config");
+  __shared__ __attribute__((aligned(1024))) double T[S][ROWS * 8];
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave / WN, wn = wave % WN;
+  const int ntiles = p.tiles_m * p.tiles_n;
+  int bid = blockIdx.x, z2 = blockIdx.y;
+  if constexpr (PM) {  // the + and - halves of a tile back to back on one XCD (see gemm_f64_kernel)
+    const int x = bid & 7, local = bid >> 3;
+    z2 = local & 1;
+    bid = ((local >> 1) << 3) | x;
+    if (bid >= ntiles) return;
+  }
+  int tm, tn;
+  tile_of(bid, p.tiles_m, p.tiles_n, tm, tn);
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int z1 = blockIdx.z;
+  const double* Ab = p.A + z1 * p.sa1 + z2 * p.sa2;
+  const double* Bb = p.B + z1 * p.sb1 + z2 * p.sb2;
+  double* Cb = p.C + z1 * p.sc1 + z2 * p.sc2;
+
+  // the source row (chunk included) of this lane in each instruction its wave issues
+  const double* src[NPW];
+  bool ok[NPW];
+  int ck[NPW];
+#pragma unroll
+  for (int j = 0; j < NPW; ++j) {
+    const int g = wave + NW * j;
+    const int r = 16 * g + (lane >> 2);
+    const int c = (lane & 3) ^ ((r >> 1) & 3);
+    const double* row = nullptr;
+    if (g < IA) {
+      const int gm = m0 + r;
+      if (gm < p.M) row = Ab + (long)gm * p.sam;
+    } else if (g < IA + IB) {
+      const int gn = n0 + r - BM;
+      if (gn < p.N) row = Bb + (long)gn * p.sbn;
+    } else if (g < NI) {
+      const int gn = n0 + r - BM - BN;
+      if (gn < p.N) row = Bb + (long)p.pm[gn] * p.sbn;
+    }
+    ok[j] = row != nullptr;
+    ck[j] = 2 * c;
+    src[j] = ok[j] ? row + 2 * c : kZero16;
+  }
+  const int nkt = (p.K + 7) / 8;
+  auto issue = [&](int kt, int st) {
+#pragma unroll
+    for (int j = 0; j < NPW; ++j) {
+      const int g = wave + NW * j;
+      if (NPW * NW == NI || g < NI) {
+        const double* a = (ok[j] && kt * 8 + ck[j] < p.K) ? src[j] + kt * 8 : kZero16;
+        __builtin_amdgcn_global_load_lds((gbl_void_t*)a, (lds_void_t*)&T[st][g * 128], 16, 0, 0);
+      }
+    }
+  };
+
+  d4 acc[RI][RJ];
+#pragma unroll
+  for (int i = 0; i < RI; ++i)
+#pragma unroll
+    for (int j = 0; j < RJ; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+  const bool minus = PM && z2 == 1;
+  const int l16 = lane & 15, q = lane >> 4;
+#pragma unroll
+  for (int st = 0; st < S - 1; ++st)
+    if (st < nkt) issue(st, st);
+  for (int kt = 0; kt < nkt; ++kt) {
+    const int st = kt % S;
+    // stage kt has landed once no more than the later stages' loads of this wave are in flight
+    if (kt + S - 2 < nkt)
+      wait_vmcnt<(S - 2) * NPWMIN>();
+    else
+      wait_vmcnt<0>();
+    // every wave has waited for its own part of the stage; no memory fence is needed (and
+    // __syncthreads would add one that drains all stages in flight)
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    const double* Ts = T[st];
+    dd2 fa[RI], fb[RJ];
+#pragma unroll
+    for (int i = 0; i < RI; ++i) {
+      const int r = wm * TM + 16 * i + l16;
+      fa[i] = *reinterpret_cast<const dd2*>(Ts + r * 8 + 2 * (q ^ ((r >> 1) & 3)));
+    }
+#pragma unroll
+    for (int j = 0; j < RJ; ++j) {
+      const int r = BM + wn * TN + 16 * j + l16;
+      fb[j] = *reinterpret_cast<const dd2*>(Ts + r * 8 + 2 * (q ^ ((r >> 1) & 3)));
+      if constexpr (PM) {
+        const int rw = r + BN;  // (r + BN) has the same swizzle as r: BN is a multiple of 16
+        const dd2 w = *reinterpret_cast<const dd2*>(Ts + rw * 8 + 2 * (q ^ ((rw >> 1) & 3)));
+        fb[j] = minus ? fb[j] - w : fb[j] + w;
+      }
+    }
+    // the stage refilled now was last read in the previous iteration, before this barrier
+    if (kt + S - 1 < nkt) issue(kt + S - 1, (kt + S - 1) % S);
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int i = 0; i < RI; ++i)
+#pragma unroll
+        for (int j = 0; j < RJ; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i][h], fb[j][h], acc[i][j], 0, 0, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < RI; ++i)
+#pragma unroll
+    for (int j = 0; j < RJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + wm * TM + 16 * i + q + 4 * r;
+        const int gn = n0 + wn * TN + 16 * j + l16;
+        if (gm < p.M && gn < p.N) {
+          const double v = p.alpha * acc[i][j][r];
+          double* c = Cb + (long)gm * p.scm + (long)gn * p.scn;
+          *c = (p.beta == 0.0) ? v : v + p.beta * *c;
+        }
+      }
+}
+
+// K-contiguous operands with 16-byte aligned rows and an even K (the loads move K-value pairs).
+bool dma_eligible(const GP& p) {
+  auto al = [](const void* x) { return (reinterpret_cast<uintptr_t>(x) & 15) == 0; };
+  return p.sak == 1 && p.sbk == 1 && p.nred == 1 && p.K % 2 == 0 && p.sam % 2 == 0 && p.sbn % 2 == 0 &&
+         p.sa1 % 2 == 0 && p.sa2 % 2 == 0 && p.sb1 % 2 == 0 && p.sb2 % 2 == 0 && al(p.A) && al(p.B);
+}
+
+template <int BM, int BN, int WM, int WN, int S>
+hipError_t launch_dma(GP p, int nb1, bool pm, hipStream_t s) {
+  p.tiles_m = (p.M + BM - 1) / BM;
+  p.tiles_n = (p.N + BN - 1) / BN;
+  p.split = 1;
+  p.part = nullptr;
+  const int tiles = p.tiles_m * p.tiles_n;
+  if (pm) {  // both halves in grid.x, padded to whole groups of 8
+    dim3 grid(2 * ((tiles + 7) / 8 * 8), 1, nb1);
+    hipLaunchKernelGGL((gemm_f64_dma_kernel<BM, BN, WM, WN, S, true>), grid, dim3(WM * WN * 64), 0, s, p);
+  } else {
+    dim3 grid(tiles, p.nb2, nb1);
+    hipLaunchKernelGGL((gemm_f64_dma_kernel<BM, BN, WM, WN, S, false>), grid, dim3(WM * WN * 64), 0, s, p);
+  }
+  return hipGetLastError();
+}
+
 // Ladder: BM x 128 tiles of 8 waves, both halves (grid.y = 2), no split-K, A/B staged k-fast.
 template <int BM, int WM>
 hipError_t launch_ladder(GP p, bool pm, hipStream_t s) {
@@ -401,6 +581,11 @@ hipError_t gemm_f64(const Gemm& g, hipStream_t s) {
       return (double)((t + 255) / 256) * bm * bn / rate;
     };
     const double e128 = est(128, 128, 59.5), e256 = est(256, 128, 60.0), e192 = est(192, 192, 61.5);
+    if (dma_eligible(p)) {  // direct-to-LDS tiles sustain ~67-68 TFLOP/s on full rounds
+      const double d192 = est(192, 192, 68.0), d256 = est(256, 128, 67.0);
+      if (d192 <= d256 && d192 < e128) return launch_dma<192, 192, 2, 4, 4>(p, g.nb1, false, s);
+      if (d256 < e128) return launch_dma<256, 128, 4, 2, 4>(p, g.nb1, false, s);
+    }
     if (e192 < e128 && e192 <= e256) return launch_cfg<192, 192, 16, 2, 4, 1>(p, amf, bnf, g.nb1, nullptr, 0, s);
     if (e256 < e128) return launch_cfg<256, 128, 16, 4, 2, 1>(p, amf, bnf, g.nb1, nullptr, 0, s);
     return launch_cfg<128, 128, 16, 2, 2, 2>(p, amf, bnf, g.nb1, g.ws, g.ws_elems, s);
@@ -451,6 +636,11 @@ hipError_t gemm_f64_ladder(int M, int Tv, const double* A, const double* V, long
   // Row tiles of 256, 224 or 128 pair rows: the least padded M wins (each extra row is a full
   // row of wasted products); on a tie the taller tile, which reads the vvvv operand fewer times.
   const long pad256 = (M + 255L) / 256 * 256, pad224 = (M + 223L) / 224 * 224, pad128 = (M + 127L) / 128 * 128;
+  if (dma_eligible(p)) {
+    if (pad256 <= pad224 && pad256 <= pad128) return launch_dma<256, 128, 4, 2, 4>(p, 1, pmode, s);
+    if (pad224 <= pad128) return launch_dma<224, 128, 2, 4, 4>(p, 1, pmode, s);
+    return launch_dma<128, 128, 2, 4, 4>(p, 1, pmode, s);
+  }
   if (pad256 <= pad224 && pad256 <= pad128) return launch_ladder<256, 4>(p, pmode, s);
   if (pad224 <= pad128) return launch_ladder<224, 2>(p, pmode, s);
   return launch_ladder<128, 2>(p, pmode, s);
