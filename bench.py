@@ -44,7 +44,8 @@ from gen.synth_df import WORKLOADS, converging_sigma, make_system, single_excita
 
 METRIC = "N^6 residual TFLOP/s, mixed vs FP64 @|dE|<1e-6 Eh; solves/s + p99 latency"
 FP64_MFMA_PEAK_TFLOPS = 78.6
-LADDER_KERNEL = {"fp64": "gemm_f64_kernel", "fp32": "gemm_lowp_kernel",
+LADDER_KERNEL = {"fp64": "gemm_f64_dma_kernel (direct-to-LDS; gemm_f64_kernel for odd strides)",
+                 "fp32": "gemm_lowp_kernel",
                  "bf16x3": "gemm_bf16x3_dma_kernel or gemm_bf16x3_kernel by size"}
 LADDER_SOURCE = {"fp64": "gemm_f64.hip", "fp32": "gemm_lowp.hip", "bf16x3": "gemm_lowp.hip"}
 
@@ -53,7 +54,7 @@ LADDER_SOURCE = {"fp64": "gemm_f64.hip", "fp32": "gemm_lowp.hip", "bf16x3": "gem
 # (workload, vvvv, precision) with the sha256 of the kernel source they were taken on: a kernel
 # changed since then reports null.
 TRAFFIC = {
-    ("o20v180q600", "full", "fp64"): (4.854e9, "3b15a4311da48af103d0df122e7bfc85d253be8e0d090854514c533d9633113f"),
+    ("o20v180q600", "full", "fp64"): (5.404e+09, "35aec536ebd2588a9f455e548effffe6dcd46e4582a2812acc43ede0c27503ed"),
     ("o40v360q1200", "packed", "bf16x3"): (148.5e9, "8ad008633cc3e480492421d76a3250465080aeffeda05d027978bf5093ec2ec6"),
 }
 

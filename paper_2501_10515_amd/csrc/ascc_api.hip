@@ -161,9 +161,10 @@ struct ascc_ints {
   double* eps;    // [n] Fock diagonal
   double* fov;    // [o][v] reference Fock, occupied-virtual block
   double* Bov;    // [Q][o][v]
+  double* BovT;   // [o][v][Q]: the same, K = Q contiguous
   double* KL;     // [2][ov][ov]: (ib|ja), 2(ia|jb) - (ib|ja)
   double* Lijab;  // [o][o][v][v]: 2(ia|jb) - (ib|ja)
-  double* Gwz;    // [v][v][ov + o^2]: (kc|bd) at [c][d][k*v+b], (kc|ld) at [c][d][ov + k*o+l]
+  double* Gwz;    // [ov + o^2][v][v]: (kc|bd) at [k*v+b][c][d], (kc|ld) at [ov + k*o+l][c][d]
   double* V;      // FULL: [v^2][v^2], (ac|bd) at [R(a,b)][R(c,d)] (pair order: a <= b first, see pack_full)
                   // PACKED: [2][T(v)][T(v)], (ac|bd) +- (ad|bc) at [p(a,b)][p(c,d)], a <= b, c <= d
   double* pairtab;  // FULL: int32 [T(v)]: row R(b,a) of V for pair p(a,b), a <= b
@@ -174,7 +175,7 @@ struct ascc_ints {
   double* hc;                    // [n][o]
   double* Fh;                    // [n][n]
   double *J;                     // [Q]
-  double *BvoT, *Boo, *Bvv;      // [Q][o][v] (B^_ai at [Q][i][a]), [Q][o][o], [Q][v][v]
+  double *BvoTt, *Boo, *Bvv;     // [o][v][Q] (B^_ai at [i][a][Q]), [Q][o][o], [Q][v][v]
   double *G1, *G2, *G3, *G4;     // ovov, [k][i][a][c], ovov, [k][i][l][j]
   double *TU, *Y, *XZ, *P;       // each [2][ov][ov]
   double *Nq;                    // [Q][o][v]
@@ -185,7 +186,7 @@ struct ascc_ints {
   double *partial;               // reduction scratch
   double *splitk;                // split-K partial tiles of small-output contractions
   // FP32 shadows of the large-contraction operands (only for a low-precision integral set)
-  float *Vf, *GwzTf, *KLf;       // constant: vvvv, [ov+o^2][v^2] transposed (kc|bd)|(kc|ld), K|L
+  float *Vf, *GwzTf, *KLf;       // constant: vvvv, [ov+o^2][v^2] (kc|bd)|(kc|ld), K|L
   float *Tpf, *t2f, *TUf, *XZf;  // per residual: ladder rows, t2 rows, Tx|U, Xc|Zd
   // per residual, K = naux or o^2 contiguous: B^_ai as [ia][Q], B^_ki [ki][Q], B^_ac [ac][Q],
   // B^_kc [kc][Q], B^_kc as [Q][kc], t2 as [ab][ij], chi [ij][kl]
@@ -282,11 +283,12 @@ std::vector<std::pair<double* ascc_ints::*, long>> ints_plan(long o, long v, lon
       {&ascc_ints::B, Q * nn},        {&ascc_ints::h, nn},           {&ascc_ints::eps, n},
       {&ascc_ints::fov, ov},          {&ascc_ints::Bov, Q * ov},     {&ascc_ints::KL, 2 * ovov},
       {&ascc_ints::Lijab, oo * vv},   {&ascc_ints::Gwz, vv * (ov + oo)},
+      {&ascc_ints::BovT, ov * Q},
       {&ascc_ints::V, full ? vv * vv : 2 * Tv * Tv},
       {&ascc_ints::pairtab, full ? Tv : 0},
       {&ascc_ints::Tp, 2 * To * Tv},  {&ascc_ints::Rp, 2 * To * Tv},
       {&ascc_ints::Bc, Q * n * o},    {&ascc_ints::Bh, Q * nn},      {&ascc_ints::hc, n * o},
-      {&ascc_ints::Fh, nn},           {&ascc_ints::J, Q},            {&ascc_ints::BvoT, Q * ov},
+      {&ascc_ints::Fh, nn},           {&ascc_ints::J, Q},            {&ascc_ints::BvoTt, Q * ov},
       {&ascc_ints::Boo, Q * oo},      {&ascc_ints::Bvv, Q * vv},     {&ascc_ints::G1, ovov},
       {&ascc_ints::G2, oo * vv},      {&ascc_ints::G3, ovov},        {&ascc_ints::G4, oo * oo},
       {&ascc_ints::TU, 2 * ovov},     {&ascc_ints::Y, 2 * ovov},     {&ascc_ints::XZ, 2 * ovov},
@@ -573,9 +575,7 @@ size_t ints_footprint(long o, long v, long Q, int precision, int mode) {
   if (precision != ASCC_PREC_FP64)
     for (const auto& item : lowp_plan(o, v, Q, mode))
       off = align_up(off) + std::max<size_t>((size_t)item.second, 1) * sizeof(float);
-  const long vv = v * v, wzl = o * v + o * o;
-  long temp = build_temp_elems(o, v, mode, nullptr);
-  if (precision != ASCC_PREC_FP64) temp = std::max(temp, wzl * vv);
+  const long temp = build_temp_elems(o, v, mode, nullptr);
   return align_up(off) + sizeof(double) * (size_t)std::max<long>(temp, 1);
 }
 
@@ -597,9 +597,9 @@ int residual_core(ascc_ints* I, const double* t1, const double* t2, double* r1, 
 
   // --- contiguous dressed blocks
   {
-    int d[4] = {Q, o, v, 1};
-    Perm4In x = pin(I->Bh + o * n, nn, 1, n, 0, 1.0);  // B^_ai -> [Q][i][a]
-    HIPCHK(permute4(I->BvoT, d, 0.0, &x, 1, s));
+    int d[4] = {o, v, Q, 1};
+    Perm4In x = pin(I->Bh + o * n, 1, n, nn, 0, 1.0);  // B^_ai -> [i][a][Q]
+    HIPCHK(permute4(I->BvoTt, d, 0.0, &x, 1, s));
     int d2[4] = {Q, o, o, 1};
     x = pin(I->Bh, nn, n, 1, 0, 1.0);
     HIPCHK(permute4(I->Boo, d2, 0.0, &x, 1, s));
@@ -633,9 +633,9 @@ int residual_core(ascc_ints* I, const double* t1, const double* t2, double* r1, 
   phase_begin(I, PH_DF, s);
   // g^_aibj enters R2 unmultiplied by amplitudes: always FP64, so the low-precision residual's
   // rounding floor stays proportional to the amplitudes
-  HIPCHK(mm(I, gemm_rm(ov, ov, Q, 1.0, I->BvoT, ov, true, I->BvoT, ov, false, 0.0, I->G1, ov), s));    // g^_aibj
+  HIPCHK(mm(I, gemm_rm(ov, ov, Q, 1.0, I->BvoTt, Q, false, I->BvoTt, Q, true, 0.0, I->G1, ov), s));    // g^_aibj
   if (lowp) {  // the same products on K-contiguous low-precision shadows (B^_kc ones are constant)
-    HIPCHK(shadow_t(I, I->BvoTtf, I->BvoT, ov, ov, Q, s));
+    HIPCHK(shadow(I, I->BvoTtf, I->BvoTt, ov, Q, s));
     HIPCHK(shadow_t(I, I->BooTf, I->Boo, oo, oo, Q, s));
     HIPCHK(shadow_t(I, I->BvvTf, I->Bvv, vv, vv, Q, s));
     HIPCHK(gemm_lowp(lp_nt(I, oo, vv, Q, 1, I->BooTf, lQ, 0, I->BvvTf, lQ, 0, I->G2, vv, 0), s));    // g^_kiac
@@ -644,8 +644,9 @@ int residual_core(ascc_ints* I, const double* t1, const double* t2, double* r1, 
     HIPCHK(gemm_lowp(lp_nt(I, Q, ov, ov, 1, I->Bovf, lov, 0, I->TUf + ov * lov, lov, 0, I->Nq, ov, 0), s));
   } else {
     HIPCHK(mm(I, gemm_rm(oo, vv, Q, 1.0, I->Boo, oo, true, I->Bvv, vv, false, 0.0, I->G2, vv), s));    // g^_kiac
-    HIPCHK(mm(I, gemm_rm(ov, ov, Q, 1.0, I->BvoT, ov, true, I->Bov, ov, false, 0.0, I->G3, ov), s));   // g^_aikc
-    HIPCHK(mm(I, gemm_rm(Q, ov, ov, 1.0, I->Bov, ov, false, U, ov, false, 0.0, I->Nq, ov), s));        // N_Q[k,a]
+    HIPCHK(mm(I, gemm_rm(ov, ov, Q, 1.0, I->BvoTt, Q, false, I->BovT, Q, true, 0.0, I->G3, ov), s));   // g^_aikc
+    // N_Q[k,a] = sum_lc B_Q,lc u_kl^ac (U is symmetric: its rows are its columns)
+    HIPCHK(mm(I, gemm_rm(Q, ov, ov, 1.0, I->Bov, ov, false, U, ov, true, 0.0, I->Nq, ov), s));
   }
   HIPCHK(mm(I, gemm_rm(oo, oo, Q, 1.0, I->Boo, oo, true, I->Boo, oo, false, 0.0, I->G4, oo), s));      // g^_kilj
 
@@ -657,7 +658,7 @@ int residual_core(ascc_ints* I, const double* t1, const double* t2, double* r1, 
     HIPCHK(shadow(I, I->t2f, t2, oo, vv, s));
     HIPCHK(gemm_lowp(lp_nt(I, oo, wzl, vv, 1, I->t2f, ld, 0, I->GwzTf, ld, 0, I->WZ, wzl, 0), s));
   } else {
-    HIPCHK(mm(I, gemm_rm(oo, wzl, vv, 1.0, t2, vv, false, I->Gwz, wzl, false, 0.0, I->WZ, wzl), s));
+    HIPCHK(mm(I, gemm_rm(oo, wzl, vv, 1.0, t2, vv, false, I->Gwz, vv, true, 0.0, I->WZ, wzl), s));
   }
 
   phase_end(I, s);
@@ -914,13 +915,16 @@ int build_constants(ascc_ints* I, const double* Bsrc, const double* fock, int fo
     int d[4] = {Q, o, v, 1};
     Perm4In x = pin(I->B + o, nn, n, 1, 0, 1.0);
     HIPCHK(permute4(I->Bov, d, 0.0, &x, 1, s));
+    int dt[4] = {o, v, Q, 1};
+    Perm4In xt = pin(I->B + o, n, 1, nn, 0, 1.0);  // B_kc -> [k][c][Q]
+    HIPCHK(permute4(I->BovT, dt, 0.0, &xt, 1, s));
     int d2[4] = {Q, v, v, 1};
     Perm4In y = pin(I->B + o * n + o, nn, n, 1, 0, 1.0);
     HIPCHK(permute4(I->Bvv, d2, 0.0, &y, 1, s));
   }
   // J = (ia|jb) into G1 (work), then K and L
   double* Jov = I->G1;
-  HIPCHK(mm(I, gemm_rm(ov, ov, Q, 1.0, I->Bov, ov, true, I->Bov, ov, false, 0.0, Jov, ov), s));
+  HIPCHK(mm(I, gemm_rm(ov, ov, Q, 1.0, I->BovT, Q, false, I->BovT, Q, true, 0.0, Jov, ov), s));
   {
     int d[4] = {o, v, o, v};
     const long si = (long)v * o * v, sa = (long)o * v, sj = v, sb = 1;
@@ -932,7 +936,7 @@ int build_constants(ascc_ints* I, const double* Bsrc, const double* fock, int fo
     Perm4In z = pin(I->KL + ovov, si, sj, sa, sb, 1.0);
     HIPCHK(permute4(I->Lijab, d2, 0.0, &z, 1, s));
   }
-  // Gwz: (kc|bd) at [c][d][k*v + b] from a temporary [(k,c)][(b,d)] product
+  // Gwz: (kc|bd) at [k*v + b][c][d] from a temporary [(k,c)][(b,d)] product (rows K-contiguous)
   {
     double* tmp = nullptr;
     Pool tmp_alloc = sub_pool(I->pool);
@@ -940,16 +944,16 @@ int build_constants(ascc_ints* I, const double* Bsrc, const double* fock, int fo
     if (rc2) return rc2;
     hipError_t e = mm(I, gemm_rm(ov, vv, Q, 1.0, I->Bov, ov, true, I->Bvv, vv, false, 0.0, tmp, vv), s);
     if (e == hipSuccess) {
-      long ostr[4] = {(long)v * wzl, wzl, v, 1};
+      long ostr[4] = {v, 1, (long)v * vv, vv};
       int d[4] = {v, v, o, v};  // (c, d, k, b) <- tmp[k][c][b][d]
       Perm4In x = pin(tmp, vv, 1, (long)v * vv, v, 1.0);
       e = permute4_strided(I->Gwz, ostr, d, 0.0, &x, 1, s);
     }
     if (e == hipSuccess) {
-      long ostr[4] = {(long)v * wzl, wzl, o, 1};
+      long ostr[4] = {v, 1, (long)o * vv, vv};
       int d[4] = {v, v, o, o};  // (c, d, k, l) <- J[k][c][l][d]
       Perm4In x = pin(Jov, (long)o * v, 1, (long)v * o * v, v, 1.0);
-      e = permute4_strided(I->Gwz + ov, ostr, d, 0.0, &x, 1, s);
+      e = permute4_strided(I->Gwz + ov * vv, ostr, d, 0.0, &x, 1, s);
     }
     if (e == hipSuccess && !tmp_alloc.base) e = d_sync(s);  // carved temporaries need no wait
     free_all(tmp_alloc);
@@ -1006,7 +1010,7 @@ int build_constants(ascc_ints* I, const double* Bsrc, const double* fock, int fo
   return ASCC_OK;
 }
 
-// FP32 shadows of the constant operands: (ac|bd), [(kc|bd)|(kc|ld)] transposed to [n][(cd)], K|L.
+// FP32 shadows of the constant operands: (ac|bd), [(kc|bd)|(kc|ld)] as [n][(cd)], K|L.
 int build_lowp_shadows(ascc_ints* I, hipStream_t s) {
   const long vv = I->vv, ov = I->ov, oo = I->oo, wzl = ov + oo;
   const long Tv = (long)I->nv * (I->nv + 1) / 2;
@@ -1019,18 +1023,9 @@ int build_lowp_shadows(ascc_ints* I, hipStream_t s) {
   }
   HIPCHK(shadow(I, I->KLf, I->KL, 2 * ov, ov, s));
   const long Q = I->naux;
-  HIPCHK(shadow_t(I, I->BovTf, I->Bov, ov, ov, Q, s));  // B_kc (undressed by T1) as [kc][Q]
+  HIPCHK(shadow(I, I->BovTf, I->BovT, ov, Q, s));      // B_kc (undressed by T1) as [kc][Q]
   HIPCHK(shadow(I, I->Bovf, I->Bov, Q, ov, s));         // and as [Q][kc]
-  double* tmp = nullptr;
-  Pool tmp_alloc = sub_pool(I->pool);
-  int rc = dalloc(tmp_alloc, &tmp, (size_t)(wzl * vv));
-  if (rc) return rc;
-  int d[4] = {(int)wzl, (int)vv, 1, 1};  // tmp[n][cd] = Gwz[cd][n]
-  Perm4In x = pin(I->Gwz, 1, wzl, 0, 0, 1.0);
-  hipError_t e = permute4(tmp, d, 0.0, &x, 1, s);
-  if (e == hipSuccess) e = shadow(I, I->GwzTf, tmp, wzl, vv, s);
-  if (e == hipSuccess && !tmp_alloc.base) e = d_sync(s);  // carved temporaries need no wait
-  free_all(tmp_alloc);
+  const hipError_t e = shadow(I, I->GwzTf, I->Gwz, wzl, vv, s);  // Gwz rows are K-contiguous already
   if (e != hipSuccess) {
     if (!(bounds_checking() && e == hipErrorInvalidValue)) set_error(std::string("FP32 shadows: ") + hipGetErrorString(e));
     return ASCC_E_HIP;

@@ -127,8 +127,8 @@ __global__ void add_fvo_kernel(double* r1, const double* F, int o, int v) {
 // T1 dressing applied from the column correction: for each of the stacked n x n matrices,
 //   b(x, q) = S[x][q] + (q < o ? Tc[x][q] : 0)   with Tc[x][i] = sum_a S[x][o + a] t1[i][a],
 //   D[p][q] = b(p, q) - [p >= o] sum_{i < o} t1[i][p - o] b(i, q).
-// One workgroup per 64-column panel of one matrix, walking its rows in chunks of 64; the rows b(i, .)
-// of the panel and the t1 columns of a row chunk are staged in LDS 32 values of i at a time.
+// One workgroup per 64 x 64 tile of one matrix; the rows b(i, .) of its columns and the t1 columns
+// of its rows are staged in LDS 32 values of i at a time.
 __global__ __launch_bounds__(kThreads) void dress_apply_kernel(double* __restrict__ D, const double* __restrict__ S,
                                                                const double* __restrict__ Tc,
                                                                const double* __restrict__ t1, int o, int v) {
@@ -137,43 +137,42 @@ __global__ __launch_bounds__(kThreads) void dress_apply_kernel(double* __restric
   __shared__ double tl[IC][RC];
   const int n = o + v;
   const long nn = (long)n * n;
-  const int z = blockIdx.y, c0 = blockIdx.x * CW;
+  const int z = blockIdx.z, c0 = blockIdx.x * CW, r0 = blockIdx.y * RC;
   const double* Sz = S + z * nn;
   const double* Tz = Tc + (long)z * n * o;
   double* Dz = D + z * nn;
-  const int c = threadIdx.x % CW, rg = threadIdx.x / CW;  // this thread: column c0 + c, rows rg + 4j
+  const int c = threadIdx.x % CW, rg = threadIdx.x / CW;  // this thread: column c0 + c, rows r0 + rg + 4j
   const int q = c0 + c;
-  for (int r0 = 0; r0 < n; r0 += RC) {
-    double acc[RJ];
+  double acc[RJ];
 #pragma unroll
-    for (int j = 0; j < RJ; ++j) {
-      const int p = r0 + rg + 4 * j;
-      acc[j] = (p < n && q < n) ? Sz[(long)p * n + q] + (q < o ? Tz[(long)p * o + q] : 0.0) : 0.0;
-    }
-    if (r0 + RC > o) {  // the chunk has rows p >= o
-      for (int i0 = 0; i0 < o; i0 += IC) {
-        __syncthreads();
-        for (int e = threadIdx.x; e < IC * CW; e += kThreads) {
-          const int i = i0 + e / CW, qq = c0 + e % CW;
-          bt[e / CW][e % CW] = (i < o && qq < n) ? Sz[(long)i * n + qq] + (qq < o ? Tz[(long)i * o + qq] : 0.0) : 0.0;
-        }
-        for (int e = threadIdx.x; e < IC * RC; e += kThreads) {
-          const int i = i0 + e / RC, p = r0 + e % RC;
-          tl[e / RC][e % RC] = (i < o && p >= o && p < n) ? t1[(long)i * v + (p - o)] : 0.0;
-        }
-        __syncthreads();
-        for (int ii = 0; ii < IC; ++ii) {
-          const double b = bt[ii][c];
+  for (int j = 0; j < RJ; ++j) {
+    const int p = r0 + rg + 4 * j;
+    acc[j] = (p < n && q < n) ? Sz[(long)p * n + q] + (q < o ? Tz[(long)p * o + q] : 0.0) : 0.0;
+  }
+  if (r0 + RC > o) {  // the tile has rows p >= o
+    for (int i0 = 0; i0 < o; i0 += IC) {
+      if (i0 > 0) __syncthreads();
+      for (int e = threadIdx.x; e < IC * CW; e += kThreads) {
+        const int i = i0 + e / CW, qq = c0 + e % CW;
+        bt[e / CW][e % CW] = (i < o && qq < n) ? Sz[(long)i * n + qq] + (qq < o ? Tz[(long)i * o + qq] : 0.0) : 0.0;
+      }
+      for (int e = threadIdx.x; e < IC * RC; e += kThreads) {
+        const int i = i0 + e / RC, p = r0 + e % RC;
+        tl[e / RC][e % RC] = (i < o && p >= o && p < n) ? t1[(long)i * v + (p - o)] : 0.0;
+      }
+      __syncthreads();
+      const int iend = min(IC, o - i0);
+      for (int ii = 0; ii < iend; ++ii) {
+        const double b = bt[ii][c];
 #pragma unroll
-          for (int j = 0; j < RJ; ++j) acc[j] -= tl[ii][rg + 4 * j] * b;
-        }
+        for (int j = 0; j < RJ; ++j) acc[j] -= tl[ii][rg + 4 * j] * b;
       }
     }
+  }
 #pragma unroll
-    for (int j = 0; j < RJ; ++j) {
-      const int p = r0 + rg + 4 * j;
-      if (p < n && q < n) Dz[(long)p * n + q] = acc[j];
-    }
+  for (int j = 0; j < RJ; ++j) {
+    const int p = r0 + rg + 4 * j;
+    if (p < n && q < n) Dz[(long)p * n + q] = acc[j];
   }
 }
 
@@ -713,8 +712,8 @@ hipError_t dress_apply(double* D, const double* S, const double* Tc, const doubl
                              range_ok(Tc, 0, nb * n * o - 1, 8, "dress Tc") && range_ok(t1, 0, (long)o * v - 1, 8, "dress t1")))
     return hipErrorInvalidValue;
   if (dry_run()) return hipSuccess;
-  hipLaunchKernelGGL(dress_apply_kernel, dim3((unsigned)((n + 63) / 64), (unsigned)nb), dim3(kThreads), 0, s, D, S, Tc,
-                     t1, o, v);
+  const unsigned tiles = (unsigned)((n + 63) / 64);
+  hipLaunchKernelGGL(dress_apply_kernel, dim3(tiles, tiles, (unsigned)nb), dim3(kThreads), 0, s, D, S, Tc, t1, o, v);
   return hipGetLastError();
 }
 

@@ -327,8 +327,9 @@ __global__ __launch_bounds__(WM* WN * 64, 1) void gemm_f64_dma_kernel(GP p) {
     bid = ((local >> 1) << 3) | x;
     if (bid >= ntiles) return;
   }
+  const int slice = PM ? 0 : bid / ntiles;  // split-K slice (never for PM)
   int tm, tn;
-  tile_of(bid, p.tiles_m, p.tiles_n, tm, tn);
+  tile_of(bid - slice * ntiles, p.tiles_m, p.tiles_n, tm, tn);
   const int m0 = tm * BM, n0 = tn * BN;
   const int z1 = blockIdx.z;
   const double* Ab = p.A + z1 * p.sa1 + z2 * p.sa2;
@@ -359,7 +360,9 @@ __global__ __launch_bounds__(WM* WN * 64, 1) void gemm_f64_dma_kernel(GP p) {
     ck[j] = 2 * c;
     src[j] = ok[j] ? row + 2 * c : kZero16;
   }
-  const int nkt = (p.K + 7) / 8;
+  // stages [kt0, kt0 + nkt) of this slice
+  const int kt0 = slice * p.it_per_split;
+  const int nkt = min((p.K + 7) / 8, kt0 + p.it_per_split) - kt0;
   auto issue = [&](int kt, int st) {
 #pragma unroll
     for (int j = 0; j < NPW; ++j) {
@@ -380,8 +383,8 @@ __global__ __launch_bounds__(WM* WN * 64, 1) void gemm_f64_dma_kernel(GP p) {
   const int l16 = lane & 15, q = lane >> 4;
 #pragma unroll
   for (int st = 0; st < S - 1; ++st)
-    if (st < nkt) issue(st, st);
-  for (int kt = 0; kt < nkt; ++kt) {
+    if (st < nkt) issue(kt0 + st, st);
+  for (int kt = 0; kt < nkt; ++kt) {  // kt counts stages of this slice
     const int st = kt % S;
     // stage kt has landed once no more than the later stages' loads of this wave are in flight
     if (kt + S - 2 < nkt)
@@ -411,7 +414,7 @@ __global__ __launch_bounds__(WM* WN * 64, 1) void gemm_f64_dma_kernel(GP p) {
       }
     }
     // the stage refilled now was last read in the previous iteration, before this barrier
-    if (kt + S - 1 < nkt) issue(kt + S - 1, (kt + S - 1) % S);
+    if (kt + S - 1 < nkt) issue(kt0 + kt + S - 1, (kt + S - 1) % S);
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
@@ -430,8 +433,13 @@ __global__ __launch_bounds__(WM* WN * 64, 1) void gemm_f64_dma_kernel(GP p) {
         const int gn = n0 + wn * TN + 16 * j + l16;
         if (gm < p.M && gn < p.N) {
           const double v = p.alpha * acc[i][j][r];
-          double* c = Cb + (long)gm * p.scm + (long)gn * p.scn;
-          *c = (p.beta == 0.0) ? v : v + p.beta * *c;
+          if (p.split > 1) {
+            const long zl = (long)z1 * gridDim.y + z2;
+            p.part[(((long)slice * gridDim.z * gridDim.y + zl) * p.M + gm) * p.N + gn] = v;
+          } else {
+            double* c = Cb + (long)gm * p.scm + (long)gn * p.scn;
+            *c = (p.beta == 0.0) ? v : v + p.beta * *c;
+          }
         }
       }
 }
@@ -443,21 +451,58 @@ bool dma_eligible(const GP& p) {
          p.sa1 % 2 == 0 && p.sa2 % 2 == 0 && p.sb1 % 2 == 0 && p.sb2 % 2 == 0 && al(p.A) && al(p.B);
 }
 
+// split > 1 (never with pm): K cut into `split` slices whose partial tiles go to ws, then summed
+// in slice order by splitk_reduce.
 template <int BM, int BN, int WM, int WN, int S>
-hipError_t launch_dma(GP p, int nb1, bool pm, hipStream_t s) {
+hipError_t launch_dma(GP p, int nb1, bool pm, int split, double* ws, hipStream_t s) {
   p.tiles_m = (p.M + BM - 1) / BM;
   p.tiles_n = (p.N + BN - 1) / BN;
-  p.split = 1;
-  p.part = nullptr;
+  const int nkt = (p.K + 7) / 8;
+  p.it_per_split = (nkt + split - 1) / split;
+  p.split = (nkt + p.it_per_split - 1) / p.it_per_split;
+  p.part = p.split > 1 ? ws : nullptr;
   const int tiles = p.tiles_m * p.tiles_n;
   if (pm) {  // both halves in grid.x, padded to whole groups of 8
     dim3 grid(2 * ((tiles + 7) / 8 * 8), 1, nb1);
     hipLaunchKernelGGL((gemm_f64_dma_kernel<BM, BN, WM, WN, S, true>), grid, dim3(WM * WN * 64), 0, s, p);
   } else {
-    dim3 grid(tiles, p.nb2, nb1);
+    dim3 grid(tiles * p.split, p.nb2, nb1);
     hipLaunchKernelGGL((gemm_f64_dma_kernel<BM, BN, WM, WN, S, false>), grid, dim3(WM * WN * 64), 0, s, p);
   }
+  if (p.split > 1) {
+    const long outs = (long)p.M * p.N * p.nb2 * nb1;
+    hipLaunchKernelGGL(splitk_reduce, dim3((unsigned)std::min<long>((outs + 255) / 256, 4096)), dim3(256), 0, s, p, nb1,
+                       outs);
+  }
   return hipGetLastError();
+}
+
+// Direct-to-LDS launch for a non-pair-combined contraction: the tile (192 x 192, 256 x 128 or
+// 224 x 128) and split-K count with the least estimated time = whole rounds of 256 workgroups x
+// tile area x K-stages per slice; split-K only with scratch, when the tiles cannot fill one round.
+hipError_t launch_dma_auto(const GP& p, int nb1, double* ws, long ws_elems, hipStream_t s) {
+  const long nbatch = (long)p.nb2 * nb1, outs = (long)p.M * p.N * nbatch;
+  const int nkt = (p.K + 7) / 8;
+  int best = -1, best_split = 1;
+  double best_cost = 0.0;
+  const int bms[3] = {192, 256, 224}, bns[3] = {192, 128, 128};
+  for (int c = 0; c < 3; ++c) {
+    const long tiles = (long)((p.M + bms[c] - 1) / bms[c]) * ((p.N + bns[c] - 1) / bns[c]) * nbatch;
+    int sp = 1;
+    if (ws && tiles < 192 && nkt >= 32) {
+      sp = (int)std::min<long>({256 / tiles, (long)nkt / 16, 256L, ws_elems / std::max<long>(outs, 1)});
+      sp = std::max(sp, 1);
+    }
+    const double cost = (double)((tiles * sp + 255) / 256) * bms[c] * bns[c] * ((nkt + sp - 1) / sp);
+    if (best < 0 || cost < best_cost) {
+      best = c;
+      best_cost = cost;
+      best_split = sp;
+    }
+  }
+  if (best == 0) return launch_dma<192, 192, 2, 4, 4>(p, nb1, false, best_split, ws, s);
+  if (best == 1) return launch_dma<256, 128, 4, 2, 4>(p, nb1, false, best_split, ws, s);
+  return launch_dma<224, 128, 2, 4, 4>(p, nb1, false, best_split, ws, s);
 }
 
 // Ladder: BM x 128 tiles of 8 waves, both halves (grid.y = 2), no split-K, A/B staged k-fast.
@@ -581,18 +626,18 @@ hipError_t gemm_f64(const Gemm& g, hipStream_t s) {
       return (double)((t + 255) / 256) * bm * bn / rate;
     };
     const double e128 = est(128, 128, 59.5), e256 = est(256, 128, 60.0), e192 = est(192, 192, 61.5);
-    if (dma_eligible(p)) {  // direct-to-LDS tiles sustain ~67-68 TFLOP/s on full rounds
-      const double d192 = est(192, 192, 68.0), d256 = est(256, 128, 67.0);
-      if (d192 <= d256 && d192 < e128) return launch_dma<192, 192, 2, 4, 4>(p, g.nb1, false, s);
-      if (d256 < e128) return launch_dma<256, 128, 4, 2, 4>(p, g.nb1, false, s);
-    }
+    // direct-to-LDS tiles sustain ~67-68 TFLOP/s on full rounds
+    if (dma_eligible(p)) return launch_dma_auto(p, g.nb1, g.ws, g.ws_elems, s);
     if (e192 < e128 && e192 <= e256) return launch_cfg<192, 192, 16, 2, 4, 1>(p, amf, bnf, g.nb1, nullptr, 0, s);
     if (e256 < e128) return launch_cfg<256, 128, 16, 4, 2, 1>(p, amf, bnf, g.nb1, nullptr, 0, s);
     return launch_cfg<128, 128, 16, 2, 2, 2>(p, amf, bnf, g.nb1, g.ws, g.ws_elems, s);
   }
   // a long K lets split-K make up for too few 128 x 128 tiles
   const bool long_k = g.ws && (long)g.K * g.nred >= 2048 && tiles128 >= 64;
-  if (g.M >= 96 && g.N >= 96 && long_k) return launch_cfg<128, 128, 16, 2, 2, 2>(p, amf, bnf, g.nb1, g.ws, g.ws_elems, s);
+  if (g.M >= 96 && g.N >= 96 && long_k) {
+    if (dma_eligible(p)) return launch_dma_auto(p, g.nb1, g.ws, g.ws_elems, s);
+    return launch_cfg<128, 128, 16, 2, 2, 2>(p, amf, bnf, g.nb1, g.ws, g.ws_elems, s);
+  }
   const long tiles64 = (long)((g.M + 63) / 64) * ((g.N + 63) / 64) * nbatch;
   if (g.M >= 48 && g.N >= 48 && tiles64 >= 128) return launch_cfg<64, 64, 16, 2, 2, 2>(p, amf, bnf, g.nb1, g.ws, g.ws_elems, s);
   return launch_cfg<32, 32, 16, 1, 1, 3>(p, amf, bnf, g.nb1, g.ws, g.ws_elems, s);
@@ -637,9 +682,9 @@ hipError_t gemm_f64_ladder(int M, int Tv, const double* A, const double* V, long
   // row of wasted products); on a tie the taller tile, which reads the vvvv operand fewer times.
   const long pad256 = (M + 255L) / 256 * 256, pad224 = (M + 223L) / 224 * 224, pad128 = (M + 127L) / 128 * 128;
   if (dma_eligible(p)) {
-    if (pad256 <= pad224 && pad256 <= pad128) return launch_dma<256, 128, 4, 2, 4>(p, 1, pmode, s);
-    if (pad224 <= pad128) return launch_dma<224, 128, 2, 4, 4>(p, 1, pmode, s);
-    return launch_dma<128, 128, 2, 4, 4>(p, 1, pmode, s);
+    if (pad256 <= pad224 && pad256 <= pad128) return launch_dma<256, 128, 4, 2, 4>(p, 1, pmode, 1, nullptr, s);
+    if (pad224 <= pad128) return launch_dma<224, 128, 2, 4, 4>(p, 1, pmode, 1, nullptr, s);
+    return launch_dma<128, 128, 2, 4, 4>(p, 1, pmode, 1, nullptr, s);
   }
   if (pad256 <= pad224 && pad256 <= pad128) return launch_ladder<256, 4>(p, pmode, s);
   if (pad224 <= pad128) return launch_ladder<224, 2>(p, pmode, s);

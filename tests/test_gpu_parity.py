@@ -155,3 +155,36 @@ def test_residual_parity_o20v180q600_full_size():
         assert np.abs(r1 - r1_ref).max() <= TOL * scale
         assert np.abs(r2 - r2_ref).max() <= TOL * scale
         assert abs(e - e_ref) <= TOL * max(1.0, abs(e_ref))
+
+
+@pytest.mark.slow
+def test_residual_parity_direct_to_lds_paths_ragged():
+    """o17 v132 Q400 against the oracle, both vvvv modes: sized so that every large contraction takes
+    the direct-to-LDS FP64 path with ragged tiles (rings ov = 2244 = 11 x 192 + 132; ladder
+    T(o) = 153 rows in 224-row tiles and T(v) = 8778 = 68 x 128 + 74 columns; W/Z split over K with
+    o^2 = 289 rows; G1/G3 with K = Q; N_Q split over K)."""
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2501_10515_amd as P
+    from oracle import cs_ccsd
+
+    from .gpu_util import dev, gpu_residual
+
+    o, v, Q = 17, 132, 400
+    B, eps = make_system(o, v, Q, 21, sigma=converging_sigma(v, Q))
+    t1, t2 = random_amplitudes(o, v, 78, 0.02, 0.02)
+    fock = np.diag(eps)
+    r1_ref, r2_ref = cs_ccsd.residual(B, fock, t1, t2)
+    e_ref = cs_ccsd.energy(B, fock, t1, t2)
+    scale = max(1.0, np.abs(r2_ref).max())
+    for vm in (P.ASCC_VVVV_FULL, P.ASCC_VVVV_PACKED):
+        print(f"o17v132q400 vvvv_mode={vm}", flush=True)
+        ints = P.ascc_build_ints(dev(B), dev(eps), o, vvvv_mode=vm)
+        r1, r2, e = gpu_residual(P, ints, t1, t2)
+        ints.close()
+        torch.cuda.empty_cache()
+        assert np.abs(r1 - r1_ref).max() <= TOL * scale
+        assert np.abs(r2 - r2_ref).max() <= TOL * scale
+        assert abs(e - e_ref) <= TOL * max(1.0, abs(e_ref))
