@@ -229,19 +229,31 @@ __global__ __launch_bounds__(WM* WN * 64, MINB) void gemm_f64_kernel(GP p) {
       }
 }
 
-// C_z(m,n) = beta * C_z(m,n) + sum_s part[s][z][m][n], summed in slice order.
+// C_z(m,n) = beta * C_z(m,n) + sum_s part[s][z][m][n].  Each block takes 64 consecutive outputs; its
+// four waves sum four contiguous slice ranges in slice order, and the four partial sums are added
+// in wave order (a fixed order, so the result is deterministic).
 __global__ __launch_bounds__(256) void splitk_reduce(GP p, int nb1, long total) {
-  for (long x = blockIdx.x * 256L + threadIdx.x; x < total; x += (long)gridDim.x * 256) {
-    const long mn = (long)p.M * p.N;
-    const long zl = x / mn, r = x % mn;
-    const int gm = r / p.N, gn = r % p.N;
-    const int z1 = zl / p.nb2, z2 = zl % p.nb2;
-    double acc = 0.0;
-    for (int sl = 0; sl < p.split; ++sl) acc += p.part[(long)sl * total + x];
-    double* c = p.C + z1 * p.sc1 + z2 * p.sc2 + gm * p.scm + gn * p.scn;
-    *c = (p.beta == 0.0) ? acc : acc + p.beta * *c;
-  }
+  __shared__ double red[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const long x = blockIdx.x * 64L + lane;
+  const int s0 = (int)((long)p.split * w / 4), s1 = (int)((long)p.split * (w + 1) / 4);
+  double acc = 0.0;
+  if (x < total)
+    for (int sl = s0; sl < s1; ++sl) acc += p.part[(long)sl * total + x];
+  red[w][lane] = acc;
+  __syncthreads();
+  if (w != 0 || x >= total) return;
+  const double sum = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+  const long mn = (long)p.M * p.N;
+  const long zl = x / mn, r = x % mn;
+  const int gm = r / p.N, gn = r % p.N;
+  const int z1 = zl / p.nb2, z2 = zl % p.nb2;
+  double* c = p.C + z1 * p.sc1 + z2 * p.sc2 + gm * p.scm + gn * p.scn;
+  *c = (p.beta == 0.0) ? sum : sum + p.beta * *c;
 }
+
+// grid of splitk_reduce for `outs` outputs
+inline unsigned splitk_blocks(long outs) { return (unsigned)((outs + 63) / 64); }
 
 template <int BM, int BN, int BK, int WM, int WN, int MINB>
 hipError_t launch_cfg(const GP& p0, bool amf, bool bnf, int nb1, double* ws, long ws_elems, hipStream_t s) {
@@ -274,10 +286,7 @@ hipError_t launch_cfg(const GP& p0, bool amf, bool bnf, int nb1, double* ws, lon
     hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, WM, WN, MINB, false, true>), grid, block, 0, s, p);
   else
     hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, WM, WN, MINB, false, false>), grid, block, 0, s, p);
-  if (p.split > 1) {
-    const long blocks = std::min<long>((outs + 255) / 256, 4096);
-    hipLaunchKernelGGL(splitk_reduce, dim3((unsigned)blocks), dim3(256), 0, s, p, nb1, outs);
-  }
+  if (p.split > 1) hipLaunchKernelGGL(splitk_reduce, dim3(splitk_blocks(outs)), dim3(256), 0, s, p, nb1, outs);
   return hipGetLastError();
 }
 
@@ -452,7 +461,7 @@ bool dma_eligible(const GP& p) {
 }
 
 // split > 1 (never with pm): K cut into `split` slices whose partial tiles go to ws, then summed
-// in slice order by splitk_reduce.
+// in a fixed order by splitk_reduce.
 template <int BM, int BN, int WM, int WN, int S>
 hipError_t launch_dma(GP p, int nb1, bool pm, int split, double* ws, hipStream_t s) {
   p.tiles_m = (p.M + BM - 1) / BM;
@@ -471,8 +480,7 @@ hipError_t launch_dma(GP p, int nb1, bool pm, int split, double* ws, hipStream_t
   }
   if (p.split > 1) {
     const long outs = (long)p.M * p.N * p.nb2 * nb1;
-    hipLaunchKernelGGL(splitk_reduce, dim3((unsigned)std::min<long>((outs + 255) / 256, 4096)), dim3(256), 0, s, p, nb1,
-                       outs);
+    hipLaunchKernelGGL(splitk_reduce, dim3(splitk_blocks(outs)), dim3(256), 0, s, p, nb1, outs);
   }
   return hipGetLastError();
 }
