@@ -127,52 +127,41 @@ __global__ void add_fvo_kernel(double* r1, const double* F, int o, int v) {
 // T1 dressing applied from the column correction: for each of the stacked n x n matrices,
 //   b(x, q) = S[x][q] + (q < o ? Tc[x][q] : 0)   with Tc[x][i] = sum_a S[x][o + a] t1[i][a],
 //   D[p][q] = b(p, q) - [p >= o] sum_{i < o} t1[i][p - o] b(i, q).
-// One workgroup per 64 x 64 tile of one matrix; the rows b(i, .) of its columns and the t1 columns
-// of its rows are staged in LDS 32 values of i at a time.
+// One thread per column q of a 32-row chunk of one matrix: b(i, q) is read once per i and applied to
+// all 32 rows; the t1 coefficients depend on the row only, so they are wave-uniform (scalar loads).
 __global__ __launch_bounds__(kThreads) void dress_apply_kernel(double* __restrict__ D, const double* __restrict__ S,
                                                                const double* __restrict__ Tc,
                                                                const double* __restrict__ t1, int o, int v) {
-  constexpr int CW = 64, RC = 64, IC = 32, RJ = RC / (kThreads / CW);
-  __shared__ double bt[IC][CW];
-  __shared__ double tl[IC][RC];
+  constexpr int RC = 32;
   const int n = o + v;
   const long nn = (long)n * n;
-  const int z = blockIdx.z, c0 = blockIdx.x * CW, r0 = blockIdx.y * RC;
+  const int z = blockIdx.z, r0 = blockIdx.x * RC, q = blockIdx.y * kThreads + threadIdx.x;
+  if (q >= n) return;
   const double* Sz = S + z * nn;
   const double* Tz = Tc + (long)z * n * o;
   double* Dz = D + z * nn;
-  const int c = threadIdx.x % CW, rg = threadIdx.x / CW;  // this thread: column c0 + c, rows r0 + rg + 4j
-  const int q = c0 + c;
-  double acc[RJ];
+  const bool qlo = q < o;
+  double acc[RC];
 #pragma unroll
-  for (int j = 0; j < RJ; ++j) {
-    const int p = r0 + rg + 4 * j;
-    acc[j] = (p < n && q < n) ? Sz[(long)p * n + q] + (q < o ? Tz[(long)p * o + q] : 0.0) : 0.0;
+  for (int r = 0; r < RC; ++r) {
+    const int p = r0 + r;
+    acc[r] = p < n ? Sz[(long)p * n + q] + (qlo ? Tz[(long)p * o + q] : 0.0) : 0.0;
   }
-  if (r0 + RC > o) {  // the tile has rows p >= o
-    for (int i0 = 0; i0 < o; i0 += IC) {
-      if (i0 > 0) __syncthreads();
-      for (int e = threadIdx.x; e < IC * CW; e += kThreads) {
-        const int i = i0 + e / CW, qq = c0 + e % CW;
-        bt[e / CW][e % CW] = (i < o && qq < n) ? Sz[(long)i * n + qq] + (qq < o ? Tz[(long)i * o + qq] : 0.0) : 0.0;
-      }
-      for (int e = threadIdx.x; e < IC * RC; e += kThreads) {
-        const int i = i0 + e / RC, p = r0 + e % RC;
-        tl[e / RC][e % RC] = (i < o && p >= o && p < n) ? t1[(long)i * v + (p - o)] : 0.0;
-      }
-      __syncthreads();
-      const int iend = min(IC, o - i0);
-      for (int ii = 0; ii < iend; ++ii) {
-        const double b = bt[ii][c];
+  if (r0 + RC > o) {  // the chunk has rows p >= o
+    for (int i = 0; i < o; ++i) {
+      const double b = Sz[(long)i * n + q] + (qlo ? Tz[(long)i * o + q] : 0.0);
+      const double* ti = t1 + (long)i * v;
 #pragma unroll
-        for (int j = 0; j < RJ; ++j) acc[j] -= tl[ii][rg + 4 * j] * b;
+      for (int r = 0; r < RC; ++r) {
+        const int p = r0 + r;
+        if (p >= o && p < n) acc[r] -= ti[p - o] * b;
       }
     }
   }
 #pragma unroll
-  for (int j = 0; j < RJ; ++j) {
-    const int p = r0 + rg + 4 * j;
-    if (p < n && q < n) Dz[(long)p * n + q] = acc[j];
+  for (int r = 0; r < RC; ++r) {
+    const int p = r0 + r;
+    if (p < n) Dz[(long)p * n + q] = acc[r];
   }
 }
 
@@ -492,23 +481,61 @@ __global__ __launch_bounds__(kThreads) void pack_tpm_kernel(double* __restrict__
 }
 
 // RL[i][j][a][b] from R+-[p][p(a,b)]: R^ab = R+ + R- (a <= b), R+ - R- (a > b), with R_ij = R_ji^T.
+// One workgroup per pair i <= j and 32 x 32 block (A <= B) of (a, b): with u = R+ + R-, w = R+ - R-
+// at the packed index p(a, b), a <= b, the four outputs are RL[i][j][a][b] = RL[j][i][b][a] = u and
+// RL[i][j][b][a] = RL[j][i][a][b] = w (the residual's pair symmetry; R- vanishes on a = b).  Each
+// packed element is read once; the transposed writes go through an LDS tile.
 __global__ __launch_bounds__(kThreads) void unpack_rpm_kernel(double* __restrict__ RL, const double* __restrict__ Rplus,
-                                                             const double* __restrict__ Rminus, int o, int v) {
-  const int i = blockIdx.y / o, j = blockIdx.y % o;
+                                                             const double* __restrict__ Rminus, int o, int v,
+                                                             int nblk) {
+  __shared__ double tu[32][33], tw[32][33];
   const long Tv = (long)v * (v + 1) / 2, vv = (long)v * v;
-  const long p = (i <= j) ? pidx(i, j, o) : pidx(j, i, o);
+  // block pair (A, B), A <= B, from blockIdx.x
+  int A = 0, rem = blockIdx.x;
+  while (rem >= nblk - A) {
+    rem -= nblk - A;
+    ++A;
+  }
+  const int B = A + rem;
+  int i = 0, prem = blockIdx.y;  // pair i <= j from blockIdx.y
+  while (prem >= o - i) {
+    prem -= o - i;
+    ++i;
+  }
+  const int j = i + prem;
+  const long p = pidx(i, j, o);
   const double* plus = Rplus + p * Tv;
   const double* minus = Rminus + p * Tv;
-  double* dst = RL + ((long)i * o + j) * vv;
-  for (long x = blockIdx.x * (long)blockDim.x + threadIdx.x; x < vv; x += (long)gridDim.x * blockDim.x) {
-    int a = x / v, b = x % v;
-    if (i > j) {
-      const int t = a;
-      a = b;
-      b = t;
+  double* dij = RL + ((long)i * o + j) * vv;
+  double* dji = RL + ((long)j * o + i) * vv;
+  const int a0 = 32 * A, b0 = 32 * B;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  // read: rows a = a0 + ty + 8r, columns b = b0 + tx (contiguous in the packed row)
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int la = ty + 8 * r, a = a0 + la, b = b0 + tx;
+    double u = 0.0, w = 0.0;
+    const bool in = a < v && b < v && a <= b;
+    if (in) {
+      const long k = pidx(a, b, v);
+      const double x = plus[k], y = minus[k];
+      u = x + y;
+      w = x - y;
+      dij[(long)a * v + b] = u;
+      if (i != j) dji[(long)a * v + b] = (a == b) ? u : w;
     }
-    const long k = (a <= b) ? pidx(a, b, v) : pidx(b, a, v);
-    dst[x] = (a <= b) ? plus[k] + minus[k] : plus[k] - minus[k];
+    tu[la][tx] = u;
+    tw[la][tx] = w;
+  }
+  __syncthreads();
+  // transposed writes: position (b, a), a = a0 + tx contiguous
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int lb = ty + 8 * r, b = b0 + lb, a = a0 + tx;
+    if (a < v && b < v && a < b) {
+      dij[(long)b * v + a] = tw[tx][lb];
+      if (i != j) dji[(long)b * v + a] = tu[tx][lb];
+    }
   }
 }
 
@@ -712,8 +739,8 @@ hipError_t dress_apply(double* D, const double* S, const double* Tc, const doubl
                              range_ok(Tc, 0, nb * n * o - 1, 8, "dress Tc") && range_ok(t1, 0, (long)o * v - 1, 8, "dress t1")))
     return hipErrorInvalidValue;
   if (dry_run()) return hipSuccess;
-  const unsigned tiles = (unsigned)((n + 63) / 64);
-  hipLaunchKernelGGL(dress_apply_kernel, dim3(tiles, tiles, (unsigned)nb), dim3(kThreads), 0, s, D, S, Tc, t1, o, v);
+  hipLaunchKernelGGL(dress_apply_kernel, dim3((unsigned)((n + 31) / 32), (unsigned)((n + kThreads - 1) / kThreads), (unsigned)nb),
+                     dim3(kThreads), 0, s, D, S, Tc, t1, o, v);
   return hipGetLastError();
 }
 
@@ -760,8 +787,9 @@ hipError_t unpack_rpm(double* RL, const double* Rplus, const double* Rminus, int
                              chk(Rminus, To * Tv, "unpack_rpm minus")))
     return hipErrorInvalidValue;
   if (dry_run()) return hipSuccess;
-  dim3 grid((unsigned)std::min<long>((vv + kThreads - 1) / kThreads, 64), o * o);
-  hipLaunchKernelGGL(unpack_rpm_kernel, grid, dim3(kThreads), 0, s, RL, Rplus, Rminus, o, v);
+  const int nblk = (v + 31) / 32;
+  dim3 grid((unsigned)(nblk * (nblk + 1) / 2), (unsigned)To);
+  hipLaunchKernelGGL(unpack_rpm_kernel, grid, dim3(kThreads), 0, s, RL, Rplus, Rminus, o, v, nblk);
   return hipGetLastError();
 }
 
