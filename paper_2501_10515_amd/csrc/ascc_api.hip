@@ -944,16 +944,14 @@ int build_constants(ascc_ints* I, const double* Bsrc, const double* fock, int fo
     if (rc2) return rc2;
     hipError_t e = mm(I, gemm_rm(ov, vv, Q, 1.0, I->Bov, ov, true, I->Bvv, vv, false, 0.0, tmp, vv), s);
     if (e == hipSuccess) {
-      long ostr[4] = {v, 1, (long)v * vv, vv};
-      int d[4] = {v, v, o, v};  // (c, d, k, b) <- tmp[k][c][b][d]
-      Perm4In x = pin(tmp, vv, 1, (long)v * vv, v, 1.0);
-      e = permute4_strided(I->Gwz, ostr, d, 0.0, &x, 1, s);
+      int d[4] = {o, v, v, v};  // Gwz[k][b][c][d] <- tmp[k][c][b][d]: d contiguous on both sides
+      Perm4In x = pin(tmp, (long)v * vv, v, vv, 1, 1.0);
+      e = permute4(I->Gwz, d, 0.0, &x, 1, s);
     }
     if (e == hipSuccess) {
-      long ostr[4] = {v, 1, (long)o * vv, vv};
-      int d[4] = {v, v, o, o};  // (c, d, k, l) <- J[k][c][l][d]
-      Perm4In x = pin(Jov, (long)o * v, 1, (long)v * o * v, v, 1.0);
-      e = permute4_strided(I->Gwz + ov * vv, ostr, d, 0.0, &x, 1, s);
+      int d[4] = {o, o, v, v};  // Gwz[ov + k*o + l][c][d] <- J[k][c][l][d]
+      Perm4In x = pin(Jov, (long)v * o * v, v, (long)o * v, 1, 1.0);
+      e = permute4(I->Gwz + ov * vv, d, 0.0, &x, 1, s);
     }
     if (e == hipSuccess && !tmp_alloc.base) e = d_sync(s);  // carved temporaries need no wait
     free_all(tmp_alloc);
