@@ -910,7 +910,8 @@ int build_constants(ascc_ints* I, const double* Bsrc, const double* fock, int fo
   int rc = add_two_electron_fock(I, I->h, I->B, I->J, o, v, Q, -1.0, s);
   if (rc) return rc;
 
-  // B_ov and undressed B_vv (the latter into the work array Bvv)
+  // B_ov and the undressed B_vv, the latter as [a][c][Q] (K = Q contiguous, into the work array Bvv,
+  // which every residual overwrites with the dressed [Q][a][c])
   {
     int d[4] = {Q, o, v, 1};
     Perm4In x = pin(I->B + o, nn, n, 1, 0, 1.0);
@@ -918,8 +919,8 @@ int build_constants(ascc_ints* I, const double* Bsrc, const double* fock, int fo
     int dt[4] = {o, v, Q, 1};
     Perm4In xt = pin(I->B + o, n, 1, nn, 0, 1.0);  // B_kc -> [k][c][Q]
     HIPCHK(permute4(I->BovT, dt, 0.0, &xt, 1, s));
-    int d2[4] = {Q, v, v, 1};
-    Perm4In y = pin(I->B + o * n + o, nn, n, 1, 0, 1.0);
+    int d2[4] = {v, v, Q, 1};
+    Perm4In y = pin(I->B + o * n + o, n, 1, nn, 0, 1.0);
     HIPCHK(permute4(I->Bvv, d2, 0.0, &y, 1, s));
   }
   // J = (ia|jb) into G1 (work), then K and L
@@ -942,7 +943,7 @@ int build_constants(ascc_ints* I, const double* Bsrc, const double* fock, int fo
     Pool tmp_alloc = sub_pool(I->pool);
     int rc2 = dalloc(tmp_alloc, &tmp, (size_t)ov * vv);
     if (rc2) return rc2;
-    hipError_t e = mm(I, gemm_rm(ov, vv, Q, 1.0, I->Bov, ov, true, I->Bvv, vv, false, 0.0, tmp, vv), s);
+    hipError_t e = mm(I, gemm_rm(ov, vv, Q, 1.0, I->BovT, Q, false, I->Bvv, Q, true, 0.0, tmp, vv), s);
     if (e == hipSuccess) {
       int d[4] = {o, v, v, v};  // Gwz[k][b][c][d] <- tmp[k][c][b][d]: d contiguous on both sides
       Perm4In x = pin(tmp, (long)v * vv, v, vv, 1, 1.0);
@@ -961,20 +962,21 @@ int build_constants(ascc_ints* I, const double* Bsrc, const double* fock, int fo
       return ASCC_E_HIP;
     }
   }
-  // V[a][b][c][d] = (ac|bd) = sum_Q B_Q,ac B_Q,bd, batched over (a, b); packed: in chunks of a
+  // V[a][b][c][d] = (ac|bd) = sum_Q B_Q,ac B_Q,bd, batched over (a, b); packed: in chunks of a.
+  // Both operands are rows of the [a][c][Q] B_vv: K-contiguous.
   auto vslab = [&](int a0, int na, double* dst) -> hipError_t {
     Gemm g;
     g.M = v;
     g.N = v;
     g.K = Q;
-    g.A = I->Bvv + (long)a0 * v;
-    g.sam = 1;
-    g.sak = vv;
-    g.sa1 = v;
+    g.A = I->Bvv + (long)a0 * v * Q;
+    g.sam = Q;
+    g.sak = 1;
+    g.sa1 = (long)v * Q;
     g.B = I->Bvv;
-    g.sbk = vv;
-    g.sbn = 1;
-    g.sb2 = v;
+    g.sbk = 1;
+    g.sbn = Q;
+    g.sb2 = (long)v * Q;
     g.C = dst;
     g.scm = v;
     g.scn = 1;
