@@ -17,4 +17,8 @@ Contents, each module citing the passage of the paper it follows:
   ``so_ccsd`` through the spin-adaptation relations (Supporting Information S1).
 * ``solver``      -- diagonal approximate-Jacobian update with DIIS (Sec. III.B) and the
   convergence test (Sec. III.A).
+* ``ascc``        -- the transformed Hamiltonian Hbar = e^{S^dagger} H e^{-S^dagger} of a 1-CSF
+  state (Eqs. (eqn:1CSF-S), (eqn: sim)) and the initial guess T^P(0) = S - S^2/2
+  (Eq. (eqn:TP-guess)), pinned to determinant-space matrix exponentials and to the
+  two-electron limit.
 """

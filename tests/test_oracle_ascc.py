@@ -1,0 +1,125 @@
+"""The ASCC transformed Hamiltonian of the oracle (oracle/ascc.py), pinned on the CPU:
+
+* against the definition Hbar = e^{S^dagger} H e^{-S^dagger} (paper Eq. (eqn: sim)) evaluated with
+  dense matrix exponentials in the full determinant space;
+* against the spectrum of H, which a similarity transform preserves (Sec. II.A);
+* the initial guess T^P(0) = S - S^2/2 (Eq. (eqn:TP-guess)) against the 1-CSF reference S|phi_0>
+  of Eq. (eqn: 1csf);
+* the closed-shell residual of the non-symmetric Hbar against brute-force projections;
+* the two-electron limit: a converged ASCC solution is an exact eigenstate of H.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from gen.synth_df import converging_sigma, make_system, random_amplitudes
+from oracle import ascc, cs_ccsd, solver
+from oracle.bruteforce import BruteForce, closed_shell_to_so, so_maps, so_to_closed_shell
+
+
+def _eri(B):
+    return np.einsum("Qpq,Qrs->pqrs", B, B)
+
+
+def _spin_orbital(no, nv, spatial_index, spin):
+    sp, sn = so_maps(no, nv)
+    return int(np.flatnonzero((sp == spatial_index) & (sn == spin))[0])
+
+
+def _s_ops(bf, no, nv, hole, particle):
+    """Dense S and S^dagger of Eq. (eqn:1CSF-S) in the determinant space of ``bf``."""
+    s = 1.0 / np.sqrt(2.0)
+    S = sum(s * bf.space.E(_spin_orbital(no, nv, particle, sg), _spin_orbital(no, nv, hole, sg)) for sg in (0, 1))
+    Sd = sum(s * bf.space.E(_spin_orbital(no, nv, hole, sg), _spin_orbital(no, nv, particle, sg)) for sg in (0, 1))
+    return S.toarray(), Sd.toarray()
+
+
+CASES = [(1, 3, 5, 31, 0, 1), (2, 3, 8, 32, 1, 2), (2, 3, 7, 33, 0, 4), (3, 2, 6, 34, 2, 3)]
+
+
+@pytest.mark.parametrize("o,v,Q,seed,hole,particle", CASES)
+def test_transformed_integrals_are_the_similarity_transform(o, v, Q, seed, hole, particle):
+    B, eps = make_system(o, v, Q, seed, sigma=0.3)
+    h = cs_ccsd.core_hamiltonian_df(B, np.diag(eps), o)
+    bf = BruteForce(h, _eri(B), o, v)
+    H = bf.hamiltonian_matrix()
+    _, Sd = _s_ops(bf, o, v, hole, particle)
+    Hbar_def = sla.expm(Sd) @ H @ sla.expm(-Sd)
+    Bbar, hbar = ascc.transform(B, h, hole, particle)
+    assert np.abs(Bbar - Bbar.transpose(0, 2, 1)).max() > 1e-3  # really not symmetric
+    Hbar = BruteForce(hbar, _eri(Bbar), o, v).hamiltonian_matrix()
+    assert np.abs(Hbar - Hbar_def).max() < 1e-12
+    # the spectrum is that of H
+    ev_h = np.sort(np.linalg.eigvalsh(H))
+    ev_bar = np.sort(np.linalg.eigvals(Hbar).real)
+    assert np.abs(ev_h - ev_bar).max() < 1e-9
+
+
+def test_a_wrong_transform_is_caught():
+    """Transforming with (1 + K) on both sides (a plausible slip) breaks the definition."""
+    o, v, Q, seed, hole, particle = 2, 3, 8, 32, 1, 2
+    B, eps = make_system(o, v, Q, seed, sigma=0.3)
+    h = cs_ccsd.core_hamiltonian_df(B, np.diag(eps), o)
+    bf = BruteForce(h, _eri(B), o, v)
+    _, Sd = _s_ops(bf, o, v, hole, particle)
+    Hbar_def = sla.expm(Sd) @ bf.hamiltonian_matrix() @ sla.expm(-Sd)
+    n = o + v
+    L = np.eye(n) + ascc.s_dagger_matrix(n, hole, particle)
+    Bw = np.einsum("pr,Qrs,sq->Qpq", L, B, L)
+    Hw = BruteForce(L @ h @ L, _eri(Bw), o, v).hamiltonian_matrix()
+    assert np.abs(Hw - Hbar_def).max() > 1e-3
+
+
+@pytest.mark.parametrize("o,v,hole,particle", [(1, 3, 0, 1), (2, 3, 1, 2), (2, 2, 0, 3)])
+def test_initial_guess_gives_the_1csf_reference(o, v, hole, particle):
+    """e^{-S^dagger} e^{T^P(0)} |phi_0> = S |phi_0> for T^P(0) = S - S^2/2 (Eqs. (eqn: ogascc), (eqn: 1csf))."""
+    B, eps = make_system(o, v, 4, 40, sigma=0.3)
+    h = cs_ccsd.core_hamiltonian_df(B, np.diag(eps), o)
+    bf = BruteForce(h, _eri(B), o, v)
+    S, Sd = _s_ops(bf, o, v, hole, particle)
+    t1, t2 = ascc.initial_guess(o, v, hole, particle)
+    t1so, t2so = closed_shell_to_so(t1, t2)
+    psi = sla.expm(-Sd) @ bf.exp_T(t1so, t2so, bf.ref)
+    target = S @ bf.ref
+    assert np.abs(psi - target).max() < 1e-12
+    assert np.linalg.norm(target) > 0.99  # S|phi_0> is a normalised singlet CSF
+
+
+@pytest.mark.parametrize("o,v,Q,seed,hole,particle", CASES)
+def test_closed_shell_residual_of_the_transformed_hamiltonian(o, v, Q, seed, hole, particle):
+    """The dressed closed-shell oracle, fed the non-symmetric Bbar and fbar, equals the projections."""
+    B, eps = make_system(o, v, Q, seed, sigma=0.3)
+    Bbar, fbar = ascc.transformed_inputs(B, eps, o, hole, particle)
+    h = cs_ccsd.core_hamiltonian_df(B, np.diag(eps), o)
+    _, hbar = ascc.transform(B, h, hole, particle)
+    assert np.abs(cs_ccsd.core_hamiltonian_df(Bbar, fbar, o) - hbar).max() < 1e-12
+    t1, t2 = random_amplitudes(o, v, seed + 60, 0.1, 0.1)
+    t1, t2 = t1 + ascc.initial_guess(o, v, hole, particle)[0], t2 + ascc.initial_guess(o, v, hole, particle)[1]
+    t1so, t2so = closed_shell_to_so(t1, t2)
+    E, r1so, r2so = BruteForce(hbar, _eri(Bbar), o, v).projections(t1so, t2so)
+    R1, R2 = so_to_closed_shell(r1so, r2so, o, v)
+    r1, r2 = cs_ccsd.residual(Bbar, fbar, t1, t2)
+    assert np.abs(r1 - R1).max() < 1e-11
+    assert np.abs(r2 - R2).max() < 1e-11
+    e_ref = ascc.reference_energy(Bbar, fbar, o)
+    assert abs(E - e_ref - cs_ccsd.energy(Bbar, fbar, t1, t2)) < 1e-11
+
+
+@pytest.mark.parametrize("v,Q,seed,particle", [(3, 6, 41, 1), (4, 8, 42, 2), (5, 9, 43, 1)])
+def test_two_electron_ascc_solution_is_an_eigenstate(v, Q, seed, particle):
+    """With two electrons T1 + T2 is the full cluster operator, so a converged ASCC solution of Hbar is
+    an exact eigenstate of H (Sec. II.A: FCI in the limit of a complete T): its energy is in the
+    spectrum of H, and it is not the ground state the plain CC iteration would find."""
+    o, hole = 1, 0
+    B, eps = make_system(o, v, Q, seed, sigma=converging_sigma(v, Q))
+    Bbar, fbar = ascc.transformed_inputs(B, eps, o, hole, particle)
+    t1, t2 = ascc.initial_guess(o, v, hole, particle)
+    res = solver.solve(lambda a, b: cs_ccsd.residual(Bbar, fbar, a, b),
+                       lambda a, b: cs_ccsd.energy(Bbar, fbar, a, b), eps, t1, t2, maxiter=300, tol_rnorm=1e-11)
+    assert res["converged"]
+    E = ascc.reference_energy(Bbar, fbar, o) + res["E"]
+    h = cs_ccsd.core_hamiltonian_df(B, np.diag(eps), o)
+    H = BruteForce(h, _eri(B), o, v).hamiltonian_matrix()
+    ev = np.linalg.eigvalsh(H)
+    assert np.abs(ev - E).min() < 1e-9
+    assert abs(E - ev.min()) > 1e-3
