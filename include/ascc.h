@@ -115,6 +115,31 @@ int ascc_build_ints_ws(const double* d_B, const double* d_fock, int fock_is_diag
                        int precision, int vvvv_mode, void* d_workspace, size_t ws_bytes, void* stream,
                        ascc_ints** out);
 
+/* The integral set of the ASCC transformed Hamiltonian of a 1-CSF state (Sec. II.A):
+ * Hbar = e^{S^dagger} H e^{-S^dagger} (Eq. (eqn: sim)) with S = (1/sqrt 2)(p_up^dagger h_up +
+ * p_dn^dagger h_dn) (Eq. (eqn:1CSF-S)), where H is given exactly as for ascc_build_ints.
+ *   hole      the orbital h (occupied: 0 <= hole < no)
+ *   particle  the orbital p (virtual: no <= particle < no + nv, a full orbital index)
+ * S^dagger is one-body with the spatial matrix K = E_hp / sqrt 2 (K^2 = 0), so Hbar stays two-body:
+ * on the device every index pair of the DF factors and of the one-electron operator transforms as
+ * x -> (1 + K) x (1 - K) before the constant blocks are formed (Bbar is then not symmetric in p,q).
+ * The Jacobi denominators keep the diagonal of d_fock; the energy's f_ia is that of Hbar.  Every
+ * other call then works on this handle unchanged (the amplitude equations of Hbar are those of
+ * the ground state, Eq. (eqn:amp)); start it from ascc_initial_guess.  Synchronises `stream`.
+ * Errors: as ascc_build_ints; ASCC_E_ARG for a hole or particle out of range. */
+int ascc_build_ints_hbar(const double* d_B, const double* d_fock, int fock_is_diag, int no, int nv, int naux,
+                         int precision, int vvvv_mode, int hole, int particle, void* stream, ascc_ints** out);
+
+/* The initial cluster operator T^P(0) = beta S + gamma S^2 of Eq. (eqn:TP-guess) (the paper's
+ * values: beta = 1, gamma = -1/2), written as closed-shell amplitudes into caller-owned device
+ * arrays d_t1 [no][nv] and d_t2 [no][no][nv][nv]: every entry 0 except t1[hole][particle - no] =
+ * beta / sqrt 2 and t2[hole][hole][particle - no][particle - no] = gamma (S^2 has only the
+ * opposite-spin pair excitation).  With beta = 1 and gamma = -1/2, e^{-S^dagger} e^{T} |phi_0> is
+ * the 1-CSF reference S |phi_0> of Eq. (eqn: 1csf).  Asynchronous on `stream` (a kernel, no memset).
+ * Errors: ASCC_E_ARG, ASCC_E_HIP. */
+int ascc_initial_guess(double* d_t1, double* d_t2, int no, int nv, int hole, int particle, double beta, double gamma,
+                       void* stream);
+
 /* Residual and energy at the given amplitudes (Eqs. (eqn:energy), (eqn:amp)).
  *   d_t1 [no][nv], d_t2 [no][no][nv][nv] with t2[i][j][a][b] == t2[j][i][b][a] (read only)
  *   d_r1 [no][nv], d_r2 [no][no][nv][nv]  (written; R2 has the same pair symmetry)

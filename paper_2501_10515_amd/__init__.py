@@ -28,10 +28,12 @@ from ._lib import (  # noqa: F401
     Server,
     ascc_batch_reserve,
     ascc_build_ints,
+    ascc_build_ints_hbar,
     ascc_build_ints_ws,
     ascc_diis_create,
     ascc_diis_create_ws,
     ascc_diis_reset,
+    ascc_initial_guess,
     ascc_last_error,
     ascc_phase_count,
     ascc_phase_name,

@@ -82,6 +82,9 @@ def load_library():
     L.ascc_workspace_bytes.argtypes = [c_int, c_int, c_int, c_int, c_int, c_int, c_size_p, c_size_p]
     L.ascc_build_ints.argtypes = [vp, vp, c_int, c_int, c_int, c_int, c_int, c_int, vp, ctypes.POINTER(vp)]
     L.ascc_residual.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.ascc_build_ints_hbar.argtypes = [vp, vp, c_int, c_int, c_int, c_int, c_int, c_int, c_int, c_int, vp,
+                                       ctypes.POINTER(vp)]
+    L.ascc_initial_guess.argtypes = [vp, vp, c_int, c_int, c_int, c_int, c_double, c_double, vp]
     L.ascc_diis_create.argtypes = [vp, c_int, c_int, ctypes.POINTER(vp)]
     L.ascc_diis_reset.argtypes = [vp, vp]
     L.ascc_update.argtypes = [vp, vp, vp, vp, vp, vp, vp, c_double, vp, vp]
@@ -207,6 +210,32 @@ def ascc_build_ints(B: torch.Tensor, fock: torch.Tensor, no: int, precision: int
     _check(load_library().ascc_build_ints(pB, pf, diag, no, nv, naux, precision, vvvv_mode, _stream(stream),
                                           ctypes.byref(h)))
     return Ints(h, no, nv, naux)
+
+
+def ascc_build_ints_hbar(B: torch.Tensor, fock: torch.Tensor, no: int, hole: int, particle: int,
+                         precision: int = ASCC_PREC_FP64, vvvv_mode: int = ASCC_VVVV_FULL, stream=None) -> Ints:
+    """Integral set of the 1-CSF transformed Hamiltonian Hbar (``particle`` is a full orbital index)."""
+    naux, n, n2 = B.shape
+    if n != n2:
+        raise ValueError("B must be [naux][n][n]")
+    nv = n - no
+    pB = _dev(B, "B")
+    if fock.dim() == 1:
+        pf, diag = _dev(fock, "fock", (n,)), 1
+    else:
+        pf, diag = _dev(fock, "fock", (n, n)), 0
+    h = ctypes.c_void_p()
+    _check(load_library().ascc_build_ints_hbar(pB, pf, diag, no, nv, naux, precision, vvvv_mode, hole, particle,
+                                               _stream(stream), ctypes.byref(h)))
+    return Ints(h, no, nv, naux)
+
+
+def ascc_initial_guess(t1, t2, hole: int, particle: int, beta: float = 1.0, gamma: float = -0.5, stream=None):
+    """Write T^P(0) = beta S + gamma S^2 into device t1 [no][nv] and t2 [no][no][nv][nv]."""
+    no, nv = t1.shape
+    _check(load_library().ascc_initial_guess(_dev(t1, "t1", (no, nv)), _dev(t2, "t2", (no, no, nv, nv)), no, nv,
+                                             hole, particle, ctypes.c_double(beta), ctypes.c_double(gamma),
+                                             _stream(stream)))
 
 
 def ascc_residual(ints: Ints, t1, t2, r1, r2, e, stream=None):

@@ -880,7 +880,14 @@ int residual_fp64(ascc_ints* I, const double* t1, const double* t2, double* r1, 
   return residual_core(I, t1, t2, r1, r2, e, nullptr, s);
 }
 
-int build_constants(ascc_ints* I, const double* Bsrc, const double* fock, int fock_is_diag, hipStream_t s) {
+// hole >= 0: the integrals of Hbar = e^{S^dagger} H e^{-S^dagger} for S = (1/sqrt 2) sum_spin p^dagger h
+// (hole h occupied, particle p virtual; Sec. II.A, Eqs. (eqn:1CSF-S), (eqn: sim)).  S^dagger is
+// one-body with the spatial matrix K = E_hp / sqrt 2 (K^2 = 0), so every integral index pair
+// transforms as x -> (1 + K) x (1 - K): Bbar_Q and hbar, applied right after h is formed, so every
+// constant block below is one of Hbar.  The Jacobi denominators keep the diagonal of the given Fock
+// matrix; the f_ia of the energy is that of Hbar, fbar = hbar + sum_k [2 (pq|kk)bar - (pk|kq)bar].
+int build_constants(ascc_ints* I, const double* Bsrc, const double* fock, int fock_is_diag, int hole, int particle,
+                    hipStream_t s) {
   const int o = I->no, v = I->nv, Q = I->naux;
   const long n = I->n, nn = n * n, ov = I->ov, oo = I->oo, vv = I->vv, ovov = I->ovov;
   const long wzl = ov + oo;
@@ -909,6 +916,16 @@ int build_constants(ascc_ints* I, const double* Bsrc, const double* fock, int fo
   // h = f - sum_k (2 (pq|kk) - (pk|kq))
   int rc = add_two_electron_fock(I, I->h, I->B, I->J, o, v, Q, -1.0, s);
   if (rc) return rc;
+  if (hole >= 0) {
+    const double c = 1.0 / std::sqrt(2.0);
+    HIPCHK(onebody_transform(I->B, Q, (int)n, hole, particle, c, s));
+    HIPCHK(onebody_transform(I->h, 1, (int)n, hole, particle, c, s));
+    HIPCHK(d_copy(I->Fh, I->h, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
+    if ((rc = add_two_electron_fock(I, I->Fh, I->B, I->J, o, v, Q, 1.0, s))) return rc;  // fbar
+    int d[4] = {o, v, 1, 1};
+    Perm4In x = pin(I->Fh + o, n, 1, 0, 0, 1.0);
+    HIPCHK(permute4(I->fov, d, 0.0, &x, 1, s));
+  }
 
   // B_ov and the undressed B_vv, the latter as [a][c][Q] (K = Q contiguous, into the work array Bvv,
   // which every residual overwrites with the dressed [Q][a][c])
@@ -1113,23 +1130,48 @@ int ascc_ints_shape(const ascc_ints* I, int* no, int* nv, int* naux) {
 }
 
 static int build_ints_impl(const double* d_B, const double* d_fock, int fock_is_diag, int no, int nv, int naux,
-                           int precision, int vvvv_mode, void* ws, size_t ws_bytes, void* stream, ascc_ints** out);
+                           int precision, int vvvv_mode, int hole, int particle, void* ws, size_t ws_bytes,
+                           void* stream, ascc_ints** out);
 
 int ascc_build_ints(const double* d_B, const double* d_fock, int fock_is_diag, int no, int nv, int naux, int precision,
                     int vvvv_mode, void* stream, ascc_ints** out) {
-  return build_ints_impl(d_B, d_fock, fock_is_diag, no, nv, naux, precision, vvvv_mode, nullptr, 0, stream, out);
+  return build_ints_impl(d_B, d_fock, fock_is_diag, no, nv, naux, precision, vvvv_mode, -1, -1, nullptr, 0, stream,
+                         out);
+}
+
+int ascc_build_ints_hbar(const double* d_B, const double* d_fock, int fock_is_diag, int no, int nv, int naux,
+                         int precision, int vvvv_mode, int hole, int particle, void* stream, ascc_ints** out) {
+  if (out) *out = nullptr;
+  if (hole < 0 || hole >= no || particle < no || particle >= no + nv)
+    return fail(ASCC_E_ARG, "hole must be an occupied and particle a virtual orbital index");
+  return build_ints_impl(d_B, d_fock, fock_is_diag, no, nv, naux, precision, vvvv_mode, hole, particle, nullptr, 0,
+                         stream, out);
+}
+
+int ascc_initial_guess(double* d_t1, double* d_t2, int no, int nv, int hole, int particle, double beta, double gamma,
+                       void* stream) {
+  if (!d_t1 || !d_t2) return fail(ASCC_E_ARG, "NULL amplitude array");
+  if (no < 1 || nv < 1 || hole < 0 || hole >= no || particle < no || particle >= no + nv)
+    return fail(ASCC_E_ARG, "hole must be an occupied and particle a virtual orbital index");
+  ScopedBuffers user;
+  user.add(d_t1, sizeof(double) * no * nv);
+  user.add(d_t2, sizeof(double) * no * no * nv * nv);
+  HIPCHK(initial_guess(d_t1, d_t2, no, nv, hole, particle - no, beta / std::sqrt(2.0), gamma,
+                       static_cast<hipStream_t>(stream)));
+  return ASCC_OK;
 }
 
 int ascc_build_ints_ws(const double* d_B, const double* d_fock, int fock_is_diag, int no, int nv, int naux,
                        int precision, int vvvv_mode, void* d_workspace, size_t ws_bytes, void* stream,
                        ascc_ints** out) {
   if (!d_workspace) return fail(ASCC_E_ARG, "d_workspace is NULL");
-  return build_ints_impl(d_B, d_fock, fock_is_diag, no, nv, naux, precision, vvvv_mode, d_workspace, ws_bytes, stream,
-                         out);
+  return build_ints_impl(d_B, d_fock, fock_is_diag, no, nv, naux, precision, vvvv_mode, -1, -1, d_workspace, ws_bytes,
+                         stream, out);
 }
 
 static int build_ints_impl(const double* d_B, const double* d_fock, int fock_is_diag, int no, int nv, int naux,
-                           int precision, int vvvv_mode, void* ws, size_t ws_bytes, void* stream, ascc_ints** out) {
+                           int precision, int vvvv_mode, int hole, int particle, void* ws, size_t ws_bytes,
+                           void* stream, ascc_ints** out) {
   if (!out) return fail(ASCC_E_ARG, "out is NULL");
   *out = nullptr;
   if (!d_B || !d_fock) return fail(ASCC_E_ARG, "d_B and d_fock must be device pointers");
@@ -1174,7 +1216,7 @@ static int build_ints_impl(const double* d_B, const double* d_fock, int fock_is_
   ScopedBuffers user;
   user.add(d_B, sizeof(double) * Q * nn);
   user.add(d_fock, sizeof(double) * (fock_is_diag ? n : nn));
-  if (!rc) rc = build_constants(I, d_B, d_fock, fock_is_diag, s);
+  if (!rc) rc = build_constants(I, d_B, d_fock, fock_is_diag, hole, particle, s);
   if (!rc && precision != ASCC_PREC_FP64) rc = build_lowp_shadows(I, s);
   if (!rc && !ws) {  // a workspace build stays asynchronous on `stream`
     hipError_t e = d_sync(s);

@@ -78,12 +78,17 @@ __global__ __launch_bounds__(kThreads) void permute4_tiled_kernel(P4 p, int t, i
 }
 
 // Doubles residual, element (i,j,a,b) of the [o][o][v][v] output:
-//   R = G1[iajb] + RL[ijab] + EM[ijab] + EM[jiba]
+//   R = 1/2 (G1[iajb] + G1[jbia]) + 1/2 (RL[ijab] + RL[jiba]) + EM[ijab] + EM[jiba]
 //       - 1/2 (P1[jbia] + P1[iajb]) + 1/2 (P2[jbia] + P2[iajb]) - (P1[ibja] + P1[jaib])
-// (ovov arrays are [o][v][o][v]).  One workgroup per (i, j) and 32 x 32 block of (a, b): the four
-// terms that run along a (EM[jiba], P1[jbia], P2[jbia], P1[ibja]) are summed into an LDS tile
-// with reads along a, then the output row is written along b, where every other term is
-// contiguous, so all reads and writes are coalesced.
+// (ovov arrays are [o][v][o][v]).  G1 and RL are pair-symmetric in exact arithmetic; taking their
+// symmetric parts makes R[ijab] = R[jiba] whatever the rounding of the products behind them (a
+// low-precision ladder is not), so amplitudes that start pair-symmetric stay so.  The part of t2
+// odd under the joint (ij)(ab) swap is outside the closed-shell equations and barely damped by
+// the Jacobi step; fed by rounding, it stalls the DIIS iteration of excited (ASCC) states.
+// One workgroup per (i, j) and 32 x 32 block of (a, b): the six terms that run along a (EM[jiba],
+// RL[jiba], G1[jbia], P1[jbia], P2[jbia], P1[ibja]) are summed into an LDS tile with reads along
+// a, then the output row is written along b, where every other term is contiguous, so all reads
+// and writes are coalesced.
 __global__ __launch_bounds__(kThreads) void assemble_r2_kernel(double* __restrict__ r2, const double* __restrict__ g1,
                                                               const double* __restrict__ rl,
                                                               const double* __restrict__ em,
@@ -100,8 +105,11 @@ __global__ __launch_bounds__(kThreads) void assemble_r2_kernel(double* __restric
   for (int k = 0; k < 4; ++k) {  // tile[b - b0][a - a0], reads along a
     const int b = b0 + ty + 8 * k, a = a0 + tx;
     double t = 0.0;
-    if (a < v && b < v)
-      t = em[ji + (long)b * v + a] - 0.5 * p1[ov(j, b, i, a)] + 0.5 * p2[ov(j, b, i, a)] - p1[ov(i, b, j, a)];
+    if (a < v && b < v) {
+      const long jbia = ov(j, b, i, a);
+      t = em[ji + (long)b * v + a] + 0.5 * (rl[ji + (long)b * v + a] + g1[jbia]) - 0.5 * p1[jbia] + 0.5 * p2[jbia] -
+          p1[ov(i, b, j, a)];
+    }
     tile[ty + 8 * k][tx] = t;
   }
   __syncthreads();
@@ -111,7 +119,8 @@ __global__ __launch_bounds__(kThreads) void assemble_r2_kernel(double* __restric
     if (a < v && b < v) {
       const long x = ij + (long)a * v + b;
       const long iajb = ov(i, a, j, b);
-      r2[x] = g1[iajb] + rl[x] + em[x] - 0.5 * p1[iajb] + 0.5 * p2[iajb] - p1[ov(j, a, i, b)] + tile[tx][ty + 8 * k];
+      r2[x] = 0.5 * (g1[iajb] + rl[x]) + em[x] - 0.5 * p1[iajb] + 0.5 * p2[iajb] - p1[ov(j, a, i, b)] +
+              tile[tx][ty + 8 * k];
     }
   }
 }
@@ -162,6 +171,29 @@ __global__ __launch_bounds__(kThreads) void dress_apply_kernel(double* __restric
   for (int r = 0; r < RC; ++r) {
     const int p = r0 + r;
     if (p < n) Dz[(long)p * n + q] = acc[r];
+  }
+}
+
+// x -> (1 + c E_hp) x (1 - c E_hp) on each of nb stacked n x n matrices (E_hp: the unit matrix with a
+// one at row h, column p): row h += c row p, then column p -= c column h of the result.  One
+// workgroup per matrix; the two steps touch disjoint rows / columns of their own step.
+__global__ __launch_bounds__(kThreads) void onebody_transform_kernel(double* __restrict__ X, int n, int h, int p,
+                                                                     double c) {
+  double* Xz = X + (long)blockIdx.x * n * n;
+  for (int q = threadIdx.x; q < n; q += kThreads) Xz[(long)h * n + q] += c * Xz[(long)p * n + q];
+  __syncthreads();
+  for (int r = threadIdx.x; r < n; r += kThreads) Xz[(long)r * n + p] -= c * Xz[(long)r * n + h];
+}
+
+// t1 = 0 except t1[h][a] = s1; t2 = 0 except t2[h][h][a][a] = s2.
+__global__ __launch_bounds__(kThreads) void initial_guess_kernel(double* __restrict__ t1, double* __restrict__ t2,
+                                                                 long len1, long len2, long k1, long k2, double s1,
+                                                                 double s2) {
+  for (long x = blockIdx.x * (long)kThreads + threadIdx.x; x < len1 + len2; x += (long)gridDim.x * kThreads) {
+    if (x < len1)
+      t1[x] = (x == k1) ? s1 : 0.0;
+    else
+      t2[x - len1] = (x - len1 == k2) ? s2 : 0.0;
   }
 }
 
@@ -741,6 +773,27 @@ hipError_t dress_apply(double* D, const double* S, const double* Tc, const doubl
   if (dry_run()) return hipSuccess;
   hipLaunchKernelGGL(dress_apply_kernel, dim3((unsigned)((n + 31) / 32), (unsigned)((n + kThreads - 1) / kThreads), (unsigned)nb),
                      dim3(kThreads), 0, s, D, S, Tc, t1, o, v);
+  return hipGetLastError();
+}
+
+hipError_t onebody_transform(double* X, long nb, int n, int h, int p, double c, hipStream_t s) {
+  if (nb < 1 || n < 1) return hipSuccess;
+  if (h < 0 || h >= n || p < 0 || p >= n || h == p || nb > 0x7fffffffL) return hipErrorInvalidValue;
+  if (bounds_checking() && !range_ok(X, 0, nb * n * n - 1, 8, "one-body transform")) return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  hipLaunchKernelGGL(onebody_transform_kernel, dim3((unsigned)nb), dim3(kThreads), 0, s, X, n, h, p, c);
+  return hipGetLastError();
+}
+
+hipError_t initial_guess(double* t1, double* t2, int no, int nv, int h, int a, double s1, double s2, hipStream_t s) {
+  const long len1 = (long)no * nv, len2 = len1 * len1;
+  if (h < 0 || h >= no || a < 0 || a >= nv) return hipErrorInvalidValue;
+  if (bounds_checking() && !(range_ok(t1, 0, len1 - 1, 8, "guess t1") && range_ok(t2, 0, len2 - 1, 8, "guess t2")))
+    return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  const long k1 = (long)h * nv + a, k2 = (((long)h * no + h) * nv + a) * nv + a;
+  hipLaunchKernelGGL(initial_guess_kernel, dim3(grid_for(len1 + len2)), dim3(kThreads), 0, s, t1, t2, len1, len2, k1,
+                     k2, s1, s2);
   return hipGetLastError();
 }
 

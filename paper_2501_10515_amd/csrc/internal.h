@@ -168,6 +168,11 @@ hipError_t add_fvo(double* r1, const double* fhat, int no, int nv, hipStream_t s
 hipError_t dress_apply(double* D, const double* S, const double* Tc, const double* t1, int o, int v, int nb,
                        hipStream_t s);
 
+// x -> (1 + c E_hp) x (1 - c E_hp) in place on nb stacked n x n matrices (E_hp: one at row h, column p).
+hipError_t onebody_transform(double* X, long nb, int n, int h, int p, double c, hipStream_t s);
+// t1 = 0, t2 = 0 except t1[h][a] = s1 and t2[h][h][a][a] = s2.
+hipError_t initial_guess(double* t1, double* t2, int no, int nv, int h, int a, double s1, double s2, hipStream_t s);
+
 // J[Q] = sum_k Bh[Q][k][k]
 hipError_t diag_trace(double* J, const double* Bh, int naux, int n, int no, hipStream_t s);
 

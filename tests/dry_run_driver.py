@@ -46,6 +46,8 @@ def main(shapes):
     L.ascc_diis_create_ws.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, ctypes.c_size_t, ctypes.POINTER(vp)]
     L.ascc_ints_free.argtypes = [vp]
     L.ascc_diis_free.argtypes = [vp]
+    L.ascc_build_ints_hbar.argtypes = [vp, vp] + [ctypes.c_int] * 8 + [vp, ctypes.POINTER(vp)]
+    L.ascc_initial_guess.argtypes = [vp, vp] + [ctypes.c_int] * 4 + [ctypes.c_double] * 2 + [vp]
     ok = True
     for shape in shapes:
         o, v, Q, diag = shape[:4]
@@ -90,6 +92,16 @@ def main(shapes):
                 rc = L.ascc_solve(h, ctypes.byref(Opts(1e-8, 0, 0, 3, 8, 1, 0.0, 1e-3, 1)), t1, t2, ctypes.byref(res),
                                   None)
             L.ascc_ints_free(h)
+        if rc == 0:  # the transformed Hamiltonian of a 1-CSF state, its guess and one residual
+            h4 = vp()
+            rc = L.ascc_build_ints_hbar(B, F, diag, o, v, Q, prec, mode, o - 1, o, None, ctypes.byref(h4))
+            if rc == 0:
+                t1, t2, r1, r2, e = (fake(8 * o * v), fake(8 * o * o * v * v), fake(8 * o * v),
+                                     fake(8 * o * o * v * v), fake(8))
+                rc = L.ascc_initial_guess(t1, t2, o, v, o - 1, o, ctypes.c_double(1.0), ctypes.c_double(-0.5), None)
+                if rc == 0:
+                    rc = L.ascc_residual(h4, t1, t2, r1, r2, e, None)
+                L.ascc_ints_free(h4)
         if rc == 0:  # the same build and an update carved from exact-size workspaces
             ib, dbytes = ctypes.c_size_t(), ctypes.c_size_t()
             rc = L.ascc_workspace_bytes(o, v, Q, prec, mode, 8, ctypes.byref(ib), ctypes.byref(dbytes))

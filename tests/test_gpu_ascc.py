@@ -1,0 +1,166 @@
+"""The ASCC transformed Hamiltonian of a 1-CSF state on the GPU (ascc_build_ints_hbar,
+ascc_initial_guess), through the C ABI, against the oracle (oracle/ascc.py, itself pinned to
+determinant-space matrix exponentials and the two-electron eigenstate limit)."""
+import numpy as np
+import pytest
+
+from gen.synth_df import converging_sigma, make_system, random_amplitudes, random_symmetric_fock
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2501_10515_amd as P
+
+    P.load_library()
+    return P
+
+
+SHAPES = [
+    (2, 3, 8, 1, 0, 3, False),    # smallest with a hole below the top
+    (3, 5, 12, 2, 2, 3, True),    # non-canonical Fock matrix
+    (5, 20, 60, 0, 4, 5, False),  # HOMO -> LUMO at o5 v20 Q60
+    (7, 45, 37, 3, 6, 9, True),   # ragged against every tile size
+    (4, 70, 150, 4, 1, 30, False),
+]
+
+
+@pytest.mark.parametrize("mode", ["full", "packed"])
+@pytest.mark.parametrize("o,v,Q,seed,hole,particle,full", SHAPES)
+def test_hbar_residual_and_energy_match_oracle(P, o, v, Q, seed, hole, particle, full, mode):
+    from oracle import ascc, cs_ccsd
+
+    from .gpu_util import dev, gpu_residual
+
+    print(f"case o={o} v={v} Q={Q} seed={seed} hole={hole} particle={particle} full={full} vvvv={mode}", flush=True)
+    B, eps = make_system(o, v, Q, seed, sigma=0.1)
+    fock = random_symmetric_fock(eps, 0.05, seed + 7) if full else np.diag(eps)
+    Bbar, fbar = ascc.transformed_inputs(B, fock, o, hole, particle)
+    t1, t2 = random_amplitudes(o, v, seed + 100, 0.05, 0.05)
+    g1, g2 = ascc.initial_guess(o, v, hole, particle)
+    t1, t2 = t1 + g1, t2 + g2
+    r1_ref, r2_ref = cs_ccsd.residual(Bbar, fbar, t1, t2)
+    e_ref = cs_ccsd.energy(Bbar, fbar, t1, t2)
+    vm = P.ASCC_VVVV_FULL if mode == "full" else P.ASCC_VVVV_PACKED
+    ints = P.ascc_build_ints_hbar(dev(B), dev(fock if full else eps), o, hole, particle, vvvv_mode=vm)
+    r1, r2, e = gpu_residual(P, ints, t1, t2)
+    ints.close()
+    scale = max(1.0, np.abs(r2_ref).max())
+    assert np.abs(r1 - r1_ref).max() <= TOL * scale
+    assert np.abs(r2 - r2_ref).max() <= TOL * scale
+    assert abs(e - e_ref) <= TOL * scale
+
+
+# error bounds relative to max|R|, as for the untransformed Hamiltonian (tests/test_gpu_lowp.py)
+REL = {"fp32": 2e-6, "bf16x3": 4e-5}
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("o,v,Q,seed,hole,particle,full", [SHAPES[1], SHAPES[3], (3, 12, 36, 7, 2, 3, False)])
+def test_hbar_low_precision_residual_error_is_bounded(P, o, v, Q, seed, hole, particle, full, prec):
+    from oracle import ascc, cs_ccsd
+
+    from .gpu_util import dev, gpu_residual
+
+    print(f"case o={o} v={v} Q={Q} seed={seed} hole={hole} particle={particle} full={full} {prec}", flush=True)
+    B, eps = make_system(o, v, Q, seed, sigma=0.1)
+    fock = random_symmetric_fock(eps, 0.05, seed + 7) if full else np.diag(eps)
+    Bbar, fbar = ascc.transformed_inputs(B, fock, o, hole, particle)
+    t1, t2 = random_amplitudes(o, v, seed + 100, 0.05, 0.05)
+    g1, g2 = ascc.initial_guess(o, v, hole, particle)
+    t1, t2 = t1 + g1, t2 + g2
+    r1_ref, r2_ref = cs_ccsd.residual(Bbar, fbar, t1, t2)
+    pc = P.ASCC_PREC_FP32 if prec == "fp32" else P.ASCC_PREC_BF16X3
+    ints = P.ascc_build_ints_hbar(dev(B), dev(fock if full else eps), o, hole, particle, precision=pc,
+                                  vvvv_mode=P.ASCC_VVVV_PACKED)
+    r1, r2, _ = gpu_residual(P, ints, t1, t2)
+    ints.close()
+    scale = max(np.abs(r2_ref).max(), np.abs(r1_ref).max())
+    err = max(np.abs(r1 - r1_ref).max(), np.abs(r2 - r2_ref).max())
+    print(f"  max|dR| = {err:.3e}  (max|R| = {scale:.3e}, rel {err / scale:.2e})", flush=True)
+    assert err <= REL[prec] * scale
+    # pair symmetry R_ij^ab = R_ji^ba holds to FP64 rounding, not to the low precision's: the
+    # iteration must not feed the part of t2 odd under the joint swap
+    assert np.abs(r2 - r2.transpose(1, 0, 3, 2)).max() <= 1e-14 * scale
+
+
+def test_initial_guess_entries(P):
+    import torch
+
+    from oracle import ascc
+
+    o, v, hole, particle = 4, 7, 1, 6
+    t1 = torch.full((o, v), 3.0, dtype=torch.float64, device="cuda")
+    t2 = torch.full((o, o, v, v), 3.0, dtype=torch.float64, device="cuda")
+    P.ascc_initial_guess(t1, t2, hole, particle, beta=0.9, gamma=-0.405)
+    torch.cuda.synchronize()
+    r1, r2 = ascc.initial_guess(o, v, hole, particle, beta=0.9, gamma=-0.405)
+    assert np.array_equal(t1.cpu().numpy(), r1)
+    assert np.array_equal(t2.cpu().numpy(), r2)
+
+
+# systems whose excited-state iteration converges from T^P(0) in the oracle
+SOLVES = [(3, 12, 36, 7, 2, 3), (4, 16, 48, 3, 3, 4), (6, 24, 72, 5, 5, 6)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+@pytest.mark.parametrize("o,v,Q,seed,hole,particle", SOLVES)
+def test_ascc_solve_from_the_guess_matches_oracle(P, o, v, Q, seed, hole, particle, prec):
+    import torch
+
+    from oracle import ascc, cs_ccsd, solver
+
+    print(f"solve o={o} v={v} Q={Q} seed={seed} {hole}->{particle} {prec}", flush=True)
+    B, eps = make_system(o, v, Q, seed, sigma=converging_sigma(v, Q))
+    Bbar, fbar = ascc.transformed_inputs(B, eps, o, hole, particle)
+    g1, g2 = ascc.initial_guess(o, v, hole, particle)
+    # the excited-state iteration creeps near |R| ~ 1e-9 (a slow mode of the Jacobi step), so the
+    # oracle is taken well past the GPU tolerance and the comparison bound covers |R| = 1e-8
+    ref = solver.solve(lambda a, b: cs_ccsd.residual(Bbar, fbar, a, b),
+                       lambda a, b: cs_ccsd.energy(Bbar, fbar, a, b), eps, g1, g2, maxiter=600, tol_rnorm=1e-11)
+    assert ref["converged"]
+    pc = P.ASCC_PREC_FP64 if prec == "fp64" else P.ASCC_PREC_BF16X3
+    ints = P.ascc_build_ints_hbar(torch.from_numpy(B).cuda(), torch.from_numpy(eps).cuda(), o, hole, particle,
+                                  precision=pc, vvvv_mode=P.ASCC_VVVV_PACKED)
+    t1 = torch.empty((o, v), dtype=torch.float64, device="cuda")
+    t2 = torch.empty((o, o, v, v), dtype=torch.float64, device="cuda")
+    P.ascc_initial_guess(t1, t2, hole, particle)
+    res = P.ascc_solve(ints, t1, t2, tol_rnorm=1e-8, maxiter=400, lowp_rnorm=1e-6 if prec != "fp64" else 0.0,
+                       raise_on_not_converged=False)
+    ints.close()
+    print(prec, res, ref["E"], flush=True)
+    assert res["converged"]
+    assert abs(res["e_corr"] - ref["E"]) <= 2e-8
+    assert np.abs(t2.cpu().numpy() - ref["t2"]).max() <= 1e-7
+
+
+def test_two_electron_ascc_energy_is_an_excited_eigenvalue(P):
+    import torch
+
+    from oracle import ascc, cs_ccsd
+    from oracle.bruteforce import BruteForce
+
+    o, v, Q, seed, hole, particle = 1, 4, 8, 42, 0, 3
+    B, eps = make_system(o, v, Q, seed, sigma=converging_sigma(v, Q))
+    ints = P.ascc_build_ints_hbar(torch.from_numpy(B).cuda(), torch.from_numpy(eps).cuda(), o, hole, particle,
+                                  vvvv_mode=P.ASCC_VVVV_PACKED)
+    t1 = torch.empty((o, v), dtype=torch.float64, device="cuda")
+    t2 = torch.empty((o, o, v, v), dtype=torch.float64, device="cuda")
+    P.ascc_initial_guess(t1, t2, hole, particle)
+    res = P.ascc_solve(ints, t1, t2, tol_rnorm=1e-11, maxiter=400)
+    ints.close()
+    assert res["converged"]
+    Bbar, fbar = ascc.transformed_inputs(B, eps, o, hole, particle)
+    E = ascc.reference_energy(Bbar, fbar, o) + res["e_corr"]
+    h = cs_ccsd.core_hamiltonian_df(B, np.diag(eps), o)
+    ev = np.linalg.eigvalsh(BruteForce(h, np.einsum("Qpq,Qrs->pqrs", B, B), o, v).hamiltonian_matrix())
+    print("E", E, "spectrum", ev, flush=True)
+    assert np.abs(ev - E).min() < 1e-9
+    assert abs(E - ev.min()) > 1e-3
