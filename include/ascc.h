@@ -287,6 +287,17 @@ const char* ascc_phase_name(int k);
 int ascc_timing_enable(ascc_ints* ints, int enable);
 int ascc_timing_read(ascc_ints* ints, double* ms, int* counts, int n);
 
+/* Reference energy <phi_0|H|phi_0> of an integral set (paper Eq. (eqn:energy): the total energy
+ * is this plus the correlation energy that ascc_residual / ascc_solve report), formed at build time
+ * as sum_{i<no} (h_ii + f_ii) from the core Hamiltonian h = f - sum_k [2 (pq|kk) - (pk|kq)] and the
+ * reference Fock matrix f.  For a set from ascc_build_ints_hbar both are the transformed ones
+ * (hbar, fbar of Eq. (eqn: sim)), so <phi_0|Hbar|phi_0> + e_corr is the ASCC total energy of the
+ * state and its difference from the ground-state total is the excitation energy.
+ *   e0      HOST pointer to one double (written).
+ *   stream  the stream the handle was built on (or 0): waited for before reading.
+ * Errors: ASCC_E_ARG for NULL arguments, ASCC_E_HIP if the copy fails.  A dry run writes 0. */
+int ascc_reference_energy(const ascc_ints* ints, double* e0, void* stream);
+
 /* Shape queries on a built handle (host-only). */
 int ascc_ints_shape(const ascc_ints* ints, int* no, int* nv, int* naux);
 

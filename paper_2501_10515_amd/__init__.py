@@ -37,6 +37,7 @@ from ._lib import (  # noqa: F401
     ascc_last_error,
     ascc_phase_count,
     ascc_phase_name,
+    ascc_reference_energy,
     ascc_timing_enable,
     ascc_timing_read,
     ascc_get_precision,

@@ -66,7 +66,8 @@ EXPORTS = ("ascc_workspace_bytes", "ascc_build_ints", "ascc_residual", "ascc_dii
            "ascc_phase_count", "ascc_phase_name", "ascc_timing_enable", "ascc_timing_read", "ascc_set_precision",
            "ascc_get_precision", "ascc_batch_reserve", "ascc_residual_batch", "ascc_build_ints_ws",
            "ascc_diis_create_ws", "ascc_server_create", "ascc_server_submit", "ascc_server_step",
-           "ascc_server_info", "ascc_server_free")
+           "ascc_server_info", "ascc_server_free", "ascc_build_ints_hbar", "ascc_initial_guess",
+           "ascc_reference_energy")
 
 
 def load_library():
@@ -85,6 +86,7 @@ def load_library():
     L.ascc_build_ints_hbar.argtypes = [vp, vp, c_int, c_int, c_int, c_int, c_int, c_int, c_int, c_int, vp,
                                        ctypes.POINTER(vp)]
     L.ascc_initial_guess.argtypes = [vp, vp, c_int, c_int, c_int, c_int, c_double, c_double, vp]
+    L.ascc_reference_energy.argtypes = [vp, ctypes.POINTER(c_double), vp]
     L.ascc_diis_create.argtypes = [vp, c_int, c_int, ctypes.POINTER(vp)]
     L.ascc_diis_reset.argtypes = [vp, vp]
     L.ascc_update.argtypes = [vp, vp, vp, vp, vp, vp, vp, c_double, vp, vp]
@@ -236,6 +238,13 @@ def ascc_initial_guess(t1, t2, hole: int, particle: int, beta: float = 1.0, gamm
     _check(load_library().ascc_initial_guess(_dev(t1, "t1", (no, nv)), _dev(t2, "t2", (no, no, nv, nv)), no, nv,
                                              hole, particle, ctypes.c_double(beta), ctypes.c_double(gamma),
                                              _stream(stream)))
+
+
+def ascc_reference_energy(ints: Ints, stream=None) -> float:
+    """<phi_0|H|phi_0> of the integral set (of Hbar for an ascc_build_ints_hbar set); waits for the stream."""
+    e0 = ctypes.c_double()
+    _check(load_library().ascc_reference_energy(ints.handle, ctypes.byref(e0), _stream(stream)))
+    return e0.value
 
 
 def ascc_residual(ints: Ints, t1, t2, r1, r2, e, stream=None):

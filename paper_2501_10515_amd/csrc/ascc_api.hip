@@ -160,6 +160,7 @@ struct ascc_ints {
   double* h;      // [n][n] core Hamiltonian
   double* eps;    // [n] Fock diagonal
   double* fov;    // [o][v] reference Fock, occupied-virtual block
+  double* e0;     // [1] reference energy <phi_0|H|phi_0> = sum_i (h_ii + f_ii)
   double* Bov;    // [Q][o][v]
   double* BovT;   // [o][v][Q]: the same, K = Q contiguous
   double* KL;     // [2][ov][ov]: (ib|ja), 2(ia|jb) - (ib|ja)
@@ -281,7 +282,8 @@ std::vector<std::pair<double* ascc_ints::*, long>> ints_plan(long o, long v, lon
   const bool full = (mode == ASCC_VVVV_FULL);
   return {
       {&ascc_ints::B, Q * nn},        {&ascc_ints::h, nn},           {&ascc_ints::eps, n},
-      {&ascc_ints::fov, ov},          {&ascc_ints::Bov, Q * ov},     {&ascc_ints::KL, 2 * ovov},
+      {&ascc_ints::fov, ov},          {&ascc_ints::e0, 1},
+      {&ascc_ints::Bov, Q * ov},      {&ascc_ints::KL, 2 * ovov},
       {&ascc_ints::Lijab, oo * vv},   {&ascc_ints::Gwz, vv * (ov + oo)},
       {&ascc_ints::BovT, ov * Q},
       {&ascc_ints::V, full ? vv * vv : 2 * Tv * Tv},
@@ -925,6 +927,10 @@ int build_constants(ascc_ints* I, const double* Bsrc, const double* fock, int fo
     int d[4] = {o, v, 1, 1};
     Perm4In x = pin(I->Fh + o, n, 1, 0, 0, 1.0);
     HIPCHK(permute4(I->fov, d, 0.0, &x, 1, s));
+    // the transformed reference energy, while Fh still holds fbar (residuals reuse Fh as work)
+    HIPCHK(reference_energy(I->e0, I->h, n + 1, nn, I->Fh, n + 1, nn, o, s));
+  } else {
+    HIPCHK(reference_energy(I->e0, I->h, n + 1, nn, I->eps, 1, n, o, s));
   }
 
   // B_ov and the undressed B_vv, the latter as [a][c][Q] (K = Q contiguous, into the work array Bvv,
@@ -1119,6 +1125,18 @@ int ascc_timing_read(ascc_ints* I, double* ms, int* counts, int n) {
   }
   I->marks.clear();
   return rc;
+}
+
+int ascc_reference_energy(const ascc_ints* I, double* e0, void* stream) {
+  if (!I || !e0) return fail(ASCC_E_ARG, "NULL argument to ascc_reference_energy");
+  if (dry_run()) {
+    *e0 = 0.0;
+    return ASCC_OK;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (d_copy(e0, I->e0, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess || d_sync(s) != hipSuccess)
+    return fail(ASCC_E_HIP, "reading the reference energy failed");
+  return ASCC_OK;
 }
 
 int ascc_ints_shape(const ascc_ints* I, int* no, int* nv, int* naux) {

@@ -797,6 +797,33 @@ hipError_t initial_guess(double* t1, double* t2, int no, int nv, int h, int a, d
   return hipGetLastError();
 }
 
+// e0 = sum_{i<o} (h[i * hs] + f[i * fs]): one workgroup, fixed-order tree sum (o <= 256 per thread pass).
+__global__ __launch_bounds__(kThreads) void reference_energy_kernel(double* e0, const double* h, long hs,
+                                                                   const double* f, long fs, int o) {
+  __shared__ double red[kThreads];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < o; i += kThreads) acc += h[(long)i * hs] + f[(long)i * fs];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) e0[0] = red[0];
+}
+
+hipError_t reference_energy(double* e0, const double* h, long hs, long hlen, const double* f, long fs, long flen,
+                            int o, hipStream_t s) {
+  if (o < 1 || hs < 0 || fs < 0) return hipErrorInvalidValue;
+  if (bounds_checking() && !(range_ok(e0, 0, 0, 8, "reference energy e0") &&
+                             range_ok(h, 0, hlen - 1, 8, "reference energy h") && (o - 1) * hs < hlen &&
+                             range_ok(f, 0, flen - 1, 8, "reference energy f") && (o - 1) * fs < flen))
+    return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  hipLaunchKernelGGL(reference_energy_kernel, dim3(1), dim3(kThreads), 0, s, e0, h, hs, f, fs, o);
+  return hipGetLastError();
+}
+
 hipError_t diag_trace(double* J, const double* Bh, int naux, int n, int no, hipStream_t s) {
   if (bounds_checking() && !(range_ok(J, 0, naux - 1, 8, "trace J") &&
                              range_ok(Bh, 0, (long)naux * n * n - 1, 8, "trace B")))

@@ -170,6 +170,9 @@ hipError_t dress_apply(double* D, const double* S, const double* Tc, const doubl
 
 // x -> (1 + c E_hp) x (1 - c E_hp) in place on nb stacked n x n matrices (E_hp: one at row h, column p).
 hipError_t onebody_transform(double* X, long nb, int n, int h, int p, double c, hipStream_t s);
+// e0[0] = sum_{i<o} (h[i * hs] + f[i * fs]) (hlen, flen: elements of h and f, for the bounds check).
+hipError_t reference_energy(double* e0, const double* h, long hs, long hlen, const double* f, long fs, long flen,
+                            int o, hipStream_t s);
 // t1 = 0, t2 = 0 except t1[h][a] = s1 and t2[h][h][a][a] = s2.
 hipError_t initial_guess(double* t1, double* t2, int no, int nv, int h, int a, double s1, double s2, hipStream_t s);
 

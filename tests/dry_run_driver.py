@@ -48,6 +48,7 @@ def main(shapes):
     L.ascc_diis_free.argtypes = [vp]
     L.ascc_build_ints_hbar.argtypes = [vp, vp] + [ctypes.c_int] * 8 + [vp, ctypes.POINTER(vp)]
     L.ascc_initial_guess.argtypes = [vp, vp] + [ctypes.c_int] * 4 + [ctypes.c_double] * 2 + [vp]
+    L.ascc_reference_energy.argtypes = [vp, ctypes.POINTER(ctypes.c_double), vp]
     ok = True
     for shape in shapes:
         o, v, Q, diag = shape[:4]
@@ -101,6 +102,9 @@ def main(shapes):
                 rc = L.ascc_initial_guess(t1, t2, o, v, o - 1, o, ctypes.c_double(1.0), ctypes.c_double(-0.5), None)
                 if rc == 0:
                     rc = L.ascc_residual(h4, t1, t2, r1, r2, e, None)
+                if rc == 0:
+                    e0 = ctypes.c_double(1.0)
+                    rc = L.ascc_reference_energy(h4, ctypes.byref(e0), None)
                 L.ascc_ints_free(h4)
         if rc == 0:  # the same build and an update carved from exact-size workspaces
             ib, dbytes = ctypes.c_size_t(), ctypes.c_size_t()

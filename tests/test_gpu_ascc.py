@@ -51,11 +51,18 @@ def test_hbar_residual_and_energy_match_oracle(P, o, v, Q, seed, hole, particle,
     vm = P.ASCC_VVVV_FULL if mode == "full" else P.ASCC_VVVV_PACKED
     ints = P.ascc_build_ints_hbar(dev(B), dev(fock if full else eps), o, hole, particle, vvvv_mode=vm)
     r1, r2, e = gpu_residual(P, ints, t1, t2)
+    e0 = P.ascc_reference_energy(ints)
     ints.close()
     scale = max(1.0, np.abs(r2_ref).max())
     assert np.abs(r1 - r1_ref).max() <= TOL * scale
     assert np.abs(r2 - r2_ref).max() <= TOL * scale
     assert abs(e - e_ref) <= TOL * scale
+    assert abs(e0 - ascc.reference_energy(Bbar, fbar, o)) <= TOL * max(1.0, abs(e0))
+    # and of the untransformed set
+    ints = P.ascc_build_ints(dev(B), dev(fock if full else eps), o, vvvv_mode=vm)
+    e0 = P.ascc_reference_energy(ints)
+    ints.close()
+    assert abs(e0 - ascc.reference_energy(B, fock, o)) <= TOL * max(1.0, abs(e0))
 
 
 # error bounds relative to max|R|, as for the untransformed Hamiltonian (tests/test_gpu_lowp.py)
@@ -155,10 +162,9 @@ def test_two_electron_ascc_energy_is_an_excited_eigenvalue(P):
     t2 = torch.empty((o, o, v, v), dtype=torch.float64, device="cuda")
     P.ascc_initial_guess(t1, t2, hole, particle)
     res = P.ascc_solve(ints, t1, t2, tol_rnorm=1e-11, maxiter=400)
+    E = P.ascc_reference_energy(ints) + res["e_corr"]  # the total energy, entirely from the GPU
     ints.close()
     assert res["converged"]
-    Bbar, fbar = ascc.transformed_inputs(B, eps, o, hole, particle)
-    E = ascc.reference_energy(Bbar, fbar, o) + res["e_corr"]
     h = cs_ccsd.core_hamiltonian_df(B, np.diag(eps), o)
     ev = np.linalg.eigvalsh(BruteForce(h, np.einsum("Qpq,Qrs->pqrs", B, B), o, v).hamiltonian_matrix())
     print("E", E, "spectrum", ev, flush=True)
