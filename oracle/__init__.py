@@ -21,4 +21,7 @@ Contents, each module citing the passage of the paper it follows:
   state (Eqs. (eqn:1CSF-S), (eqn: sim)) and the initial guess T^P(0) = S - S^2/2
   (Eq. (eqn:TP-guess)), pinned to determinant-space matrix exponentials and to the
   two-electron limit.
+* ``plascc``      -- the partially linearised residual (Sec. II.C): the closed-shell residual
+  without its terms with two powers of the mixed doubles T^M (Eq. (eqn: pnm split)), pinned to
+  brute-force projections with T^M taken in the spin-orbital basis.
 """
