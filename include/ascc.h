@@ -287,6 +287,22 @@ const char* ascc_phase_name(int k);
 int ascc_timing_enable(ascc_ints* ints, int enable);
 int ascc_timing_read(ascc_ints* ints, double* ms, int* counts, int n);
 
+/* Partial linearisation, PLASCC (paper Sec. II.C): later residuals of this integral set leave out
+ * every term that carries two or more powers of the mixed doubles T^M, the amplitudes whose index
+ * set holds both a primary orbital (the hole or the particle of S) and a non-primary one
+ * (Sec. II.B, Eq. (eqn: pnm split)); singles count for nothing here (kept to all orders).  The
+ * doubles residual is of degree two in T2, so exactly its part quadratic in T^M is removed; the
+ * singles residual and the energy are unchanged.  The paper applies the same removal, with the
+ * same primaries, to the ground-state equations: call this on an ascc_build_ints set too.
+ *   hole      occupied orbital index in [0, no), or < 0 to return to the full equations.
+ *   particle  virtual orbital index in [no, no + nv) (full orbital numbering).
+ * The first call with hole >= 0 allocates device work buffers of
+ * 5 m no nv + naux (no nv + 2 m) doubles, m = no + nv - 1 (library-allocated even for a set built
+ * in a caller workspace; released by ascc_ints_free).  The removal costs N^5 work per residual.
+ * Host call, no stream work.  Errors: ASCC_E_ARG (NULL handle, indices out of range),
+ * ASCC_E_NOMEM. */
+int ascc_set_plascc(ascc_ints* ints, int hole, int particle);
+
 /* Reference energy <phi_0|H|phi_0> of an integral set (paper Eq. (eqn:energy): the total energy
  * is this plus the correlation energy that ascc_residual / ascc_solve report), formed at build time
  * as sum_{i<no} (h_ii + f_ii) from the core Hamiltonian h = f - sum_k [2 (pq|kk) - (pk|kq)] and the

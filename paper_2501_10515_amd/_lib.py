@@ -67,7 +67,7 @@ EXPORTS = ("ascc_workspace_bytes", "ascc_build_ints", "ascc_residual", "ascc_dii
            "ascc_get_precision", "ascc_batch_reserve", "ascc_residual_batch", "ascc_build_ints_ws",
            "ascc_diis_create_ws", "ascc_server_create", "ascc_server_submit", "ascc_server_step",
            "ascc_server_info", "ascc_server_free", "ascc_build_ints_hbar", "ascc_initial_guess",
-           "ascc_reference_energy")
+           "ascc_reference_energy", "ascc_set_plascc")
 
 
 def load_library():
@@ -87,6 +87,7 @@ def load_library():
                                        ctypes.POINTER(vp)]
     L.ascc_initial_guess.argtypes = [vp, vp, c_int, c_int, c_int, c_int, c_double, c_double, vp]
     L.ascc_reference_energy.argtypes = [vp, ctypes.POINTER(c_double), vp]
+    L.ascc_set_plascc.argtypes = [vp, c_int, c_int]
     L.ascc_diis_create.argtypes = [vp, c_int, c_int, ctypes.POINTER(vp)]
     L.ascc_diis_reset.argtypes = [vp, vp]
     L.ascc_update.argtypes = [vp, vp, vp, vp, vp, vp, vp, c_double, vp, vp]
@@ -238,6 +239,11 @@ def ascc_initial_guess(t1, t2, hole: int, particle: int, beta: float = 1.0, gamm
     _check(load_library().ascc_initial_guess(_dev(t1, "t1", (no, nv)), _dev(t2, "t2", (no, no, nv, nv)), no, nv,
                                              hole, particle, ctypes.c_double(beta), ctypes.c_double(gamma),
                                              _stream(stream)))
+
+
+def ascc_set_plascc(ints: Ints, hole: int, particle: int = -1):
+    """Leave out the terms with two powers of the mixed doubles in later residuals (hole < 0: off)."""
+    _check(load_library().ascc_set_plascc(ints.handle, hole, particle))
 
 
 def ascc_reference_energy(ints: Ints, stream=None) -> float:

@@ -198,6 +198,11 @@ struct ascc_ints {
   double *Tp_all = nullptr, *Rp_all = nullptr, *RL_all = nullptr;
   float* Tpf_all = nullptr;
   Pool batch;
+  // partial linearisation (ascc_set_plascc): primaries and the slab buffers of the removal
+  int pl_hole = -1, pl_pa = -1;
+  double *plA = nullptr, *plC = nullptr, *plK = nullptr, *plW = nullptr, *plG = nullptr;  // [m][ov] / [ov][m]
+  double *plN = nullptr, *plBp = nullptr, *plNw = nullptr;                              // [Q][ov], [Q][m] x 2
+  Pool pl;
   // optional per-phase timing with HIP events (ascc_timing_enable)
   bool timing = false;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;  // (phase, (start, end))
@@ -216,10 +221,10 @@ namespace {
 
 const char* const kPhaseNames[] = {"dress",  "amp_views", "df_ints", "wz",      "pp_pack",  "pp_ladder",
                                    "pp_unpack", "hh_ladder", "ring_y", "ring_xz", "ring_p", "n5_terms",
-                                   "assemble", "energy",    "update"};
+                                   "assemble", "energy",    "update",  "plascc"};
 constexpr int kNumPhases = sizeof(kPhaseNames) / sizeof(kPhaseNames[0]);
 enum Phase { PH_DRESS, PH_AMP, PH_DF, PH_WZ, PH_PACK, PH_LADDER, PH_UNPACK, PH_HH, PH_RING_Y, PH_RING_XZ, PH_RING_P,
-             PH_N5, PH_ASSEMBLE, PH_ENERGY, PH_UPDATE };
+             PH_N5, PH_ASSEMBLE, PH_ENERGY, PH_UPDATE, PH_PLASCC };
 
 hipEvent_t take_event(ascc_ints* I) {
   if (!I->event_pool.empty()) {
@@ -581,6 +586,96 @@ size_t ints_footprint(long o, long v, long Q, int precision, int mode) {
   return align_up(off) + sizeof(double) * (size_t)std::max<long>(temp, 1);
 }
 
+// Partial linearisation (Sec. II.C): remove from the doubles residual every term with two powers
+// of the mixed doubles T2^M (amplitudes whose index set holds the hole h or the particle pa and is
+// not all primary; Sec. II.B, Eq. (eqn: pnm split)).  With T1 fixed the doubles residual is of
+// degree two in T2 and its quadratic part does not involve T1 (the (kc|ld) integrals are not
+// dressed), so the removal is that quadratic part evaluated at T2^M, subtracted from the four
+// intermediates that carry it before the assembly:
+//   hole-hole ladder  RL -= Z^M t^M,  Z^M_ij[k,l] = sum_cd t^M_ij^cd (kc|ld)
+//   rings             P1 += 1/2 Tx^M (Tx^M K)^T,  P2 -= 1/2 U^M (U^M L)^T
+//   E terms           EM += t^M A^M(b,c) + B^M(k,j) t^M through N^M_Q[k,a] = sum_lc B_Q,lc u^M_kl^ac.
+// Tx^M and U^M are ov x ov matrices that vanish outside the rows and columns of the primary set
+// Rp (m = o + v - 1 rows (i, a) with i = h or a = pa), so every ring product splits into slabs of
+// m rows or columns: N^5 work, never the dense o^3 v^3 one.  Runs after the rings and the E
+// terms, in buffers those have finished with (G2, chi, Y, Abc, Bkj).
+int plascc_remove(ascc_ints* I, const double* t2, double* RL, hipStream_t s) {
+  const int o = I->no, v = I->nv, Q = I->naux, h = I->pl_hole, pa = I->pl_pa;
+  const long ov = I->ov, oo = I->oo, vv = I->vv, ovov = I->ovov, m = (long)v + o - 1;
+  double* tM = I->G2;
+  double* ZM = I->chi;
+  HIPCHK(mixed_doubles(tM, t2, o, v, h, pa, s));
+  HIPCHK(mm(I, gemm_rm(oo, oo, vv, 1.0, tM, vv, false, I->Gwz + ov * vv, vv, true, 0.0, ZM, oo), s));
+  HIPCHK(mm(I, gemm_rm(oo, vv, oo, -1.0, ZM, oo, false, tM, vv, false, 1.0, RL, vv), s));
+  const double kappa[2] = {0.5, -0.5};
+  for (int z = 0; z < 2; ++z) {  // z = 0: Tx with K; z = 1: U with L (U's slabs stay for the E terms)
+    const double* T = I->TU + z * ovov;
+    const double* K = I->KL + z * ovov;
+    double* YM = I->Y + z * ovov;
+    double* P = I->P + z * ovov;
+    HIPCHK(rp_gather_rows(I->plA, T, ov, ov, ov, o, v, h, pa, true, s));   // T^M rows in Rp
+    HIPCHK(rp_gather_cols(I->plC, T, ov, ov, o, v, h, pa, true, s));       // T^M rows outside Rp (cols in Rp)
+    HIPCHK(rp_gather_rows(I->plK, K, ov, ov, ov, o, v, h, pa, false, s));
+    // Y^M = T^M K (K symmetric): C_p K_p everywhere (zero on Rp rows), then A_p K onto the Rp rows
+    HIPCHK(mm(I, gemm_rm(ov, ov, m, 1.0, I->plC, m, false, I->plK, ov, false, 0.0, YM, ov), s));
+    HIPCHK(mm(I, gemm_rm(m, ov, ov, 1.0, I->plA, ov, false, K, ov, true, 0.0, I->plW, ov), s));
+    HIPCHK(rp_scatter_add_rows(YM, ov, ov, I->plW, ov, 1.0, o, v, h, pa, s));
+    // P += kappa T^M Y^M^T, split the same way
+    HIPCHK(rp_gather_cols(I->plG, YM, ov, ov, o, v, h, pa, false, s));
+    HIPCHK(mm(I, gemm_rm(ov, ov, m, kappa[z], I->plC, m, false, I->plG, m, true, 1.0, P, ov), s));
+    HIPCHK(mm(I, gemm_rm(m, ov, ov, 1.0, I->plA, ov, false, YM, ov, true, 0.0, I->plW, ov), s));
+    HIPCHK(rp_scatter_add_rows(P, ov, ov, I->plW, ov, kappa[z], o, v, h, pa, s));
+  }
+  // N^M[Q][r] = sum_c B_Q,c U^M[r][c]: columns outside Rp from the Rp columns of B, Rp columns from A_p
+  HIPCHK(rp_gather_cols(I->plBp, I->Bov, ov, Q, o, v, h, pa, false, s));
+  HIPCHK(mm(I, gemm_rm(Q, ov, m, 1.0, I->plBp, m, false, I->plC, m, true, 0.0, I->plN, ov), s));
+  HIPCHK(mm(I, gemm_rm(Q, m, ov, 1.0, I->Bov, ov, false, I->plA, ov, true, 0.0, I->plNw, m), s));
+  HIPCHK(rp_scatter_add_cols(I->plN, ov, Q, I->plNw, 1.0, o, v, h, pa, s));
+  // A^M[b][c] = sum_Qk N^M_Q[k,b] B_Q,kc;  EM[ij][a][b] += sum_c t^M_ij^ac A^M[b][c]
+  HIPCHK(mm(I, gemm_rm(v, v, (long)Q * o, 1.0, I->plN, v, true, I->Bov, v, false, 0.0, I->Abc, v), s));
+  HIPCHK(mm(I, gemm_rm(oo * v, v, v, 1.0, tM, v, false, I->Abc, v, true, 1.0, I->EM, v), s));
+  {  // B^M[k][j] = sum_Qd B_Q,kd N^M_Q[j,d]
+    Gemm g;
+    g.M = o;
+    g.N = o;
+    g.K = v;
+    g.A = I->Bov;
+    g.sam = v;
+    g.sak = 1;
+    g.sar = ov;
+    g.B = I->plN;
+    g.sbk = 1;
+    g.sbn = v;
+    g.sbr = ov;
+    g.C = I->Bkj;
+    g.scm = o;
+    g.scn = 1;
+    g.nred = Q;
+    HIPCHK(mm(I, g, s));
+  }
+  {  // EM[i][j][ab] += sum_k B^M[k][j] t^M_ik^ab   (batched over i)
+    Gemm g;
+    g.M = o;
+    g.N = vv;
+    g.K = o;
+    g.A = I->Bkj;
+    g.sam = 1;
+    g.sak = o;
+    g.B = tM;
+    g.sbk = vv;
+    g.sbn = 1;
+    g.sb2 = (long)o * vv;
+    g.C = I->EM;
+    g.scm = vv;
+    g.scn = 1;
+    g.sc2 = (long)o * vv;
+    g.beta = 1.0;
+    g.nb2 = o;
+    HIPCHK(mm(I, g, s));
+  }
+  return ASCC_OK;
+}
+
 // One state's residual.  RLx == nullptr: the ladder is computed here into I->RL; otherwise RLx
 // already holds this state's particle-particle ladder (from a batched launch).
 int residual_core(ascc_ints* I, const double* t1, const double* t2, double* r1, double* r2, double* e,
@@ -825,6 +920,13 @@ int residual_core(ascc_ints* I, const double* t1, const double* t2, double* r1, 
     HIPCHK(mm(I, g, s));
   }
 
+  phase_end(I, s);
+  if (I->pl_hole >= 0) {
+    phase_begin(I, PH_PLASCC, s);
+    if ((rc = plascc_remove(I, t2, RL, s))) return rc;
+    phase_end(I, s);
+  }
+  phase_begin(I, PH_N5, s);
   // --- singles
   {  // r1[i][a] = sum_Qd N_Q[i,d] B^_Q,ad
     Gemm g;
@@ -1127,6 +1229,35 @@ int ascc_timing_read(ascc_ints* I, double* ms, int* counts, int n) {
   return rc;
 }
 
+int ascc_set_plascc(ascc_ints* I, int hole, int particle) {
+  if (!I) return fail(ASCC_E_ARG, "NULL handle");
+  if (hole < 0) {  // back to the full equations; the buffers stay for a later call
+    I->pl_hole = I->pl_pa = -1;
+    return ASCC_OK;
+  }
+  if (hole >= I->no || particle < I->no || particle >= I->n)
+    return fail(ASCC_E_ARG, "hole must be an occupied and particle a virtual orbital index");
+  if (!I->plA) {
+    const size_t ov = I->ov, m = (size_t)I->nv + I->no - 1, Q = I->naux;
+    int rc = dalloc(I->pl, &I->plA, m * ov);
+    if (!rc) rc = dalloc(I->pl, &I->plC, ov * m);
+    if (!rc) rc = dalloc(I->pl, &I->plK, m * ov);
+    if (!rc) rc = dalloc(I->pl, &I->plW, m * ov);
+    if (!rc) rc = dalloc(I->pl, &I->plG, ov * m);
+    if (!rc) rc = dalloc(I->pl, &I->plN, Q * ov);
+    if (!rc) rc = dalloc(I->pl, &I->plBp, Q * m);
+    if (!rc) rc = dalloc(I->pl, &I->plNw, Q * m);
+    if (rc) {
+      free_all(I->pl);
+      I->plA = I->plC = I->plK = I->plW = I->plG = I->plN = I->plBp = I->plNw = nullptr;
+      return rc;
+    }
+  }
+  I->pl_hole = hole;
+  I->pl_pa = particle - I->no;
+  return ASCC_OK;
+}
+
 int ascc_reference_energy(const ascc_ints* I, double* e0, void* stream) {
   if (!I || !e0) return fail(ASCC_E_ARG, "NULL argument to ascc_reference_energy");
   if (dry_run()) {
@@ -1253,6 +1384,7 @@ static int build_ints_impl(const double* d_B, const double* d_fock, int fock_is_
 void ascc_ints_free(ascc_ints* I) {
   if (!I) return;
   free_all(I->batch);
+  free_all(I->pl);
   free_all(I->pool);
   if (I->pool.base) unregister_buffer(I->pool.base);
   for (auto& m : I->marks) {

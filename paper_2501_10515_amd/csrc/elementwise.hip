@@ -797,6 +797,74 @@ hipError_t initial_guess(double* t1, double* t2, int no, int nv, int h, int a, d
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------------------
+// The primary set Rp of (i, a) row indices r = i*v + a of an ov x ov matrix, for a hole h and a
+// virtual index pa: Rp = {r : i == h or a == pa}, m = v + o - 1 rows, listed in the compact order
+// k < v -> (h, k); k = v + q -> (i, pa) with i = q (q < h) or q + 1 (q >= h).
+__device__ __forceinline__ long rp_row(long k, int o, int v, int h, int pa) {
+  if (k < v) return (long)h * v + k;
+  const long q = k - v;
+  return (q < h ? q : q + 1) * (long)v + pa;
+}
+__device__ __forceinline__ bool rp_member(long r, int v, int h, int pa) { return r / v == h || r % v == pa; }
+
+// dst[k][c] = src[rp_row(k) * lds + c] (k < m, c < ncols); with zero_hp, the entry at row and
+// column (h, pa) is written as 0.
+__global__ void rp_gather_rows_kernel(double* __restrict__ dst, const double* __restrict__ src, long lds, long ncols,
+                                      int o, int v, int h, int pa, int zero_hp) {
+  const long m = (long)v + o - 1, total = m * ncols;
+  const long hp = (long)h * v + pa;
+  for (long x = blockIdx.x * (long)blockDim.x + threadIdx.x; x < total; x += (long)gridDim.x * blockDim.x) {
+    const long k = x / ncols, c = x - k * ncols;
+    const long r = rp_row(k, o, v, h, pa);
+    dst[x] = (zero_hp && r == hp && c == hp) ? 0.0 : src[r * lds + c];
+  }
+}
+
+// dst[r][k] = src[r * lds + rp_row(k)] (r < nrows, k < m); with zero_rp, rows r in Rp are 0.
+__global__ void rp_gather_cols_kernel(double* __restrict__ dst, const double* __restrict__ src, long lds, long nrows,
+                                      int o, int v, int h, int pa, int zero_rp) {
+  const long m = (long)v + o - 1, total = nrows * m;
+  for (long x = blockIdx.x * (long)blockDim.x + threadIdx.x; x < total; x += (long)gridDim.x * blockDim.x) {
+    const long r = x / m, k = x - r * m;
+    dst[x] = (zero_rp && rp_member(r, v, h, pa)) ? 0.0 : src[r * lds + rp_row(k, o, v, h, pa)];
+  }
+}
+
+// dst[rp_row(k) * ldd + c] += alpha * src[k][c] (rows of Rp are distinct: no two threads share a target).
+__global__ void rp_scatter_add_rows_kernel(double* __restrict__ dst, long ldd, const double* __restrict__ src,
+                                           long ncols, double alpha, int o, int v, int h, int pa) {
+  const long m = (long)v + o - 1, total = m * ncols;
+  for (long x = blockIdx.x * (long)blockDim.x + threadIdx.x; x < total; x += (long)gridDim.x * blockDim.x) {
+    const long k = x / ncols, c = x - k * ncols;
+    dst[rp_row(k, o, v, h, pa) * ldd + c] += alpha * src[x];
+  }
+}
+
+// dst[r * ldd + rp_row(k)] += alpha * src[r][k] (r < nrows, k < m).
+__global__ void rp_scatter_add_cols_kernel(double* __restrict__ dst, long ldd, const double* __restrict__ src,
+                                           long nrows, double alpha, int o, int v, int h, int pa) {
+  const long m = (long)v + o - 1, total = nrows * m;
+  for (long x = blockIdx.x * (long)blockDim.x + threadIdx.x; x < total; x += (long)gridDim.x * blockDim.x) {
+    const long r = x / m, k = x - r * m;
+    dst[r * ldd + rp_row(k, o, v, h, pa)] += alpha * src[x];
+  }
+}
+
+// dst[i][j][a][b] = src[i][j][a][b] where the index set holds h (in i, j) or pa (in a, b) and is
+// not all primary (the mixed doubles), else 0.
+__global__ void mixed_doubles_kernel(double* __restrict__ dst, const double* __restrict__ src, int o, int v, int h,
+                                     int pa) {
+  const long vv = (long)v * v, total = (long)o * o * vv;
+  for (long x = blockIdx.x * (long)blockDim.x + threadIdx.x; x < total; x += (long)gridDim.x * blockDim.x) {
+    const long ij = x / vv, ab = x - ij * vv;
+    const int i = (int)(ij / o), j = (int)(ij % o), a = (int)(ab / v), b = (int)(ab % v);
+    const bool any = i == h || j == h || a == pa || b == pa;
+    const bool all = i == h && j == h && a == pa && b == pa;
+    dst[x] = (any && !all) ? src[x] : 0.0;
+  }
+}
+
 // e0 = sum_{i<o} (h[i * hs] + f[i * fs]): one workgroup, fixed-order tree sum (o <= 256 per thread pass).
 __global__ __launch_bounds__(kThreads) void reference_energy_kernel(double* e0, const double* h, long hs,
                                                                    const double* f, long fs, int o) {
@@ -821,6 +889,74 @@ hipError_t reference_energy(double* e0, const double* h, long hs, long hlen, con
     return hipErrorInvalidValue;
   if (dry_run()) return hipSuccess;
   hipLaunchKernelGGL(reference_energy_kernel, dim3(1), dim3(kThreads), 0, s, e0, h, hs, f, fs, o);
+  return hipGetLastError();
+}
+
+namespace {
+bool rp_args_ok(int o, int v, int h, int pa) { return o >= 1 && v >= 1 && h >= 0 && h < o && pa >= 0 && pa < v; }
+unsigned rp_grid(long total) { return (unsigned)std::max<long>(1, std::min<long>((total + 255) / 256, 8192)); }
+}  // namespace
+
+hipError_t rp_gather_rows(double* dst, const double* src, long lds, long src_rows, long ncols, int o, int v, int h,
+                          int pa, bool zero_hp, hipStream_t s) {
+  const long ov = (long)o * v, m = (long)v + o - 1;
+  if (!rp_args_ok(o, v, h, pa) || src_rows < ov || ncols > lds || ncols < 1) return hipErrorInvalidValue;
+  if (bounds_checking() && !(range_ok(dst, 0, m * ncols - 1, 8, "Rp gather rows dst") &&
+                             range_ok(src, 0, (src_rows - 1) * lds + ncols - 1, 8, "Rp gather rows src")))
+    return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  hipLaunchKernelGGL(rp_gather_rows_kernel, dim3(rp_grid(m * ncols)), dim3(256), 0, s, dst, src, lds, ncols, o, v, h,
+                     pa, zero_hp ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t rp_gather_cols(double* dst, const double* src, long lds, long nrows, int o, int v, int h, int pa,
+                          bool zero_rp, hipStream_t s) {
+  const long ov = (long)o * v, m = (long)v + o - 1;
+  if (!rp_args_ok(o, v, h, pa) || lds < ov || nrows < 1) return hipErrorInvalidValue;
+  if (bounds_checking() && !(range_ok(dst, 0, nrows * m - 1, 8, "Rp gather cols dst") &&
+                             range_ok(src, 0, (nrows - 1) * lds + ov - 1, 8, "Rp gather cols src")))
+    return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  hipLaunchKernelGGL(rp_gather_cols_kernel, dim3(rp_grid(nrows * m)), dim3(256), 0, s, dst, src, lds, nrows, o, v, h,
+                     pa, zero_rp ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t rp_scatter_add_rows(double* dst, long ldd, long dst_rows, const double* src, long ncols, double alpha, int o,
+                               int v, int h, int pa, hipStream_t s) {
+  const long ov = (long)o * v, m = (long)v + o - 1;
+  if (!rp_args_ok(o, v, h, pa) || dst_rows < ov || ncols > ldd || ncols < 1) return hipErrorInvalidValue;
+  if (bounds_checking() && !(range_ok(dst, 0, (dst_rows - 1) * ldd + ncols - 1, 8, "Rp scatter rows dst") &&
+                             range_ok(src, 0, m * ncols - 1, 8, "Rp scatter rows src")))
+    return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  hipLaunchKernelGGL(rp_scatter_add_rows_kernel, dim3(rp_grid(m * ncols)), dim3(256), 0, s, dst, ldd, src, ncols, alpha,
+                     o, v, h, pa);
+  return hipGetLastError();
+}
+
+hipError_t rp_scatter_add_cols(double* dst, long ldd, long nrows, const double* src, double alpha, int o, int v, int h,
+                               int pa, hipStream_t s) {
+  const long ov = (long)o * v, m = (long)v + o - 1;
+  if (!rp_args_ok(o, v, h, pa) || ldd < ov || nrows < 1) return hipErrorInvalidValue;
+  if (bounds_checking() && !(range_ok(dst, 0, (nrows - 1) * ldd + ov - 1, 8, "Rp scatter cols dst") &&
+                             range_ok(src, 0, nrows * m - 1, 8, "Rp scatter cols src")))
+    return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  hipLaunchKernelGGL(rp_scatter_add_cols_kernel, dim3(rp_grid(nrows * m)), dim3(256), 0, s, dst, ldd, src, nrows,
+                     alpha, o, v, h, pa);
+  return hipGetLastError();
+}
+
+hipError_t mixed_doubles(double* dst, const double* src, int o, int v, int h, int pa, hipStream_t s) {
+  const long total = (long)o * o * v * v;
+  if (!rp_args_ok(o, v, h, pa)) return hipErrorInvalidValue;
+  if (bounds_checking() && !(range_ok(dst, 0, total - 1, 8, "mixed doubles dst") &&
+                             range_ok(src, 0, total - 1, 8, "mixed doubles src")))
+    return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  hipLaunchKernelGGL(mixed_doubles_kernel, dim3(rp_grid(total)), dim3(256), 0, s, dst, src, o, v, h, pa);
   return hipGetLastError();
 }
 

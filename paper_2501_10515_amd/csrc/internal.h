@@ -170,6 +170,22 @@ hipError_t dress_apply(double* D, const double* S, const double* Tc, const doubl
 
 // x -> (1 + c E_hp) x (1 - c E_hp) in place on nb stacked n x n matrices (E_hp: one at row h, column p).
 hipError_t onebody_transform(double* X, long nb, int n, int h, int p, double c, hipStream_t s);
+// The primary rows Rp = {r = i*v + a : i == h or a == pa} of an ov x ov matrix (m = v + o - 1 of
+// them, compact order: (h, 0..v-1), then (i, pa) for i != h ascending).
+//   rp_gather_rows:  dst[m][ncols]  = rows Rp of src (leading dimension lds, src_rows >= ov rows);
+//                    zero_hp writes the entry at row and column (h, pa) as 0.
+//   rp_gather_cols:  dst[nrows][m]  = columns Rp of src; zero_rp writes rows r in Rp as 0.
+//   rp_scatter_add_rows / _cols: the inverse placements, dst += alpha * src.
+// mixed_doubles: dst = src on the mixed doubles (index set holds h or pa, not all primary), else 0.
+hipError_t rp_gather_rows(double* dst, const double* src, long lds, long src_rows, long ncols, int o, int v, int h,
+                          int pa, bool zero_hp, hipStream_t s);
+hipError_t rp_gather_cols(double* dst, const double* src, long lds, long nrows, int o, int v, int h, int pa,
+                          bool zero_rp, hipStream_t s);
+hipError_t rp_scatter_add_rows(double* dst, long ldd, long dst_rows, const double* src, long ncols, double alpha, int o,
+                               int v, int h, int pa, hipStream_t s);
+hipError_t rp_scatter_add_cols(double* dst, long ldd, long nrows, const double* src, double alpha, int o, int v, int h,
+                               int pa, hipStream_t s);
+hipError_t mixed_doubles(double* dst, const double* src, int o, int v, int h, int pa, hipStream_t s);
 // e0[0] = sum_{i<o} (h[i * hs] + f[i * fs]) (hlen, flen: elements of h and f, for the bounds check).
 hipError_t reference_energy(double* e0, const double* h, long hs, long hlen, const double* f, long fs, long flen,
                             int o, hipStream_t s);

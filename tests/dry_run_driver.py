@@ -49,6 +49,7 @@ def main(shapes):
     L.ascc_build_ints_hbar.argtypes = [vp, vp] + [ctypes.c_int] * 8 + [vp, ctypes.POINTER(vp)]
     L.ascc_initial_guess.argtypes = [vp, vp] + [ctypes.c_int] * 4 + [ctypes.c_double] * 2 + [vp]
     L.ascc_reference_energy.argtypes = [vp, ctypes.POINTER(ctypes.c_double), vp]
+    L.ascc_set_plascc.argtypes = [vp, ctypes.c_int, ctypes.c_int]
     ok = True
     for shape in shapes:
         o, v, Q, diag = shape[:4]
@@ -100,6 +101,14 @@ def main(shapes):
                 t1, t2, r1, r2, e = (fake(8 * o * v), fake(8 * o * o * v * v), fake(8 * o * v),
                                      fake(8 * o * o * v * v), fake(8))
                 rc = L.ascc_initial_guess(t1, t2, o, v, o - 1, o, ctypes.c_double(1.0), ctypes.c_double(-0.5), None)
+                if rc == 0:
+                    rc = L.ascc_residual(h4, t1, t2, r1, r2, e, None)
+                if rc == 0:  # and with the partial linearisation of the same primaries
+                    rc = L.ascc_set_plascc(h4, o - 1, o)
+                if rc == 0:
+                    rc = L.ascc_residual(h4, t1, t2, r1, r2, e, None)
+                if rc == 0:
+                    rc = L.ascc_set_plascc(h4, 0, o + v - 1)
                 if rc == 0:
                     rc = L.ascc_residual(h4, t1, t2, r1, r2, e, None)
                 if rc == 0:
