@@ -2,7 +2,8 @@
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--vvvv full|packed]
                 [--precision fp64|fp32|bf16x3] [--generator literal|converging] [--no-compare]
-                [--no-cpu-baseline] [--serve ...] [--solve [--ascc H,P|homo-lumo] [--solve-tol T] [--lowp-rnorm R]]
+                [--no-cpu-baseline] [--serve ...] [--solve [--ascc H,P|homo-lumo] [--plascc] [--solve-tol T]
+                [--lowp-rnorm R]]
 
 A step is one pass of the whole iteration on the device: T1 dressing, every residual term,
 the energy and residual-norm reductions, the Jacobi update and DIIS (ascc_residual followed
@@ -22,7 +23,8 @@ traffic = HBM bytes per launch from rocprofv3 counters (table below), null where
 
 variants (FP64 runs): the same workload and step with the other vvvv storage and with the N^6
 contractions in FP32 and in split-BF16x3 (fewer steps each), as TFLOP/s on the same F_N6 count
-and speedup over the main run.
+and speedup over the main run; and the same step with the PLASCC term removal (primaries
+HOMO -> LUMO) in FP64 and split-BF16x3, with the time of the removal itself.
 
 cpu_baseline: the FP64 oracle (oracle/cs_ccsd.py, numpy) timed on the host for one residual
 evaluation of the same workload (rank 0 only), as F_N6 / seconds.
@@ -121,12 +123,13 @@ def cpu_baseline(B, eps, o, v, nstates=1):
                        + (f"; one of its {nstates} states" if nstates > 1 else ""))}
 
 
-def run_throughput(P, torch, B, eps, o, v, Q, vvvv, precision, steps, warmup, guesses=None):
+def run_throughput(P, torch, B, eps, o, v, Q, vvvv, precision, steps, warmup, guesses=None, plascc=None):
     """Time `steps` iterations (residual + update) after `warmup` untimed ones.
 
     guesses None: one state from T = 0.  Otherwise one state per (i, a) pair, T2 = 0 and
     t1[i, a] = 0.5, all sharing the integral set: one ascc_residual_batch call (one ladder
     launch over every state) and one ascc_update per state, each with its own DIIS history.
+    plascc (hole, particle): the same iteration with the PLASCC term removal of those primaries.
     """
     dev = torch.device("cuda:0")
     mode = P.ASCC_VVVV_FULL if vvvv == "full" else P.ASCC_VVVV_PACKED
@@ -139,6 +142,8 @@ def run_throughput(P, torch, B, eps, o, v, Q, vvvv, precision, steps, warmup, gu
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
     del dB
+    if plascc is not None:
+        P.ascc_set_plascc(ints, *plascc)
     nst = 1 if guesses is None else len(guesses)
     t1s = [torch.zeros((o, v), dtype=torch.float64, device=dev) for _ in range(nst)]
     t2s = [torch.zeros((o, o, v, v), dtype=torch.float64, device=dev) for _ in range(nst)]
@@ -280,6 +285,8 @@ def serve_main(args):
     if state is not None:  # the ground state of the same system, FP64: the excitation energy
         dB, deps = torch.from_numpy(B).to(dev), torch.from_numpy(eps).to(dev)
         ints = P.ascc_build_ints(dB, deps, o, vvvv_mode=mode)
+        if prim is not None:  # the same removal in the ground state (Sec. II.C)
+            P.ascc_set_plascc(ints, *prim)
         del dB
         t1 = torch.zeros((o, v), dtype=torch.float64, device=dev)
         t2 = torch.zeros((o, o, v, v), dtype=torch.float64, device=dev)
@@ -318,10 +325,18 @@ def solve_main(args):
         hole, particle = (int(x) for x in args.ascc.split(",")) if args.ascc != "homo-lumo" else (o - 1, o)
         state = (hole, particle)
 
+    prim = None  # primaries of the PLASCC term removal
+    if args.plascc:
+        prim = state if state is not None else (o - 1, o)
+
     def build(dB, deps, pc, mode):
         if state is None:
-            return P.ascc_build_ints(dB, deps, o, precision=pc, vvvv_mode=mode)
-        return P.ascc_build_ints_hbar(dB, deps, o, state[0], state[1], precision=pc, vvvv_mode=mode)
+            ints = P.ascc_build_ints(dB, deps, o, precision=pc, vvvv_mode=mode)
+        else:
+            ints = P.ascc_build_ints_hbar(dB, deps, o, state[0], state[1], precision=pc, vvvv_mode=mode)
+        if prim is not None:
+            P.ascc_set_plascc(ints, *prim)
+        return ints
 
     def start(t1, t2):  # T = 0, or the ASCC guess T^P(0) = S - S^2/2
         if state is None:
@@ -373,6 +388,8 @@ def solve_main(args):
     if state is not None:  # the ground state of the same system, FP64: the excitation energy
         dB, deps = torch.from_numpy(B).to(dev), torch.from_numpy(eps).to(dev)
         ints = P.ascc_build_ints(dB, deps, o, vvvv_mode=mode)
+        if prim is not None:  # the same removal in the ground state (Sec. II.C)
+            P.ascc_set_plascc(ints, *prim)
         del dB
         t1 = torch.zeros((o, v), dtype=torch.float64, device=dev)
         t2 = torch.zeros((o, o, v, v), dtype=torch.float64, device=dev)
@@ -386,13 +403,16 @@ def solve_main(args):
             rr["excitation_energy_eV"] = round((rr["e_total"] - ground["e_total"]) * 27.211386, 6)
     main = res.get("bf16x3_refined") or next(iter(res.values()))
     what = "ground state" if state is None else f"ASCC 1-CSF state {state[0]}->{state[1]} (transformed Hamiltonian)"
+    if prim is not None:
+        what = f"PLASCC ({prim[0]}->{prim[1]} primaries), " + what
     out = {"metric": f"time to converged energy, mixed vs FP64 (|dE| < 1e-6 Eh), {what}", "unit": "s",
            "value": main["solve_s"], "higher_is_better": False, "n_gpus": 1, "vs_baseline": None, "dtype": "f64",
            "data": "synthetic",
            "config": {"workload": args.workload, "no": o, "nv": v, "naux": Q, "seed": seed, "generator": "converging",
                       "sigma": sigma, "vvvv": args.vvvv, "tol_rnorm": tol, "lowp_rnorm": args.lowp_rnorm,
                       "state": "ground" if state is None else {"hole": state[0], "particle": state[1],
-                                                                "guess": "T^P(0) = S - S^2/2"}},
+                                                                "guess": "T^P(0) = S - S^2/2"},
+                      "plascc_primaries": list(prim) if prim is not None else None},
            "modes": res}
     if ground is not None:
         out["ground_state_fp64"] = ground
@@ -420,6 +440,8 @@ def main():
     ap.add_argument("--solve", action="store_true", help="precision study: full solves of --workload per mode")
     ap.add_argument("--ascc", default="", help="with --solve: an ASCC 1-CSF state, 'hole,particle' (orbital "
                     "indices) or 'homo-lumo', solved on its transformed Hamiltonian from T^P(0)")
+    ap.add_argument("--plascc", action="store_true", help="with --solve: the PLASCC term removal, primaries of "
+                    "--ascc (or HOMO -> LUMO for the ground state), in every solve")
     ap.add_argument("--solve-tol", type=float, default=1e-7)
     ap.add_argument("--solve-maxiter", type=int, default=60)
     ap.add_argument("--lowp-rnorm", type=float, default=1e-7,
@@ -495,13 +517,14 @@ def main():
     if not args.no_compare and args.precision == "fp64":
         comp = {}
         other = "packed" if args.vvvv == "full" else "full"
-        for vm, pr in ((other, "fp64"), (args.vvvv, "fp32"), (args.vvvv, "bf16x3"), ("packed", "bf16x3")):
-            key = f"{pr}_{vm}"
-            if key in comp:
+        for vm, pr, pl in ((other, "fp64", None), (args.vvvv, "fp32", None), (args.vvvv, "bf16x3", None),
+                           ("packed", "bf16x3", None), (args.vvvv, "fp64", (o - 1, o)), (args.vvvv, "bf16x3", (o - 1, o))):
+            key = f"{pr}_{vm}" + ("_plascc" if pl else "")
+            if key in comp or (pl and nstates > 1):
                 continue
             try:
                 r = run_throughput(P, torch, B, eps, o, v, Q, vm, pr, max(3, args.steps // 3), min(2, args.warmup),
-                                   guesses)
+                                   guesses, plascc=pl)
                 rl, rn = r["phases"]["pp_ladder"]
                 lms = rl / max(rn, 1)
                 lach = nstates * ladder_flops(o, v) / (lms * 1e-3) / 1e12
@@ -512,6 +535,10 @@ def main():
                              # the ladder against the peak of the arithmetic that carries it
                              "pp_ladder_tflops": round(lach, 3),
                              "pp_ladder_frac": round(lach / PEAKS[pr], 4)}
+                if pl:  # the PLASCC removal (primaries HOMO -> LUMO) and its own phase
+                    pms, pn = r["phases"].get("plascc", (0.0, 0))
+                    comp[key]["plascc_primaries"] = list(pl)
+                    comp[key]["plascc_phase_ms"] = round(pms / max(r["steps"], 1), 4)
             except Exception as exc:  # keep the primary measurement if a comparison fails
                 comp[key] = {"error": str(exc)[:200]}
         out["variants"] = comp

@@ -640,8 +640,9 @@ hipError_t gemm_f64(const Gemm& g, hipStream_t s) {
     if (e256 < e128) return launch_cfg<256, 128, 16, 4, 2, 1>(p, amf, bnf, g.nb1, nullptr, 0, s);
     return launch_cfg<128, 128, 16, 2, 2, 2>(p, amf, bnf, g.nb1, g.ws, g.ws_elems, s);
   }
-  // a long K lets split-K make up for too few 128 x 128 tiles
-  const bool long_k = g.ws && (long)g.K * g.nred >= 2048 && tiles128 >= 64;
+  // a long K lets split-K make up for too few 128 x 128 tiles (down to 16 of them: split into up
+  // to 32 slices, a long K still leaves each slice enough iterations to hide its reduction)
+  const bool long_k = g.ws && (long)g.K * g.nred >= 2048 && tiles128 >= 16;
   if (g.M >= 96 && g.N >= 96 && long_k) {
     if (dma_eligible(p)) return launch_dma_auto(p, g.nb1, g.ws, g.ws_elems, s);
     return launch_cfg<128, 128, 16, 2, 2, 2>(p, amf, bnf, g.nb1, g.ws, g.ws_elems, s);
