@@ -200,8 +200,9 @@ struct ascc_ints {
   Pool batch;
   // partial linearisation (ascc_set_plascc): primaries and the slab buffers of the removal
   int pl_hole = -1, pl_pa = -1;
-  double *plA = nullptr, *plC = nullptr, *plK = nullptr, *plW = nullptr, *plG = nullptr;  // [m][ov] / [ov][m]
-  double *plN = nullptr, *plBp = nullptr, *plNw = nullptr;                              // [Q][ov], [Q][m] x 2
+  double *plA, *plC, *plKr, *plKpp, *plYp, *plYpp, *plS, *plZ, *plZt, *plW;  // ov-cross slabs (rings)
+  double *plN, *plBp, *plNw;                                                 // N^M and its slabs
+  double *plTa, *plTc, *plGc, *plZo, *plZh, *plRc, *plEc;                    // oo / vv-cross slabs
   Pool pl;
   // optional per-phase timing with HIP events (ascc_timing_enable)
   bool timing = false;
@@ -278,6 +279,7 @@ uintptr_t fake_alloc(size_t bytes) {
 inline int* pair_minus(const ascc_ints* I) { return reinterpret_cast<int*>(I->pairtab); }
 
 constexpr long kSplitKElems = 1L << 23;  // 64 MiB of split-K partials
+inline long pad_even(long x) { return x + (x & 1); }  // compact slab widths, even for the direct-to-LDS path
 
 // Every device array of an integral set with its element count, in allocation order; the
 // same list gives ascc_workspace_bytes its exact answer.
@@ -587,53 +589,84 @@ size_t ints_footprint(long o, long v, long Q, int precision, int mode) {
 }
 
 // Partial linearisation (Sec. II.C): remove from the doubles residual every term with two powers
-// of the mixed doubles T2^M (amplitudes whose index set holds the hole h or the particle pa and is
+// of the mixed doubles t^M (amplitudes whose index set holds the hole h or the particle pa and is
 // not all primary; Sec. II.B, Eq. (eqn: pnm split)).  With T1 fixed the doubles residual is of
 // degree two in T2 and its quadratic part does not involve T1 (the (kc|ld) integrals are not
-// dressed), so the removal is that quadratic part evaluated at T2^M, subtracted from the four
+// dressed), so the removal is that quadratic part evaluated at t^M, taken out of the four
 // intermediates that carry it before the assembly:
 //   hole-hole ladder  RL -= Z^M t^M,  Z^M_ij[k,l] = sum_cd t^M_ij^cd (kc|ld)
-//   rings             P1 += 1/2 Tx^M (Tx^M K)^T,  P2 -= 1/2 U^M (U^M L)^T
+//   rings             P1 += 1/2 Tx^M K Tx^M^T,  P2 -= 1/2 U^M L U^M^T   (K, L symmetric)
 //   E terms           EM += t^M A^M(b,c) + B^M(k,j) t^M through N^M_Q[k,a] = sum_lc B_Q,lc u^M_kl^ac.
-// Tx^M and U^M are ov x ov matrices that vanish outside the rows and columns of the primary set
-// Rp (m = o + v - 1 rows (i, a) with i = h or a = pa), so every ring product splits into slabs of
-// m rows or columns: N^5 work, never the dense o^3 v^3 one.  Runs after the rings and the E
-// terms, in buffers those have finished with (G2, chi, Y, Abc, Bkj).
+// The mixed amplitudes live on crosses (see Cross): as ov x ov matrices Tx^M and U^M vanish off
+// the rows and columns of the (i, a) cross X (i = h or a = pa, m = o + v - 1); as oo x vv
+// matrices, t^M rows ij of the occupied cross are full and the other rows hold only the virtual
+// cross ab.  Every product is split along those crosses into slabs: N^5 work.  The ring term is a
+// symmetric matrix; its (X, X) and (X, not X) blocks come from the X rows of Y = T K that the ring
+// stage has just formed, the (not X, not X) block is C_p K_pp C_p^T with C_p the X columns of the
+// rows outside X.  Runs after the rings and E terms, in G2, chi, Abc and Bkj, which those are
+// done with, and in the compact buffers of ascc_set_plascc.
 int plascc_remove(ascc_ints* I, const double* t2, double* RL, hipStream_t s) {
   const int o = I->no, v = I->nv, Q = I->naux, h = I->pl_hole, pa = I->pl_pa;
-  const long ov = I->ov, oo = I->oo, vv = I->vv, ovov = I->ovov, m = (long)v + o - 1;
+  const long ov = I->ov, oo = I->oo, vv = I->vv, ovov = I->ovov;
+  const Cross X{o, v, h, pa}, Xo{o, o, h, h}, Xv{v, v, pa, pa};
+  const long m = X.m(), mp = pad_even(m), mo = Xo.m(), mop = pad_even(mo), mvp = pad_even(Xv.m());
   double* tM = I->G2;
-  double* ZM = I->chi;
   HIPCHK(mixed_doubles(tM, t2, o, v, h, pa, s));
-  HIPCHK(mm(I, gemm_rm(oo, oo, vv, 1.0, tM, vv, false, I->Gwz + ov * vv, vv, true, 0.0, ZM, oo), s));
-  HIPCHK(mm(I, gemm_rm(oo, vv, oo, -1.0, ZM, oo, false, tM, vv, false, 1.0, RL, vv), s));
+  // --- hole-hole ladder.  tA: the occupied-cross rows of t^M; tC: the virtual-cross columns of the
+  // other rows
+  const double* G = I->Gwz + ov * vv;  // (kc|ld) at [k*o + l][c*v + d]
+  double* ZM = I->chi;
+  HIPCHK(cross_gather_rows(I->plTa, vv, tM, vv, oo, vv, Xo, false, s));
+  HIPCHK(cross_gather_cols(I->plTc, mvp, tM, vv, oo, Xv, &Xo, s));
+  HIPCHK(cross_gather_cols(I->plGc, mvp, G, vv, oo, Xv, nullptr, s));
+  HIPCHK(mm(I, gemm_rm(oo, oo, mvp, 1.0, I->plTc, mvp, false, I->plGc, mvp, true, 0.0, ZM, oo), s));
+  HIPCHK(mm(I, gemm_rm(mo, oo, vv, 1.0, I->plTa, vv, false, G, vv, true, 0.0, I->plZo, oo), s));
+  HIPCHK(cross_scatter_add_rows(ZM, oo, oo, I->plZo, oo, oo, 1.0, Xo, s));
+  HIPCHK(cross_gather_cols(I->plZh, mop, ZM, oo, oo, Xo, nullptr, s));
+  HIPCHK(mm(I, gemm_rm(oo, vv, mo, -1.0, I->plZh, mop, false, I->plTa, vv, false, 1.0, RL, vv), s));
+  HIPCHK(mm(I, gemm_rm(oo, mvp, oo, 1.0, ZM, oo, false, I->plTc, mvp, false, 0.0, I->plRc, mvp), s));
+  HIPCHK(cross_scatter_add_cols(RL, vv, oo, I->plRc, mvp, -1.0, Xv, s));
+  // --- rings, z = 0: Tx with K into P1 (+1/2); z = 1: U with L into P2 (-1/2).  U's slabs stay in
+  // plA / plC for the E terms.
   const double kappa[2] = {0.5, -0.5};
-  for (int z = 0; z < 2; ++z) {  // z = 0: Tx with K; z = 1: U with L (U's slabs stay for the E terms)
+  for (int z = 0; z < 2; ++z) {
     const double* T = I->TU + z * ovov;
     const double* K = I->KL + z * ovov;
-    double* YM = I->Y + z * ovov;
+    const double* Y = I->Y + z * ovov;  // T K from the ring stage
     double* P = I->P + z * ovov;
-    HIPCHK(rp_gather_rows(I->plA, T, ov, ov, ov, o, v, h, pa, true, s));   // T^M rows in Rp
-    HIPCHK(rp_gather_cols(I->plC, T, ov, ov, o, v, h, pa, true, s));       // T^M rows outside Rp (cols in Rp)
-    HIPCHK(rp_gather_rows(I->plK, K, ov, ov, ov, o, v, h, pa, false, s));
-    // Y^M = T^M K (K symmetric): C_p K_p everywhere (zero on Rp rows), then A_p K onto the Rp rows
-    HIPCHK(mm(I, gemm_rm(ov, ov, m, 1.0, I->plC, m, false, I->plK, ov, false, 0.0, YM, ov), s));
-    HIPCHK(mm(I, gemm_rm(m, ov, ov, 1.0, I->plA, ov, false, K, ov, true, 0.0, I->plW, ov), s));
-    HIPCHK(rp_scatter_add_rows(YM, ov, ov, I->plW, ov, 1.0, o, v, h, pa, s));
-    // P += kappa T^M Y^M^T, split the same way
-    HIPCHK(rp_gather_cols(I->plG, YM, ov, ov, o, v, h, pa, false, s));
-    HIPCHK(mm(I, gemm_rm(ov, ov, m, kappa[z], I->plC, m, false, I->plG, m, true, 1.0, P, ov), s));
-    HIPCHK(mm(I, gemm_rm(m, ov, ov, 1.0, I->plA, ov, false, YM, ov, true, 0.0, I->plW, ov), s));
-    HIPCHK(rp_scatter_add_rows(P, ov, ov, I->plW, ov, kappa[z], o, v, h, pa, s));
+    HIPCHK(cross_gather_rows(I->plA, ov, T, ov, ov, ov, X, true, s));  // X rows of T^M
+    HIPCHK(cross_gather_cols(I->plC, mp, T, ov, ov, X, &X, s));         // C_p
+    HIPCHK(cross_gather_rows(I->plKr, ov, K, ov, ov, ov, X, false, s));
+    HIPCHK(cross_gather_cols(I->plKpp, mp, I->plKr, ov, m, X, nullptr, s));  // K_pp
+    HIPCHK(cross_rows_without_corner(I->plYp, ov, Y, T, K, X, s));          // X rows of T^M K
+    HIPCHK(cross_gather_cols(I->plYpp, mp, I->plYp, ov, m, X, nullptr, s));
+    // (X, X) block
+    HIPCHK(mm(I, gemm_rm(m, m, ov, 1.0, I->plYp, ov, false, I->plA, ov, true, 0.0, I->plS, mp), s));
+    HIPCHK(cross_scatter_add_block(P, ov, I->plS, mp, kappa[z], X, s));
+    // (X, not X) and, by symmetry, (not X, X)
+    HIPCHK(mm(I, gemm_rm(m, ov, mp, 1.0, I->plYpp, mp, false, I->plC, mp, true, 0.0, I->plZ, ov), s));
+    HIPCHK(cross_scatter_add_rows(P, ov, ov, I->plZ, ov, ov, kappa[z], X, s));
+    HIPCHK(mm(I, gemm_rm(ov, m, mp, 1.0, I->plC, mp, false, I->plYpp, mp, true, 0.0, I->plZt, mp), s));
+    HIPCHK(cross_scatter_add_cols(P, ov, ov, I->plZt, mp, kappa[z], X, s));
+    // (not X, not X) = C_p K_pp C_p^T
+    HIPCHK(mm(I, gemm_rm(ov, m, m, 1.0, I->plC, mp, false, I->plKpp, mp, false, 0.0, I->plW, mp), s));
+    HIPCHK(mm(I, gemm_rm(ov, ov, mp, kappa[z], I->plW, mp, false, I->plC, mp, true, 1.0, P, ov), s));
   }
-  // N^M[Q][r] = sum_c B_Q,c U^M[r][c]: columns outside Rp from the Rp columns of B, Rp columns from A_p
-  HIPCHK(rp_gather_cols(I->plBp, I->Bov, ov, Q, o, v, h, pa, false, s));
-  HIPCHK(mm(I, gemm_rm(Q, ov, m, 1.0, I->plBp, m, false, I->plC, m, true, 0.0, I->plN, ov), s));
-  HIPCHK(mm(I, gemm_rm(Q, m, ov, 1.0, I->Bov, ov, false, I->plA, ov, true, 0.0, I->plNw, m), s));
-  HIPCHK(rp_scatter_add_cols(I->plN, ov, Q, I->plNw, 1.0, o, v, h, pa, s));
+  // --- E terms.  N^M[Q][r] = sum_c B_Q,c U^M[r][c]: columns outside X from C_p, X columns from the
+  // X rows of U^M
+  HIPCHK(cross_gather_cols(I->plBp, mp, I->Bov, ov, Q, X, nullptr, s));
+  HIPCHK(mm(I, gemm_rm(Q, ov, mp, 1.0, I->plBp, mp, false, I->plC, mp, true, 0.0, I->plN, ov), s));
+  HIPCHK(mm(I, gemm_rm(Q, m, ov, 1.0, I->Bov, ov, false, I->plA, ov, true, 0.0, I->plNw, mp), s));
+  HIPCHK(cross_scatter_add_cols(I->plN, ov, Q, I->plNw, mp, 1.0, X, s));
   // A^M[b][c] = sum_Qk N^M_Q[k,b] B_Q,kc;  EM[ij][a][b] += sum_c t^M_ij^ac A^M[b][c]
   HIPCHK(mm(I, gemm_rm(v, v, (long)Q * o, 1.0, I->plN, v, true, I->Bov, v, false, 0.0, I->Abc, v), s));
-  HIPCHK(mm(I, gemm_rm(oo * v, v, v, 1.0, tM, v, false, I->Abc, v, true, 1.0, I->EM, v), s));
+  HIPCHK(mm(I, gemm_rm(mo * v, v, v, 1.0, I->plTa, v, false, I->Abc, v, true, 0.0, I->plEc, v), s));
+  HIPCHK(cross_scatter_add_rows(I->EM, vv, oo, I->plEc, vv, vv, 1.0, Xo, s));
+  {  // rows outside the occupied cross, a = pa: EM[ij][pa][b] += sum_c t^M_ij^{pa c} A^M[b][c]
+    Gemm g = gemm_rm(oo, v, v, 1.0, I->plTc, mvp, false, I->Abc, v, true, 1.0, I->EM + (long)pa * v, vv);
+    HIPCHK(mm(I, g, s));
+  }
+  HIPCHK(em_cross_column(I->EM, I->plTc, mvp, I->Abc, o, v, pa, s));  // ... and a != pa, c = pa
   {  // B^M[k][j] = sum_Qd B_Q,kd N^M_Q[j,d]
     Gemm g;
     g.M = o;
@@ -1237,19 +1270,29 @@ int ascc_set_plascc(ascc_ints* I, int hole, int particle) {
   }
   if (hole >= I->no || particle < I->no || particle >= I->n)
     return fail(ASCC_E_ARG, "hole must be an occupied and particle a virtual orbital index");
-  if (!I->plA) {
-    const size_t ov = I->ov, m = (size_t)I->nv + I->no - 1, Q = I->naux;
-    int rc = dalloc(I->pl, &I->plA, m * ov);
-    if (!rc) rc = dalloc(I->pl, &I->plC, ov * m);
-    if (!rc) rc = dalloc(I->pl, &I->plK, m * ov);
-    if (!rc) rc = dalloc(I->pl, &I->plW, m * ov);
-    if (!rc) rc = dalloc(I->pl, &I->plG, ov * m);
-    if (!rc) rc = dalloc(I->pl, &I->plN, Q * ov);
-    if (!rc) rc = dalloc(I->pl, &I->plBp, Q * m);
-    if (!rc) rc = dalloc(I->pl, &I->plNw, Q * m);
+  if (!I->pl.total) {
+    const long ov = I->ov, oo = I->oo, vv = I->vv, Q = I->naux;
+    const long m = (long)I->no + I->nv - 1, mp = pad_even(m);
+    const long mo = 2L * I->no - 1, mop = pad_even(mo), mvp = pad_even(2L * I->nv - 1);
+    const std::pair<double* ascc_ints::*, long> plan[] = {
+        {&ascc_ints::plA, m * ov},   {&ascc_ints::plC, ov * mp},   {&ascc_ints::plKr, m * ov},
+        {&ascc_ints::plKpp, m * mp}, {&ascc_ints::plYp, m * ov},   {&ascc_ints::plYpp, m * mp},
+        {&ascc_ints::plS, m * mp},   {&ascc_ints::plZ, m * ov},    {&ascc_ints::plZt, ov * mp},
+        {&ascc_ints::plW, ov * mp},  {&ascc_ints::plN, Q * ov},    {&ascc_ints::plBp, Q * mp},
+        {&ascc_ints::plNw, Q * mp},  {&ascc_ints::plTa, mo * vv},  {&ascc_ints::plTc, oo * mvp},
+        {&ascc_ints::plGc, oo * mvp}, {&ascc_ints::plZo, mo * oo}, {&ascc_ints::plZh, oo * mop},
+        {&ascc_ints::plRc, oo * mvp}, {&ascc_ints::plEc, mo * vv},
+    };
+    int rc = ASCC_OK;
+    for (const auto& item : plan)
+      if (!rc) rc = dalloc(I->pl, &(I->*(item.first)), (size_t)item.second);
+    // padding columns that products read but never write (plW) must hold zeros: clear them all
+    for (const auto& item : plan)
+      if (!rc && !dry_run() && hipMemset(I->*(item.first), 0, sizeof(double) * item.second) != hipSuccess)
+        rc = fail(ASCC_E_HIP, "clearing the PLASCC buffers failed");
     if (rc) {
       free_all(I->pl);
-      I->plA = I->plC = I->plK = I->plW = I->plG = I->plN = I->plBp = I->plNw = nullptr;
+      I->pl = Pool();
       return rc;
     }
   }

@@ -798,56 +798,94 @@ hipError_t initial_guess(double* t1, double* t2, int no, int nv, int h, int a, d
 }
 
 // ---------------------------------------------------------------------------------------
-// The primary set Rp of (i, a) row indices r = i*v + a of an ov x ov matrix, for a hole h and a
-// virtual index pa: Rp = {r : i == h or a == pa}, m = v + o - 1 rows, listed in the compact order
-// k < v -> (h, k); k = v + q -> (i, pa) with i = q (q < h) or q + 1 (q >= h).
-__device__ __forceinline__ long rp_row(long k, int o, int v, int h, int pa) {
-  if (k < v) return (long)h * v + k;
-  const long q = k - v;
-  return (q < h ? q : q + 1) * (long)v + pa;
+// Cross index sets (internal.h): over r = i * nv + a (i < no, a < nv) the members i == h or
+// a == pa, m = nv + no - 1 of them in the compact order k < nv -> (h, k), k = nv + q -> (i, pa)
+// with i = q (q < h) or q + 1 (q >= h).
+__device__ __forceinline__ long cross_row(const Cross& X, long k) {
+  if (k < X.nv) return (long)X.h * X.nv + k;
+  const long q = k - X.nv;
+  return (q < X.h ? q : q + 1) * (long)X.nv + X.pa;
 }
-__device__ __forceinline__ bool rp_member(long r, int v, int h, int pa) { return r / v == h || r % v == pa; }
+__device__ __forceinline__ bool cross_member(const Cross& X, long r) { return r / X.nv == X.h || r % X.nv == X.pa; }
 
-// dst[k][c] = src[rp_row(k) * lds + c] (k < m, c < ncols); with zero_hp, the entry at row and
-// column (h, pa) is written as 0.
-__global__ void rp_gather_rows_kernel(double* __restrict__ dst, const double* __restrict__ src, long lds, long ncols,
-                                      int o, int v, int h, int pa, int zero_hp) {
-  const long m = (long)v + o - 1, total = m * ncols;
-  const long hp = (long)h * v + pa;
+// dst[k][c] = src[cross_row(k)][c] (c < ncols); with zero_diag, the entry whose row and column
+// are both the cross's corner r = h * nv + pa is written as 0.
+__global__ void cross_gather_rows_kernel(double* __restrict__ dst, long ldd, const double* __restrict__ src, long lds,
+                                         long ncols, Cross X, int zero_diag) {
+  const long m = X.m(), total = m * ncols, hp = (long)X.h * X.nv + X.pa;
   for (long x = blockIdx.x * (long)blockDim.x + threadIdx.x; x < total; x += (long)gridDim.x * blockDim.x) {
     const long k = x / ncols, c = x - k * ncols;
-    const long r = rp_row(k, o, v, h, pa);
-    dst[x] = (zero_hp && r == hp && c == hp) ? 0.0 : src[r * lds + c];
+    const long r = cross_row(X, k);
+    dst[k * ldd + c] = (zero_diag && r == hp && c == hp) ? 0.0 : src[r * lds + c];
   }
 }
 
-// dst[r][k] = src[r * lds + rp_row(k)] (r < nrows, k < m); with zero_rp, rows r in Rp are 0.
-__global__ void rp_gather_cols_kernel(double* __restrict__ dst, const double* __restrict__ src, long lds, long nrows,
-                                      int o, int v, int h, int pa, int zero_rp) {
-  const long m = (long)v + o - 1, total = nrows * m;
+// dst[r][k] = src[r][cross_row(k)] for k < m and 0 for m <= k < ldd (padding); with zero_rows,
+// rows r that are members of the row cross R are written as 0.
+__global__ void cross_gather_cols_kernel(double* __restrict__ dst, long ldd, const double* __restrict__ src, long lds,
+                                         long nrows, Cross X, Cross R, int zero_rows) {
+  const long m = X.m(), total = nrows * ldd;
   for (long x = blockIdx.x * (long)blockDim.x + threadIdx.x; x < total; x += (long)gridDim.x * blockDim.x) {
-    const long r = x / m, k = x - r * m;
-    dst[x] = (zero_rp && rp_member(r, v, h, pa)) ? 0.0 : src[r * lds + rp_row(k, o, v, h, pa)];
+    const long r = x / ldd, k = x - r * ldd;
+    dst[x] = (k >= m || (zero_rows && cross_member(R, r))) ? 0.0 : src[r * lds + cross_row(X, k)];
   }
 }
 
-// dst[rp_row(k) * ldd + c] += alpha * src[k][c] (rows of Rp are distinct: no two threads share a target).
-__global__ void rp_scatter_add_rows_kernel(double* __restrict__ dst, long ldd, const double* __restrict__ src,
-                                           long ncols, double alpha, int o, int v, int h, int pa) {
-  const long m = (long)v + o - 1, total = m * ncols;
+// dst[cross_row(k)][c] += alpha * src[k][c] (members are distinct: no two threads share a target).
+__global__ void cross_scatter_add_rows_kernel(double* __restrict__ dst, long ldd, const double* __restrict__ src,
+                                              long lds, long ncols, double alpha, Cross X) {
+  const long m = X.m(), total = m * ncols;
   for (long x = blockIdx.x * (long)blockDim.x + threadIdx.x; x < total; x += (long)gridDim.x * blockDim.x) {
     const long k = x / ncols, c = x - k * ncols;
-    dst[rp_row(k, o, v, h, pa) * ldd + c] += alpha * src[x];
+    dst[cross_row(X, k) * ldd + c] += alpha * src[k * lds + c];
   }
 }
 
-// dst[r * ldd + rp_row(k)] += alpha * src[r][k] (r < nrows, k < m).
-__global__ void rp_scatter_add_cols_kernel(double* __restrict__ dst, long ldd, const double* __restrict__ src,
-                                           long nrows, double alpha, int o, int v, int h, int pa) {
-  const long m = (long)v + o - 1, total = nrows * m;
+// dst[r][cross_row(k)] += alpha * src[r][k]   (r < nrows, k < m).
+__global__ void cross_scatter_add_cols_kernel(double* __restrict__ dst, long ldd, const double* __restrict__ src,
+                                              long lds, long nrows, double alpha, Cross X) {
+  const long m = X.m(), total = nrows * m;
   for (long x = blockIdx.x * (long)blockDim.x + threadIdx.x; x < total; x += (long)gridDim.x * blockDim.x) {
     const long r = x / m, k = x - r * m;
-    dst[r * ldd + rp_row(k, o, v, h, pa)] += alpha * src[x];
+    dst[r * ldd + cross_row(X, k)] += alpha * src[r * lds + k];
+  }
+}
+
+// dst[cross_row(k1)][cross_row(k2)] += alpha * src[k1][k2].
+__global__ void cross_scatter_add_block_kernel(double* __restrict__ dst, long ldd, const double* __restrict__ src,
+                                               long lds, double alpha, Cross X) {
+  const long m = X.m(), total = m * m;
+  for (long x = blockIdx.x * (long)blockDim.x + threadIdx.x; x < total; x += (long)gridDim.x * blockDim.x) {
+    const long k1 = x / m, k2 = x - k1 * m;
+    dst[cross_row(X, k1) * ldd + cross_row(X, k2)] += alpha * src[k1 * lds + k2];
+  }
+}
+
+// dst[k][c] = Y[cross_row(k)][c] - [cross_row(k) == hp] T[hp][hp] K[hp][c]  (square ld x ld operands,
+// hp = h * nv + pa): the cross rows of (T with its corner entry removed) K, from Y = T K.
+__global__ void cross_rows_without_corner_kernel(double* __restrict__ dst, long ldd, const double* __restrict__ Y,
+                                                 const double* __restrict__ T, const double* __restrict__ K, long ld,
+                                                 Cross X) {
+  const long m = X.m(), total = m * ld, hp = (long)X.h * X.nv + X.pa;
+  const double thp = T[hp * ld + hp];
+  for (long x = blockIdx.x * (long)blockDim.x + threadIdx.x; x < total; x += (long)gridDim.x * blockDim.x) {
+    const long k = x / ld, c = x - k * ld;
+    const long r = cross_row(X, k);
+    dst[k * ldd + c] = Y[r * ld + c] - (r == hp ? thp * K[hp * ld + c] : 0.0);
+  }
+}
+
+// EM[ij][a][b] += tc[ij][v + q(a)] * A[b][pa] for a != pa (q(a) = a - [a > pa]): the part of
+// sum_c t^M_ij^ac A[b][c] from the entries (a, pa) of rows ij outside the occupied cross, which
+// tc holds (compact vv-cross columns, rows of the occupied cross zero).
+__global__ void em_cross_column_kernel(double* __restrict__ em, const double* __restrict__ tc, long ldt,
+                                       const double* __restrict__ A, int o, int v, int pa) {
+  const long vv = (long)v * v, total = (long)o * o * vv;
+  for (long x = blockIdx.x * (long)blockDim.x + threadIdx.x; x < total; x += (long)gridDim.x * blockDim.x) {
+    const long ij = x / vv, ab = x - ij * vv;
+    const int a = (int)(ab / v), b = (int)(ab % v);
+    if (a == pa) continue;
+    em[x] += tc[ij * ldt + v + (a < pa ? a : a - 1)] * A[(long)b * v + pa];
   }
 }
 
@@ -893,70 +931,110 @@ hipError_t reference_energy(double* e0, const double* h, long hs, long hlen, con
 }
 
 namespace {
-bool rp_args_ok(int o, int v, int h, int pa) { return o >= 1 && v >= 1 && h >= 0 && h < o && pa >= 0 && pa < v; }
-unsigned rp_grid(long total) { return (unsigned)std::max<long>(1, std::min<long>((total + 255) / 256, 8192)); }
+bool cross_ok(const Cross& X) { return X.no >= 1 && X.nv >= 1 && X.h >= 0 && X.h < X.no && X.pa >= 0 && X.pa < X.nv; }
+unsigned ew_grid(long total) { return (unsigned)std::max<long>(1, std::min<long>((total + 255) / 256, 8192)); }
 }  // namespace
 
-hipError_t rp_gather_rows(double* dst, const double* src, long lds, long src_rows, long ncols, int o, int v, int h,
-                          int pa, bool zero_hp, hipStream_t s) {
-  const long ov = (long)o * v, m = (long)v + o - 1;
-  if (!rp_args_ok(o, v, h, pa) || src_rows < ov || ncols > lds || ncols < 1) return hipErrorInvalidValue;
-  if (bounds_checking() && !(range_ok(dst, 0, m * ncols - 1, 8, "Rp gather rows dst") &&
-                             range_ok(src, 0, (src_rows - 1) * lds + ncols - 1, 8, "Rp gather rows src")))
+hipError_t cross_gather_rows(double* dst, long ldd, const double* src, long lds, long src_rows, long ncols,
+                             const Cross& X, bool zero_diag, hipStream_t s) {
+  const long m = X.m();
+  if (!cross_ok(X) || src_rows < X.n() || ncols < 1 || ncols > lds || ncols > ldd) return hipErrorInvalidValue;
+  if (bounds_checking() && !(range_ok(dst, 0, (m - 1) * ldd + ncols - 1, 8, "cross gather rows dst") &&
+                             range_ok(src, 0, (src_rows - 1) * lds + ncols - 1, 8, "cross gather rows src")))
     return hipErrorInvalidValue;
   if (dry_run()) return hipSuccess;
-  hipLaunchKernelGGL(rp_gather_rows_kernel, dim3(rp_grid(m * ncols)), dim3(256), 0, s, dst, src, lds, ncols, o, v, h,
-                     pa, zero_hp ? 1 : 0);
+  hipLaunchKernelGGL(cross_gather_rows_kernel, dim3(ew_grid(m * ncols)), dim3(256), 0, s, dst, ldd, src, lds, ncols, X,
+                     zero_diag ? 1 : 0);
   return hipGetLastError();
 }
 
-hipError_t rp_gather_cols(double* dst, const double* src, long lds, long nrows, int o, int v, int h, int pa,
-                          bool zero_rp, hipStream_t s) {
-  const long ov = (long)o * v, m = (long)v + o - 1;
-  if (!rp_args_ok(o, v, h, pa) || lds < ov || nrows < 1) return hipErrorInvalidValue;
-  if (bounds_checking() && !(range_ok(dst, 0, nrows * m - 1, 8, "Rp gather cols dst") &&
-                             range_ok(src, 0, (nrows - 1) * lds + ov - 1, 8, "Rp gather cols src")))
+hipError_t cross_gather_cols(double* dst, long ldd, const double* src, long lds, long nrows, const Cross& X,
+                             const Cross* zero_rows, hipStream_t s) {
+  const long m = X.m();
+  if (!cross_ok(X) || lds < X.n() || nrows < 1 || ldd < m || (zero_rows && (!cross_ok(*zero_rows) || zero_rows->n() < nrows)))
+    return hipErrorInvalidValue;
+  if (bounds_checking() && !(range_ok(dst, 0, nrows * ldd - 1, 8, "cross gather cols dst") &&
+                             range_ok(src, 0, (nrows - 1) * lds + X.n() - 1, 8, "cross gather cols src")))
     return hipErrorInvalidValue;
   if (dry_run()) return hipSuccess;
-  hipLaunchKernelGGL(rp_gather_cols_kernel, dim3(rp_grid(nrows * m)), dim3(256), 0, s, dst, src, lds, nrows, o, v, h,
-                     pa, zero_rp ? 1 : 0);
+  const Cross R = zero_rows ? *zero_rows : X;
+  hipLaunchKernelGGL(cross_gather_cols_kernel, dim3(ew_grid(nrows * ldd)), dim3(256), 0, s, dst, ldd, src, lds, nrows, X,
+                     R, zero_rows ? 1 : 0);
   return hipGetLastError();
 }
 
-hipError_t rp_scatter_add_rows(double* dst, long ldd, long dst_rows, const double* src, long ncols, double alpha, int o,
-                               int v, int h, int pa, hipStream_t s) {
-  const long ov = (long)o * v, m = (long)v + o - 1;
-  if (!rp_args_ok(o, v, h, pa) || dst_rows < ov || ncols > ldd || ncols < 1) return hipErrorInvalidValue;
-  if (bounds_checking() && !(range_ok(dst, 0, (dst_rows - 1) * ldd + ncols - 1, 8, "Rp scatter rows dst") &&
-                             range_ok(src, 0, m * ncols - 1, 8, "Rp scatter rows src")))
+hipError_t cross_scatter_add_rows(double* dst, long ldd, long dst_rows, const double* src, long lds, long ncols,
+                                  double alpha, const Cross& X, hipStream_t s) {
+  const long m = X.m();
+  if (!cross_ok(X) || dst_rows < X.n() || ncols < 1 || ncols > ldd || ncols > lds) return hipErrorInvalidValue;
+  if (bounds_checking() && !(range_ok(dst, 0, (dst_rows - 1) * ldd + ncols - 1, 8, "cross scatter rows dst") &&
+                             range_ok(src, 0, (m - 1) * lds + ncols - 1, 8, "cross scatter rows src")))
     return hipErrorInvalidValue;
   if (dry_run()) return hipSuccess;
-  hipLaunchKernelGGL(rp_scatter_add_rows_kernel, dim3(rp_grid(m * ncols)), dim3(256), 0, s, dst, ldd, src, ncols, alpha,
-                     o, v, h, pa);
+  hipLaunchKernelGGL(cross_scatter_add_rows_kernel, dim3(ew_grid(m * ncols)), dim3(256), 0, s, dst, ldd, src, lds, ncols,
+                     alpha, X);
   return hipGetLastError();
 }
 
-hipError_t rp_scatter_add_cols(double* dst, long ldd, long nrows, const double* src, double alpha, int o, int v, int h,
-                               int pa, hipStream_t s) {
-  const long ov = (long)o * v, m = (long)v + o - 1;
-  if (!rp_args_ok(o, v, h, pa) || ldd < ov || nrows < 1) return hipErrorInvalidValue;
-  if (bounds_checking() && !(range_ok(dst, 0, (nrows - 1) * ldd + ov - 1, 8, "Rp scatter cols dst") &&
-                             range_ok(src, 0, nrows * m - 1, 8, "Rp scatter cols src")))
+hipError_t cross_scatter_add_cols(double* dst, long ldd, long nrows, const double* src, long lds, double alpha,
+                                  const Cross& X, hipStream_t s) {
+  const long m = X.m();
+  if (!cross_ok(X) || ldd < X.n() || nrows < 1 || lds < m) return hipErrorInvalidValue;
+  if (bounds_checking() && !(range_ok(dst, 0, (nrows - 1) * ldd + X.n() - 1, 8, "cross scatter cols dst") &&
+                             range_ok(src, 0, (nrows - 1) * lds + m - 1, 8, "cross scatter cols src")))
     return hipErrorInvalidValue;
   if (dry_run()) return hipSuccess;
-  hipLaunchKernelGGL(rp_scatter_add_cols_kernel, dim3(rp_grid(nrows * m)), dim3(256), 0, s, dst, ldd, src, nrows,
-                     alpha, o, v, h, pa);
+  hipLaunchKernelGGL(cross_scatter_add_cols_kernel, dim3(ew_grid(nrows * m)), dim3(256), 0, s, dst, ldd, src, lds, nrows,
+                     alpha, X);
+  return hipGetLastError();
+}
+
+hipError_t cross_scatter_add_block(double* dst, long ldd, const double* src, long lds, double alpha, const Cross& X,
+                                   hipStream_t s) {
+  const long m = X.m();
+  if (!cross_ok(X) || ldd < X.n() || lds < m) return hipErrorInvalidValue;
+  if (bounds_checking() && !(range_ok(dst, 0, (X.n() - 1) * ldd + X.n() - 1, 8, "cross scatter block dst") &&
+                             range_ok(src, 0, (m - 1) * lds + m - 1, 8, "cross scatter block src")))
+    return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  hipLaunchKernelGGL(cross_scatter_add_block_kernel, dim3(ew_grid(m * m)), dim3(256), 0, s, dst, ldd, src, lds, alpha, X);
+  return hipGetLastError();
+}
+
+hipError_t cross_rows_without_corner(double* dst, long ldd, const double* Y, const double* T, const double* K,
+                                     const Cross& X, hipStream_t s) {
+  const long m = X.m(), ld = X.n();
+  if (!cross_ok(X) || ldd < ld) return hipErrorInvalidValue;
+  if (bounds_checking() && !(range_ok(dst, 0, (m - 1) * ldd + ld - 1, 8, "cross rows dst") &&
+                             range_ok(Y, 0, ld * ld - 1, 8, "cross rows Y") && range_ok(T, 0, ld * ld - 1, 8, "cross rows T") &&
+                             range_ok(K, 0, ld * ld - 1, 8, "cross rows K")))
+    return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  hipLaunchKernelGGL(cross_rows_without_corner_kernel, dim3(ew_grid(m * ld)), dim3(256), 0, s, dst, ldd, Y, T, K, ld, X);
+  return hipGetLastError();
+}
+
+hipError_t em_cross_column(double* em, const double* tc, long ldt, const double* A, int o, int v, int pa,
+                           hipStream_t s) {
+  const long total = (long)o * o * v * v, mv = 2L * v - 1;
+  if (o < 1 || v < 1 || pa < 0 || pa >= v || ldt < mv) return hipErrorInvalidValue;
+  if (bounds_checking() && !(range_ok(em, 0, total - 1, 8, "EM cross column em") &&
+                             range_ok(tc, 0, ((long)o * o - 1) * ldt + mv - 1, 8, "EM cross column t") &&
+                             range_ok(A, 0, (long)v * v - 1, 8, "EM cross column A")))
+    return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  hipLaunchKernelGGL(em_cross_column_kernel, dim3(ew_grid(total)), dim3(256), 0, s, em, tc, ldt, A, o, v, pa);
   return hipGetLastError();
 }
 
 hipError_t mixed_doubles(double* dst, const double* src, int o, int v, int h, int pa, hipStream_t s) {
   const long total = (long)o * o * v * v;
-  if (!rp_args_ok(o, v, h, pa)) return hipErrorInvalidValue;
+  if (o < 1 || v < 1 || h < 0 || h >= o || pa < 0 || pa >= v) return hipErrorInvalidValue;
   if (bounds_checking() && !(range_ok(dst, 0, total - 1, 8, "mixed doubles dst") &&
                              range_ok(src, 0, total - 1, 8, "mixed doubles src")))
     return hipErrorInvalidValue;
   if (dry_run()) return hipSuccess;
-  hipLaunchKernelGGL(mixed_doubles_kernel, dim3(rp_grid(total)), dim3(256), 0, s, dst, src, o, v, h, pa);
+  hipLaunchKernelGGL(mixed_doubles_kernel, dim3(ew_grid(total)), dim3(256), 0, s, dst, src, o, v, h, pa);
   return hipGetLastError();
 }
 

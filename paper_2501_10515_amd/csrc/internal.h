@@ -170,21 +170,40 @@ hipError_t dress_apply(double* D, const double* S, const double* Tc, const doubl
 
 // x -> (1 + c E_hp) x (1 - c E_hp) in place on nb stacked n x n matrices (E_hp: one at row h, column p).
 hipError_t onebody_transform(double* X, long nb, int n, int h, int p, double c, hipStream_t s);
-// The primary rows Rp = {r = i*v + a : i == h or a == pa} of an ov x ov matrix (m = v + o - 1 of
-// them, compact order: (h, 0..v-1), then (i, pa) for i != h ascending).
-//   rp_gather_rows:  dst[m][ncols]  = rows Rp of src (leading dimension lds, src_rows >= ov rows);
-//                    zero_hp writes the entry at row and column (h, pa) as 0.
-//   rp_gather_cols:  dst[nrows][m]  = columns Rp of src; zero_rp writes rows r in Rp as 0.
-//   rp_scatter_add_rows / _cols: the inverse placements, dst += alpha * src.
+// A cross index set: over the n = no * nv indices r = i * nv + a, the members with i == h or
+// a == pa (m = no + nv - 1 of them), listed compactly as (h, 0 .. nv-1), then (i, pa) for i != h
+// ascending.  With (no, nv, h, pa) = (o, v, hole, particle) it is the set of (i, a) rows of an
+// ov x ov matrix that touch a primary orbital; (o, o, h, h) and (v, v, pa, pa) are the pair
+// indices ij and ab that do.
+struct Cross {
+  int no = 1, nv = 1, h = 0, pa = 0;
+  __host__ __device__ long n() const { return (long)no * nv; }
+  __host__ __device__ long m() const { return (long)no + nv - 1; }
+};
+//   cross_gather_rows: dst[k][c] = src[row k of X][c], c < ncols (zero_diag: the corner entry
+//                      at row and column h*nv + pa written as 0).
+//   cross_gather_cols: dst[r][k] = src[r][col k of X] for k < m, 0 for m <= k < ldd; zero_rows:
+//                      rows r that are members of *zero_rows written as 0.
+//   cross_scatter_add_rows / _cols / _block: the inverse placements, dst += alpha * src.
+//   cross_rows_without_corner: dst[k][c] = Y[row k][c] - [row k == hp] T[hp][hp] K[hp][c] for
+//                      square X.n() x X.n() operands (the cross rows of T' K, T' = T minus its
+//                      corner entry, from Y = T K).
+//   em_cross_column:   EM[ij][a][b] += tc[ij][v + a - [a > pa]] * A[b][pa] for a != pa.
 // mixed_doubles: dst = src on the mixed doubles (index set holds h or pa, not all primary), else 0.
-hipError_t rp_gather_rows(double* dst, const double* src, long lds, long src_rows, long ncols, int o, int v, int h,
-                          int pa, bool zero_hp, hipStream_t s);
-hipError_t rp_gather_cols(double* dst, const double* src, long lds, long nrows, int o, int v, int h, int pa,
-                          bool zero_rp, hipStream_t s);
-hipError_t rp_scatter_add_rows(double* dst, long ldd, long dst_rows, const double* src, long ncols, double alpha, int o,
-                               int v, int h, int pa, hipStream_t s);
-hipError_t rp_scatter_add_cols(double* dst, long ldd, long nrows, const double* src, double alpha, int o, int v, int h,
-                               int pa, hipStream_t s);
+hipError_t cross_gather_rows(double* dst, long ldd, const double* src, long lds, long src_rows, long ncols,
+                             const Cross& X, bool zero_diag, hipStream_t s);
+hipError_t cross_gather_cols(double* dst, long ldd, const double* src, long lds, long nrows, const Cross& X,
+                             const Cross* zero_rows, hipStream_t s);
+hipError_t cross_scatter_add_rows(double* dst, long ldd, long dst_rows, const double* src, long lds, long ncols,
+                                  double alpha, const Cross& X, hipStream_t s);
+hipError_t cross_scatter_add_cols(double* dst, long ldd, long nrows, const double* src, long lds, double alpha,
+                                  const Cross& X, hipStream_t s);
+hipError_t cross_scatter_add_block(double* dst, long ldd, const double* src, long lds, double alpha, const Cross& X,
+                                   hipStream_t s);
+hipError_t cross_rows_without_corner(double* dst, long ldd, const double* Y, const double* T, const double* K,
+                                     const Cross& X, hipStream_t s);
+hipError_t em_cross_column(double* em, const double* tc, long ldt, const double* A, int o, int v, int pa,
+                           hipStream_t s);
 hipError_t mixed_doubles(double* dst, const double* src, int o, int v, int h, int pa, hipStream_t s);
 // e0[0] = sum_{i<o} (h[i * hs] + f[i * fs]) (hlen, flen: elements of h and f, for the bounds check).
 hipError_t reference_energy(double* e0, const double* h, long hs, long hlen, const double* f, long fs, long flen,
