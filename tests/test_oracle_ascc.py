@@ -123,3 +123,73 @@ def test_two_electron_ascc_solution_is_an_eigenstate(v, Q, seed, particle):
     ev = np.linalg.eigvalsh(H)
     assert np.abs(ev - E).min() < 1e-9
     assert abs(E - ev.min()) > 1e-3
+
+
+# ---- the second ansatz (Sec. II.D)
+
+@pytest.mark.parametrize("alpha", [0.0, 0.15, -0.2])
+@pytest.mark.parametrize("o,v,hole,particle", [(1, 3, 0, 1), (2, 3, 1, 2), (2, 2, 0, 3)])
+def test_both_ansatz_give_the_reference_with_an_aufbau_part(o, v, hole, particle, alpha):
+    """With gamma = -beta^2/2, e^{-S^dagger} e^{T^P(0)} |phi_0> = beta (alpha |phi_0> + S |phi_0>) for
+    beta = 1/(1 + alpha); with S -> -S (the hole sign flipped) and beta = 1/(1 - alpha) the same state
+    up to normalisation: both ansatz target alpha |phi_0> + S |phi_0> (Eq. (eqn:ref-with-nz-aufbau))."""
+    B, eps = make_system(o, v, 4, 40, sigma=0.3)
+    h = cs_ccsd.core_hamiltonian_df(B, np.diag(eps), o)
+    bf = BruteForce(h, _eri(B), o, v)
+    S, Sd = _s_ops(bf, o, v, hole, particle)
+    target = alpha * bf.ref + S @ bf.ref
+    b_plus, b_minus = ascc.two_ansatz_betas(alpha)
+    for sign, beta in ((1.0, b_plus), (-1.0, b_minus)):
+        t1, t2 = ascc.initial_guess(o, v, hole, particle, beta=sign * beta, gamma=-0.5 * beta * beta)
+        t1so, t2so = closed_shell_to_so(t1, t2)
+        psi = sla.expm(-sign * Sd) @ bf.exp_T(t1so, t2so, bf.ref)
+        # psi = c * target for one scalar c
+        c = (target @ psi) / (target @ target)
+        assert np.abs(psi - c * target).max() < 1e-12
+        assert abs(c - sign * beta) < 1e-12
+
+
+def test_flipped_sign_is_the_transform_of_the_sign_flipped_orbitals():
+    """S -> -S on H is the standard transform of H with the hole orbital's sign flipped (F B F, F h F),
+    conjugated back by F: the two ansatz differ only by that phase convention."""
+    o, v, Q, seed, hole, particle = 2, 3, 8, 32, 1, 3
+    B, eps = make_system(o, v, Q, seed, sigma=0.3)
+    h = cs_ccsd.core_hamiltonian_df(B, np.diag(eps), o)
+    F = np.eye(o + v)
+    F[hole, hole] = -1.0
+    Bm, hm = ascc.transform(B, h, hole, particle, sign=-1.0)
+    Bf, hf = ascc.transform(np.einsum("pr,Qrs,sq->Qpq", F, B, F), F @ h @ F, hole, particle, sign=1.0)
+    assert np.abs(np.einsum("pr,Qrs,sq->Qpq", F, Bf, F) - Bm).max() < 1e-14
+    assert np.abs(F @ hf @ F - hm).max() < 1e-14
+    # and the flipped transform is the definition with -S
+    bf = BruteForce(h, _eri(B), o, v)
+    _, Sd = _s_ops(bf, o, v, hole, particle)
+    Hdef = sla.expm(-Sd) @ bf.hamiltonian_matrix() @ sla.expm(Sd)
+    assert np.abs(BruteForce(hm, _eri(Bm), o, v).hamiltonian_matrix() - Hdef).max() < 1e-12
+
+
+def test_flipped_solve_equals_the_solve_on_sign_flipped_orbitals():
+    o, v, Q, seed, hole, particle = 3, 12, 36, 7, 2, 3
+    B, eps = make_system(o, v, Q, seed, sigma=converging_sigma(v, Q))
+    F = np.ones(o + v)
+    F[hole] = -1.0
+    BF = B * F[None, :, None] * F[None, None, :]
+    beta = ascc.two_ansatz_betas(0.1)[1]
+    a = ascc.solve_state(B, eps, o, hole, particle, beta=beta, sign=-1.0)
+    b = ascc.solve_state(BF, eps, o, hole, particle, beta=beta, sign=1.0)
+    assert a["converged"] and b["converged"]
+    assert abs(a["E"] - b["E"]) < 1e-9
+
+
+@pytest.mark.parametrize("alpha", [0.0, 0.1])
+def test_two_electron_two_ansatz_energies_are_eigenvalues(alpha):
+    o, v, Q, seed, hole, particle = 1, 4, 8, 42, 0, 3
+    B, eps = make_system(o, v, Q, seed, sigma=converging_sigma(v, Q))
+    r = ascc.two_ansatz(B, eps, o, hole, particle, alpha, tol_rnorm=1e-11)
+    assert r["converged"]
+    h = cs_ccsd.core_hamiltonian_df(B, np.diag(eps), o)
+    ev = np.linalg.eigvalsh(BruteForce(h, _eri(B), o, v).hamiltonian_matrix())
+    for key in ("plus", "minus"):
+        assert np.abs(ev - r[key]["E"]).min() < 1e-9
+        assert r[key]["E"] - ev.min() > 1e-3
+    assert r["E"] == pytest.approx(0.5 * (r["plus"]["E"] + r["minus"]["E"]))
