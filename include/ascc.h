@@ -116,19 +116,22 @@ int ascc_build_ints_ws(const double* d_B, const double* d_fock, int fock_is_diag
                        ascc_ints** out);
 
 /* The integral set of the ASCC transformed Hamiltonian of a 1-CSF state (Sec. II.A):
- * Hbar = e^{S^dagger} H e^{-S^dagger} (Eq. (eqn: sim)) with S = (1/sqrt 2)(p_up^dagger h_up +
+ * Hbar = e^{S^dagger} H e^{-S^dagger} (Eq. (eqn: sim)) with S = (s/sqrt 2)(p_up^dagger h_up +
  * p_dn^dagger h_dn) (Eq. (eqn:1CSF-S)), where H is given exactly as for ascc_build_ints.
  *   hole      the orbital h (occupied: 0 <= hole < no)
  *   particle  the orbital p (virtual: no <= particle < no + nv, a full orbital index)
- * S^dagger is one-body with the spatial matrix K = E_hp / sqrt 2 (K^2 = 0), so Hbar stays two-body:
+ *   s_sign    s = +1: S as the paper writes it; s = -1: the same S after flipping the sign of the
+ *             hole orbital, which the second ansatz of Sec. II.D uses (see ascc_two_ansatz).
+ * S^dagger is one-body with the spatial matrix K = s E_hp / sqrt 2 (K^2 = 0), so Hbar stays two-body:
  * on the device every index pair of the DF factors and of the one-electron operator transforms as
  * x -> (1 + K) x (1 - K) before the constant blocks are formed (Bbar is then not symmetric in p,q).
  * The Jacobi denominators keep the diagonal of d_fock; the energy's f_ia is that of Hbar.  Every
  * other call then works on this handle unchanged (the amplitude equations of Hbar are those of
  * the ground state, Eq. (eqn:amp)); start it from ascc_initial_guess.  Synchronises `stream`.
- * Errors: as ascc_build_ints; ASCC_E_ARG for a hole or particle out of range. */
+ * Errors: as ascc_build_ints; ASCC_E_ARG for a hole or particle out of range or s_sign not +-1. */
 int ascc_build_ints_hbar(const double* d_B, const double* d_fock, int fock_is_diag, int no, int nv, int naux,
-                         int precision, int vvvv_mode, int hole, int particle, void* stream, ascc_ints** out);
+                         int precision, int vvvv_mode, int hole, int particle, int s_sign, void* stream,
+                         ascc_ints** out);
 
 /* The initial cluster operator T^P(0) = beta S + gamma S^2 of Eq. (eqn:TP-guess) (the paper's
  * values: beta = 1, gamma = -1/2), written as closed-shell amplitudes into caller-owned device
@@ -302,6 +305,31 @@ int ascc_timing_read(ascc_ints* ints, double* ms, int* counts, int n);
  * Host call, no stream work.  Errors: ASCC_E_ARG (NULL handle, indices out of range),
  * ASCC_E_NOMEM. */
 int ascc_set_plascc(ascc_ints* ints, int hole, int particle);
+
+/* The two ansatz choices of Sec. II.D for a 1-CSF state whose reference has the Aufbau coefficient
+ * alpha, alpha |phi_0> + S |phi_0> (Eq. (eqn:ref-with-nz-aufbau)), |alpha| < 1: the guess of
+ * Eq. (eqn:TP-guess) with gamma = -beta^2/2 reaches it for (1 - beta)/beta = alpha, and, with the
+ * hole orbital's sign flipped (S -> -S, s_sign = -1), for (1 - beta)/beta = -alpha.  Both are solved
+ * (ascc_build_ints_hbar, ascc_initial_guess with beta s and gamma, ascc_solve) one after the other,
+ * each on an integral set that is freed before the next is built; the reported energy is the mean
+ * of the two total energies.  For alpha = 0 both have beta = 1.
+ *   d_B, d_fock, fock_is_diag, no, nv, naux, precision, vvvv_mode, hole, particle: as for
+ *             ascc_build_ints_hbar; opts: as for ascc_solve (its low-precision hand-over applies
+ *             to both solves).
+ *   d_t1[2], d_t2[2]: caller-owned device arrays [no][nv] and [no][no][nv][nv] that receive the
+ *             amplitudes of the two solves ([0]: s = +1, [1]: s = -1).
+ *   res       host struct (written).
+ * Synchronises `stream`.  Errors: as the calls above; ASCC_E_ARG for |alpha| >= 1;
+ * ASCC_E_NOT_CONVERGED if either solve does not converge (res still written). */
+typedef struct ascc_two_ansatz_result {
+  double e_total[2];  /* total energies: [0] s = +1, beta = 1/(1 + alpha); [1] s = -1, beta = 1/(1 - alpha) */
+  double e_mean;      /* their mean: the reported ASCC energy                                           */
+  double beta[2];
+  ascc_result solve[2];
+} ascc_two_ansatz_result;
+int ascc_two_ansatz(const double* d_B, const double* d_fock, int fock_is_diag, int no, int nv, int naux, int precision,
+                    int vvvv_mode, int hole, int particle, double alpha, const ascc_opts* opts, double* const* d_t1,
+                    double* const* d_t2, ascc_two_ansatz_result* res, void* stream);
 
 /* Reference energy <phi_0|H|phi_0> of an integral set (paper Eq. (eqn:energy): the total energy
  * is this plus the correlation energy that ascc_residual / ascc_solve report), formed at build time

@@ -40,6 +40,7 @@ from ._lib import (  # noqa: F401
     ascc_reference_energy,
     ascc_timing_enable,
     ascc_timing_read,
+    ascc_two_ansatz,
     ascc_get_precision,
     ascc_residual,
     ascc_residual_batch,

@@ -61,13 +61,18 @@ class Result(ctypes.Structure):
                 ("lowp_iterations", ctypes.c_int)]
 
 
+class TwoAnsatzResult(ctypes.Structure):
+    _fields_ = [("e_total", ctypes.c_double * 2), ("e_mean", ctypes.c_double), ("beta", ctypes.c_double * 2),
+                ("solve", Result * 2)]
+
+
 EXPORTS = ("ascc_workspace_bytes", "ascc_build_ints", "ascc_residual", "ascc_diis_create", "ascc_diis_reset",
            "ascc_update", "ascc_solve", "ascc_ints_free", "ascc_diis_free", "ascc_ints_shape", "ascc_last_error",
            "ascc_phase_count", "ascc_phase_name", "ascc_timing_enable", "ascc_timing_read", "ascc_set_precision",
            "ascc_get_precision", "ascc_batch_reserve", "ascc_residual_batch", "ascc_build_ints_ws",
            "ascc_diis_create_ws", "ascc_server_create", "ascc_server_submit", "ascc_server_step",
            "ascc_server_info", "ascc_server_free", "ascc_build_ints_hbar", "ascc_initial_guess",
-           "ascc_reference_energy", "ascc_set_plascc")
+           "ascc_reference_energy", "ascc_set_plascc", "ascc_two_ansatz")
 
 
 def load_library():
@@ -83,8 +88,11 @@ def load_library():
     L.ascc_workspace_bytes.argtypes = [c_int, c_int, c_int, c_int, c_int, c_int, c_size_p, c_size_p]
     L.ascc_build_ints.argtypes = [vp, vp, c_int, c_int, c_int, c_int, c_int, c_int, vp, ctypes.POINTER(vp)]
     L.ascc_residual.argtypes = [vp, vp, vp, vp, vp, vp, vp]
-    L.ascc_build_ints_hbar.argtypes = [vp, vp, c_int, c_int, c_int, c_int, c_int, c_int, c_int, c_int, vp,
+    L.ascc_build_ints_hbar.argtypes = [vp, vp, c_int, c_int, c_int, c_int, c_int, c_int, c_int, c_int, c_int, vp,
                                        ctypes.POINTER(vp)]
+    L.ascc_two_ansatz.argtypes = [vp, vp, c_int, c_int, c_int, c_int, c_int, c_int, c_int, c_int, c_double,
+                                  ctypes.POINTER(Opts), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                  ctypes.POINTER(TwoAnsatzResult), vp]
     L.ascc_initial_guess.argtypes = [vp, vp, c_int, c_int, c_int, c_int, c_double, c_double, vp]
     L.ascc_reference_energy.argtypes = [vp, ctypes.POINTER(c_double), vp]
     L.ascc_set_plascc.argtypes = [vp, c_int, c_int]
@@ -216,8 +224,10 @@ def ascc_build_ints(B: torch.Tensor, fock: torch.Tensor, no: int, precision: int
 
 
 def ascc_build_ints_hbar(B: torch.Tensor, fock: torch.Tensor, no: int, hole: int, particle: int,
-                         precision: int = ASCC_PREC_FP64, vvvv_mode: int = ASCC_VVVV_FULL, stream=None) -> Ints:
-    """Integral set of the 1-CSF transformed Hamiltonian Hbar (``particle`` is a full orbital index)."""
+                         precision: int = ASCC_PREC_FP64, vvvv_mode: int = ASCC_VVVV_FULL, stream=None,
+                         s_sign: int = 1) -> Ints:
+    """Integral set of the 1-CSF transformed Hamiltonian Hbar (``particle`` is a full orbital index;
+    s_sign = -1: S of the hole-sign-flipped orbitals)."""
     naux, n, n2 = B.shape
     if n != n2:
         raise ValueError("B must be [naux][n][n]")
@@ -229,7 +239,7 @@ def ascc_build_ints_hbar(B: torch.Tensor, fock: torch.Tensor, no: int, hole: int
         pf, diag = _dev(fock, "fock", (n, n)), 0
     h = ctypes.c_void_p()
     _check(load_library().ascc_build_ints_hbar(pB, pf, diag, no, nv, naux, precision, vvvv_mode, hole, particle,
-                                               _stream(stream), ctypes.byref(h)))
+                                               s_sign, _stream(stream), ctypes.byref(h)))
     return Ints(h, no, nv, naux)
 
 
@@ -239,6 +249,35 @@ def ascc_initial_guess(t1, t2, hole: int, particle: int, beta: float = 1.0, gamm
     _check(load_library().ascc_initial_guess(_dev(t1, "t1", (no, nv)), _dev(t2, "t2", (no, no, nv, nv)), no, nv,
                                              hole, particle, ctypes.c_double(beta), ctypes.c_double(gamma),
                                              _stream(stream)))
+
+
+def ascc_two_ansatz(B: torch.Tensor, fock: torch.Tensor, no: int, hole: int, particle: int, alpha: float, t1s, t2s,
+                    precision: int = ASCC_PREC_FP64, vvvv_mode: int = ASCC_VVVV_FULL, tol_rnorm=1e-8, tol_rmax=0.0,
+                    tol_de=0.0, maxiter=100, diis_size=8, diis_start=1, level_shift=0.0, lowp_rnorm=0.0,
+                    lowp_maxiter=0, stream=None, raise_on_not_converged=True) -> dict:
+    """Both ansatz of a 1-CSF state with Aufbau coefficient alpha; t1s, t2s: two device arrays each."""
+    naux, n, n2 = B.shape
+    if n != n2:
+        raise ValueError("B must be [naux][n][n]")
+    nv = n - no
+    pB = _dev(B, "B")
+    if fock.dim() == 1:
+        pf, diag = _dev(fock, "fock", (n,)), 1
+    else:
+        pf, diag = _dev(fock, "fock", (n, n)), 0
+    p1 = (ctypes.c_void_p * 2)(*[_dev(t, "t1", (no, nv)).value for t in t1s])
+    p2 = (ctypes.c_void_p * 2)(*[_dev(t, "t2", (no, no, nv, nv)).value for t in t2s])
+    opts = Opts(tol_rnorm, tol_rmax, tol_de, maxiter, diis_size, diis_start, level_shift, lowp_rnorm, lowp_maxiter)
+    res = TwoAnsatzResult()
+    rc = load_library().ascc_two_ansatz(pB, pf, diag, no, nv, naux, precision, vvvv_mode, hole, particle,
+                                        ctypes.c_double(alpha), ctypes.byref(opts), p1, p2, ctypes.byref(res),
+                                        _stream(stream))
+    out = dict(e_total=[res.e_total[0], res.e_total[1]], e_mean=res.e_mean, beta=[res.beta[0], res.beta[1]],
+               solves=[dict(e_corr=r.e_corr, rnorm=r.rnorm, iterations=r.iterations, converged=bool(r.converged),
+                            lowp_iterations=r.lowp_iterations) for r in res.solve], status=rc)
+    if rc != ASCC_OK and not (rc == ASCC_E_NOT_CONVERGED and not raise_on_not_converged):
+        raise AsccError(rc, ascc_last_error())
+    return out
 
 
 def ascc_set_plascc(ints: Ints, hole: int, particle: int = -1):

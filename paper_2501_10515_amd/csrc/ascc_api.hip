@@ -1017,14 +1017,14 @@ int residual_fp64(ascc_ints* I, const double* t1, const double* t2, double* r1, 
   return residual_core(I, t1, t2, r1, r2, e, nullptr, s);
 }
 
-// hole >= 0: the integrals of Hbar = e^{S^dagger} H e^{-S^dagger} for S = (1/sqrt 2) sum_spin p^dagger h
-// (hole h occupied, particle p virtual; Sec. II.A, Eqs. (eqn:1CSF-S), (eqn: sim)).  S^dagger is
-// one-body with the spatial matrix K = E_hp / sqrt 2 (K^2 = 0), so every integral index pair
+// hole >= 0: the integrals of Hbar = e^{S^dagger} H e^{-S^dagger} for S = (s/sqrt 2) sum_spin p^dagger h
+// (hole h occupied, particle p virtual, s = s_sign = +-1; Sec. II.A, Eqs. (eqn:1CSF-S), (eqn: sim)).
+// S^dagger is one-body with the spatial matrix K = s E_hp / sqrt 2 (K^2 = 0), so every integral index pair
 // transforms as x -> (1 + K) x (1 - K): Bbar_Q and hbar, applied right after h is formed, so every
 // constant block below is one of Hbar.  The Jacobi denominators keep the diagonal of the given Fock
 // matrix; the f_ia of the energy is that of Hbar, fbar = hbar + sum_k [2 (pq|kk)bar - (pk|kq)bar].
 int build_constants(ascc_ints* I, const double* Bsrc, const double* fock, int fock_is_diag, int hole, int particle,
-                    hipStream_t s) {
+                    int s_sign, hipStream_t s) {
   const int o = I->no, v = I->nv, Q = I->naux;
   const long n = I->n, nn = n * n, ov = I->ov, oo = I->oo, vv = I->vv, ovov = I->ovov;
   const long wzl = ov + oo;
@@ -1054,7 +1054,7 @@ int build_constants(ascc_ints* I, const double* Bsrc, const double* fock, int fo
   int rc = add_two_electron_fock(I, I->h, I->B, I->J, o, v, Q, -1.0, s);
   if (rc) return rc;
   if (hole >= 0) {
-    const double c = 1.0 / std::sqrt(2.0);
+    const double c = s_sign / std::sqrt(2.0);
     HIPCHK(onebody_transform(I->B, Q, (int)n, hole, particle, c, s));
     HIPCHK(onebody_transform(I->h, 1, (int)n, hole, particle, c, s));
     HIPCHK(d_copy(I->Fh, I->h, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
@@ -1322,22 +1322,24 @@ int ascc_ints_shape(const ascc_ints* I, int* no, int* nv, int* naux) {
 }
 
 static int build_ints_impl(const double* d_B, const double* d_fock, int fock_is_diag, int no, int nv, int naux,
-                           int precision, int vvvv_mode, int hole, int particle, void* ws, size_t ws_bytes,
-                           void* stream, ascc_ints** out);
+                           int precision, int vvvv_mode, int hole, int particle, int s_sign, void* ws,
+                           size_t ws_bytes, void* stream, ascc_ints** out);
 
 int ascc_build_ints(const double* d_B, const double* d_fock, int fock_is_diag, int no, int nv, int naux, int precision,
                     int vvvv_mode, void* stream, ascc_ints** out) {
-  return build_ints_impl(d_B, d_fock, fock_is_diag, no, nv, naux, precision, vvvv_mode, -1, -1, nullptr, 0, stream,
+  return build_ints_impl(d_B, d_fock, fock_is_diag, no, nv, naux, precision, vvvv_mode, -1, -1, 1, nullptr, 0, stream,
                          out);
 }
 
 int ascc_build_ints_hbar(const double* d_B, const double* d_fock, int fock_is_diag, int no, int nv, int naux,
-                         int precision, int vvvv_mode, int hole, int particle, void* stream, ascc_ints** out) {
+                         int precision, int vvvv_mode, int hole, int particle, int s_sign, void* stream,
+                         ascc_ints** out) {
   if (out) *out = nullptr;
   if (hole < 0 || hole >= no || particle < no || particle >= no + nv)
     return fail(ASCC_E_ARG, "hole must be an occupied and particle a virtual orbital index");
-  return build_ints_impl(d_B, d_fock, fock_is_diag, no, nv, naux, precision, vvvv_mode, hole, particle, nullptr, 0,
-                         stream, out);
+  if (s_sign != 1 && s_sign != -1) return fail(ASCC_E_ARG, "s_sign must be +1 or -1");
+  return build_ints_impl(d_B, d_fock, fock_is_diag, no, nv, naux, precision, vvvv_mode, hole, particle, s_sign, nullptr,
+                         0, stream, out);
 }
 
 int ascc_initial_guess(double* d_t1, double* d_t2, int no, int nv, int hole, int particle, double beta, double gamma,
@@ -1357,13 +1359,13 @@ int ascc_build_ints_ws(const double* d_B, const double* d_fock, int fock_is_diag
                        int precision, int vvvv_mode, void* d_workspace, size_t ws_bytes, void* stream,
                        ascc_ints** out) {
   if (!d_workspace) return fail(ASCC_E_ARG, "d_workspace is NULL");
-  return build_ints_impl(d_B, d_fock, fock_is_diag, no, nv, naux, precision, vvvv_mode, -1, -1, d_workspace, ws_bytes,
-                         stream, out);
+  return build_ints_impl(d_B, d_fock, fock_is_diag, no, nv, naux, precision, vvvv_mode, -1, -1, 1, d_workspace,
+                         ws_bytes, stream, out);
 }
 
 static int build_ints_impl(const double* d_B, const double* d_fock, int fock_is_diag, int no, int nv, int naux,
-                           int precision, int vvvv_mode, int hole, int particle, void* ws, size_t ws_bytes,
-                           void* stream, ascc_ints** out) {
+                           int precision, int vvvv_mode, int hole, int particle, int s_sign, void* ws,
+                           size_t ws_bytes, void* stream, ascc_ints** out) {
   if (!out) return fail(ASCC_E_ARG, "out is NULL");
   *out = nullptr;
   if (!d_B || !d_fock) return fail(ASCC_E_ARG, "d_B and d_fock must be device pointers");
@@ -1408,7 +1410,7 @@ static int build_ints_impl(const double* d_B, const double* d_fock, int fock_is_
   ScopedBuffers user;
   user.add(d_B, sizeof(double) * Q * nn);
   user.add(d_fock, sizeof(double) * (fock_is_diag ? n : nn));
-  if (!rc) rc = build_constants(I, d_B, d_fock, fock_is_diag, hole, particle, s);
+  if (!rc) rc = build_constants(I, d_B, d_fock, fock_is_diag, hole, particle, s_sign, s);
   if (!rc && precision != ASCC_PREC_FP64) rc = build_lowp_shadows(I, s);
   if (!rc && !ws) {  // a workspace build stays asynchronous on `stream`
     hipError_t e = d_sync(s);
@@ -1695,6 +1697,43 @@ int ascc_solve(ascc_ints* I, const ascc_opts* opts, double* t1, double* t2, ascc
   ascc_diis_free(D);
   if (rc) return rc;
   if (status == ASCC_E_NOT_CONVERGED) set_error("not converged in maxiter iterations");
+  return status;
+}
+
+int ascc_two_ansatz(const double* d_B, const double* d_fock, int fock_is_diag, int no, int nv, int naux, int precision,
+                    int vvvv_mode, int hole, int particle, double alpha, const ascc_opts* opts, double* const* d_t1,
+                    double* const* d_t2, ascc_two_ansatz_result* res, void* stream) {
+  if (!opts || !d_t1 || !d_t2 || !res || !d_t1[0] || !d_t1[1] || !d_t2[0] || !d_t2[1])
+    return fail(ASCC_E_ARG, "NULL argument to ascc_two_ansatz");
+  if (!(std::fabs(alpha) < 1.0)) return fail(ASCC_E_ARG, "|alpha| must be below 1");
+  std::memset(res, 0, sizeof(*res));
+  res->beta[0] = 1.0 / (1.0 + alpha);  // (1 - beta)/beta = alpha
+  res->beta[1] = 1.0 / (1.0 - alpha);  // hole sign flipped: (1 - beta)/beta = -alpha
+  int status = ASCC_OK;
+  for (int k = 0; k < 2; ++k) {
+    const int sign = k == 0 ? 1 : -1;
+    const double beta = res->beta[k];
+    ascc_ints* I = nullptr;
+    int rc = ascc_build_ints_hbar(d_B, d_fock, fock_is_diag, no, nv, naux, precision, vvvv_mode, hole, particle, sign,
+                                  stream, &I);
+    if (rc) return rc;
+    rc = ascc_initial_guess(d_t1[k], d_t2[k], no, nv, hole, particle, sign * beta, -0.5 * beta * beta, stream);
+    if (!rc) rc = ascc_solve(I, opts, d_t1[k], d_t2[k], &res->solve[k], stream);
+    double e0 = 0.0;
+    if (!rc || rc == ASCC_E_NOT_CONVERGED) {
+      const int rc0 = ascc_reference_energy(I, &e0, stream);
+      if (rc0) rc = rc0;
+    }
+    ascc_ints_free(I);
+    if (rc == ASCC_E_NOT_CONVERGED) {
+      status = rc;
+    } else if (rc) {
+      return rc;
+    }
+    res->e_total[k] = e0 + res->solve[k].e_corr;
+  }
+  res->e_mean = 0.5 * (res->e_total[0] + res->e_total[1]);
+  if (status) set_error("a two-ansatz solve did not converge in maxiter iterations");
   return status;
 }
 

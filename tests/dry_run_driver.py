@@ -27,6 +27,11 @@ class Result(ctypes.Structure):
                 ("lowp_iterations", ctypes.c_int)]
 
 
+class TwoAnsatzResult(ctypes.Structure):
+    _fields_ = [("e_total", ctypes.c_double * 2), ("e_mean", ctypes.c_double), ("beta", ctypes.c_double * 2),
+                ("solve", Result * 2)]
+
+
 def main(shapes):
     L = ctypes.CDLL(str(LIB))
     vp = ctypes.c_void_p
@@ -46,10 +51,13 @@ def main(shapes):
     L.ascc_diis_create_ws.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, ctypes.c_size_t, ctypes.POINTER(vp)]
     L.ascc_ints_free.argtypes = [vp]
     L.ascc_diis_free.argtypes = [vp]
-    L.ascc_build_ints_hbar.argtypes = [vp, vp] + [ctypes.c_int] * 8 + [vp, ctypes.POINTER(vp)]
+    L.ascc_build_ints_hbar.argtypes = [vp, vp] + [ctypes.c_int] * 9 + [vp, ctypes.POINTER(vp)]
     L.ascc_initial_guess.argtypes = [vp, vp] + [ctypes.c_int] * 4 + [ctypes.c_double] * 2 + [vp]
     L.ascc_reference_energy.argtypes = [vp, ctypes.POINTER(ctypes.c_double), vp]
     L.ascc_set_plascc.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+    L.ascc_two_ansatz.argtypes = [vp, vp] + [ctypes.c_int] * 8 + [ctypes.c_double, ctypes.POINTER(Opts),
+                                                                    ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                                                    ctypes.POINTER(TwoAnsatzResult), vp]
     ok = True
     for shape in shapes:
         o, v, Q, diag = shape[:4]
@@ -96,7 +104,7 @@ def main(shapes):
             L.ascc_ints_free(h)
         if rc == 0:  # the transformed Hamiltonian of a 1-CSF state, its guess and one residual
             h4 = vp()
-            rc = L.ascc_build_ints_hbar(B, F, diag, o, v, Q, prec, mode, o - 1, o, None, ctypes.byref(h4))
+            rc = L.ascc_build_ints_hbar(B, F, diag, o, v, Q, prec, mode, o - 1, o, -1, None, ctypes.byref(h4))
             if rc == 0:
                 t1, t2, r1, r2, e = (fake(8 * o * v), fake(8 * o * o * v * v), fake(8 * o * v),
                                      fake(8 * o * o * v * v), fake(8))
@@ -115,6 +123,13 @@ def main(shapes):
                     e0 = ctypes.c_double(1.0)
                     rc = L.ascc_reference_energy(h4, ctypes.byref(e0), None)
                 L.ascc_ints_free(h4)
+            if rc == 0:  # both ansatz of the state, each built, solved and freed in turn
+                t1s = (vp * 2)(fake(8 * o * v), fake(8 * o * v))
+                t2s = (vp * 2)(fake(8 * o * o * v * v), fake(8 * o * o * v * v))
+                tres = TwoAnsatzResult()
+                rc = L.ascc_two_ansatz(B, F, diag, o, v, Q, prec, mode, o - 1, o, 0.1,
+                                       ctypes.byref(Opts(1e-8, 0, 0, 3, 8, 1, 0.0, 1e-3, 1)), t1s, t2s,
+                                       ctypes.byref(tres), None)
         if rc == 0:  # the same build and an update carved from exact-size workspaces
             ib, dbytes = ctypes.c_size_t(), ctypes.c_size_t()
             rc = L.ascc_workspace_bytes(o, v, Q, prec, mode, 8, ctypes.byref(ib), ctypes.byref(dbytes))

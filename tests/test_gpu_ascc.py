@@ -170,3 +170,59 @@ def test_two_electron_ascc_energy_is_an_excited_eigenvalue(P):
     print("E", E, "spectrum", ev, flush=True)
     assert np.abs(ev - E).min() < 1e-9
     assert abs(E - ev.min()) > 1e-3
+
+
+# ---- the second ansatz: S of the hole-sign-flipped orbitals, and both solves averaged
+
+@pytest.mark.parametrize("o,v,Q,seed,hole,particle,full", [SHAPES[1], SHAPES[3]])
+def test_flipped_sign_transform_matches_oracle(P, o, v, Q, seed, hole, particle, full):
+    from oracle import ascc, cs_ccsd
+
+    from .gpu_util import dev, gpu_residual
+
+    print(f"case o={o} v={v} Q={Q} seed={seed} {hole}->{particle} s=-1", flush=True)
+    B, eps = make_system(o, v, Q, seed, sigma=0.1)
+    fock = random_symmetric_fock(eps, 0.05, seed + 7) if full else np.diag(eps)
+    Bbar, fbar = ascc.transformed_inputs(B, fock, o, hole, particle, sign=-1.0)
+    t1, t2 = random_amplitudes(o, v, seed + 100, 0.05, 0.05)
+    g1, g2 = ascc.initial_guess(o, v, hole, particle, beta=-1.1, gamma=-0.605)
+    t1, t2 = t1 + g1, t2 + g2
+    r1_ref, r2_ref = cs_ccsd.residual(Bbar, fbar, t1, t2)
+    ints = P.ascc_build_ints_hbar(dev(B), dev(fock if full else eps), o, hole, particle, s_sign=-1,
+                                  vvvv_mode=P.ASCC_VVVV_PACKED)
+    r1, r2, e = gpu_residual(P, ints, t1, t2)
+    e0 = P.ascc_reference_energy(ints)
+    ints.close()
+    scale = max(1.0, np.abs(r2_ref).max())
+    assert np.abs(r1 - r1_ref).max() <= TOL * scale
+    assert np.abs(r2 - r2_ref).max() <= TOL * scale
+    assert abs(e - cs_ccsd.energy(Bbar, fbar, t1, t2)) <= TOL * scale
+    assert abs(e0 - ascc.reference_energy(Bbar, fbar, o)) <= TOL * max(1.0, abs(e0))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+@pytest.mark.parametrize("alpha", [0.0, 0.1])
+def test_two_ansatz_matches_oracle(P, alpha, prec):
+    import torch
+
+    from oracle import ascc
+
+    o, v, Q, seed, hole, particle = 3, 12, 36, 7, 2, 3
+    print(f"two ansatz o={o} v={v} alpha={alpha} {prec}", flush=True)
+    B, eps = make_system(o, v, Q, seed, sigma=converging_sigma(v, Q))
+    ref = ascc.two_ansatz(B, eps, o, hole, particle, alpha, tol_rnorm=1e-11, maxiter=600)
+    assert ref["converged"]
+    t1s = [torch.empty((o, v), dtype=torch.float64, device="cuda") for _ in range(2)]
+    t2s = [torch.empty((o, o, v, v), dtype=torch.float64, device="cuda") for _ in range(2)]
+    pc = P.ASCC_PREC_FP64 if prec == "fp64" else P.ASCC_PREC_BF16X3
+    r = P.ascc_two_ansatz(torch.from_numpy(B).cuda(), torch.from_numpy(eps).cuda(), o, hole, particle, alpha, t1s,
+                          t2s, precision=pc, vvvv_mode=P.ASCC_VVVV_PACKED, tol_rnorm=1e-8, maxiter=400,
+                          lowp_rnorm=1e-6 if prec != "fp64" else 0.0, raise_on_not_converged=False)
+    print(r, ref["plus"]["E"], ref["minus"]["E"], flush=True)
+    assert all(s["converged"] for s in r["solves"])
+    assert r["beta"] == pytest.approx(list(ascc.two_ansatz_betas(alpha)), abs=1e-15)
+    assert abs(r["e_total"][0] - ref["plus"]["E"]) <= 2e-8
+    assert abs(r["e_total"][1] - ref["minus"]["E"]) <= 2e-8
+    assert abs(r["e_mean"] - ref["E"]) <= 2e-8
+    assert np.abs(t2s[0].cpu().numpy() - ref["plus"]["t2"]).max() <= 1e-7
+    assert np.abs(t2s[1].cpu().numpy() - ref["minus"]["t2"]).max() <= 1e-7

@@ -58,10 +58,18 @@ def test_argument_errors_are_reported_not_thrown():
     # the 1-CSF entries reject a hole that is not occupied or a particle that is not virtual
     for hole, particle in [(-1, 3), (2, 3), (0, 1), (0, 5)]:  # no = 2, nv = 3
         h = ctypes.c_void_p(1)
-        rc = lib.ascc_build_ints_hbar(None, None, 1, 2, 3, 4, 0, 0, hole, particle, None, ctypes.byref(h))
+        rc = lib.ascc_build_ints_hbar(None, None, 1, 2, 3, 4, 0, 0, hole, particle, 1, None, ctypes.byref(h))
         assert rc == P.ASCC_E_ARG and "orbital index" in P.ascc_last_error() and not h.value
-    rc = lib.ascc_build_ints_hbar(None, None, 1, 2, 3, 4, 0, 0, 1, 2, None, ctypes.byref(h))
+    rc = lib.ascc_build_ints_hbar(None, None, 1, 2, 3, 4, 0, 0, 1, 2, 1, None, ctypes.byref(h))
     assert rc == P.ASCC_E_ARG and "device pointers" in P.ascc_last_error()
+    rc = lib.ascc_build_ints_hbar(None, None, 1, 2, 3, 4, 0, 0, 1, 2, 0, None, ctypes.byref(h))
+    assert rc == P.ASCC_E_ARG and "s_sign" in P.ascc_last_error()
+    opts = P._lib.Opts(1e-8, 0, 0, 10, 8, 1, 0.0, 0.0, 0)
+    res = P._lib.TwoAnsatzResult()
+    two = (ctypes.c_void_p * 2)(1, 1)
+    rc = lib.ascc_two_ansatz(None, None, 1, 2, 3, 4, 0, 0, 1, 2, 1.0, ctypes.byref(opts), two, two, ctypes.byref(res),
+                             None)
+    assert rc == P.ASCC_E_ARG and "alpha" in P.ascc_last_error()
     assert lib.ascc_initial_guess(None, None, 2, 3, 0, 2, 1.0, -0.5, None) == P.ASCC_E_ARG
 
 
