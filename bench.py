@@ -3,7 +3,7 @@
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--vvvv full|packed]
                 [--precision fp64|fp32|bf16x3] [--generator literal|converging] [--no-compare]
                 [--no-cpu-baseline] [--serve ...] [--solve [--ascc H,P|homo-lumo] [--plascc] [--solve-tol T]
-                [--lowp-rnorm R]]
+                [--lowp-rnorm R]] [--two-ansatz ALPHA [--ascc H,P]]
 
 A step is one pass of the whole iteration on the device: T1 dressing, every residual term,
 the energy and residual-norm reductions, the Jacobi update and DIIS (ascc_residual followed
@@ -281,23 +281,6 @@ def serve_main(args):
             r["max_abs_dE_vs_fp64"] = float(max(abs(a - b) for a, b in zip(r["energies"], base["energies"])))
     for r in res.values():
         r.pop("energies")
-    ground = None
-    if state is not None:  # the ground state of the same system, FP64: the excitation energy
-        dB, deps = torch.from_numpy(B).to(dev), torch.from_numpy(eps).to(dev)
-        ints = P.ascc_build_ints(dB, deps, o, vvvv_mode=mode)
-        if prim is not None:  # the same removal in the ground state (Sec. II.C)
-            P.ascc_set_plascc(ints, *prim)
-        del dB
-        t1 = torch.zeros((o, v), dtype=torch.float64, device=dev)
-        t2 = torch.zeros((o, o, v, v), dtype=torch.float64, device=dev)
-        r = P.ascc_solve(ints, t1, t2, tol_rnorm=tol, maxiter=args.solve_maxiter, raise_on_not_converged=False)
-        ground = {"e_total": P.ascc_reference_energy(ints) + r["e_corr"], "iterations": r["iterations"],
-                  "converged": r["converged"]}
-        ints.close()
-        del t1, t2
-        torch.cuda.empty_cache()
-        for rr in res.values():
-            rr["excitation_energy_eV"] = round((rr["e_total"] - ground["e_total"]) * 27.211386, 6)
     main = res.get("bf16x3_refined") or next(iter(res.values()))
     out["value"] = round(main["solves_per_s"], 4)
     out["higher_is_better"] = True
@@ -306,6 +289,14 @@ def serve_main(args):
     out["p99_s"] = round(main["p99_s"], 4)
     out["modes"] = res
     print(json.dumps(out), flush=True)
+
+
+def criterion(args) -> dict:
+    """Convergence test of the solves: |R|_2 <= --solve-tol, or with --paper-criterion the paper's own
+    (Sec. III.A): max|R| <= 1e-5 and |dE| < 1e-7 Eh in one iteration."""
+    if args.paper_criterion:
+        return dict(tol_rnorm=0.0, tol_rmax=1e-5, tol_de=1e-7)
+    return dict(tol_rnorm=args.solve_tol)
 
 
 def solve_main(args):
@@ -345,7 +336,7 @@ def solve_main(args):
         else:
             P.ascc_initial_guess(t1, t2, state[0], state[1])
     mode = P.ASCC_VVVV_FULL if args.vvvv == "full" else P.ASCC_VVVV_PACKED
-    tol = args.solve_tol
+    crit = criterion(args)
     res = {}
     for name, pc, lowp_rnorm in (("fp64", P.ASCC_PREC_FP64, 0.0), ("bf16x3_refined", P.ASCC_PREC_BF16X3, args.lowp_rnorm),
                                  ("fp32_refined", P.ASCC_PREC_FP32, args.lowp_rnorm)):
@@ -363,12 +354,12 @@ def solve_main(args):
         # untimed one-iteration solve first: the solver's DIIS history and work arrays (tens of GB
         # here) are then no longer the first touch of fresh device memory inside the timed solve
         start(t1, t2)
-        P.ascc_solve(ints, t1, t2, tol_rnorm=tol, maxiter=1, lowp_rnorm=lowp_rnorm, raise_on_not_converged=False)
+        P.ascc_solve(ints, t1, t2, maxiter=1, lowp_rnorm=lowp_rnorm, raise_on_not_converged=False, **crit)
         start(t1, t2)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        r = P.ascc_solve(ints, t1, t2, tol_rnorm=tol, maxiter=args.solve_maxiter, lowp_rnorm=lowp_rnorm,
-                         raise_on_not_converged=False)
+        r = P.ascc_solve(ints, t1, t2, maxiter=args.solve_maxiter, lowp_rnorm=lowp_rnorm,
+                         raise_on_not_converged=False, **crit)
         torch.cuda.synchronize()
         t_solve = time.perf_counter() - t0
         print(f"solve mode {name}: {t_solve:.2f} s, {r['iterations']} iterations", file=sys.stderr, flush=True)
@@ -393,7 +384,7 @@ def solve_main(args):
         del dB
         t1 = torch.zeros((o, v), dtype=torch.float64, device=dev)
         t2 = torch.zeros((o, o, v, v), dtype=torch.float64, device=dev)
-        r = P.ascc_solve(ints, t1, t2, tol_rnorm=tol, maxiter=args.solve_maxiter, raise_on_not_converged=False)
+        r = P.ascc_solve(ints, t1, t2, maxiter=args.solve_maxiter, raise_on_not_converged=False, **crit)
         ground = {"e_total": P.ascc_reference_energy(ints) + r["e_corr"], "iterations": r["iterations"],
                   "converged": r["converged"]}
         ints.close()
@@ -409,13 +400,61 @@ def solve_main(args):
            "value": main["solve_s"], "higher_is_better": False, "n_gpus": 1, "vs_baseline": None, "dtype": "f64",
            "data": "synthetic",
            "config": {"workload": args.workload, "no": o, "nv": v, "naux": Q, "seed": seed, "generator": "converging",
-                      "sigma": sigma, "vvvv": args.vvvv, "tol_rnorm": tol, "lowp_rnorm": args.lowp_rnorm,
+                      "sigma": sigma, "vvvv": args.vvvv, "criterion": crit, "lowp_rnorm": args.lowp_rnorm,
                       "state": "ground" if state is None else {"hole": state[0], "particle": state[1],
                                                                 "guess": "T^P(0) = S - S^2/2"},
                       "plascc_primaries": list(prim) if prim is not None else None},
            "modes": res}
     if ground is not None:
         out["ground_state_fp64"] = ground
+    print(json.dumps(out), flush=True)
+
+
+def two_ansatz_main(args):
+    """Both ansatz of a 1-CSF state (Aufbau coefficient --two-ansatz ALPHA) per precision mode: the
+    time of the pair of solves (each integral set built, solved and freed in turn), both total
+    energies and their mean."""
+    import torch
+
+    import paper_2501_10515_amd as P
+
+    wl = WORKLOADS[args.workload]
+    o, v, Q, seed = wl["no"], wl["nv"], wl["naux"], wl["seed"]
+    sigma = converging_sigma(v, Q)
+    B, eps = make_system(o, v, Q, seed, sigma=sigma)
+    dev = torch.device("cuda:0")
+    hole, particle = (int(x) for x in args.ascc.split(",")) if args.ascc not in ("", "homo-lumo") else (o - 1, o)
+    mode = P.ASCC_VVVV_FULL if args.vvvv == "full" else P.ASCC_VVVV_PACKED
+    dB, deps = torch.from_numpy(B).to(dev), torch.from_numpy(eps).to(dev)
+    t1s = [torch.empty((o, v), dtype=torch.float64, device=dev) for _ in range(2)]
+    t2s = [torch.empty((o, o, v, v), dtype=torch.float64, device=dev) for _ in range(2)]
+    res = {}
+    for name, pc, lowp in (("fp64", P.ASCC_PREC_FP64, 0.0), ("bf16x3_refined", P.ASCC_PREC_BF16X3, args.lowp_rnorm)):
+        if args.serve_precisions and name.split("_")[0] not in args.serve_precisions.split(","):
+            continue
+        kw = dict(precision=pc, vvvv_mode=mode, lowp_rnorm=lowp, raise_on_not_converged=False, **criterion(args))
+        P.ascc_two_ansatz(dB, deps, o, hole, particle, args.two_ansatz, t1s, t2s, maxiter=1, **kw)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = P.ascc_two_ansatz(dB, deps, o, hole, particle, args.two_ansatz, t1s, t2s, maxiter=args.solve_maxiter, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        print(f"two-ansatz mode {name}: {dt:.2f} s", file=sys.stderr, flush=True)
+        res[name] = {"seconds": round(dt, 3), "e_total": r["e_total"], "e_mean": r["e_mean"], "beta": r["beta"],
+                     "solves": r["solves"]}
+    base = res.get("fp64")
+    for name, r in res.items():
+        if base is not None and name != "fp64":
+            r["abs_dE_mean_vs_fp64"] = abs(r["e_mean"] - base["e_mean"])
+            r["speedup_vs_fp64"] = round(base["seconds"] / r["seconds"], 3)
+    main = res.get("bf16x3_refined") or next(iter(res.values()))
+    out = {"metric": "time to the two-ansatz ASCC energy (both solves), mixed vs FP64", "unit": "s",
+           "value": main["seconds"], "higher_is_better": False, "n_gpus": 1, "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": args.workload, "no": o, "nv": v, "naux": Q, "seed": seed, "generator": "converging",
+                      "sigma": sigma, "vvvv": args.vvvv, "criterion": criterion(args), "lowp_rnorm": args.lowp_rnorm,
+                      "hole": hole, "particle": particle, "alpha": args.two_ansatz},
+           "modes": res}
     print(json.dumps(out), flush=True)
 
 
@@ -442,7 +481,11 @@ def main():
                     "indices) or 'homo-lumo', solved on its transformed Hamiltonian from T^P(0)")
     ap.add_argument("--plascc", action="store_true", help="with --solve: the PLASCC term removal, primaries of "
                     "--ascc (or HOMO -> LUMO for the ground state), in every solve")
+    ap.add_argument("--two-ansatz", type=float, default=None, metavar="ALPHA",
+                    help="both ansatz of the --ascc state (default HOMO -> LUMO) for Aufbau coefficient ALPHA")
     ap.add_argument("--solve-tol", type=float, default=1e-7)
+    ap.add_argument("--paper-criterion", action="store_true",
+                    help="solves converge on max|R| <= 1e-5 and |dE| < 1e-7 Eh instead of --solve-tol")
     ap.add_argument("--solve-maxiter", type=int, default=60)
     ap.add_argument("--lowp-rnorm", type=float, default=1e-7,
                     help="hand-over residual norm of the low-precision bulk (the rounding-floor test also applies)")
@@ -454,6 +497,9 @@ def main():
 
     if args.serve:
         serve_main(args)
+        return
+    if args.two_ansatz is not None:
+        two_ansatz_main(args)
         return
     if args.solve:
         solve_main(args)
