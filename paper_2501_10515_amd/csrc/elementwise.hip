@@ -174,6 +174,52 @@ __global__ __launch_bounds__(kThreads) void dress_apply_kernel(double* __restric
   }
 }
 
+// The same dressing with the chunk's t1 coefficients staged in LDS first: for fixed i the 32
+// coefficients t1[i][p - o] of the chunk's rows are contiguous, zero for rows p < o or p >= n, so
+// the inner loop is branch-free and reads them as LDS broadcasts instead of one dependent scalar
+// load per (i, row).
+constexpr int kDressRows = 32;
+__global__ __launch_bounds__(kThreads) void dress_apply_lds_kernel(double* __restrict__ D, const double* __restrict__ S,
+                                                                   const double* __restrict__ Tc,
+                                                                   const double* __restrict__ t1, int o, int v) {
+  extern __shared__ double coef[];  // [o][kDressRows]
+  const int n = o + v;
+  const long nn = (long)n * n;
+  const int z = blockIdx.z, r0 = blockIdx.x * kDressRows, q = blockIdx.y * kThreads + threadIdx.x;
+  const bool lower = r0 + kDressRows > o;  // the chunk has rows p >= o
+  if (lower) {
+    for (int x = threadIdx.x; x < o * kDressRows; x += kThreads) {
+      const int i = x / kDressRows, p = r0 + (x - i * kDressRows);
+      coef[x] = (p >= o && p < n) ? t1[(long)i * v + (p - o)] : 0.0;
+    }
+    __syncthreads();
+  }
+  if (q >= n) return;
+  const double* Sz = S + z * nn;
+  const double* Tz = Tc + (long)z * n * o;
+  double* Dz = D + z * nn;
+  const bool qlo = q < o;
+  double acc[kDressRows];
+#pragma unroll
+  for (int r = 0; r < kDressRows; ++r) {
+    const int p = r0 + r;
+    acc[r] = p < n ? Sz[(long)p * n + q] + (qlo ? Tz[(long)p * o + q] : 0.0) : 0.0;
+  }
+  if (lower) {
+    for (int i = 0; i < o; ++i) {
+      const double b = Sz[(long)i * n + q] + (qlo ? Tz[(long)i * o + q] : 0.0);
+      const double* ci = coef + i * kDressRows;
+#pragma unroll
+      for (int r = 0; r < kDressRows; ++r) acc[r] -= ci[r] * b;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kDressRows; ++r) {
+    const int p = r0 + r;
+    if (p < n) Dz[(long)p * n + q] = acc[r];
+  }
+}
+
 // x -> (1 + c E_hp) x (1 - c E_hp) on each of nb stacked n x n matrices (E_hp: the unit matrix with a
 // one at row h, column p): row h += c row p, then column p -= c column h of the result.  One
 // workgroup per matrix; the two steps touch disjoint rows / columns of their own step.
@@ -771,6 +817,13 @@ hipError_t dress_apply(double* D, const double* S, const double* Tc, const doubl
                              range_ok(Tc, 0, nb * n * o - 1, 8, "dress Tc") && range_ok(t1, 0, (long)o * v - 1, 8, "dress t1")))
     return hipErrorInvalidValue;
   if (dry_run()) return hipSuccess;
+  if (o <= 256) {  // coefficients of one chunk: o * 32 doubles of LDS, 64 KB at most
+    hipLaunchKernelGGL(dress_apply_lds_kernel,
+                       dim3((unsigned)((n + kDressRows - 1) / kDressRows), (unsigned)((n + kThreads - 1) / kThreads),
+                            (unsigned)nb),
+                       dim3(kThreads), (size_t)o * kDressRows * sizeof(double), s, D, S, Tc, t1, o, v);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(dress_apply_kernel, dim3((unsigned)((n + 31) / 32), (unsigned)((n + kThreads - 1) / kThreads), (unsigned)nb),
                      dim3(kThreads), 0, s, D, S, Tc, t1, o, v);
   return hipGetLastError();

@@ -650,8 +650,8 @@ hipError_t gemm_f64(const Gemm& g, hipStream_t s) {
   const long tiles64 = (long)((g.M + 63) / 64) * ((g.N + 63) / 64) * nbatch;
   if (g.M >= 48 && g.N >= 48 && tiles64 >= 128) return launch_cfg<64, 64, 16, 2, 2, 2>(p, amf, bnf, g.nb1, g.ws, g.ws_elems, s);
   // a narrow output over a long K: 64 x 64 tiles of four waves, split along K, keep more of each
-  // CU busy than single-wave 32 x 32 tiles
-  if (g.ws && g.M >= 32 && g.N >= 32 && (long)g.K * g.nred >= 2048 && tiles64 < 192)
+  // CU busy (and more loads in flight) than single-wave 32 x 32 tiles
+  if (g.ws && g.M >= 16 && g.N >= 16 && (long)g.K * g.nred >= 2048 && tiles64 < 192)
     return launch_cfg<64, 64, 16, 2, 2, 2>(p, amf, bnf, g.nb1, g.ws, g.ws_elems, s);
   return launch_cfg<32, 32, 16, 1, 1, 3>(p, amf, bnf, g.nb1, g.ws, g.ws_elems, s);
 }
