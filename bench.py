@@ -59,7 +59,7 @@ LADDER_SOURCE = {"fp64": "gemm_f64.hip", "fp32": "gemm_lowp.hip", "bf16x3": "gem
 # (workload, vvvv, precision) with the sha256 of the kernel source they were taken on: a kernel
 # changed since then reports null.
 TRAFFIC = {
-    ("o20v180q600", "full", "fp64"): (5.441e+09, "331e298484d40276b330689322e14ce155f01a44a82a78ee560ac4dee37a9c6f"),
+    ("o20v180q600", "full", "fp64"): (5.331e+09, "bfd87cf674c6e0f608d28deace5a98fe722725c4e019e199fe397075f7161181"),
     ("o40v360q1200", "packed", "bf16x3"): (1.474e+11, "8692cddb0d74f53367dadd64809cd11efe62b3b5e809dd59b323e9d8e9a3f3f4"),
 }
 
