@@ -204,7 +204,7 @@ typedef struct ascc_opts {
   /* FP64 refinement of a low-precision solve: when the handle's precision is FP32 or BF16X3,
    * the iteration first runs in that precision without a convergence test until |R|_2 <=
    * lowp_rnorm, or lowp_maxiter iterations (<= 0: that bound unused), or |R|_2 has not set a
-   * new minimum (by 1%) for 4 iterations (the rounding floor of the low precision), then restarts
+   * new minimum (by 1%) for 8 iterations (the rounding floor of the low precision), then restarts
    * DIIS and continues in FP64 until the tests above pass.  The handle's precision is restored. */
   double lowp_rnorm;
   int lowp_maxiter;

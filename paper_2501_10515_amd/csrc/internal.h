@@ -113,9 +113,12 @@ hipError_t to_lowp_pm(int prec, float* out, long ldo, const double* V, long ldv,
 inline long lowp_ld(long k) { return (k + 31) / 32 * 32; }
 
 // Hand-over test of a low-precision bulk phase: the residual norm has reached the rounding floor
-// of the contractions when it has not set a new minimum (by 1%) for kPatience iterations.
+// of the contractions when it has not set a new minimum (by 1%) for kPatience iterations.  Eight,
+// not fewer: the excited-state (ASCC) iteration has plateaus of several iterations well above the
+// floor, and a low-precision iteration costs less than half an FP64 one, so waiting longer is
+// cheap while an early hand-over leaves most of the work to FP64.
 struct LowpStall {
-  static constexpr int kPatience = 4;
+  static constexpr int kPatience = 8;
   double best = 0.0;
   int since = 0;
   bool stalled(double rnorm) {
