@@ -14,6 +14,10 @@
  *   the reference Fock matrix; with S = 0 (ground state) Hbar = H (Eq. (eqn: sim)).
  *   The update is the diagonal approximate Jacobian with DIIS (Sec. III.B); the convergence
  *   test is max|R| and |dE| (Sec. III.A), optionally the residual 2-norm.
+ *   For a 1-CSF excited state, ascc_build_ints_hbar forms Hbar = e^{S^dagger} H e^{-S^dagger}
+ *   (Sec. II.A) and ascc_initial_guess the guess T^P(0) = beta S + gamma S^2; ascc_set_plascc
+ *   switches to the partially linearised equations (Sec. II.C); ascc_two_ansatz solves both
+ *   ansatz choices of Sec. II.D.  The mixed triples T^M_3' of Sec. II.B.1 are not provided.
  *
  * Conventions shared by every call:
  *   - no = occupied orbitals, nv = virtual orbitals, naux = fitting functions, n = no + nv;
@@ -21,16 +25,17 @@
  *   - Pointers named d_* are DEVICE memory on the current HIP device, owned by the caller,
  *     and must stay valid until the stream work that uses them has finished.
  *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).  Every call
- *     except ascc_build_ints, ascc_diis_create and ascc_solve is asynchronous on it.
+ *     except ascc_build_ints(_hbar), ascc_diis_create, ascc_solve, ascc_two_ansatz and
+ *     ascc_reference_energy is asynchronous on it (ascc_set_plascc issues no stream work).
  *   - Amplitude and residual arrays are double precision.  `precision` selects the arithmetic
  *     of the large contractions only; energies, norms, the update and DIIS are always FP64.
  *   - Every function returns ASCC_OK (0) or a negative ASCC_E_* code and never throws, exits
  *     or aborts; ascc_last_error() returns a message for the last failure on this thread.
- *   - Device memory: ascc_build_ints, ascc_batch_reserve and ascc_diis_create allocate the
- *     library's own device memory (integrals, work arrays, DIIS history; ascc_workspace_bytes
- *     reports the amount for the first and the last); ascc_*_free releases it.  ascc_solve
- *     allocates its DIIS state and iteration arrays and frees them before returning.  No other
- *     call allocates device memory.
+ *   - Device memory: ascc_build_ints(_hbar), ascc_batch_reserve, ascc_set_plascc and
+ *     ascc_diis_create allocate the library's own device memory (integrals, work arrays, DIIS
+ *     history; ascc_workspace_bytes reports the amount for the integrals and the DIIS state);
+ *     ascc_*_free releases it.  ascc_solve and ascc_two_ansatz allocate their own state and
+ *     free it before returning.  No other call allocates device memory.
  *   - A handle is not re-entrant: calls that share an ascc_ints (its work arrays) or an
  *     ascc_diis must be ordered on one stream.
  */
