@@ -207,10 +207,13 @@ typedef struct ascc_opts {
   int diis_start;     /* first 0-based iteration whose pair is stored                 */
   double level_shift; /* added to |D| (D - shift); 0 for the plain Jacobi step         */
   /* FP64 refinement of a low-precision solve: when the handle's precision is FP32 or BF16X3,
-   * the iteration first runs in that precision without a convergence test until |R|_2 <=
-   * lowp_rnorm, or lowp_maxiter iterations (<= 0: that bound unused), or |R|_2 has not set a
-   * new minimum (by 1%) for 8 iterations (the rounding floor of the low precision), then restarts
-   * DIIS and continues in FP64 until the tests above pass.  The handle's precision is restored. */
+   * the iteration first runs in that precision until its statistics pass the tests above, or
+   * |R|_2 <= lowp_rnorm, or lowp_maxiter iterations (<= 0: that bound unused), or |R|_2 has not
+   * set a new minimum (by 1%) for 8 iterations (the rounding floor of the low precision); then
+   * the same amplitudes are evaluated in FP64: if the tests pass there (with the energy change of
+   * the last low-precision iteration) the solve ends, else DIIS restarts from that FP64 residual
+   * and the iteration continues in FP64 until the tests pass.  A solve never ends on a
+   * low-precision residual.  The handle's precision is restored. */
   double lowp_rnorm;
   int lowp_maxiter;
 } ascc_opts;

@@ -1633,6 +1633,8 @@ int ascc_solve(ascc_ints* I, const ascc_opts* opts, double* t1, double* t2, ascc
   int status = ASCC_E_NOT_CONVERGED;
   int lowp_iters = 0;
   LowpStall stall;
+  bool confirm = false;  // the next evaluation is the first FP64 one after a hand-over
+  double handover_de = 0.0;
   for (int it = 0; !rc && it < opts->maxiter; ++it) {
     rc = residual_fp64(I, t1, t2, r1, r2, e, s);
     if (rc) break;
@@ -1658,29 +1660,44 @@ int ascc_solve(ascc_ints* I, const ascc_opts* opts, double* t1, double* t2, ascc
       status = fail(ASCC_E_NONFINITE, "non-finite residual or energy at iteration " + std::to_string(it));
       break;
     }
+    // the first FP64 evaluation after the hand-over is at the amplitudes of the last low-precision
+    // iteration: its energy change is that iteration's
+    if (confirm) res->de = handover_de;
+    const bool ok = (opts->tol_rnorm <= 0 || res->rnorm <= opts->tol_rnorm) &&
+                    (opts->tol_rmax <= 0 || res->rmax <= opts->tol_rmax) &&
+                    (opts->tol_de <= 0 || std::fabs(res->de) < opts->tol_de);
     if (lowp_phase) {
-      // low-precision bulk: no convergence test; hand over to FP64 once the residual is small
-      // enough, stops improving (its rounding floor), or the low-precision budget is spent (the
-      // DIIS history restarts in FP64)
+      // low-precision bulk: hand over to FP64 (which decides convergence) once the statistics
+      // already pass the convergence test, the residual is small enough, it stops improving (its
+      // rounding floor), or the low-precision budget is spent
       ++lowp_iters;
       res->lowp_iterations = lowp_iters;
-      const bool done = (opts->lowp_rnorm > 0 && hstats[3] <= opts->lowp_rnorm) ||
+      const bool done = ok || (opts->lowp_rnorm > 0 && hstats[3] <= opts->lowp_rnorm) ||
                         (opts->lowp_maxiter > 0 && lowp_iters >= opts->lowp_maxiter) || stall.stalled(hstats[3]);
       if (done) {
         lowp_phase = false;
         I->cur_prec = ASCC_PREC_FP64;
-        rc = ascc_diis_reset(D, stream);
-        if (rc) break;
+        confirm = true;
+        handover_de = hstats[1];
         continue;  // re-evaluate the same amplitudes in FP64
       }
     } else {
-      const bool ok = (opts->tol_rnorm <= 0 || hstats[3] <= opts->tol_rnorm) &&
-                      (opts->tol_rmax <= 0 || hstats[2] <= opts->tol_rmax) &&
-                      (opts->tol_de <= 0 || std::fabs(hstats[1]) < opts->tol_de);
       if (ok) {
         res->converged = 1;
         status = ASCC_OK;
         break;
+      }
+      if (confirm) {
+        // not converged in FP64 yet: the DIIS history restarts from this FP64 residual (the
+        // low-precision pairs carry the rounding of those contractions), and the update is redone
+        confirm = false;
+        if ((rc = ascc_diis_reset(D, stream))) break;
+        if (d_copy(t1s, t1, sizeof(double) * I->ov, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+            d_copy(t2s, t2, sizeof(double) * I->oovv, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+          rc = fail(ASCC_E_HIP, "copy of amplitudes failed");
+          break;
+        }
+        if ((rc = ascc_update(I, D, t1s, t2s, r1, r2, e, opts->level_shift, stats, stream))) break;
       }
     }
     // accept the update

@@ -264,9 +264,13 @@ bool consume(ascc_server* S, Request* R, double now) {
     R->t_done = now;
     return true;
   }
+  const bool ok = (o.tol_rnorm <= 0 || st[3] <= o.tol_rnorm) && (o.tol_rmax <= 0 || st[2] <= o.tol_rmax) &&
+                  (o.tol_de <= 0 || std::fabs(st[1]) < o.tol_de);
   if (R->lowp_phase) {
     R->lowp_iterations += 1;
-    const bool done = (o.lowp_rnorm > 0 && st[3] <= o.lowp_rnorm) ||
+    // hand over when the low-precision statistics already pass the convergence test (FP64 then
+    // confirms it), or on the residual / budget / rounding-floor rules
+    const bool done = ok || (o.lowp_rnorm > 0 && st[3] <= o.lowp_rnorm) ||
                       (o.lowp_maxiter > 0 && R->lowp_iterations >= o.lowp_maxiter) || R->stall.stalled(st[3]);
     if (done) {
       R->lowp_phase = false;
@@ -274,8 +278,6 @@ bool consume(ascc_server* S, Request* R, double now) {
       (void)ascc_diis_reset(R->diis, R->stream);
     }
   } else {
-    const bool ok = (o.tol_rnorm <= 0 || st[3] <= o.tol_rnorm) && (o.tol_rmax <= 0 || st[2] <= o.tol_rmax) &&
-                    (o.tol_de <= 0 || std::fabs(st[1]) < o.tol_de);
     if (ok) {
       R->status = ASCC_OK;
       R->t_done = now;
