@@ -226,3 +226,31 @@ def test_two_ansatz_matches_oracle(P, alpha, prec):
     assert abs(r["e_mean"] - ref["E"]) <= 2e-8
     assert np.abs(t2s[0].cpu().numpy() - ref["plus"]["t2"]).max() <= 1e-7
     assert np.abs(t2s[1].cpu().numpy() - ref["minus"]["t2"]).max() <= 1e-7
+
+
+def test_mixed_solve_ends_on_an_fp64_residual_under_the_paper_test(P):
+    """With the paper's test (max|R| <= 1e-5, |dE| < 1e-7; Sec. III.A) the low-precision bulk may
+    hand over on its own statistics; the solve must still end only where the FP64 residual at the
+    returned amplitudes passes."""
+    import torch
+
+    from .gpu_util import gpu_residual
+
+    o, v, Q, seed, hole, particle = 6, 24, 72, 5, 5, 6
+    B, eps = make_system(o, v, Q, seed, sigma=converging_sigma(v, Q))
+    dB, deps = torch.from_numpy(B).cuda(), torch.from_numpy(eps).cuda()
+    ints = P.ascc_build_ints_hbar(dB, deps, o, hole, particle, precision=P.ASCC_PREC_BF16X3,
+                                  vvvv_mode=P.ASCC_VVVV_PACKED)
+    t1 = torch.empty((o, v), dtype=torch.float64, device="cuda")
+    t2 = torch.empty((o, o, v, v), dtype=torch.float64, device="cuda")
+    P.ascc_initial_guess(t1, t2, hole, particle)
+    res = P.ascc_solve(ints, t1, t2, tol_rnorm=0.0, tol_rmax=1e-5, tol_de=1e-7, maxiter=400, lowp_rnorm=1e-9)
+    print(res, flush=True)
+    assert res["converged"] and res["lowp_iterations"] >= 1
+    assert P.ascc_get_precision(ints) == P.ASCC_PREC_BF16X3  # restored
+    P.ascc_set_precision(ints, P.ASCC_PREC_FP64)
+    r1, r2, e = gpu_residual(P, ints, t1.cpu().numpy(), t2.cpu().numpy())
+    ints.close()
+    assert max(np.abs(r1).max(), np.abs(r2).max()) <= 1e-5
+    assert abs(e - res["e_corr"]) < 1e-12
+    assert abs(res["rmax"] - max(np.abs(r1).max(), np.abs(r2).max())) < 1e-12
