@@ -268,6 +268,9 @@ typedef struct ascc_request_info {
   double e_corr, rnorm, rmax; /* of the last completed iteration                     */
   double t_submit, t_admit, t_done; /* caller clock values (ascc_server_submit/step) */
   size_t bytes;                     /* HBM footprint                                  */
+  double e_ref;      /* <phi_0|H|phi_0> of the request's integral set (of Hbar for a state), once
+                        the request has finished; e_ref + e_corr is its total energy         */
+  int hole, particle; /* the 1-CSF state of ascc_server_submit_state, or -1, -1           */
 } ascc_request_info;
 
 /* Errors: ASCC_E_ARG, ASCC_E_NOMEM (slab allocation). */
@@ -276,6 +279,13 @@ int ascc_server_create(const ascc_server_opts* opts, ascc_server** out);
  * Errors: ASCC_E_ARG, ASCC_E_SHAPE, ASCC_E_NOMEM (larger than the whole budget). */
 int ascc_server_submit(ascc_server* srv, const double* h_B, const double* h_eps, int no, int nv, int naux,
                        double t_submit, int* id);
+/* Queue an ASCC 1-CSF excited-state request (Sec. II.A): its integral set is Hbar of the state
+ * (hole, particle, s_sign as for ascc_build_ints_hbar) and its amplitudes start from T^P(0) =
+ * beta s S - (beta^2 / 2) S^2 (ascc_initial_guess; beta = 1 is Eq. (eqn:TP-guess)); otherwise it is
+ * served exactly like a ground-state request, with the same footprint.
+ * Errors: as ascc_server_submit; ASCC_E_ARG for a hole or particle out of range or s_sign not +-1. */
+int ascc_server_submit_state(ascc_server* srv, const double* h_B, const double* h_eps, int no, int nv, int naux,
+                             int hole, int particle, int s_sign, double beta, double t_submit, int* id);
 /* Retire finished requests, admit queued ones, launch the next iterations; `now` is the caller's
  * clock, recorded as admission / completion times.  Errors: ASCC_E_ARG, ASCC_E_HIP. */
 int ascc_server_step(ascc_server* srv, double now, int* n_queued, int* n_running, int* n_done);
@@ -338,6 +348,12 @@ typedef struct ascc_two_ansatz_result {
 int ascc_two_ansatz(const double* d_B, const double* d_fock, int fock_is_diag, int no, int nv, int naux, int precision,
                     int vvvv_mode, int hole, int particle, double alpha, const ascc_opts* opts, double* const* d_t1,
                     double* const* d_t2, ascc_two_ansatz_result* res, void* stream);
+
+/* The workspace form of ascc_build_ints_hbar (arguments as there and as for ascc_build_ints_ws:
+ * the integral set is carved from d_workspace, asynchronous on `stream`). */
+int ascc_build_ints_hbar_ws(const double* d_B, const double* d_fock, int fock_is_diag, int no, int nv, int naux,
+                            int precision, int vvvv_mode, int hole, int particle, int s_sign, void* d_workspace,
+                            size_t ws_bytes, void* stream, ascc_ints** out);
 
 /* Reference energy <phi_0|H|phi_0> of an integral set (paper Eq. (eqn:energy): the total energy
  * is this plus the correlation energy that ascc_residual / ascc_solve report), formed at build time

@@ -29,6 +29,7 @@ from ._lib import (  # noqa: F401
     ascc_batch_reserve,
     ascc_build_ints,
     ascc_build_ints_hbar,
+    ascc_build_ints_hbar_ws,
     ascc_build_ints_ws,
     ascc_diis_create,
     ascc_diis_create_ws,

@@ -52,7 +52,8 @@ class RequestInfo(ctypes.Structure):
                 ("status", ctypes.c_int), ("iterations", ctypes.c_int), ("lowp_iterations", ctypes.c_int),
                 ("e_corr", ctypes.c_double), ("rnorm", ctypes.c_double), ("rmax", ctypes.c_double),
                 ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
-                ("bytes", ctypes.c_size_t)]
+                ("bytes", ctypes.c_size_t), ("e_ref", ctypes.c_double), ("hole", ctypes.c_int),
+                ("particle", ctypes.c_int)]
 
 
 class Result(ctypes.Structure):
@@ -72,7 +73,8 @@ EXPORTS = ("ascc_workspace_bytes", "ascc_build_ints", "ascc_residual", "ascc_dii
            "ascc_get_precision", "ascc_batch_reserve", "ascc_residual_batch", "ascc_build_ints_ws",
            "ascc_diis_create_ws", "ascc_server_create", "ascc_server_submit", "ascc_server_step",
            "ascc_server_info", "ascc_server_free", "ascc_build_ints_hbar", "ascc_initial_guess",
-           "ascc_reference_energy", "ascc_set_plascc", "ascc_two_ansatz")
+           "ascc_reference_energy", "ascc_set_plascc", "ascc_two_ansatz", "ascc_build_ints_hbar_ws",
+           "ascc_server_submit_state")
 
 
 def load_library():
@@ -102,6 +104,8 @@ def load_library():
     L.ascc_solve.argtypes = [vp, ctypes.POINTER(Opts), vp, vp, ctypes.POINTER(Result), vp]
     L.ascc_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]
     L.ascc_server_submit.argtypes = [vp, vp, vp, c_int, c_int, c_int, c_double, ctypes.POINTER(c_int)]
+    L.ascc_server_submit_state.argtypes = [vp, vp, vp, c_int, c_int, c_int, c_int, c_int, c_int, c_double, c_double,
+                                           ctypes.POINTER(c_int)]
     L.ascc_server_step.argtypes = [vp, c_double, ctypes.POINTER(c_int), ctypes.POINTER(c_int), ctypes.POINTER(c_int)]
     L.ascc_server_info.argtypes = [vp, c_int, ctypes.POINTER(RequestInfo)]
     L.ascc_server_free.argtypes = [vp]
@@ -120,6 +124,8 @@ def load_library():
     L.ascc_set_precision.argtypes = [vp, c_int]
     L.ascc_build_ints_ws.argtypes = [vp, vp, c_int, c_int, c_int, c_int, c_int, c_int, vp, ctypes.c_size_t, vp,
                                      ctypes.POINTER(vp)]
+    L.ascc_build_ints_hbar_ws.argtypes = [vp, vp, c_int, c_int, c_int, c_int, c_int, c_int, c_int, c_int, c_int, vp,
+                                          ctypes.c_size_t, vp, ctypes.POINTER(vp)]
     L.ascc_diis_create_ws.argtypes = [vp, c_int, c_int, vp, ctypes.c_size_t, ctypes.POINTER(vp)]
     L.ascc_batch_reserve.argtypes = [vp, c_int]
     L.ascc_residual_batch.argtypes = [vp, c_int, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
@@ -249,6 +255,27 @@ def ascc_initial_guess(t1, t2, hole: int, particle: int, beta: float = 1.0, gamm
     _check(load_library().ascc_initial_guess(_dev(t1, "t1", (no, nv)), _dev(t2, "t2", (no, no, nv, nv)), no, nv,
                                              hole, particle, ctypes.c_double(beta), ctypes.c_double(gamma),
                                              _stream(stream)))
+
+
+def ascc_build_ints_hbar_ws(B: torch.Tensor, fock: torch.Tensor, no: int, hole: int, particle: int,
+                            workspace: torch.Tensor, precision: int = ASCC_PREC_FP64,
+                            vvvv_mode: int = ASCC_VVVV_FULL, s_sign: int = 1, stream=None) -> Ints:
+    """ascc_build_ints_hbar carved from a caller-owned device workspace (uint8 tensor)."""
+    naux, n, n2 = B.shape
+    if n != n2:
+        raise ValueError("B must be [naux][n][n]")
+    nv = n - no
+    pB = _dev(B, "B")
+    if fock.dim() == 1:
+        pf, diag = _dev(fock, "fock", (n,)), 1
+    else:
+        pf, diag = _dev(fock, "fock", (n, n)), 0
+    nbytes = workspace.numel() * workspace.element_size()
+    h = ctypes.c_void_p()
+    _check(load_library().ascc_build_ints_hbar_ws(pB, pf, diag, no, nv, naux, precision, vvvv_mode, hole, particle,
+                                                  s_sign, _workspace_ptr(workspace, nbytes), nbytes, _stream(stream),
+                                                  ctypes.byref(h)))
+    return Ints(h, no, nv, naux, workspace)
 
 
 def ascc_two_ansatz(B: torch.Tensor, fock: torch.Tensor, no: int, hole: int, particle: int, alpha: float, t1s, t2s,
@@ -424,16 +451,23 @@ class Server:
         _check(load_library().ascc_server_create(ctypes.byref(opts), ctypes.byref(h)))
         self.handle = h
 
-    def submit(self, B, eps, no: int, t_submit: float) -> int:
+    def submit(self, B, eps, no: int, t_submit: float, hole: int = -1, particle: int = -1, s_sign: int = 1,
+               beta: float = 1.0) -> int:
+        """Queue a ground-state request, or (hole >= 0) the 1-CSF ASCC state hole -> particle."""
         import numpy as np
 
         B = np.ascontiguousarray(B, dtype=np.float64)
         eps = np.ascontiguousarray(eps, dtype=np.float64)
         naux, n, _ = B.shape
         rid = ctypes.c_int()
-        _check(load_library().ascc_server_submit(self.handle, B.ctypes.data_as(ctypes.c_void_p),
-                                                 eps.ctypes.data_as(ctypes.c_void_p), no, n - no, naux,
-                                                 ctypes.c_double(t_submit), ctypes.byref(rid)))
+        pB, pe = B.ctypes.data_as(ctypes.c_void_p), eps.ctypes.data_as(ctypes.c_void_p)
+        if hole < 0:
+            _check(load_library().ascc_server_submit(self.handle, pB, pe, no, n - no, naux,
+                                                     ctypes.c_double(t_submit), ctypes.byref(rid)))
+        else:
+            _check(load_library().ascc_server_submit_state(self.handle, pB, pe, no, n - no, naux, hole, particle,
+                                                           s_sign, ctypes.c_double(beta), ctypes.c_double(t_submit),
+                                                           ctypes.byref(rid)))
         return rid.value
 
     def step(self, now: float):

@@ -1342,6 +1342,18 @@ int ascc_build_ints_hbar(const double* d_B, const double* d_fock, int fock_is_di
                          0, stream, out);
 }
 
+int ascc_build_ints_hbar_ws(const double* d_B, const double* d_fock, int fock_is_diag, int no, int nv, int naux,
+                            int precision, int vvvv_mode, int hole, int particle, int s_sign, void* d_workspace,
+                            size_t ws_bytes, void* stream, ascc_ints** out) {
+  if (out) *out = nullptr;
+  if (!d_workspace) return fail(ASCC_E_ARG, "d_workspace is NULL");
+  if (hole < 0 || hole >= no || particle < no || particle >= no + nv)
+    return fail(ASCC_E_ARG, "hole must be an occupied and particle a virtual orbital index");
+  if (s_sign != 1 && s_sign != -1) return fail(ASCC_E_ARG, "s_sign must be +1 or -1");
+  return build_ints_impl(d_B, d_fock, fock_is_diag, no, nv, naux, precision, vvvv_mode, hole, particle, s_sign,
+                         d_workspace, ws_bytes, stream, out);
+}
+
 int ascc_initial_guess(double* d_t1, double* d_t2, int no, int nv, int hole, int particle, double beta, double gamma,
                        void* stream) {
   if (!d_t1 || !d_t2) return fail(ASCC_E_ARG, "NULL amplitude array");

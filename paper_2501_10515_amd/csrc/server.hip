@@ -50,6 +50,8 @@ struct Request {
   LowpStall stall;
   int iterations = 0, lowp_iterations = 0;
   double e_corr = 0, rnorm = 0, rmax = 0, de = 0;
+  int hole = -1, particle = -1, s_sign = 1;  // a 1-CSF state (hole >= 0) or the ground state
+  double beta = 1.0, e_ref = 0.0;
 };
 
 }  // namespace
@@ -210,15 +212,24 @@ int admit(ascc_server* S, Request* R, double now) {
   if (hipMemcpyAsync(R->dB, R->hB.data(), 8 * R->hB.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemcpyAsync(R->deps, R->heps.data(), 8 * n, hipMemcpyHostToDevice, s) != hipSuccess)
     return sfail(ASCC_E_HIP, "upload of request inputs failed");
-  int rc = ascc_build_ints_ws(R->dB, R->deps, 1, R->o, R->v, R->Q, S->opts.precision, S->opts.vvvv_mode, ints_ws,
-                              R->ints_bytes, s, &R->ints);
+  int rc = R->hole < 0 ? ascc_build_ints_ws(R->dB, R->deps, 1, R->o, R->v, R->Q, S->opts.precision,
+                                            S->opts.vvvv_mode, ints_ws, R->ints_bytes, s, &R->ints)
+                       : ascc_build_ints_hbar_ws(R->dB, R->deps, 1, R->o, R->v, R->Q, S->opts.precision,
+                                                 S->opts.vvvv_mode, R->hole, R->particle, R->s_sign, ints_ws,
+                                                 R->ints_bytes, s, &R->ints);
   if (rc) return rc;
   rc = ascc_diis_create_ws(R->ints, S->opts.solve.diis_size, S->opts.solve.diis_start, diis_ws, R->diis_bytes,
                            &R->diis);
   if (rc) return rc;
-  int d1[4] = {(int)ov, 1, 1, 1}, d2[4] = {(int)oovv, 1, 1, 1};
-  if (permute4(R->t1, d1, 0.0, nullptr, 0, s) != hipSuccess || permute4(R->t2, d2, 0.0, nullptr, 0, s) != hipSuccess)
-    return sfail(ASCC_E_HIP, "amplitude initialisation failed");
+  if (R->hole >= 0) {  // T^P(0) of the state
+    if ((rc = ascc_initial_guess(R->t1, R->t2, R->o, R->v, R->hole, R->particle, R->s_sign * R->beta,
+                                 -0.5 * R->beta * R->beta, s)))
+      return rc;
+  } else {
+    int d1[4] = {(int)ov, 1, 1, 1}, d2[4] = {(int)oovv, 1, 1, 1};
+    if (permute4(R->t1, d1, 0.0, nullptr, 0, s) != hipSuccess || permute4(R->t2, d2, 0.0, nullptr, 0, s) != hipSuccess)
+      return sfail(ASCC_E_HIP, "amplitude initialisation failed");
+  }
   R->lowp_phase = (S->opts.precision != ASCC_PREC_FP64);
   if (S->opts.use_graphs) {
     if (R->lowp_phase && (rc = capture(R, S->opts.precision, &R->g_low))) return rc;
@@ -281,12 +292,14 @@ bool consume(ascc_server* S, Request* R, double now) {
     if (ok) {
       R->status = ASCC_OK;
       R->t_done = now;
+      (void)ascc_reference_energy(R->ints, &R->e_ref, R->stream);  // the stream is idle: no wait
       return true;
     }
   }
   if (R->iterations >= o.maxiter) {
     R->status = ASCC_E_NOT_CONVERGED;
     R->t_done = now;
+    (void)ascc_reference_energy(R->ints, &R->e_ref, R->stream);
     return true;
   }
   return false;
@@ -313,6 +326,22 @@ int ascc_server_create(const ascc_server_opts* opts, ascc_server** out) {
   register_buffer(S->slab, S->slab_bytes);
   S->free_list[0] = S->slab_bytes;
   *out = S;
+  return ASCC_OK;
+}
+
+int ascc_server_submit_state(ascc_server* S, const double* h_B, const double* h_eps, int no, int nv, int naux,
+                             int hole, int particle, int s_sign, double beta, double t_submit, int* id) {
+  if (hole < 0 || hole >= no || particle < no || particle >= no + nv)
+    return sfail(ASCC_E_ARG, "hole must be an occupied and particle a virtual orbital index");
+  if (s_sign != 1 && s_sign != -1) return sfail(ASCC_E_ARG, "s_sign must be +1 or -1");
+  if (!(beta > 0.0)) return sfail(ASCC_E_ARG, "beta must be positive");
+  int rc = ascc_server_submit(S, h_B, h_eps, no, nv, naux, t_submit, id);
+  if (rc) return rc;
+  Request* R = S->reqs[*id];
+  R->hole = hole;
+  R->particle = particle;
+  R->s_sign = s_sign;
+  R->beta = beta;
   return ASCC_OK;
 }
 
@@ -420,6 +449,9 @@ int ascc_server_info(const ascc_server* S, int id, ascc_request_info* info) {
   info->t_done = R->t_done;
   size_t ib = 0, db = 0;
   info->bytes = request_bytes(S, R->o, R->v, R->Q, &ib, &db);
+  info->e_ref = R->e_ref;
+  info->hole = R->hole;
+  info->particle = R->particle;
   return ASCC_OK;
 }
 

@@ -55,6 +55,7 @@ def main(shapes):
     L.ascc_initial_guess.argtypes = [vp, vp] + [ctypes.c_int] * 4 + [ctypes.c_double] * 2 + [vp]
     L.ascc_reference_energy.argtypes = [vp, ctypes.POINTER(ctypes.c_double), vp]
     L.ascc_set_plascc.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+    L.ascc_build_ints_hbar_ws.argtypes = [vp, vp] + [ctypes.c_int] * 9 + [vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
     L.ascc_two_ansatz.argtypes = [vp, vp] + [ctypes.c_int] * 8 + [ctypes.c_double, ctypes.POINTER(Opts),
                                                                     ctypes.POINTER(vp), ctypes.POINTER(vp),
                                                                     ctypes.POINTER(TwoAnsatzResult), vp]
@@ -123,6 +124,18 @@ def main(shapes):
                     e0 = ctypes.c_double(1.0)
                     rc = L.ascc_reference_energy(h4, ctypes.byref(e0), None)
                 L.ascc_ints_free(h4)
+            if rc == 0:  # the state's integral set carved from an exact-size workspace
+                ib, dbytes = ctypes.c_size_t(), ctypes.c_size_t()
+                rc = L.ascc_workspace_bytes(o, v, Q, prec, mode, 8, ctypes.byref(ib), ctypes.byref(dbytes))
+                h5 = vp()
+                if rc == 0:
+                    rc = L.ascc_build_ints_hbar_ws(B, F, diag, o, v, Q, prec, mode, 0, o + v - 1, 1, fake(ib.value),
+                                                   ib.value, None, ctypes.byref(h5))
+                if rc == 0:
+                    t1, t2, r1, r2, e = (fake(8 * o * v), fake(8 * o * o * v * v), fake(8 * o * v),
+                                         fake(8 * o * o * v * v), fake(8))
+                    rc = L.ascc_residual(h5, t1, t2, r1, r2, e, None)
+                    L.ascc_ints_free(h5)
             if rc == 0:  # both ansatz of the state, each built, solved and freed in turn
                 t1s = (vp * 2)(fake(8 * o * v), fake(8 * o * v))
                 t2s = (vp * 2)(fake(8 * o * o * v * v), fake(8 * o * o * v * v))

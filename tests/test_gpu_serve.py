@@ -31,9 +31,10 @@ def _requests():
     return out
 
 
-def _serve(P, reqs, order, precision, gap=0.0, graphs=True, budget=2 << 30, max_active=8):
+def _serve(P, reqs, order, precision, gap=0.0, graphs=True, budget=2 << 30, max_active=8, tol_rnorm=1e-9,
+           maxiter=200):
     srv = P.Server(budget, max_active=max_active, precision=precision, vvvv_mode=P.ASCC_VVVV_PACKED,
-                   use_graphs=graphs, tol_rnorm=1e-9, maxiter=200, lowp_rnorm=1e-5)
+                   use_graphs=graphs, tol_rnorm=tol_rnorm, maxiter=maxiter, lowp_rnorm=1e-5)
     t0 = time.perf_counter()
     ids = {}
     pending = list(order)
@@ -41,8 +42,9 @@ def _serve(P, reqs, order, precision, gap=0.0, graphs=True, budget=2 << 30, max_
         now = time.perf_counter() - t0
         while pending and now >= gap * len(ids):
             k = pending.pop(0)
-            o, B, eps = reqs[k]
-            ids[k] = srv.submit(B, eps, o, now)
+            o, B, eps = reqs[k][:3]
+            state = reqs[k][3] if len(reqs[k]) > 3 else (-1, -1)  # (hole, particle) of a 1-CSF state
+            ids[k] = srv.submit(B, eps, o, now, hole=state[0], particle=state[1])
         q, r, d = srv.step(now)
         if not pending and d == len(order):
             break
@@ -94,3 +96,36 @@ def test_graph_replay_equals_direct_launches(P):
     b = _serve(P, reqs, [0, 1], P.ASCC_PREC_FP64, graphs=False)
     for k in a:
         assert a[k]["e_corr"] == b[k]["e_corr"] and a[k]["iterations"] == b[k]["iterations"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_served_excited_states_alone_equal_mixed_and_oracle(P, prec):
+    """ASCC 1-CSF states (Hbar integral sets, T^P(0) guesses) served among ground-state requests."""
+    from oracle import ascc, cs_ccsd, solver
+
+    reqs = _requests()[:3]
+    for o, v, Q, seed, hole, particle in [(3, 12, 36, 7, 2, 3), (6, 24, 72, 5, 5, 6)]:
+        B, eps = make_system(o, v, Q, seed, sigma=converging_sigma(v, Q))
+        reqs.append((o, B, eps, (hole, particle)))
+    pc = P.ASCC_PREC_FP64 if prec == "fp64" else P.ASCC_PREC_BF16X3
+    mixed = _serve(P, reqs, list(range(len(reqs))), pc, tol_rnorm=1e-8, maxiter=400)
+    for k in (3, 4):
+        alone = _serve(P, reqs, [k], pc, tol_rnorm=1e-8, maxiter=400)[k]
+        m = mixed[k]
+        print(k, prec, m, flush=True)
+        assert alone["status"] == 0 and m["status"] == 0
+        assert (m["hole"], m["particle"]) == reqs[k][3]
+        assert alone["iterations"] == m["iterations"] and alone["e_corr"] == m["e_corr"]
+        o, B, eps, (hole, particle) = reqs[k]
+        Bbar, fbar = ascc.transformed_inputs(B, eps, o, hole, particle)
+        g1, g2 = ascc.initial_guess(o, eps.size - o, hole, particle)
+        ref = solver.solve(lambda a, b: cs_ccsd.residual(Bbar, fbar, a, b),
+                           lambda a, b: cs_ccsd.energy(Bbar, fbar, a, b), eps, g1, g2, maxiter=600,
+                           tol_rnorm=1e-11)
+        assert ref["converged"]
+        assert abs(m["e_corr"] - ref["E"]) <= 2e-8
+        assert abs(m["e_ref"] - ascc.reference_energy(Bbar, fbar, o)) <= 1e-10
+    for k in range(3):  # the ground-state requests of the mix still match their own oracle
+        o, B, eps = reqs[k]
+        assert mixed[k]["status"] == 0 and mixed[k]["hole"] == -1
+        assert abs(mixed[k]["e_ref"] - ascc.reference_energy(B, eps, o)) <= 1e-10

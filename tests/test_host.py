@@ -35,7 +35,8 @@ def test_binding_covers_the_abi():
         if name in ("ascc_ints_free", "ascc_diis_free", "ascc_ints_shape"):
             continue  # owned by the Ints / Diis wrappers
         if name.startswith("ascc_server_"):
-            method = {"create": "__init__", "free": "close"}.get(name[len("ascc_server_"):], name[len("ascc_server_"):])
+            method = {"create": "__init__", "free": "close", "submit_state": "submit"}.get(
+                name[len("ascc_server_"):], name[len("ascc_server_"):])
             assert hasattr(P.Server, method), name
             continue
         assert hasattr(P, name), name
