@@ -218,7 +218,7 @@ def serve_requests(nreq: int):
 
 
 def run_serving(P, arrivals, reqs, precision: int, budget: int, max_active: int, tol_rnorm: float,
-                lowp_rnorm: float = 1e-5):
+                lowp_rnorm: float = 1e-5, states=()):
     srv = P.Server(budget, max_active=max_active, precision=precision, vvvv_mode=P.ASCC_VVVV_PACKED,
                    use_graphs=True, tol_rnorm=tol_rnorm, maxiter=150, lowp_rnorm=lowp_rnorm)
     n = len(reqs)
@@ -230,7 +230,10 @@ def run_serving(P, arrivals, reqs, precision: int, budget: int, max_active: int,
         now = time.perf_counter() - t0
         while nxt < n and arrivals[nxt] <= now:
             o, B, eps = reqs[nxt]
-            ids.append(srv.submit(B, eps, o, float(arrivals[nxt])))
+            if nxt in states:  # the HOMO -> LUMO ASCC state of this request's system
+                ids.append(srv.submit(B, eps, o, float(arrivals[nxt]), hole=o - 1, particle=o))
+            else:
+                ids.append(srv.submit(B, eps, o, float(arrivals[nxt])))
             nxt += 1
         q, r, d = srv.step(now)
         if now - last_print > 15.0:
@@ -247,8 +250,15 @@ def run_serving(P, arrivals, reqs, precision: int, budget: int, max_active: int,
     lat = np.array([x["t_done"] - x["t_submit"] for x in infos])
     done = max(x["t_done"] for x in infos)
     ok = sum(1 for x in infos if x["status"] == 0)
+    st = [x for x in infos if x["hole"] >= 0]
+    extra = {}
+    if st:
+        lst = np.array([x["t_done"] - x["t_submit"] for x in st])
+        extra = dict(states=len(st), states_converged=sum(1 for x in st if x["status"] == 0),
+                     states_p50_s=float(np.percentile(lst, 50)), states_p99_s=float(np.percentile(lst, 99)),
+                     states_mean_iterations=float(np.mean([x["iterations"] for x in st])))
     return dict(solves_per_s=n / (done - float(arrivals[0])), p50_s=float(np.percentile(lat, 50)),
-                p99_s=float(np.percentile(lat, 99)), converged=ok, n=n,
+                p99_s=float(np.percentile(lat, 99)), converged=ok, n=n, **extra,
                 mean_iterations=float(np.mean([x["iterations"] for x in infos])),
                 mean_lowp_iterations=float(np.mean([x["lowp_iterations"] for x in infos])),
                 energies=[x["e_corr"] for x in infos])
@@ -260,19 +270,22 @@ def serve_main(args):
     import paper_2501_10515_amd as P
 
     arrivals, reqs = serve_requests(args.requests)
+    # --serve-states F: every request k with k % round(1/F) == 0 asks for its HOMO -> LUMO ASCC state
+    states = set(range(0, args.requests, max(1, round(1.0 / args.serve_states)))) if args.serve_states > 0 else set()
     budget = int(args.budget_gb * (1 << 30))
     out = {"metric": "served solves/s (continuous batching, Poisson arrivals 20 req/s)", "unit": "solves/s",
            "n_gpus": 1, "data": "synthetic", "dtype": "f64",
            "config": {"workload": f"serve{args.requests}", "arrival_rate_per_s": 20, "no": "U{4..24}",
                       "nv": "9 no", "naux": "3 (no + nv)", "seeds": f"100..{99 + args.requests}",
                       "generator": "converging", "hbm_budget_gb": args.budget_gb, "max_active": args.max_active,
-                      "tol_rnorm": args.serve_tol, "lowp_rnorm": args.lowp_rnorm, "vvvv": "packed"}}
+                      "tol_rnorm": args.serve_tol, "lowp_rnorm": args.lowp_rnorm, "vvvv": "packed",
+                      "excited_state_requests": len(states)}}
     res = {}
     for name, pc in (("bf16x3_refined", P.ASCC_PREC_BF16X3), ("fp32_refined", P.ASCC_PREC_FP32),
                      ("fp64", P.ASCC_PREC_FP64)):
         if args.serve_precisions and name.split("_")[0] not in args.serve_precisions.split(","):
             continue
-        r = run_serving(P, arrivals, reqs, pc, budget, args.max_active, args.serve_tol, args.lowp_rnorm)
+        r = run_serving(P, arrivals, reqs, pc, budget, args.max_active, args.serve_tol, args.lowp_rnorm, states)
         res[name] = r
         print(f"serving mode {name}: {r['solves_per_s']:.3f} solves/s", file=sys.stderr, flush=True)
     base = res.get("fp64")
@@ -476,6 +489,8 @@ def main():
     ap.add_argument("--max-active", type=int, default=32)
     ap.add_argument("--serve-tol", type=float, default=1e-7)
     ap.add_argument("--serve-precisions", default="", help="comma list of fp64,fp32,bf16x3 (default all)")
+    ap.add_argument("--serve-states", type=float, default=0.0,
+                    help="fraction of requests that ask for an ASCC excited state (HOMO -> LUMO) instead")
     ap.add_argument("--solve", action="store_true", help="precision study: full solves of --workload per mode")
     ap.add_argument("--ascc", default="", help="with --solve: an ASCC 1-CSF state, 'hole,particle' (orbital "
                     "indices) or 'homo-lumo', solved on its transformed Hamiltonian from T^P(0)")
