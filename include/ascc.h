@@ -330,7 +330,9 @@ int ascc_set_plascc(ascc_ints* ints, int hole, int particle);
  * hole orbital's sign flipped (S -> -S, s_sign = -1), for (1 - beta)/beta = -alpha.  Both are solved
  * (ascc_build_ints_hbar, ascc_initial_guess with beta s and gamma, ascc_solve) one after the other,
  * each on an integral set that is freed before the next is built; the reported energy is the mean
- * of the two total energies.  For alpha = 0 both have beta = 1.
+ * of the two total energies.  For alpha = 0 both have beta = 1.  When only one of the two
+ * converges, its energy alone is reported (Sec. III.A: the paper keeps the single converged
+ * solution); when neither does, the state has no energy (ASCC_E_NOT_CONVERGED).
  *   d_B, d_fock, fock_is_diag, no, nv, naux, precision, vvvv_mode, hole, particle: as for
  *             ascc_build_ints_hbar; opts: as for ascc_solve (its low-precision hand-over applies
  *             to both solves).
@@ -338,12 +340,13 @@ int ascc_set_plascc(ascc_ints* ints, int hole, int particle);
  *             amplitudes of the two solves ([0]: s = +1, [1]: s = -1).
  *   res       host struct (written).
  * Synchronises `stream`.  Errors: as the calls above; ASCC_E_ARG for |alpha| >= 1;
- * ASCC_E_NOT_CONVERGED if either solve does not converge (res still written). */
+ * ASCC_E_NOT_CONVERGED if neither solve converges (res still written). */
 typedef struct ascc_two_ansatz_result {
   double e_total[2];  /* total energies: [0] s = +1, beta = 1/(1 + alpha); [1] s = -1, beta = 1/(1 - alpha) */
-  double e_mean;      /* their mean: the reported ASCC energy                                           */
+  double e_mean;      /* the reported ASCC energy: the mean of the converged solves' total energies     */
   double beta[2];
   ascc_result solve[2];
+  int used;           /* which solves e_mean averages: bit 0 = [0], bit 1 = [1] (0: neither converged)  */
 } ascc_two_ansatz_result;
 int ascc_two_ansatz(const double* d_B, const double* d_fock, int fock_is_diag, int no, int nv, int naux, int precision,
                     int vvvv_mode, int hole, int particle, double alpha, const ascc_opts* opts, double* const* d_t1,

@@ -109,12 +109,16 @@ def solve_state(B, fock, no, hole, particle, beta=1.0, sign=1.0, tol_rnorm=1e-10
 
 def two_ansatz(B, fock, no, hole, particle, alpha, **kw):
     """The two ansatz choices for the Aufbau coefficient alpha: S as defined with beta = 1/(1 + alpha),
-    and the hole sign flipped (S -> -S) with beta = 1/(1 - alpha); and the mean of their total energies."""
+    and the hole sign flipped (S -> -S) with beta = 1/(1 - alpha).  The state's energy (Sec. III.A):
+    the mean of the two total energies, the converged one alone if the other solve fails, none
+    (converged False) if both fail."""
     b_plus, b_minus = two_ansatz_betas(alpha)
     plus = solve_state(B, fock, no, hole, particle, beta=b_plus, sign=1.0, **kw)
     minus = solve_state(B, fock, no, hole, particle, beta=b_minus, sign=-1.0, **kw)
-    return dict(plus=plus, minus=minus, E=0.5 * (plus["E"] + minus["E"]),
-                converged=plus["converged"] and minus["converged"])
+    done = [r for r in (plus, minus) if r["converged"]]
+    E = sum(r["E"] for r in done) / len(done) if done else 0.5 * (plus["E"] + minus["E"])
+    return dict(plus=plus, minus=minus, E=E, converged=len(done) == 2, any_converged=bool(done),
+                used=(1 if plus["converged"] else 0) | (2 if minus["converged"] else 0))
 
 
 def reference_energy(B: np.ndarray, fock: np.ndarray, no: int) -> float:

@@ -64,7 +64,7 @@ class Result(ctypes.Structure):
 
 class TwoAnsatzResult(ctypes.Structure):
     _fields_ = [("e_total", ctypes.c_double * 2), ("e_mean", ctypes.c_double), ("beta", ctypes.c_double * 2),
-                ("solve", Result * 2)]
+                ("solve", Result * 2), ("used", ctypes.c_int)]
 
 
 EXPORTS = ("ascc_workspace_bytes", "ascc_build_ints", "ascc_residual", "ascc_diis_create", "ascc_diis_reset",
@@ -300,6 +300,7 @@ def ascc_two_ansatz(B: torch.Tensor, fock: torch.Tensor, no: int, hole: int, par
                                         ctypes.c_double(alpha), ctypes.byref(opts), p1, p2, ctypes.byref(res),
                                         _stream(stream))
     out = dict(e_total=[res.e_total[0], res.e_total[1]], e_mean=res.e_mean, beta=[res.beta[0], res.beta[1]],
+               used=res.used,
                solves=[dict(e_corr=r.e_corr, rnorm=r.rnorm, iterations=r.iterations, converged=bool(r.converged),
                             lowp_iterations=r.lowp_iterations) for r in res.solve], status=rc)
     if rc != ASCC_OK and not (rc == ASCC_E_NOT_CONVERGED and not raise_on_not_converged):

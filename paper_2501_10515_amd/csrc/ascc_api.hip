@@ -1761,9 +1761,19 @@ int ascc_two_ansatz(const double* d_B, const double* d_fock, int fock_is_diag, i
     }
     res->e_total[k] = e0 + res->solve[k].e_corr;
   }
-  res->e_mean = 0.5 * (res->e_total[0] + res->e_total[1]);
-  if (status) set_error("a two-ansatz solve did not converge in maxiter iterations");
-  return status;
+  // the paper's rule for a state: the mean of the two solutions, the single converged one when the
+  // other fails, and no energy when neither converges
+  res->used = (res->solve[0].converged ? 1 : 0) | (res->solve[1].converged ? 2 : 0);
+  if (res->used == 3 || res->used == 0)
+    res->e_mean = 0.5 * (res->e_total[0] + res->e_total[1]);
+  else
+    res->e_mean = res->e_total[res->used == 1 ? 0 : 1];
+  (void)status;
+  if (res->used == 0) {
+    set_error("neither two-ansatz solve converged in maxiter iterations");
+    return ASCC_E_NOT_CONVERGED;
+  }
+  return ASCC_OK;
 }
 
 }  // extern "C"

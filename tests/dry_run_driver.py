@@ -29,7 +29,7 @@ class Result(ctypes.Structure):
 
 class TwoAnsatzResult(ctypes.Structure):
     _fields_ = [("e_total", ctypes.c_double * 2), ("e_mean", ctypes.c_double), ("beta", ctypes.c_double * 2),
-                ("solve", Result * 2)]
+                ("solve", Result * 2), ("used", ctypes.c_int)]
 
 
 def main(shapes):

@@ -254,3 +254,23 @@ def test_mixed_solve_ends_on_an_fp64_residual_under_the_paper_test(P):
     assert max(np.abs(r1).max(), np.abs(r2).max()) <= 1e-5
     assert abs(e - res["e_corr"]) < 1e-12
     assert abs(res["rmax"] - max(np.abs(r1).max(), np.abs(r2).max())) < 1e-12
+
+
+def test_two_ansatz_reports_the_single_converged_solution(P):
+    import torch
+
+    o, v, Q, seed, hole, particle = 3, 12, 36, 7, 2, 3
+    B, eps = make_system(o, v, Q, seed, sigma=converging_sigma(v, Q))
+    dB, deps = torch.from_numpy(B).cuda(), torch.from_numpy(eps).cuda()
+    t1s = [torch.empty((o, v), dtype=torch.float64, device="cuda") for _ in range(2)]
+    t2s = [torch.empty((o, o, v, v), dtype=torch.float64, device="cuda") for _ in range(2)]
+    full = P.ascc_two_ansatz(dB, deps, o, hole, particle, 0.1, t1s, t2s, tol_rnorm=1e-8, maxiter=400)
+    its = [s["iterations"] for s in full["solves"]]
+    assert full["used"] == 3 and its[0] != its[1]
+    cap = min(its)
+    r = P.ascc_two_ansatz(dB, deps, o, hole, particle, 0.1, t1s, t2s, tol_rnorm=1e-8, maxiter=cap)
+    k = its.index(cap)
+    assert r["status"] == 0 and r["used"] == 1 << k
+    assert r["e_mean"] == r["e_total"][k]
+    with pytest.raises(P.AsccError):
+        P.ascc_two_ansatz(dB, deps, o, hole, particle, 0.1, t1s, t2s, tol_rnorm=1e-8, maxiter=3)

@@ -193,3 +193,20 @@ def test_two_electron_two_ansatz_energies_are_eigenvalues(alpha):
         assert np.abs(ev - r[key]["E"]).min() < 1e-9
         assert r[key]["E"] - ev.min() > 1e-3
     assert r["E"] == pytest.approx(0.5 * (r["plus"]["E"] + r["minus"]["E"]))
+
+
+def test_two_ansatz_keeps_the_single_converged_solution():
+    """Sec. III.A: when one of the two solves fails, its partner's energy is reported alone."""
+    o, v, Q, seed, hole, particle = 3, 12, 36, 7, 2, 3
+    B, eps = make_system(o, v, Q, seed, sigma=converging_sigma(v, Q))
+    full = ascc.two_ansatz(B, eps, o, hole, particle, 0.1)
+    n_plus, n_minus = full["plus"]["iterations"], full["minus"]["iterations"]
+    assert full["converged"] and n_plus != n_minus
+    cap = min(n_plus, n_minus)  # only the faster solve finishes
+    r = ascc.two_ansatz(B, eps, o, hole, particle, 0.1, maxiter=cap)
+    faster = "plus" if n_plus < n_minus else "minus"
+    assert r["any_converged"] and not r["converged"]
+    assert r["used"] == (1 if faster == "plus" else 2)
+    assert r["E"] == r[faster]["E"]
+    none = ascc.two_ansatz(B, eps, o, hole, particle, 0.1, maxiter=3)
+    assert not none["any_converged"] and none["used"] == 0
