@@ -226,6 +226,9 @@ typedef struct ascc_result {
   int iterations;  /* residual evaluations made                             */
   int converged;   /* 1 if every requested test passed                      */
   int lowp_iterations; /* of which in low precision                         */
+  int stalled;     /* not converged, but near it: the last energy change below the energy test
+                      (tol_de, or 1e-7 Eh when tol_de is unused) and each residual test missed by
+                      less than a factor 10 -- the paper keeps such states, marked (Sec. III.A) */
 } ascc_result;
 
 /* Iterate residual -> convergence test -> update from the amplitudes in (d_t1, d_t2)
@@ -234,7 +237,8 @@ typedef struct ascc_result {
  * read the 8-double statistics block.  On return (t1, t2) hold the amplitudes the reported
  * energy and residual norms belong to.
  * Errors: ASCC_E_ARG, ASCC_E_NOMEM, ASCC_E_HIP, ASCC_E_NONFINITE (res filled up to the
- * failing iteration), ASCC_E_NOT_CONVERGED (res and amplitudes are the last iterate). */
+ * failing iteration), ASCC_E_NOT_CONVERGED (res and amplitudes are the last iterate;
+ * res->stalled marks a solve that stopped near convergence). */
 int ascc_solve(ascc_ints* ints, const ascc_opts* opts, double* d_t1, double* d_t2, ascc_result* res,
                void* stream);
 
@@ -330,9 +334,10 @@ int ascc_set_plascc(ascc_ints* ints, int hole, int particle);
  * hole orbital's sign flipped (S -> -S, s_sign = -1), for (1 - beta)/beta = -alpha.  Both are solved
  * (ascc_build_ints_hbar, ascc_initial_guess with beta s and gamma, ascc_solve) one after the other,
  * each on an integral set that is freed before the next is built; the reported energy is the mean
- * of the two total energies.  For alpha = 0 both have beta = 1.  When only one of the two
- * converges, its energy alone is reported (Sec. III.A: the paper keeps the single converged
- * solution); when neither does, the state has no energy (ASCC_E_NOT_CONVERGED).
+ * of the two total energies.  For alpha = 0 both have beta = 1.  A solve counts when it converged
+ * or stalled near convergence (ascc_result.stalled); when only one of the two counts, its energy
+ * alone is reported (Sec. III.A: the paper keeps the single converged solution, and stalled
+ * states marked); when neither does, the state has no energy (ASCC_E_NOT_CONVERGED).
  *   d_B, d_fock, fock_is_diag, no, nv, naux, precision, vvvv_mode, hole, particle: as for
  *             ascc_build_ints_hbar; opts: as for ascc_solve (its low-precision hand-over applies
  *             to both solves).

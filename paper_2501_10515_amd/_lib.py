@@ -59,7 +59,7 @@ class RequestInfo(ctypes.Structure):
 class Result(ctypes.Structure):
     _fields_ = [("e_corr", ctypes.c_double), ("rnorm", ctypes.c_double), ("rmax", ctypes.c_double),
                 ("de", ctypes.c_double), ("iterations", ctypes.c_int), ("converged", ctypes.c_int),
-                ("lowp_iterations", ctypes.c_int)]
+                ("lowp_iterations", ctypes.c_int), ("stalled", ctypes.c_int)]
 
 
 class TwoAnsatzResult(ctypes.Structure):
@@ -302,7 +302,8 @@ def ascc_two_ansatz(B: torch.Tensor, fock: torch.Tensor, no: int, hole: int, par
     out = dict(e_total=[res.e_total[0], res.e_total[1]], e_mean=res.e_mean, beta=[res.beta[0], res.beta[1]],
                used=res.used,
                solves=[dict(e_corr=r.e_corr, rnorm=r.rnorm, iterations=r.iterations, converged=bool(r.converged),
-                            lowp_iterations=r.lowp_iterations) for r in res.solve], status=rc)
+                            lowp_iterations=r.lowp_iterations, stalled=bool(r.stalled)) for r in res.solve],
+               status=rc)
     if rc != ASCC_OK and not (rc == ASCC_E_NOT_CONVERGED and not raise_on_not_converged):
         raise AsccError(rc, ascc_last_error())
     return out
@@ -353,7 +354,8 @@ def ascc_solve(ints: Ints, t1, t2, tol_rnorm=1e-8, tol_rmax=0.0, tol_de=0.0, max
     rc = load_library().ascc_solve(ints.handle, ctypes.byref(opts), _dev(t1, "t1", (o, v)),
                                    _dev(t2, "t2", (o, o, v, v)), ctypes.byref(res), _stream(stream))
     out = dict(e_corr=res.e_corr, rnorm=res.rnorm, rmax=res.rmax, de=res.de, iterations=res.iterations,
-               converged=bool(res.converged), lowp_iterations=res.lowp_iterations, status=rc)
+               converged=bool(res.converged), lowp_iterations=res.lowp_iterations, stalled=bool(res.stalled),
+               status=rc)
     if rc != ASCC_OK and not (rc == ASCC_E_NOT_CONVERGED and not raise_on_not_converged):
         raise AsccError(rc, ascc_last_error())
     return out

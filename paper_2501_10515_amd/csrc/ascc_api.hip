@@ -1725,7 +1725,15 @@ int ascc_solve(ascc_ints* I, const ascc_opts* opts, double* t1, double* t2, ascc
   free_all(work);
   ascc_diis_free(D);
   if (rc) return rc;
-  if (status == ASCC_E_NOT_CONVERGED) set_error("not converged in maxiter iterations");
+  if (status == ASCC_E_NOT_CONVERGED) {
+    // near convergence: the energy no longer moves at the energy test's precision and every
+    // residual test is missed by less than a factor 10
+    const double tde = opts->tol_de > 0 ? opts->tol_de : 1e-7;
+    res->stalled = res->iterations > 1 && std::fabs(res->de) < tde &&
+                   (opts->tol_rnorm <= 0 || res->rnorm <= 10.0 * opts->tol_rnorm) &&
+                   (opts->tol_rmax <= 0 || res->rmax <= 10.0 * opts->tol_rmax);
+    set_error(res->stalled ? "stalled near convergence in maxiter iterations" : "not converged in maxiter iterations");
+  }
   return status;
 }
 
@@ -1763,14 +1771,15 @@ int ascc_two_ansatz(const double* d_B, const double* d_fock, int fock_is_diag, i
   }
   // the paper's rule for a state: the mean of the two solutions, the single converged one when the
   // other fails, and no energy when neither converges
-  res->used = (res->solve[0].converged ? 1 : 0) | (res->solve[1].converged ? 2 : 0);
+  auto counts = [](const ascc_result& r) { return r.converged || r.stalled; };
+  res->used = (counts(res->solve[0]) ? 1 : 0) | (counts(res->solve[1]) ? 2 : 0);
   if (res->used == 3 || res->used == 0)
     res->e_mean = 0.5 * (res->e_total[0] + res->e_total[1]);
   else
     res->e_mean = res->e_total[res->used == 1 ? 0 : 1];
   (void)status;
   if (res->used == 0) {
-    set_error("neither two-ansatz solve converged in maxiter iterations");
+    set_error("neither two-ansatz solve converged (or stalled near convergence) in maxiter iterations");
     return ASCC_E_NOT_CONVERGED;
   }
   return ASCC_OK;

@@ -24,7 +24,7 @@ class Opts(ctypes.Structure):
 class Result(ctypes.Structure):
     _fields_ = [("e_corr", ctypes.c_double), ("rnorm", ctypes.c_double), ("rmax", ctypes.c_double),
                 ("de", ctypes.c_double), ("iterations", ctypes.c_int), ("converged", ctypes.c_int),
-                ("lowp_iterations", ctypes.c_int)]
+                ("lowp_iterations", ctypes.c_int), ("stalled", ctypes.c_int)]
 
 
 class TwoAnsatzResult(ctypes.Structure):

@@ -274,3 +274,31 @@ def test_two_ansatz_reports_the_single_converged_solution(P):
     assert r["e_mean"] == r["e_total"][k]
     with pytest.raises(P.AsccError):
         P.ascc_two_ansatz(dB, deps, o, hole, particle, 0.1, t1s, t2s, tol_rnorm=1e-8, maxiter=3)
+
+
+def test_solve_marks_a_stall_near_convergence(P):
+    """A solve stopped by maxiter near its test (energy change below 1e-7 Eh, residual within a factor
+    10 of the test) is marked stalled, as the paper marks such states (Sec. III.A)."""
+    import torch
+
+    o, v, Q = 5, 20, 60
+    B, eps = make_system(o, v, Q, 0, sigma=converging_sigma(v, Q))
+    dB, deps = torch.from_numpy(B).cuda(), torch.from_numpy(eps).cuda()
+    ints = P.ascc_build_ints(dB, deps, o)
+    t1 = torch.zeros((o, v), dtype=torch.float64, device="cuda")
+    t2 = torch.zeros((o, o, v, v), dtype=torch.float64, device="cuda")
+    ref = P.ascc_solve(ints, t1, t2, tol_rnorm=1e-8, maxiter=100)
+    n, r_n = ref["iterations"], ref["rnorm"]
+    seen = set()
+    for cap in (n, n - 2, 3):
+        tol = r_n / 5.0  # out of reach within n iterations
+        t1.zero_()
+        t2.zero_()
+        res = P.ascc_solve(ints, t1, t2, tol_rnorm=tol, maxiter=cap, raise_on_not_converged=False)
+        print(cap, res, flush=True)
+        assert not res["converged"]
+        expect = abs(res["de"]) < 1e-7 and res["rnorm"] <= 10.0 * tol
+        assert res["stalled"] == expect
+        seen.add(res["stalled"])
+    ints.close()
+    assert seen == {True, False}
