@@ -285,11 +285,15 @@ int ascc_server_submit(ascc_server* srv, const double* h_B, const double* h_eps,
                        double t_submit, int* id);
 /* Queue an ASCC 1-CSF excited-state request (Sec. II.A): its integral set is Hbar of the state
  * (hole, particle, s_sign as for ascc_build_ints_hbar) and its amplitudes start from T^P(0) =
- * beta s S - (beta^2 / 2) S^2 (ascc_initial_guess; beta = 1 is Eq. (eqn:TP-guess)); otherwise it is
- * served exactly like a ground-state request, with the same footprint.
- * Errors: as ascc_server_submit; ASCC_E_ARG for a hole or particle out of range or s_sign not +-1. */
+ * beta s S - (beta^2 / 2) S^2 (ascc_initial_guess; beta = 1 is Eq. (eqn:TP-guess)); with plascc = 1 its
+ * residuals leave out the terms quadratic in the mixed doubles (ascc_set_plascc, whose small
+ * work buffers are allocated at admission outside the slab); otherwise it is served exactly like a
+ * ground-state request, with the same footprint.  Both ansatz of Sec. II.D are two requests
+ * (s_sign = +1 and -1 with their beta).
+ * Errors: as ascc_server_submit; ASCC_E_ARG for a hole or particle out of range, s_sign not +-1 or
+ * beta <= 0. */
 int ascc_server_submit_state(ascc_server* srv, const double* h_B, const double* h_eps, int no, int nv, int naux,
-                             int hole, int particle, int s_sign, double beta, double t_submit, int* id);
+                             int hole, int particle, int s_sign, double beta, int plascc, double t_submit, int* id);
 /* Retire finished requests, admit queued ones, launch the next iterations; `now` is the caller's
  * clock, recorded as admission / completion times.  Errors: ASCC_E_ARG, ASCC_E_HIP. */
 int ascc_server_step(ascc_server* srv, double now, int* n_queued, int* n_running, int* n_done);

@@ -104,8 +104,8 @@ def load_library():
     L.ascc_solve.argtypes = [vp, ctypes.POINTER(Opts), vp, vp, ctypes.POINTER(Result), vp]
     L.ascc_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]
     L.ascc_server_submit.argtypes = [vp, vp, vp, c_int, c_int, c_int, c_double, ctypes.POINTER(c_int)]
-    L.ascc_server_submit_state.argtypes = [vp, vp, vp, c_int, c_int, c_int, c_int, c_int, c_int, c_double, c_double,
-                                           ctypes.POINTER(c_int)]
+    L.ascc_server_submit_state.argtypes = [vp, vp, vp, c_int, c_int, c_int, c_int, c_int, c_int, c_double, c_int,
+                                           c_double, ctypes.POINTER(c_int)]
     L.ascc_server_step.argtypes = [vp, c_double, ctypes.POINTER(c_int), ctypes.POINTER(c_int), ctypes.POINTER(c_int)]
     L.ascc_server_info.argtypes = [vp, c_int, ctypes.POINTER(RequestInfo)]
     L.ascc_server_free.argtypes = [vp]
@@ -455,8 +455,9 @@ class Server:
         self.handle = h
 
     def submit(self, B, eps, no: int, t_submit: float, hole: int = -1, particle: int = -1, s_sign: int = 1,
-               beta: float = 1.0) -> int:
-        """Queue a ground-state request, or (hole >= 0) the 1-CSF ASCC state hole -> particle."""
+               beta: float = 1.0, plascc: bool = False) -> int:
+        """Queue a ground-state request, or (hole >= 0) the 1-CSF ASCC state hole -> particle (PLASCC
+        equations with plascc)."""
         import numpy as np
 
         B = np.ascontiguousarray(B, dtype=np.float64)
@@ -469,8 +470,8 @@ class Server:
                                                      ctypes.c_double(t_submit), ctypes.byref(rid)))
         else:
             _check(load_library().ascc_server_submit_state(self.handle, pB, pe, no, n - no, naux, hole, particle,
-                                                           s_sign, ctypes.c_double(beta), ctypes.c_double(t_submit),
-                                                           ctypes.byref(rid)))
+                                                           s_sign, ctypes.c_double(beta), 1 if plascc else 0,
+                                                           ctypes.c_double(t_submit), ctypes.byref(rid)))
         return rid.value
 
     def step(self, now: float):

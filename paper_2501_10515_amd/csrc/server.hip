@@ -52,6 +52,7 @@ struct Request {
   double e_corr = 0, rnorm = 0, rmax = 0, de = 0;
   int hole = -1, particle = -1, s_sign = 1;  // a 1-CSF state (hole >= 0) or the ground state
   double beta = 1.0, e_ref = 0.0;
+  bool plascc = false;
 };
 
 }  // namespace
@@ -221,6 +222,7 @@ int admit(ascc_server* S, Request* R, double now) {
   rc = ascc_diis_create_ws(R->ints, S->opts.solve.diis_size, S->opts.solve.diis_start, diis_ws, R->diis_bytes,
                            &R->diis);
   if (rc) return rc;
+  if (R->plascc && (rc = ascc_set_plascc(R->ints, R->hole, R->particle))) return rc;
   if (R->hole >= 0) {  // T^P(0) of the state
     if ((rc = ascc_initial_guess(R->t1, R->t2, R->o, R->v, R->hole, R->particle, R->s_sign * R->beta,
                                  -0.5 * R->beta * R->beta, s)))
@@ -330,7 +332,8 @@ int ascc_server_create(const ascc_server_opts* opts, ascc_server** out) {
 }
 
 int ascc_server_submit_state(ascc_server* S, const double* h_B, const double* h_eps, int no, int nv, int naux,
-                             int hole, int particle, int s_sign, double beta, double t_submit, int* id) {
+                             int hole, int particle, int s_sign, double beta, int plascc, double t_submit,
+                             int* id) {
   if (hole < 0 || hole >= no || particle < no || particle >= no + nv)
     return sfail(ASCC_E_ARG, "hole must be an occupied and particle a virtual orbital index");
   if (s_sign != 1 && s_sign != -1) return sfail(ASCC_E_ARG, "s_sign must be +1 or -1");
@@ -342,6 +345,7 @@ int ascc_server_submit_state(ascc_server* S, const double* h_B, const double* h_
   R->particle = particle;
   R->s_sign = s_sign;
   R->beta = beta;
+  R->plascc = plascc != 0;
   return ASCC_OK;
 }
 

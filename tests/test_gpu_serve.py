@@ -43,8 +43,9 @@ def _serve(P, reqs, order, precision, gap=0.0, graphs=True, budget=2 << 30, max_
         while pending and now >= gap * len(ids):
             k = pending.pop(0)
             o, B, eps = reqs[k][:3]
-            state = reqs[k][3] if len(reqs[k]) > 3 else (-1, -1)  # (hole, particle) of a 1-CSF state
-            ids[k] = srv.submit(B, eps, o, now, hole=state[0], particle=state[1])
+            state = reqs[k][3] if len(reqs[k]) > 3 else (-1, -1)  # (hole, particle[, plascc]) of a 1-CSF state
+            ids[k] = srv.submit(B, eps, o, now, hole=state[0], particle=state[1],
+                                plascc=len(state) > 2 and state[2])
         q, r, d = srv.step(now)
         if not pending and d == len(order):
             break
@@ -129,3 +130,24 @@ def test_served_excited_states_alone_equal_mixed_and_oracle(P, prec):
         o, B, eps = reqs[k]
         assert mixed[k]["status"] == 0 and mixed[k]["hole"] == -1
         assert abs(mixed[k]["e_ref"] - ascc.reference_energy(B, eps, o)) <= 1e-10
+
+
+def test_served_plascc_state_matches_oracle(P):
+    """A PLASCC state request (Sec. II.C) among ASCC and ground-state requests."""
+    from oracle import ascc, plascc, solver
+
+    o, v, Q, seed, hole, particle = 3, 12, 36, 7, 2, 3
+    B, eps = make_system(o, v, Q, seed, sigma=converging_sigma(v, Q))
+    reqs = _requests()[:2] + [(o, B, eps, (hole, particle)), (o, B, eps, (hole, particle, True))]
+    res = _serve(P, reqs, [0, 1, 2, 3], P.ASCC_PREC_FP64, tol_rnorm=1e-8, maxiter=400)
+    assert all(r["status"] == 0 for r in res.values())
+    Bbar, fbar = ascc.transformed_inputs(B, eps, o, hole, particle)
+    g1, g2 = ascc.initial_guess(o, v, hole, particle)
+    ref = solver.solve(lambda a, b: plascc.residual(Bbar, fbar, a, b, hole, particle),
+                       lambda a, b: plascc.energy(Bbar, fbar, a, b), eps, g1, g2, maxiter=600, tol_rnorm=1e-11)
+    assert ref["converged"]
+    print(res[3]["e_corr"], ref["E"], res[2]["e_corr"], flush=True)
+    assert abs(res[3]["e_corr"] - ref["E"]) <= 2e-8
+    assert abs(res[3]["e_corr"] - res[2]["e_corr"]) > 1e-4  # PLASCC differs from ASCC
+    alone = _serve(P, reqs, [3], P.ASCC_PREC_FP64, tol_rnorm=1e-8, maxiter=400)[3]
+    assert alone["iterations"] == res[3]["iterations"] and alone["e_corr"] == res[3]["e_corr"]
