@@ -1286,10 +1286,13 @@ int ascc_set_plascc(ascc_ints* I, int hole, int particle) {
     int rc = ASCC_OK;
     for (const auto& item : plan)
       if (!rc) rc = dalloc(I->pl, &(I->*(item.first)), (size_t)item.second);
-    // padding columns that products read but never write (plW) must hold zeros: clear them all
+    // padding columns that products read but never write (plW) must hold zeros: clear them all,
+    // and wait for the clears, so that work on any stream (non-blocking ones too) sees zeros
     for (const auto& item : plan)
       if (!rc && !dry_run() && hipMemset(I->*(item.first), 0, sizeof(double) * item.second) != hipSuccess)
         rc = fail(ASCC_E_HIP, "clearing the PLASCC buffers failed");
+    if (!rc && !dry_run() && hipStreamSynchronize(nullptr) != hipSuccess)
+      rc = fail(ASCC_E_HIP, "clearing the PLASCC buffers failed");
     if (rc) {
       free_all(I->pl);
       I->pl = Pool();
