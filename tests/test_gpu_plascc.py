@@ -183,3 +183,40 @@ def test_plascc_excited_and_ground_solves_match_oracle(P, o, v, Q, seed, hole, p
     assert abs(rg["e_corr"] - ref_g["E"]) <= 2e-8
     omega_ref = (ascc.reference_energy(Bbar, fbar, o) + ref_x["E"]) - (ascc.reference_energy(B, f, o) + ref_g["E"])
     assert abs((ex - eg) - omega_ref) <= 4e-8
+
+
+@pytest.mark.slow
+def test_ascc_and_plascc_residuals_at_full_size(P):
+    """The o20 v180 Q600 workload with the full vvvv block, state 19 -> 20 (HOMO -> LUMO): the
+    Hbar residual and the PLASCC residual against the oracle.  The crosses have m = o + v - 1 = 199
+    rows, so every cross slab of the removal spans more than one tile."""
+    import torch
+
+    from oracle import ascc, cs_ccsd, plascc
+
+    from .gpu_util import dev, gpu_residual
+
+    o, v, Q, hole, particle = 20, 180, 600, 19, 20
+    B, eps = make_system(o, v, Q, 1, sigma=converging_sigma(v, Q))
+    Bbar, fbar = ascc.transformed_inputs(B, eps, o, hole, particle)
+    t1, t2 = random_amplitudes(o, v, 79, 0.01, 0.01)
+    g1, g2 = ascc.initial_guess(o, v, hole, particle)
+    t1, t2 = t1 + g1, t2 + g2
+    ints = P.ascc_build_ints_hbar(dev(B), dev(eps), o, hole, particle, vvvv_mode=P.ASCC_VVVV_FULL)
+    a1, a2, ea = gpu_residual(P, ints, t1, t2)
+    P.ascc_set_plascc(ints, hole, particle)
+    p1, p2, ep = gpu_residual(P, ints, t1, t2)
+    ints.close()
+    torch.cuda.empty_cache()
+    print("GPU residuals done; oracle ...", flush=True)
+    r1_ref, r2_ref = cs_ccsd.residual(Bbar, fbar, t1, t2)
+    e_ref = cs_ccsd.energy(Bbar, fbar, t1, t2)
+    scale = max(1.0, np.abs(r2_ref).max())
+    assert np.abs(a1 - r1_ref).max() <= TOL * scale
+    assert np.abs(a2 - r2_ref).max() <= TOL * scale
+    assert abs(ea - e_ref) <= TOL * max(1.0, abs(e_ref))
+    c = plascc.mixed_quadratic(Bbar, fbar, t1, t2, hole, particle)
+    print(f"max|c| = {np.abs(c).max():.3e}", flush=True)
+    assert np.abs(c).max() > 1e-6
+    assert np.array_equal(p1, a1) and ep == ea  # the singles and the energy keep every term
+    assert np.abs(p2 - (r2_ref - c)).max() <= TOL * scale
