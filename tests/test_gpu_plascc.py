@@ -220,3 +220,14 @@ def test_ascc_and_plascc_residuals_at_full_size(P):
     assert np.abs(c).max() > 1e-6
     assert np.array_equal(p1, a1) and ep == ea  # the singles and the energy keep every term
     assert np.abs(p2 - (r2_ref - c)).max() <= TOL * scale
+    # the split-BF16x3 step that the bench times beside it, within the low-precision bound
+    ints = P.ascc_build_ints_hbar(dev(B), dev(eps), o, hole, particle, precision=P.ASCC_PREC_BF16X3,
+                                  vvvv_mode=P.ASCC_VVVV_FULL)
+    P.ascc_set_plascc(ints, hole, particle)
+    q1, q2, _ = gpu_residual(P, ints, t1, t2)
+    ints.close()
+    torch.cuda.empty_cache()
+    rs = max(np.abs(r2_ref - c).max(), np.abs(r1_ref).max())
+    err = max(np.abs(q1 - r1_ref).max(), np.abs(q2 - (r2_ref - c)).max())
+    print(f"bf16x3: max|dR| = {err:.3e} (max|R| = {rs:.3e}, rel {err / rs:.2e})", flush=True)
+    assert err <= REL["bf16x3"] * rs
