@@ -302,3 +302,35 @@ def test_solve_marks_a_stall_near_convergence(P):
         seen.add(res["stalled"])
     ints.close()
     assert seen == {True, False}
+
+
+@pytest.mark.slow
+def test_second_ansatz_residual_at_full_size(P):
+    """The second ansatz (hole sign flipped, Sec. II.D) on the o20 v180 Q600 workload with the full
+    vvvv block, state 19 -> 20, from its own guess (beta = 1 / (1 - alpha) at alpha = 0.1, gamma =
+    -beta^2 / 2): residual, energy and reference energy against the oracle."""
+    import torch
+
+    from oracle import ascc, cs_ccsd
+
+    from .gpu_util import dev, gpu_residual
+
+    o, v, Q, hole, particle = 20, 180, 600, 19, 20
+    beta = ascc.two_ansatz_betas(0.1)[1]
+    B, eps = make_system(o, v, Q, 1, sigma=converging_sigma(v, Q))
+    t1, t2 = random_amplitudes(o, v, 80, 0.01, 0.01)
+    g1, g2 = ascc.initial_guess(o, v, hole, particle, beta=-beta, gamma=-0.5 * beta * beta)
+    t1, t2 = t1 + g1, t2 + g2
+    ints = P.ascc_build_ints_hbar(dev(B), dev(eps), o, hole, particle, s_sign=-1, vvvv_mode=P.ASCC_VVVV_FULL)
+    r1, r2, e = gpu_residual(P, ints, t1, t2)
+    e0 = P.ascc_reference_energy(ints)
+    ints.close()
+    torch.cuda.empty_cache()
+    print("GPU residual done; oracle ...", flush=True)
+    Bbar, fbar = ascc.transformed_inputs(B, eps, o, hole, particle, sign=-1.0)
+    r1_ref, r2_ref = cs_ccsd.residual(Bbar, fbar, t1, t2)
+    scale = max(1.0, np.abs(r2_ref).max())
+    assert np.abs(r1 - r1_ref).max() <= TOL * scale
+    assert np.abs(r2 - r2_ref).max() <= TOL * scale
+    assert abs(e - cs_ccsd.energy(Bbar, fbar, t1, t2)) <= TOL * scale
+    assert abs(e0 - ascc.reference_energy(Bbar, fbar, o)) <= TOL * max(1.0, abs(e0))
