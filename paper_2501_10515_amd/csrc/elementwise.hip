@@ -85,42 +85,66 @@ __global__ __launch_bounds__(kThreads) void permute4_tiled_kernel(P4 p, int t, i
 // low-precision ladder is not), so amplitudes that start pair-symmetric stay so.  The part of t2
 // odd under the joint (ij)(ab) swap is outside the closed-shell equations and barely damped by
 // the Jacobi step; fed by rounding, it stalls the DIIS iteration of excited (ASCC) states.
-// One workgroup per (i, j) and 32 x 32 block of (a, b): the six terms that run along a (EM[jiba],
-// RL[jiba], G1[jbia], P1[jbia], P2[jbia], P1[ibja]) are summed into an LDS tile with reads along
-// a, then the output row is written along b, where every other term is contiguous, so all reads
-// and writes are coalesced.
+// R2[ij][ab] = X(i,j,a,b) + X(j,i,b,a) with
+//   X(i,j,a,b) = EM[ijab] + (RL[ijab] + G1[iajb]) / 2 - P1[iajb] / 2 + P2[iajb] / 2 - P1[jaib].
+// One workgroup per pair i <= j and 32 x 32 blocks (A, B) of (a, b): it forms X(i,j) on A x B with
+// reads along b and X(j,i) on B x A with reads along a (every term is contiguous in the index read
+// along), keeps both tiles in LDS and writes R2[ij] on A x B and R2[ji] on B x A, so each input
+// element is read once.  For i = j only A <= B runs; with A = B both tiles are the same block and
+// the two writes of an element carry the same value.
+__device__ __forceinline__ double assemble_x(const double* __restrict__ g1, const double* __restrict__ rl,
+                                             const double* __restrict__ em, const double* __restrict__ p1,
+                                             const double* __restrict__ p2, long x, long iajb, long jaib) {
+  return 0.5 * (g1[iajb] + rl[x]) + em[x] - 0.5 * p1[iajb] + 0.5 * p2[iajb] - p1[jaib];
+}
+
 __global__ __launch_bounds__(kThreads) void assemble_r2_kernel(double* __restrict__ r2, const double* __restrict__ g1,
                                                               const double* __restrict__ rl,
                                                               const double* __restrict__ em,
                                                               const double* __restrict__ p1,
                                                               const double* __restrict__ p2, int o, int v) {
-  __shared__ double tile[32][33];
+  __shared__ double t1[32][33], t2[32][33];  // t1[a - a0][b - b0] = X(i,j,a,b), t2[b - b0][a - a0] = X(j,i,b,a)
   const int tv = (v + 31) / 32;
-  const int a0 = (blockIdx.x / tv) * 32, b0 = (blockIdx.x % tv) * 32;
-  const int i = blockIdx.y, j = blockIdx.z;
+  const int ta = blockIdx.y / tv, tb = blockIdx.y % tv;
+  // pair p = j (j + 1) / 2 + i, i <= j
+  const long p = blockIdx.x;
+  int j = (int)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
+  while ((long)j * (j + 1) / 2 > p) --j;
+  while ((long)(j + 1) * (j + 2) / 2 <= p) ++j;
+  const int i = (int)(p - (long)j * (j + 1) / 2);
+  if (i == j && ta > tb) return;
+  const int a0 = ta * 32, b0 = tb * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
-  auto ov = [&](int p, int x, int q, int y) -> long { return ((long)(p * v + x) * o + q) * v + y; };
+  auto ov = [&](int q, int x, int r, int y) -> long { return ((long)(q * v + x) * o + r) * v + y; };
   const long ij = ((long)i * o + j) * v * v, ji = ((long)j * o + i) * v * v;
+  double x1[4], x2[4];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {  // tile[b - b0][a - a0], reads along a
-    const int b = b0 + ty + 8 * k, a = a0 + tx;
-    double t = 0.0;
-    if (a < v && b < v) {
-      const long jbia = ov(j, b, i, a);
-      t = em[ji + (long)b * v + a] + 0.5 * (rl[ji + (long)b * v + a] + g1[jbia]) - 0.5 * p1[jbia] + 0.5 * p2[jbia] -
-          p1[ov(i, b, j, a)];
+  for (int k = 0; k < 4; ++k) {
+    const int r = ty + 8 * k;
+    {  // X(i,j,a,b), a = a0 + r, b = b0 + tx: along b
+      const int a = a0 + r, b = b0 + tx;
+      x1[k] = (a < v && b < v) ? assemble_x(g1, rl, em, p1, p2, ij + (long)a * v + b, ov(i, a, j, b), ov(j, a, i, b))
+                               : 0.0;
+      t1[r][tx] = x1[k];
     }
-    tile[ty + 8 * k][tx] = t;
+    {  // X(j,i,b,a), b = b0 + r, a = a0 + tx: along a
+      const int b = b0 + r, a = a0 + tx;
+      x2[k] = (a < v && b < v) ? assemble_x(g1, rl, em, p1, p2, ji + (long)b * v + a, ov(j, b, i, a), ov(i, b, j, a))
+                               : 0.0;
+      t2[r][tx] = x2[k];
+    }
   }
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {  // output along b
-    const int a = a0 + ty + 8 * k, b = b0 + tx;
-    if (a < v && b < v) {
-      const long x = ij + (long)a * v + b;
-      const long iajb = ov(i, a, j, b);
-      r2[x] = 0.5 * (g1[iajb] + rl[x]) + em[x] - 0.5 * p1[iajb] + 0.5 * p2[iajb] - p1[ov(j, a, i, b)] +
-              tile[tx][ty + 8 * k];
+  for (int k = 0; k < 4; ++k) {
+    const int r = ty + 8 * k;
+    {  // R2[ij][a][b] = X(i,j,a,b) + X(j,i,b,a)
+      const int a = a0 + r, b = b0 + tx;
+      if (a < v && b < v) r2[ij + (long)a * v + b] = x1[k] + t2[tx][r];
+    }
+    {  // R2[ji][b][a] = X(j,i,b,a) + X(i,j,a,b)
+      const int b = b0 + r, a = a0 + tx;
+      if (a < v && b < v) r2[ji + (long)b * v + a] = x2[k] + t1[tx][r];
     }
   }
 }
@@ -793,9 +817,10 @@ hipError_t assemble_r2(double* r2, const double* g1, const double* rl, const dou
         range_ok(p1, 0, ovov - 1, 8, "assemble p1") && range_ok(p2, 0, ovov - 1, 8, "assemble p2")))
     return hipErrorInvalidValue;
   if (dry_run()) return hipSuccess;
-  const int tv = (nv + 31) / 32;
-  hipLaunchKernelGGL(assemble_r2_kernel, dim3((unsigned)(tv * tv), (unsigned)no, (unsigned)no), dim3(kThreads), 0, s, r2,
-                     g1, rl, em, p1, p2, no, nv);
+  const long tv = (nv + 31) / 32, pairs = (long)no * (no + 1) / 2;
+  if (tv * tv > 65535 || pairs > 0x7fffffffL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(assemble_r2_kernel, dim3((unsigned)pairs, (unsigned)(tv * tv)), dim3(kThreads), 0, s, r2, g1, rl,
+                     em, p1, p2, no, nv);
   return hipGetLastError();
 }
 
