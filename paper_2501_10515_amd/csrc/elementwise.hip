@@ -413,7 +413,9 @@ __global__ __launch_bounds__(kThreads) void update_stage1(UK p) {
 }
 
 // Bordered DIIS system over the valid slots, oldest first; returns false if a pivot is tiny.
-__device__ bool diis_solve(DiisState* st, int m) {
+// A and xs: (kMaxDiis + 1) x (kMaxDiis + 2) and kMaxDiis + 1 doubles of the caller's LDS (one thread
+// eliminates; LDS rather than private arrays, which would live in scratch memory).
+__device__ bool diis_solve(DiisState* st, int m, double* A, double* xs) {
   int order[kMaxDiis];
   int nv = 0;
   for (int k = 0; k < m; ++k)
@@ -425,7 +427,6 @@ __device__ bool diis_solve(DiisState* st, int m) {
       order[y - 1] = t;
     }
   constexpr int W = kMaxDiis + 2;
-  double A[(kMaxDiis + 1) * W];
   const int nn = nv + 1;
   double scale = 0.0;
   for (int r = 0; r < nv; ++r)
@@ -459,7 +460,6 @@ __device__ bool diis_solve(DiisState* st, int m) {
       for (int k = c; k <= nn; ++k) A[r * W + k] -= f * A[c * W + k];
     }
   }
-  double xs[kMaxDiis + 1];
   for (int r = nn - 1; r >= 0; --r) {
     double acc = A[r * W + nn];
     for (int k = r + 1; k < nn; ++k) acc -= A[r * W + k] * xs[k];
@@ -476,6 +476,7 @@ __global__ __launch_bounds__(kThreads) void update_stage2(DiisState* st, const d
   const bool store = st->calls >= start;
   __shared__ double sh[kThreads / 64];
   __shared__ double red[3 + kMaxDiis];
+  __shared__ double sysA[(kMaxDiis + 1) * (kMaxDiis + 2)], sysx[kMaxDiis + 1];
   double a = 0.0;
   for (int k = threadIdx.x; k < nblk; k += blockDim.x) a += partial[(long)k * nstat + 0];
   double v = block_sum(a, sh);
@@ -513,7 +514,7 @@ __global__ __launch_bounds__(kThreads) void update_stage2(DiisState* st, const d
     st->nvec = nvalid;
     for (int k = 0; k < kMaxDiis; ++k) st->coef[k] = 0.0;
     while (st->nvec >= 2 && !(flags & 1)) {
-      if (diis_solve(st, m)) break;
+      if (diis_solve(st, m, sysA, sysx)) break;
       int oldest = -1;
       for (int k = 0; k < m; ++k)
         if (st->slot_age[k] >= 0 && (oldest < 0 || st->slot_age[k] < st->slot_age[oldest])) oldest = k;
