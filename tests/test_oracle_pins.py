@@ -242,3 +242,42 @@ def test_jacobi_diis_reaches_the_exact_solution_of_a_linear_problem():
         x = np.concatenate([res["t1"].ravel(), res["t2"].ravel()])
         assert np.abs(x - x_exact).max() <= 1e-10 * (1 + np.abs(x_exact).max())
     assert len(with_diis["history"]) < len(plain["history"])
+
+
+def test_convergence_tests_flip_at_the_known_iteration():
+    """The solver's convergence test (Sec. III.A: max|R| and |dE| per iteration, plus the residual
+    2-norm) on a problem whose iterates are known exactly: o = v = 1, eps = (-1/2, 1/2), so D1 = -1 and
+    D2 = -2, and R(t) = -D t / 2, so every Jacobi step halves t (DIIS off).  From t = 1 the k-th
+    iterate is t = 2^-k with r1 = 2^-(k+1), r2 = 2^-k (max|R| = 2^-k) and, for E = t1 + t2, dE = -2^(1-k).
+    A tolerance equal to an achieved value separates <= from <, the negative dE catches a missing
+    absolute value, and a pair of tests must both hold."""
+    eps = np.array([-0.5, 0.5])
+    d1, d2 = solver.denominators(eps, 1)
+    assert d1.item() == -1.0 and d2.item() == -2.0
+
+    def residual(t1, t2):
+        return -0.5 * d1 * t1, -0.5 * d2 * t2
+
+    def energy(t1, t2):
+        return float(t1.sum() + t2.sum())
+
+    one1, one2 = np.ones((1, 1)), np.ones((1, 1, 1, 1))
+
+    def stop(**tol):
+        res = solver.solve(residual, energy, eps, one1, one2, maxiter=40, diis_size=1, **tol)
+        assert res["converged"]
+        k = res["iterations"] - 1
+        assert res["t1"].item() == 2.0 ** -k and res["t2"].item() == 2.0 ** -k  # the amplitudes tested
+        return k
+
+    assert stop(tol_rnorm=None, tol_rmax=2.0 ** -5) == 5       # max|R| <= tol, equality passes
+    assert stop(tol_rnorm=None, tol_de=2.0 ** -4) == 6         # |dE| < tol, equality does not
+    assert stop(tol_rnorm=float(np.sqrt(2.0 ** -8 + 2.0 ** -6))) == 3
+    assert stop(tol_rnorm=None, tol_rmax=2.0 ** -5, tol_de=2.0 ** -2) == 5  # both must hold
+    assert stop(tol_rnorm=None, tol_rmax=2.0 ** -2, tol_de=2.0 ** -4) == 6
+    # the first iteration has no energy change: the energy test alone cannot pass there
+    assert stop(tol_rnorm=None, tol_de=10.0) == 1
+    hist = solver.solve(residual, energy, eps, one1, one2, maxiter=4, diis_size=1, tol_rnorm=None,
+                        tol_rmax=1e-30)["history"]
+    assert [h["dE"] for h in hist[1:]] == [-1.0, -0.5, -0.25]
+    assert [h["rmax"] for h in hist] == [1.0, 0.5, 0.25, 0.125]
