@@ -33,9 +33,10 @@
  *     or aborts; ascc_last_error() returns a message for the last failure on this thread.
  *   - Device memory: ascc_build_ints(_hbar), ascc_batch_reserve, ascc_set_plascc and
  *     ascc_diis_create allocate the library's own device memory (integrals, work arrays, DIIS
- *     history; ascc_workspace_bytes reports the amount for the integrals and the DIIS state);
- *     ascc_*_free releases it.  ascc_solve and ascc_two_ansatz allocate their own state and
- *     free it before returning.  No other call allocates device memory.
+ *     history, PLASCC buffers; ascc_workspace_bytes and ascc_plascc_workspace_bytes report the
+ *     amounts); ascc_*_free releases it.  Their *_ws forms carve the same arrays from a caller
+ *     workspace instead and allocate nothing.  ascc_solve and ascc_two_ansatz allocate their own
+ *     state and free it before returning.  No other call allocates device memory.
  *   - A handle is not re-entrant: calls that share an ascc_ints (its work arrays) or an
  *     ascc_diis must be ordered on one stream.
  */
@@ -286,9 +287,9 @@ int ascc_server_submit(ascc_server* srv, const double* h_B, const double* h_eps,
 /* Queue an ASCC 1-CSF excited-state request (Sec. II.A): its integral set is Hbar of the state
  * (hole, particle, s_sign as for ascc_build_ints_hbar) and its amplitudes start from T^P(0) =
  * beta s S - (beta^2 / 2) S^2 (ascc_initial_guess; beta = 1 is Eq. (eqn:TP-guess)); with plascc = 1 its
- * residuals leave out the terms quadratic in the mixed doubles (ascc_set_plascc, whose small
- * work buffers are allocated at admission outside the slab); otherwise it is served exactly like a
- * ground-state request, with the same footprint.  Both ansatz of Sec. II.D are two requests
+ * residuals leave out the terms quadratic in the mixed doubles (ascc_set_plascc_ws: its work
+ * buffers are part of the request's footprint, carved from the slab and cleared on the request's
+ * stream); otherwise it is served exactly like a ground-state request, with the same footprint.  Both ansatz of Sec. II.D are two requests
  * (s_sign = +1 and -1 with their beta).
  * Errors: as ascc_server_submit; ASCC_E_ARG for a hole or particle out of range, s_sign not +-1 or
  * beta <= 0. */
@@ -325,12 +326,28 @@ int ascc_timing_read(ascc_ints* ints, double* ms, int* counts, int n);
  * same primaries, to the ground-state equations: call this on an ascc_build_ints set too.
  *   hole      occupied orbital index in [0, no), or < 0 to return to the full equations.
  *   particle  virtual orbital index in [no, no + nv) (full orbital numbering).
- * The first call with hole >= 0 allocates device work buffers of
- * 5 m no nv + naux (no nv + 2 m) doubles, m = no + nv - 1 (library-allocated even for a set built
- * in a caller workspace; released by ascc_ints_free).  The removal costs N^5 work per residual.
- * Host call, no stream work.  Errors: ASCC_E_ARG (NULL handle, indices out of range),
- * ASCC_E_NOMEM. */
+ * The first call with hole >= 0 allocates the removal's device work buffers (compact slabs along
+ * the primary crosses; their exact size is what ascc_plascc_workspace_bytes reports, up to
+ * even padding 8 m no nv + 3 m^2 + naux (no nv + 2 m) + 2 (2 no - 1) nv^2 + 3 no^2 (2 nv - 1) +
+ * 2 no^2 (2 no - 1) doubles, m = no + nv - 1), clears
+ * them and waits for the clears (released by ascc_ints_free).  The removal costs N^5 work per
+ * residual.  Synchronous.  Errors: ASCC_E_ARG (NULL handle, indices out of range), ASCC_E_NOMEM,
+ * ASCC_E_HIP. */
 int ascc_set_plascc(ascc_ints* ints, int hole, int particle);
+
+/* Exact device bytes of the PLASCC work buffers of an integral set of this shape (the workspace
+ * ascc_set_plascc_ws needs).  Host-only.  Errors: ASCC_E_SHAPE, ASCC_E_ARG. */
+int ascc_plascc_workspace_bytes(int no, int nv, int naux, size_t* bytes);
+
+/* ascc_set_plascc carving its work buffers from the caller's workspace d_workspace (256-byte
+ * aligned, ws_bytes >= ascc_plascc_workspace_bytes) instead of allocating: for callers that admit
+ * work by memory footprint (the request server) or must not call the allocator.  The buffers are
+ * cleared by a kernel queued on `stream` (no memset, no synchronisation); residuals of this handle
+ * must run on `stream` or be ordered after it.  The workspace must outlive the handle; a handle
+ * keeps the buffers of its first call (a later call with another workspace is ASCC_E_STATE).
+ * hole < 0 returns to the full equations (d_workspace may then be NULL).
+ * Errors: as ascc_set_plascc; ASCC_E_NOMEM if ws_bytes is too small. */
+int ascc_set_plascc_ws(ascc_ints* ints, int hole, int particle, void* d_workspace, size_t ws_bytes, void* stream);
 
 /* The two ansatz choices of Sec. II.D for a 1-CSF state whose reference has the Aufbau coefficient
  * alpha, alpha |phi_0> + S |phi_0> (Eq. (eqn:ref-with-nz-aufbau)), |alpha| < 1: the guess of
@@ -341,7 +358,9 @@ int ascc_set_plascc(ascc_ints* ints, int hole, int particle);
  * of the two total energies.  For alpha = 0 both have beta = 1.  A solve counts when it converged
  * or stalled near convergence (ascc_result.stalled); when only one of the two counts, its energy
  * alone is reported (Sec. III.A: the paper keeps the single converged solution, and stalled
- * states marked); when neither does, the state has no energy (ASCC_E_NOT_CONVERGED).
+ * states marked); when neither does, the state has no energy (ASCC_E_NOT_CONVERGED).  A solve whose
+ * iteration becomes non-finite (ASCC_E_NONFINITE from ascc_solve) is such a failed solve: it is
+ * recorded in res->solve with converged = 0 and the other ansatz is still solved.
  *   d_B, d_fock, fock_is_diag, no, nv, naux, precision, vvvv_mode, hole, particle: as for
  *             ascc_build_ints_hbar; opts: as for ascc_solve (its low-precision hand-over applies
  *             to both solves).

@@ -45,7 +45,9 @@ from ._lib import (  # noqa: F401
     ascc_get_precision,
     ascc_residual,
     ascc_residual_batch,
+    ascc_plascc_workspace_bytes,
     ascc_set_plascc,
+    ascc_set_plascc_ws,
     ascc_set_precision,
     ascc_solve,
     ascc_update,

@@ -74,7 +74,7 @@ EXPORTS = ("ascc_workspace_bytes", "ascc_build_ints", "ascc_residual", "ascc_dii
            "ascc_diis_create_ws", "ascc_server_create", "ascc_server_submit", "ascc_server_step",
            "ascc_server_info", "ascc_server_free", "ascc_build_ints_hbar", "ascc_initial_guess",
            "ascc_reference_energy", "ascc_set_plascc", "ascc_two_ansatz", "ascc_build_ints_hbar_ws",
-           "ascc_server_submit_state")
+           "ascc_server_submit_state", "ascc_plascc_workspace_bytes", "ascc_set_plascc_ws")
 
 
 def load_library():
@@ -98,6 +98,8 @@ def load_library():
     L.ascc_initial_guess.argtypes = [vp, vp, c_int, c_int, c_int, c_int, c_double, c_double, vp]
     L.ascc_reference_energy.argtypes = [vp, ctypes.POINTER(c_double), vp]
     L.ascc_set_plascc.argtypes = [vp, c_int, c_int]
+    L.ascc_plascc_workspace_bytes.argtypes = [c_int, c_int, c_int, c_size_p]
+    L.ascc_set_plascc_ws.argtypes = [vp, c_int, c_int, vp, ctypes.c_size_t, vp]
     L.ascc_diis_create.argtypes = [vp, c_int, c_int, ctypes.POINTER(vp)]
     L.ascc_diis_reset.argtypes = [vp, vp]
     L.ascc_update.argtypes = [vp, vp, vp, vp, vp, vp, vp, c_double, vp, vp]
@@ -312,6 +314,22 @@ def ascc_two_ansatz(B: torch.Tensor, fock: torch.Tensor, no: int, hole: int, par
 def ascc_set_plascc(ints: Ints, hole: int, particle: int = -1):
     """Leave out the terms with two powers of the mixed doubles in later residuals (hole < 0: off)."""
     _check(load_library().ascc_set_plascc(ints.handle, hole, particle))
+
+
+def ascc_plascc_workspace_bytes(no: int, nv: int, naux: int) -> int:
+    """Exact device bytes of the PLASCC work buffers of an integral set of this shape."""
+    b = ctypes.c_size_t()
+    _check(load_library().ascc_plascc_workspace_bytes(no, nv, naux, ctypes.byref(b)))
+    return b.value
+
+
+def ascc_set_plascc_ws(ints: Ints, hole: int, particle: int, workspace, stream=None):
+    """ascc_set_plascc with the work buffers carved from a caller workspace (a device tensor of at
+    least ascc_plascc_workspace_bytes bytes that must outlive the handle); cleared on the stream."""
+    nbytes = workspace.numel() * workspace.element_size()
+    _check(load_library().ascc_set_plascc_ws(ints.handle, hole, particle, _dev(workspace, "workspace"), nbytes,
+                                             _stream(stream)))
+    ints._keep = getattr(ints, "_keep", []) + [workspace]
 
 
 def ascc_reference_energy(ints: Ints, stream=None) -> float:

@@ -1200,6 +1200,81 @@ int check_shape(int no, int nv, int naux) {
   return ASCC_OK;
 }
 
+// Work buffers of the PLASCC removal (compact cross slabs, see plascc_remove), in carving order.
+std::vector<std::pair<double* ascc_ints::*, long>> plascc_plan(long o, long v, long Q) {
+  const long ov = o * v, oo = o * o, vv = v * v;
+  const long m = o + v - 1, mp = pad_even(m);
+  const long mo = 2 * o - 1, mop = pad_even(mo), mvp = pad_even(2 * v - 1);
+  return {
+      {&ascc_ints::plA, m * ov},    {&ascc_ints::plC, ov * mp},   {&ascc_ints::plKr, m * ov},
+      {&ascc_ints::plKpp, m * mp},  {&ascc_ints::plYp, m * ov},   {&ascc_ints::plYpp, m * mp},
+      {&ascc_ints::plS, m * mp},    {&ascc_ints::plZ, m * ov},    {&ascc_ints::plZt, ov * mp},
+      {&ascc_ints::plW, ov * mp},   {&ascc_ints::plN, Q * ov},    {&ascc_ints::plBp, Q * mp},
+      {&ascc_ints::plNw, Q * mp},   {&ascc_ints::plTa, mo * vv},  {&ascc_ints::plTc, oo * mvp},
+      {&ascc_ints::plGc, oo * mvp}, {&ascc_ints::plZo, mo * oo},  {&ascc_ints::plZh, oo * mop},
+      {&ascc_ints::plRc, oo * mvp}, {&ascc_ints::plEc, mo * vv},
+  };
+}
+
+size_t plascc_footprint(long o, long v, long Q) {
+  size_t off = 0;
+  for (const auto& item : plascc_plan(o, v, Q))
+    off = align_up(off) + std::max<size_t>((size_t)item.second, 1) * sizeof(double);
+  return align_up(off);
+}
+
+// ascc_set_plascc (ws == nullptr: library-allocated buffers, cleared synchronously) and
+// ascc_set_plascc_ws (carved from the caller's workspace, cleared by a kernel on `s`; no
+// allocation and no synchronisation).
+int set_plascc_impl(ascc_ints* I, int hole, int particle, void* ws, size_t ws_bytes, hipStream_t s) {
+  if (!I) return fail(ASCC_E_ARG, "NULL handle");
+  if (hole < 0) {  // back to the full equations; the buffers stay for a later call
+    I->pl_hole = I->pl_pa = -1;
+    return ASCC_OK;
+  }
+  if (hole >= I->no || particle < I->no || particle >= I->n)
+    return fail(ASCC_E_ARG, "hole must be an occupied and particle a virtual orbital index");
+  if (ws && I->pl.total && I->pl.base != static_cast<char*>(ws))
+    return fail(ASCC_E_STATE, "PLASCC buffers of this integral set already live elsewhere");
+  if (!I->pl.total) {
+    const auto plan = plascc_plan(I->no, I->nv, I->naux);
+    if (ws) {
+      if (reinterpret_cast<uintptr_t>(ws) % kAlign) return fail(ASCC_E_ARG, "workspace must be 256-byte aligned");
+      const size_t need = plascc_footprint(I->no, I->nv, I->naux);
+      if (ws_bytes < need)
+        return fail(ASCC_E_NOMEM, "PLASCC workspace too small: needs " + std::to_string(need) + " bytes");
+      I->pl.base = static_cast<char*>(ws);
+      I->pl.size = ws_bytes;
+    }
+    int rc = ASCC_OK;
+    for (const auto& item : plan)
+      if (!rc) rc = dalloc(I->pl, &(I->*(item.first)), (size_t)item.second);
+    // padding columns that products read but never write (plW) must hold zeros: clear them all
+    for (const auto& item : plan) {
+      if (rc) break;
+      if (ws) {  // a fill kernel on the caller's stream, ordered before every later residual on it
+        const int d[4] = {1, 1, 1, (int)std::max<long>(item.second, 1)};
+        if (permute4(I->*(item.first), d, 0.0, nullptr, 0, s) != hipSuccess)
+          rc = fail(ASCC_E_HIP, "clearing the PLASCC buffers failed");
+      } else if (!dry_run() && hipMemset(I->*(item.first), 0, sizeof(double) * item.second) != hipSuccess) {
+        rc = fail(ASCC_E_HIP, "clearing the PLASCC buffers failed");
+      }
+    }
+    // the allocating form waits for its clears, so that work on any stream (non-blocking ones too)
+    // sees zeros
+    if (!rc && !ws && !dry_run() && hipStreamSynchronize(nullptr) != hipSuccess)
+      rc = fail(ASCC_E_HIP, "clearing the PLASCC buffers failed");
+    if (rc) {
+      free_all(I->pl);
+      I->pl = Pool();
+      return rc;
+    }
+  }
+  I->pl_hole = hole;
+  I->pl_pa = particle - I->no;
+  return ASCC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1262,46 +1337,21 @@ int ascc_timing_read(ascc_ints* I, double* ms, int* counts, int n) {
   return rc;
 }
 
-int ascc_set_plascc(ascc_ints* I, int hole, int particle) {
-  if (!I) return fail(ASCC_E_ARG, "NULL handle");
-  if (hole < 0) {  // back to the full equations; the buffers stay for a later call
-    I->pl_hole = I->pl_pa = -1;
-    return ASCC_OK;
-  }
-  if (hole >= I->no || particle < I->no || particle >= I->n)
-    return fail(ASCC_E_ARG, "hole must be an occupied and particle a virtual orbital index");
-  if (!I->pl.total) {
-    const long ov = I->ov, oo = I->oo, vv = I->vv, Q = I->naux;
-    const long m = (long)I->no + I->nv - 1, mp = pad_even(m);
-    const long mo = 2L * I->no - 1, mop = pad_even(mo), mvp = pad_even(2L * I->nv - 1);
-    const std::pair<double* ascc_ints::*, long> plan[] = {
-        {&ascc_ints::plA, m * ov},   {&ascc_ints::plC, ov * mp},   {&ascc_ints::plKr, m * ov},
-        {&ascc_ints::plKpp, m * mp}, {&ascc_ints::plYp, m * ov},   {&ascc_ints::plYpp, m * mp},
-        {&ascc_ints::plS, m * mp},   {&ascc_ints::plZ, m * ov},    {&ascc_ints::plZt, ov * mp},
-        {&ascc_ints::plW, ov * mp},  {&ascc_ints::plN, Q * ov},    {&ascc_ints::plBp, Q * mp},
-        {&ascc_ints::plNw, Q * mp},  {&ascc_ints::plTa, mo * vv},  {&ascc_ints::plTc, oo * mvp},
-        {&ascc_ints::plGc, oo * mvp}, {&ascc_ints::plZo, mo * oo}, {&ascc_ints::plZh, oo * mop},
-        {&ascc_ints::plRc, oo * mvp}, {&ascc_ints::plEc, mo * vv},
-    };
-    int rc = ASCC_OK;
-    for (const auto& item : plan)
-      if (!rc) rc = dalloc(I->pl, &(I->*(item.first)), (size_t)item.second);
-    // padding columns that products read but never write (plW) must hold zeros: clear them all,
-    // and wait for the clears, so that work on any stream (non-blocking ones too) sees zeros
-    for (const auto& item : plan)
-      if (!rc && !dry_run() && hipMemset(I->*(item.first), 0, sizeof(double) * item.second) != hipSuccess)
-        rc = fail(ASCC_E_HIP, "clearing the PLASCC buffers failed");
-    if (!rc && !dry_run() && hipStreamSynchronize(nullptr) != hipSuccess)
-      rc = fail(ASCC_E_HIP, "clearing the PLASCC buffers failed");
-    if (rc) {
-      free_all(I->pl);
-      I->pl = Pool();
-      return rc;
-    }
-  }
-  I->pl_hole = hole;
-  I->pl_pa = particle - I->no;
+int ascc_plascc_workspace_bytes(int no, int nv, int naux, size_t* bytes) {
+  int rc = check_shape(no, nv, naux);
+  if (rc) return rc;
+  if (!bytes) return fail(ASCC_E_ARG, "NULL argument to ascc_plascc_workspace_bytes");
+  *bytes = plascc_footprint(no, nv, naux);
   return ASCC_OK;
+}
+
+int ascc_set_plascc(ascc_ints* I, int hole, int particle) {
+  return set_plascc_impl(I, hole, particle, nullptr, 0, nullptr);
+}
+
+int ascc_set_plascc_ws(ascc_ints* I, int hole, int particle, void* d_workspace, size_t ws_bytes, void* stream) {
+  if (hole >= 0 && !d_workspace) return fail(ASCC_E_ARG, "NULL workspace for ascc_set_plascc_ws");
+  return set_plascc_impl(I, hole, particle, d_workspace, ws_bytes, static_cast<hipStream_t>(stream));
 }
 
 int ascc_reference_energy(const ascc_ints* I, double* e0, void* stream) {
@@ -1715,7 +1765,9 @@ int ascc_solve(ascc_ints* I, const ascc_opts* opts, double* t1, double* t2, ascc
         if ((rc = ascc_update(I, D, t1s, t2s, r1, r2, e, opts->level_shift, stats, stream))) break;
       }
     }
-    // accept the update
+    // accept the update, except after the last evaluation: a solve that ends unconverged returns the
+    // amplitudes its reported energy and residual norms were evaluated at
+    if (it + 1 == opts->maxiter) break;
     if (d_copy(t1, t1s, sizeof(double) * I->ov, hipMemcpyDeviceToDevice, s) != hipSuccess ||
         d_copy(t2, t2s, sizeof(double) * I->oovv, hipMemcpyDeviceToDevice, s) != hipSuccess) {
       rc = fail(ASCC_E_HIP, "copy of amplitudes failed");
@@ -1759,13 +1811,16 @@ int ascc_two_ansatz(const double* d_B, const double* d_fock, int fock_is_diag, i
     if (rc) return rc;
     rc = ascc_initial_guess(d_t1[k], d_t2[k], no, nv, hole, particle, sign * beta, -0.5 * beta * beta, stream);
     if (!rc) rc = ascc_solve(I, opts, d_t1[k], d_t2[k], &res->solve[k], stream);
+    // a solve that ends without converging, or whose iteration diverged to non-finite values, is a
+    // failed ansatz: recorded (converged = 0) and the other one still runs
+    const bool failed_solve = rc == ASCC_E_NOT_CONVERGED || rc == ASCC_E_NONFINITE;
     double e0 = 0.0;
-    if (!rc || rc == ASCC_E_NOT_CONVERGED) {
+    if (!rc || failed_solve) {
       const int rc0 = ascc_reference_energy(I, &e0, stream);
       if (rc0) rc = rc0;
     }
     ascc_ints_free(I);
-    if (rc == ASCC_E_NOT_CONVERGED) {
+    if (failed_solve) {
       status = rc;
     } else if (rc) {
       return rc;
@@ -1782,7 +1837,8 @@ int ascc_two_ansatz(const double* d_B, const double* d_fock, int fock_is_diag, i
     res->e_mean = res->e_total[res->used == 1 ? 0 : 1];
   (void)status;
   if (res->used == 0) {
-    set_error("neither two-ansatz solve converged (or stalled near convergence) in maxiter iterations");
+    set_error("neither two-ansatz solve converged (or stalled near convergence) in maxiter iterations" +
+              std::string(status == ASCC_E_NONFINITE ? " (an iteration became non-finite)" : ""));
     return ASCC_E_NOT_CONVERGED;
   }
   return ASCC_OK;

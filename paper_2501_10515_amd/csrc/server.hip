@@ -37,7 +37,7 @@ struct Request {
   double t_submit = 0, t_admit = -1, t_done = -1;
   int status = 1;  // 1 queued, 2 running, 0 converged, <0 ASCC_E_*
   size_t bytes = 0, off = 0;
-  size_t ints_bytes = 0, diis_bytes = 0;
+  size_t ints_bytes = 0, diis_bytes = 0, plascc_bytes = 0;
   ascc_ints* ints = nullptr;
   ascc_diis* diis = nullptr;
   double *t1 = nullptr, *t2 = nullptr, *r1 = nullptr, *r2 = nullptr, *e = nullptr, *stats = nullptr;
@@ -112,17 +112,22 @@ void slab_give(ascc_server* S, size_t off, size_t bytes) {
 
 size_t align_s(size_t x) { return (x + kSlabAlign - 1) / kSlabAlign * kSlabAlign; }
 
-// Layout of a request's region: [ints | diis | t1 t2 r1 r2 e stats eps | B staging]
-size_t request_bytes(const ascc_server* S, int o, int v, int Q, size_t* ib, size_t* db) {
-  size_t ints_b = 0, diis_b = 0;
+// Layout of a request's region: [ints | diis | t1 t2 r1 r2 e stats eps | B staging | PLASCC buffers]
+// (the last only for a PLASCC request): its whole device working set.
+size_t request_bytes(const ascc_server* S, int o, int v, int Q, bool plascc, size_t* ib, size_t* db,
+                     size_t* pb) {
+  size_t ints_b = 0, diis_b = 0, pl_b = 0;
   if (ascc_workspace_bytes(o, v, Q, S->opts.precision, S->opts.vvvv_mode, S->opts.solve.diis_size, &ints_b, &diis_b))
     return 0;
+  if (plascc && ascc_plascc_workspace_bytes(o, v, Q, &pl_b)) return 0;
   *ib = ints_b;
   *db = diis_b;
+  *pb = pl_b;
   const size_t ov = (size_t)o * v, oovv = (size_t)o * o * v * v, n = (size_t)o + v;
   size_t b = align_s(ints_b) + align_s(diis_b);
   b += align_s(8 * ov) * 2 + align_s(8 * oovv) * 2 + align_s(8) + align_s(64) + align_s(8 * n);
   b += align_s(8 * (size_t)Q * n * n);
+  b += align_s(pl_b);
   return b;
 }
 
@@ -191,6 +196,8 @@ int admit(ascc_server* S, Request* R, double now) {
   R->stats = carve(64);
   R->deps = carve(8 * n);
   R->dB = carve(8 * (size_t)R->Q * n * n);
+  char* plascc_ws = base + p;  // R->plascc_bytes (0 unless a PLASCC request)
+  p += align_s(R->plascc_bytes);
   if (!S->stream_pool.empty()) {
     R->stream = S->stream_pool.back();
     S->stream_pool.pop_back();
@@ -222,7 +229,9 @@ int admit(ascc_server* S, Request* R, double now) {
   rc = ascc_diis_create_ws(R->ints, S->opts.solve.diis_size, S->opts.solve.diis_start, diis_ws, R->diis_bytes,
                            &R->diis);
   if (rc) return rc;
-  if (R->plascc && (rc = ascc_set_plascc(R->ints, R->hole, R->particle))) return rc;
+  if (R->plascc &&
+      (rc = ascc_set_plascc_ws(R->ints, R->hole, R->particle, plascc_ws, R->plascc_bytes, s)))
+    return rc;
   if (R->hole >= 0) {  // T^P(0) of the state
     if ((rc = ascc_initial_guess(R->t1, R->t2, R->o, R->v, R->hole, R->particle, R->s_sign * R->beta,
                                  -0.5 * R->beta * R->beta, s)))
@@ -338,6 +347,12 @@ int ascc_server_submit_state(ascc_server* S, const double* h_B, const double* h_
     return sfail(ASCC_E_ARG, "hole must be an occupied and particle a virtual orbital index");
   if (s_sign != 1 && s_sign != -1) return sfail(ASCC_E_ARG, "s_sign must be +1 or -1");
   if (!(beta > 0.0)) return sfail(ASCC_E_ARG, "beta must be positive");
+  if (plascc && S) {
+    size_t ib = 0, db = 0, pb = 0;
+    const size_t bytes = request_bytes(S, no, nv, naux, true, &ib, &db, &pb);
+    if (!bytes) return ASCC_E_SHAPE;
+    if (bytes > S->slab_bytes) return sfail(ASCC_E_NOMEM, "request larger than the whole HBM budget");
+  }
   int rc = ascc_server_submit(S, h_B, h_eps, no, nv, naux, t_submit, id);
   if (rc) return rc;
   Request* R = S->reqs[*id];
@@ -352,8 +367,9 @@ int ascc_server_submit_state(ascc_server* S, const double* h_B, const double* h_
 int ascc_server_submit(ascc_server* S, const double* h_B, const double* h_eps, int no, int nv, int naux,
                        double t_submit, int* id) {
   if (!S || !h_B || !h_eps || !id) return sfail(ASCC_E_ARG, "NULL argument to ascc_server_submit");
-  size_t ib = 0, db = 0;
-  const size_t bytes = request_bytes(S, no, nv, naux, &ib, &db);
+  size_t ib = 0, db = 0, pb = 0;
+  // the footprint of a PLASCC request (ascc_server_submit_state) is checked there
+  const size_t bytes = request_bytes(S, no, nv, naux, false, &ib, &db, &pb);
   if (!bytes) return ASCC_E_SHAPE;  // message set by ascc_workspace_bytes
   if (bytes > S->slab_bytes) return sfail(ASCC_E_NOMEM, "request larger than the whole HBM budget");
   Request* R = new Request();
@@ -404,7 +420,8 @@ int ascc_server_step(ascc_server* S, double now, int* n_queued, int* n_running, 
   // 2. admission in arrival order while the head fits the remaining budget and a slot is free
   while (!S->queue.empty() && (int)S->running.size() < S->opts.max_active) {
     Request* R = S->reqs[S->queue.front()];
-    const size_t bytes = request_bytes(S, R->o, R->v, R->Q, &R->ints_bytes, &R->diis_bytes);
+    const size_t bytes = request_bytes(S, R->o, R->v, R->Q, R->plascc, &R->ints_bytes, &R->diis_bytes,
+                                       &R->plascc_bytes);
     size_t off = 0;
     if (!slab_take(S, bytes, &off)) break;
     R->off = off;
@@ -451,8 +468,8 @@ int ascc_server_info(const ascc_server* S, int id, ascc_request_info* info) {
   info->t_submit = R->t_submit;
   info->t_admit = R->t_admit;
   info->t_done = R->t_done;
-  size_t ib = 0, db = 0;
-  info->bytes = request_bytes(S, R->o, R->v, R->Q, &ib, &db);
+  size_t ib = 0, db = 0, pb = 0;
+  info->bytes = request_bytes(S, R->o, R->v, R->Q, R->plascc, &ib, &db, &pb);
   info->e_ref = R->e_ref;
   info->hole = R->hole;
   info->particle = R->particle;

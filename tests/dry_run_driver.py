@@ -55,6 +55,8 @@ def main(shapes):
     L.ascc_initial_guess.argtypes = [vp, vp] + [ctypes.c_int] * 4 + [ctypes.c_double] * 2 + [vp]
     L.ascc_reference_energy.argtypes = [vp, ctypes.POINTER(ctypes.c_double), vp]
     L.ascc_set_plascc.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+    L.ascc_plascc_workspace_bytes.argtypes = [ctypes.c_int] * 3 + [ctypes.POINTER(ctypes.c_size_t)]
+    L.ascc_set_plascc_ws.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, ctypes.c_size_t, vp]
     L.ascc_build_ints_hbar_ws.argtypes = [vp, vp] + [ctypes.c_int] * 9 + [vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
     L.ascc_two_ansatz.argtypes = [vp, vp] + [ctypes.c_int] * 8 + [ctypes.c_double, ctypes.POINTER(Opts),
                                                                     ctypes.POINTER(vp), ctypes.POINTER(vp),
@@ -135,6 +137,16 @@ def main(shapes):
                     t1, t2, r1, r2, e = (fake(8 * o * v), fake(8 * o * o * v * v), fake(8 * o * v),
                                          fake(8 * o * o * v * v), fake(8))
                     rc = L.ascc_residual(h5, t1, t2, r1, r2, e, None)
+                    if rc == 0:  # PLASCC buffers carved from an exact-size workspace (one byte less refused)
+                        pb = ctypes.c_size_t()
+                        rc = L.ascc_plascc_workspace_bytes(o, v, Q, ctypes.byref(pb))
+                        if rc == 0 and L.ascc_set_plascc_ws(h5, 0, o + v - 1, fake(pb.value), pb.value - 1, None) != -3:
+                            rc = -101
+                            print("undersized PLASCC workspace accepted", flush=True)
+                        if rc == 0:
+                            rc = L.ascc_set_plascc_ws(h5, 0, o + v - 1, fake(pb.value), pb.value, None)
+                        if rc == 0:
+                            rc = L.ascc_residual(h5, t1, t2, r1, r2, e, None)
                     L.ascc_ints_free(h5)
             if rc == 0:  # both ansatz of the state, each built, solved and freed in turn
                 t1s = (vp * 2)(fake(8 * o * v), fake(8 * o * v))

@@ -334,3 +334,33 @@ def test_second_ansatz_residual_at_full_size(P):
     assert np.abs(r2 - r2_ref).max() <= TOL * scale
     assert abs(e - cs_ccsd.energy(Bbar, fbar, t1, t2)) <= TOL * scale
     assert abs(e0 - ascc.reference_energy(Bbar, fbar, o)) <= TOL * max(1.0, abs(e0))
+
+
+def test_two_ansatz_keeps_the_other_solve_when_one_diverges(P):
+    """alpha = -(1 - 2^-52) gives the first ansatz beta = 2^52: its iteration overflows to non-finite
+    values within a few steps, while the sign-flipped ansatz (beta ~ 1/2) converges.  The state's
+    energy is then the converged solve's alone (Sec. III.A), as in the oracle's two-ansatz rule."""
+    import warnings
+
+    import torch
+
+    from oracle import ascc
+
+    o, v, Q, seed, hole, particle = 3, 12, 36, 7, 2, 3
+    alpha = -(1.0 - 2.0 ** -52)
+    B, eps = make_system(o, v, Q, seed, sigma=converging_sigma(v, Q))
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")  # the diverging oracle solve overflows
+        ref = ascc.two_ansatz(B, eps, o, hole, particle, alpha, tol_rnorm=1e-11, maxiter=600)
+    assert ref["used"] == 2
+    t1s = [torch.empty((o, v), dtype=torch.float64, device="cuda") for _ in range(2)]
+    t2s = [torch.empty((o, o, v, v), dtype=torch.float64, device="cuda") for _ in range(2)]
+    r = P.ascc_two_ansatz(torch.from_numpy(B).cuda(), torch.from_numpy(eps).cuda(), o, hole, particle, alpha, t1s,
+                          t2s, tol_rnorm=1e-8, maxiter=400)
+    print(r, flush=True)
+    assert r["status"] == 0 and r["used"] == 2
+    assert not r["solves"][0]["converged"] and not r["solves"][0]["stalled"]
+    assert r["solves"][0]["iterations"] < 400  # stopped at the non-finite iteration, not at maxiter
+    assert r["solves"][1]["converged"]
+    assert r["e_mean"] == r["e_total"][1]
+    assert abs(r["e_mean"] - ref["E"]) <= 2e-8

@@ -8,9 +8,10 @@ pytestmark = pytest.mark.gpu
 
 # Error bounds relative to max|R| of the exact residual.  FP32 operands carry a relative
 # rounding error u = 2^-24 each; BF16x3 products drop the lo*lo term (2^-16 relative) and keep
-# hi/lo representation errors of 2^-17; both accumulate in FP32 within K chunks of 2048.  With
-# sums of a few thousand terms of mixed sign the observed error stays well below sqrt(K)*u_eff
-# times the largest term; the bounds below leave a factor of about ten over what is measured.
+# hi/lo representation errors of 2^-17; FP32 accumulates within K chunks of 2048 and BF16x3
+# within chunks of 8192 (then FP64 across chunks).  With sums of a few thousand terms of mixed
+# sign the observed error stays well below sqrt(K)*u_eff times the largest term; the bounds below
+# leave a factor of about ten over what is measured.
 REL = {"fp32": 2e-6, "bf16x3": 4e-5}
 
 
@@ -91,3 +92,75 @@ def test_refined_solve_matches_fp64_oracle(P, prec):
     print(res, ref["E"], flush=True)
     assert res["converged"] and res["lowp_iterations"] >= 3
     assert abs(res["e_corr"] - ref["E"]) <= 1e-9
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("mode", ["full", "packed"])
+def test_lowp_ladder_over_several_k_chunks(P, mode, prec):
+    """o40 v130: the ladder product has M = T(o) = 820 rows per half and K = N = T(v) = 8515, so the
+    split-BF16x3 contraction runs on its direct-to-LDS kernel (4 x 34 x 2 = 272 tiles of 256 x 256)
+    and flushes its FP32 sums into the FP64 result twice (K chunks of 8192), and the FP32 one five
+    times (chunks of 2048): the residual against the FP64 oracle."""
+    from oracle import cs_ccsd
+
+    from .gpu_util import dev, gpu_residual
+
+    o, v, Q, seed = 40, 130, 200, 11
+    print(f"case o={o} v={v} Q={Q} vvvv={mode} prec={prec}", flush=True)
+    B, eps = make_system(o, v, Q, seed, sigma=0.1)
+    t1, t2 = random_amplitudes(o, v, seed + 100, 0.02, 0.02)
+    r1_ref, r2_ref = cs_ccsd.residual(B, np.diag(eps), t1, t2)
+    pc = P.ASCC_PREC_FP32 if prec == "fp32" else P.ASCC_PREC_BF16X3
+    vm = P.ASCC_VVVV_FULL if mode == "full" else P.ASCC_VVVV_PACKED
+    ints = P.ascc_build_ints(dev(B), dev(eps), o, precision=pc, vvvv_mode=vm)
+    r1, r2, e = gpu_residual(P, ints, t1, t2)
+    scale = max(np.abs(r2_ref).max(), np.abs(r1_ref).max())
+    err = max(np.abs(r1 - r1_ref).max(), np.abs(r2 - r2_ref).max())
+    print(f"  max|dR| = {err:.3e}  (max|R| = {scale:.3e}, rel {err / scale:.2e})", flush=True)
+    assert err <= REL[prec] * scale
+    # the same handle switched to FP64 gives the exact residual
+    P.ascc_set_precision(ints, P.ASCC_PREC_FP64)
+    q1, q2, _ = gpu_residual(P, ints, t1, t2)
+    ints.close()
+    assert max(np.abs(q1 - r1_ref).max(), np.abs(q2 - r2_ref).max()) <= 1e-10 * max(1.0, scale)
+
+
+@pytest.mark.slow
+def test_mixed_precision_solves_meet_the_energy_gate_at_o40_v360(P):
+    """The precision study's gate at o40 v360 Q1200 (seed 2, convergence-variant width): split-BF16x3
+    and FP32 bulk iterations finished in FP64 land within |dE| < 1e-6 Eh of the FP64 GPU solve (the
+    reference at this size), each converged to |R|_2 <= 1e-7 on an FP64 residual."""
+    import torch
+
+    from gen.synth_df import converging_sigma
+
+    from .gpu_util import dev
+
+    o, v, Q, seed = 40, 360, 1200, 2
+    B, eps = make_system(o, v, Q, seed, sigma=converging_sigma(v, Q))
+    dB, deps = dev(B), dev(eps)
+    del B
+    t1 = torch.zeros((o, v), dtype=torch.float64, device="cuda")
+    t2 = torch.zeros((o, o, v, v), dtype=torch.float64, device="cuda")
+    out = {}
+    for prec in ("bf16x3", "fp32"):
+        pc = P.ASCC_PREC_FP32 if prec == "fp32" else P.ASCC_PREC_BF16X3
+        ints = P.ascc_build_ints(dB, deps, o, precision=pc, vvvv_mode=P.ASCC_VVVV_PACKED)
+        if prec == "bf16x3":  # the FP64 reference on the same handle's FP64 operands
+            P.ascc_set_precision(ints, P.ASCC_PREC_FP64)
+            t1.zero_()
+            t2.zero_()
+            out["fp64"] = P.ascc_solve(ints, t1, t2, tol_rnorm=1e-7, maxiter=60)
+            P.ascc_set_precision(ints, pc)
+        t1.zero_()
+        t2.zero_()
+        out[prec] = P.ascc_solve(ints, t1, t2, tol_rnorm=1e-7, maxiter=60, lowp_rnorm=1e-7)
+        ints.close()
+        torch.cuda.empty_cache()
+    for k, r in out.items():
+        print(k, r, f"|dE| vs fp64 = {abs(r['e_corr'] - out['fp64']['e_corr']):.2e}", flush=True)
+        assert r["converged"] and r["rnorm"] <= 1e-7
+    for k in ("bf16x3", "fp32"):
+        assert out[k]["lowp_iterations"] >= 5
+        assert abs(out[k]["e_corr"] - out["fp64"]["e_corr"]) < 1e-6

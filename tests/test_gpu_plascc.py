@@ -231,3 +231,60 @@ def test_ascc_and_plascc_residuals_at_full_size(P):
     err = max(np.abs(q1 - r1_ref).max(), np.abs(q2 - (r2_ref - c)).max())
     print(f"bf16x3: max|dR| = {err:.3e} (max|R| = {rs:.3e}, rel {err / rs:.2e})", flush=True)
     assert err <= REL["bf16x3"] * rs
+
+
+def test_plascc_workspace_form_equals_the_allocating_form(P):
+    """ascc_set_plascc_ws (buffers carved from a caller workspace filled with garbage, cleared on the
+    stream) gives the residual of ascc_set_plascc bit for bit, on two primaries in a row."""
+    import torch
+
+    from .gpu_util import dev, gpu_residual
+
+    o, v, Q, seed = 7, 45, 37, 3
+    B, eps = make_system(o, v, Q, seed, sigma=0.1)
+    t1, t2 = random_amplitudes(o, v, seed + 100, 0.05, 0.05)
+    a = P.ascc_build_ints(dev(B), dev(eps), o, vvvv_mode=P.ASCC_VVVV_PACKED)
+    b = P.ascc_build_ints(dev(B), dev(eps), o, vvvv_mode=P.ASCC_VVVV_PACKED)
+    nbytes = P.ascc_plascc_workspace_bytes(o, v, Q)
+    ws = torch.full((nbytes // 8,), float("nan"), dtype=torch.float64, device="cuda")
+    for hole, particle in [(6, 9), (2, 7 + 44)]:
+        P.ascc_set_plascc(a, hole, particle)
+        P.ascc_set_plascc_ws(b, hole, particle, ws)
+        ra, rb = gpu_residual(P, a, t1, t2), gpu_residual(P, b, t1, t2)
+        assert np.array_equal(ra[0], rb[0]) and np.array_equal(ra[1], rb[1]) and ra[2] == rb[2]
+    with pytest.raises(P.AsccError) as exc:  # one byte short
+        c = P.ascc_build_ints(dev(B), dev(eps), o, vvvv_mode=P.ASCC_VVVV_PACKED)
+        P.ascc_set_plascc_ws(c, 6, 9, ws[: (nbytes - 8) // 8])
+    assert exc.value.code == P.ASCC_E_NOMEM
+    a.close()
+    b.close()
+
+
+def test_served_plascc_request_footprint_is_exact(P):
+    """A PLASCC request's slab share is its integral set, DIIS state, amplitudes, staging and the
+    PLASCC buffers, each as the workspace queries report them: nothing is allocated beside the slab."""
+    import time
+
+    o, v, Q, seed, hole, particle = 3, 12, 36, 7, 2, 3
+    B, eps = make_system(o, v, Q, seed, sigma=converging_sigma(v, Q))
+    srv = P.Server(1 << 30, max_active=2, precision=P.ASCC_PREC_FP64, vvvv_mode=P.ASCC_VVVV_PACKED, tol_rnorm=1e-8,
+                   maxiter=400)
+    ids = [srv.submit(B, eps, o, 0.0, hole=hole, particle=particle),
+           srv.submit(B, eps, o, 0.0, hole=hole, particle=particle, plascc=True)]
+    t0 = time.perf_counter()
+    while srv.step(time.perf_counter() - t0)[2] < 2:
+        assert time.perf_counter() - t0 < 60
+    plain, pl = srv.info(ids[0]), srv.info(ids[1])
+    srv.close()
+    assert plain["status"] == 0 and pl["status"] == 0
+    extra = P.ascc_plascc_workspace_bytes(o, v, Q)
+    assert pl["bytes"] - plain["bytes"] == (extra + 255) // 256 * 256
+    ib, db = P.ascc_workspace_bytes(o, v, Q, P.ASCC_PREC_FP64, P.ASCC_VVVV_PACKED, 8)
+    n = o + v
+
+    def al(x):
+        return (x + 255) // 256 * 256
+
+    expect = al(ib) + al(db) + 2 * al(8 * o * v) + 2 * al(8 * o * o * v * v) + al(8) + al(64) + al(8 * n) + \
+        al(8 * Q * n * n)
+    assert plain["bytes"] == expect

@@ -78,17 +78,28 @@ def test_alone_equals_mixed_and_oracle(P, prec):
         assert abs(m["e_corr"] - ref["E"]) <= 1e-8
 
 
-def test_admission_respects_the_budget(P):
-    """A budget that fits one request at a time still completes everything, one after another."""
-    reqs = _requests()[:3]
-    sizes = [P.ascc_workspace_bytes(o, B.shape[1] - o, B.shape[0], P.ASCC_PREC_FP64, P.ASCC_VVVV_PACKED, 8)
-             for o, B, _ in reqs]
-    budget = int(1.2 * max(a + b for a, b in sizes)) + (64 << 20)
-    res = _serve(P, reqs, [0, 1, 2], P.ASCC_PREC_FP64, budget=budget)
-    admits = sorted((r["t_admit"], r["t_done"]) for r in res.values())
-    for (a0, d0), (a1, d1) in zip(admits, admits[1:]):
-        assert a1 >= d0 - 1e-9 or True  # admission order is FIFO; overlap is allowed only if both fit
+@pytest.mark.parametrize("room", ["one", "two"])
+def test_admission_respects_the_budget(P, room):
+    """Footprint admission: at every moment the requests holding slab memory fit the budget.  With room
+    for one request (the budget is below the two smallest footprints together) they run strictly one
+    after another; with room for two, at most two overlap."""
+    reqs = _requests()[:4]
+    res = _serve(P, reqs, [0, 1, 2, 3], P.ASCC_PREC_FP64, budget=1 << 30)  # sizes from the server itself
+    fp = sorted(r["bytes"] for r in res.values())
+    budget = fp[-1] + (1 << 20) if room == "one" else fp[-1] + fp[-2] + (1 << 20)
+    assert (fp[0] + fp[1] > budget) if room == "one" else (sum(fp[:3]) > budget)
+    res = _serve(P, reqs, [0, 1, 2, 3], P.ASCC_PREC_FP64, budget=budget)
     assert all(r["status"] == 0 for r in res.values())
+    iv = [(r["t_admit"], r["t_done"], r["bytes"]) for r in res.values()]
+    for a, _, _ in iv:  # slab bytes held at each admission instant
+        held = sum(b for a2, d2, b in iv if a2 <= a < d2)
+        assert held <= budget
+    if room == "one":
+        iv.sort()
+        for (a0, d0, _), (a1, d1, _) in zip(iv, iv[1:]):
+            assert a1 >= d0
+    else:
+        assert max(sum(1 for a2, d2, _ in iv if a2 <= a < d2) for a, _, _ in iv) <= 2
 
 
 def test_graph_replay_equals_direct_launches(P):
