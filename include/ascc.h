@@ -243,6 +243,20 @@ typedef struct ascc_result {
 int ascc_solve(ascc_ints* ints, const ascc_opts* opts, double* d_t1, double* d_t2, ascc_result* res,
                void* stream);
 
+/* ascc_solve for callers that cannot allocate device memory -- code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc: the same iteration, arguments, results and errors
+ * as ascc_solve, with its DIIS state, residual, trial amplitudes and statistics carved from a fixed
+ * 64 MiB device array of the library instead of allocated (each GPU that runs the library holds one
+ * until the process ends) and the statistics read into host stack memory.  No hipMalloc, hipFree
+ * or other allocating routine is called.  The solver state must fit: (2 m + 2)(no nv + no^2 nv^2)
+ * doubles plus a few KiB, m = opts->diis_size (with m = 8 up to about no = 8, nv = 72); larger
+ * requests fail with ASCC_E_NOMEM before any work.  Every call on one GPU shares that GPU's array
+ * and leaves its last contents there: calls that overlap on one GPU (other threads, other streams)
+ * race and must not be made.  Synchronises `stream` once per iteration, as ascc_solve does.
+ * Errors: as ascc_solve; ASCC_E_NOMEM when the solver state exceeds the fixed array. */
+int ascc_solve_noalloc(ascc_ints* ints, const ascc_opts* opts, double* d_t1, double* d_t2, ascc_result* res,
+                       void* stream);
+
 /* ---- Request server: many independent solves on one GPU --------------------------------
  * A request is one Hamiltonian (DF tensor + orbital energies, diagonal Fock) solved from T = 0
  * with opts.solve.  The server owns one device slab of hbm_budget bytes (allocated at creation)

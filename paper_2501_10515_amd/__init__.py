@@ -50,6 +50,7 @@ from ._lib import (  # noqa: F401
     ascc_set_plascc_ws,
     ascc_set_precision,
     ascc_solve,
+    ascc_solve_noalloc,
     ascc_update,
     ascc_workspace_bytes,
     library_path,

@@ -74,7 +74,8 @@ EXPORTS = ("ascc_workspace_bytes", "ascc_build_ints", "ascc_residual", "ascc_dii
            "ascc_diis_create_ws", "ascc_server_create", "ascc_server_submit", "ascc_server_step",
            "ascc_server_info", "ascc_server_free", "ascc_build_ints_hbar", "ascc_initial_guess",
            "ascc_reference_energy", "ascc_set_plascc", "ascc_two_ansatz", "ascc_build_ints_hbar_ws",
-           "ascc_server_submit_state", "ascc_plascc_workspace_bytes", "ascc_set_plascc_ws")
+           "ascc_server_submit_state", "ascc_plascc_workspace_bytes", "ascc_set_plascc_ws",
+           "ascc_solve_noalloc")
 
 
 def load_library():
@@ -104,6 +105,7 @@ def load_library():
     L.ascc_diis_reset.argtypes = [vp, vp]
     L.ascc_update.argtypes = [vp, vp, vp, vp, vp, vp, vp, c_double, vp, vp]
     L.ascc_solve.argtypes = [vp, ctypes.POINTER(Opts), vp, vp, ctypes.POINTER(Result), vp]
+    L.ascc_solve_noalloc.argtypes = [vp, ctypes.POINTER(Opts), vp, vp, ctypes.POINTER(Result), vp]
     L.ascc_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]
     L.ascc_server_submit.argtypes = [vp, vp, vp, c_int, c_int, c_int, c_double, ctypes.POINTER(c_int)]
     L.ascc_server_submit_state.argtypes = [vp, vp, vp, c_int, c_int, c_int, c_int, c_int, c_int, c_double, c_int,
@@ -365,18 +367,23 @@ def ascc_update(ints: Ints, diis: Diis, t1, t2, r1, r2, e, stats, level_shift: f
 
 def ascc_solve(ints: Ints, t1, t2, tol_rnorm=1e-8, tol_rmax=0.0, tol_de=0.0, maxiter=100, diis_size=8,
                diis_start=1, level_shift=0.0, lowp_rnorm=0.0, lowp_maxiter=0, stream=None,
-               raise_on_not_converged=True) -> dict:
+               raise_on_not_converged=True, _entry="ascc_solve") -> dict:
     o, v = ints.no, ints.nv
     opts = Opts(tol_rnorm, tol_rmax, tol_de, maxiter, diis_size, diis_start, level_shift, lowp_rnorm, lowp_maxiter)
     res = Result()
-    rc = load_library().ascc_solve(ints.handle, ctypes.byref(opts), _dev(t1, "t1", (o, v)),
-                                   _dev(t2, "t2", (o, o, v, v)), ctypes.byref(res), _stream(stream))
+    rc = getattr(load_library(), _entry)(ints.handle, ctypes.byref(opts), _dev(t1, "t1", (o, v)),
+                                         _dev(t2, "t2", (o, o, v, v)), ctypes.byref(res), _stream(stream))
     out = dict(e_corr=res.e_corr, rnorm=res.rnorm, rmax=res.rmax, de=res.de, iterations=res.iterations,
                converged=bool(res.converged), lowp_iterations=res.lowp_iterations, stalled=bool(res.stalled),
                status=rc)
     if rc != ASCC_OK and not (rc == ASCC_E_NOT_CONVERGED and not raise_on_not_converged):
         raise AsccError(rc, ascc_last_error())
     return out
+
+
+def ascc_solve_noalloc(ints: Ints, t1, t2, **kw) -> dict:
+    """ascc_solve with the solver state in the library's fixed device array (no device allocation)."""
+    return ascc_solve(ints, t1, t2, _entry="ascc_solve_noalloc", **kw)
 
 
 def ascc_phase_count() -> int:

@@ -1667,17 +1667,47 @@ int ascc_update(ascc_ints* I, ascc_diis* D, double* t1, double* t2, const double
   return ASCC_OK;
 }
 
-int ascc_solve(ascc_ints* I, const ascc_opts* opts, double* t1, double* t2, ascc_result* res, void* stream) {
+}  // extern "C"
+
+namespace ascc {
+
+uintptr_t dry_run_address(size_t bytes) { return fake_alloc(bytes); }
+
+// Device bytes of the solver state that solve_impl carves from a workspace: the DIIS state, then
+// r1, r2, e, the statistics block and the trial amplitudes t1s, t2s.
+size_t solve_workspace_bytes(long o, long v, int diis_size) {
+  const long ov = o * v, oovv = o * o * v * v;
+  size_t off = diis_footprint(o, v, diis_size);
+  for (long n : {ov, oovv, 1L, 8L, ov, oovv}) off = align_up(off) + sizeof(double) * (size_t)n;
+  return align_up(off);
+}
+
+// The solve loop of ascc_solve.  ws == nullptr: the DIIS state and work arrays are allocated here and
+// the statistics are read through pinned host memory; otherwise everything is carved from
+// [ws, ws + ws_bytes) (>= solve_workspace_bytes) and no allocation is made.
+int solve_impl(ascc_ints* I, const ascc_opts* opts, double* t1, double* t2, ascc_result* res, void* stream,
+               char* ws, size_t ws_bytes) {
   if (!I || !opts || !t1 || !t2 || !res) return fail(ASCC_E_ARG, "NULL argument to ascc_solve");
   if (opts->maxiter < 1) return fail(ASCC_E_ARG, "maxiter must be >= 1");
+  if (opts->diis_size < 1 || opts->diis_size > kMaxDiis) return fail(ASCC_E_ARG, "diis_size must be in 1..16");
   hipStream_t s = static_cast<hipStream_t>(stream);
   std::memset(res, 0, sizeof(*res));
   const int prec0 = I->cur_prec;
   bool lowp_phase = (prec0 != ASCC_PREC_FP64);
+  size_t dbytes = 0;
+  if (ws) {
+    dbytes = diis_footprint(I->no, I->nv, opts->diis_size);
+    if (ws_bytes < solve_workspace_bytes(I->no, I->nv, opts->diis_size))
+      return fail(ASCC_E_NOMEM, "solver workspace too small");
+  }
   ascc_diis* D = nullptr;
-  int rc = ascc_diis_create(I, opts->diis_size, opts->diis_start, &D);
+  int rc = diis_create_impl(I, opts->diis_size, opts->diis_start, ws, dbytes, &D);
   if (rc) return rc;
   Pool work;
+  if (ws) {
+    work.base = ws + dbytes;
+    work.size = ws_bytes - dbytes;
+  }
   double *r1 = nullptr, *r2 = nullptr, *e = nullptr, *stats = nullptr, *t1s = nullptr, *t2s = nullptr;
   rc = dalloc(work, &r1, I->ov);
   if (!rc) rc = dalloc(work, &r2, I->oovv);
@@ -1687,8 +1717,11 @@ int ascc_solve(ascc_ints* I, const ascc_opts* opts, double* t1, double* t2, ascc
   if (!rc) rc = dalloc(work, &t2s, I->oovv);
   double* hstats = nullptr;
   static double dry_stats[8];
+  double local_stats[8];
   if (dry_run()) {
     hstats = dry_stats;  // a dry run reports zeros: converged after one iteration
+  } else if (ws) {
+    hstats = local_stats;  // pageable: the copy completes before the stream synchronisation returns
   } else if (!rc && hipHostMalloc((void**)&hstats, 8 * sizeof(double), 0) != hipSuccess) {
     rc = fail(ASCC_E_NOMEM, "pinned host allocation failed");
   }
@@ -1776,7 +1809,7 @@ int ascc_solve(ascc_ints* I, const ascc_opts* opts, double* t1, double* t2, ascc
   }
   I->cur_prec = prec0;
   (void)d_sync(s);
-  if (hstats && !dry_run()) (void)hipHostFree(hstats);
+  if (hstats && !dry_run() && !ws) (void)hipHostFree(hstats);
   free_all(work);
   ascc_diis_free(D);
   if (rc) return rc;
@@ -1790,6 +1823,14 @@ int ascc_solve(ascc_ints* I, const ascc_opts* opts, double* t1, double* t2, ascc
     set_error(res->stalled ? "stalled near convergence in maxiter iterations" : "not converged in maxiter iterations");
   }
   return status;
+}
+
+}  // namespace ascc
+
+extern "C" {
+
+int ascc_solve(ascc_ints* I, const ascc_opts* opts, double* t1, double* t2, ascc_result* res, void* stream) {
+  return solve_impl(I, opts, t1, t2, res, stream, nullptr, 0);
 }
 
 int ascc_two_ansatz(const double* d_B, const double* d_fock, int fock_is_diag, int no, int nv, int naux, int precision,

@@ -7,6 +7,10 @@
 #include <cstdint>
 #include <string>
 
+struct ascc_ints;
+struct ascc_opts;
+struct ascc_result;
+
 namespace ascc {
 
 // Status used inside the library; converted to the ASCC_E_* codes at the ABI boundary.
@@ -258,5 +262,13 @@ struct UpdateArgs {
 };
 hipError_t diis_update(const UpdateArgs& u, hipStream_t s);
 int update_partial_blocks();
+
+// The solve loop of ascc_solve with its DIIS state and work arrays carved from [ws, ws + ws_bytes)
+// (ws == nullptr: allocated, as ascc_solve does), and the bytes that carving needs.
+size_t solve_workspace_bytes(long o, long v, int diis_size);
+int solve_impl(ascc_ints* I, const ascc_opts* opts, double* t1, double* t2, ascc_result* res, void* stream, char* ws,
+               size_t ws_bytes);
+// An unbacked, never dereferenced device address range for a dry run.
+uintptr_t dry_run_address(size_t bytes);
 
 }  // namespace ascc

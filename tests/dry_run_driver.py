@@ -42,6 +42,7 @@ def main(shapes):
     L.ascc_diis_create.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp)]
     L.ascc_update.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_double, vp, vp]
     L.ascc_solve.argtypes = [vp, ctypes.POINTER(Opts), vp, vp, ctypes.POINTER(Result), vp]
+    L.ascc_solve_noalloc.argtypes = [vp, ctypes.POINTER(Opts), vp, vp, ctypes.POINTER(Result), vp]
     L.ascc_batch_reserve.argtypes = [vp, ctypes.c_int]
     L.ascc_residual_batch.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                       ctypes.POINTER(vp), vp, vp]
@@ -104,6 +105,14 @@ def main(shapes):
                 res = Result()
                 rc = L.ascc_solve(h, ctypes.byref(Opts(1e-8, 0, 0, 3, 8, 1, 0.0, 1e-3, 1)), t1, t2, ctypes.byref(res),
                                   None)
+            if rc == 0:  # the same solve in the fixed solver array: it fits up to about o8 v72 with m = 8
+                res = Result()
+                rcn = L.ascc_solve_noalloc(h, ctypes.byref(Opts(1e-8, 0, 0, 3, 8, 1, 0.0, 1e-3, 1)), t1, t2,
+                                           ctypes.byref(res), None)
+                fits = 18 * (o * v + o * o * v * v) * 8 + (1 << 20) <= 64 << 20
+                if (rcn == 0) != fits or (rcn != 0 and rcn != -3):
+                    rc = -102
+                    print(f"ascc_solve_noalloc status {rcn} (fits {fits})", flush=True)
             L.ascc_ints_free(h)
         if rc == 0:  # the transformed Hamiltonian of a 1-CSF state, its guess and one residual
             h4 = vp()
