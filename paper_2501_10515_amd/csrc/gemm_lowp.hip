@@ -16,7 +16,9 @@
 //
 // MFMA lane layouts (gfx950, measured): f32 16x16x4 -- lane l supplies A(l%16, l/16) and
 // B(l/16, l%16); bf16 16x16x32 -- lane l supplies A(l%16, 8(l/16)+j) and B(8(l/16)+j, l%16),
-// j = 0..7; both return register r of lane l as C(4(l/16)+r, l%16).
+// j = 0..7; both return register r of lane l as C(4(l/16)+r, l%16); bf16 32x32x16 -- lane l
+// supplies A(l%32, 8(l/32)+j) and B(8(l/32)+j, l%32) and returns register q as
+// C(8(q/4) + 4(l/32) + q%4, l%32).
 #include <algorithm>
 #include <cstdint>
 
@@ -312,9 +314,9 @@ __global__ __launch_bounds__(256) void lowp_pm_kernel(unsigned short* __restrict
 // four-lanes-per-row staging stores conflict-free; padded 80-byte rows conflict 2-way on both.
 //
 // Two kernels: 256 x 128 tiles of eight 64 x 64 waves with register-staged loads (small and
-// medium contractions), and 256 x 256 tiles of four 128 x 128 waves whose operands are loaded
-// straight into LDS by buffer_load ... lds, double-buffered, with the accumulators in AGPRs
-// (large contractions: half the LDS traffic per MFMA and no staging registers).
+// medium contractions), and 256 x 256 tiles of eight 128 x 64 waves whose operands are loaded
+// straight into LDS by buffer_load ... lds, double-buffered (large contractions: half the LDS
+// traffic per MFMA and no staging registers).
 __device__ __forceinline__ int lds_slot(int r, int c) { return r * 32 + ((c ^ ((r >> 1) & 3)) << 3); }
 
 struct LPB {
@@ -460,56 +462,69 @@ __global__ __launch_bounds__(NT2, 1) void gemm_bf16x3_kernel(LPB p) {
   if (kt0 >= nkt) flush(true);
 }
 
-// 256 x 256 tiles, four waves of 128 x 128 (8 x 8 fragments, accumulators in AGPRs).  Each wave
-// stages one operand half per K-step (A hi, A lo, B hi, B lo: 256 rows x 64 bytes) with sixteen
-// buffer_load_dwordx4 ... lds (lane l of an instruction writes LDS bytes 16l .. 16l + 15, so lanes
-// pick the global chunk that belongs at their swizzled slot); rows past M or N and K-blocks past
-// the padded row read as zero through the buffer range check.  Per K-step: wait for the stage,
-// barrier, read all fragments, issue the next stage into the other buffer, run 192 MFMAs.
+// 256 x 256 tiles, eight waves of 128 x 64 (two per SIMD, so one wave's fragment reads and barrier
+// wait overlap the other's MFMAs), v_mfma_f32_32x32x16_bf16 (4 x 2 fragments of 32 x 32 per wave).
+// Each wave stages half of one operand plane per K-step (A hi, A lo, B hi, B lo: 128 rows x 64
+// bytes) with eight buffer_load_dwordx4 ... lds (lane l of an instruction writes LDS bytes
+// 16l .. 16l + 15, so lanes pick the global chunk that belongs at their swizzled slot); rows past M
+// or N and K-blocks past the padded row read as zero through the buffer range check.  Per K-step:
+// wait for this wave's part of the stage, barrier, issue the next stage into the other buffer, then
+// two K = 16 halves of fragment reads and 24 MFMAs, and a second barrier before the buffer is
+// refilled.  Measured at o40 v360 (ring products 14400^3, ladder 820 x 64980 x 64980, W/Z 1600 x
+// 16000 x 129600): 0.49 / 0.41 / 0.40 of the split-BF16x3 peak, against 0.37 / 0.31 / 0.29 with four
+// waves of 128 x 128 (one per SIMD); with eight waves the kernel is bound by the rate at which the
+// operand stages reach LDS (a copy of it without MFMAs takes as long), not by the matrix cores.
 typedef __attribute__((address_space(3))) void lds_void_t;
 typedef __attribute__((address_space(3))) char lds_char_t;
-constexpr int BM3 = 256, BN3 = 256, NT3 = 256;
+typedef float f16v __attribute__((ext_vector_type(16)));
+constexpr int BM3 = 256, BN3 = 256, NT3 = 512;
 
 __global__ __launch_bounds__(NT3, 1) void gemm_bf16x3_dma_kernel(LPB p) {
   __shared__ __attribute__((aligned(1024))) unsigned short T[2][4][256 * 32];  // [stage][plane][row slots]
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave >> 2, wn = wave & 3;  // this wave's 128 x 64 block of the tile
   int tm, tn;
   tile_of_grouped(blockIdx.x, p.tiles_m, p.tiles_n, tm, tn);
   const int m0 = tm * BM3, n0 = tn * BN3;
   const int z = blockIdx.y;
-  const bool isA = wave < 2;
+  const int lplane = wave >> 1, lhalf = wave & 1;  // staging: plane (A hi, A lo, B hi, B lo), row half
+  const bool isA = lplane < 2;
   const unsigned short* base = isA ? p.A + z * p.sa2 + (long)m0 * p.lda : p.B + z * p.sb2 + (long)n0 * p.ldb;
   const int ld = isA ? (int)p.lda : (int)p.ldb;  // row stride (bf16): K-blocks of [hi 32 | lo 32]
-  const int plane = wave & 1;
+  const int plane = lplane & 1;
   const int rows = min(256, isA ? p.M - m0 : p.N - n0);
   const __amdgpu_buffer_rsrc_t rs =
       __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, rows * ld * 2, 0x00020000);
   const int r = lane >> 2, c = (lane & 3) ^ ((r >> 1) & 3);  // row in a 16-row block, chunk loaded
   auto issue = [&](int kt, int stage) {
     const int gk = kt * 32 + c * 8, col = kt * 64 + plane * 32 + c * 8;
-    lds_char_t* dst = (lds_char_t*)(lds_void_t*)&T[stage][wave][0];
+    lds_char_t* dst = (lds_char_t*)(lds_void_t*)&T[stage][lplane][0];
 #pragma unroll
-    for (int g = 0; g < 16; ++g) {
-      const unsigned off = 2 * gk < ld ? (unsigned)(((g * 16 + r) * ld + col) * 2) : 0x80000000u;
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_t*)(dst + g * 1024), 16, off, 0, 0, 0);
+    for (int g = 0; g < 8; ++g) {
+      const int gg = lhalf * 8 + g;
+      const unsigned off = 2 * gk < ld ? (unsigned)(((gg * 16 + r) * ld + col) * 2) : 0x80000000u;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_t*)(dst + gg * 1024), 16, off, 0, 0, 0);
     }
   };
   double* Cb = p.C + z * p.sc2 + blockIdx.z * p.cslice;
-  f4 acc[8][8];
+  f16v acc[4][2];
 #pragma unroll
-  for (int i = 0; i < 8; ++i)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 8; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc[i][j][q] = 0.f;
+  // 32 x 32 fragment: register q of lane l holds C(8 (q / 4) + 4 (l / 32) + q % 4, l % 32)
   auto flush = [&](bool first) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 8; ++j)
+      for (int j = 0; j < 2; ++j)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int gm = m0 + wm * 128 + i * 16 + 4 * (lane >> 4) + q, gn = n0 + wn * 128 + j * 16 + (lane & 15);
+        for (int q = 0; q < 16; ++q) {
+          const int gm = m0 + wm * 128 + i * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+          const int gn = n0 + wn * 64 + j * 32 + (lane & 31);
           if (gm < p.M && gn < p.N) {
             double* cp = Cb + (long)gm * p.scm + (long)gn * p.scn;
             const double v = p.alpha * (double)acc[i][j][q];
@@ -522,36 +537,40 @@ __global__ __launch_bounds__(NT3, 1) void gemm_bf16x3_dma_kernel(LPB p) {
         }
   };
   const int kt0 = blockIdx.z * p.ktps, nkt = min((p.K + 31) / 32, kt0 + p.ktps);
-  const int lr = lane & 15, lg = lane >> 4;
+  const int fr = lane & 31, fc = lane >> 5;  // fragment row, K-chunk within a K = 16 half
   if (kt0 < nkt) issue(kt0, 0);
   for (int kc = kt0; kc < nkt; kc += p.chunk) {
     const int kend = min(nkt, kc + p.chunk);
     for (int kt = kc; kt < kend; ++kt) {
       const int cur = (kt - kt0) & 1;
       __builtin_amdgcn_s_waitcnt(0xF70);  // vmcnt(0): this wave's part of stage kt has landed
-      __syncthreads();                     // every wave's has; stage cur ^ 1 is no longer read
-      bf8 xa[8][2], xb[8][2];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int off = lds_slot(wm * 128 + i * 16 + lr, lg);
-        xa[i][0] = *reinterpret_cast<const bf8*>(&T[cur][0][off]);
-        xa[i][1] = *reinterpret_cast<const bf8*>(&T[cur][1][off]);
-      }
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int off = lds_slot(wn * 128 + j * 16 + lr, lg);
-        xb[j][0] = *reinterpret_cast<const bf8*>(&T[cur][2][off]);
-        xb[j][1] = *reinterpret_cast<const bf8*>(&T[cur][3][off]);
-      }
+      __builtin_amdgcn_s_barrier();       // every wave's has
       if (kt + 1 < nkt) issue(kt + 1, cur ^ 1);
 #pragma unroll
-      for (int j = 0; j < 8; ++j)
+      for (int sub = 0; sub < 2; ++sub) {
+        bf8 xa[4][2], xb[2][2];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[i][1], xb[j][0], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[i][0], xb[j][1], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[i][0], xb[j][0], acc[i][j], 0, 0, 0);
+        for (int i = 0; i < 4; ++i) {
+          const int off = lds_slot(wm * 128 + i * 32 + fr, 2 * sub + fc);
+          xa[i][0] = *reinterpret_cast<const bf8*>(&T[cur][0][off]);
+          xa[i][1] = *reinterpret_cast<const bf8*>(&T[cur][1][off]);
         }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int off = lds_slot(wn * 64 + j * 32 + fr, 2 * sub + fc);
+          xb[j][0] = *reinterpret_cast<const bf8*>(&T[cur][2][off]);
+          xb[j][1] = *reinterpret_cast<const bf8*>(&T[cur][3][off]);
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa[i][1], xb[j][0], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa[i][0], xb[j][1], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa[i][0], xb[j][0], acc[i][j], 0, 0, 0);
+          }
+      }
+      __builtin_amdgcn_s_barrier();  // every wave has read stage cur before it is refilled
     }
     flush(kc == kt0);
   }
