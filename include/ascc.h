@@ -262,13 +262,19 @@ int ascc_solve_noalloc(ascc_ints* ints, const ascc_opts* opts, double* d_t1, dou
  * with opts.solve.  The server owns one device slab of hbm_budget bytes (allocated at creation)
  * and carves each admitted request's complete working set from it, admitting queued requests in
  * arrival order whenever the head of the queue fits and fewer than max_active are running.
- * Every running request has its own stream; one iteration (ascc_residual + ascc_update) is
- * captured per precision into a hipGraph (use_graphs = 1) and replayed, and each
- * ascc_server_step launches one iteration for every running request whose previous iteration
- * has finished, so requests overlap on the device and join or leave between iterations.  With a
- * low `precision` the bulk iterations run in it and the last ones in FP64 (opts.solve.lowp_*).
- * All calls are host-side and never wait for the device except ascc_server_free (and the
- * synchronous integral build of a request during the step that admits it). */
+ * Ground-state requests of one shape (no, nv, naux) are bucketed: a bucket is a slab region of
+ * up to 8 equal slots (as many as a quarter of the budget holds; 1 if the budget is tighter), and
+ * one iteration of all its running slots is one batched pass -- every contraction one launch over
+ * the slots, the Jacobi/DIIS update one launch set -- for the slots in low precision and for those
+ * in FP64, captured once per slot set into a hipGraph (use_graphs = 1) and replayed.  Excited-state
+ * and PLASCC requests run in buckets of one slot.  Every bucket has its own stream, and each
+ * ascc_server_step launches the next iteration of every bucket whose previous one has finished,
+ * so buckets overlap on the device and requests join or leave between iterations.  Each request's
+ * results are those it gets alone (a slot's contractions take the same kernels and summation order
+ * in a batch as alone).  With a low `precision` the bulk iterations run in it and the last ones in
+ * FP64 (opts.solve.lowp_*).  All calls are host-side and never wait for the device except
+ * ascc_server_free (and short waits on an idle bucket stream when a request changes precision or
+ * finishes). */
 typedef struct ascc_server ascc_server;
 
 typedef struct ascc_server_opts {
@@ -290,6 +296,8 @@ typedef struct ascc_request_info {
   double e_ref;      /* <phi_0|H|phi_0> of the request's integral set (of Hbar for a state), once
                         the request has finished; e_ref + e_corr is its total energy         */
   int hole, particle; /* the 1-CSF state of ascc_server_submit_state, or -1, -1           */
+  int bucket, slot;   /* the size bucket and slot the request ran in (-1 while queued or
+                         after it finished: the last ones it held are kept)              */
 } ascc_request_info;
 
 /* Errors: ASCC_E_ARG, ASCC_E_NOMEM (slab allocation). */

@@ -53,7 +53,7 @@ class RequestInfo(ctypes.Structure):
                 ("e_corr", ctypes.c_double), ("rnorm", ctypes.c_double), ("rmax", ctypes.c_double),
                 ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
                 ("bytes", ctypes.c_size_t), ("e_ref", ctypes.c_double), ("hole", ctypes.c_int),
-                ("particle", ctypes.c_int)]
+                ("particle", ctypes.c_int), ("bucket", ctypes.c_int), ("slot", ctypes.c_int)]
 
 
 class Result(ctypes.Structure):

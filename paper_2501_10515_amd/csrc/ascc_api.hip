@@ -40,6 +40,9 @@ void set_error(const std::string& msg) { g_last_error = msg; }
 
 static std::mutex g_buf_mu;
 static std::map<uintptr_t, size_t> g_bufs;
+// set while a slot batch is issued: its launches span the slots, so an access may lie in an
+// enclosing buffer (a server slab, a batch region) rather than in the base slot's own array
+static thread_local bool g_enclosing_ok = false;
 
 bool dry_run() {
   static const bool on = [] {
@@ -78,17 +81,26 @@ bool range_ok(const void* base, long lo, long hi, size_t elem, const char* what)
     set_error(std::string(what) + ": pointer is not inside a registered buffer");
     return false;
   }
-  --it;
-  const long long first = (long long)b + (long long)lo * (long long)elem - (long long)it->first;
-  const long long last = (long long)b + ((long long)hi + 1) * (long long)elem - (long long)it->first;
-  if (first < 0 || last > (long long)it->second) {
-    char msg[256];
-    std::snprintf(msg, sizeof msg, "%s: elements [%ld, %ld] fall outside their %zu-byte buffer (byte range %lld..%lld)",
-                  what, lo, hi, it->second, first, last);
-    set_error(msg);
-    return false;
+  // the innermost buffer that starts at or below base is tried first; an access that spans the
+  // slots of a batch is accepted if an enclosing buffer (a server slab, a batch region) holds it
+  long long first = 0, last = 0;
+  size_t size0 = 0;
+  for (auto jt = std::prev(it);; --jt) {
+    const long long f = (long long)b + (long long)lo * (long long)elem - (long long)jt->first;
+    const long long l = (long long)b + ((long long)hi + 1) * (long long)elem - (long long)jt->first;
+    if (jt == std::prev(it)) {
+      first = f;
+      last = l;
+      size0 = jt->second;
+    }
+    if (f >= 0 && l <= (long long)jt->second) return true;
+    if (!g_enclosing_ok || jt == g_bufs.begin()) break;
   }
-  return true;
+  char msg[256];
+  std::snprintf(msg, sizeof msg, "%s: elements [%ld, %ld] fall outside their %zu-byte buffer (byte range %lld..%lld)",
+                what, lo, hi, size0, first, last);
+  set_error(msg);
+  return false;
 }
 
 // Runtime calls that are skipped in a dry run (and bounds-checked when checking is on).
@@ -405,11 +417,82 @@ inline Perm4In pin(const double* p, long s0, long s1, long s2, long s3, double c
   return x;
 }
 
-// FP64 contraction with the integral set's split-K scratch.
+// ---- slot batches ----------------------------------------------------------------------
+// A batched residual evaluates n slots -- amplitude sets whose arrays repeat one layout at fixed
+// byte strides -- in one pass: each contraction is one launch with an outer batch level over the
+// slots, and each element-wise step is issued once per slot.  The arrays the residual touches are
+// registered as address ranges of the base slot with their slot stride (0 for arrays the slots
+// share); slot z of a launch is table entry z (relative to the base slot).
+struct SlotRange {
+  uintptr_t lo, hi;
+  long stride;  // bytes
+};
+struct SlotBatch {
+  int n = 1;
+  const int* dtab = nullptr;  // device table of the n slots (nullptr: 0 .. n-1)
+  const int* htab = nullptr;  // its host copy
+  int tab_max = 0;
+  std::vector<SlotRange> ranges;
+  bool bad = false;  // a pointer outside every registered range was met
+};
+thread_local SlotBatch* g_sb = nullptr;
+thread_local int g_slot = 0;  // the slot an element-wise step is being issued for
+
+inline int nslots() { return g_sb ? g_sb->n : 1; }
+long slot_stride(const void* p) {
+  const uintptr_t x = reinterpret_cast<uintptr_t>(p);
+  for (const SlotRange& r : g_sb->ranges)
+    if (x >= r.lo && x < r.hi) return r.stride;
+  g_sb->bad = true;
+  return 0;
+}
+// p (an array of the base slot) in the slot of the element-wise step being issued
+template <class T>
+T* S(T* p) {
+  if (!g_sb || !p) return p;
+  if (g_slot < 0 || g_slot >= g_sb->n) {
+    g_sb->bad = true;
+    return p;
+  }
+  const long k = g_sb->htab ? g_sb->htab[g_slot] : g_slot;
+  return reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(p) + k * slot_stride(p));
+}
+#define EACH_SLOT for (g_slot = 0; g_slot < nslots(); ++g_slot)
+
+// FP64 contraction with the integral set's split-K scratch (shared by the slots of a batch).
 inline hipError_t mm(const ascc_ints* I, Gemm g, hipStream_t s) {
   g.ws = I->splitk;
   g.ws_elems = kSplitKElems;
+  if (nslots() > 1) {
+    if (g.nb1 != 1) return hipErrorInvalidValue;
+    const long a = slot_stride(g.A), b = slot_stride(g.B), c = slot_stride(g.C);
+    if (g_sb->bad || (a | b | c) % 8) return hipErrorInvalidValue;
+    g.nb1 = g_sb->n;
+    g.sa1 = a / 8;
+    g.sb1 = b / 8;
+    g.sc1 = c / 8;
+    g.tab1 = g_sb->dtab;
+    g.tab1_max = g_sb->tab_max;
+    g.per_block = true;  // each slot sums in the order it would alone
+  }
   return gemm_f64(g, s);
+}
+
+// Low-precision contraction, one launch over the slots of a batch.
+inline hipError_t glp(GemmLP g, hipStream_t s) {
+  if (nslots() > 1) {
+    const long el = g.prec == kPrecBF16x3 ? 2 : 4;  // operand strides count bf16 or FP32 elements
+    const long a = slot_stride(g.A), b = slot_stride(g.B), c = slot_stride(g.C);
+    if (g_sb->bad || a % el || b % el || c % 8) return hipErrorInvalidValue;
+    g.nb1 = g_sb->n;
+    g.sa1 = a / el;
+    g.sb1 = b / el;
+    g.sc1 = c / 8;
+    g.tab1 = g_sb->dtab;
+    g.tab1_max = g_sb->tab_max;
+    g.per_block = true;
+  }
+  return gemm_lowp(g, s);
 }
 
 // T1 dressing of `nb` stacked n x n matrices, dst = X src Y^T with X = 1 - F, Y^T = 1 + F and
@@ -435,7 +518,7 @@ int dress(const ascc_ints* I, const double* src, double* tc, double* dst, const 
   g.sc2 = n * o;
   g.nb2 = nb;
   HIPCHK(mm(I, g, s));
-  HIPCHK(dress_apply(dst, src, tc, t1, o, v, nb, s));
+  EACH_SLOT HIPCHK(dress_apply(S(dst), S(src), S(tc), S(t1), o, v, nb, s));
   return ASCC_OK;
 }
 
@@ -443,7 +526,7 @@ int dress(const ascc_ints* I, const double* src, double* tc, double* dst, const 
 int add_two_electron_fock(const ascc_ints* I, double* F, const double* Bq, double* J, int o, int v, int Q, double sign,
                           hipStream_t s) {
   const long n = o + v, nn = n * n;
-  HIPCHK(diag_trace(J, Bq, Q, n, o, s));
+  EACH_SLOT HIPCHK(diag_trace(S(J), S(Bq), Q, n, o, s));
   {
     Gemm g;
     g.M = 1;
@@ -522,13 +605,21 @@ int lowp_kind(const ascc_ints* I) { return (I->cur_prec == ASCC_PREC_BF16X3) ? k
 // Low-precision shadow of a transpose: out row r = column r of in ([cols][ldi]), leading dimension
 // lowp_ld(cols).
 hipError_t shadow_t(const ascc_ints* I, float* out, const double* in, long ldi, long rows, long cols, hipStream_t s) {
-  return to_lowp_t(lowp_kind(I), out, lowp_ld(cols), in, ldi, rows, cols, s);
+  EACH_SLOT {
+    const hipError_t e = to_lowp_t(lowp_kind(I), S(out), lowp_ld(cols), S(in), ldi, rows, cols, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // Low-precision shadow of rows x cols FP64 (contiguous rows) with leading dimension lowp_ld(cols).
 hipError_t shadow(const ascc_ints* I, float* out, const double* in, long rows, long cols, hipStream_t s) {
   const int prec = (I->cur_prec == ASCC_PREC_BF16X3) ? kPrecBF16x3 : kPrecFP32;
-  return to_lowp_2d(prec, out, lowp_ld(cols), in, cols, rows, cols, s);
+  EACH_SLOT {
+    const hipError_t e = to_lowp_2d(prec, S(out), lowp_ld(cols), S(in), cols, rows, cols, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // Particle-particle ladder RL_s[i][j][a][b] = sum_cd (t_s)_ij^cd (ac|bd) for S states in one
@@ -572,7 +663,46 @@ int pp_ladder_states(ascc_ints* I, int S, const double* const* t2s, double* cons
   return ASCC_OK;
 }
 
+// The ladder of every slot of a batch, each against its own integral set: the pair packing per
+// slot, one contraction launch over the slots, the unpacking per slot.
+int pp_ladder_slots(ascc_ints* I, const double* t2, hipStream_t s) {
+  const int o = I->no, v = I->nv;
+  const long To = (long)o * (o + 1) / 2, Tv = (long)v * (v + 1) / 2, M = To;
+  const bool lowp = I->cur_prec != ASCC_PREC_FP64;
+  const bool full = I->vvvv_mode == ASCC_VVVV_FULL;
+  const long ld = lowp_ld(Tv);
+  phase_begin(I, PH_PACK, s);
+  EACH_SLOT HIPCHK(pack_tpm(S(I->Tp), S(I->Tp) + M * Tv, S(t2), o, v, full ? 0.5 : 1.0, s));
+  if (lowp) HIPCHK(shadow(I, I->Tpf, I->Tp, 2 * M, Tv, s));
+  phase_end(I, s);
+  phase_begin(I, PH_LADDER, s);
+  if (lowp) {
+    GemmLP g = lp_nt(I, M, Tv, Tv, 2, I->Tpf, ld, M * ld, I->Vf, ld, Tv * ld, I->Rp, Tv, M * Tv);
+    g.ws = nullptr;
+    HIPCHK(glp(g, s));
+  } else {
+    LadderBatch lb;
+    lb.n = g_sb->n;
+    lb.tab = g_sb->dtab;
+    lb.tab_max = g_sb->tab_max;
+    lb.sa = slot_stride(I->Tp) / 8;
+    lb.sv = slot_stride(I->V) / 8;
+    lb.sc = slot_stride(I->Rp) / 8;
+    if (g_sb->bad) return fail(ASCC_E_STATE, "ladder operands outside the batch's slot ranges");
+    if (full)
+      HIPCHK(gemm_f64_ladder((int)M, (int)Tv, I->Tp, I->V, I->vv, I->vv, pair_minus(I), I->Rp, s, lb));
+    else
+      HIPCHK(gemm_f64_ladder((int)M, (int)Tv, I->Tp, I->V, Tv, 0, nullptr, I->Rp, s, lb));
+  }
+  phase_end(I, s);
+  phase_begin(I, PH_UNPACK, s);
+  EACH_SLOT HIPCHK(unpack_rpm(S(I->RL), S(I->Rp), S(I->Rp) + M * Tv, o, v, s));
+  phase_end(I, s);
+  return ASCC_OK;
+}
+
 int pp_ladder(ascc_ints* I, const double* t2, hipStream_t s) {
+  if (nslots() > 1) return pp_ladder_slots(I, t2, s);
   double* RL = I->RL;
   return pp_ladder_states(I, 1, &t2, &RL, I->Tp, I->Rp, I->Tpf, s);
 }
@@ -726,19 +856,19 @@ int residual_core(ascc_ints* I, const double* t1, const double* t2, double* r1, 
   if ((rc = add_two_electron_fock(I, I->Fh, I->Bh, I->J, o, v, Q, 1.0, s))) return rc;
 
   // --- contiguous dressed blocks
-  {
+  EACH_SLOT {
     int d[4] = {o, v, Q, 1};
-    Perm4In x = pin(I->Bh + o * n, 1, n, nn, 0, 1.0);  // B^_ai -> [i][a][Q]
-    HIPCHK(permute4(I->BvoTt, d, 0.0, &x, 1, s));
+    Perm4In x = pin(S(I->Bh) + o * n, 1, n, nn, 0, 1.0);  // B^_ai -> [i][a][Q]
+    HIPCHK(permute4(S(I->BvoTt), d, 0.0, &x, 1, s));
     int d2[4] = {Q, o, o, 1};
-    x = pin(I->Bh, nn, n, 1, 0, 1.0);
-    HIPCHK(permute4(I->Boo, d2, 0.0, &x, 1, s));
+    x = pin(S(I->Bh), nn, n, 1, 0, 1.0);
+    HIPCHK(permute4(S(I->Boo), d2, 0.0, &x, 1, s));
     int d3[4] = {Q, v, v, 1};
-    x = pin(I->Bh + o * n + o, nn, n, 1, 0, 1.0);
-    HIPCHK(permute4(I->Bvv, d3, 0.0, &x, 1, s));
+    x = pin(S(I->Bh) + o * n + o, nn, n, 1, 0, 1.0);
+    HIPCHK(permute4(S(I->Bvv), d3, 0.0, &x, 1, s));
     int d4[4] = {o, v, 1, 1};
-    x = pin(I->Fh + o, n, 1, 0, 0, 1.0);  // F^_kc
-    HIPCHK(permute4(I->Fovh, d4, 0.0, &x, 1, s));
+    x = pin(S(I->Fh) + o, n, 1, 0, 0, 1.0);  // F^_kc
+    HIPCHK(permute4(S(I->Fovh), d4, 0.0, &x, 1, s));
   }
 
   phase_end(I, s);
@@ -746,13 +876,13 @@ int residual_core(ascc_ints* I, const double* t1, const double* t2, double* r1, 
   phase_begin(I, PH_AMP, s);
   double* Tx = I->TU;
   double* U = I->TU + ovov;
-  {
+  EACH_SLOT {
     int d[4] = {o, v, o, v};
     const long si = (long)o * vv, sj = vv;
-    Perm4In x = pin(t2, si, 1, sj, v, 1.0);
-    HIPCHK(permute4(Tx, d, 0.0, &x, 1, s));
-    Perm4In y[2] = {pin(t2, si, v, sj, 1, 2.0), pin(t2, si, 1, sj, v, -1.0)};
-    HIPCHK(permute4(U, d, 0.0, y, 2, s));
+    Perm4In x = pin(S(t2), si, 1, sj, v, 1.0);
+    HIPCHK(permute4(S(Tx), d, 0.0, &x, 1, s));
+    Perm4In y[2] = {pin(S(t2), si, v, sj, 1, 2.0), pin(S(t2), si, 1, sj, v, -1.0)};
+    HIPCHK(permute4(S(U), d, 0.0, y, 2, s));
   }
   const bool lowp = I->cur_prec != ASCC_PREC_FP64;
   const long lov = lowp_ld(ov), lQ = lowp_ld(Q), loo = lowp_ld(oo);
@@ -768,10 +898,10 @@ int residual_core(ascc_ints* I, const double* t1, const double* t2, double* r1, 
     HIPCHK(shadow(I, I->BvoTtf, I->BvoTt, ov, Q, s));
     HIPCHK(shadow_t(I, I->BooTf, I->Boo, oo, oo, Q, s));
     HIPCHK(shadow_t(I, I->BvvTf, I->Bvv, vv, vv, Q, s));
-    HIPCHK(gemm_lowp(lp_nt(I, oo, vv, Q, 1, I->BooTf, lQ, 0, I->BvvTf, lQ, 0, I->G2, vv, 0), s));    // g^_kiac
-    HIPCHK(gemm_lowp(lp_nt(I, ov, ov, Q, 1, I->BvoTtf, lQ, 0, I->BovTf, lQ, 0, I->G3, ov, 0), s));   // g^_aikc
+    HIPCHK(glp(lp_nt(I, oo, vv, Q, 1, I->BooTf, lQ, 0, I->BvvTf, lQ, 0, I->G2, vv, 0), s));    // g^_kiac
+    HIPCHK(glp(lp_nt(I, ov, ov, Q, 1, I->BvoTtf, lQ, 0, I->BovTf, lQ, 0, I->G3, ov, 0), s));   // g^_aikc
     // N_Q[k,a] = sum_lc B_Q,lc u_kl^ac: U is a symmetric ov x ov matrix, so its rows are its columns
-    HIPCHK(gemm_lowp(lp_nt(I, Q, ov, ov, 1, I->Bovf, lov, 0, I->TUf + ov * lov, lov, 0, I->Nq, ov, 0), s));
+    HIPCHK(glp(lp_nt(I, Q, ov, ov, 1, I->Bovf, lov, 0, I->TUf + ov * lov, lov, 0, I->Nq, ov, 0), s));
   } else {
     HIPCHK(mm(I, gemm_rm(oo, vv, Q, 1.0, I->Boo, oo, true, I->Bvv, vv, false, 0.0, I->G2, vv), s));    // g^_kiac
     HIPCHK(mm(I, gemm_rm(ov, ov, Q, 1.0, I->BvoTt, Q, false, I->BovT, Q, true, 0.0, I->G3, ov), s));   // g^_aikc
@@ -786,7 +916,7 @@ int residual_core(ascc_ints* I, const double* t1, const double* t2, double* r1, 
   if (lowp) {
     const long ld = lowp_ld(vv);
     HIPCHK(shadow(I, I->t2f, t2, oo, vv, s));
-    HIPCHK(gemm_lowp(lp_nt(I, oo, wzl, vv, 1, I->t2f, ld, 0, I->GwzTf, ld, 0, I->WZ, wzl, 0), s));
+    HIPCHK(glp(lp_nt(I, oo, wzl, vv, 1, I->t2f, ld, 0, I->GwzTf, ld, 0, I->WZ, wzl, 0), s));
   } else {
     HIPCHK(mm(I, gemm_rm(oo, wzl, vv, 1.0, t2, vv, false, I->Gwz, vv, true, 0.0, I->WZ, wzl), s));
   }
@@ -794,11 +924,11 @@ int residual_core(ascc_ints* I, const double* t1, const double* t2, double* r1, 
   phase_end(I, s);
   // --- chi[ij][kl] = g^_kilj + Z_ij[k,l]
   phase_begin(I, PH_HH, s);
-  {
+  EACH_SLOT {
     int d[4] = {o, o, o, o};
     const long o2 = oo, o3 = oo * o;
-    Perm4In x[2] = {pin(I->G4, o2, 1, o3, o, 1.0), pin(I->WZ + ov, (long)o * wzl, wzl, o, 1, 1.0)};
-    HIPCHK(permute4(I->chi, d, 0.0, x, 2, s));
+    Perm4In x[2] = {pin(S(I->G4), o2, 1, o3, o, 1.0), pin(S(I->WZ) + ov, (long)o * wzl, wzl, o, 1, 1.0)};
+    HIPCHK(permute4(S(I->chi), d, 0.0, x, 2, s));
   }
 
   phase_end(I, s);
@@ -810,7 +940,7 @@ int residual_core(ascc_ints* I, const double* t1, const double* t2, double* r1, 
     HIPCHK(shadow_t(I, I->t2Tf, t2, vv, vv, oo, s));
     GemmLP g = lp_nt(I, oo, vv, oo, 1, I->chif, loo, 0, I->t2Tf, loo, 0, RL, vv, 0);
     g.beta = 1.0;
-    HIPCHK(gemm_lowp(g, s));
+    HIPCHK(glp(g, s));
   } else {
     HIPCHK(mm(I, gemm_rm(oo, vv, oo, 1.0, I->chi, oo, false, t2, vv, false, 1.0, RL, vv), s));
   }
@@ -820,7 +950,7 @@ int residual_core(ascc_ints* I, const double* t1, const double* t2, double* r1, 
   phase_begin(I, PH_RING_Y, s);
   if (lowp) {  // K and L are symmetric matrices, so B[n][k] = B[k][n]
     const long ld = lov;
-    HIPCHK(gemm_lowp(lp_nt(I, ov, ov, ov, 2, I->TUf, ld, ov * ld, I->KLf, ld, ov * ld, I->Y, ov, ovov), s));
+    HIPCHK(glp(lp_nt(I, ov, ov, ov, 2, I->TUf, ld, ov * ld, I->KLf, ld, ov * ld, I->Y, ov, ovov), s));
   } else {
     // K and L are symmetric, so B(k, n) = KL[n][k]: both operands K-contiguous
     Gemm g = gemm_rm(ov, ov, ov, 1.0, I->TU, ov, false, I->KL, ov, true, 0.0, I->Y, ov);
@@ -832,21 +962,21 @@ int residual_core(ascc_ints* I, const double* t1, const double* t2, double* r1, 
   }
   phase_end(I, s);
   phase_begin(I, PH_RING_XZ, s);
-  {
+  EACH_SLOT {
     int d[4] = {o, v, o, v};  // (i, a, k, c)
     const long si = vv, sa = v, sk = (long)o * vv, sc = 1;  // G2[k][i][a][c]
-    Perm4In x[2] = {pin(I->G2, si, sa, sk, sc, 1.0), pin(I->Y, (long)v * o * v, (long)o * v, v, 1, -0.5)};
-    HIPCHK(permute4(I->XZ, d, 0.0, x, 2, s));
-    Perm4In z[3] = {pin(I->G3, (long)v * o * v, (long)o * v, v, 1, 2.0), pin(I->G2, si, sa, sk, sc, -1.0),
-                    pin(I->Y + ovov, (long)v * o * v, (long)o * v, v, 1, 0.5)};
-    HIPCHK(permute4(I->XZ + ovov, d, 0.0, z, 3, s));
+    Perm4In x[2] = {pin(S(I->G2), si, sa, sk, sc, 1.0), pin(S(I->Y), (long)v * o * v, (long)o * v, v, 1, -0.5)};
+    HIPCHK(permute4(S(I->XZ), d, 0.0, x, 2, s));
+    Perm4In z[3] = {pin(S(I->G3), (long)v * o * v, (long)o * v, v, 1, 2.0), pin(S(I->G2), si, sa, sk, sc, -1.0),
+                    pin(S(I->Y) + ovov, (long)v * o * v, (long)o * v, v, 1, 0.5)};
+    HIPCHK(permute4(S(I->XZ) + ovov, d, 0.0, z, 3, s));
   }
   phase_end(I, s);
   phase_begin(I, PH_RING_P, s);
   if (lowp) {  // P1 = Tx Xc^T, P2 = U Zd^T
     const long ld = lowp_ld(ov);
     HIPCHK(shadow(I, I->XZf, I->XZ, 2 * ov, ov, s));
-    HIPCHK(gemm_lowp(lp_nt(I, ov, ov, ov, 2, I->TUf, ld, ov * ld, I->XZf, ld, ov * ld, I->P, ov, ovov), s));
+    HIPCHK(glp(lp_nt(I, ov, ov, ov, 2, I->TUf, ld, ov * ld, I->XZf, ld, ov * ld, I->P, ov, ovov), s));
   } else {
     Gemm g = gemm_rm(ov, ov, ov, 1.0, I->TU, ov, false, I->XZ, ov, true, 0.0, I->P, ov);
     g.sa2 = ovov;
@@ -879,13 +1009,13 @@ int residual_core(ascc_ints* I, const double* t1, const double* t2, double* r1, 
     g.nred = Q;
     HIPCHK(mm(I, g, s));
   }
-  {
+  EACH_SLOT {
     int d[4] = {v, v, 1, 1};
-    Perm4In x[2] = {pin(I->Fh + o * n + o, n, 1, 0, 0, 1.0), pin(I->Abc, v, 1, 0, 0, -1.0)};
-    HIPCHK(permute4(I->Fvvp, d, 0.0, x, 2, s));
+    Perm4In x[2] = {pin(S(I->Fh) + o * n + o, n, 1, 0, 0, 1.0), pin(S(I->Abc), v, 1, 0, 0, -1.0)};
+    HIPCHK(permute4(S(I->Fvvp), d, 0.0, x, 2, s));
     int d2[4] = {o, o, 1, 1};
-    Perm4In y[2] = {pin(I->Fh, n, 1, 0, 0, 1.0), pin(I->Bkj, o, 1, 0, 0, 1.0)};
-    HIPCHK(permute4(I->Foop, d2, 0.0, y, 2, s));
+    Perm4In y[2] = {pin(S(I->Fh), n, 1, 0, 0, 1.0), pin(S(I->Bkj), o, 1, 0, 0, 1.0)};
+    HIPCHK(permute4(S(I->Foop), d2, 0.0, y, 2, s));
   }
   // EM = sum_c t_ij^ac F'_bc
   HIPCHK(mm(I, gemm_rm(oo * v, v, v, 1.0, t2, v, false, I->Fvvp, v, true, 0.0, I->EM, v), s));
@@ -955,6 +1085,7 @@ int residual_core(ascc_ints* I, const double* t1, const double* t2, double* r1, 
 
   phase_end(I, s);
   if (I->pl_hole >= 0) {
+    if (nslots() > 1) return fail(ASCC_E_STATE, "the PLASCC removal is not evaluated in a slot batch");
     phase_begin(I, PH_PLASCC, s);
     if ((rc = plascc_remove(I, t2, RL, s))) return rc;
     phase_end(I, s);
@@ -999,15 +1130,16 @@ int residual_core(ascc_ints* I, const double* t1, const double* t2, double* r1, 
     g.beta = 1.0;
     HIPCHK(mm(I, g, s));
   }
-  HIPCHK(add_fvo(r1, I->Fh, o, v, s));
+  EACH_SLOT HIPCHK(add_fvo(S(r1), S(I->Fh), o, v, s));
 
   phase_end(I, s);
   // --- doubles assembly and energy
   phase_begin(I, PH_ASSEMBLE, s);
-  HIPCHK(assemble_r2(r2, I->G1, RL, I->EM, I->P, I->P + ovov, o, v, s));
+  EACH_SLOT HIPCHK(assemble_r2(S(r2), S(I->G1), S(RL), S(I->EM), S(I->P), S(I->P) + ovov, o, v, s));
   phase_end(I, s);
   phase_begin(I, PH_ENERGY, s);
-  HIPCHK(energy(e, I->partial, t1, t2, I->Lijab, I->fov, o, v, s));
+  EACH_SLOT HIPCHK(energy(S(e), S(I->partial), S(t1), S(t2), S(I->Lijab), S(I->fov), o, v, s));
+  if (g_sb && g_sb->bad) return fail(ASCC_E_STATE, "a residual array lies outside the batch's slot ranges");
   phase_end(I, s);
   return ASCC_OK;
 }
@@ -1016,6 +1148,20 @@ int residual_fp64(ascc_ints* I, const double* t1, const double* t2, double* r1, 
                   hipStream_t s) {
   return residual_core(I, t1, t2, r1, r2, e, nullptr, s);
 }
+
+// Clears the slot-batch context however the batched pass ends.
+struct SlotBatchScope {
+  explicit SlotBatchScope(SlotBatch* b) {
+    g_sb = b;
+    g_slot = 0;
+    g_enclosing_ok = true;
+  }
+  ~SlotBatchScope() {
+    g_sb = nullptr;
+    g_slot = 0;
+    g_enclosing_ok = false;
+  }
+};
 
 // hole >= 0: the integrals of Hbar = e^{S^dagger} H e^{-S^dagger} for S = (s/sqrt 2) sum_spin p^dagger h
 // (hole h occupied, particle p virtual, s = s_sign = +-1; Sec. II.A, Eqs. (eqn:1CSF-S), (eqn: sim)).
@@ -1672,6 +1818,61 @@ int ascc_update(ascc_ints* I, ascc_diis* D, double* t1, double* t2, const double
 namespace ascc {
 
 uintptr_t dry_run_address(size_t bytes) { return fake_alloc(bytes); }
+
+int iterate_slots(ascc_ints* I, ascc_diis* D, int n, const int* dtab, const int* htab, const char* region,
+                  long stride, double* t1, double* t2, double* r1, double* r2, double* e, double* stats,
+                  hipStream_t s) {
+  if (!I || !D || n < 1 || !htab || !region || stride <= 0 || !t1 || !t2 || !r1 || !r2 || !e || !stats)
+    return fail(ASCC_E_ARG, "invalid slot batch");
+  if (D->no != I->no || D->nv != I->nv) return fail(ASCC_E_STATE, "DIIS state and integrals differ in shape");
+  SlotBatch sb;
+  sb.n = n;
+  sb.dtab = dtab;
+  sb.htab = htab;
+  for (int z = 0; z < n; ++z) {
+    if (htab[z] < 0) return fail(ASCC_E_ARG, "slot table entries are offsets from the base slot (>= 0)");
+    sb.tab_max = std::max(sb.tab_max, htab[z]);
+  }
+  const uintptr_t lo = reinterpret_cast<uintptr_t>(region);
+  sb.ranges.push_back({lo, lo + (uintptr_t)stride, stride});
+  int rc;
+  {
+    SlotBatchScope scope(&sb);
+    rc = residual_core(I, t1, t2, r1, r2, e, nullptr, s);
+  }
+  if (rc) return rc;
+  UpdateArgs u;
+  u.t1 = t1;
+  u.t2 = t2;
+  u.r1 = r1;
+  u.r2 = r2;
+  u.e = e;
+  u.eps = I->eps;
+  u.hist_t = D->hist_t;
+  u.hist_e = D->hist_e;
+  u.partial = D->partial;
+  u.st = D->st;
+  u.stats = stats;
+  u.no = I->no;
+  u.nv = I->nv;
+  u.m = D->m;
+  u.start = D->start;
+  u.len = D->len;
+  u.shift = 0.0;
+  u.nslot = n;
+  u.ss = stride;
+  u.tab = dtab;
+  u.tab_max = sb.tab_max;
+  phase_begin(I, PH_UPDATE, s);
+  {
+    g_enclosing_ok = true;
+    const hipError_t e2 = diis_update(u, s);
+    g_enclosing_ok = false;
+    HIPCHK(e2);
+  }
+  phase_end(I, s);
+  return ASCC_OK;
+}
 
 // Device bytes of the solver state that solve_impl carves from a workspace: the DIIS state, then
 // r1, r2, e, the statistics block and the trial amplitudes t1s, t2s.

@@ -6,6 +6,8 @@
 #include <algorithm>
 #include <cmath>
 
+#include <type_traits>
+
 #include "internal.h"
 
 namespace ascc {
@@ -371,9 +373,29 @@ struct UK {
   int o, v, m, start, nstat;
   long len;
   double shift;
+  long ss;         // byte stride between the slots of a batched update (0: one slot)
+  const int* tab;  // slot of grid row blockIdx.y (nullptr: blockIdx.y)
 };
 
+// The same pointer in slot k of a batched update (slots at a fixed byte stride).
+template <class T>
+__device__ __forceinline__ T* in_slot(T* p, long k, long ss) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(const_cast<typename std::remove_const<T>::type*>(p)) + k * ss);
+}
+
 __global__ __launch_bounds__(kThreads) void update_stage1(UK p) {
+  if (p.ss) {  // this grid row's slot
+    const long k = p.tab ? p.tab[blockIdx.y] : blockIdx.y;
+    p.t1 = in_slot(p.t1, k, p.ss);
+    p.t2 = in_slot(p.t2, k, p.ss);
+    p.r1 = in_slot(p.r1, k, p.ss);
+    p.r2 = in_slot(p.r2, k, p.ss);
+    p.eps = in_slot(p.eps, k, p.ss);
+    p.hist_t = in_slot(p.hist_t, k, p.ss);
+    p.hist_e = in_slot(p.hist_e, k, p.ss);
+    p.partial = in_slot(p.partial, k, p.ss);
+    p.st = in_slot(p.st, k, p.ss);
+  }
   __shared__ double sh[kThreads / 64];
   const int head = p.st->head;
   const bool store = p.st->calls >= p.start;  // decided on the device, so a captured graph replays it
@@ -472,7 +494,14 @@ __device__ bool diis_solve(DiisState* st, int m, double* A, double* xs) {
 
 __global__ __launch_bounds__(kThreads) void update_stage2(DiisState* st, const double* partial, int nblk, int nstat,
                                                          int m, int start, const double* e, double* stats,
-                                                         double shift) {
+                                                         double shift, long ss, const int* tab) {
+  if (ss) {  // this grid row's slot; its statistics block is row k of stats
+    const long k = tab ? tab[blockIdx.y] : blockIdx.y;
+    st = in_slot(st, k, ss);
+    partial = in_slot(partial, k, ss);
+    e = in_slot(e, k, ss);
+    stats += 8 * k;
+  }
   const bool store = st->calls >= start;
   __shared__ double sh[kThreads / 64];
   __shared__ double red[3 + kMaxDiis];
@@ -540,7 +569,15 @@ __global__ __launch_bounds__(kThreads) void update_stage2(DiisState* st, const d
 
 // t <- sum_k coef[k] hist_t[k] once two or more pairs are stored (no-op otherwise).
 __global__ __launch_bounds__(kThreads) void update_stage3(double* t1, double* t2, const double* hist_t,
-                                                         const DiisState* st, int m, long ov, long len) {
+                                                         const DiisState* st, int m, long ov, long len, long ss,
+                                                         const int* tab) {
+  if (ss) {
+    const long k = tab ? tab[blockIdx.y] : blockIdx.y;
+    t1 = in_slot(t1, k, ss);
+    t2 = in_slot(t2, k, ss);
+    hist_t = in_slot(hist_t, k, ss);
+    st = in_slot(st, k, ss);
+  }
   if (st->nvec < 2 || (st->flags & 1)) return;
   double c[kMaxDiis];
   for (int k = 0; k < kMaxDiis; ++k) c[k] = (k < m) ? st->coef[k] : 0.0;
@@ -1219,23 +1256,35 @@ hipError_t diis_update(const UpdateArgs& u, hipStream_t s) {
   p.nstat = 3 + kMaxDiis;
   p.len = u.len;
   p.shift = u.shift;
+  p.ss = u.nslot > 1 || u.tab ? u.ss : 0;
+  p.tab = u.tab;
   const long ov = (long)u.no * u.nv;
-  if (bounds_checking() &&
-      !(range_ok(u.t1, 0, ov - 1, 8, "update t1") && range_ok(u.t2, 0, u.len - ov - 1, 8, "update t2") &&
-        range_ok(u.r1, 0, ov - 1, 8, "update r1") && range_ok(u.r2, 0, u.len - ov - 1, 8, "update r2") &&
-        range_ok(u.e, 0, 0, 8, "update e") && range_ok(u.eps, 0, u.no + u.nv - 1, 8, "update eps") &&
-        range_ok(u.hist_t, 0, (long)u.m * u.len - 1, 8, "update hist_t") &&
-        range_ok(u.hist_e, 0, (long)u.m * u.len - 1, 8, "update hist_e") &&
-        range_ok(u.partial, 0, (long)kRedBlocks * (3 + kMaxDiis) - 1, 8, "update partial") &&
-        range_ok(u.st, 0, 0, sizeof(DiisState), "update state") && range_ok(u.stats, 0, 7, 8, "update stats")))
-    return hipErrorInvalidValue;
+  if (u.nslot < 1 || u.nslot > 65535 || (p.ss % 8)) return hipErrorInvalidValue;
+  if (bounds_checking()) {
+    // every slot the table can name (or every grid row), each checked where it lies
+    const long nk = u.tab ? u.tab_max + 1 : u.nslot;
+    for (long k = 0; k < (p.ss ? nk : 1); ++k) {
+      const long o8 = k * p.ss / 8;  // slot offset in doubles
+      auto at = [&](const void* q) { return reinterpret_cast<const char*>(q) + k * p.ss; };
+      if (!(range_ok(at(u.t1), 0, ov - 1, 8, "update t1") && range_ok(at(u.t2), 0, u.len - ov - 1, 8, "update t2") &&
+            range_ok(at(u.r1), 0, ov - 1, 8, "update r1") && range_ok(at(u.r2), 0, u.len - ov - 1, 8, "update r2") &&
+            range_ok(at(u.e), 0, 0, 8, "update e") && range_ok(at(u.eps), 0, u.no + u.nv - 1, 8, "update eps") &&
+            range_ok(at(u.hist_t), 0, (long)u.m * u.len - 1, 8, "update hist_t") &&
+            range_ok(at(u.hist_e), 0, (long)u.m * u.len - 1, 8, "update hist_e") &&
+            range_ok(at(u.partial), 0, (long)kRedBlocks * (3 + kMaxDiis) - 1, 8, "update partial") &&
+            range_ok(at(u.st), 0, 0, sizeof(DiisState), "update state") &&
+            range_ok(u.stats, 8 * (p.ss ? k : 0), 8 * (p.ss ? k : 0) + 7, 8, "update stats")))
+        return hipErrorInvalidValue;
+      (void)o8;
+    }
+  }
   if (u.m < 1 || u.m > kMaxDiis) return hipErrorInvalidValue;
   if (dry_run()) return hipSuccess;
-  hipLaunchKernelGGL(update_stage1, dim3(kRedBlocks), dim3(kThreads), 0, s, p);
-  hipLaunchKernelGGL(update_stage2, dim3(1), dim3(kThreads), 0, s, u.st, u.partial, kRedBlocks, 3 + kMaxDiis,
-                     u.m, u.start, u.e, u.stats, u.shift);
-  hipLaunchKernelGGL(update_stage3, dim3(grid_for(u.len)), dim3(kThreads), 0, s, u.t1, u.t2, u.hist_t, u.st, u.m,
-                     (long)u.no * u.nv, u.len);
+  hipLaunchKernelGGL(update_stage1, dim3(kRedBlocks, u.nslot), dim3(kThreads), 0, s, p);
+  hipLaunchKernelGGL(update_stage2, dim3(1, u.nslot), dim3(kThreads), 0, s, u.st, u.partial, kRedBlocks, 3 + kMaxDiis,
+                     u.m, u.start, u.e, u.stats, u.shift, p.ss, u.tab);
+  hipLaunchKernelGGL(update_stage3, dim3(grid_for(u.len), u.nslot), dim3(kThreads), 0, s, u.t1, u.t2, u.hist_t, u.st,
+                     u.m, (long)u.no * u.nv, u.len, p.ss, u.tab);
   return hipGetLastError();
 }
 

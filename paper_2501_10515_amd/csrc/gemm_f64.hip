@@ -42,6 +42,7 @@ struct GP {
   int split, it_per_split;  // split-K: slices of the (nred x K-tile) iteration space
   double* part;             // partial tiles [split][nb1*nb2][M][N] when split > 1
   const int* pm;            // pair-combined B (ladder): second row of pair n
+  const int* tab1;          // batch level 1: operand block of grid index z1 (nullptr: z1 itself)
 };
 
 // Workgroup-to-tile map.  Workgroups are dispatched to the 8 XCDs round-robin; each XCD gets
@@ -96,9 +97,10 @@ __global__ __launch_bounds__(WM* WN * 64, MINB) void gemm_f64_kernel(GP p) {
   tile_of(bid - slice * ntiles, p.tiles_m, p.tiles_n, tm, tn);
   const int m0 = tm * BM, n0 = tn * BN;
   const int z1 = blockIdx.z;
-  const double* Ab = p.A + z1 * p.sa1 + z2 * p.sa2;
-  const double* Bb = p.B + z1 * p.sb1 + z2 * p.sb2;
-  double* Cb = p.C + z1 * p.sc1 + z2 * p.sc2;
+  const int zs = p.tab1 ? p.tab1[z1] : z1;  // operand block of batch level 1
+  const double* Ab = p.A + zs * p.sa1 + z2 * p.sa2;
+  const double* Bb = p.B + zs * p.sb1 + z2 * p.sb2;
+  double* Cb = p.C + zs * p.sc1 + z2 * p.sc2;
 
   // acc[i][j]: register r of lane l holds C(16i + l/16 + 4r, 16j + l%16) of the wave's tile
   typedef double d4 __attribute__((ext_vector_type(4)));
@@ -248,19 +250,22 @@ __global__ __launch_bounds__(256) void splitk_reduce(GP p, int nb1, long total) 
   const long zl = x / mn, r = x % mn;
   const int gm = r / p.N, gn = r % p.N;
   const int z1 = zl / p.nb2, z2 = zl % p.nb2;
-  double* c = p.C + z1 * p.sc1 + z2 * p.sc2 + gm * p.scm + gn * p.scn;
+  const int zs = p.tab1 ? p.tab1[z1] : z1;
+  double* c = p.C + zs * p.sc1 + z2 * p.sc2 + gm * p.scm + gn * p.scn;
   *c = (p.beta == 0.0) ? sum : sum + p.beta * *c;
 }
 
 // grid of splitk_reduce for `outs` outputs
 inline unsigned splitk_blocks(long outs) { return (unsigned)((outs + 63) / 64); }
 
+// nb1d: the outer batch count the split-K decision is made for (1: as for one operand block, so a
+// block's sums take the same order whatever the batch; nb1 otherwise).
 template <int BM, int BN, int BK, int WM, int WN, int MINB>
-hipError_t launch_cfg(const GP& p0, bool amf, bool bnf, int nb1, double* ws, long ws_elems, hipStream_t s) {
+hipError_t launch_cfg(const GP& p0, bool amf, bool bnf, int nb1, int nb1d, double* ws, long ws_elems, hipStream_t s) {
   GP p = p0;
   p.tiles_m = (p.M + BM - 1) / BM;
   p.tiles_n = (p.N + BN - 1) / BN;
-  const long tiles = (long)p.tiles_m * p.tiles_n * p.nb2 * nb1;
+  const long tiles = (long)p.tiles_m * p.tiles_n * p.nb2 * nb1d;
   const int nit = ((p.K + BK - 1) / BK) * p.nred;
   p.split = 1;
   p.it_per_split = nit;
@@ -341,9 +346,10 @@ __global__ __launch_bounds__(WM* WN * 64, 1) void gemm_f64_dma_kernel(GP p) {
   tile_of(bid - slice * ntiles, p.tiles_m, p.tiles_n, tm, tn);
   const int m0 = tm * BM, n0 = tn * BN;
   const int z1 = blockIdx.z;
-  const double* Ab = p.A + z1 * p.sa1 + z2 * p.sa2;
-  const double* Bb = p.B + z1 * p.sb1 + z2 * p.sb2;
-  double* Cb = p.C + z1 * p.sc1 + z2 * p.sc2;
+  const int zs = p.tab1 ? p.tab1[z1] : z1;  // operand block of batch level 1
+  const double* Ab = p.A + zs * p.sa1 + z2 * p.sa2;
+  const double* Bb = p.B + zs * p.sb1 + z2 * p.sb2;
+  double* Cb = p.C + zs * p.sc1 + z2 * p.sc2;
 
   // the source row (chunk included) of this lane in each instruction its wave issues
   const double* src[NPW];
@@ -488,8 +494,8 @@ hipError_t launch_dma(GP p, int nb1, bool pm, int split, double* ws, hipStream_t
 // Direct-to-LDS launch for a non-pair-combined contraction: the tile (192 x 192, 256 x 128 or
 // 224 x 128) and split-K count with the least estimated time = whole rounds of 256 workgroups x
 // tile area x K-stages per slice; split-K only with scratch, when the tiles cannot fill one round.
-hipError_t launch_dma_auto(const GP& p, int nb1, double* ws, long ws_elems, hipStream_t s) {
-  const long nbatch = (long)p.nb2 * nb1, outs = (long)p.M * p.N * nbatch;
+hipError_t launch_dma_auto(const GP& p, int nb1, int nb1d, double* ws, long ws_elems, hipStream_t s) {
+  const long nbatch = (long)p.nb2 * nb1d, outs = (long)p.M * p.N * p.nb2 * nb1;
   const int nkt = (p.K + 7) / 8;
   int best = -1, best_split = 1;
   double best_cost = 0.0;
@@ -515,7 +521,7 @@ hipError_t launch_dma_auto(const GP& p, int nb1, double* ws, long ws_elems, hipS
 
 // Ladder: BM x 128 tiles of 8 waves, both halves (grid.y = 2), no split-K, A/B staged k-fast.
 template <int BM, int WM>
-hipError_t launch_ladder(GP p, bool pm, hipStream_t s) {
+hipError_t launch_ladder(GP p, int nb1, bool pm, hipStream_t s) {
   constexpr int BK = 16, WN = 8 / WM;
   p.tiles_m = (p.M + BM - 1) / BM;
   p.tiles_n = (p.N + 127) / 128;
@@ -524,7 +530,7 @@ hipError_t launch_ladder(GP p, bool pm, hipStream_t s) {
   p.part = nullptr;
   const int tiles = p.tiles_m * p.tiles_n;
   // pair-combined: the two halves interleave in grid.x (see the kernel), padded to groups of 8
-  dim3 grid(pm ? 2 * ((tiles + 7) / 8 * 8) : tiles, pm ? 1 : 2, 1), block(512);
+  dim3 grid(pm ? 2 * ((tiles + 7) / 8 * 8) : tiles, pm ? 1 : 2, nb1), block(512);
   if (pm)
     hipLaunchKernelGGL((gemm_f64_kernel<BM, 128, BK, WM, WN, 1, false, false, true>), grid, block, 0, s, p);
   else
@@ -575,13 +581,14 @@ static void affine_range(const long* ext, const long* str, int n, long& lo, long
 
 static bool gemm_in_bounds(const Gemm& g) {
   long lo, hi;
-  const long ea[5] = {g.M, g.K, g.nb1, g.nb2, g.nred}, sa[5] = {g.sam, g.sak, g.sa1, g.sa2, g.sar};
+  const long e1 = g.tab1 ? g.tab1_max + 1 : g.nb1;  // batch level 1 spans the table's entries
+  const long ea[5] = {g.M, g.K, e1, g.nb2, g.nred}, sa[5] = {g.sam, g.sak, g.sa1, g.sa2, g.sar};
   affine_range(ea, sa, 5, lo, hi);
   if (!range_ok(g.A, lo, hi, sizeof(double), "gemm A")) return false;
-  const long eb[5] = {g.K, g.N, g.nb1, g.nb2, g.nred}, sb[5] = {g.sbk, g.sbn, g.sb1, g.sb2, g.sbr};
+  const long eb[5] = {g.K, g.N, e1, g.nb2, g.nred}, sb[5] = {g.sbk, g.sbn, g.sb1, g.sb2, g.sbr};
   affine_range(eb, sb, 5, lo, hi);
   if (!range_ok(g.B, lo, hi, sizeof(double), "gemm B")) return false;
-  const long ec[4] = {g.M, g.N, g.nb1, g.nb2}, sc[4] = {g.scm, g.scn, g.sc1, g.sc2};
+  const long ec[4] = {g.M, g.N, e1, g.nb2}, sc[4] = {g.scm, g.scn, g.sc1, g.sc2};
   affine_range(ec, sc, 4, lo, hi);
   if (!range_ok(g.C, lo, hi, sizeof(double), "gemm C")) return false;
   return !g.ws || range_ok(g.ws, 0, g.ws_elems - 1, sizeof(double), "gemm split-K scratch");
@@ -592,7 +599,8 @@ hipError_t gemm_f64(const Gemm& g, hipStream_t s) {
   if (bounds_checking() && !gemm_in_bounds(g)) return hipErrorInvalidValue;
   if (dry_run()) return hipSuccess;
   if (g.nb1 > 65535 || g.nb2 > 65535) return hipErrorInvalidValue;
-  const int nbatch = g.nb1 * g.nb2;
+  // tile and split-K choices: for the whole batch, or as for one block of the outer level
+  const int nb1d = g.per_block ? 1 : g.nb1, nbatch = nb1d * g.nb2;
   if (g.K <= 0 || g.nred <= 0) return hipErrorInvalidValue;  // callers never pass an empty contraction
   GP p;
   p.M = g.M;
@@ -620,6 +628,7 @@ hipError_t gemm_f64(const Gemm& g, hipStream_t s) {
   p.nb2 = g.nb2;
   p.nred = g.nred;
   p.pm = nullptr;
+  p.tab1 = g.tab1;
   // Global-load order: an operand whose m (n) stride is 1 is read m-fast (n-fast).
   const bool amf = (g.sam == 1 && g.sak != 1);
   const bool bnf = (g.sbn == 1) || (g.sbk != 1);
@@ -635,37 +644,40 @@ hipError_t gemm_f64(const Gemm& g, hipStream_t s) {
     };
     const double e128 = est(128, 128, 59.5), e256 = est(256, 128, 60.0), e192 = est(192, 192, 61.5);
     // direct-to-LDS tiles sustain ~67-68 TFLOP/s on full rounds
-    if (dma_eligible(p)) return launch_dma_auto(p, g.nb1, g.ws, g.ws_elems, s);
-    if (e192 < e128 && e192 <= e256) return launch_cfg<192, 192, 16, 2, 4, 1>(p, amf, bnf, g.nb1, nullptr, 0, s);
-    if (e256 < e128) return launch_cfg<256, 128, 16, 4, 2, 1>(p, amf, bnf, g.nb1, nullptr, 0, s);
-    return launch_cfg<128, 128, 16, 2, 2, 2>(p, amf, bnf, g.nb1, g.ws, g.ws_elems, s);
+    if (dma_eligible(p)) return launch_dma_auto(p, g.nb1, nb1d, g.ws, g.ws_elems, s);
+    if (e192 < e128 && e192 <= e256) return launch_cfg<192, 192, 16, 2, 4, 1>(p, amf, bnf, g.nb1, nb1d, nullptr, 0, s);
+    if (e256 < e128) return launch_cfg<256, 128, 16, 4, 2, 1>(p, amf, bnf, g.nb1, nb1d, nullptr, 0, s);
+    return launch_cfg<128, 128, 16, 2, 2, 2>(p, amf, bnf, g.nb1, nb1d, g.ws, g.ws_elems, s);
   }
   // a long K lets split-K make up for too few 128 x 128 tiles (down to 16 of them: split into up
   // to 32 slices, a long K still leaves each slice enough iterations to hide its reduction)
   const bool long_k = g.ws && (long)g.K * g.nred >= 2048 && tiles128 >= 16;
   if (g.M >= 96 && g.N >= 96 && long_k) {
-    if (dma_eligible(p)) return launch_dma_auto(p, g.nb1, g.ws, g.ws_elems, s);
-    return launch_cfg<128, 128, 16, 2, 2, 2>(p, amf, bnf, g.nb1, g.ws, g.ws_elems, s);
+    if (dma_eligible(p)) return launch_dma_auto(p, g.nb1, nb1d, g.ws, g.ws_elems, s);
+    return launch_cfg<128, 128, 16, 2, 2, 2>(p, amf, bnf, g.nb1, nb1d, g.ws, g.ws_elems, s);
   }
   const long tiles64 = (long)((g.M + 63) / 64) * ((g.N + 63) / 64) * nbatch;
-  if (g.M >= 48 && g.N >= 48 && tiles64 >= 128) return launch_cfg<64, 64, 16, 2, 2, 2>(p, amf, bnf, g.nb1, g.ws, g.ws_elems, s);
+  if (g.M >= 48 && g.N >= 48 && tiles64 >= 128)
+    return launch_cfg<64, 64, 16, 2, 2, 2>(p, amf, bnf, g.nb1, nb1d, g.ws, g.ws_elems, s);
   // a narrow output over a long K: 64 x 64 tiles of four waves, split along K, keep more of each
   // CU busy (and more loads in flight) than single-wave 32 x 32 tiles
   if (g.ws && g.M >= 16 && g.N >= 16 && (long)g.K * g.nred >= 2048 && tiles64 < 192)
-    return launch_cfg<64, 64, 16, 2, 2, 2>(p, amf, bnf, g.nb1, g.ws, g.ws_elems, s);
-  return launch_cfg<32, 32, 16, 1, 1, 3>(p, amf, bnf, g.nb1, g.ws, g.ws_elems, s);
+    return launch_cfg<64, 64, 16, 2, 2, 2>(p, amf, bnf, g.nb1, nb1d, g.ws, g.ws_elems, s);
+  return launch_cfg<32, 32, 16, 1, 1, 3>(p, amf, bnf, g.nb1, nb1d, g.ws, g.ws_elems, s);
 }
 
 hipError_t gemm_f64_ladder(int M, int Tv, const double* A, const double* V, long ldv, long vrows, const int* pm,
-                           double* C, hipStream_t s) {
+                           double* C, hipStream_t s, const LadderBatch& lb) {
   if (M <= 0 || Tv <= 0) return hipSuccess;
   const bool pmode = pm != nullptr;
   if (pmode && (ldv < Tv || vrows < Tv)) return hipErrorInvalidValue;
   const long half = (long)M * Tv;
   if (bounds_checking()) {
     const long vlast = pmode ? (vrows - 1) * ldv + Tv - 1 : 2L * Tv * Tv - 1;
-    if (!(range_ok(A, 0, 2 * half - 1, sizeof(double), "ladder A") && range_ok(C, 0, 2 * half - 1, sizeof(double), "ladder C") &&
-          range_ok(V, 0, vlast, sizeof(double), "ladder V") &&
+    const long e1 = lb.tab ? lb.tab_max : lb.n - 1;  // last operand block of batch level 1
+    if (!(range_ok(A, 0, e1 * lb.sa + 2 * half - 1, sizeof(double), "ladder A") &&
+          range_ok(C, 0, e1 * lb.sc + 2 * half - 1, sizeof(double), "ladder C") &&
+          range_ok(V, 0, e1 * lb.sv + vlast, sizeof(double), "ladder V") &&
           (!pmode || range_ok(pm, 0, Tv - 1, sizeof(int), "ladder pair rows"))))
       return hipErrorInvalidValue;
   }
@@ -691,17 +703,22 @@ hipError_t gemm_f64_ladder(int M, int Tv, const double* A, const double* V, long
   p.nb2 = 2;
   p.nred = 1;
   p.pm = pm;
+  p.sa1 = lb.sa;
+  p.sb1 = lb.sv;
+  p.sc1 = lb.sc;
+  p.tab1 = lb.tab;
   // Row tiles of 256, 224 or 128 pair rows: the least padded M wins (each extra row is a full
   // row of wasted products); on a tie the taller tile, which reads the vvvv operand fewer times.
   const long pad256 = (M + 255L) / 256 * 256, pad224 = (M + 223L) / 224 * 224, pad128 = (M + 127L) / 128 * 128;
+  if (lb.n > 65535) return hipErrorInvalidValue;
   if (dma_eligible(p)) {
-    if (pad256 <= pad224 && pad256 <= pad128) return launch_dma<256, 128, 4, 2, 4>(p, 1, pmode, 1, nullptr, s);
-    if (pad224 <= pad128) return launch_dma<224, 128, 2, 4, 4>(p, 1, pmode, 1, nullptr, s);
-    return launch_dma<128, 128, 2, 4, 4>(p, 1, pmode, 1, nullptr, s);
+    if (pad256 <= pad224 && pad256 <= pad128) return launch_dma<256, 128, 4, 2, 4>(p, lb.n, pmode, 1, nullptr, s);
+    if (pad224 <= pad128) return launch_dma<224, 128, 2, 4, 4>(p, lb.n, pmode, 1, nullptr, s);
+    return launch_dma<128, 128, 2, 4, 4>(p, lb.n, pmode, 1, nullptr, s);
   }
-  if (pad256 <= pad224 && pad256 <= pad128) return launch_ladder<256, 4>(p, pmode, s);
-  if (pad224 <= pad128) return launch_ladder<224, 2>(p, pmode, s);
-  return launch_ladder<128, 2>(p, pmode, s);
+  if (pad256 <= pad224 && pad256 <= pad128) return launch_ladder<256, 4>(p, lb.n, pmode, s);
+  if (pad224 <= pad128) return launch_ladder<224, 2>(p, lb.n, pmode, s);
+  return launch_ladder<128, 2>(p, lb.n, pmode, s);
 }
 
 }  // namespace ascc

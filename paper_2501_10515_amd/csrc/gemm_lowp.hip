@@ -43,6 +43,11 @@ struct LP {
   int chunk;    // K-tiles per FP32 accumulation chunk
   int ktps;     // K-tiles per split-K slice (blockIdx.z); the whole K when not split
   long cslice;  // C offset between slices (partial tiles of a split launch), 0 otherwise
+  // batch: blockIdx.y = z1 * nb + z; z1 selects operand block tab1[z1] (or z1) at strides
+  // sa1, sb1, sc1 (partial tiles of a split launch: block z1 itself)
+  int nb, part;
+  const int* tab1;
+  long sa1, sb1, sc1;
 };
 
 // Round-to-nearest-even FP32 -> bf16 bits (finite inputs; NaN stays NaN).
@@ -96,10 +101,11 @@ __global__ __launch_bounds__(NT, 1) void gemm_lowp_kernel(LP p) {
   int tm, tn;
   tile_of_lp(blockIdx.x, p.tiles_m, p.tiles_m * p.tiles_n, tm, tn);
   const int m0 = tm * BM, n0 = tn * BN;
-  const int z = blockIdx.y;
-  const float* Ab = p.A + z * p.sa2;
-  const float* Bb = p.B + z * p.sb2;
-  double* Cb = p.C + z * p.sc2 + blockIdx.z * p.cslice;
+  const int z = blockIdx.y % p.nb, z1 = blockIdx.y / p.nb;
+  const int zs = p.tab1 ? p.tab1[z1] : z1;
+  const float* Ab = p.A + z * p.sa2 + zs * p.sa1;
+  const float* Bb = p.B + z * p.sb2 + zs * p.sb1;
+  double* Cb = p.C + z * p.sc2 + (p.part ? z1 : zs) * p.sc1 + blockIdx.z * p.cslice;
 
   f4 acc[4][4];
 #pragma unroll
@@ -332,6 +338,9 @@ struct LPB {
   int chunk;
   int ktps;
   long cslice;
+  int nb, part;  // batch levels as in LP
+  const int* tab1;
+  long sa1, sb1, sc1;
 };
 
 constexpr int BM2 = 256, BN2 = 128, BK2 = 32, NT2 = 512;
@@ -345,10 +354,11 @@ __global__ __launch_bounds__(NT2, 1) void gemm_bf16x3_kernel(LPB p) {
   int tm, tn;
   tile_of_lp(blockIdx.x, p.tiles_m, p.tiles_m * p.tiles_n, tm, tn);
   const int m0 = tm * BM2, n0 = tn * BN2;
-  const int z = blockIdx.y;
-  const unsigned short* Ab = p.A + z * p.sa2;
-  const unsigned short* Bb = p.B + z * p.sb2;
-  double* Cb = p.C + z * p.sc2 + blockIdx.z * p.cslice;
+  const int z = blockIdx.y % p.nb, z1 = blockIdx.y / p.nb;
+  const int zs = p.tab1 ? p.tab1[z1] : z1;
+  const unsigned short* Ab = p.A + z * p.sa2 + zs * p.sa1;
+  const unsigned short* Bb = p.B + z * p.sb2 + zs * p.sb1;
+  double* Cb = p.C + z * p.sc2 + (p.part ? z1 : zs) * p.sc1 + blockIdx.z * p.cslice;
 
   f4 acc[4][4];
 #pragma unroll
@@ -487,10 +497,12 @@ __global__ __launch_bounds__(NT3, 1) void gemm_bf16x3_dma_kernel(LPB p) {
   int tm, tn;
   tile_of_grouped(blockIdx.x, p.tiles_m, p.tiles_n, tm, tn);
   const int m0 = tm * BM3, n0 = tn * BN3;
-  const int z = blockIdx.y;
+  const int z = blockIdx.y % p.nb, z1 = blockIdx.y / p.nb;
+  const int zs = p.tab1 ? p.tab1[z1] : z1;
   const int lplane = wave >> 1, lhalf = wave & 1;  // staging: plane (A hi, A lo, B hi, B lo), row half
   const bool isA = lplane < 2;
-  const unsigned short* base = isA ? p.A + z * p.sa2 + (long)m0 * p.lda : p.B + z * p.sb2 + (long)n0 * p.ldb;
+  const unsigned short* base = isA ? p.A + z * p.sa2 + zs * p.sa1 + (long)m0 * p.lda
+                                   : p.B + z * p.sb2 + zs * p.sb1 + (long)n0 * p.ldb;
   const int ld = isA ? (int)p.lda : (int)p.ldb;  // row stride (bf16): K-blocks of [hi 32 | lo 32]
   const int plane = lplane & 1;
   const int rows = min(256, isA ? p.M - m0 : p.N - n0);
@@ -507,7 +519,7 @@ __global__ __launch_bounds__(NT3, 1) void gemm_bf16x3_dma_kernel(LPB p) {
       __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_t*)(dst + gg * 1024), 16, off, 0, 0, 0);
     }
   };
-  double* Cb = p.C + z * p.sc2 + blockIdx.z * p.cslice;
+  double* Cb = p.C + z * p.sc2 + (p.part ? z1 : zs) * p.sc1 + blockIdx.z * p.cslice;
   f16v acc[4][2];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -579,15 +591,18 @@ __global__ __launch_bounds__(NT3, 1) void gemm_bf16x3_dma_kernel(LPB p) {
 
 
 // C_z(m,n) = beta * C_z(m,n) + sum_s part[s][z][m][n], summed in slice order.
-__global__ __launch_bounds__(256) void lowp_splitk_reduce(double* C, long scm, long scn, long sc2, double beta,
-                                                          const double* part, int M, int N, long total, int split) {
+__global__ __launch_bounds__(256) void lowp_splitk_reduce(double* C, long scm, long scn, long sc2, long sc1, int nb,
+                                                          const int* tab1, double beta, const double* part, int M,
+                                                          int N, long total, int split) {
   for (long x = blockIdx.x * 256L + threadIdx.x; x < total; x += (long)gridDim.x * 256) {
     const long mn = (long)M * N;
-    const long z = x / mn, r = x % mn;
+    const long za = x / mn, r = x % mn;
+    const int z = (int)(za % nb), z1 = (int)(za / nb);
+    const int zs = tab1 ? tab1[z1] : z1;
     const int m = (int)(r / N), n = (int)(r % N);
     double acc = 0.0;
     for (int sl = 0; sl < split; ++sl) acc += part[(long)sl * total + x];
-    double* c = C + z * sc2 + m * scm + n * scn;
+    double* c = C + z * sc2 + zs * sc1 + m * scm + n * scn;
     *c = (beta == 0.0) ? acc : acc + beta * *c;
   }
 }
@@ -600,7 +615,7 @@ struct SplitPlan {
 SplitPlan plan_split(const GemmLP& g, long tiles, int nkt) {
   SplitPlan sp;
   sp.ktps = nkt;
-  const long outs = (long)g.M * g.N * g.nb;
+  const long outs = (long)g.M * g.N * g.nb * g.nb1;
   if (!g.ws || tiles >= 192 || nkt < 32) return sp;
   long n = std::min<long>({(256 + tiles - 1) / tiles, (long)nkt / 16, g.ws_elems / std::max<long>(outs, 1)});
   if (n < 2) return sp;
@@ -633,17 +648,20 @@ hipError_t to_lowp_2d(int prec, float* out, long ldo, const double* in, long ldi
 }
 
 hipError_t gemm_lowp(const GemmLP& g, hipStream_t s) {
-  if (g.M <= 0 || g.N <= 0 || g.nb <= 0) return hipSuccess;
-  if (g.K <= 0 || g.nb > 65535 || (g.prec != kPrecFP32 && g.prec != kPrecBF16x3)) return hipErrorInvalidValue;
+  if (g.M <= 0 || g.N <= 0 || g.nb <= 0 || g.nb1 <= 0) return hipSuccess;
+  if (g.K <= 0 || (long)g.nb * g.nb1 > 65535 || (g.prec != kPrecFP32 && g.prec != kPrecBF16x3))
+    return hipErrorInvalidValue;
   const bool bf = (g.prec == kPrecBF16x3);
   // bf16: interleaved rows; the row strides are equal multiples of 64 and cover K
-  if (bf && (((g.lda | g.ldb | g.sa2 | g.sb2) & 63) || g.lda != g.ldb || g.lda / 2 < g.K)) return hipErrorInvalidValue;
+  if (bf && (((g.lda | g.ldb | g.sa2 | g.sb2 | g.sa1 | g.sb1) & 63) || g.lda != g.ldb || g.lda / 2 < g.K))
+    return hipErrorInvalidValue;
+  const long nz1 = g.tab1 ? g.tab1_max + 1 : g.nb1;  // operand blocks of the outer batch level
   if (bounds_checking()) {
     // bf16: every staged chunk stays inside its padded row
-    const long la = (long)(g.M - 1) * g.lda + (bf ? g.lda - 1 : g.K - 1) + (long)(g.nb - 1) * g.sa2;
-    const long lb = (long)(g.N - 1) * g.ldb + (bf ? g.ldb - 1 : g.K - 1) + (long)(g.nb - 1) * g.sb2;
+    const long la = (long)(g.M - 1) * g.lda + (bf ? g.lda - 1 : g.K - 1) + (long)(g.nb - 1) * g.sa2 + (nz1 - 1) * g.sa1;
+    const long lb = (long)(g.N - 1) * g.ldb + (bf ? g.ldb - 1 : g.K - 1) + (long)(g.nb - 1) * g.sb2 + (nz1 - 1) * g.sb1;
     long lo = 0, hi = 0;
-    const long dc[3] = {(long)(g.M - 1) * g.scm, (long)(g.N - 1) * g.scn, (long)(g.nb - 1) * g.sc2};
+    const long dc[4] = {(long)(g.M - 1) * g.scm, (long)(g.N - 1) * g.scn, (long)(g.nb - 1) * g.sc2, (nz1 - 1) * g.sc1};
     for (long d : dc) {
       if (d < 0) lo += d; else hi += d;
     }
@@ -654,15 +672,15 @@ hipError_t gemm_lowp(const GemmLP& g, hipStream_t s) {
   }
   if (dry_run()) return hipSuccess;
   const int chunk = g.chunk_ktiles > 0 ? g.chunk_ktiles : (bf ? 256 : 64);
-  if (bf) {
-    LPB p;
+  const int nbz = g.nb * g.nb1;                       // grid.y
+  const int nbd = g.per_block ? g.nb : nbz;            // the batch the kernel and split choices see
+  // the batch and output fields shared by both parameter blocks
+  auto common = [&](auto& p) {
     p.M = g.M;
     p.N = g.N;
     p.K = g.K;
-    p.A = reinterpret_cast<const unsigned short*>(g.A);
     p.lda = g.lda;
     p.sa2 = g.sa2;
-    p.B = reinterpret_cast<const unsigned short*>(g.B);
     p.ldb = g.ldb;
     p.sb2 = g.sb2;
     p.C = g.C;
@@ -673,72 +691,64 @@ hipError_t gemm_lowp(const GemmLP& g, hipStream_t s) {
     p.beta = g.beta;
     p.chunk = chunk;
     p.cslice = 0;
-    const int nkt = (g.K + 31) / 32;
-    // buffer descriptors cover one tile's rows: 256 * ld bf16 must stay below 2^31 bytes
-    const long t3 = (long)((g.M + BM3 - 1) / BM3) * ((g.N + BN3 - 1) / BN3) * g.nb;
-    if (t3 >= 256 && 512L * g.lda < (1L << 31)) {
-      p.tiles_m = (g.M + BM3 - 1) / BM3;
-      p.tiles_n = (g.N + BN3 - 1) / BN3;
-      p.ktps = nkt;
-      hipLaunchKernelGGL(gemm_bf16x3_dma_kernel, dim3(p.tiles_m * p.tiles_n, g.nb, 1), dim3(NT3), 0, s, p);
-      return hipGetLastError();
-    }
-    p.tiles_m = (g.M + BM2 - 1) / BM2;
-    p.tiles_n = (g.N + BN2 - 1) / BN2;
-    const SplitPlan sp = plan_split(g, (long)p.tiles_m * p.tiles_n * g.nb, nkt);
-    p.ktps = sp.ktps;
-    if (sp.split > 1) {  // partial tiles [split][nb][M][N] in the scratch, then the ordered sum
-      p.C = g.ws;
-      p.scm = g.N;
-      p.scn = 1;
-      p.sc2 = (long)g.M * g.N;
-      p.cslice = (long)g.M * g.N * g.nb;
-      p.beta = 0.0;
-    }
-    hipLaunchKernelGGL(gemm_bf16x3_kernel, dim3(p.tiles_m * p.tiles_n, g.nb, sp.split), dim3(NT2), 0, s, p);
-    if (sp.split > 1) {
-      const long total = (long)g.M * g.N * g.nb;
-      hipLaunchKernelGGL(lowp_splitk_reduce, dim3((unsigned)std::min<long>((total + 255) / 256, 4096)), dim3(256), 0, s,
-                         g.C, g.scm, g.scn, g.sc2, g.beta, g.ws, g.M, g.N, total, sp.split);
-    }
-    return hipGetLastError();
-  }
-  LP p;
-  p.M = g.M;
-  p.N = g.N;
-  p.K = g.K;
-  p.A = g.A;
-  p.lda = g.lda;
-  p.sa2 = g.sa2;
-  p.B = g.B;
-  p.ldb = g.ldb;
-  p.sb2 = g.sb2;
-  p.C = g.C;
-  p.scm = g.scm;
-  p.scn = g.scn;
-  p.sc2 = g.sc2;
-  p.alpha = g.alpha;
-  p.beta = g.beta;
-  p.tiles_m = (g.M + BM - 1) / BM;
-  p.tiles_n = (g.N + BN - 1) / BN;
-  p.chunk = chunk;
-  p.cslice = 0;
-  const SplitPlan sp = plan_split(g, (long)p.tiles_m * p.tiles_n * g.nb, (g.K + 31) / 32);
-  p.ktps = sp.ktps;
-  if (sp.split > 1) {
+    p.nb = g.nb;
+    p.part = 0;
+    p.tab1 = g.tab1;
+    p.sa1 = g.sa1;
+    p.sb1 = g.sb1;
+    p.sc1 = g.sc1;
+  };
+  // split launches write partial tiles [split][nb1][nb][M][N] into the scratch
+  auto to_partials = [&](auto& p) {
     p.C = g.ws;
     p.scm = g.N;
     p.scn = 1;
     p.sc2 = (long)g.M * g.N;
-    p.cslice = (long)g.M * g.N * g.nb;
+    p.sc1 = (long)g.M * g.N * g.nb;
+    p.cslice = (long)g.M * g.N * nbz;
     p.beta = 0.0;
-  }
-  hipLaunchKernelGGL(gemm_lowp_kernel, dim3(p.tiles_m * p.tiles_n, g.nb, sp.split), dim3(NT), 0, s, p);
-  if (sp.split > 1) {
-    const long total = (long)g.M * g.N * g.nb;
+    p.part = 1;
+  };
+  auto reduce = [&](int split) {
+    const long total = (long)g.M * g.N * nbz;
     hipLaunchKernelGGL(lowp_splitk_reduce, dim3((unsigned)std::min<long>((total + 255) / 256, 4096)), dim3(256), 0, s,
-                       g.C, g.scm, g.scn, g.sc2, g.beta, g.ws, g.M, g.N, total, sp.split);
+                       g.C, g.scm, g.scn, g.sc2, g.sc1, g.nb, g.tab1, g.beta, g.ws, g.M, g.N, total, split);
+  };
+  if (bf) {
+    LPB p;
+    common(p);
+    p.A = reinterpret_cast<const unsigned short*>(g.A);
+    p.B = reinterpret_cast<const unsigned short*>(g.B);
+    const int nkt = (g.K + 31) / 32;
+    // buffer descriptors cover one tile's rows: 256 * ld bf16 must stay below 2^31 bytes
+    const long t3 = (long)((g.M + BM3 - 1) / BM3) * ((g.N + BN3 - 1) / BN3) * nbd;
+    if (t3 >= 256 && 512L * g.lda < (1L << 31)) {
+      p.tiles_m = (g.M + BM3 - 1) / BM3;
+      p.tiles_n = (g.N + BN3 - 1) / BN3;
+      p.ktps = nkt;
+      hipLaunchKernelGGL(gemm_bf16x3_dma_kernel, dim3(p.tiles_m * p.tiles_n, nbz, 1), dim3(NT3), 0, s, p);
+      return hipGetLastError();
+    }
+    p.tiles_m = (g.M + BM2 - 1) / BM2;
+    p.tiles_n = (g.N + BN2 - 1) / BN2;
+    const SplitPlan sp = plan_split(g, (long)p.tiles_m * p.tiles_n * nbd, nkt);
+    p.ktps = sp.ktps;
+    if (sp.split > 1) to_partials(p);
+    hipLaunchKernelGGL(gemm_bf16x3_kernel, dim3(p.tiles_m * p.tiles_n, nbz, sp.split), dim3(NT2), 0, s, p);
+    if (sp.split > 1) reduce(sp.split);
+    return hipGetLastError();
   }
+  LP p;
+  common(p);
+  p.A = g.A;
+  p.B = g.B;
+  p.tiles_m = (g.M + BM - 1) / BM;
+  p.tiles_n = (g.N + BN - 1) / BN;
+  const SplitPlan sp = plan_split(g, (long)p.tiles_m * p.tiles_n * nbd, (g.K + 31) / 32);
+  p.ktps = sp.ktps;
+  if (sp.split > 1) to_partials(p);
+  hipLaunchKernelGGL(gemm_lowp_kernel, dim3(p.tiles_m * p.tiles_n, nbz, sp.split), dim3(NT), 0, s, p);
+  if (sp.split > 1) reduce(sp.split);
   return hipGetLastError();
 }
 

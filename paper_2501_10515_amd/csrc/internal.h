@@ -8,6 +8,7 @@
 #include <string>
 
 struct ascc_ints;
+struct ascc_diis;
 struct ascc_opts;
 struct ascc_result;
 
@@ -58,6 +59,23 @@ struct Gemm {
   // are then summed in a fixed order (deterministic).  nullptr disables splitting.
   double* ws = nullptr;
   long ws_elems = 0;
+  // Optional table of batch level 1: grid index z1 takes operand block tab1[z1] (device array of
+  // nb1 entries, each at most tab1_max); nullptr: block z1.
+  const int* tab1 = nullptr;
+  int tab1_max = 0;
+  // tile and split-K choices as for one block of batch level 1 (the same summation order for
+  // each block whatever nb1 is, as long as the split-K scratch holds the partials of every block)
+  bool per_block = false;
+};
+
+// Batch level of the particle-particle ladder: n operand blocks (A, V and C offset by sa, sv, sc
+// elements per block; the pair-row table, which depends on v only, is shared), block z taken from
+// tab[z] when tab is given (entries at most tab_max).
+struct LadderBatch {
+  int n = 1;
+  const int* tab = nullptr;
+  int tab_max = 0;
+  long sa = 0, sv = 0, sc = 0;
 };
 
 // Convenience constructors for row-major matrices:
@@ -75,7 +93,7 @@ hipError_t gemm_f64(const Gemm& g, hipStream_t s);
 // diagonal k = (c,c) this is twice the packed V+, so A carries half the diagonal t+).
 // No split-K, so every output is summed in the same order whatever M is.
 hipError_t gemm_f64_ladder(int M, int Tv, const double* A, const double* V, long ldv, long vrows, const int* pm,
-                           double* C, hipStream_t s);
+                           double* C, hipStream_t s, const LadderBatch& lb = LadderBatch());
 
 // Low-precision contraction with FP64 result (gemm_lowp.hip):
 //   C_z(m,n) = alpha * sum_k A_z[m*lda + k] * B_z[n*ldb + k] + beta * C_z(m,n)
@@ -101,6 +119,14 @@ struct GemmLP {
   // FP64 partial tiles land here and are then summed in slice order (deterministic).
   double* ws = nullptr;
   long ws_elems = 0;
+  // Optional outer batch level over operand blocks: nb1 blocks at strides sa1, sb1 (in the units of
+  // lda) and sc1 (FP64 elements); block z1 taken from tab1[z1] when tab1 is given (entries at most
+  // tab1_max).
+  int nb1 = 1;
+  long sa1 = 0, sb1 = 0, sc1 = 0;
+  const int* tab1 = nullptr;
+  int tab1_max = 0;
+  bool per_block = false;  // kernel and split-K choices as for one outer block (see Gemm)
 };
 hipError_t gemm_lowp(const GemmLP& g, hipStream_t s);
 // Low-precision shadow of a row-major FP64 matrix with the leading dimension padded to ldo
@@ -259,6 +285,13 @@ struct UpdateArgs {
   int start;  // calls before this (device-side count) store no pair in the history
   long len;   // no*nv + no*no*nv*nv
   double shift;
+  // Batched update of nslot amplitude sets: every pointer above except stats names slot 0 of a
+  // layout repeated at a byte stride ss (slot k at + k ss, k = tab[z] for grid row z when tab is
+  // given, entries at most tab_max); stats is [slot][8].
+  int nslot = 1;
+  long ss = 0;
+  const int* tab = nullptr;
+  int tab_max = 0;
 };
 hipError_t diis_update(const UpdateArgs& u, hipStream_t s);
 int update_partial_blocks();
@@ -270,5 +303,13 @@ int solve_impl(ascc_ints* I, const ascc_opts* opts, double* t1, double* t2, ascc
                size_t ws_bytes);
 // An unbacked, never dereferenced device address range for a dry run.
 uintptr_t dry_run_address(size_t bytes);
+// One iteration (residual, then the Jacobi/DIIS update) of n slots that repeat one layout at a
+// byte stride: I, D and the amplitude / residual / energy pointers are those of the base slot,
+// whose layout spans [region, region + stride); slot z of the batch is the base slot + htab[z]
+// (dtab: the same table in device memory, read by the batched contractions and the update).
+// stats receives one row of 8 statistics per slot, row htab[z] for slot z (see ascc_update).
+int iterate_slots(ascc_ints* I, ::ascc_diis* D, int n, const int* dtab, const int* htab, const char* region,
+                  long stride, double* t1, double* t2, double* r1, double* r2, double* e, double* stats,
+                  hipStream_t s);
 
 }  // namespace ascc

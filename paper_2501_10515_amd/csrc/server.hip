@@ -1,19 +1,22 @@
 // Request loop for many independent solves on one GPU (continuous batching at the iteration
 // level).
 //
-// * Admission by HBM footprint: the server owns one device slab (allocated once) and carves
-//   each admitted request's whole working set -- integral set, DIIS state, amplitudes,
-//   residuals, staging for its DF tensor -- out of it with a first-fit free list, in arrival
-//   order.  No device allocation happens while requests run.
-// * Every running request has its own stream.  One iteration (residual + Jacobi/DIIS update)
-//   is captured once per precision into a hipGraph and replayed; each step of the loop
-//   launches one iteration for every running request whose previous iteration has finished,
-//   so work of different requests overlaps on the device, and requests join and leave between
-//   iterations as slab space and stream slots free up.
-// * The convergence test reads an 8-double statistics block copied to pinned host memory
-//   behind each iteration (polled with an event, never a blocking wait).  A low-precision
-//   request runs its bulk iterations in that precision and finishes in FP64 (the FP64
-//   refinement of ascc_solve).
+// * Admission by HBM footprint: the server owns one device slab (allocated once) and carves from
+//   it, in arrival order, the working set of each admitted request -- integral set, DIIS state,
+//   amplitudes, residuals, staging for its DF tensor (and PLASCC buffers) -- with a first-fit free
+//   list.  No device allocation happens while requests run.
+// * Size buckets: ground-state requests of one shape (no, nv, naux) share a bucket, a slab region
+//   of up to kMaxSlots equal slots (as many as a quarter of the budget holds) in which every slot
+//   repeats one layout at a fixed stride.  The running slots of a bucket advance together: one
+//   iteration of all of them is one batched pass (iterate_slots: every contraction one launch over
+//   the slots, the update and DIIS one launch set), for the slots in low precision and for those
+//   in FP64, each captured once per slot set into a hipGraph and replayed.  Excited-state and PLASCC
+//   requests have buckets of one slot.  Each bucket has its own stream, so buckets overlap on the
+//   device; requests join and leave their bucket between iterations as slab space and slots free.
+// * The convergence test reads each slot's 8-double statistics row from one pinned copy of the
+//   bucket's statistics block behind each iteration (polled with an event, never a blocking
+//   wait).  A low-precision request runs its bulk iterations in that precision and finishes in
+//   FP64 (the FP64 refinement of ascc_solve).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -30,29 +33,54 @@ using namespace ascc;
 namespace {
 
 constexpr size_t kSlabAlign = 256;
+constexpr int kMaxSlots = 8;  // slots per bucket
 
 struct Request {
   int id = 0, o = 0, v = 0, Q = 0;
-  std::vector<double> hB, heps;  // host copies until admission
+  std::vector<double> hB, heps;  // host copies until the first iteration has run
   double t_submit = 0, t_admit = -1, t_done = -1;
   int status = 1;  // 1 queued, 2 running, 0 converged, <0 ASCC_E_*
-  size_t bytes = 0, off = 0;
+  size_t bytes = 0;  // the slot's footprint
   size_t ints_bytes = 0, diis_bytes = 0, plascc_bytes = 0;
   ascc_ints* ints = nullptr;
   ascc_diis* diis = nullptr;
-  double *t1 = nullptr, *t2 = nullptr, *r1 = nullptr, *r2 = nullptr, *e = nullptr, *stats = nullptr;
+  double *t1 = nullptr, *t2 = nullptr, *r1 = nullptr, *r2 = nullptr, *e = nullptr;
   double *dB = nullptr, *deps = nullptr;
-  double* hstats = nullptr;  // pinned, 8 doubles
-  hipStream_t stream = nullptr;
-  hipEvent_t ev = nullptr;
-  hipGraphExec_t g_low = nullptr, g_fp64 = nullptr;
-  bool inflight = false, lowp_phase = false;
+  bool lowp_phase = false;
   LowpStall stall;
   int iterations = 0, lowp_iterations = 0;
   double e_corr = 0, rnorm = 0, rmax = 0, de = 0;
   int hole = -1, particle = -1, s_sign = 1;  // a 1-CSF state (hole >= 0) or the ground state
   double beta = 1.0, e_ref = 0.0;
   bool plascc = false;
+  int bucket = -1, slot = -1;
+  int last_bucket = -1, last_slot = -1;  // reported by ascc_server_info
+};
+
+// A slab region of equal slots for requests of one shape; slot k's working set starts at
+// region + header + k * stride and is carved in the same order in every slot.
+struct Bucket {
+  int o = 0, v = 0, Q = 0;
+  bool shared = false;  // ground-state bucket that later requests of this shape join
+  int cap = 1;
+  size_t stride = 0, header = 0, off = 0, bytes = 0;
+  char* region = nullptr;
+  double* dstats = nullptr;  // [cap][8] statistics rows, device
+  int* dtab = nullptr;       // [2][cap] slot tables (low precision, FP64), device
+  double* hstats = nullptr;  // pinned copy of dstats
+  int* htab = nullptr;       // pinned [2][cap]
+  std::vector<int> slot_req;  // request id per slot, -1 free
+  hipStream_t stream = nullptr;
+  hipEvent_t ev = nullptr;
+  bool inflight = false;
+  std::vector<int> launched;  // slots of the in-flight iteration
+  std::map<std::pair<int, unsigned>, hipGraphExec_t> graphs;  // (phase, slot mask)
+  char* slot_base(int k) const { return region + header + (size_t)k * stride; }
+  int used() const {
+    int n = 0;
+    for (int r : slot_req) n += (r >= 0);
+    return n;
+  }
 };
 
 }  // namespace
@@ -64,10 +92,11 @@ struct ascc_server {
   std::map<size_t, size_t> free_list;  // offset -> length
   std::vector<Request*> reqs;
   std::deque<int> queue;
-  std::vector<int> running;
+  int running = 0;
+  std::map<int, Bucket*> buckets;
+  int next_bucket = 0;
   std::vector<hipStream_t> stream_pool;
   std::vector<hipEvent_t> event_pool;
-  std::vector<double*> pinned_pool;
   int n_done = 0;
 };
 
@@ -112,7 +141,7 @@ void slab_give(ascc_server* S, size_t off, size_t bytes) {
 
 size_t align_s(size_t x) { return (x + kSlabAlign - 1) / kSlabAlign * kSlabAlign; }
 
-// Layout of a request's region: [ints | diis | t1 t2 r1 r2 e stats eps | B staging | PLASCC buffers]
+// Layout of a request's slot: [ints | diis | t1 t2 r1 r2 e | eps | B staging | PLASCC buffers]
 // (the last only for a PLASCC request): its whole device working set.
 size_t request_bytes(const ascc_server* S, int o, int v, int Q, bool plascc, size_t* ib, size_t* db,
                      size_t* pb) {
@@ -125,59 +154,104 @@ size_t request_bytes(const ascc_server* S, int o, int v, int Q, bool plascc, siz
   *pb = pl_b;
   const size_t ov = (size_t)o * v, oovv = (size_t)o * o * v * v, n = (size_t)o + v;
   size_t b = align_s(ints_b) + align_s(diis_b);
-  b += align_s(8 * ov) * 2 + align_s(8 * oovv) * 2 + align_s(8) + align_s(64) + align_s(8 * n);
+  b += align_s(8 * ov) * 2 + align_s(8 * oovv) * 2 + align_s(8) + align_s(8 * n);
   b += align_s(8 * (size_t)Q * n * n);
   b += align_s(pl_b);
   return b;
 }
 
-void release(ascc_server* S, Request* R) {
-  if (R->g_low) (void)hipGraphExecDestroy(R->g_low);
-  if (R->g_fp64) (void)hipGraphExecDestroy(R->g_fp64);
-  R->g_low = R->g_fp64 = nullptr;
+size_t bucket_header(int cap) { return align_s(64 * (size_t)cap) + align_s(2 * sizeof(int) * (size_t)cap); }
+
+void drop_graphs(Bucket* B) {
+  for (auto& g : B->graphs) (void)hipGraphExecDestroy(g.second);
+  B->graphs.clear();
+}
+
+void release_bucket(ascc_server* S, int bid) {
+  Bucket* B = S->buckets[bid];
+  drop_graphs(B);
+  slab_give(S, B->off, B->bytes);
+  if (B->stream) S->stream_pool.push_back(B->stream);
+  if (B->ev) S->event_pool.push_back(B->ev);
+  if (B->hstats) (void)hipHostFree(B->hstats);
+  if (B->htab) (void)hipHostFree(B->htab);
+  delete B;
+  S->buckets.erase(bid);
+}
+
+// Frees a request's slot (its handles are host structs over slab memory).
+void release_request(ascc_server* S, Request* R) {
   if (R->diis) ascc_diis_free(R->diis);
   if (R->ints) ascc_ints_free(R->ints);
   R->diis = nullptr;
   R->ints = nullptr;
-  if (R->bytes) slab_give(S, R->off, R->bytes);
-  R->bytes = 0;
-  if (R->stream) S->stream_pool.push_back(R->stream);
-  if (R->ev) S->event_pool.push_back(R->ev);
-  if (R->hstats) S->pinned_pool.push_back(R->hstats);
-  R->stream = nullptr;
-  R->ev = nullptr;
-  R->hstats = nullptr;
+  if (R->bucket >= 0) {
+    Bucket* B = S->buckets[R->bucket];
+    B->slot_req[R->slot] = -1;
+    if (B->used() == 0 && !B->inflight) release_bucket(S, R->bucket);
+  }
+  R->bucket = R->slot = -1;
 }
 
-// One iteration (residual at t, then the update of t) on the request's stream.
-int iteration(Request* R, hipStream_t s) {
-  int rc = ascc_residual(R->ints, R->t1, R->t2, R->r1, R->r2, R->e, s);
-  if (!rc) rc = ascc_update(R->ints, R->diis, R->t1, R->t2, R->r1, R->r2, R->e, 0.0, R->stats, s);
-  return rc;
-}
-
-int capture(Request* R, int precision, hipGraphExec_t* out) {
-  int rc = ascc_set_precision(R->ints, precision);
-  if (rc) return rc;
-  hipGraph_t g = nullptr;
-  if (hipStreamBeginCapture(R->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
-    return sfail(ASCC_E_HIP, "hipStreamBeginCapture failed");
-  rc = iteration(R, R->stream);
-  hipError_t e = hipStreamEndCapture(R->stream, &g);
+int open_bucket(ascc_server* S, const Request* R, size_t slot_bytes, int* bid) {
+  const bool shared = R->hole < 0 && !R->plascc;
+  int cap = 1;
+  if (shared) {
+    const size_t fit = S->slab_bytes / 4 / std::max<size_t>(slot_bytes, 1);
+    cap = (int)std::min<size_t>(std::max<size_t>(fit, 1), std::min(kMaxSlots, S->opts.max_active));
+  }
+  size_t off = 0;
+  while (!slab_take(S, bucket_header(cap) + (size_t)cap * slot_bytes, &off)) {
+    if (cap == 1) return ASCC_E_NOMEM;  // not now: the head of the queue waits
+    cap = 1;
+  }
+  Bucket* B = new Bucket();
+  B->o = R->o;
+  B->v = R->v;
+  B->Q = R->Q;
+  B->shared = shared;
+  B->cap = cap;
+  B->stride = slot_bytes;
+  B->header = bucket_header(cap);
+  B->off = off;
+  B->bytes = B->header + (size_t)cap * slot_bytes;
+  B->region = S->slab + off;
+  B->dstats = reinterpret_cast<double*>(B->region);
+  B->dtab = reinterpret_cast<int*>(B->region + align_s(64 * (size_t)cap));
+  B->slot_req.assign(cap, -1);
+  int rc = ASCC_OK;
+  if (!S->stream_pool.empty()) {
+    B->stream = S->stream_pool.back();
+    S->stream_pool.pop_back();
+  } else if (hipStreamCreateWithFlags(&B->stream, hipStreamNonBlocking) != hipSuccess) {
+    rc = sfail(ASCC_E_HIP, "hipStreamCreate failed");
+  }
+  if (!rc) {
+    if (!S->event_pool.empty()) {
+      B->ev = S->event_pool.back();
+      S->event_pool.pop_back();
+    } else if (hipEventCreateWithFlags(&B->ev, hipEventDisableTiming) != hipSuccess) {
+      rc = sfail(ASCC_E_HIP, "hipEventCreate failed");
+    }
+  }
+  if (!rc && (hipHostMalloc((void**)&B->hstats, 64 * (size_t)cap, 0) != hipSuccess ||
+              hipHostMalloc((void**)&B->htab, 2 * sizeof(int) * (size_t)cap, 0) != hipSuccess))
+    rc = sfail(ASCC_E_NOMEM, "pinned host allocation failed");
+  *bid = S->next_bucket++;
+  S->buckets[*bid] = B;
   if (rc) {
-    if (g) (void)hipGraphDestroy(g);
+    release_bucket(S, *bid);
     return rc;
   }
-  if (e != hipSuccess) return sfail(ASCC_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-  e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(g);
-  if (e != hipSuccess) return sfail(ASCC_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
   return ASCC_OK;
 }
 
+// Carve the request's slot, upload its inputs and build its integral set, DIIS state and starting
+// amplitudes on the bucket's stream.
 int admit(ascc_server* S, Request* R, double now) {
+  Bucket* B = S->buckets[R->bucket];
   const size_t ov = (size_t)R->o * R->v, oovv = (size_t)R->o * R->o * R->v * R->v, n = (size_t)R->o + R->v;
-  char* base = S->slab + R->off;
+  char* base = B->slot_base(R->slot);
   size_t p = 0;
   char* ints_ws = base + p;
   p += align_s(R->ints_bytes);
@@ -193,30 +267,11 @@ int admit(ascc_server* S, Request* R, double now) {
   R->r1 = carve(8 * ov);
   R->r2 = carve(8 * oovv);
   R->e = carve(8);
-  R->stats = carve(64);
   R->deps = carve(8 * n);
   R->dB = carve(8 * (size_t)R->Q * n * n);
   char* plascc_ws = base + p;  // R->plascc_bytes (0 unless a PLASCC request)
   p += align_s(R->plascc_bytes);
-  if (!S->stream_pool.empty()) {
-    R->stream = S->stream_pool.back();
-    S->stream_pool.pop_back();
-  } else if (hipStreamCreateWithFlags(&R->stream, hipStreamNonBlocking) != hipSuccess) {
-    return sfail(ASCC_E_HIP, "hipStreamCreate failed");
-  }
-  if (!S->event_pool.empty()) {
-    R->ev = S->event_pool.back();
-    S->event_pool.pop_back();
-  } else if (hipEventCreateWithFlags(&R->ev, hipEventDisableTiming) != hipSuccess) {
-    return sfail(ASCC_E_HIP, "hipEventCreate failed");
-  }
-  if (!S->pinned_pool.empty()) {
-    R->hstats = S->pinned_pool.back();
-    S->pinned_pool.pop_back();
-  } else if (hipHostMalloc((void**)&R->hstats, 64, 0) != hipSuccess) {
-    return sfail(ASCC_E_NOMEM, "pinned host allocation failed");
-  }
-  hipStream_t s = R->stream;
+  hipStream_t s = B->stream;
   if (hipMemcpyAsync(R->dB, R->hB.data(), 8 * R->hB.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemcpyAsync(R->deps, R->heps.data(), 8 * n, hipMemcpyHostToDevice, s) != hipSuccess)
     return sfail(ASCC_E_HIP, "upload of request inputs failed");
@@ -229,8 +284,7 @@ int admit(ascc_server* S, Request* R, double now) {
   rc = ascc_diis_create_ws(R->ints, S->opts.solve.diis_size, S->opts.solve.diis_start, diis_ws, R->diis_bytes,
                            &R->diis);
   if (rc) return rc;
-  if (R->plascc &&
-      (rc = ascc_set_plascc_ws(R->ints, R->hole, R->particle, plascc_ws, R->plascc_bytes, s)))
+  if (R->plascc && (rc = ascc_set_plascc_ws(R->ints, R->hole, R->particle, plascc_ws, R->plascc_bytes, s)))
     return rc;
   if (R->hole >= 0) {  // T^P(0) of the state
     if ((rc = ascc_initial_guess(R->t1, R->t2, R->o, R->v, R->hole, R->particle, R->s_sign * R->beta,
@@ -242,36 +296,89 @@ int admit(ascc_server* S, Request* R, double now) {
       return sfail(ASCC_E_HIP, "amplitude initialisation failed");
   }
   R->lowp_phase = (S->opts.precision != ASCC_PREC_FP64);
-  if (S->opts.use_graphs) {
-    if (R->lowp_phase && (rc = capture(R, S->opts.precision, &R->g_low))) return rc;
-    if ((rc = capture(R, ASCC_PREC_FP64, &R->g_fp64))) return rc;
-  }
   (void)ascc_set_precision(R->ints, R->lowp_phase ? S->opts.precision : ASCC_PREC_FP64);
   R->t_admit = now;
   R->status = 2;
   return ASCC_OK;
 }
 
-int launch(Request* R) {
-  hipStream_t s = R->stream;
-  if (R->g_fp64) {
-    if (hipGraphLaunch(R->lowp_phase ? R->g_low : R->g_fp64, s) != hipSuccess)
-      return sfail(ASCC_E_HIP, "hipGraphLaunch failed");
-  } else {
-    int rc = iteration(R, s);
-    if (rc) return rc;
+// One batched iteration of the slots `slots` (ascending) of a bucket, all in phase `phase`
+// (0 low precision, 1 FP64): the slot table goes to the device, then the captured graph of this slot
+// set is replayed (captured on first use) or the pass is issued directly.
+int launch_group(ascc_server* S, Bucket* B, int phase, const std::vector<int>& slots) {
+  const int n = (int)slots.size(), base = slots[0];
+  int* ht = B->htab + phase * B->cap;
+  int* dt = B->dtab + phase * B->cap;
+  unsigned mask = 0;
+  for (int z = 0; z < n; ++z) {
+    ht[z] = slots[z] - base;
+    mask |= 1u << slots[z];
   }
-  if (hipMemcpyAsync(R->hstats, R->stats, 64, hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipEventRecord(R->ev, s) != hipSuccess)
+  Request* R0 = S->reqs[B->slot_req[base]];
+  hipStream_t s = B->stream;
+  if (hipMemcpyAsync(dt, ht, sizeof(int) * n, hipMemcpyHostToDevice, s) != hipSuccess)
+    return sfail(ASCC_E_HIP, "slot table upload failed");
+  const int prec = phase == 0 ? S->opts.precision : ASCC_PREC_FP64;
+  int rc = ascc_set_precision(R0->ints, prec);
+  if (rc) return rc;
+  auto pass = [&]() {
+    return iterate_slots(R0->ints, R0->diis, n, dt, ht, B->slot_base(base), (long)B->stride, R0->t1, R0->t2, R0->r1,
+                         R0->r2, R0->e, B->dstats + 8 * base, s);
+  };
+  if (!S->opts.use_graphs) return pass();
+  // A graph holds the launches of one slot set; it stays valid when the requests in those slots
+  // change, since every slot keeps its addresses and the launch sequence depends only on the shape,
+  // the precision and the options.
+  auto key = std::make_pair(phase, mask);
+  auto it = B->graphs.find(key);
+  if (it == B->graphs.end()) {
+    if (B->graphs.size() >= 64) drop_graphs(B);
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return sfail(ASCC_E_HIP, "hipStreamBeginCapture failed");
+    rc = pass();
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return sfail(ASCC_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return sfail(ASCC_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    it = B->graphs.emplace(key, x).first;
+  }
+  if (hipGraphLaunch(it->second, s) != hipSuccess) return sfail(ASCC_E_HIP, "hipGraphLaunch failed");
+  return ASCC_OK;
+}
+
+// Launch the next iteration of every running slot of an idle bucket.
+int launch_bucket(ascc_server* S, Bucket* B) {
+  std::vector<int> groups[2];
+  for (int k = 0; k < B->cap; ++k) {
+    const int id = B->slot_req[k];
+    if (id < 0 || S->reqs[id]->status != 2) continue;
+    groups[S->reqs[id]->lowp_phase ? 0 : 1].push_back(k);
+  }
+  B->launched.clear();
+  for (int ph = 0; ph < 2; ++ph) {
+    if (groups[ph].empty()) continue;
+    const int rc = launch_group(S, B, ph, groups[ph]);
+    if (rc) return rc;
+    B->launched.insert(B->launched.end(), groups[ph].begin(), groups[ph].end());
+  }
+  if (B->launched.empty()) return ASCC_OK;
+  if (hipMemcpyAsync(B->hstats, B->dstats, 64 * (size_t)B->cap, hipMemcpyDeviceToHost, B->stream) != hipSuccess ||
+      hipEventRecord(B->ev, B->stream) != hipSuccess)
     return sfail(ASCC_E_HIP, "statistics copy failed");
-  R->inflight = true;
+  B->inflight = true;
   return ASCC_OK;
 }
 
 // Consume a finished iteration's statistics; returns true if the request is finished.
-bool consume(ascc_server* S, Request* R, double now) {
+bool consume(ascc_server* S, Request* R, const double* st, hipStream_t s, double now) {
   const ascc_opts& o = S->opts.solve;
-  const double* st = R->hstats;
   if (R->iterations == 0) {  // the uploads ran before this iteration on the same stream
     std::vector<double>().swap(R->hB);
     std::vector<double>().swap(R->heps);
@@ -297,20 +404,18 @@ bool consume(ascc_server* S, Request* R, double now) {
     if (done) {
       R->lowp_phase = false;
       (void)ascc_set_precision(R->ints, ASCC_PREC_FP64);
-      (void)ascc_diis_reset(R->diis, R->stream);
+      (void)ascc_diis_reset(R->diis, s);
     }
-  } else {
-    if (ok) {
-      R->status = ASCC_OK;
-      R->t_done = now;
-      (void)ascc_reference_energy(R->ints, &R->e_ref, R->stream);  // the stream is idle: no wait
-      return true;
-    }
+  } else if (ok) {
+    R->status = ASCC_OK;
+    R->t_done = now;
+    (void)ascc_reference_energy(R->ints, &R->e_ref, s);  // the stream is idle: no wait
+    return true;
   }
   if (R->iterations >= o.maxiter) {
     R->status = ASCC_E_NOT_CONVERGED;
     R->t_done = now;
-    (void)ascc_reference_energy(R->ints, &R->e_ref, R->stream);
+    (void)ascc_reference_energy(R->ints, &R->e_ref, s);
     return true;
   }
   return false;
@@ -351,7 +456,7 @@ int ascc_server_submit_state(ascc_server* S, const double* h_B, const double* h_
     size_t ib = 0, db = 0, pb = 0;
     const size_t bytes = request_bytes(S, no, nv, naux, true, &ib, &db, &pb);
     if (!bytes) return ASCC_E_SHAPE;
-    if (bytes > S->slab_bytes) return sfail(ASCC_E_NOMEM, "request larger than the whole HBM budget");
+    if (bucket_header(1) + bytes > S->slab_bytes) return sfail(ASCC_E_NOMEM, "request larger than the whole HBM budget");
   }
   int rc = ascc_server_submit(S, h_B, h_eps, no, nv, naux, t_submit, id);
   if (rc) return rc;
@@ -371,7 +476,7 @@ int ascc_server_submit(ascc_server* S, const double* h_B, const double* h_eps, i
   // the footprint of a PLASCC request (ascc_server_submit_state) is checked there
   const size_t bytes = request_bytes(S, no, nv, naux, false, &ib, &db, &pb);
   if (!bytes) return ASCC_E_SHAPE;  // message set by ascc_workspace_bytes
-  if (bytes > S->slab_bytes) return sfail(ASCC_E_NOMEM, "request larger than the whole HBM budget");
+  if (bucket_header(1) + bytes > S->slab_bytes) return sfail(ASCC_E_NOMEM, "request larger than the whole HBM budget");
   Request* R = new Request();
   R->id = (int)S->reqs.size();
   R->o = no;
@@ -381,73 +486,94 @@ int ascc_server_submit(ascc_server* S, const double* h_B, const double* h_eps, i
   R->hB.assign(h_B, h_B + (size_t)naux * n * n);
   R->heps.assign(h_eps, h_eps + n);
   R->t_submit = t_submit;
-  R->ints_bytes = ib;
-  R->diis_bytes = db;
-  R->bytes = 0;
   S->reqs.push_back(R);
   S->queue.push_back(R->id);
   *id = R->id;
-  (void)bytes;
   return ASCC_OK;
 }
 
 int ascc_server_step(ascc_server* S, double now, int* n_queued, int* n_running, int* n_done) {
   if (!S) return sfail(ASCC_E_ARG, "NULL server");
-  // 1. finished iterations
-  for (size_t k = 0; k < S->running.size();) {
-    Request* R = S->reqs[S->running[k]];
-    if (R->inflight) {
-      const hipError_t q = hipEventQuery(R->ev);
-      if (q == hipErrorNotReady) {
-        ++k;
-        continue;
-      }
-      R->inflight = false;
+  // 1. finished iterations: every slot of a bucket whose iteration has completed
+  std::vector<int> bids;
+  for (auto& b : S->buckets) bids.push_back(b.first);
+  for (int bid : bids) {
+    Bucket* B = S->buckets[bid];
+    if (!B->inflight) continue;
+    const hipError_t q = hipEventQuery(B->ev);
+    if (q == hipErrorNotReady) continue;
+    B->inflight = false;
+    for (int k : B->launched) {
+      const int id = B->slot_req[k];
+      if (id < 0) continue;
+      Request* R = S->reqs[id];
+      bool finished;
       if (q != hipSuccess) {
         R->status = ASCC_E_HIP;
         R->t_done = now;
-      } else if (!consume(S, R, now)) {
-        ++k;
-        continue;
+        finished = true;
+      } else {
+        finished = consume(S, R, B->hstats + 8 * k, B->stream, now);
       }
-      release(S, R);
-      S->n_done += 1;
-      S->running.erase(S->running.begin() + k);
-      continue;
+      if (finished) {
+        release_request(S, R);
+        S->running -= 1;
+        S->n_done += 1;
+        if (!S->buckets.count(bid)) break;  // the bucket emptied and was released
+      }
     }
-    ++k;
+    if (S->buckets.count(bid) && S->buckets[bid]->used() == 0) release_bucket(S, bid);
   }
-  // 2. admission in arrival order while the head fits the remaining budget and a slot is free
-  while (!S->queue.empty() && (int)S->running.size() < S->opts.max_active) {
+  // 2. admission in arrival order while the head fits (a free slot of its shape's bucket, or a new
+  //    bucket in the remaining budget) and fewer than max_active requests run
+  while (!S->queue.empty() && S->running < S->opts.max_active) {
     Request* R = S->reqs[S->queue.front()];
     const size_t bytes = request_bytes(S, R->o, R->v, R->Q, R->plascc, &R->ints_bytes, &R->diis_bytes,
                                        &R->plascc_bytes);
-    size_t off = 0;
-    if (!slab_take(S, bytes, &off)) break;
-    R->off = off;
-    R->bytes = bytes;
+    const bool shared = R->hole < 0 && !R->plascc;
+    int bid = -1, slot = -1;
+    if (shared)
+      for (auto& b : S->buckets) {
+        Bucket* B = b.second;
+        if (!B->shared || B->o != R->o || B->v != R->v || B->Q != R->Q) continue;
+        for (int k = 0; k < B->cap && slot < 0; ++k)
+          if (B->slot_req[k] < 0) slot = k;
+        if (slot >= 0) {
+          bid = b.first;
+          break;
+        }
+      }
+    if (bid < 0) {
+      const int rc = open_bucket(S, R, bytes, &bid);
+      if (rc == ASCC_E_NOMEM) break;  // waits for memory
+      if (rc) return rc;
+      slot = 0;
+    }
+    Bucket* B = S->buckets[bid];
     S->queue.pop_front();
+    R->bucket = R->last_bucket = bid;
+    R->slot = R->last_slot = slot;
+    R->bytes = bytes;
+    B->slot_req[slot] = R->id;
     const int rc = admit(S, R, now);
     if (rc) {
       R->status = rc;
       R->t_done = now;
-      if (R->stream) (void)hipStreamSynchronize(R->stream);
-      release(S, R);
+      (void)hipStreamSynchronize(B->stream);
+      release_request(S, R);
       S->n_done += 1;
       continue;
     }
-    S->running.push_back(R->id);
+    S->running += 1;
   }
-  // 3. one more iteration for every running request that is idle
-  for (int id : S->running) {
-    Request* R = S->reqs[id];
-    if (!R->inflight) {
-      const int rc = launch(R);
-      if (rc) return rc;
-    }
+  // 3. one more iteration for the running slots of every idle bucket
+  for (auto& b : S->buckets) {
+    if (b.second->inflight) continue;
+    const int rc = launch_bucket(S, b.second);
+    if (rc) return rc;
   }
   if (n_queued) *n_queued = (int)S->queue.size();
-  if (n_running) *n_running = (int)S->running.size();
+  if (n_running) *n_running = S->running;
   if (n_done) *n_done = S->n_done;
   return ASCC_OK;
 }
@@ -473,6 +599,8 @@ int ascc_server_info(const ascc_server* S, int id, ascc_request_info* info) {
   info->e_ref = R->e_ref;
   info->hole = R->hole;
   info->particle = R->particle;
+  info->bucket = R->last_bucket;
+  info->slot = R->last_slot;
   return ASCC_OK;
 }
 
@@ -480,12 +608,18 @@ void ascc_server_free(ascc_server* S) {
   if (!S) return;
   (void)hipDeviceSynchronize();
   for (Request* R : S->reqs) {
-    release(S, R);
+    if (R->diis) ascc_diis_free(R->diis);
+    if (R->ints) ascc_ints_free(R->ints);
     delete R;
+  }
+  std::vector<int> bids;
+  for (auto& b : S->buckets) bids.push_back(b.first);
+  for (int bid : bids) {
+    S->buckets[bid]->inflight = false;
+    release_bucket(S, bid);
   }
   for (hipStream_t s : S->stream_pool) (void)hipStreamDestroy(s);
   for (hipEvent_t e : S->event_pool) (void)hipEventDestroy(e);
-  for (double* p : S->pinned_pool) (void)hipHostFree(p);
   unregister_buffer(S->slab);
   (void)hipFree(S->slab);
   delete S;

@@ -285,6 +285,5 @@ def test_served_plascc_request_footprint_is_exact(P):
     def al(x):
         return (x + 255) // 256 * 256
 
-    expect = al(ib) + al(db) + 2 * al(8 * o * v) + 2 * al(8 * o * o * v * v) + al(8) + al(64) + al(8 * n) + \
-        al(8 * Q * n * n)
+    expect = al(ib) + al(db) + 2 * al(8 * o * v) + 2 * al(8 * o * o * v * v) + al(8) + al(8 * n) + al(8 * Q * n * n)
     assert plain["bytes"] == expect

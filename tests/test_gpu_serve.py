@@ -162,3 +162,38 @@ def test_served_plascc_state_matches_oracle(P):
     assert abs(res[3]["e_corr"] - res[2]["e_corr"]) > 1e-4  # PLASCC differs from ASCC
     alone = _serve(P, reqs, [3], P.ASCC_PREC_FP64, tol_rnorm=1e-8, maxiter=400)[3]
     assert alone["iterations"] == res[3]["iterations"] and alone["e_corr"] == res[3]["e_corr"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_same_size_requests_share_a_bucket_and_match_alone(P, prec):
+    """Six requests of one shape (o4 v16 Q60, different integrals) arriving together run as slots of
+    one bucket -- one batched launch per contraction for all of them -- and each result equals the
+    request served alone bit for bit (the same kernels and summation order per slot), with two other
+    shapes in the mix."""
+    from oracle import cs_ccsd, solver
+
+    reqs = []
+    for k in range(6):
+        B, eps = make_system(4, 16, 60, 700 + k, sigma=converging_sigma(16, 60))
+        reqs.append((4, B, eps))
+    for k, o in enumerate([3, 5]):
+        v, Q = 4 * o, 15 * o
+        B, eps = make_system(o, v, Q, 720 + k, sigma=converging_sigma(v, Q))
+        reqs.append((o, B, eps))
+    pc = P.ASCC_PREC_FP64 if prec == "fp64" else P.ASCC_PREC_BF16X3
+    mixed = _serve(P, reqs, list(range(len(reqs))), pc, budget=4 << 30, max_active=16)
+    buckets = {mixed[k]["bucket"] for k in range(6)}
+    assert len(buckets) == 1 and sorted(mixed[k]["slot"] for k in range(6)) == list(range(6))
+    assert all(mixed[k]["bucket"] not in buckets for k in (6, 7))
+    for k in range(len(reqs)):
+        alone = _serve(P, reqs, [k], pc, budget=4 << 30)[k]
+        m = mixed[k]
+        print(k, prec, m["e_corr"], alone["e_corr"], m["iterations"], m["lowp_iterations"], flush=True)
+        assert alone["status"] == 0 and m["status"] == 0
+        assert alone["iterations"] == m["iterations"] and alone["lowp_iterations"] == m["lowp_iterations"]
+        assert alone["e_corr"] == m["e_corr"]
+    o, B, eps = reqs[2]
+    ref = solver.solve(lambda a, b: cs_ccsd.residual(B, np.diag(eps), a, b),
+                       lambda a, b: cs_ccsd.energy(B, np.diag(eps), a, b), eps, np.zeros((o, 16)),
+                       np.zeros((o, o, 16, 16)), maxiter=200, tol_rnorm=1e-9)
+    assert abs(mixed[2]["e_corr"] - ref["E"]) <= 1e-8
