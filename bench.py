@@ -154,6 +154,7 @@ def build_handle(P, torch, B, eps, o, vvvv, precision):
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
     del dB, deps
+    ints.bench_build = (prec, mode)
     return ints, build_s
 
 
@@ -168,17 +169,26 @@ def timed_steps(P, torch, ints, o, v, precision, steps, warmup, guesses=None, pl
     if plascc is not None:
         P.ascc_set_plascc(ints, *plascc)
     nst = 1 if guesses is None else len(guesses)
-    t1s = [torch.zeros((o, v), dtype=torch.float64, device=dev) for _ in range(nst)]
-    t2s = [torch.zeros((o, o, v, v), dtype=torch.float64, device=dev) for _ in range(nst)]
+    # the states' arrays stacked (evenly spaced), so a batch runs its terms in grouped passes
+    T1 = torch.zeros((nst, o, v), dtype=torch.float64, device=dev)
+    T2 = torch.zeros((nst, o, o, v, v), dtype=torch.float64, device=dev)
     for k, (i, a) in enumerate(guesses or []):
-        t1s[k][i, a] = 0.5
-    r1s, r2s = [torch.empty_like(t) for t in t1s], [torch.empty_like(t) for t in t2s]
+        T1[k, i, a] = 0.5
+    R1, R2 = torch.empty_like(T1), torch.empty_like(T2)
+    t1s, t2s, r1s, r2s = list(T1), list(T2), list(R1), list(R2)
     e = torch.empty(nst, dtype=torch.float64, device=dev)
     stats = torch.empty((nst, 8), dtype=torch.float64, device=dev)
     diis = [P.ascc_diis_create(ints, 8, 1) for _ in range(nst)]
     stream = torch.cuda.current_stream()
+    group = 1
     if guesses is not None:
-        P.ascc_batch_reserve(ints, nst)
+        # states per grouped pass: as many work-array copies (up to 4) as 80% of the free memory holds
+        pc, vm = ints.bench_build  # the precision and vvvv storage the handle was built with
+        base = P.ascc_batch_workspace_bytes(o, v, ints.naux, nst, 1, precision=pc, vvvv_mode=vm)
+        block = P.ascc_batch_workspace_bytes(o, v, ints.naux, nst, 2, precision=pc, vvvv_mode=vm) - base
+        free = torch.cuda.mem_get_info()[0]
+        group = int(max(1, min(4, nst, (0.8 * free - base) // max(block, 1))))
+        P.ascc_batch_reserve_ws(ints, nst, group)
 
     def step():
         if guesses is None:
@@ -210,9 +220,9 @@ def timed_steps(P, torch, ints, o, v, precision, steps, warmup, guesses=None, pl
         d.close()
     if plascc is not None:
         P.ascc_set_plascc(ints, -1)
-    del t1s, t2s, r1s, r2s
+    del t1s, t2s, r1s, r2s, T1, T2, R1, R2
     torch.cuda.empty_cache()
-    return dict(ms_step=ms_step, wall=wall, phases=phases, steps=steps, nstates=nst,
+    return dict(ms_step=ms_step, wall=wall, phases=phases, steps=steps, nstates=nst, group=group,
                 last={"E": [float(x) for x in st[:, 0]] if nst > 1 else float(st[0, 0]),
                       "rnorm": [float(x) for x in st[:, 3]] if nst > 1 else float(st[0, 3]),
                       "finite": bool(np.isfinite(st[:, 3]).all())})
@@ -676,8 +686,9 @@ def headline(args):
             "workload": args.workload, "no": o, "nv": v, "naux": Q, "seed": seed, "nstates": nstates,
             "generator": args.generator, "sigma": sigma, "vvvv": args.vvvv, "precision": "fp64",
             "step": ("ascc_residual + ascc_update (one Jacobi/DIIS iteration)" if nstates == 1 else
-                     f"ascc_residual_batch over {nstates} states + {nstates} x ascc_update (FP64 master "
-                     f"amplitudes per state, wider than the FP32 sets the workload names)"),
+                     f"ascc_residual_batch over {nstates} states (one pp-ladder launch for all, the other terms "
+                     f"in batched passes of {main_run.get('group')} states) + {nstates} x ascc_update (FP64 "
+                     f"master amplitudes per state, wider than the FP32 sets the workload names)"),
             "flops_per_step_F_N6": flops,
         },
         "roofline": {

@@ -33,9 +33,9 @@
  *     or aborts; ascc_last_error() returns a message for the last failure on this thread.
  *   - Device memory: ascc_build_ints(_hbar), ascc_batch_reserve, ascc_set_plascc and
  *     ascc_diis_create allocate the library's own device memory (integrals, work arrays, DIIS
- *     history, PLASCC buffers; ascc_workspace_bytes and ascc_plascc_workspace_bytes report the
- *     amounts); ascc_*_free releases it.  Their *_ws forms carve the same arrays from a caller
- *     workspace instead and allocate nothing.  ascc_solve and ascc_two_ansatz allocate their own
+ *     history, batch buffers, PLASCC buffers; ascc_workspace_bytes, ascc_batch_workspace_bytes and
+ *     ascc_plascc_workspace_bytes report the amounts); ascc_*_free releases it.  Their *_ws forms
+ *     carve the same arrays from a caller workspace instead and allocate nothing.  ascc_solve and ascc_two_ansatz allocate their own
  *     state and free it before returning.  No other call allocates device memory.
  *   - A handle is not re-entrant: calls that share an ascc_ints (its work arrays) or an
  *     ascc_diis must be ordered on one stream.
@@ -159,16 +159,36 @@ int ascc_residual(ascc_ints* ints, const double* d_t1, const double* d_t2, doubl
 
 /* Capacity for batched residuals of up to max_states amplitude sets on this integral set:
  * allocates the stacked ladder operands and one ladder result per state (device memory;
- * freed by ascc_ints_free; a larger later request reallocates).  Synchronous.
+ * freed by ascc_ints_free; a larger later request reallocates; the same as
+ * ascc_batch_reserve_ws(ints, max_states, 1, NULL, 0)).  Synchronous.
  * Errors: ASCC_E_ARG, ASCC_E_NOMEM. */
 int ascc_batch_reserve(ascc_ints* ints, int max_states);
+
+/* Exact device bytes of a batch capacity (ascc_batch_reserve_ws with the same max_states and
+ * group) for an integral set of this shape, precision and vvvv_mode.  Host-only.
+ * Errors: ASCC_E_SHAPE, ASCC_E_ARG. */
+int ascc_batch_workspace_bytes(int no, int nv, int naux, int precision, int vvvv_mode, int max_states, int group,
+                               size_t* bytes);
+
+/* Batch capacity of max_states states whose residual terms other than the pp ladder run `group`
+ * states at a time as one batched pass (every contraction one launch over the group's states
+ * against the shared integrals, 1 <= group <= max_states; group = 1: state by state): the stacked
+ * ladder operands and results plus `group` copies of the residual work arrays (about the integral
+ * set's own work arrays each; ascc_batch_workspace_bytes gives the total).  d_workspace != NULL:
+ * carved from it (256-byte aligned, >= that size; it must outlive the handle; no allocation);
+ * NULL: allocated (freed by ascc_ints_free).  Replaces any earlier capacity.  Host-only.
+ * Errors: ASCC_E_ARG, ASCC_E_NOMEM. */
+int ascc_batch_reserve_ws(ascc_ints* ints, int max_states, int group, void* d_workspace, size_t ws_bytes);
 
 /* Residuals and energies of nstates amplitude sets that share this integral set (several
  * states of one Hamiltonian).  d_t1[k], d_t2[k], d_r1[k], d_r2[k] are host arrays of device
  * pointers with the shapes of ascc_residual; d_e is a device array [nstates].  The particle-
  * particle ladders of all states are one launch over the shared vvvv block (its tiles are
- * streamed once for the batch); every other term runs per state.  Each state's result is the
- * one ascc_residual gives for it alone (the same arithmetic in the same order).  Asynchronous.
+ * streamed once for the batch).  With a capacity of group > 1 and evenly spaced state arrays
+ * (d_t1[k] = d_t1[0] + k (d_t1[1] - d_t1[0]), likewise d_t2, d_r1, d_r2) every other term runs
+ * `group` states per batched pass; otherwise state by state (and always with the PLASCC removal).
+ * Each state's result is the one ascc_residual gives for it alone (the same arithmetic in the same
+ * order).  Asynchronous.
  * Errors: ASCC_E_ARG, ASCC_E_STATE (nstates above the reserved capacity), ASCC_E_HIP. */
 int ascc_residual_batch(ascc_ints* ints, int nstates, const double* const* d_t1, const double* const* d_t2,
                         double* const* d_r1, double* const* d_r2, double* d_e, void* stream);

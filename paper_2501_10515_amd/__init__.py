@@ -27,6 +27,8 @@ from ._lib import (  # noqa: F401
     Ints,
     Server,
     ascc_batch_reserve,
+    ascc_batch_reserve_ws,
+    ascc_batch_workspace_bytes,
     ascc_build_ints,
     ascc_build_ints_hbar,
     ascc_build_ints_hbar_ws,

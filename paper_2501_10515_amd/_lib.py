@@ -75,7 +75,7 @@ EXPORTS = ("ascc_workspace_bytes", "ascc_build_ints", "ascc_residual", "ascc_dii
            "ascc_server_info", "ascc_server_free", "ascc_build_ints_hbar", "ascc_initial_guess",
            "ascc_reference_energy", "ascc_set_plascc", "ascc_two_ansatz", "ascc_build_ints_hbar_ws",
            "ascc_server_submit_state", "ascc_plascc_workspace_bytes", "ascc_set_plascc_ws",
-           "ascc_solve_noalloc")
+           "ascc_solve_noalloc", "ascc_batch_workspace_bytes", "ascc_batch_reserve_ws")
 
 
 def load_library():
@@ -101,6 +101,8 @@ def load_library():
     L.ascc_set_plascc.argtypes = [vp, c_int, c_int]
     L.ascc_plascc_workspace_bytes.argtypes = [c_int, c_int, c_int, c_size_p]
     L.ascc_set_plascc_ws.argtypes = [vp, c_int, c_int, vp, ctypes.c_size_t, vp]
+    L.ascc_batch_workspace_bytes.argtypes = [c_int] * 7 + [c_size_p]
+    L.ascc_batch_reserve_ws.argtypes = [vp, c_int, c_int, vp, ctypes.c_size_t]
     L.ascc_diis_create.argtypes = [vp, c_int, c_int, ctypes.POINTER(vp)]
     L.ascc_diis_reset.argtypes = [vp, vp]
     L.ascc_update.argtypes = [vp, vp, vp, vp, vp, vp, vp, c_double, vp, vp]
@@ -417,6 +419,25 @@ def ascc_get_precision(ints: Ints) -> int:
 
 def ascc_batch_reserve(ints: Ints, max_states: int):
     _check(load_library().ascc_batch_reserve(ints.handle, max_states))
+
+
+def ascc_batch_workspace_bytes(no: int, nv: int, naux: int, max_states: int, group: int = 1,
+                               precision: int = ASCC_PREC_FP64, vvvv_mode: int = ASCC_VVVV_FULL) -> int:
+    b = ctypes.c_size_t()
+    _check(load_library().ascc_batch_workspace_bytes(no, nv, naux, precision, vvvv_mode, max_states, group,
+                                                     ctypes.byref(b)))
+    return b.value
+
+
+def ascc_batch_reserve_ws(ints: Ints, max_states: int, group: int = 1, workspace=None):
+    """Batch capacity with `group` states per batched pass; workspace: a device tensor of at least
+    ascc_batch_workspace_bytes bytes (kept alive with the handle), or None to let the library allocate."""
+    if workspace is None:
+        _check(load_library().ascc_batch_reserve_ws(ints.handle, max_states, group, None, 0))
+        return
+    nbytes = workspace.numel() * workspace.element_size()
+    _check(load_library().ascc_batch_reserve_ws(ints.handle, max_states, group, _dev(workspace, "workspace"), nbytes))
+    ints._keep = getattr(ints, "_keep", []) + [workspace]
 
 
 def ascc_residual_batch(ints: Ints, t1s, t2s, r1s, r2s, e, stream=None):

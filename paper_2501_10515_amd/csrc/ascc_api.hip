@@ -209,6 +209,9 @@ struct ascc_ints {
   int max_states = 0;
   double *Tp_all = nullptr, *Rp_all = nullptr, *RL_all = nullptr;
   float* Tpf_all = nullptr;
+  int group = 1;             // states per batched pass of the other terms (ascc_batch_reserve_ws)
+  char* group_base = nullptr;  // `group` work blocks of group_block bytes
+  size_t group_block = 0;
   Pool batch;
   // partial linearisation (ascc_set_plascc): primaries and the slab buffers of the removal
   int pl_hole = -1, pl_pa = -1;
@@ -1346,6 +1349,138 @@ int check_shape(int no, int nv, int naux) {
   return ASCC_OK;
 }
 
+// The residual work arrays of an integral set (what one state's residual writes; not the
+// ladder operands, which a batch stacks separately), FP64 then low precision, in carving order.
+bool is_constant(double* ascc_ints::*m) {
+  return m == &ascc_ints::B || m == &ascc_ints::h || m == &ascc_ints::eps || m == &ascc_ints::fov ||
+         m == &ascc_ints::e0 || m == &ascc_ints::Bov || m == &ascc_ints::KL || m == &ascc_ints::Lijab ||
+         m == &ascc_ints::Gwz || m == &ascc_ints::BovT || m == &ascc_ints::V || m == &ascc_ints::pairtab ||
+         m == &ascc_ints::Tp || m == &ascc_ints::Rp;
+}
+bool is_constant(float* ascc_ints::*m) {
+  return m == &ascc_ints::Vf || m == &ascc_ints::GwzTf || m == &ascc_ints::KLf || m == &ascc_ints::BovTf ||
+         m == &ascc_ints::Bovf || m == &ascc_ints::Tpf;
+}
+size_t work_block_bytes(long o, long v, long Q, int precision, int mode) {
+  size_t off = 0;
+  for (const auto& item : ints_plan(o, v, Q, mode))
+    if (!is_constant(item.first)) off = align_up(off) + std::max<size_t>((size_t)item.second, 1) * sizeof(double);
+  if (precision != ASCC_PREC_FP64)
+    for (const auto& item : lowp_plan(o, v, Q, mode))
+      if (!is_constant(item.first)) off = align_up(off) + std::max<size_t>((size_t)item.second, 1) * sizeof(float);
+  return align_up(off);
+}
+// Stacked ladder operands and results for max_states states, then `group` work blocks (group > 1).
+size_t batch_footprint(long o, long v, long Q, int precision, int mode, long max_states, int group) {
+  const long To = o * (o + 1) / 2, Tv = v * (v + 1) / 2;
+  const long rows = 2 * To * Tv, lrows = 2 * To * lowp_ld(Tv);
+  size_t off = align_up(sizeof(double) * (size_t)(max_states * rows));
+  off += align_up(sizeof(double) * (size_t)(max_states * rows));
+  off += align_up(sizeof(double) * (size_t)(max_states * o * o * v * v));
+  if (precision != ASCC_PREC_FP64) off += align_up(sizeof(float) * (size_t)(max_states * lrows));
+  if (group > 1) off += (size_t)group * work_block_bytes(o, v, Q, precision, mode);
+  return off;
+}
+
+int batch_reserve_impl(ascc_ints* I, int max_states, int group, void* ws, size_t ws_bytes) {
+  if (max_states < 1 || max_states > 4096) return fail(ASCC_E_ARG, "max_states must be in 1..4096");
+  if (group < 1 || group > max_states) return fail(ASCC_E_ARG, "group must be in 1..max_states");
+  if (ws && (reinterpret_cast<uintptr_t>(ws) % kAlign)) return fail(ASCC_E_ARG, "workspace must be 256-byte aligned");
+  const size_t need = batch_footprint(I->no, I->nv, I->naux, I->precision, I->vvvv_mode, max_states, group);
+  if (ws && ws_bytes < need) return fail(ASCC_E_NOMEM, "batch workspace too small: needs " + std::to_string(need) + " bytes");
+  free_all(I->batch);
+  I->batch = Pool();
+  I->max_states = 0;
+  I->group = 1;
+  I->group_base = nullptr;
+  I->group_block = 0;
+  I->Tp_all = I->Rp_all = I->RL_all = nullptr;
+  I->Tpf_all = nullptr;
+  if (ws) {
+    I->batch.base = static_cast<char*>(ws);
+    I->batch.size = ws_bytes;
+  }
+  const long o = I->no, v = I->nv, To = o * (o + 1) / 2, Tv = v * (v + 1) / 2;
+  const long rows = 2 * To * Tv, lrows = 2 * To * lowp_ld(Tv);
+  int rc = dalloc(I->batch, &I->Tp_all, (size_t)(max_states * rows));
+  if (!rc) rc = dalloc(I->batch, &I->Rp_all, (size_t)(max_states * rows));
+  if (!rc) rc = dalloc(I->batch, &I->RL_all, (size_t)(max_states * I->oovv));
+  if (!rc && I->precision != ASCC_PREC_FP64) rc = dalloc(I->batch, &I->Tpf_all, (size_t)(max_states * lrows));
+  if (!rc && group > 1) {
+    I->group_block = work_block_bytes(o, v, I->naux, I->precision, I->vvvv_mode);
+    rc = dalloc(I->batch, &I->group_base, (size_t)group * I->group_block);
+  }
+  if (rc) {
+    free_all(I->batch);
+    I->batch = Pool();
+    return rc;
+  }
+  I->max_states = max_states;
+  I->group = group;
+  return ASCC_OK;
+}
+
+// The residual terms other than the pp ladder (already in RL) of n states as one batched pass: the
+// handle's work arrays are pointed at the first of the group work blocks for the pass (the states'
+// arrays sit one block apart), the shared integrals are used by every state, and the states' own
+// arrays are evenly spaced (t1[k] = t1[0] + k (t1[1] - t1[0]), likewise t2, r1, r2; e[k]; RL[k] one
+// o^2 v^2 block apart).
+int residual_group(ascc_ints* I, int n, int nstates, const double* const* t1, const double* const* t2,
+                   double* const* r1, double* const* r2, double* e, double* RL, hipStream_t s) {
+  if (n == 1) return residual_core(I, t1[0], t2[0], r1[0], r2[0], e, RL, s);
+  const long o = I->no, v = I->nv, Q = I->naux;
+  // point every work array at block 0 (restored below)
+  std::vector<std::pair<double* ascc_ints::*, double*>> saved;
+  std::vector<std::pair<float* ascc_ints::*, float*>> savedf;
+  size_t off = 0;
+  for (const auto& item : ints_plan(o, v, Q, I->vvvv_mode))
+    if (!is_constant(item.first)) {
+      off = align_up(off);
+      saved.push_back({item.first, I->*(item.first)});
+      I->*(item.first) = reinterpret_cast<double*>(I->group_base + off);
+      off += std::max<size_t>((size_t)item.second, 1) * sizeof(double);
+    }
+  if (I->precision != ASCC_PREC_FP64)
+    for (const auto& item : lowp_plan(o, v, Q, I->vvvv_mode))
+      if (!is_constant(item.first)) {
+        off = align_up(off);
+        savedf.push_back({item.first, I->*(item.first)});
+        I->*(item.first) = reinterpret_cast<float*>(I->group_base + off);
+        off += std::max<size_t>((size_t)item.second, 1) * sizeof(float);
+      }
+  SlotBatch sb;
+  sb.n = n;
+  auto add = [&](const void* p, size_t bytes, long stride) {
+    const uintptr_t lo = reinterpret_cast<uintptr_t>(p);
+    sb.ranges.push_back({lo, lo + bytes, stride});
+  };
+  auto step = [&](const void* const* a) {
+    return nstates > 1 ? (long)((const char*)a[1] - (const char*)a[0]) : 0L;
+  };
+  add(I->group_base, I->group_block, (long)I->group_block);
+  add(t1[0], sizeof(double) * I->ov, step((const void* const*)t1));
+  add(t2[0], sizeof(double) * I->oovv, step((const void* const*)t2));
+  add(r1[0], sizeof(double) * I->ov, step((const void* const*)r1));
+  add(r2[0], sizeof(double) * I->oovv, step((const void* const*)r2));
+  add(e, sizeof(double), (long)sizeof(double));
+  add(RL, sizeof(double) * I->oovv, (long)(sizeof(double) * I->oovv));
+  for (const auto& item : ints_plan(o, v, Q, I->vvvv_mode))  // shared integrals: stride 0
+    if (is_constant(item.first) && I->*(item.first))
+      add(I->*(item.first), std::max<size_t>((size_t)item.second, 1) * sizeof(double), 0);
+  if (I->precision != ASCC_PREC_FP64)
+    for (const auto& item : lowp_plan(o, v, Q, I->vvvv_mode))
+      if (is_constant(item.first) && I->*(item.first))
+        add(I->*(item.first), std::max<size_t>((size_t)item.second, 1) * sizeof(float), 0);
+  int rc;
+  {
+    SlotBatchScope scope(&sb);
+    rc = residual_core(I, t1[0], t2[0], r1[0], r2[0], e, RL, s);
+  }
+  for (auto& x : saved) I->*(x.first) = x.second;
+  for (auto& x : savedf) I->*(x.first) = x.second;
+  return rc;
+}
+
 // Work buffers of the PLASCC removal (compact cross slabs, see plascc_remove), in carving order.
 std::vector<std::pair<double* ascc_ints::*, long>> plascc_plan(long o, long v, long Q) {
   const long ov = o * v, oo = o * o, vv = v * v;
@@ -1662,26 +1797,26 @@ int ascc_residual(ascc_ints* I, const double* t1, const double* t2, double* r1, 
   return residual_fp64(I, t1, t2, r1, r2, e, static_cast<hipStream_t>(stream));
 }
 
+int ascc_batch_workspace_bytes(int no, int nv, int naux, int precision, int vvvv_mode, int max_states, int group,
+                               size_t* bytes) {
+  int rc = check_shape(no, nv, naux);
+  if (rc) return rc;
+  if (!bytes || max_states < 1 || max_states > 4096 || group < 1 || group > max_states)
+    return fail(ASCC_E_ARG, "need 1 <= group <= max_states <= 4096 and an output pointer");
+  if (precision < ASCC_PREC_FP64 || precision > ASCC_PREC_BF16X3) return fail(ASCC_E_ARG, "unsupported precision");
+  *bytes = batch_footprint(no, nv, naux, precision, vvvv_mode, max_states, group);
+  return ASCC_OK;
+}
+
 int ascc_batch_reserve(ascc_ints* I, int max_states) {
   if (!I) return fail(ASCC_E_ARG, "NULL handle");
-  if (max_states < 1 || max_states > 4096) return fail(ASCC_E_ARG, "max_states must be in 1..4096");
-  if (max_states <= I->max_states) return ASCC_OK;
-  free_all(I->batch);
-  I->max_states = 0;
-  I->Tp_all = I->Rp_all = I->RL_all = nullptr;
-  I->Tpf_all = nullptr;
-  const long o = I->no, v = I->nv, To = o * (o + 1) / 2, Tv = v * (v + 1) / 2, vv = I->vv;
-  const long rows = 2 * To * Tv, lrows = 2 * To * lowp_ld(Tv);
-  int rc = dalloc(I->batch, &I->Tp_all, (size_t)(max_states * rows));
-  if (!rc) rc = dalloc(I->batch, &I->Rp_all, (size_t)(max_states * rows));
-  if (!rc) rc = dalloc(I->batch, &I->RL_all, (size_t)(max_states * I->oovv));
-  if (!rc && I->precision != ASCC_PREC_FP64) rc = dalloc(I->batch, &I->Tpf_all, (size_t)(max_states * lrows));
-  if (rc) {
-    free_all(I->batch);
-    return rc;
-  }
-  I->max_states = max_states;
-  return ASCC_OK;
+  if (max_states <= I->max_states && I->group == 1) return ASCC_OK;
+  return batch_reserve_impl(I, max_states, 1, nullptr, 0);
+}
+
+int ascc_batch_reserve_ws(ascc_ints* I, int max_states, int group, void* d_workspace, size_t ws_bytes) {
+  if (!I) return fail(ASCC_E_ARG, "NULL handle");
+  return batch_reserve_impl(I, max_states, group, d_workspace, ws_bytes);
 }
 
 int ascc_residual_batch(ascc_ints* I, int nstates, const double* const* t1, const double* const* t2,
@@ -1692,7 +1827,28 @@ int ascc_residual_batch(ascc_ints* I, int nstates, const double* const* t1, cons
   for (int k = 0; k < nstates; ++k)
     if (!t1[k] || !t2[k] || !r1[k] || !r2[k]) return fail(ASCC_E_ARG, "NULL state pointer");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  // the other terms: groups of states as one batched pass when the state arrays are evenly spaced
+  // (ascending)
+  auto even = [&](const void* const* a, size_t bytes) {
+    const long d = nstates > 1 ? (long)((const char*)a[1] - (const char*)a[0]) : 0;
+    if (nstates > 1 && d < (long)bytes) return false;
+    for (int k = 2; k < nstates; ++k)
+      if ((const char*)a[k] - (const char*)a[0] != (long)k * d) return false;
+    return true;
+  };
+  const bool grouped = I->group > 1 && I->pl_hole < 0 && even((const void* const*)t1, 8 * I->ov) &&
+                       even((const void* const*)t2, 8 * I->oovv) && even((const void* const*)r1, 8 * I->ov) &&
+                       even((const void* const*)r2, 8 * I->oovv);
   ScopedBuffers user;
+  if (grouped) {  // each array family as one span (the batched launches cross the states)
+    auto span = [&](const void* const* a, size_t bytes) {
+      user.add(a[0], (size_t)((const char*)a[nstates - 1] - (const char*)a[0]) + bytes);
+    };
+    span((const void* const*)t1, sizeof(double) * I->ov);
+    span((const void* const*)t2, sizeof(double) * I->oovv);
+    span((const void* const*)r1, sizeof(double) * I->ov);
+    span((const void* const*)r2, sizeof(double) * I->oovv);
+  }
   for (int k = 0; k < nstates; ++k) {
     user.add(t1[k], sizeof(double) * I->ov);
     user.add(t2[k], sizeof(double) * I->oovv);
@@ -1704,7 +1860,13 @@ int ascc_residual_batch(ascc_ints* I, int nstates, const double* const* t1, cons
   for (int k = 0; k < nstates; ++k) RLs[k] = I->RL_all + (long)k * I->oovv;
   int rc = pp_ladder_states(I, nstates, t2, RLs.data(), I->Tp_all, I->Rp_all, I->Tpf_all, s);
   if (rc) return rc;
-  for (int k = 0; k < nstates && !rc; ++k) rc = residual_core(I, t1[k], t2[k], r1[k], r2[k], e + k, RLs[k], s);
+  if (!grouped) {
+    for (int k = 0; k < nstates && !rc; ++k) rc = residual_core(I, t1[k], t2[k], r1[k], r2[k], e + k, RLs[k], s);
+    return rc;
+  }
+  for (int g0 = 0; g0 < nstates && !rc; g0 += I->group)
+    rc = residual_group(I, std::min(I->group, nstates - g0), nstates, t1 + g0, t2 + g0, r1 + g0, r2 + g0, e + g0,
+                        RLs[g0], s);
   return rc;
 }
 

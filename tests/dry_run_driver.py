@@ -44,6 +44,8 @@ def main(shapes):
     L.ascc_solve.argtypes = [vp, ctypes.POINTER(Opts), vp, vp, ctypes.POINTER(Result), vp]
     L.ascc_solve_noalloc.argtypes = [vp, ctypes.POINTER(Opts), vp, vp, ctypes.POINTER(Result), vp]
     L.ascc_batch_reserve.argtypes = [vp, ctypes.c_int]
+    L.ascc_batch_reserve_ws.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, ctypes.c_size_t]
+    L.ascc_batch_workspace_bytes.argtypes = [ctypes.c_int] * 7 + [ctypes.POINTER(ctypes.c_size_t)]
     L.ascc_residual_batch.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                       ctypes.POINTER(vp), vp, vp]
     L.ascc_workspace_bytes.argtypes = [ctypes.c_int] * 6 + [ctypes.POINTER(ctypes.c_size_t)] * 2
@@ -101,6 +103,21 @@ def main(shapes):
                 br2 = arr(*[fake(8 * o * o * v * v) for _ in range(S)])
                 if rc == 0:
                     rc = L.ascc_residual_batch(h, S, bt1, bt2, br1, br2, fake(8 * S), None)
+                if rc == 0:  # five evenly spaced states in batched passes of two, from an exact workspace
+                    S5, G = 5, 2
+                    wb = ctypes.c_size_t()
+                    rc = L.ascc_batch_workspace_bytes(o, v, Q, prec, mode, S5, G, ctypes.byref(wb))
+                    if rc == 0:
+                        rc = L.ascc_batch_reserve_ws(h, S5, G, fake(wb.value), wb.value)
+                    arr5 = vp * S5
+                    st1, st2, sr1, sr2 = (fake(8 * o * v * S5), fake(8 * o * o * v * v * S5), fake(8 * o * v * S5),
+                                          fake(8 * o * o * v * v * S5))
+                    bt1 = arr5(*[st1.value + 8 * o * v * k for k in range(S5)])
+                    bt2 = arr5(*[st2.value + 8 * o * o * v * v * k for k in range(S5)])
+                    br1 = arr5(*[sr1.value + 8 * o * v * k for k in range(S5)])
+                    br2 = arr5(*[sr2.value + 8 * o * o * v * v * k for k in range(S5)])
+                    if rc == 0:
+                        rc = L.ascc_residual_batch(h, S5, bt1, bt2, br1, br2, fake(8 * S5), None)
             if rc == 0:
                 res = Result()
                 rc = L.ascc_solve(h, ctypes.byref(Opts(1e-8, 0, 0, 3, 8, 1, 0.0, 1e-3, 1)), t1, t2, ctypes.byref(res),

@@ -70,3 +70,40 @@ def test_batch_capacity_is_enforced(P):
         P.ascc_residual_batch(ints, [t1, t1], [t2, t2], [t1.clone(), t1.clone()], [t2.clone(), t2.clone()], e)
     assert exc.value.code == P.ASCC_E_STATE
     ints.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("o,v,Q,S,G", [(3, 7, 15, 5, 2), (6, 40, 90, 5, 3), (9, 70, 130, 4, 4)])
+def test_grouped_passes_equal_alone_bitwise(P, o, v, Q, S, G, prec):
+    """Every term in batched passes of G states (each contraction one launch over the group against
+    the shared integrals), from a caller workspace of exactly the reported size: each state's
+    residual and energy equal the single-state ones bit for bit."""
+    import torch
+
+    from oracle import cs_ccsd
+
+    from .gpu_util import dev, gpu_residual, host
+
+    print(f"case o={o} v={v} Q={Q} S={S} G={G} prec={prec}", flush=True)
+    B, eps = make_system(o, v, Q, 43, sigma=0.1)
+    amps = [random_amplitudes(o, v, 400 + k, 0.05, 0.05) for k in range(S)]
+    pc = {"fp64": P.ASCC_PREC_FP64, "fp32": P.ASCC_PREC_FP32, "bf16x3": P.ASCC_PREC_BF16X3}[prec]
+    ints = P.ascc_build_ints(dev(B), dev(eps), o, precision=pc, vvvv_mode=P.ASCC_VVVV_PACKED)
+    nbytes = P.ascc_batch_workspace_bytes(o, v, Q, S, G, precision=pc, vvvv_mode=P.ASCC_VVVV_PACKED)
+    ws = torch.full((nbytes // 8,), float("nan"), dtype=torch.float64, device="cuda")
+    P.ascc_batch_reserve_ws(ints, S, G, ws)
+    T1 = dev(np.stack([a[0] for a in amps]))  # evenly spaced state arrays
+    T2 = dev(np.stack([a[1] for a in amps]))
+    R1, R2 = torch.empty_like(T1), torch.empty_like(T2)
+    e = torch.empty(S, dtype=torch.float64, device="cuda")
+    P.ascc_residual_batch(ints, list(T1), list(T2), list(R1), list(R2), e)
+    torch.cuda.synchronize()
+    eb = host(e)
+    for k in range(S):
+        r1, r2, ek = gpu_residual(P, ints, *amps[k])
+        assert np.array_equal(host(R1[k]), r1) and np.array_equal(host(R2[k]), r2), f"state {k}"
+        assert eb[k] == ek
+        if prec == "fp64":
+            ref1, ref2 = cs_ccsd.residual(B, np.diag(eps), *amps[k])
+            assert max(np.abs(r1 - ref1).max(), np.abs(r2 - ref2).max()) <= 1e-10
+    ints.close()
