@@ -633,11 +633,14 @@ def step_summary(run, flops, o, v, prec, nstates=1):
     lach = nstates * ladder_flops(o, v) / (lad * 1e-3) / 1e12
     out["pp_ladder_tflops"] = round(lach, 3)
     out["pp_ladder_frac"] = round(lach / PEAKS[prec], 4)
-    rings = [x for x in (phase_avg(ph, "ring_y"), phase_avg(ph, "ring_p")) if x]
-    if rings:  # in the low modes ring_p also holds the shadow of its operand
-        rms = sum(rings) / len(rings)
-        rach = nstates * ring_flops(o, v) / (rms * 1e-3) / 1e12
-        out["ring_ms"] = round(rms, 4)
+    ry, rp = ph.get("ring_y", (0.0, 0)), ph.get("ring_p", (0.0, 0))
+    if ry[1] and rp[1]:
+        # per step, each state's two ring launches (several states share a launch in a grouped
+        # pass); in the low modes ring_p also holds the shadow of its operand
+        ms_step_rings = (ry[0] + rp[0]) / run["steps"]
+        rach = 2 * nstates * ring_flops(o, v) / (ms_step_rings * 1e-3) / 1e12
+        out["ring_ms"] = round((ry[0] + rp[0]) / (ry[1] + rp[1]), 4)  # per launch
+        out["ring_ms_per_step"] = round(ms_step_rings, 4)
         out["ring_tflops"] = round(rach, 3)
         out["ring_frac"] = round(rach / PEAKS[prec], 4)
     return out
@@ -697,8 +700,8 @@ def headline(args):
                       "then P1 with P2)",
             "achieved": fp64.get("ring_tflops"), "peak": PEAKS["fp64"], "unit": "TFLOP/s",
             "frac": fp64.get("ring_frac"), "traffic": None, "launch_ms": ring_ms,
-            "algorithmic_flops_per_launch": nstates * ring_flops(o, v),
-            "share_of_step": round(2 * ring_ms / ms_step, 4) if ring_ms else None,
+            "algorithmic_flops_per_launch": main_run.get("group", 1) * ring_flops(o, v),
+            "share_of_step": round(fp64["ring_ms_per_step"] / ms_step, 4) if ring_ms else None,
         },
         "fp64_step": fp64,
         "phases_ms_per_step": {k: round(ms / main_run["steps"], 4) for k, (ms, n) in phases.items() if n},
@@ -914,6 +917,26 @@ def summarize_counters(passes, args):
     out["bf16x3_step"] = agg(list(range(ends[2] + 1, ends[3] + 1)))
     fp32_first = ends[4] + 1  # the FP32 step follows its warm-up
     out["fp32_step"] = agg(list(range(fp32_first, ends[5] + 1)))
+    # the pp-ladder launch of each step: its first contraction after the pair packing
+    def ladder(rng, tag):
+        ks = list(rng)
+        pk = [k for k in ks if "pack_tpm" in seq[k][0]["kernel"]]
+        if not pk:
+            return None
+        gm = [k for k in ks if k > pk[0] and "gemm_" in seq[k][0]["kernel"]]
+        if not gm:
+            return None
+        a = agg([gm[0]])
+        name = seq[gm[0]][0]["kernel"]
+        name = name[name.find("gemm_"):]
+        return {"kernel": name[:max(name.find("("), 0) or len(name)][:60], "traffic_bytes": a["hbm_bytes"],
+                "mfma_util": a["mfma_util"], "algorithmic_flops": ladder_flops(o, v),
+                "mfma_flops_executed": a["mfma_flops_executed"], "step": tag}
+    for tag, rng in (("fp64", fp64_step), ("bf16x3", range(ends[2] + 1, ends[3] + 1)),
+                     ("fp32", range(fp32_first, ends[5] + 1))):
+        lad = ladder(rng, tag)
+        if lad:
+            out[f"{tag}_ladder_launch"] = lad
     # the ring launches of the FP64 step: its direct-to-LDS FP64 GEMM dispatches with the largest grid
     dma = [k for k in fp64_step if "gemm_f64_dma_kernel" in seq[k][0]["kernel"]]
     if dma:
