@@ -21,6 +21,10 @@ Contents, each module citing the passage of the paper it follows:
   state (Eqs. (eqn:1CSF-S), (eqn: sim)) and the initial guess T^P(0) = S - S^2/2
   (Eq. (eqn:TP-guess)), pinned to determinant-space matrix exponentials and to the
   two-electron limit.
+* ``triples``     -- the 1-CSF mixed triples T^M_3' (Sec. II.B.1, Eq. (eqn:H1TP)): the slice of
+  triples with at least three primary spin orbitals, its spin-orbital working equations in
+  T1-transformed form and their couplings into the closed-shell singles and doubles, and an
+  ASCCSD solve; pinned to brute-force projections with T3 (``bruteforce`` extended to triples).
 * ``plascc``      -- the partially linearised residual (Sec. II.C): the closed-shell residual
   without its terms with two powers of the mixed doubles T^M (Eq. (eqn: pnm split)), pinned to
   brute-force projections with T^M taken in the spin-orbital basis.

@@ -4,11 +4,13 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
 
 What it computes (paper Sec. II.A):
 
-* the exponential ansatz with T = T1 + T2, where T_N carries the prefactor (1/N!)^2 and the
-  operator string a^dagger b^dagger ... j i (Eq. (eqn: CC equation) and the T_N definition);
+* the exponential ansatz with T = T1 + T2 (+ T3), where T_N carries the prefactor (1/N!)^2 and
+  the operator string a^dagger b^dagger ... j i (Eq. (eqn: CC equation) and the T_N definition);
 * the energy <phi_0| e^{-T} H e^{T} |phi_0> (Eq. (eqn:energy));
-* the residuals <mu| e^{-T} H e^{T} |phi_0> for every singly and doubly excited determinant
-  mu (Eq. (eqn:amp)); with S = 0 the transformed Hamiltonian is H itself (Eq. (eqn: sim)).
+* the residuals <mu| e^{-T} H e^{T} |phi_0> for every singly, doubly and (optionally) triply
+  excited determinant mu (Eq. (eqn:amp)); with S = 0 the transformed Hamiltonian is H itself
+  (Eq. (eqn: sim)).  Triples enter the 1-CSF excited-state ansatz through the mixed slice
+  T^M_3' (Sec. II.B.1); here T3 is a full antisymmetric tensor, zero wherever the caller wants.
 
 Everything is done with explicit second-quantised operators on bit-string determinants, so
 nothing here depends on a factorisation of the CC equations.  Cost grows as the number of
@@ -145,29 +147,74 @@ class BruteForce:
                 out += self._Es[nocc + a][i] @ w[a, i]
         return out
 
-    def exp_T(self, t1so, t2so, psi, sign: float = 1.0) -> np.ndarray:
+    def apply_T3(self, t3so: np.ndarray, psi: np.ndarray) -> np.ndarray:
+        """T3 psi with T3 = 1/36 sum_ijkabc t_ijk^abc a^dagger_a a^dagger_b a^dagger_c a_k a_j a_i.
+
+        a^dagger_a a^dagger_b a^dagger_c a_k a_j a_i = E_ai E_bj E_ck (all occupied i, j, k and
+        virtual a, b, c), so T3 = 1/36 sum t_ijk^abc E_ai (E_bj (E_ck psi)).
+        """
+        nocc = 2 * self.no
+        nvir = self.nso - nocc
+        E = self._Es
+        p1 = [[E[nocc + c][k] @ psi for k in range(nocc)] for c in range(nvir)]  # [c][k]
+        p2 = np.stack([np.stack([np.stack([np.stack([E[nocc + b][j] @ p1[c][k] for k in range(nocc)])
+                                           for c in range(nvir)]) for j in range(nocc)]) for b in range(nvir)])
+        w = np.einsum("ijkabc,bjckD->aiD", t3so, p2) / 36.0
+        out = np.zeros_like(psi)
+        for a in range(nvir):
+            for i in range(nocc):
+                out += E[nocc + a][i] @ w[a, i]
+        return out
+
+    def exp_T(self, t1so, t2so, psi, sign: float = 1.0, t3so=None) -> np.ndarray:
         """exp(sign*T) psi by its finite Taylor series (T is nilpotent)."""
         total = psi.copy()
         term = psi.copy()
         for k in range(1, 2 * self.no + 2):
-            term = sign * self.apply_T(t1so, t2so, term) / k
+            nxt = self.apply_T(t1so, t2so, term)
+            if t3so is not None:
+                nxt = nxt + self.apply_T3(t3so, term)
+            term = sign * nxt / k
             if not np.any(term):
                 break
             total += term
         return total
 
-    def similarity_vector(self, t1so, t2so) -> np.ndarray:
+    def similarity_vector(self, t1so, t2so, t3so=None) -> np.ndarray:
         """e^{-T} H e^{T} |phi_0>."""
-        v = self.exp_T(t1so, t2so, self.ref, 1.0)
+        v = self.exp_T(t1so, t2so, self.ref, 1.0, t3so)
         v = self.apply_H(v)
-        return self.exp_T(t1so, t2so, v, -1.0)
+        return self.exp_T(t1so, t2so, v, -1.0, t3so)
 
-    def projections(self, t1so, t2so):
-        """Energy and spin-orbital residuals R_i^a, R_ij^ab (antisymmetric) by projection.
+    def triple(self, i, j, k, a, b, c) -> np.ndarray:
+        """|phi_ijk^abc> = a^dagger_a a^dagger_b a^dagger_c a_k a_j a_i |phi_0> (spin-orbital indices,
+        occupied i, j, k from 0 and virtual a, b, c from 0)."""
+        nocc = 2 * self.no
+        E = self._Es
+        return E[nocc + a][i] @ (E[nocc + b][j] @ (E[nocc + c][k] @ self.ref))
+
+    def triples_projections(self, t1so, t2so, t3so=None, v=None) -> np.ndarray:
+        """R_ijk^abc = <phi_ijk^abc| e^{-T} H e^{T} |phi_0> for every triple, as a full antisymmetric tensor."""
+        if v is None:
+            v = self.similarity_vector(t1so, t2so, t3so)
+        nocc = 2 * self.no
+        nvir = self.nso - nocc
+        r3 = np.zeros((nocc,) * 3 + (nvir,) * 3)
+        for occ in itertools.combinations(range(nocc), 3):
+            for vir in itertools.combinations(range(nvir), 3):
+                x = float(self.triple(*occ, *vir) @ v)
+                for po, so in _signed_permutations(occ):
+                    for pv, sv in _signed_permutations(vir):
+                        r3[po + pv] = so * sv * x
+        return r3
+
+    def projections(self, t1so, t2so, t3so=None, triples: bool = False):
+        """Energy and spin-orbital residuals R_i^a, R_ij^ab (antisymmetric) by projection, and
+        R_ijk^abc as well when ``triples`` is set.
 
         |phi_i^a> = a^dagger_a a_i |phi_0>, |phi_ij^ab> = a^dagger_a a^dagger_b a_j a_i |phi_0>.
         """
-        v = self.similarity_vector(t1so, t2so)
+        v = self.similarity_vector(t1so, t2so, t3so)
         nocc = 2 * self.no
         nvir = self.nso - nocc
         E = float(self.ref @ v)
@@ -186,6 +233,8 @@ class BruteForce:
                         r2[j, i, a, b] = -x
                         r2[i, j, b, a] = -x
                         r2[j, i, b, a] = x
+        if triples:
+            return E, r1, r2, self.triples_projections(t1so, t2so, t3so, v)
         return E, r1, r2
 
     def hamiltonian_matrix(self) -> np.ndarray:
@@ -210,6 +259,15 @@ class BruteForce:
         Sz = 0.5 * sum(self._Es[alpha[s]][alpha[s]] - self._Es[beta[s]][beta[s]] for s in range(n))
         S2 = Sminus @ Splus + Sz @ Sz + Sz
         return S2.toarray()
+
+
+def _signed_permutations(idx):
+    """Every ordering of ``idx`` with the sign of the permutation that produces it."""
+    out = []
+    for perm in itertools.permutations(range(len(idx))):
+        inv = sum(1 for x in range(len(perm)) for y in range(x + 1, len(perm)) if perm[x] > perm[y])
+        out.append((tuple(idx[q] for q in perm), -1 if inv % 2 else 1))
+    return out
 
 
 def closed_shell_to_so(t1: np.ndarray, t2: np.ndarray):
