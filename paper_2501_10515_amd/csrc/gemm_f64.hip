@@ -17,7 +17,7 @@
 // (8 waves, one per CU), all with K staged 16 deep, chosen per call by how well whole rounds of 256 workgroups cover
 // the output; 64 x 64 and 32 x 32 for small outputs; 128 x 128 with split-K when a long K meets
 // too few tiles.  The particle-particle ladder has its own entry point (gemm_f64_ladder): 256-,
-// 224- or 128-row tiles, whichever pads the pair dimension least, and optionally the
+// 224-, 208- or 128-row tiles, whichever pads the pair dimension least, and optionally the
 // symmetric/antisymmetric vvvv combinations formed while staging from the stored full (ac|bd).
 #include <algorithm>
 #include <cstdint>
@@ -707,13 +707,18 @@ hipError_t gemm_f64_ladder(int M, int Tv, const double* A, const double* V, long
   p.sb1 = lb.sv;
   p.sc1 = lb.sc;
   p.tab1 = lb.tab;
-  // Row tiles of 256, 224 or 128 pair rows: the least padded M wins (each extra row is a full
+  // Row tiles of 256, 224, 208 or 128 pair rows: the least padded M wins (each extra row is a full
   // row of wasted products); on a tie the taller tile, which reads the vvvv operand fewer times.
+  // 208 rows (one wave column of 13 x 16 rows per wave) fit T(40) = 820 pairs in four tiles with
+  // 1.5 % padding where 224 rows pad by 9 %.
   const long pad256 = (M + 255L) / 256 * 256, pad224 = (M + 223L) / 224 * 224, pad128 = (M + 127L) / 128 * 128;
+  const long pad208 = (M + 207L) / 208 * 208;
   if (lb.n > 65535) return hipErrorInvalidValue;
   if (dma_eligible(p)) {
-    if (pad256 <= pad224 && pad256 <= pad128) return launch_dma<256, 128, 4, 2, 4>(p, lb.n, pmode, 1, nullptr, s);
-    if (pad224 <= pad128) return launch_dma<224, 128, 2, 4, 4>(p, lb.n, pmode, 1, nullptr, s);
+    if (pad256 <= pad224 && pad256 <= pad208 && pad256 <= pad128)
+      return launch_dma<256, 128, 4, 2, 4>(p, lb.n, pmode, 1, nullptr, s);
+    if (pad224 <= pad208 && pad224 <= pad128) return launch_dma<224, 128, 2, 4, 4>(p, lb.n, pmode, 1, nullptr, s);
+    if (pad208 <= pad128) return launch_dma<208, 128, 1, 8, 4>(p, lb.n, pmode, 1, nullptr, s);
     return launch_dma<128, 128, 2, 4, 4>(p, lb.n, pmode, 1, nullptr, s);
   }
   if (pad256 <= pad224 && pad256 <= pad128) return launch_ladder<256, 4>(p, lb.n, pmode, s);

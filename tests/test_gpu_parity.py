@@ -36,6 +36,7 @@ SHAPES = [
     (7, 45, 37, 3, True),   # ragged against every tile size
     (4, 70, 150, 4, False),
     (9, 33, 130, 5, True),
+    (19, 24, 60, 6, False), # 190 pair rows: one 208-row ladder tile
 ]
 
 
