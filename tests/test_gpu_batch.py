@@ -107,3 +107,44 @@ def test_grouped_passes_equal_alone_bitwise(P, o, v, Q, S, G, prec):
             ref1, ref2 = cs_ccsd.residual(B, np.diag(eps), *amps[k])
             assert max(np.abs(r1 - ref1).max(), np.abs(r2 - ref2).max()) <= 1e-10
     ints.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_sixteen_states_o30v270_grouped_equal_alone(P, prec):
+    """The multi-state workload at its own size: 16 states of o30 v270 Q900 (packed vvvv), the other
+    terms in passes of 3 states with a remainder pass, one ladder launch for all 16; every state's
+    residual and energy equal its single-state ones bit for bit (the single-state path is the one
+    pinned to the oracle at o20 v180 Q600)."""
+    import torch
+
+    from gen.synth_df import converging_sigma
+
+    from .gpu_util import dev, host
+
+    o, v, Q, S, G = 30, 270, 900, 16, 3
+    print(f"case o={o} v={v} Q={Q} S={S} G={G} prec={prec}", flush=True)
+    B, eps = make_system(o, v, Q, 44, sigma=converging_sigma(v, Q))
+    pc = P.ASCC_PREC_FP64 if prec == "fp64" else P.ASCC_PREC_BF16X3
+    ints = P.ascc_build_ints(dev(B), dev(eps), o, precision=pc, vvvv_mode=P.ASCC_VVVV_PACKED)
+    del B
+    nbytes = P.ascc_batch_workspace_bytes(o, v, Q, S, G, precision=pc, vvvv_mode=P.ASCC_VVVV_PACKED)
+    ws = torch.empty((nbytes // 8,), dtype=torch.float64, device="cuda")
+    P.ascc_batch_reserve_ws(ints, S, G, ws)
+    gen = torch.Generator(device="cuda").manual_seed(45)
+    T1 = 0.02 * torch.randn((S, o, v), dtype=torch.float64, device="cuda", generator=gen)
+    T2 = 0.02 * torch.randn((S, o, o, v, v), dtype=torch.float64, device="cuda", generator=gen)
+    T2 = 0.5 * (T2 + T2.permute(0, 2, 1, 4, 3))  # pair symmetry t_ij^ab = t_ji^ba
+    R1, R2 = torch.empty_like(T1), torch.empty_like(T2)
+    e = torch.empty(S, dtype=torch.float64, device="cuda")
+    P.ascc_residual_batch(ints, list(T1), list(T2), list(R1), list(R2), e)
+    torch.cuda.synchronize()
+    eb = host(e)
+    r1, r2 = torch.empty_like(T1[0]), torch.empty_like(T2[0])
+    e1 = torch.empty(1, dtype=torch.float64, device="cuda")
+    for k in range(S):
+        P.ascc_residual(ints, T1[k], T2[k], r1, r2, e1)
+        torch.cuda.synchronize()
+        assert torch.equal(R1[k], r1) and torch.equal(R2[k], r2), f"state {k}"
+        assert eb[k] == float(host(e1)[0]), f"state {k}"
+    assert float(R2.abs().max()) > 1e-3
+    ints.close()

@@ -197,3 +197,33 @@ def test_same_size_requests_share_a_bucket_and_match_alone(P, prec):
                        lambda a, b: cs_ccsd.energy(B, np.diag(eps), a, b), eps, np.zeros((o, 16)),
                        np.zeros((o, o, 16, 16)), maxiter=200, tol_rnorm=1e-9)
     assert abs(mixed[2]["e_corr"] - ref["E"]) <= 1e-8
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_thirty_two_requests_match_the_oracle(P, prec):
+    """A stream of 32 requests of five shapes (o2-o6, v = 4o, Q = 15o; up to eight of one shape),
+    arriving together into at most 16 in flight: every one converges, several share
+    buckets, every energy is within 1e-8 Eh of the oracle's solve of the same system, and four of
+    them equal the request served alone bit for bit."""
+    from oracle import cs_ccsd, solver
+
+    sizes = [2, 3, 4, 5, 6, 4, 3, 5, 4, 2, 6, 4, 3, 5, 4, 3, 2, 4, 5, 3, 6, 4, 3, 5, 2, 4, 3, 5, 4, 6, 3, 5]
+    reqs = []
+    for k, o in enumerate(sizes):
+        v, Q = 4 * o, 15 * o
+        B, eps = make_system(o, v, Q, 800 + k, sigma=converging_sigma(v, Q))
+        reqs.append((o, B, eps))
+    pc = P.ASCC_PREC_FP64 if prec == "fp64" else P.ASCC_PREC_BF16X3
+    mixed = _serve(P, reqs, list(range(len(reqs))), pc, budget=4 << 30, max_active=16)
+    assert all(mixed[k]["status"] == 0 for k in range(len(reqs)))
+    assert max(mixed[k]["slot"] for k in range(len(reqs))) >= 2  # some bucket held three or more slots
+    for k, (o, B, eps) in enumerate(reqs):
+        v = eps.size - o
+        ref = solver.solve(lambda a, b: cs_ccsd.residual(B, np.diag(eps), a, b),
+                           lambda a, b: cs_ccsd.energy(B, np.diag(eps), a, b), eps, np.zeros((o, v)),
+                           np.zeros((o, o, v, v)), maxiter=200, tol_rnorm=1e-9)
+        print(k, o, prec, mixed[k]["e_corr"], ref["E"], mixed[k]["bucket"], mixed[k]["slot"], flush=True)
+        assert abs(mixed[k]["e_corr"] - ref["E"]) <= 1e-8
+    for k in (0, 7, 18, 29):
+        alone = _serve(P, reqs, [k], pc, budget=4 << 30)[k]
+        assert alone["iterations"] == mixed[k]["iterations"] and alone["e_corr"] == mixed[k]["e_corr"]
