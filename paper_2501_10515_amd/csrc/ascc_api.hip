@@ -653,6 +653,7 @@ int pp_ladder_states(ascc_ints* I, int S, const double* const* t2s, double* cons
   if (lowp) {  // no split-K: a state's rows are summed in the same order whatever S is
     GemmLP g = lp_nt(I, M, Tv, Tv, 2, Tpf, ld, M * ld, I->Vf, ld, Tv * ld, Rp, Tv, M * Tv);
     g.ws = nullptr;
+    g.m_dec = (int)To;  // the kernel choice of one state's rows
     HIPCHK(gemm_lowp(g, s));
   }
   else if (full)

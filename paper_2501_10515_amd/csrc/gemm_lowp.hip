@@ -319,10 +319,11 @@ __global__ __launch_bounds__(256) void lowp_pm_kernel(unsigned short* __restrict
 // the fragment reads of v_mfma_f32_16x16x32_bf16 (row = lane % 16, chunk = lane / 16) and the
 // four-lanes-per-row staging stores conflict-free; padded 80-byte rows conflict 2-way on both.
 //
-// Two kernels: 256 x 128 tiles of eight 64 x 64 waves with register-staged loads (small and
-// medium contractions), and 256 x 256 tiles of eight 128 x 64 waves whose operands are loaded
-// straight into LDS by buffer_load ... lds, double-buffered (large contractions: half the LDS
-// traffic per MFMA and no staging registers).
+// Two kernels: 256 x 128 tiles of eight 64 x 64 waves with register-staged loads (small
+// contractions: fewer than 128 tiles of 256 x 256, or 64 with split-K scratch), and 256 x 256 tiles
+// of eight 128 x 64 waves whose operands are loaded straight into LDS by buffer_load ... lds,
+// double-buffered (the rest, K split into slices to fill a round when the tiles are too few: half
+// the LDS traffic per MFMA and no staging registers).
 __device__ __forceinline__ int lds_slot(int r, int c) { return r * 32 + ((c ^ ((r >> 1) & 3)) << 3); }
 
 struct LPB {
@@ -721,12 +722,28 @@ hipError_t gemm_lowp(const GemmLP& g, hipStream_t s) {
     p.B = reinterpret_cast<const unsigned short*>(g.B);
     const int nkt = (g.K + 31) / 32;
     // buffer descriptors cover one tile's rows: 256 * ld bf16 must stay below 2^31 bytes
-    const long t3 = (long)((g.M + BM3 - 1) / BM3) * ((g.N + BN3 - 1) / BN3) * nbd;
-    if (t3 >= 256 && 512L * g.lda < (1L << 31)) {
+    const int mdec = g.m_dec > 0 ? g.m_dec : g.M;
+    const long t3 = (long)((mdec + BM3 - 1) / BM3) * ((g.N + BN3 - 1) / BN3) * nbd;
+    const bool dma_ok = 512L * g.lda < (1L << 31);
+    // from 128 tiles on (half a round) the eight-wave kernel beats the register-staged one even
+    // with the round partly idle; from 64 tiles with scratch, K is cut into slices so that the
+    // tiles of all slices fill one round (partial tiles summed in slice order)
+    int dsplit = 0;
+    if (dma_ok && t3 >= 128) {
+      dsplit = 1;
+    } else if (dma_ok && g.ws && t3 >= 64) {
+      const long outs = (long)g.M * g.N * g.nb * g.nb1;
+      const long n = std::min<long>({256 / t3, (long)nkt / 16, g.ws_elems / std::max<long>(outs, 1)});
+      if (n >= 2) dsplit = (int)n;
+    }
+    if (dsplit > 0) {
       p.tiles_m = (g.M + BM3 - 1) / BM3;
       p.tiles_n = (g.N + BN3 - 1) / BN3;
-      p.ktps = nkt;
-      hipLaunchKernelGGL(gemm_bf16x3_dma_kernel, dim3(p.tiles_m * p.tiles_n, nbz, 1), dim3(NT3), 0, s, p);
+      p.ktps = (nkt + dsplit - 1) / dsplit;
+      const int split = (nkt + p.ktps - 1) / p.ktps;
+      if (split > 1) to_partials(p);
+      hipLaunchKernelGGL(gemm_bf16x3_dma_kernel, dim3(p.tiles_m * p.tiles_n, nbz, split), dim3(NT3), 0, s, p);
+      if (split > 1) reduce(split);
       return hipGetLastError();
     }
     p.tiles_m = (g.M + BM2 - 1) / BM2;

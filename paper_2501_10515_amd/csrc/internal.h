@@ -127,6 +127,9 @@ struct GemmLP {
   const int* tab1 = nullptr;
   int tab1_max = 0;
   bool per_block = false;  // kernel and split-K choices as for one outer block (see Gemm)
+  // rows that decide the kernel (0: M): operands stacking the rows of several states pass one
+  // state's rows, so that every state's rows are summed exactly as when it is alone
+  int m_dec = 0;
 };
 hipError_t gemm_lowp(const GemmLP& g, hipStream_t s);
 // Low-precision shadow of a row-major FP64 matrix with the leading dimension padded to ldo
