@@ -148,3 +148,5 @@ def test_sixteen_states_o30v270_grouped_equal_alone(P, prec):
         assert eb[k] == float(host(e1)[0]), f"state {k}"
     assert float(R2.abs().max()) > 1e-3
     ints.close()
+    del T1, T2, R1, R2, ws, r1, r2
+    torch.cuda.empty_cache()  # return the tens of GB held here to the device for the later tests

@@ -138,6 +138,7 @@ def test_mixed_precision_solves_meet_the_energy_gate_at_o40_v360(P):
     from .gpu_util import dev
 
     o, v, Q, seed = 40, 360, 1200, 2
+    torch.cuda.empty_cache()  # the integral sets here take most of the device: start from free memory
     B, eps = make_system(o, v, Q, seed, sigma=converging_sigma(v, Q))
     dB, deps = dev(B), dev(eps)
     del B
