@@ -643,6 +643,7 @@ def step_summary(run, flops, o, v, prec, nstates=1):
         out["ring_ms_per_step"] = round(ms_step_rings, 4)
         out["ring_tflops"] = round(rach, 3)
         out["ring_frac"] = round(rach / PEAKS[prec], 4)
+    out["phases_ms_per_step"] = {k: round(ms / run["steps"], 4) for k, (ms, n) in ph.items() if n}
     return out
 
 
