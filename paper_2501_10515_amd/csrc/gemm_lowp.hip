@@ -6,7 +6,8 @@
 // rounded to nearest even by the conversion kernels); C is FP64 with general strides.  Two
 // arithmetic policies:
 //
-//   FP32   : v_mfma_f32_16x16x4_f32 on FP32 shadows.
+//   FP32   : v_mfma_f32_16x16x4_f32 on FP32 shadows (256 x 256 direct-to-LDS tiles for large
+//            products, 128 x 128 register-staged ones for small).
 //   BF16X3 : the shadows are two bf16 planes, x = hi + lo with hi = RNE_bf16(x),
 //            lo = RNE_bf16(x - hi); v_mfma_f32_16x16x32_bf16 forms lo*hi + hi*lo + hi*hi (the
 //            lo*lo term, relative size 2^-16, is dropped).
@@ -591,6 +592,119 @@ __global__ __launch_bounds__(NT3, 1) void gemm_bf16x3_dma_kernel(LPB p) {
 }
 
 
+// FP32, direct to LDS: 256 x 256 tiles, eight waves of 128 x 64 (two per SIMD), v_mfma_f32_16x16x4_f32.
+// A stage holds 16 K-values of every tile row (64 bytes; the 16-byte chunk c of row r at slot
+// c ^ ((r >> 1) & 3), the layout of the FP64 direct-to-LDS kernel), four stages (three in flight),
+// one barrier per stage after a per-wave vmcnt wait.  Each wave loads 64 rows of one operand per
+// stage (four 1 KB buffer_load ... lds; rows past M or N read as zero through the buffer range
+// check, the K padding of the shadows is zero).  Each fragment read returns four K-values of a row
+// and feeds four MFMAs: lane group g = l / 16 supplies K = 4g + t to MFMA t, identically for A and B.
+// FP32 accumulation within K chunks, FP64 across them; split-K slices as in the other kernels.
+constexpr int BM4 = 256, BN4 = 256, NT4 = 512, S4 = 4;
+
+__global__ __launch_bounds__(NT4, 1) void gemm_f32_dma_kernel(LP p) {
+  __shared__ __attribute__((aligned(1024))) float T[S4][(BM4 + BN4) * 16];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave >> 2, wn = wave & 3;  // this wave's 128 x 64 block of the tile
+  int tm, tn;
+  tile_of_grouped(blockIdx.x, p.tiles_m, p.tiles_n, tm, tn);
+  const int m0 = tm * BM4, n0 = tn * BN4;
+  const int z = blockIdx.y % p.nb, z1 = blockIdx.y / p.nb;
+  const int zs = p.tab1 ? p.tab1[z1] : z1;
+  // staging: waves 0-3 load rows 64 w .. 64 w + 63 of the A tile, waves 4-7 the same of the B tile
+  const bool isA = wave < 4;
+  const int r0 = 64 * (wave & 3);
+  const float* base = isA ? p.A + z * p.sa2 + zs * p.sa1 + (long)(m0 + r0) * p.lda
+                          : p.B + z * p.sb2 + zs * p.sb1 + (long)(n0 + r0) * p.ldb;
+  const int ld = isA ? (int)p.lda : (int)p.ldb;  // row stride (floats), a multiple of 32 covering K
+  const int rows = max(0, min(64, (isA ? p.M - m0 : p.N - n0) - r0));
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, rows * ld * 4, 0x00020000);
+  const int lr = lane >> 2, c = (lane & 3) ^ ((lr >> 1) & 3);  // row in a 16-row block, chunk loaded
+  const int lrow0 = (isA ? 0 : BM4) + r0;                         // first LDS row of this wave's rows
+  auto issue = [&](int ks, int stage) {
+    lds_char_t* dst = (lds_char_t*)(lds_void_t*)&T[stage][lrow0 * 16];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const unsigned off = (unsigned)(((g * 16 + lr) * ld + ks * 16 + c * 4) * 4);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_t*)(dst + g * 1024), 16, off, 0, 0, 0);
+    }
+  };
+  double* Cb = p.C + z * p.sc2 + (p.part ? z1 : zs) * p.sc1 + blockIdx.z * p.cslice;
+  f4 acc[8][4];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  auto flush = [&](bool first) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gm = m0 + wm * 128 + i * 16 + 4 * (lane >> 4) + r;
+          const int gn = n0 + wn * 64 + j * 16 + (lane & 15);
+          if (gm < p.M && gn < p.N) {
+            double* cp = Cb + (long)gm * p.scm + (long)gn * p.scn;
+            const double v = p.alpha * (double)acc[i][j][r];
+            if (first)
+              *cp = (p.beta == 0.0) ? v : v + p.beta * *cp;
+            else
+              *cp += v;
+          }
+          acc[i][j][r] = 0.f;
+        }
+  };
+  // stages of 16 K-values [ks0, nks) of this split-K slice (ktps and chunk count 32-wide K-tiles)
+  const int ks0 = blockIdx.z * 2 * p.ktps, nks = min((p.K + 15) / 16, ks0 + 2 * p.ktps);
+  const int chunk = 2 * p.chunk;
+  const int l16 = lane & 15, q = lane >> 4;
+#pragma unroll
+  for (int st = 0; st < S4 - 1; ++st)
+    if (ks0 + st < nks) issue(ks0 + st, st);
+  for (int kc = ks0; kc < nks; kc += chunk) {
+    const int kend = min(nks, kc + chunk);
+    for (int ks = kc; ks < kend; ++ks) {
+      const int st = (ks - ks0) % S4;
+      // stage ks has landed once no more than the later stages' loads (four per stage) of this
+      // wave are in flight
+      const int ahead = min(S4 - 2, nks - 1 - ks);
+      if (ahead >= 2)
+        __builtin_amdgcn_s_waitcnt(0xF78);  // vmcnt(8)
+      else if (ahead == 1)
+        __builtin_amdgcn_s_waitcnt(0xF74);  // vmcnt(4)
+      else
+        __builtin_amdgcn_s_waitcnt(0xF70);  // vmcnt(0)
+      __builtin_amdgcn_s_barrier();
+      const float* Ts = T[st];
+      f4 fa[8], fb[4];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int r = wm * 128 + i * 16 + l16;
+        fa[i] = *reinterpret_cast<const f4*>(Ts + r * 16 + 4 * (q ^ ((r >> 1) & 3)));
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = BM4 + wn * 64 + j * 16 + l16;
+        fb[j] = *reinterpret_cast<const f4*>(Ts + r * 16 + 4 * (q ^ ((r >> 1) & 3)));
+      }
+      // the stage refilled now was last read in the previous iteration, before this barrier
+      if (ks + S4 - 1 < nks) issue(ks + S4 - 1, (ks - ks0 + S4 - 1) % S4);
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i][t], fb[j][t], acc[i][j], 0, 0, 0);
+    }
+    flush(kc == ks0);
+  }
+  if (ks0 >= nks) flush(true);
+}
+
 // C_z(m,n) = beta * C_z(m,n) + sum_s part[s][z][m][n], summed in slice order.
 __global__ __launch_bounds__(256) void lowp_splitk_reduce(double* C, long scm, long scn, long sc2, long sc1, int nb,
                                                           const int* tab1, double beta, const double* part, int M,
@@ -759,6 +873,35 @@ hipError_t gemm_lowp(const GemmLP& g, hipStream_t s) {
   common(p);
   p.A = g.A;
   p.B = g.B;
+  {
+    // the direct-to-LDS kernel for the same sizes as the split-BF16x3 one (16-byte aligned rows,
+    // zero-padded to whole K stages of 16)
+    const int mdec = g.m_dec > 0 ? g.m_dec : g.M;
+    const long t4 = (long)((mdec + BM4 - 1) / BM4) * ((g.N + BN4 - 1) / BN4) * nbd;
+    const int nkt = (g.K + 31) / 32;
+    const long k16 = (g.K + 15L) / 16 * 16;
+    auto al16 = [](const void* x) { return (reinterpret_cast<uintptr_t>(x) & 15) == 0; };
+    const bool dma_ok = al16(g.A) && al16(g.B) && ((g.lda | g.ldb | g.sa2 | g.sb2 | g.sa1 | g.sb1) & 3) == 0 &&
+                        g.lda >= k16 && g.ldb >= k16 && 256L * std::max(g.lda, g.ldb) < (1L << 31);
+    int dsplit = 0;
+    if (dma_ok && t4 >= 128) {
+      dsplit = 1;
+    } else if (dma_ok && g.ws && t4 >= 64) {
+      const long outs = (long)g.M * g.N * g.nb * g.nb1;
+      const long n = std::min<long>({256 / t4, (long)nkt / 16, g.ws_elems / std::max<long>(outs, 1)});
+      if (n >= 2) dsplit = (int)n;
+    }
+    if (dsplit > 0) {
+      p.tiles_m = (g.M + BM4 - 1) / BM4;
+      p.tiles_n = (g.N + BN4 - 1) / BN4;
+      p.ktps = (nkt + dsplit - 1) / dsplit;
+      const int split = (nkt + p.ktps - 1) / p.ktps;
+      if (split > 1) to_partials(p);
+      hipLaunchKernelGGL(gemm_f32_dma_kernel, dim3(p.tiles_m * p.tiles_n, nbz, split), dim3(NT4), 0, s, p);
+      if (split > 1) reduce(split);
+      return hipGetLastError();
+    }
+  }
   p.tiles_m = (g.M + BM - 1) / BM;
   p.tiles_n = (g.N + BN - 1) / BN;
   const SplitPlan sp = plan_split(g, (long)p.tiles_m * p.tiles_n * nbd, (g.K + 31) / 32);
