@@ -64,8 +64,8 @@ enum {
   ASCC_PREC_FP64 = 0,  /* every contraction in FP64 on the FP64 matrix cores                    */
   ASCC_PREC_FP32 = 1,  /* the N^6 contractions (pp ladder, W/Z, rings) on FP32 matrix cores     */
   ASCC_PREC_BF16X3 = 2 /* the same on bf16 matrix cores with x = hi + lo splits: hi*hi + hi*lo  */
-                       /* + lo*hi.  Both low modes accumulate in FP32 within K chunks (2048 for */
-                       /* FP32, 8192 for BF16X3) and in FP64 across chunks; everything else   */
+                       /* + lo*hi.  Both low modes accumulate in FP32 within K chunks of 8192  */
+                       /* and in FP64 across chunks; everything else                         */
                        /* stays FP64                                                          */
 };
 

@@ -8,9 +8,9 @@ pytestmark = pytest.mark.gpu
 
 # Error bounds relative to max|R| of the exact residual.  FP32 operands carry a relative
 # rounding error u = 2^-24 each; BF16x3 products drop the lo*lo term (2^-16 relative) and keep
-# hi/lo representation errors of 2^-17; FP32 accumulates within K chunks of 2048 and BF16x3
-# within chunks of 8192 (then FP64 across chunks).  With sums of a few thousand terms of mixed
-# sign the observed error stays well below sqrt(K)*u_eff times the largest term; the bounds below
+# hi/lo representation errors of 2^-17; both accumulate in FP32 within K chunks of 8192 (then FP64
+# across chunks).  With sums of a few thousand terms of mixed sign the observed error stays well
+# below sqrt(K)*u_eff times the largest term; the bounds below
 # leave a factor of about ten over what is measured.
 REL = {"fp32": 2e-6, "bf16x3": 4e-5}
 
@@ -100,8 +100,8 @@ def test_refined_solve_matches_fp64_oracle(P, prec):
 def test_lowp_ladder_over_several_k_chunks(P, mode, prec):
     """o40 v130: the ladder product has M = T(o) = 820 rows per half and K = N = T(v) = 8515, so the
     split-BF16x3 contraction runs on its direct-to-LDS kernel (4 x 34 x 2 = 272 tiles of 256 x 256)
-    and flushes its FP32 sums into the FP64 result twice (K chunks of 8192), and the FP32 one five
-    times (chunks of 2048): the residual against the FP64 oracle."""
+    and flushes its FP32 sums into the FP64 result twice (K chunks of 8192), as does the FP32 one on
+    its direct-to-LDS kernel: the residual against the FP64 oracle."""
     from oracle import cs_ccsd
 
     from .gpu_util import dev, gpu_residual
