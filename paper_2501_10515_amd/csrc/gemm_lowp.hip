@@ -51,6 +51,14 @@ struct LP {
   long sa1, sb1, sc1;
 };
 
+// The eight-wave split-BF16x3 kernel adds a later FP32 chunk's partial sum into the FP64 result with
+// a non-returning FP64 atomic add, performed at L2: the old value is never read into registers
+// (2.8 % of the o40 v360 split-BF16x3 step; the FP32 kernels' 16 x 16 output layout, four rows per
+// instruction, made the same change twice as slow there, so they keep the load-add-store).  Each
+// element has one writer (the lane that owns it) and its chunks arrive in order, so the sums are
+// those of a load-add-store; the first chunk's plain stores are waited for before any add follows.
+__device__ __forceinline__ void add_to(double* p, double v) { unsafeAtomicAdd(p, v); }
+
 // Round-to-nearest-even FP32 -> bf16 bits (finite inputs; NaN stays NaN).
 __device__ __forceinline__ unsigned short bf16_rne(float f) {
   const uint32_t u = __float_as_uint(f);
@@ -545,10 +553,11 @@ __global__ __launch_bounds__(NT3, 1) void gemm_bf16x3_dma_kernel(LPB p) {
             if (first)
               *cp = (p.beta == 0.0) ? v : v + p.beta * *cp;
             else
-              *cp += v;
+              add_to(cp, v);
           }
           acc[i][j][q] = 0.f;
         }
+    if (first) __builtin_amdgcn_s_waitcnt(0xF70);  // the stores have reached L2
   };
   const int kt0 = blockIdx.z * p.ktps, nkt = min((p.K + 31) / 32, kt0 + p.ktps);
   const int fr = lane & 31, fc = lane >> 5;  // fragment row, K-chunk within a K = 16 half
