@@ -111,7 +111,7 @@ __global__ __launch_bounds__(NT, 1) void gemm_lowp_kernel(LP p) {
   tile_of_lp(blockIdx.x, p.tiles_m, p.tiles_m * p.tiles_n, tm, tn);
   const int m0 = tm * BM, n0 = tn * BN;
   const int z = blockIdx.y % p.nb, z1 = blockIdx.y / p.nb;
-  const int zs = p.tab1 ? p.tab1[z1] : z1;
+  const int zs = __builtin_amdgcn_readfirstlane(p.tab1 ? p.tab1[z1] : z1);  // uniform: scalar buffer descriptors
   const float* Ab = p.A + z * p.sa2 + zs * p.sa1;
   const float* Bb = p.B + z * p.sb2 + zs * p.sb1;
   double* Cb = p.C + z * p.sc2 + (p.part ? z1 : zs) * p.sc1 + blockIdx.z * p.cslice;
@@ -365,7 +365,7 @@ __global__ __launch_bounds__(NT2, 1) void gemm_bf16x3_kernel(LPB p) {
   tile_of_lp(blockIdx.x, p.tiles_m, p.tiles_m * p.tiles_n, tm, tn);
   const int m0 = tm * BM2, n0 = tn * BN2;
   const int z = blockIdx.y % p.nb, z1 = blockIdx.y / p.nb;
-  const int zs = p.tab1 ? p.tab1[z1] : z1;
+  const int zs = __builtin_amdgcn_readfirstlane(p.tab1 ? p.tab1[z1] : z1);  // uniform: scalar buffer descriptors
   const unsigned short* Ab = p.A + z * p.sa2 + zs * p.sa1;
   const unsigned short* Bb = p.B + z * p.sb2 + zs * p.sb1;
   double* Cb = p.C + z * p.sc2 + (p.part ? z1 : zs) * p.sc1 + blockIdx.z * p.cslice;
@@ -482,6 +482,17 @@ __global__ __launch_bounds__(NT2, 1) void gemm_bf16x3_kernel(LPB p) {
   if (kt0 >= nkt) flush(true);
 }
 
+// Buffer descriptor of a wave-uniform range (base, bytes), built from scalar registers: every
+// component goes through readfirstlane, so the buffer loads take it straight from SGPRs (left to
+// itself the compiler kept parts of it in VGPRs and wrapped each load in a waterfall loop).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t uniform_rsrc(const void* base, int bytes) {
+  const uintptr_t b = reinterpret_cast<uintptr_t>(base);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+  void* ub = reinterpret_cast<void*>(((uintptr_t)hi << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(ub, (short)0, __builtin_amdgcn_readfirstlane(bytes), 0x00020000);
+}
+
 // 256 x 256 tiles, eight waves of 128 x 64 (two per SIMD, so one wave's fragment reads and barrier
 // wait overlap the other's MFMAs), v_mfma_f32_32x32x16_bf16 (4 x 2 fragments of 32 x 32 per wave).
 // Each wave stages half of one operand plane per K-step (A hi, A lo, B hi, B lo: 128 rows x 64
@@ -508,7 +519,7 @@ __global__ __launch_bounds__(NT3, 1) void gemm_bf16x3_dma_kernel(LPB p) {
   tile_of_grouped(blockIdx.x, p.tiles_m, p.tiles_n, tm, tn);
   const int m0 = tm * BM3, n0 = tn * BN3;
   const int z = blockIdx.y % p.nb, z1 = blockIdx.y / p.nb;
-  const int zs = p.tab1 ? p.tab1[z1] : z1;
+  const int zs = __builtin_amdgcn_readfirstlane(p.tab1 ? p.tab1[z1] : z1);  // uniform: scalar buffer descriptors
   const int lplane = wave >> 1, lhalf = wave & 1;  // staging: plane (A hi, A lo, B hi, B lo), row half
   const bool isA = lplane < 2;
   const unsigned short* base = isA ? p.A + z * p.sa2 + zs * p.sa1 + (long)m0 * p.lda
@@ -516,8 +527,7 @@ __global__ __launch_bounds__(NT3, 1) void gemm_bf16x3_dma_kernel(LPB p) {
   const int ld = isA ? (int)p.lda : (int)p.ldb;  // row stride (bf16): K-blocks of [hi 32 | lo 32]
   const int plane = lplane & 1;
   const int rows = min(256, isA ? p.M - m0 : p.N - n0);
-  const __amdgpu_buffer_rsrc_t rs =
-      __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, rows * ld * 2, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rs = uniform_rsrc(base, rows * ld * 2);
   const int r = lane >> 2, c = (lane & 3) ^ ((r >> 1) & 3);  // row in a 16-row block, chunk loaded
   auto issue = [&](int kt, int stage) {
     const int gk = kt * 32 + c * 8, col = kt * 64 + plane * 32 + c * 8;
@@ -620,7 +630,7 @@ __global__ __launch_bounds__(NT4, 1) void gemm_f32_dma_kernel(LP p) {
   tile_of_grouped(blockIdx.x, p.tiles_m, p.tiles_n, tm, tn);
   const int m0 = tm * BM4, n0 = tn * BN4;
   const int z = blockIdx.y % p.nb, z1 = blockIdx.y / p.nb;
-  const int zs = p.tab1 ? p.tab1[z1] : z1;
+  const int zs = __builtin_amdgcn_readfirstlane(p.tab1 ? p.tab1[z1] : z1);  // uniform: scalar buffer descriptors
   // staging: waves 0-3 load rows 64 w .. 64 w + 63 of the A tile, waves 4-7 the same of the B tile
   const bool isA = wave < 4;
   const int r0 = 64 * (wave & 3);
@@ -628,8 +638,7 @@ __global__ __launch_bounds__(NT4, 1) void gemm_f32_dma_kernel(LP p) {
                           : p.B + z * p.sb2 + zs * p.sb1 + (long)(n0 + r0) * p.ldb;
   const int ld = isA ? (int)p.lda : (int)p.ldb;  // row stride (floats), a multiple of 32 covering K
   const int rows = max(0, min(64, (isA ? p.M - m0 : p.N - n0) - r0));
-  const __amdgpu_buffer_rsrc_t rs =
-      __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, rows * ld * 4, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rs = uniform_rsrc(base, rows * ld * 4);
   const int lr = lane >> 2, c = (lane & 3) ^ ((lr >> 1) & 3);  // row in a 16-row block, chunk loaded
   const int lrow0 = (isA ? 0 : BM4) + r0;                         // first LDS row of this wave's rows
   auto issue = [&](int ks, int stage) {
