@@ -59,6 +59,32 @@ def test_lowp_residual_error_is_bounded(P, o, v, Q, seed, full, mode, prec):
     assert max(np.abs(r1 - r1_ref).max(), np.abs(r2 - r2_ref).max()) <= 1e-10
 
 
+@pytest.mark.parametrize("mode", ["full", "packed"])
+def test_lowp_split_k_direct_to_lds_products(P, mode):
+    """o10 v140: the ring pair (ov = 1400: 72 tiles of 256 x 256) is too small for one round, so the
+    FP32 and split-BF16x3 direct-to-LDS kernels cut its K into two slices whose partial tiles
+    (2 x 1400^2 doubles, within the split-K scratch) are summed in slice order; both residuals
+    against the FP64 oracle."""
+    from oracle import cs_ccsd
+
+    from .gpu_util import dev, gpu_residual
+
+    o, v, Q, seed = 10, 140, 200, 12
+    B, eps = make_system(o, v, Q, seed, sigma=0.1)
+    t1, t2 = random_amplitudes(o, v, seed + 100, 0.05, 0.05)
+    r1_ref, r2_ref = cs_ccsd.residual(B, np.diag(eps), t1, t2)
+    scale = max(np.abs(r2_ref).max(), np.abs(r1_ref).max())
+    vm = P.ASCC_VVVV_FULL if mode == "full" else P.ASCC_VVVV_PACKED
+    for prec, pc in (("fp32", P.ASCC_PREC_FP32), ("bf16x3", P.ASCC_PREC_BF16X3)):
+        print(f"case o={o} v={v} Q={Q} vvvv={mode} prec={prec}", flush=True)
+        ints = P.ascc_build_ints(dev(B), dev(eps), o, precision=pc, vvvv_mode=vm)
+        r1, r2, _ = gpu_residual(P, ints, t1, t2)
+        ints.close()
+        err = max(np.abs(r1 - r1_ref).max(), np.abs(r2 - r2_ref).max())
+        print(f"  max|dR| = {err:.3e}  (max|R| = {scale:.3e}, rel {err / scale:.2e})", flush=True)
+        assert err <= REL[prec] * scale
+
+
 def test_precision_switch_requires_low_precision_build(P):
     from .gpu_util import dev
 
