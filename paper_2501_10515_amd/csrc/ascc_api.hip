@@ -346,9 +346,11 @@ std::vector<std::pair<float* ascc_ints::*, long>> lowp_plan(long o, long v, long
 long build_temp_elems(long o, long v, int mode, long* chunk_a) {
   const long vvv = v * v * v;
   long ac = std::max<long>(1, std::min<long>(v, (256L << 20) / std::max<long>(vvv, 1)));  // about 2 GB
+  // a packed set needs the (ac|bd) slabs with b >= a only and computes those with b >= the chunk's
+  // first a: chunks of at most v/16 values of a keep that within about 3 % of the a <= b triangle
+  if (mode == ASCC_VVVV_PACKED) ac = std::min<long>(ac, std::max<long>(1, (v + 15) / 16));
   if (chunk_a) *chunk_a = ac;
   const long wtmp = o * v * v * v;
-  (void)mode;
   return std::max(wtmp, ac * vvv);
 }
 
@@ -1270,9 +1272,13 @@ int build_constants(ascc_ints* I, const double* Bsrc, const double* fock, int fo
       return ASCC_E_HIP;
     }
   }
-  // V[a][b][c][d] = (ac|bd) = sum_Q B_Q,ac B_Q,bd, batched over (a, b); packed: in chunks of a.
-  // Both operands are rows of the [a][c][Q] B_vv: K-contiguous.
+  // V[a][b][c][d] = (ac|bd) = sum_Q B_Q,ac B_Q,bd, batched over (a, b), in chunks of a.  Both
+  // operands are rows of the [a][c][Q] B_vv: K-contiguous.  The packed halves read only the slabs
+  // with b >= a (V[a][b][d][c] = (ad|bc) is the same slab), so a packed build starts b at the
+  // chunk's first a; the full matrix needs every b.
+  const bool full = I->vvvv_mode == ASCC_VVVV_FULL;
   auto vslab = [&](int a0, int na, double* dst) -> hipError_t {
+    const int b0 = full ? 0 : a0;
     Gemm g;
     g.M = v;
     g.N = v;
@@ -1281,21 +1287,20 @@ int build_constants(ascc_ints* I, const double* Bsrc, const double* fock, int fo
     g.sam = Q;
     g.sak = 1;
     g.sa1 = (long)v * Q;
-    g.B = I->Bvv;
+    g.B = I->Bvv + (long)b0 * v * Q;
     g.sbk = 1;
     g.sbn = Q;
     g.sb2 = (long)v * Q;
-    g.C = dst;
+    g.C = dst + (long)b0 * vv;
     g.scm = v;
     g.scn = 1;
     g.sc1 = (long)v * vv;
     g.sc2 = vv;
     g.nb1 = na;
-    g.nb2 = v;
+    g.nb2 = v - b0;
     return mm(I, g, s);
   };
   // in chunks of a through a temporary: scattered to the full matrix in pair order, or packed
-  const bool full = I->vvvv_mode == ASCC_VVVV_FULL;
   if (full) HIPCHK(pair_minus_rows(pair_minus(I), v, s));
   long ac = 1;
   const long elems = build_temp_elems(o, v, I->vvvv_mode, &ac);
