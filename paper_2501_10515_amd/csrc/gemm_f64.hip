@@ -299,13 +299,16 @@ hipError_t launch_cfg(const GP& p0, bool amf, bool bnf, int nb1, int nb1d, doubl
 // Direct-to-LDS path for K-contiguous operands, A(m,k) = A[m*sam + k] and B(k,n) = B[n*sbn + k]:
 // rows go from global memory straight into LDS with global_load_lds_dwordx4 (lane l of an
 // instruction writes LDS bytes 16l .. 16l + 15), S stages in flight, one barrier per stage and no
-// staging registers.  A stage holds 8 K-values of every tile row (64 bytes) with the 16-byte chunk
-// c of row r at slot c ^ ((r >> 1) & 3), which makes the fragment reads conflict-free.  Each
-// fragment read returns two K-values and feeds two MFMAs: lane group g = l / 16 supplies K = 2g to
-// the first and 2g + 1 to the second, identically for A and B.  Rows past M or N and K-values past
-// K are read from a 16-byte zero block instead, so every load instruction runs on all lanes and the
-// per-wave vmcnt bookkeeping is exact.  PM: B is pair-combined as in gemm_f64_kernel, both rows of
-// each pair staged and combined at the fragment read.
+// staging registers.  A stage holds KS K-values of every tile row: KS = 8 (64-byte rows, the 16-byte
+// chunk c of row r at slot c ^ ((r >> 1) & 3)) or KS = 16 (whole 128-byte lines, chunk c of row r
+// at slot c ^ (r & 7)); either swizzle makes the fragment reads conflict-free.  Each fragment read
+// returns two K-values and feeds two MFMAs: lane group g = l / 16 supplies K = 2g to the first and
+// 2g + 1 to the second, identically for A and B; a 16-deep stage is read as two 8-deep halves in
+// order, so the MFMA sequence along K, and with it every result, is the same for both depths.  Rows
+// past M or N and K-values past K are read from a 16-byte zero block instead, so every load
+// instruction runs on all lanes and the per-wave vmcnt bookkeeping is exact.  PM: B is
+// pair-combined as in gemm_f64_kernel, both rows of each pair staged and combined at the fragment
+// read (8-deep stages: two B rows per pair leave no room for three 16-deep ones).
 typedef __attribute__((address_space(3))) void lds_void_t;
 typedef __attribute__((address_space(1))) const void gbl_void_t;
 __device__ __attribute__((aligned(16))) double kZero16[2];
@@ -317,18 +320,21 @@ __device__ __forceinline__ void wait_vmcnt() {
   __builtin_amdgcn_s_waitcnt(0xF70 | (N & 15) | ((N >> 4) << 14));
 }
 
-template <int BM, int BN, int WM, int WN, int S, bool PM>
+template <int BM, int BN, int WM, int WN, int S, bool PM, int KS>
 __global__ __launch_bounds__(WM* WN * 64, 1) void gemm_f64_dma_kernel(GP p) {
   typedef double dd2 __attribute__((ext_vector_type(2)));
   typedef double d4 __attribute__((ext_vector_type(4)));
   constexpr int NW = WM * WN;
   constexpr int TM = BM / WM, TN = BN / WN, RI = TM / 16, RJ = TN / 16;
   constexpr int NB = PM ? 2 : 1;
-  constexpr int IA = BM / 16, IB = BN / 16, NI = IA + NB * IB;  // 1 KB load instructions per stage
-  constexpr int NPW = (NI + NW - 1) / NW, NPWMIN = NI / NW;      // per wave
+  constexpr int CPR = KS / 2, RPI = 64 / CPR;  // 16-byte chunks per staged row, rows per load instruction
+  constexpr int IA = BM / RPI, IB = BN / RPI, NI = IA + NB * IB;  // 1 KB load instructions per stage
+  constexpr int NPW = (NI + NW - 1) / NW, NPWMIN = NI / NW;        // per wave
   constexpr int ROWS = BM + NB * BN;
   static_assert(TM % 16 == 0 && TN % 16 == 0 && S >= 3 && NPWMIN >= 1, "tile config");
-  __shared__ __attribute__((aligned(1024))) double T[S][ROWS * 8];
+  static_assert(KS == 8 || (KS == 16 && !PM), "stage depth");
+  __shared__ __attribute__((aligned(1024))) double T[S][ROWS * KS];
+  auto swz = [](int r) { return KS == 8 ? (r >> 1) & 3 : r & 7; };  // slot of chunk 0 of row r
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -358,8 +364,8 @@ __global__ __launch_bounds__(WM* WN * 64, 1) void gemm_f64_dma_kernel(GP p) {
 #pragma unroll
   for (int j = 0; j < NPW; ++j) {
     const int g = wave + NW * j;
-    const int r = 16 * g + (lane >> 2);
-    const int c = (lane & 3) ^ ((r >> 1) & 3);
+    const int r = RPI * g + lane / CPR;
+    const int c = (lane % CPR) ^ swz(r);
     const double* row = nullptr;
     if (g < IA) {
       const int gm = m0 + r;
@@ -377,13 +383,13 @@ __global__ __launch_bounds__(WM* WN * 64, 1) void gemm_f64_dma_kernel(GP p) {
   }
   // stages [kt0, kt0 + nkt) of this slice
   const int kt0 = slice * p.it_per_split;
-  const int nkt = min((p.K + 7) / 8, kt0 + p.it_per_split) - kt0;
+  const int nkt = min((p.K + KS - 1) / KS, kt0 + p.it_per_split) - kt0;
   auto issue = [&](int kt, int st) {
 #pragma unroll
     for (int j = 0; j < NPW; ++j) {
       const int g = wave + NW * j;
       if (NPW * NW == NI || g < NI) {
-        const double* a = (ok[j] && kt * 8 + ck[j] < p.K) ? src[j] + kt * 8 : kZero16;
+        const double* a = (ok[j] && kt * KS + ck[j] < p.K) ? src[j] + kt * KS : kZero16;
         __builtin_amdgcn_global_load_lds((gbl_void_t*)a, (lds_void_t*)&T[st][g * 128], 16, 0, 0);
       }
     }
@@ -412,31 +418,34 @@ __global__ __launch_bounds__(WM* WN * 64, 1) void gemm_f64_dma_kernel(GP p) {
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
     const double* Ts = T[st];
-    dd2 fa[RI], fb[RJ];
 #pragma unroll
-    for (int i = 0; i < RI; ++i) {
-      const int r = wm * TM + 16 * i + l16;
-      fa[i] = *reinterpret_cast<const dd2*>(Ts + r * 8 + 2 * (q ^ ((r >> 1) & 3)));
-    }
+    for (int kk = 0; kk < KS / 8; ++kk) {  // 8-deep halves of the stage, in K order
+      dd2 fa[RI], fb[RJ];
 #pragma unroll
-    for (int j = 0; j < RJ; ++j) {
-      const int r = BM + wn * TN + 16 * j + l16;
-      fb[j] = *reinterpret_cast<const dd2*>(Ts + r * 8 + 2 * (q ^ ((r >> 1) & 3)));
-      if constexpr (PM) {
-        const int rw = r + BN;  // (r + BN) has the same swizzle as r: BN is a multiple of 16
-        const dd2 w = *reinterpret_cast<const dd2*>(Ts + rw * 8 + 2 * (q ^ ((rw >> 1) & 3)));
-        fb[j] = minus ? fb[j] - w : fb[j] + w;
+      for (int i = 0; i < RI; ++i) {
+        const int r = wm * TM + 16 * i + l16;
+        fa[i] = *reinterpret_cast<const dd2*>(Ts + r * KS + 2 * ((q + 4 * kk) ^ swz(r)));
       }
+#pragma unroll
+      for (int j = 0; j < RJ; ++j) {
+        const int r = BM + wn * TN + 16 * j + l16;
+        fb[j] = *reinterpret_cast<const dd2*>(Ts + r * KS + 2 * ((q + 4 * kk) ^ swz(r)));
+        if constexpr (PM) {
+          const int rw = r + BN;  // (r + BN) has the same swizzle as r: BN is a multiple of 16
+          const dd2 w = *reinterpret_cast<const dd2*>(Ts + rw * KS + 2 * ((q + 4 * kk) ^ swz(rw)));
+          fb[j] = minus ? fb[j] - w : fb[j] + w;
+        }
+      }
+      // the stage refilled now was last read in the previous iteration, before this barrier
+      if (kk == 0 && kt + S - 1 < nkt) issue(kt0 + kt + S - 1, (kt + S - 1) % S);
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int i = 0; i < RI; ++i)
+#pragma unroll
+          for (int j = 0; j < RJ; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i][h], fb[j][h], acc[i][j], 0, 0, 0);
     }
-    // the stage refilled now was last read in the previous iteration, before this barrier
-    if (kt + S - 1 < nkt) issue(kt0 + kt + S - 1, (kt + S - 1) % S);
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-      for (int i = 0; i < RI; ++i)
-#pragma unroll
-        for (int j = 0; j < RJ; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i][h], fb[j][h], acc[i][j], 0, 0, 0);
   }
 #pragma unroll
   for (int i = 0; i < RI; ++i)
@@ -468,22 +477,26 @@ bool dma_eligible(const GP& p) {
 
 // split > 1 (never with pm): K cut into `split` slices whose partial tiles go to ws, then summed
 // in a fixed order by splitk_reduce.
-template <int BM, int BN, int WM, int WN, int S>
+template <int BM, int BN, int WM, int WN, int S, int KS = 8>
 hipError_t launch_dma(GP p, int nb1, bool pm, int split, double* ws, hipStream_t s) {
+  static_assert(KS == 8 || KS == 16, "stage depth");
   p.tiles_m = (p.M + BM - 1) / BM;
   p.tiles_n = (p.N + BN - 1) / BN;
-  const int nkt = (p.K + 7) / 8;
+  const int nkt = (p.K + KS - 1) / KS;
   p.it_per_split = (nkt + split - 1) / split;
   p.split = (nkt + p.it_per_split - 1) / p.it_per_split;
   p.part = p.split > 1 ? ws : nullptr;
   const int tiles = p.tiles_m * p.tiles_n;
-  if (pm) {  // both halves in grid.x, padded to whole groups of 8
-    dim3 grid(2 * ((tiles + 7) / 8 * 8), 1, nb1);
-    hipLaunchKernelGGL((gemm_f64_dma_kernel<BM, BN, WM, WN, S, true>), grid, dim3(WM * WN * 64), 0, s, p);
-  } else {
-    dim3 grid(tiles * p.split, p.nb2, nb1);
-    hipLaunchKernelGGL((gemm_f64_dma_kernel<BM, BN, WM, WN, S, false>), grid, dim3(WM * WN * 64), 0, s, p);
+  if constexpr (KS == 8) {
+    if (pm) {  // both halves in grid.x, padded to whole groups of 8
+      dim3 grid(2 * ((tiles + 7) / 8 * 8), 1, nb1);
+      hipLaunchKernelGGL((gemm_f64_dma_kernel<BM, BN, WM, WN, S, true, 8>), grid, dim3(WM * WN * 64), 0, s, p);
+      return hipGetLastError();
+    }
   }
+  if (pm) return hipErrorInvalidValue;  // pair-combined launches use 8-deep stages
+  dim3 grid(tiles * p.split, p.nb2, nb1);
+  hipLaunchKernelGGL((gemm_f64_dma_kernel<BM, BN, WM, WN, S, false, KS>), grid, dim3(WM * WN * 64), 0, s, p);
   if (p.split > 1) {
     const long outs = (long)p.M * p.N * p.nb2 * nb1;
     hipLaunchKernelGGL(splitk_reduce, dim3(splitk_blocks(outs)), dim3(256), 0, s, p, nb1, outs);
@@ -514,9 +527,9 @@ hipError_t launch_dma_auto(const GP& p, int nb1, int nb1d, double* ws, long ws_e
       best_split = sp;
     }
   }
-  if (best == 0) return launch_dma<192, 192, 2, 4, 4>(p, nb1, false, best_split, ws, s);
-  if (best == 1) return launch_dma<256, 128, 4, 2, 4>(p, nb1, false, best_split, ws, s);
-  return launch_dma<224, 128, 2, 4, 4>(p, nb1, false, best_split, ws, s);
+  if (best == 0) return launch_dma<192, 192, 2, 4, 3, 16>(p, nb1, false, best_split, ws, s);
+  if (best == 1) return launch_dma<256, 128, 4, 2, 3, 16>(p, nb1, false, best_split, ws, s);
+  return launch_dma<224, 128, 2, 4, 3, 16>(p, nb1, false, best_split, ws, s);
 }
 
 // Ladder: BM x 128 tiles of 8 waves, both halves (grid.y = 2), no split-K, A/B staged k-fast.
@@ -715,11 +728,20 @@ hipError_t gemm_f64_ladder(int M, int Tv, const double* A, const double* V, long
   const long pad208 = (M + 207L) / 208 * 208;
   if (lb.n > 65535) return hipErrorInvalidValue;
   if (dma_eligible(p)) {
-    if (pad256 <= pad224 && pad256 <= pad208 && pad256 <= pad128)
-      return launch_dma<256, 128, 4, 2, 4>(p, lb.n, pmode, 1, nullptr, s);
-    if (pad224 <= pad208 && pad224 <= pad128) return launch_dma<224, 128, 2, 4, 4>(p, lb.n, pmode, 1, nullptr, s);
-    if (pad208 <= pad128) return launch_dma<208, 128, 1, 8, 4>(p, lb.n, pmode, 1, nullptr, s);
-    return launch_dma<128, 128, 2, 4, 4>(p, lb.n, pmode, 1, nullptr, s);
+    const int t = (pad256 <= pad224 && pad256 <= pad208 && pad256 <= pad128) ? 0
+                  : (pad224 <= pad208 && pad224 <= pad128)                     ? 1
+                  : (pad208 <= pad128)                                         ? 2
+                                                                               : 3;
+    if (pmode) {  // two B rows per pair: four 8-deep stages
+      if (t == 0) return launch_dma<256, 128, 4, 2, 4>(p, lb.n, true, 1, nullptr, s);
+      if (t == 1) return launch_dma<224, 128, 2, 4, 4>(p, lb.n, true, 1, nullptr, s);
+      if (t == 2) return launch_dma<208, 128, 1, 8, 4>(p, lb.n, true, 1, nullptr, s);
+      return launch_dma<128, 128, 2, 4, 4>(p, lb.n, true, 1, nullptr, s);
+    }
+    if (t == 0) return launch_dma<256, 128, 4, 2, 3, 16>(p, lb.n, false, 1, nullptr, s);
+    if (t == 1) return launch_dma<224, 128, 2, 4, 3, 16>(p, lb.n, false, 1, nullptr, s);
+    if (t == 2) return launch_dma<208, 128, 1, 8, 3, 16>(p, lb.n, false, 1, nullptr, s);
+    return launch_dma<128, 128, 2, 4, 3, 16>(p, lb.n, false, 1, nullptr, s);
   }
   if (pad256 <= pad224 && pad256 <= pad128) return launch_ladder<256, 4>(p, lb.n, pmode, s);
   if (pad224 <= pad128) return launch_ladder<224, 2>(p, lb.n, pmode, s);
