@@ -308,7 +308,9 @@ hipError_t launch_cfg(const GP& p0, bool amf, bool bnf, int nb1, int nb1d, doubl
 // past M or N and K-values past K are read from a 16-byte zero block instead, so every load
 // instruction runs on all lanes and the per-wave vmcnt bookkeeping is exact.  PM: B is
 // pair-combined as in gemm_f64_kernel, both rows of each pair staged and combined at the fragment
-// read (8-deep stages: two B rows per pair leave no room for three 16-deep ones).
+// read (two B rows per pair leave room for two 16-deep stages only: the next stage loads while the
+// current one is computed; every wave has read the refilled slot before the barrier that precedes
+// the refill, as with more stages).
 typedef __attribute__((address_space(3))) void lds_void_t;
 typedef __attribute__((address_space(1))) const void gbl_void_t;
 __device__ __attribute__((aligned(16))) double kZero16[2];
@@ -331,8 +333,8 @@ __global__ __launch_bounds__(WM* WN * 64, 1) void gemm_f64_dma_kernel(GP p) {
   constexpr int IA = BM / RPI, IB = BN / RPI, NI = IA + NB * IB;  // 1 KB load instructions per stage
   constexpr int NPW = (NI + NW - 1) / NW, NPWMIN = NI / NW;        // per wave
   constexpr int ROWS = BM + NB * BN;
-  static_assert(TM % 16 == 0 && TN % 16 == 0 && S >= 3 && NPWMIN >= 1, "tile config");
-  static_assert(KS == 8 || (KS == 16 && !PM), "stage depth");
+  static_assert(TM % 16 == 0 && TN % 16 == 0 && S >= 2 && NPWMIN >= 1, "tile config");
+  static_assert(KS == 8 || KS == 16, "stage depth");
   __shared__ __attribute__((aligned(1024))) double T[S][ROWS * KS];
   auto swz = [](int r) { return KS == 8 ? (r >> 1) & 3 : r & 7; };  // slot of chunk 0 of row r
 
@@ -487,14 +489,15 @@ hipError_t launch_dma(GP p, int nb1, bool pm, int split, double* ws, hipStream_t
   p.split = (nkt + p.it_per_split - 1) / p.it_per_split;
   p.part = p.split > 1 ? ws : nullptr;
   const int tiles = p.tiles_m * p.tiles_n;
-  if constexpr (KS == 8) {
-    if (pm) {  // both halves in grid.x, padded to whole groups of 8
+  if (pm) {  // both halves in grid.x, padded to whole groups of 8
+    if constexpr ((long)S * (BM + 2 * BN) * KS * 8 <= 160 * 1024) {
       dim3 grid(2 * ((tiles + 7) / 8 * 8), 1, nb1);
-      hipLaunchKernelGGL((gemm_f64_dma_kernel<BM, BN, WM, WN, S, true, 8>), grid, dim3(WM * WN * 64), 0, s, p);
+      hipLaunchKernelGGL((gemm_f64_dma_kernel<BM, BN, WM, WN, S, true, KS>), grid, dim3(WM * WN * 64), 0, s, p);
       return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;  // two B rows per pair do not fit this many stages
     }
   }
-  if (pm) return hipErrorInvalidValue;  // pair-combined launches use 8-deep stages
   dim3 grid(tiles * p.split, p.nb2, nb1);
   hipLaunchKernelGGL((gemm_f64_dma_kernel<BM, BN, WM, WN, S, false, KS>), grid, dim3(WM * WN * 64), 0, s, p);
   if (p.split > 1) {
@@ -732,11 +735,11 @@ hipError_t gemm_f64_ladder(int M, int Tv, const double* A, const double* V, long
                   : (pad224 <= pad208 && pad224 <= pad128)                     ? 1
                   : (pad208 <= pad128)                                         ? 2
                                                                                : 3;
-    if (pmode) {  // two B rows per pair: four 8-deep stages
-      if (t == 0) return launch_dma<256, 128, 4, 2, 4>(p, lb.n, true, 1, nullptr, s);
-      if (t == 1) return launch_dma<224, 128, 2, 4, 4>(p, lb.n, true, 1, nullptr, s);
-      if (t == 2) return launch_dma<208, 128, 1, 8, 4>(p, lb.n, true, 1, nullptr, s);
-      return launch_dma<128, 128, 2, 4, 4>(p, lb.n, true, 1, nullptr, s);
+    if (pmode) {  // two B rows per pair: two 16-deep stages
+      if (t == 0) return launch_dma<256, 128, 4, 2, 2, 16>(p, lb.n, true, 1, nullptr, s);
+      if (t == 1) return launch_dma<224, 128, 2, 4, 2, 16>(p, lb.n, true, 1, nullptr, s);
+      if (t == 2) return launch_dma<208, 128, 1, 8, 2, 16>(p, lb.n, true, 1, nullptr, s);
+      return launch_dma<128, 128, 2, 4, 2, 16>(p, lb.n, true, 1, nullptr, s);
     }
     if (t == 0) return launch_dma<256, 128, 4, 2, 3, 16>(p, lb.n, false, 1, nullptr, s);
     if (t == 1) return launch_dma<224, 128, 2, 4, 3, 16>(p, lb.n, false, 1, nullptr, s);
