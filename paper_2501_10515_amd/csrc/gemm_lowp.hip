@@ -613,7 +613,7 @@ __global__ __launch_bounds__(NT3, 1) void gemm_bf16x3_dma_kernel(LPB p) {
 
 // FP32, direct to LDS: 256 x 256 tiles, eight waves of 128 x 64 (two per SIMD), v_mfma_f32_16x16x4_f32.
 // A stage holds 16 K-values of every tile row (64 bytes; the 16-byte chunk c of row r at slot
-// c ^ ((r >> 1) & 3), the layout of the FP64 direct-to-LDS kernel), four stages (three in flight),
+// c ^ ((r >> 1) & 3), the 64-byte-row layout of the FP64 direct-to-LDS kernel), four stages (three in flight),
 // one barrier per stage after a per-wave vmcnt wait.  Each wave loads 64 rows of one operand per
 // stage (four 1 KB buffer_load ... lds; rows past M or N read as zero through the buffer range
 // check, the K padding of the shadows is zero).  Each fragment read returns four K-values of a row
