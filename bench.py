@@ -786,6 +786,13 @@ def headline(args):
                     variants[name]["mfma_util"] = c[f"{name}_step"]["mfma_util"]
         except Exception as exc:  # keep the measurement if the profiler is unavailable
             out["counters"] = {"error": str(exc)[:300]}
+        if "serving" in out:
+            try:
+                out["serving"]["mfma_counters"] = run_serving_counters(SERVE_COUNTER_REQUESTS)
+                for name, m in out["serving"]["mfma_counters"]["modes"].items():
+                    log(f"serving {name}: MFMA busy {m['mfma_util']:.3f} over its kernels")
+            except Exception as exc:
+                out["serving"]["mfma_counters"] = {"error": str(exc)[:300]}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(o, v, Q, seed, nstates)
     print(json.dumps(out), flush=True)
@@ -799,6 +806,45 @@ COUNTER_PASSES = (
     ("write", ["WRITE_SIZE"]),
 )
 CALIB_BYTES = 1 << 30
+SERVE_COUNTERS = ["SQ_VALU_MFMA_BUSY_CYCLES", "GRBM_GUI_ACTIVE", "SQ_INSTS_VALU_MFMA_MOPS_F64",
+                  "SQ_INSTS_VALU_MFMA_MOPS_BF16"]
+SERVE_COUNTER_REQUESTS = 64
+
+
+def run_serving_counters(nreq: int):
+    """MFMA utilisation of the serving kernels: one rocprofv3 counter pass per mode over the first
+    nreq requests of the serving stream.  The pass serialises the kernels, so the figure is that of
+    the kernels themselves (busy cycles over their active cycles), not of the wall time."""
+    import shutil
+
+    exe = shutil.which("rocprofv3")
+    if exe is None:
+        raise RuntimeError("rocprofv3 not found")
+    modes = {}
+    for name, prec in (("bf16x3_refined", "bf16x3"), ("fp64", "fp64")):
+        outdir = tempfile.mkdtemp(prefix=f"ascc_spmc_{prec}_")
+        cmd = [exe, "--pmc", *SERVE_COUNTERS, "--output-format", "csv", "-d", outdir, "-o", "run", "--",
+               sys.executable, os.path.abspath(__file__), "--serve", "--serve-precisions", prec,
+               "--requests", str(nreq)]
+        r = subprocess.run(["timeout", "-s", "KILL", "300", *cmd], capture_output=True, text=True,
+                           cwd=tempfile.gettempdir(), env=dict(os.environ, TMPDIR=tempfile.gettempdir()))
+        if r.returncode != 0:
+            raise RuntimeError(f"serving counter pass {prec} failed (rc {r.returncode}): "
+                               f"{(r.stderr or r.stdout)[-300:]}")
+        rows = _read_counters(outdir)
+        shutil.rmtree(outdir, ignore_errors=True)
+        tot = {}
+        for row in rows:
+            for k, val in row["c"].items():
+                tot[k] = tot.get(k, 0.0) + val
+        act = tot.get("GRBM_GUI_ACTIVE", 0.0) / 8.0  # summed over the 8 XCDs
+        modes[name] = {"mfma_util": tot.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) / (1024 * act) if act else None,
+                       "mfma_flops_executed": {k.rsplit("_", 1)[-1]: v * 512 for k, v in tot.items() if "MOPS" in k},
+                       "dispatches": len(rows)}
+    return {"requests": nreq, "modes": modes,
+            "method": "rocprofv3 --pmc " + " ".join(SERVE_COUNTERS) + f" over bench.py --serve --requests {nreq} "
+                      "per mode, summed over its dispatches; MFMA utilisation = SQ_VALU_MFMA_BUSY_CYCLES / "
+                      "(1024 SIMDs x GRBM_GUI_ACTIVE / 8 XCDs), of the kernels (the pass serialises them)"}
 
 
 def counter_child(args):
