@@ -500,8 +500,9 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t uniform_rsrc(const void* base,
 // 16l .. 16l + 15, so lanes pick the global chunk that belongs at their swizzled slot); rows past M
 // or N and K-blocks past the padded row read as zero through the buffer range check.  Per K-step:
 // wait for this wave's part of the stage, barrier, issue the next stage into the other buffer, then
-// two K = 16 halves of fragment reads and 24 MFMAs, and a second barrier before the buffer is
-// refilled.  Measured at o40 v360 (ring products 14400^3, ladder 820 x 64980 x 64980, W/Z 1600 x
+// two K = 16 halves of fragment reads and 24 MFMAs.  The buffer refilled after a step's barrier was
+// read in the step before, whose fragments every wave consumed before reaching that barrier, so one
+// barrier per step suffices.  Measured at o40 v360 (ring products 14400^3, ladder 820 x 64980 x 64980, W/Z 1600 x
 // 16000 x 129600): 0.49 / 0.41 / 0.40 of the split-BF16x3 peak, against 0.37 / 0.31 / 0.29 with four
 // waves of 128 x 128 (one per SIMD); with eight waves the kernel is bound by the rate at which the
 // operand stages reach LDS (a copy of it without MFMAs takes as long), not by the matrix cores.
@@ -577,7 +578,9 @@ __global__ __launch_bounds__(NT3, 1) void gemm_bf16x3_dma_kernel(LPB p) {
     for (int kt = kc; kt < kend; ++kt) {
       const int cur = (kt - kt0) & 1;
       __builtin_amdgcn_s_waitcnt(0xF70);  // vmcnt(0): this wave's part of stage kt has landed
-      __builtin_amdgcn_s_barrier();       // every wave's has
+      asm volatile("" ::: "memory");
+      __builtin_amdgcn_s_barrier();  // every wave's has, and every wave has read stage cur ^ 1
+      asm volatile("" ::: "memory");  // (its fragments fed the MFMAs of the previous step)
       if (kt + 1 < nkt) issue(kt + 1, cur ^ 1);
 #pragma unroll
       for (int sub = 0; sub < 2; ++sub) {
@@ -603,7 +606,6 @@ __global__ __launch_bounds__(NT3, 1) void gemm_bf16x3_dma_kernel(LPB p) {
             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa[i][0], xb[j][0], acc[i][j], 0, 0, 0);
           }
       }
-      __builtin_amdgcn_s_barrier();  // every wave has read stage cur before it is refilled
     }
     flush(kc == kt0);
   }
