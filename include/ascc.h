@@ -39,6 +39,11 @@
  *     state and free it before returning.  No other call allocates device memory.
  *   - A handle is not re-entrant: calls that share an ascc_ints (its work arrays) or an
  *     ascc_diis must be ordered on one stream.
+ *   - Check mode: with ASCC_CHECK_BOUNDS=1 in the environment (read once per process) every
+ *     call verifies, before it launches, that each device range it touches lies inside a
+ *     buffer it was given or owns (failing with ASCC_E_HIP and a message instead), and the
+ *     integral builds verify that the largest occupied orbital energy lies below the smallest
+ *     virtual one (ASCC_E_ARG otherwise: the Jacobi denominators must stay negative).
  */
 #ifndef ASCC_H
 #define ASCC_H

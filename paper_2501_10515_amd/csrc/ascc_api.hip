@@ -1715,6 +1715,28 @@ int ascc_build_ints_ws(const double* d_B, const double* d_fock, int fock_is_diag
                          ws_bytes, stream, out);
 }
 
+// Check mode only: the Jacobi denominators e_i - e_a (Sec. III.B) must all be negative, so the
+// largest occupied orbital energy (the Fock diagonal) must lie below the smallest virtual one.
+static int check_orbital_energies(const double* d_fock, int fock_is_diag, long o, long n, hipStream_t s) {
+  if (!bounds_checking() || dry_run()) return ASCC_OK;
+  std::vector<double> f(fock_is_diag ? n : n * n);
+  if (d_copy(f.data(), d_fock, sizeof(double) * f.size(), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      d_sync(s) != hipSuccess)
+    return fail(ASCC_E_HIP, "reading the Fock diagonal failed");
+  double omax = -HUGE_VAL, vmin = HUGE_VAL;
+  for (long p = 0; p < n; ++p) {
+    const double e = fock_is_diag ? f[p] : f[p * n + p];
+    if (p < o)
+      omax = std::max(omax, e);
+    else
+      vmin = std::min(vmin, e);
+  }
+  if (!(omax < vmin))
+    return fail(ASCC_E_ARG, "orbital energies: the largest occupied one (" + std::to_string(omax) +
+                                ") is not below the smallest virtual one (" + std::to_string(vmin) + ")");
+  return ASCC_OK;
+}
+
 static int build_ints_impl(const double* d_B, const double* d_fock, int fock_is_diag, int no, int nv, int naux,
                            int precision, int vvvv_mode, int hole, int particle, int s_sign, void* ws,
                            size_t ws_bytes, void* stream, ascc_ints** out) {
@@ -1762,6 +1784,7 @@ static int build_ints_impl(const double* d_B, const double* d_fock, int fock_is_
   ScopedBuffers user;
   user.add(d_B, sizeof(double) * Q * nn);
   user.add(d_fock, sizeof(double) * (fock_is_diag ? n : nn));
+  if (!rc) rc = check_orbital_energies(d_fock, fock_is_diag, o, n, s);
   if (!rc) rc = build_constants(I, d_B, d_fock, fock_is_diag, hole, particle, s_sign, s);
   if (!rc && precision != ASCC_PREC_FP64) rc = build_lowp_shadows(I, s);
   if (!rc && !ws) {  // a workspace build stays asynchronous on `stream`

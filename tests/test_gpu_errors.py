@@ -108,3 +108,54 @@ def test_request_larger_than_the_budget_is_refused_at_submit(P):
     infos = [srv.info(i) for i in ids]
     srv.close()
     assert all(x["status"] == 0 for x in infos)
+
+
+CHECK_MODE_CHILD = r"""
+import sys
+import numpy as np
+import torch
+sys.path.insert(0, sys.argv[1])
+import paper_2501_10515_amd as P
+from gen.synth_df import make_system
+P.load_library()
+o, v, Q = 3, 7, 15
+B, eps = make_system(o, v, Q, 5)
+dB = torch.from_numpy(B).cuda()
+P.ascc_build_ints(dB, torch.from_numpy(eps).cuda(), o).close()
+print("ordered ok", flush=True)
+fock = np.diag(eps) + 0.01 * np.ones((o + v, o + v))
+P.ascc_build_ints(dB, torch.from_numpy(fock).cuda(), o).close()
+print("full ordered ok", flush=True)
+for name, f in (("diag", eps.copy()), ("full", np.diag(eps))):
+    k = o - 1
+    val = eps[o] + 0.1  # the last occupied energy above the first virtual one
+    if f.ndim == 1:
+        f[k] = val
+    else:
+        f[k, k] = val
+    try:
+        P.ascc_build_ints(dB, torch.from_numpy(f).cuda(), o).close()
+        print(name, "no error", flush=True)
+    except P.AsccError as exc:
+        print(name, "code", exc.code, flush=True)
+"""
+
+
+def test_check_mode_refuses_crossed_orbital_energies(P, tmp_path):
+    """With ASCC_CHECK_BOUNDS=1 (read once per process, so in a child) an integral build whose
+    largest occupied orbital energy is not below the smallest virtual one fails with ASCC_E_ARG,
+    for a diagonal and for a full Fock matrix; ordered energies build as before."""
+    import os
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    script = tmp_path / "check_mode_child.py"
+    script.write_text(CHECK_MODE_CHILD)
+    print("case: check-mode child, o3 v7 Q15", flush=True)
+    r = subprocess.run([sys.executable, str(script), root], capture_output=True, text=True, timeout=240,
+                       env=dict(os.environ, ASCC_CHECK_BOUNDS="1"), cwd=root)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = r.stdout.split("\n")
+    assert "ordered ok" in lines and "full ordered ok" in lines, r.stdout
+    assert f"diag code {P.ASCC_E_ARG}" in lines and f"full code {P.ASCC_E_ARG}" in lines, r.stdout
