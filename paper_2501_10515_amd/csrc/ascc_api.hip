@@ -899,7 +899,11 @@ int residual_core(ascc_ints* I, const double* t1, const double* t2, double* r1, 
   phase_begin(I, PH_DF, s);
   // g^_aibj enters R2 unmultiplied by amplitudes: always FP64, so the low-precision residual's
   // rounding floor stays proportional to the amplitudes
-  HIPCHK(mm(I, gemm_rm(ov, ov, Q, 1.0, I->BvoTt, Q, false, I->BvoTt, Q, true, 0.0, I->G1, ov), s));    // g^_aibj
+  {  // g^_aibj: a symmetric product, its lower triangle computed and mirrored
+    Gemm g = gemm_rm(ov, ov, Q, 1.0, I->BvoTt, Q, false, I->BvoTt, Q, true, 0.0, I->G1, ov);
+    g.lower = true;
+    HIPCHK(mm(I, g, s));
+  }
   if (lowp) {  // the same products on K-contiguous low-precision shadows (B^_kc ones are constant)
     HIPCHK(shadow(I, I->BvoTtf, I->BvoTt, ov, Q, s));
     HIPCHK(shadow_t(I, I->BooTf, I->Boo, oo, oo, Q, s));

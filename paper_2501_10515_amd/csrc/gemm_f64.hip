@@ -43,6 +43,7 @@ struct GP {
   double* part;             // partial tiles [split][nb1*nb2][M][N] when split > 1
   const int* pm;            // pair-combined B (ladder): second row of pair n
   const int* tab1;          // batch level 1: operand block of grid index z1 (nullptr: z1 itself)
+  int lower;                // symmetric C: tiles on and below the diagonal only (tiles_m == tiles_n)
 };
 
 // Workgroup-to-tile map.  Workgroups are dispatched to the 8 XCDs round-robin; each XCD gets
@@ -61,6 +62,46 @@ __device__ __forceinline__ void tile_of(int bid, int tiles_m, int tiles_n, int& 
   const int r = t - g * per;
   tm = first + r % gs;
   tn = r / gs;
+}
+
+// The lower-triangle tiles (tn <= tm) of a symmetric product, each XCD a contiguous range of them
+// in row order (consecutive tiles share their A rows).
+__device__ __forceinline__ void tile_of_lower(int bid, int tiles, int& tm, int& tn) {
+  const int total = tiles * (tiles + 1) / 2;
+  const int q = total >> 3, rem = total & 7;
+  const int x = bid & 7, local = bid >> 3;
+  const int t = x * q + min(x, rem) + local;
+  int m = (int)((sqrtf(8.f * (float)t + 1.f) - 1.f) * 0.5f);
+  while ((m + 1) * (m + 2) / 2 <= t) ++m;
+  while (m * (m + 1) / 2 > t) --m;
+  tm = m;
+  tn = t - m * (m + 1) / 2;
+}
+
+// C_z(r, c) = C_z(c, r) for c > r: the strict upper triangle of a symmetric product copied from
+// its lower one through a 32 x 32 LDS tile (coalesced reads and writes).  grid.x enumerates the
+// 32 x 32 blocks on and above the diagonal, grid.y / grid.z the batch levels.
+__global__ __launch_bounds__(256) void mirror_upper_kernel(GP p) {
+  __shared__ double tile[32][33];
+  const int nb = (p.M + 31) / 32;
+  int by = (int)((sqrtf(8.f * (float)blockIdx.x + 1.f) - 1.f) * 0.5f);  // column block index
+  while ((by + 1) * (by + 2) / 2 <= (int)blockIdx.x) ++by;
+  while (by * (by + 1) / 2 > (int)blockIdx.x) --by;
+  const int bx = (int)blockIdx.x - by * (by + 1) / 2;  // row block, bx <= by
+  if (by >= nb) return;
+  const int zs = p.tab1 ? p.tab1[blockIdx.z] : (int)blockIdx.z;
+  double* C = p.C + zs * p.sc1 + (long)blockIdx.y * p.sc2;
+  const int r0 = bx * 32, c0 = by * 32;  // destination rows r0.., columns c0.. (upper side)
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int i = ty; i < 32; i += 8) {  // source C(c, r): rows c0 + i, columns r0 + tx
+    const int c = c0 + i, r = r0 + tx;
+    if (c < p.M && r < p.M) tile[i][tx] = C[(long)c * p.scm + (long)r * p.scn];
+  }
+  __syncthreads();
+  for (int i = ty; i < 32; i += 8) {
+    const int r = r0 + i, c = c0 + tx;
+    if (r < p.M && c < p.M && c > r) C[(long)r * p.scm + (long)c * p.scn] = tile[tx][i];
+  }
 }
 
 // PM: B is pair-combined (ladder against the full (ac|bd) in pair order): for batch z2 = 0 (+)
@@ -351,7 +392,10 @@ __global__ __launch_bounds__(WM* WN * 64, 1) void gemm_f64_dma_kernel(GP p) {
   }
   const int slice = PM ? 0 : bid / ntiles;  // split-K slice (never for PM)
   int tm, tn;
-  tile_of(bid - slice * ntiles, p.tiles_m, p.tiles_n, tm, tn);
+  if (!PM && p.lower)
+    tile_of_lower(bid, p.tiles_m, tm, tn);
+  else
+    tile_of(bid - slice * ntiles, p.tiles_m, p.tiles_n, tm, tn);
   const int m0 = tm * BM, n0 = tn * BN;
   const int z1 = blockIdx.z;
   const int zs = p.tab1 ? p.tab1[z1] : z1;  // operand block of batch level 1
@@ -488,7 +532,8 @@ hipError_t launch_dma(GP p, int nb1, bool pm, int split, double* ws, hipStream_t
   p.it_per_split = (nkt + split - 1) / split;
   p.split = (nkt + p.it_per_split - 1) / p.it_per_split;
   p.part = p.split > 1 ? ws : nullptr;
-  const int tiles = p.tiles_m * p.tiles_n;
+  const int tiles = p.lower ? p.tiles_m * (p.tiles_m + 1) / 2 : p.tiles_m * p.tiles_n;
+  if (p.lower && (p.split > 1 || pm || BM != BN || p.tiles_m != p.tiles_n)) return hipErrorInvalidValue;
   if (pm) {  // both halves in grid.x, padded to whole groups of 8
     if constexpr ((long)S * (BM + 2 * BN) * KS * 8 <= 160 * 1024) {
       dim3 grid(2 * ((tiles + 7) / 8 * 8), 1, nb1);
@@ -645,6 +690,19 @@ hipError_t gemm_f64(const Gemm& g, hipStream_t s) {
   p.nred = g.nred;
   p.pm = nullptr;
   p.tab1 = g.tab1;
+  p.lower = 0;
+  if (g.lower && g.M == g.N && g.beta == 0.0 && dma_eligible(p)) {
+    // symmetric C: the 192 x 192 tiles on and below the diagonal, then the mirror of the strict
+    // upper triangle (each mirrored value sums the same products in the same K order); other
+    // symmetric products (odd K, unaligned rows) take the full product below
+    p.lower = 1;
+    hipError_t e = launch_dma<192, 192, 2, 4, 3, 16>(p, g.nb1, false, 1, nullptr, s);
+    if (e != hipSuccess) return e;
+    const long nbk = (g.M + 31) / 32;
+    hipLaunchKernelGGL(mirror_upper_kernel, dim3((unsigned)(nbk * (nbk + 1) / 2), (unsigned)g.nb2, (unsigned)g.nb1),
+                       dim3(256), 0, s, p);
+    return hipGetLastError();
+  }
   // Global-load order: an operand whose m (n) stride is 1 is read m-fast (n-fast).
   const bool amf = (g.sam == 1 && g.sak != 1);
   const bool bnf = (g.sbn == 1) || (g.sbk != 1);

@@ -66,6 +66,10 @@ struct Gemm {
   // tile and split-K choices as for one block of batch level 1 (the same summation order for
   // each block whatever nb1 is, as long as the split-K scratch holds the partials of every block)
   bool per_block = false;
+  // C = A B with B(k, n) = A(n, k) is symmetric: when M == N, beta == 0 and the rows qualify for
+  // the direct-to-LDS kernel, only the tiles on and below the diagonal are computed and the strict
+  // upper triangle is copied from the lower one (otherwise the full product)
+  bool lower = false;
 };
 
 // Batch level of the particle-particle ladder: n operand blocks (A, V and C offset by sa, sv, sc
