@@ -781,25 +781,27 @@ hipError_t gemm_f64_ladder(int M, int Tv, const double* A, const double* V, long
   p.sb1 = lb.sv;
   p.sc1 = lb.sc;
   p.tab1 = lb.tab;
-  // Row tiles of 256, 224, 208 or 128 pair rows: the least padded M wins (each extra row is a full
+  // Row tiles of 256, 240, 224, 208 or 128 pair rows: the least padded M wins (each extra row is a full
   // row of wasted products); on a tie the taller tile, which reads the vvvv operand fewer times.
   // 208 rows (one wave column of 13 x 16 rows per wave) fit T(40) = 820 pairs in four tiles with
   // 1.5 % padding where 224 rows pad by 9 %.
   const long pad256 = (M + 255L) / 256 * 256, pad224 = (M + 223L) / 224 * 224, pad128 = (M + 127L) / 128 * 128;
-  const long pad208 = (M + 207L) / 208 * 208;
+  const long pad208 = (M + 207L) / 208 * 208, pad240 = (M + 239L) / 240 * 240;
   if (lb.n > 65535) return hipErrorInvalidValue;
   if (dma_eligible(p)) {
-    const int t = (pad256 <= pad224 && pad256 <= pad208 && pad256 <= pad128) ? 0
-                  : (pad224 <= pad208 && pad224 <= pad128)                     ? 1
-                  : (pad208 <= pad128)                                         ? 2
-                                                                               : 3;
+    // 240 rows (one wave column of 15 x 16 rows per wave) fit T(21) = 231 pairs with 4 % padding
+    // where 256 rows pad by 11 %, and sixteen stacked T(30) = 465 states exactly
+    const long best = std::min({pad256, pad240, pad224, pad208, pad128});
+    const int t = pad256 == best ? 0 : pad240 == best ? 4 : pad224 == best ? 1 : pad208 == best ? 2 : 3;
     if (pmode) {  // two B rows per pair: two 16-deep stages
       if (t == 0) return launch_dma<256, 128, 4, 2, 2, 16>(p, lb.n, true, 1, nullptr, s);
+      if (t == 4) return launch_dma<240, 128, 1, 8, 2, 16>(p, lb.n, true, 1, nullptr, s);
       if (t == 1) return launch_dma<224, 128, 2, 4, 2, 16>(p, lb.n, true, 1, nullptr, s);
       if (t == 2) return launch_dma<208, 128, 1, 8, 2, 16>(p, lb.n, true, 1, nullptr, s);
       return launch_dma<128, 128, 2, 4, 2, 16>(p, lb.n, true, 1, nullptr, s);
     }
     if (t == 0) return launch_dma<256, 128, 4, 2, 3, 16>(p, lb.n, false, 1, nullptr, s);
+    if (t == 4) return launch_dma<240, 128, 1, 8, 3, 16>(p, lb.n, false, 1, nullptr, s);
     if (t == 1) return launch_dma<224, 128, 2, 4, 3, 16>(p, lb.n, false, 1, nullptr, s);
     if (t == 2) return launch_dma<208, 128, 1, 8, 3, 16>(p, lb.n, false, 1, nullptr, s);
     return launch_dma<128, 128, 2, 4, 3, 16>(p, lb.n, false, 1, nullptr, s);

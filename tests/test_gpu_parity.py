@@ -37,6 +37,7 @@ SHAPES = [
     (4, 70, 150, 4, False),
     (9, 33, 130, 5, True),
     (19, 24, 60, 6, False), # 190 pair rows: one 208-row ladder tile
+    (21, 22, 60, 7, True),  # 231 pair rows: one 240-row ladder tile
 ]
 
 
