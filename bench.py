@@ -806,6 +806,8 @@ COUNTER_PASSES = (
     ("write", ["WRITE_SIZE"]),
 )
 CALIB_BYTES = 1 << 30
+RUN_T0 = time.perf_counter()  # the default run keeps its profiler passes within RUN_BUDGET_S of this
+RUN_BUDGET_S = 480.0
 SERVE_COUNTERS = ["SQ_VALU_MFMA_BUSY_CYCLES", "GRBM_GUI_ACTIVE", "SQ_INSTS_VALU_MFMA_MOPS_F64",
                   "SQ_INSTS_VALU_MFMA_MOPS_BF16"]
 SERVE_COUNTER_REQUESTS = 64
@@ -826,7 +828,10 @@ def run_serving_counters(nreq: int):
         cmd = [exe, "--pmc", *SERVE_COUNTERS, "--output-format", "csv", "-d", outdir, "-o", "run", "--",
                sys.executable, os.path.abspath(__file__), "--serve", "--serve-precisions", prec,
                "--requests", str(nreq)]
-        r = subprocess.run(["timeout", "-s", "KILL", "300", *cmd], capture_output=True, text=True,
+        left = RUN_BUDGET_S - (time.perf_counter() - RUN_T0)
+        if left < 60:
+            raise RuntimeError(f"skipped: {RUN_BUDGET_S - left:.0f} s into the run, the {prec} pass would not fit")
+        r = subprocess.run(["timeout", "-s", "KILL", str(int(min(150, left))), *cmd], capture_output=True, text=True,
                            cwd=tempfile.gettempdir(), env=dict(os.environ, TMPDIR=tempfile.gettempdir()))
         if r.returncode != 0:
             raise RuntimeError(f"serving counter pass {prec} failed (rc {r.returncode}): "
@@ -914,7 +919,7 @@ def run_counters(args):
                sys.executable, os.path.abspath(__file__), "--counter-child", "--workload", args.workload,
                "--vvvv", args.vvvv]
         t0 = time.perf_counter()
-        r = subprocess.run(["timeout", "-s", "KILL", "240", *cmd], capture_output=True, text=True,
+        r = subprocess.run(["timeout", "-s", "KILL", "150", *cmd], capture_output=True, text=True,
                            cwd=tempfile.gettempdir(), env=dict(os.environ, TMPDIR=tempfile.gettempdir()))
         if "counter child done" not in r.stdout:
             raise RuntimeError(f"rocprofv3 {name} pass failed (rc {r.returncode}): {(r.stderr or r.stdout)[-300:]}")
