@@ -584,7 +584,8 @@ def main():
     ap.add_argument("--ascc", default="", help="with --solve: an ASCC 1-CSF state, 'hole,particle' (orbital "
                     "indices) or 'homo-lumo', solved on its transformed Hamiltonian from T^P(0)")
     ap.add_argument("--plascc", action="store_true", help="with --solve: the PLASCC term removal, primaries of "
-                    "--ascc (or HOMO -> LUMO for the ground state), in every solve")
+                    "--ascc (or HOMO -> LUMO for the ground state), in every solve; without --solve: an extra "
+                    "FP64 step variant with the removal (HOMO -> LUMO)")
     ap.add_argument("--two-ansatz", type=float, default=None, metavar="ALPHA",
                     help="both ansatz of the --ascc state (default HOMO -> LUMO) for Aufbau coefficient ALPHA")
     ap.add_argument("--solve-tol", type=float, default=1e-7)
@@ -711,6 +712,11 @@ def headline(args):
         "last_stats": main_run["last"],
     }
     variants, gate = {}, {}
+    if args.plascc and nstates == 1:  # the same FP64 step with the PLASCC removal (HOMO -> LUMO primaries)
+        r = timed_steps(P, torch, ints, o, v, "fp64", args.steps, args.warmup, guesses, plascc=(o - 1, o))
+        variants["fp64_plascc"] = step_summary(r, flops, o, v, "fp64", nstates)
+        variants["fp64_plascc"]["removal_ms_per_step"] = round(r["ms_step"] - ms_step, 4)
+        log(f"fp64 plascc step {r['ms_step']:.3f} ms")
     if compare:
         ksteps, kwarm = max(3, args.steps // 2), min(2, args.warmup)
         r = timed_steps(P, torch, ints, o, v, "bf16x3", ksteps, kwarm, guesses)
