@@ -984,10 +984,13 @@ def summarize_counters(passes, args):
         gm = [k for k in ks if k > pk[0] and "gemm_" in seq[k][0]["kernel"]]
         if not gm:
             return None
-        a = agg([gm[0]])
+        # a ladder whose last row tile runs as tail tiles is two launches
+        parts = gm[:2] if len(gm) > 1 and "_tail_" in seq[gm[1]][0]["kernel"] else gm[:1]
+        a = agg(parts)
         name = seq[gm[0]][0]["kernel"]
         name = name[name.find("gemm_"):]
-        return {"kernel": name[:max(name.find("("), 0) or len(name)][:60], "traffic_bytes": a["hbm_bytes"],
+        return {"kernel": name[:max(name.find("("), 0) or len(name)][:60] + (" + tail" if len(parts) > 1 else ""),
+                "traffic_bytes": a["hbm_bytes"],
                 "mfma_util": a["mfma_util"], "algorithmic_flops": ladder_flops(o, v),
                 "mfma_flops_executed": a["mfma_flops_executed"], "step": tag}
     for tag, rng in (("fp64", fp64_step), ("bf16x3", range(ends[2] + 1, ends[3] + 1)),

@@ -613,6 +613,106 @@ __global__ __launch_bounds__(NT3, 1) void gemm_bf16x3_dma_kernel(LPB p) {
 }
 
 
+// The last rows of M (at most 64, the part of a 256-row tile that would be padding) against 256-column
+// tiles of B: eight waves of 64 x 32 (both 32-row fragments of one 32-column block each).  A stage
+// holds 64 A rows and 256 B rows in the layout of the eight-wave kernel (40 KB of loads instead of
+// 64 KB: each wave issues one A and four B loads), and every output element sees the MFMA sequence
+// and chunk flushes of that kernel, so the rows it computes are bit for bit the same.
+__global__ __launch_bounds__(NT3, 1) void gemm_bf16x3_dma_tail_kernel(LPB p) {
+  __shared__ __attribute__((aligned(1024))) unsigned short T[2][4][256 * 32];  // A planes use rows 0..63
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  int tm, tn;
+  tile_of_grouped(blockIdx.x, 1, p.tiles_n, tm, tn);
+  const int n0 = tn * BN3;
+  const int z = blockIdx.y % p.nb, z1 = blockIdx.y / p.nb;
+  const int zs = __builtin_amdgcn_readfirstlane(p.tab1 ? p.tab1[z1] : z1);
+  const unsigned short* abase = p.A + z * p.sa2 + zs * p.sa1;
+  const unsigned short* bbase = p.B + z * p.sb2 + zs * p.sb1 + (long)n0 * p.ldb;
+  const int arows = min(64, p.M), brows = min(256, p.N - n0);
+  const __amdgpu_buffer_rsrc_t ra = uniform_rsrc(abase, arows * (int)p.lda * 2);
+  const __amdgpu_buffer_rsrc_t rb = uniform_rsrc(bbase, brows * (int)p.ldb * 2);
+  const int r = lane >> 2, c = (lane & 3) ^ ((r >> 1) & 3);  // row in a 16-row block, chunk loaded
+  // load items of a stage: 0..7 are A (plane i >> 2, 16-row block i & 3), 8..39 are B (plane
+  // (i - 8) >> 4, block (i - 8) & 15); wave w issues items w, w + 8, ..., w + 32
+  auto issue = [&](int kt, int stage) {
+    const int gk = kt * 32 + c * 8;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      const int item = wave + 8 * j;
+      const bool isA = j == 0;
+      const int plane = isA ? item >> 2 : (item - 8) >> 4;
+      const int blk = isA ? item & 3 : (item - 8) & 15;
+      const int ld = isA ? (int)p.lda : (int)p.ldb;
+      const int col = kt * 64 + plane * 32 + c * 8;
+      lds_char_t* dst = (lds_char_t*)(lds_void_t*)&T[stage][(isA ? 0 : 2) + plane][blk * 16 * 32];
+      const unsigned off = 2 * gk < ld ? (unsigned)(((blk * 16 + r) * ld + col) * 2) : 0x80000000u;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(isA ? ra : rb, (lds_void_t*)dst, 16, off, 0, 0, 0);
+    }
+  };
+  double* Cb = p.C + z * p.sc2 + (p.part ? z1 : zs) * p.sc1 + blockIdx.z * p.cslice;
+  f16v acc[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[i][q] = 0.f;
+  auto flush = [&](bool first) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int gm = i * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+        const int gn = n0 + wave * 32 + (lane & 31);
+        if (gm < p.M && gn < p.N) {
+          double* cp = Cb + (long)gm * p.scm + (long)gn * p.scn;
+          const double v = p.alpha * (double)acc[i][q];
+          if (first)
+            *cp = (p.beta == 0.0) ? v : v + p.beta * *cp;
+          else
+            add_to(cp, v);
+        }
+        acc[i][q] = 0.f;
+      }
+    if (first) __builtin_amdgcn_s_waitcnt(0xF70);  // the stores have reached L2
+  };
+  const int kt0 = blockIdx.z * p.ktps, nkt = min((p.K + 31) / 32, kt0 + p.ktps);
+  const int fr = lane & 31, fc = lane >> 5;
+  if (kt0 < nkt) issue(kt0, 0);
+  for (int kc = kt0; kc < nkt; kc += p.chunk) {
+    const int kend = min(nkt, kc + p.chunk);
+    for (int kt = kc; kt < kend; ++kt) {
+      const int cur = (kt - kt0) & 1;
+      __builtin_amdgcn_s_waitcnt(0xF70);  // vmcnt(0): this wave's part of stage kt has landed
+      asm volatile("" ::: "memory");
+      __builtin_amdgcn_s_barrier();  // every wave's has, and every wave has read stage cur ^ 1
+      asm volatile("" ::: "memory");
+      if (kt + 1 < nkt) issue(kt + 1, cur ^ 1);
+#pragma unroll
+      for (int sub = 0; sub < 2; ++sub) {
+        bf8 xa[2][2], xb[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const int off = lds_slot(i * 32 + fr, 2 * sub + fc);
+          xa[i][0] = *reinterpret_cast<const bf8*>(&T[cur][0][off]);
+          xa[i][1] = *reinterpret_cast<const bf8*>(&T[cur][1][off]);
+        }
+        const int offb = lds_slot(wave * 32 + fr, 2 * sub + fc);
+        xb[0] = *reinterpret_cast<const bf8*>(&T[cur][2][offb]);
+        xb[1] = *reinterpret_cast<const bf8*>(&T[cur][3][offb]);
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa[i][1], xb[0], acc[i], 0, 0, 0);
+          acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa[i][0], xb[1], acc[i], 0, 0, 0);
+          acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa[i][0], xb[0], acc[i], 0, 0, 0);
+        }
+      }
+    }
+    flush(kc == kt0);
+  }
+  if (kt0 >= nkt) flush(true);
+}
+
+
 // FP32, direct to LDS: 256 x 256 tiles, eight waves of 128 x 64 (two per SIMD), v_mfma_f32_16x16x4_f32.
 // A stage holds 16 K-values of every tile row (64 bytes; the 16-byte chunk c of row r at slot
 // c ^ ((r >> 1) & 3), the 64-byte-row layout of the FP64 direct-to-LDS kernel), four stages (three in flight),
@@ -877,6 +977,26 @@ hipError_t gemm_lowp(const GemmLP& g, hipStream_t s) {
       p.tiles_n = (g.N + BN3 - 1) / BN3;
       p.ktps = (nkt + dsplit - 1) / dsplit;
       const int split = (nkt + p.ktps - 1) / p.ktps;
+      const int mtail = g.M % BM3;
+      if (split == 1 && mtail > 0 && mtail <= 64 && g.M > BM3) {
+        // the last, mostly padding, row tile as 64-row tail tiles of 40 KB stages (about 5/8 of a
+        // full workgroup's time) after the full row tiles, when that takes fewer rounds of 256
+        const long full = (long)(g.M / BM3) * p.tiles_n * nbz, tail = (long)p.tiles_n * nbz;
+        const double r_all = (double)((full + tail + 255) / 256);
+        const double r_split = (double)((full + 255) / 256) + 0.625 * (double)((tail + 255) / 256);
+        if (r_split < r_all) {
+          LPB pt = p;
+          p.M = g.M - mtail;
+          p.tiles_m = p.M / BM3;
+          pt.A += (long)p.M * g.lda;
+          pt.C += (long)p.M * g.scm;
+          pt.M = mtail;
+          pt.tiles_m = 1;
+          hipLaunchKernelGGL(gemm_bf16x3_dma_kernel, dim3(p.tiles_m * p.tiles_n, nbz, 1), dim3(NT3), 0, s, p);
+          hipLaunchKernelGGL(gemm_bf16x3_dma_tail_kernel, dim3(pt.tiles_n, nbz, 1), dim3(NT3), 0, s, pt);
+          return hipGetLastError();
+        }
+      }
       if (split > 1) to_partials(p);
       hipLaunchKernelGGL(gemm_bf16x3_dma_kernel, dim3(p.tiles_m * p.tiles_n, nbz, split), dim3(NT3), 0, s, p);
       if (split > 1) reduce(split);
