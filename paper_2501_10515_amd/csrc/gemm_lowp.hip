@@ -825,6 +825,122 @@ __global__ __launch_bounds__(NT4, 1) void gemm_f32_dma_kernel(LP p) {
   if (ks0 >= nks) flush(true);
 }
 
+// The last rows of M (at most 64) for the FP32 kernel above: 64 x 256 tiles, eight waves of 64 x 32
+// (four 16-row by two 16-column fragments each), stages of 64 A rows and 256 B rows (20 KB; each
+// wave loads two 16-row blocks of B, waves 0-3 also one of A), four stages.  Every output element
+// sees the MFMA sequence and chunk flushes of that kernel, so its rows are bit for bit the same.
+__global__ __launch_bounds__(NT4, 1) void gemm_f32_dma_tail_kernel(LP p) {
+  __shared__ __attribute__((aligned(1024))) float T[S4][(64 + BN4) * 16];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  int tm, tn;
+  tile_of_grouped(blockIdx.x, 1, p.tiles_n, tm, tn);
+  const int n0 = tn * BN4;
+  const int z = blockIdx.y % p.nb, z1 = blockIdx.y / p.nb;
+  const int zs = __builtin_amdgcn_readfirstlane(p.tab1 ? p.tab1[z1] : z1);
+  const float* abase = p.A + z * p.sa2 + zs * p.sa1;
+  const float* bbase = p.B + z * p.sb2 + zs * p.sb1 + (long)n0 * p.ldb;
+  const __amdgpu_buffer_rsrc_t ra = uniform_rsrc(abase, min(64, p.M) * (int)p.lda * 4);
+  const __amdgpu_buffer_rsrc_t rb = uniform_rsrc(bbase, min(256, p.N - n0) * (int)p.ldb * 4);
+  const int lr = lane >> 2, c = (lane & 3) ^ ((lr >> 1) & 3);  // row in a 16-row block, chunk loaded
+  const bool loadsA = wave < 4;                                   // three loads per stage, else two
+  auto issue = [&](int ks, int stage) {
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      const int blk = 2 * wave + g;
+      const unsigned off = (unsigned)(((blk * 16 + lr) * (int)p.ldb + ks * 16 + c * 4) * 4);
+      lds_char_t* dst = (lds_char_t*)(lds_void_t*)&T[stage][(64 + blk * 16) * 16];
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (lds_void_t*)dst, 16, off, 0, 0, 0);
+    }
+    if (loadsA) {
+      const unsigned off = (unsigned)(((wave * 16 + lr) * (int)p.lda + ks * 16 + c * 4) * 4);
+      lds_char_t* dst = (lds_char_t*)(lds_void_t*)&T[stage][(wave * 16) * 16];
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (lds_void_t*)dst, 16, off, 0, 0, 0);
+    }
+  };
+  double* Cb = p.C + z * p.sc2 + (p.part ? z1 : zs) * p.sc1 + blockIdx.z * p.cslice;
+  f4 acc[4][2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  auto flush = [&](bool first) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gm = i * 16 + 4 * (lane >> 4) + r;
+          const int gn = n0 + wave * 32 + j * 16 + (lane & 15);
+          if (gm < p.M && gn < p.N) {
+            double* cp = Cb + (long)gm * p.scm + (long)gn * p.scn;
+            const double v = p.alpha * (double)acc[i][j][r];
+            if (first)
+              *cp = (p.beta == 0.0) ? v : v + p.beta * *cp;
+            else
+              *cp += v;
+          }
+          acc[i][j][r] = 0.f;
+        }
+  };
+  const int ks0 = blockIdx.z * 2 * p.ktps, nks = min((p.K + 15) / 16, ks0 + 2 * p.ktps);
+  const int chunk = 2 * p.chunk;
+  const int l16 = lane & 15, q = lane >> 4;
+#pragma unroll
+  for (int st = 0; st < S4 - 1; ++st)
+    if (ks0 + st < nks) issue(ks0 + st, st);
+  for (int kc = ks0; kc < nks; kc += chunk) {
+    const int kend = min(nks, kc + chunk);
+    for (int ks = kc; ks < kend; ++ks) {
+      const int st = (ks - ks0) % S4;
+      // stage ks has landed once no more than the later stages' loads of this wave are in flight
+      const int ahead = min(S4 - 2, nks - 1 - ks);
+      if (loadsA) {
+        if (ahead >= 2)
+          __builtin_amdgcn_s_waitcnt(0xF76);  // vmcnt(6)
+        else if (ahead == 1)
+          __builtin_amdgcn_s_waitcnt(0xF73);  // vmcnt(3)
+        else
+          __builtin_amdgcn_s_waitcnt(0xF70);  // vmcnt(0)
+      } else {
+        if (ahead >= 2)
+          __builtin_amdgcn_s_waitcnt(0xF74);  // vmcnt(4)
+        else if (ahead == 1)
+          __builtin_amdgcn_s_waitcnt(0xF72);  // vmcnt(2)
+        else
+          __builtin_amdgcn_s_waitcnt(0xF70);  // vmcnt(0)
+      }
+      asm volatile("" ::: "memory");
+      __builtin_amdgcn_s_barrier();
+      asm volatile("" ::: "memory");
+      const float* Ts = T[st];
+      f4 fa[4], fb[2];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = i * 16 + l16;
+        fa[i] = *reinterpret_cast<const f4*>(Ts + r * 16 + 4 * (q ^ ((r >> 1) & 3)));
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int r = 64 + wave * 32 + j * 16 + l16;
+        fb[j] = *reinterpret_cast<const f4*>(Ts + r * 16 + 4 * (q ^ ((r >> 1) & 3)));
+      }
+      // the stage refilled now was last read in the previous iteration, before this barrier
+      if (ks + S4 - 1 < nks) issue(ks + S4 - 1, (ks - ks0 + S4 - 1) % S4);
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i][t], fb[j][t], acc[i][j], 0, 0, 0);
+    }
+    flush(kc == ks0);
+  }
+  if (ks0 >= nks) flush(true);
+}
+
 // C_z(m,n) = beta * C_z(m,n) + sum_s part[s][z][m][n], summed in slice order.
 __global__ __launch_bounds__(256) void lowp_splitk_reduce(double* C, long scm, long scn, long sc2, long sc1, int nb,
                                                           const int* tab1, double beta, const double* part, int M,
@@ -1038,6 +1154,27 @@ hipError_t gemm_lowp(const GemmLP& g, hipStream_t s) {
       p.tiles_n = (g.N + BN4 - 1) / BN4;
       p.ktps = (nkt + dsplit - 1) / dsplit;
       const int split = (nkt + p.ktps - 1) / p.ktps;
+      const int mtail = g.M % BM4;
+      // (the tail kernel's B range spans 256 rows of one buffer descriptor)
+      if (split == 1 && mtail > 0 && mtail <= 64 && g.M > BM4 && 1024L * g.ldb < (1L << 31)) {
+        // the last row tile as 64-row tail tiles, as for split-BF16x3 (20 KB stages: about 5/8 of
+        // a full workgroup's time)
+        const long full = (long)(g.M / BM4) * p.tiles_n * nbz, tail = (long)p.tiles_n * nbz;
+        const double r_all = (double)((full + tail + 255) / 256);
+        const double r_split = (double)((full + 255) / 256) + 0.625 * (double)((tail + 255) / 256);
+        if (r_split < r_all) {
+          LP pt = p;
+          p.M = g.M - mtail;
+          p.tiles_m = p.M / BM4;
+          pt.A += (long)p.M * g.lda;
+          pt.C += (long)p.M * g.scm;
+          pt.M = mtail;
+          pt.tiles_m = 1;
+          hipLaunchKernelGGL(gemm_f32_dma_kernel, dim3(p.tiles_m * p.tiles_n, nbz, 1), dim3(NT4), 0, s, p);
+          hipLaunchKernelGGL(gemm_f32_dma_tail_kernel, dim3(pt.tiles_n, nbz, 1), dim3(NT4), 0, s, pt);
+          return hipGetLastError();
+        }
+      }
       if (split > 1) to_partials(p);
       hipLaunchKernelGGL(gemm_f32_dma_kernel, dim3(p.tiles_m * p.tiles_n, nbz, split), dim3(NT4), 0, s, p);
       if (split > 1) reduce(split);

@@ -127,7 +127,9 @@ def test_lowp_ladder_over_several_k_chunks(P, mode, prec):
     """o40 v130: the ladder product has M = T(o) = 820 rows per half and K = N = T(v) = 8515, so the
     split-BF16x3 contraction runs on its direct-to-LDS kernel (4 x 34 x 2 = 272 tiles of 256 x 256)
     and flushes its FP32 sums into the FP64 result twice (K chunks of 8192), as does the FP32 one on
-    its direct-to-LDS kernel: the residual against the FP64 oracle."""
+    its direct-to-LDS kernel; in both, the last 52 rows of each half run as 64-row tail tiles in a
+    launch of their own (3 x 34 x 2 full tiles in one round, then 68 tail tiles): the residual
+    against the FP64 oracle."""
     from oracle import cs_ccsd
 
     from .gpu_util import dev, gpu_residual
