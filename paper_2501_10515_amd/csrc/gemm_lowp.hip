@@ -424,13 +424,15 @@ __global__ __launch_bounds__(NT2, 1) void gemm_bf16x3_kernel(LPB p) {
   double* Cw = Cb + (long)(m0 + wm * 64) * p.scm + (long)(n0 + wn * 64) * p.scn;  // wave-uniform
   const int scm = (int)p.scm, scn = (int)p.scn;
   auto flush = [&](bool first) {
+    int lx = lane;  // opaque to the compiler: the addresses below are not hoisted out of the K loop
+    asm volatile("" : "+v"(lx));
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int lm = i * 16 + 4 * (lane >> 4) + r, ln = j * 16 + (lane & 15);
+          const int lm = i * 16 + 4 * (lx >> 4) + r, ln = j * 16 + (lx & 15);
           if (m0 + wm * 64 + lm < p.M && n0 + wn * 64 + ln < p.N) {
             double* c = Cw + (lm * scm + ln * scn);
             const double v = p.alpha * (double)acc[i][j][r];
@@ -550,14 +552,18 @@ __global__ __launch_bounds__(NT3, 1) void gemm_bf16x3_dma_kernel(LPB p) {
       for (int q = 0; q < 16; ++q) acc[i][j][q] = 0.f;
   // 32 x 32 fragment: register q of lane l holds C(8 (q / 4) + 4 (l / 32) + q % 4, l % 32)
   auto flush = [&](bool first) {
+    // addresses formed here, from a lane index the compiler cannot see through: hoisted out of the
+    // K loop they would hold registers across it (and spill)
+    int ln = lane;
+    asm volatile("" : "+v"(ln));
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j)
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
-          const int gm = m0 + wm * 128 + i * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
-          const int gn = n0 + wn * 64 + j * 32 + (lane & 31);
+          const int gm = m0 + wm * 128 + i * 32 + 8 * (q >> 2) + 4 * (ln >> 5) + (q & 3);
+          const int gn = n0 + wn * 64 + j * 32 + (ln & 31);
           if (gm < p.M && gn < p.N) {
             double* cp = Cb + (long)gm * p.scm + (long)gn * p.scn;
             const double v = p.alpha * (double)acc[i][j][q];
@@ -758,14 +764,17 @@ __global__ __launch_bounds__(NT4, 1) void gemm_f32_dma_kernel(LP p) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
   auto flush = [&](bool first) {
+    // addresses formed here from an opaque lane index (hoisted, they would spill)
+    int ln = lane;
+    asm volatile("" : "+v"(ln));
 #pragma unroll
     for (int i = 0; i < 8; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int gm = m0 + wm * 128 + i * 16 + 4 * (lane >> 4) + r;
-          const int gn = n0 + wn * 64 + j * 16 + (lane & 15);
+          const int gm = m0 + wm * 128 + i * 16 + 4 * (ln >> 4) + r;
+          const int gn = n0 + wn * 64 + j * 16 + (ln & 15);
           if (gm < p.M && gn < p.N) {
             double* cp = Cb + (long)gm * p.scm + (long)gn * p.scn;
             const double v = p.alpha * (double)acc[i][j][r];
