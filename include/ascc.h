@@ -44,6 +44,10 @@
  *     buffer it was given or owns (failing with ASCC_E_HIP and a message instead), and the
  *     integral builds verify that the largest occupied orbital energy lies below the smallest
  *     virtual one (ASCC_E_ARG otherwise: the Jacobi denominators must stay negative).
+ *   - Low-precision contractions whose last 256-row tile holds at most 64 rows compute those rows
+ *     in a launch of 64-row tail tiles when that takes fewer rounds of workgroups; the rows are
+ *     bit for bit those of the full-tile launch, which ASCC_NO_TAIL_TILES=1 (read once per
+ *     process) selects instead.
  */
 #ifndef ASCC_H
 #define ASCC_H

@@ -22,6 +22,7 @@
 // C(8(q/4) + 4(l/32) + q%4, l%32).
 #include <algorithm>
 #include <cstdint>
+#include <cstdlib>
 
 #include "internal.h"
 
@@ -67,6 +68,16 @@ __device__ __forceinline__ unsigned short bf16_rne(float f) {
   return (unsigned short)(r >> 16);
 }
 __device__ __forceinline__ float bf16_to_f(unsigned short h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+// ASCC_NO_TAIL_TILES=1 (read once per process) keeps a last row tile of at most 64 rows in the
+// full-tile launch instead of the tail launch; both give the same rows bit for bit.
+bool tail_tiles_enabled() {
+  static const bool on = [] {
+    const char* e = std::getenv("ASCC_NO_TAIL_TILES");
+    return !(e && e[0] == '1');
+  }();
+  return on;
+}
 
 // Same, walked in groups of 8 M-tiles (M fastest inside a group): the workgroups resident on one
 // XCD at a time cover a compact block of C and share A and B slices in its L2.
@@ -1103,7 +1114,7 @@ hipError_t gemm_lowp(const GemmLP& g, hipStream_t s) {
       p.ktps = (nkt + dsplit - 1) / dsplit;
       const int split = (nkt + p.ktps - 1) / p.ktps;
       const int mtail = g.M % BM3;
-      if (split == 1 && mtail > 0 && mtail <= 64 && g.M > BM3) {
+      if (tail_tiles_enabled() && split == 1 && mtail > 0 && mtail <= 64 && g.M > BM3) {
         // the last, mostly padding, row tile as 64-row tail tiles of 40 KB stages (about 5/8 of a
         // full workgroup's time) after the full row tiles, when that takes fewer rounds of 256
         const long full = (long)(g.M / BM3) * p.tiles_n * nbz, tail = (long)p.tiles_n * nbz;
@@ -1165,7 +1176,7 @@ hipError_t gemm_lowp(const GemmLP& g, hipStream_t s) {
       const int split = (nkt + p.ktps - 1) / p.ktps;
       const int mtail = g.M % BM4;
       // (the tail kernel's B range spans 256 rows of one buffer descriptor)
-      if (split == 1 && mtail > 0 && mtail <= 64 && g.M > BM4 && 1024L * g.ldb < (1L << 31)) {
+      if (tail_tiles_enabled() && split == 1 && mtail > 0 && mtail <= 64 && g.M > BM4 && 1024L * g.ldb < (1L << 31)) {
         // the last row tile as 64-row tail tiles, as for split-BF16x3 (20 KB stages: about 5/8 of
         // a full workgroup's time)
         const long full = (long)(g.M / BM4) * p.tiles_n * nbz, tail = (long)p.tiles_n * nbz;

@@ -193,3 +193,57 @@ def test_mixed_precision_solves_meet_the_energy_gate_at_o40_v360(P):
     for k in ("bf16x3", "fp32"):
         assert out[k]["lowp_iterations"] >= 5
         assert abs(out[k]["e_corr"] - out["fp64"]["e_corr"]) < 1e-6
+
+
+TAIL_CHILD = r"""
+import sys
+import numpy as np
+import torch
+sys.path.insert(0, sys.argv[1])
+import paper_2501_10515_amd as P
+from gen.synth_df import make_system, random_amplitudes
+P.load_library()
+o, v, Q, seed = 40, 130, 200, 11
+B, eps = make_system(o, v, Q, seed, sigma=0.1)
+t1, t2 = random_amplitudes(o, v, seed + 100, 0.02, 0.02)
+dt1, dt2 = torch.from_numpy(t1).cuda(), torch.from_numpy(t2).cuda()
+out = {}
+for name, pc in (("fp32", P.ASCC_PREC_FP32), ("bf16x3", P.ASCC_PREC_BF16X3)):
+    ints = P.ascc_build_ints(torch.from_numpy(B).cuda(), torch.from_numpy(eps).cuda(), o, precision=pc,
+                             vvvv_mode=P.ASCC_VVVV_PACKED)
+    r1, r2 = torch.empty_like(dt1), torch.empty_like(dt2)
+    e = torch.empty(1, dtype=torch.float64, device="cuda")
+    P.ascc_residual(ints, dt1, dt2, r1, r2, e)
+    torch.cuda.synchronize()
+    out[name + "_r1"], out[name + "_r2"], out[name + "_e"] = r1.cpu().numpy(), r2.cpu().numpy(), e.cpu().numpy()
+    ints.close()
+np.savez(sys.argv[2], **out)
+print("done", flush=True)
+"""
+
+
+@pytest.mark.slow
+def test_tail_tiles_give_the_full_launch_rows_bit_for_bit(P, tmp_path):
+    """o40 v130 Q200, packed vvvv: the ladder's last row tile (52 of T(o) = 820 pair rows) runs as
+    64-row tail tiles (3 x 34 x 2 full tiles fill one round, the 68 tail tiles a cheaper second
+    one) in the FP32 and the split-BF16x3 contraction; with ASCC_NO_TAIL_TILES=1 (read once per
+    process, so in children) it stays in the full-tile launch.  Both residuals and energies agree
+    bit for bit, in both precisions."""
+    import os
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    script = tmp_path / "tail_child.py"
+    script.write_text(TAIL_CHILD)
+    res = {}
+    for knob in ("0", "1"):
+        print(f"case: o40 v130 Q200 residuals, ASCC_NO_TAIL_TILES={knob}", flush=True)
+        path = tmp_path / f"r{knob}.npz"
+        r = subprocess.run([sys.executable, str(script), root, str(path)], capture_output=True, text=True,
+                           timeout=240, env=dict(os.environ, ASCC_NO_TAIL_TILES=knob), cwd=root)
+        assert r.returncode == 0, r.stderr[-2000:]
+        res[knob] = np.load(path)
+    for k in res["0"].files:  # the 64-bit patterns, so that even the sign of a zero must agree
+        assert np.array_equal(res["0"][k].view(np.uint64), res["1"][k].view(np.uint64)), k
+    assert np.abs(res["0"]["bf16x3_r2"]).max() > 1e-4
