@@ -264,6 +264,68 @@ __global__ __launch_bounds__(256) void split_bf16_2d_kernel(unsigned short* __re
   }
 }
 
+// The same two conversions, eight columns per thread (one K-block of 32 never splits a group):
+// 16-byte loads of the FP64 source (16-byte aligned rows: `in` aligned, ldi even) and 16-byte
+// stores, one index division per eight elements; each element is converted exactly as above.
+__global__ __launch_bounds__(256) void cvt_f32_2d_v8_kernel(float* __restrict__ out, long ldo,
+                                                            const double* __restrict__ in, long ldi, long rows,
+                                                            long cols) {
+  const long per = ldo >> 3, total = rows * per;
+  for (long x = blockIdx.x * 256L + threadIdx.x; x < total; x += (long)gridDim.x * 256) {
+    const long r = x / per, c = (x - r * per) << 3;
+    const double* src = in + r * ldi + c;
+    double d[8];
+    if (c + 8 <= cols) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const double2 v = reinterpret_cast<const double2*>(src)[j];
+        d[2 * j] = v.x;
+        d[2 * j + 1] = v.y;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) d[j] = (c + j < cols) ? src[j] : 0.0;
+    }
+    float4* o = reinterpret_cast<float4*>(out + r * ldo + c);
+    o[0] = make_float4((float)d[0], (float)d[1], (float)d[2], (float)d[3]);
+    o[1] = make_float4((float)d[4], (float)d[5], (float)d[6], (float)d[7]);
+  }
+}
+
+__global__ __launch_bounds__(256) void split_bf16_2d_v8_kernel(unsigned short* __restrict__ out, long ldo,
+                                                               const double* __restrict__ in, long ldi, long rows,
+                                                               long cols) {
+  const long per = ldo >> 3, total = rows * per;
+  for (long x = blockIdx.x * 256L + threadIdx.x; x < total; x += (long)gridDim.x * 256) {
+    const long r = x / per, c = (x - r * per) << 3;
+    const double* src = in + r * ldi + c;
+    double d[8];
+    if (c + 8 <= cols) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const double2 v = reinterpret_cast<const double2*>(src)[j];
+        d[2 * j] = v.x;
+        d[2 * j + 1] = v.y;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) d[j] = (c + j < cols) ? src[j] : 0.0;
+    }
+    uint32_t hw[4], lw[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const unsigned short h0 = bf16_rne((float)d[2 * j]), h1 = bf16_rne((float)d[2 * j + 1]);
+      const unsigned short l0 = bf16_rne((float)(d[2 * j] - (double)bf16_to_f(h0)));
+      const unsigned short l1 = bf16_rne((float)(d[2 * j + 1] - (double)bf16_to_f(h1)));
+      hw[j] = (uint32_t)h0 | ((uint32_t)h1 << 16);
+      lw[j] = (uint32_t)l0 | ((uint32_t)l1 << 16);
+    }
+    unsigned short* o = out + r * 2 * ldo + (c >> 5) * 64 + (c & 31);
+    *reinterpret_cast<uint4*>(o) = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+    *reinterpret_cast<uint4*>(o + 32) = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+  }
+}
+
 // Transposing low-precision shadow: out row r (< rows) holds in[c][r] for c < cols, zero padding
 // up to ldo (a multiple of 32), laid out as to_lowp_2d lays out its rows.  32 x 32 tiles through
 // LDS, so both the reads (along r) and the writes (along c) are coalesced.
@@ -1007,13 +1069,23 @@ hipError_t to_lowp_2d(int prec, float* out, long ldo, const double* in, long ldi
                              range_ok(in, 0, (rows - 1) * ldi + cols - 1, 8, "lowp source")))
     return hipErrorInvalidValue;
   if (dry_run()) return hipSuccess;
-  long g = (total + 255) / 256;
+  // eight columns per thread where the rows allow 16-byte accesses (ldo is a multiple of 32)
+  const bool v8 = (reinterpret_cast<uintptr_t>(in) & 15) == 0 && (reinterpret_cast<uintptr_t>(out) & 15) == 0 &&
+                  (ldi & 1) == 0 && (ldo & 31) == 0;
+  long g = ((v8 ? total / 8 : total) + 255) / 256;
   if (g > 8192) g = 8192;
   if (prec == kPrecBF16x3) {
-    hipLaunchKernelGGL(split_bf16_2d_kernel, dim3((unsigned)g), dim3(256), 0, s, reinterpret_cast<unsigned short*>(out),
-                       ldo, in, ldi, rows, cols);
+    if (v8)
+      hipLaunchKernelGGL(split_bf16_2d_v8_kernel, dim3((unsigned)g), dim3(256), 0, s,
+                         reinterpret_cast<unsigned short*>(out), ldo, in, ldi, rows, cols);
+    else
+      hipLaunchKernelGGL(split_bf16_2d_kernel, dim3((unsigned)g), dim3(256), 0, s,
+                         reinterpret_cast<unsigned short*>(out), ldo, in, ldi, rows, cols);
   } else {
-    hipLaunchKernelGGL(cvt_f32_2d_kernel, dim3((unsigned)g), dim3(256), 0, s, out, ldo, in, ldi, rows, cols);
+    if (v8)
+      hipLaunchKernelGGL(cvt_f32_2d_v8_kernel, dim3((unsigned)g), dim3(256), 0, s, out, ldo, in, ldi, rows, cols);
+    else
+      hipLaunchKernelGGL(cvt_f32_2d_kernel, dim3((unsigned)g), dim3(256), 0, s, out, ldo, in, ldi, rows, cols);
   }
   return hipGetLastError();
 }
