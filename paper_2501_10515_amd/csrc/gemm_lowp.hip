@@ -570,9 +570,10 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t uniform_rsrc(const void* base,
 
 // 256 x 256 tiles, eight waves of 128 x 64 (two per SIMD, so one wave's fragment reads and barrier
 // wait overlap the other's MFMAs), v_mfma_f32_32x32x16_bf16 (4 x 2 fragments of 32 x 32 per wave).
-// Each wave stages half of one operand plane per K-step (A hi, A lo, B hi, B lo: 128 rows x 64
-// bytes) with eight buffer_load_dwordx4 ... lds (lane l of an instruction writes LDS bytes
-// 16l .. 16l + 15, so lanes pick the global chunk that belongs at their swizzled slot); rows past M
+// Each wave stages 64 rows of one operand per K-step as whole 128-byte lines (a row's K-block holds
+// hi 32 | lo 32) with eight buffer_load_dwordx4 ... lds (lane l of an instruction writes LDS bytes
+// 16l .. 16l + 15, so lanes pick the global chunk that belongs at their swizzled slot; staged as two
+// 64-byte planes, each line was fetched by two waves and the step took 3-4 % longer); rows past M
 // or N and K-blocks past the padded row read as zero through the buffer range check.  Per K-step:
 // wait for this wave's part of the stage, barrier, issue the next stage into the other buffer, then
 // two K = 16 halves of fragment reads and 24 MFMAs.  The buffer refilled after a step's barrier was
@@ -587,7 +588,9 @@ typedef float f16v __attribute__((ext_vector_type(16)));
 constexpr int BM3 = 256, BN3 = 256, NT3 = 512;
 
 __global__ __launch_bounds__(NT3, 1) void gemm_bf16x3_dma_kernel(LPB p) {
-  __shared__ __attribute__((aligned(1024))) unsigned short T[2][4][256 * 32];  // [stage][plane][row slots]
+  // [stage][operand][row][64 bf16]: a row's whole K-block (hi 32 | lo 32, one 128-byte line), its
+  // eight 16-byte chunks c at slots c ^ ((row >> 1) & 7)
+  __shared__ __attribute__((aligned(1024))) unsigned short T[2][2][256 * 64];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave >> 2, wn = wave & 3;  // this wave's 128 x 64 block of the tile
@@ -596,23 +599,27 @@ __global__ __launch_bounds__(NT3, 1) void gemm_bf16x3_dma_kernel(LPB p) {
   const int m0 = tm * BM3, n0 = tn * BN3;
   const int z = blockIdx.y % p.nb, z1 = blockIdx.y / p.nb;
   const int zs = __builtin_amdgcn_readfirstlane(p.tab1 ? p.tab1[z1] : z1);  // uniform: scalar buffer descriptors
-  const int lplane = wave >> 1, lhalf = wave & 1;  // staging: plane (A hi, A lo, B hi, B lo), row half
-  const bool isA = lplane < 2;
+  const int lop = wave >> 2, lq = wave & 3;  // staging: operand (A, B), rows 64 lq .. 64 lq + 63
+  const bool isA = lop == 0;
   const unsigned short* base = isA ? p.A + z * p.sa2 + zs * p.sa1 + (long)m0 * p.lda
                                    : p.B + z * p.sb2 + zs * p.sb1 + (long)n0 * p.ldb;
   const int ld = isA ? (int)p.lda : (int)p.ldb;  // row stride (bf16): K-blocks of [hi 32 | lo 32]
-  const int plane = lplane & 1;
   const int rows = min(256, isA ? p.M - m0 : p.N - n0);
   const __amdgpu_buffer_rsrc_t rs = uniform_rsrc(base, rows * ld * 2);
-  const int r = lane >> 2, c = (lane & 3) ^ ((r >> 1) & 3);  // row in a 16-row block, chunk loaded
+  // lane l of a load writes row l / 8 of an 8-row group, slot l % 8; the chunk that belongs there
+  // differs by 4 between even and odd groups (the swizzle's (row >> 1) & 4 term)
+  const int r8 = lane >> 3, c0 = (lane & 7) ^ (r8 >> 1);
+  const unsigned off_even = (unsigned)(((64 * lq + r8) * ld + c0 * 8) * 2);
+  const unsigned off_odd = (unsigned)(((64 * lq + r8) * ld + (c0 ^ 4) * 8) * 2);
   auto issue = [&](int kt, int stage) {
-    const int gk = kt * 32 + c * 8, col = kt * 64 + plane * 32 + c * 8;
-    lds_char_t* dst = (lds_char_t*)(lds_void_t*)&T[stage][lplane][0];
+    unsigned oe = off_even, oo = off_odd;
+    asm volatile("" : "+v"(oe), "+v"(oo));  // two offset registers across the loop, not one per load
+    lds_char_t* dst = (lds_char_t*)(lds_void_t*)&T[stage][lop][64 * lq * 64];
 #pragma unroll
     for (int g = 0; g < 8; ++g) {
-      const int gg = lhalf * 8 + g;
-      const unsigned off = 2 * gk < ld ? (unsigned)(((gg * 16 + r) * ld + col) * 2) : 0x80000000u;
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_t*)(dst + gg * 1024), 16, off, 0, 0, 0);
+      const unsigned uni = (unsigned)((8 * g * ld + kt * 64) * 2);  // wave-uniform
+      const unsigned off = kt * 64 < ld ? ((g & 1) ? oo : oe) + uni : 0x80000000u;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_t*)(dst + g * 1024), 16, off, 0, 0, 0);
     }
   };
   double* Cb = p.C + z * p.sc2 + (p.part ? z1 : zs) * p.sc1 + blockIdx.z * p.cslice;
@@ -651,6 +658,7 @@ __global__ __launch_bounds__(NT3, 1) void gemm_bf16x3_dma_kernel(LPB p) {
   };
   const int kt0 = blockIdx.z * p.ktps, nkt = min((p.K + 31) / 32, kt0 + p.ktps);
   const int fr = lane & 31, fc = lane >> 5;  // fragment row, K-chunk within a K = 16 half
+  const int sw = (fr >> 1) & 7;                // the slot swizzle of every row this lane reads
   if (kt0 < nkt) issue(kt0, 0);
   for (int kc = kt0; kc < nkt; kc += p.chunk) {
     const int kend = min(nkt, kc + p.chunk);
@@ -663,18 +671,20 @@ __global__ __launch_bounds__(NT3, 1) void gemm_bf16x3_dma_kernel(LPB p) {
       if (kt + 1 < nkt) issue(kt + 1, cur ^ 1);
 #pragma unroll
       for (int sub = 0; sub < 2; ++sub) {
+        // hi chunk q = 2 sub + fc at slot q ^ sw, lo chunk 4 + q at (q ^ sw) ^ 4 (sw depends on fr only)
+        const int hs = ((2 * sub + fc) ^ sw) * 8, ls = hs ^ 32;
         bf8 xa[4][2], xb[2][2];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int off = lds_slot(wm * 128 + i * 32 + fr, 2 * sub + fc);
-          xa[i][0] = *reinterpret_cast<const bf8*>(&T[cur][0][off]);
-          xa[i][1] = *reinterpret_cast<const bf8*>(&T[cur][1][off]);
+          const int row = (wm * 128 + i * 32 + fr) * 64;
+          xa[i][0] = *reinterpret_cast<const bf8*>(&T[cur][0][row + hs]);
+          xa[i][1] = *reinterpret_cast<const bf8*>(&T[cur][0][row + ls]);
         }
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-          const int off = lds_slot(wn * 64 + j * 32 + fr, 2 * sub + fc);
-          xb[j][0] = *reinterpret_cast<const bf8*>(&T[cur][2][off]);
-          xb[j][1] = *reinterpret_cast<const bf8*>(&T[cur][3][off]);
+          const int row = (wn * 64 + j * 32 + fr) * 64;
+          xb[j][0] = *reinterpret_cast<const bf8*>(&T[cur][1][row + hs]);
+          xb[j][1] = *reinterpret_cast<const bf8*>(&T[cur][1][row + ls]);
         }
 #pragma unroll
         for (int j = 0; j < 2; ++j)
