@@ -708,7 +708,7 @@ __global__ __launch_bounds__(NT3, 1) void gemm_bf16x3_dma_kernel(LPB p) {
 // 64 KB: each wave issues one A and four B loads), and every output element sees the MFMA sequence
 // and chunk flushes of that kernel, so the rows it computes are bit for bit the same.
 __global__ __launch_bounds__(NT3, 1) void gemm_bf16x3_dma_tail_kernel(LPB p) {
-  __shared__ __attribute__((aligned(1024))) unsigned short T[2][4][256 * 32];  // A planes use rows 0..63
+  __shared__ __attribute__((aligned(1024))) unsigned short T[2][2][256 * 64];  // A uses rows 0..63
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   int tm, tn;
@@ -721,22 +721,26 @@ __global__ __launch_bounds__(NT3, 1) void gemm_bf16x3_dma_tail_kernel(LPB p) {
   const int arows = min(64, p.M), brows = min(256, p.N - n0);
   const __amdgpu_buffer_rsrc_t ra = uniform_rsrc(abase, arows * (int)p.lda * 2);
   const __amdgpu_buffer_rsrc_t rb = uniform_rsrc(bbase, brows * (int)p.ldb * 2);
-  const int r = lane >> 2, c = (lane & 3) ^ ((r >> 1) & 3);  // row in a 16-row block, chunk loaded
-  // load items of a stage: 0..7 are A (plane i >> 2, 16-row block i & 3), 8..39 are B (plane
-  // (i - 8) >> 4, block (i - 8) & 15); wave w issues items w, w + 8, ..., w + 32
+  // whole 128-byte lines in the layout of the eight-wave kernel: a stage is 8 groups of 8 A rows and
+  // 32 of 8 B rows; wave w loads A group w and B groups w, w + 8, w + 16, w + 24, all of the parity
+  // of w, so one chunk choice per lane serves every load of the wave
+  const int r8 = lane >> 3, c = (lane & 7) ^ (r8 >> 1) ^ ((wave & 1) << 2);
+  const unsigned a_off = (unsigned)((r8 * (int)p.lda + c * 8) * 2), b_off = (unsigned)((r8 * (int)p.ldb + c * 8) * 2);
   auto issue = [&](int kt, int stage) {
-    const int gk = kt * 32 + c * 8;
+    unsigned ao = a_off, bo = b_off;
+    asm volatile("" : "+v"(ao), "+v"(bo));
+    const bool have = kt * 64 < (int)p.lda;  // the K-block exists (lda == ldb)
+    {
+      const unsigned uni = (unsigned)((8 * wave * (int)p.lda + kt * 64) * 2);
+      lds_char_t* dst = (lds_char_t*)(lds_void_t*)&T[stage][0][8 * wave * 64];
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (lds_void_t*)dst, 16, have ? ao + uni : 0x80000000u, 0, 0, 0);
+    }
 #pragma unroll
-    for (int j = 0; j < 5; ++j) {
-      const int item = wave + 8 * j;
-      const bool isA = j == 0;
-      const int plane = isA ? item >> 2 : (item - 8) >> 4;
-      const int blk = isA ? item & 3 : (item - 8) & 15;
-      const int ld = isA ? (int)p.lda : (int)p.ldb;
-      const int col = kt * 64 + plane * 32 + c * 8;
-      lds_char_t* dst = (lds_char_t*)(lds_void_t*)&T[stage][(isA ? 0 : 2) + plane][blk * 16 * 32];
-      const unsigned off = 2 * gk < ld ? (unsigned)(((blk * 16 + r) * ld + col) * 2) : 0x80000000u;
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(isA ? ra : rb, (lds_void_t*)dst, 16, off, 0, 0, 0);
+    for (int j = 0; j < 4; ++j) {
+      const int gb = wave + 8 * j;
+      const unsigned uni = (unsigned)((8 * gb * (int)p.ldb + kt * 64) * 2);
+      lds_char_t* dst = (lds_char_t*)(lds_void_t*)&T[stage][1][8 * gb * 64];
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (lds_void_t*)dst, 16, have ? bo + uni : 0x80000000u, 0, 0, 0);
     }
   };
   double* Cb = p.C + z * p.sc2 + (p.part ? z1 : zs) * p.sc1 + blockIdx.z * p.cslice;
@@ -766,6 +770,7 @@ __global__ __launch_bounds__(NT3, 1) void gemm_bf16x3_dma_tail_kernel(LPB p) {
   };
   const int kt0 = blockIdx.z * p.ktps, nkt = min((p.K + 31) / 32, kt0 + p.ktps);
   const int fr = lane & 31, fc = lane >> 5;
+  const int sw = (fr >> 1) & 7;  // the slot swizzle of every row this lane reads
   if (kt0 < nkt) issue(kt0, 0);
   for (int kc = kt0; kc < nkt; kc += p.chunk) {
     const int kend = min(nkt, kc + p.chunk);
@@ -778,16 +783,17 @@ __global__ __launch_bounds__(NT3, 1) void gemm_bf16x3_dma_tail_kernel(LPB p) {
       if (kt + 1 < nkt) issue(kt + 1, cur ^ 1);
 #pragma unroll
       for (int sub = 0; sub < 2; ++sub) {
+        const int hs = ((2 * sub + fc) ^ sw) * 8, ls = hs ^ 32;  // hi and lo chunk slots
         bf8 xa[2][2], xb[2];
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
-          const int off = lds_slot(i * 32 + fr, 2 * sub + fc);
-          xa[i][0] = *reinterpret_cast<const bf8*>(&T[cur][0][off]);
-          xa[i][1] = *reinterpret_cast<const bf8*>(&T[cur][1][off]);
+          const int row = (i * 32 + fr) * 64;
+          xa[i][0] = *reinterpret_cast<const bf8*>(&T[cur][0][row + hs]);
+          xa[i][1] = *reinterpret_cast<const bf8*>(&T[cur][0][row + ls]);
         }
-        const int offb = lds_slot(wave * 32 + fr, 2 * sub + fc);
-        xb[0] = *reinterpret_cast<const bf8*>(&T[cur][2][offb]);
-        xb[1] = *reinterpret_cast<const bf8*>(&T[cur][3][offb]);
+        const int rowb = (wave * 32 + fr) * 64;
+        xb[0] = *reinterpret_cast<const bf8*>(&T[cur][1][rowb + hs]);
+        xb[1] = *reinterpret_cast<const bf8*>(&T[cur][1][rowb + ls]);
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
           acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa[i][1], xb[0], acc[i], 0, 0, 0);
